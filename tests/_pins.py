@@ -1,0 +1,397 @@
+"""Pins for the FP64 oracle: checks against closed forms, invariants and an
+independent set-based statement of the Barnes-Hut walk.
+
+Each pin is a plain function that raises AssertionError when the oracle is
+wrong. ``test_oracle_pins.py`` runs them as tests; ``test_oracle_mutants.py``
+re-runs them against copies of the oracle with planted mistakes and checks
+that every planted mistake makes at least one pin fail.
+"""
+from __future__ import annotations
+
+import math
+import os
+
+import numpy as np
+
+import oracle
+from paper_1912_04197_amd import ics
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    return np.loadtxt(os.path.join(GOLDEN, name), comments="#", ndmin=2)
+
+
+# ------------------------------------------------------------------ direct sum
+
+def pin_two_body_softened():
+    """Hand-derived softened pair with unequal per-body softening."""
+    g = _golden("two_body_soft.txt")
+    acc, phi, _ = oracle.direct(g[:, 0:3], g[:, 3], eps=g[:, 4])
+    np.testing.assert_allclose(acc, g[:, 5:8], rtol=1e-15, atol=0)
+    np.testing.assert_allclose(phi, g[:, 8], rtol=1e-15, atol=0)
+
+
+def pin_three_collinear():
+    g = _golden("three_collinear.txt")
+    acc, phi, _ = oracle.direct(g[:, 0:3], g[:, 3])
+    np.testing.assert_allclose(acc[:, 0], g[:, 4], rtol=1e-15, atol=1e-15)
+    assert np.all(acc[:, 1:] == 0.0)
+    np.testing.assert_allclose(phi, g[:, 5], rtol=1e-15)
+
+
+def pin_two_body_uniform_softening_formula():
+    """Random pairs against a_1 = G m_2 d / (|d|^2 + eps^2)^(3/2)."""
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        x = rng.standard_normal((2, 3))
+        m = rng.random(2) + 0.1
+        e = float(rng.random())
+        G = float(rng.random() + 0.5)
+        acc, phi, _ = oracle.direct(x, m, softening=e, G=G)
+        d = x[1] - x[0]
+        r2 = float(d @ d) + e * e
+        np.testing.assert_allclose(acc[0], G * m[1] * d / r2 ** 1.5, rtol=1e-14)
+        np.testing.assert_allclose(acc[1], -G * m[0] * d / r2 ** 1.5, rtol=1e-14)
+        np.testing.assert_allclose(phi, [-G * m[1] / math.sqrt(r2), -G * m[0] / math.sqrt(r2)],
+                                   rtol=1e-14)
+
+
+def pin_newton_third_law():
+    """sum_i m_i a_i = 0 for the direct sum (symmetric pair softening)."""
+    rng = np.random.default_rng(7)
+    n = 400
+    x = rng.standard_normal((n, 3))
+    m = rng.random(n)
+    eps = 0.05 * rng.random(n)
+    acc, _, aabs = oracle.direct(x, m, eps=eps)
+    net = (m[:, None] * acc).sum(0)
+    scale = float((m * aabs).sum())
+    assert np.abs(net).max() <= 1e-14 * scale, (net, scale)
+
+
+def _polyhedra():
+    phi = (1 + 5 ** 0.5) / 2
+    octa = [(s * (i == 0), s * (i == 1), s * (i == 2)) for i in range(3) for s in (1.0, -1.0)]
+    cube = [(a, b, c) for a in (1.0, -1.0) for b in (1.0, -1.0) for c in (1.0, -1.0)]
+    ico = []
+    for a in (1.0, -1.0):
+        for b in (phi, -phi):
+            ico += [(0.0, a, b), (a, b, 0.0), (b, 0.0, a)]
+    return {"octahedron": octa, "cube": cube, "icosahedron": ico}
+
+
+def pin_symmetric_shells():
+    """A body at the centre of a regular polyhedron of equal masses feels no
+    force, and every vertex body is pulled exactly towards the centre."""
+    for name, verts in _polyhedra().items():
+        v = np.array(verts, dtype=np.float64)
+        x = np.vstack([np.zeros((1, 3)), 2.5 * v])
+        m = np.full(len(x), 0.3)
+        acc, _, aabs = oracle.direct(x, m, softening=0.1)
+        assert np.abs(acc[0]).max() <= 1e-15 * aabs[0], name
+        for k in range(1, len(x)):
+            radial = -x[k] / np.linalg.norm(x[k])
+            perp = acc[k] - (acc[k] @ radial) * radial
+            assert np.linalg.norm(perp) <= 1e-14 * aabs[k], name
+            assert acc[k] @ radial > 0, name
+
+
+def pin_shell_theorem():
+    """Uniform ball of mass M, radius R: a(r) = -G M r / R^3 inside and
+    -G M / r^2 outside; phi(r) = -G M (3R^2 - r^2) / (2 R^3) inside, -G M / r
+    outside. Massless probes in many directions per radius, small softening,
+    Monte-Carlo tolerance."""
+    n = 200_000
+    s = ics.uniform_ball(n, seed=3)
+    radii = [0.25, 0.5, 0.75, 1.5, 3.0]
+    rng = np.random.default_rng(31)
+    dirs = rng.standard_normal((48, 3))
+    dirs /= np.linalg.norm(dirs, axis=1)[:, None]
+    probes = np.vstack([r * dirs for r in radii])
+    x = np.vstack([s.pos, probes])
+    m = np.concatenate([s.mass, np.zeros(len(probes))])
+    targets = np.arange(n, n + len(probes))
+    acc, phi, _ = oracle.direct(x, m, softening=0.02, targets=targets)
+    for k, r in enumerate(radii):
+        sl = slice(48 * k, 48 * (k + 1))
+        a_rad = -(acc[sl] * dirs).sum(1).mean()
+        a_exp = r if r < 1 else 1.0 / r ** 2
+        p_exp = -(3 - r * r) / 2 if r < 1 else -1.0 / r
+        assert abs(a_rad - a_exp) <= 0.015 * a_exp, (r, a_rad, a_exp)
+        assert abs(phi[sl].mean() - p_exp) <= 0.005 * abs(p_exp), (r, phi[sl].mean(), p_exp)
+
+
+def pin_torch_bruteforce_direct():
+    """Direct sum against an all-pairs broadcast in numpy (N = 300)."""
+    rng = np.random.default_rng(9)
+    n = 300
+    x = rng.standard_normal((n, 3))
+    m = rng.random(n)
+    eps = 0.1 * rng.random(n)
+    acc, phi, _ = oracle.direct(x, m, eps=eps, G=2.0)
+    d = x[None, :, :] - x[:, None, :]
+    r2 = (d * d).sum(-1) + 0.5 * (eps[:, None] ** 2 + eps[None, :] ** 2)
+    np.fill_diagonal(r2, np.inf)
+    a_ref = 2.0 * (m[None, :, None] * d / r2[..., None] ** 1.5).sum(1)
+    p_ref = -2.0 * (m[None, :] / np.sqrt(r2)).sum(1)
+    np.testing.assert_allclose(acc, a_ref, rtol=1e-11, atol=1e-13)
+    np.testing.assert_allclose(phi, p_ref, rtol=1e-12)
+
+
+# -------------------------------------------------------------------- octree
+
+def _quantise(x):
+    """Integer cell coordinates of the root cube on a 2^21 grid (the reading
+    of the cell definition; the tree pins below check its geometry)."""
+    lo, hi = x.min(0), x.max(0)
+    L = float((hi - lo).max())
+    if L == 0.0:
+        L = 1.0
+    x0 = (lo + hi) * 0.5 - L * 0.5
+    S = 2097152.0 / L
+    q = np.clip(np.floor((x - x0) * S), 0, 2097151).astype(np.int64)
+    return q, x0, L
+
+
+def set_based_bh(x, m, theta, leaf, softening=0.0, eps=None):
+    """Barnes-Hut as a set definition, with no recursion and no bottom-up pass.
+
+    Cells exist at level l when their parent cell (level l-1) holds more than
+    ``leaf`` bodies; a cell is a leaf when it holds at most ``leaf`` bodies or
+    l = 21. For body B the accepted nodes are the internal cells that pass
+    s^2 < theta^2 D^2 while every proper ancestor fails it; the leaf pairs are
+    the members j != B of leaves whose proper ancestors all fail it. Centres of
+    mass are mass-weighted means over each cell's members.
+    Returns (acc, counts) with counts[:, 0] nodes and counts[:, 1] pairs.
+    """
+    n = len(x)
+    q, x0, L = _quantise(x)
+    cells = {}  # (level, cx, cy, cz) -> member indices
+    for lvl in range(22):
+        key = q >> (21 - lvl)
+        groups = {}
+        for i in range(n):
+            groups.setdefault((lvl, *key[i]), []).append(i)
+        for k, mem in groups.items():
+            if lvl == 0:
+                cells[k] = np.array(mem)
+            else:
+                parent = (lvl - 1, *(np.array(k[1:]) >> 1))
+                if parent in cells and len(cells[parent]) > leaf:
+                    cells[k] = np.array(mem)
+    info = {}
+    for k, mem in cells.items():
+        mm = m[mem].sum()
+        com = (m[mem, None] * x[mem]).sum(0) / mm
+        e2 = (m[mem] * eps[mem] ** 2).sum() / mm if eps is not None else 0.0
+        is_leaf = len(mem) <= leaf or k[0] == 21
+        # passes[b]: does cell k pass the opening test for body b?
+        D2 = ((com[None, :] - x) ** 2).sum(1)
+        s = L / 2 ** k[0]
+        info[k] = (mem, mm, com, e2, is_leaf, s * s < theta * theta * D2)
+    acc = np.zeros((n, 3))
+    counts = np.zeros((n, 2), np.int64)
+    eb2 = eps ** 2 if eps is not None else None
+    for k, (mem, mm, com, e2, is_leaf, passes) in info.items():
+        lvl = k[0]
+        reach = np.ones(n, bool)  # every proper ancestor fails the test
+        for a in range(lvl):
+            anc = (a, *(np.array(k[1:]) >> (lvl - a)))
+            reach &= ~info[anc][5]
+        if is_leaf:
+            for j in mem:
+                sel = reach.copy()
+                sel[j] = False
+                d = x[j][None, :] - x[sel]
+                e = 0.5 * (eb2[sel] + eps[j] ** 2) if eps is not None else softening ** 2
+                acc[sel] += m[j] * d / ((d * d).sum(1) + e)[:, None] ** 1.5
+                counts[sel, 1] += 1
+        else:
+            sel = reach & passes
+            d = com[None, :] - x[sel]
+            e = 0.5 * (eb2[sel] + e2) if eps is not None else softening ** 2
+            acc[sel] += mm * d / ((d * d).sum(1) + e)[:, None] ** 1.5
+            counts[sel, 0] += 1
+    return acc, counts
+
+
+def pin_set_based_walk():
+    """Recursive walk == set-based definition: identical per-body node and pair
+    counts, accelerations to 1e-12 of the absolute-term sum."""
+    cases = [
+        (ics.uniform_ball(300, seed=1).pos, 0.5, 4, None),
+        (ics.plummer(256, seed=2).pos, 0.7, 1, None),
+        (ics.uniform_cube(200, seed=3).pos, 0.3, 8, None),
+    ]
+    rng = np.random.default_rng(4)
+    for x, theta, leaf, _ in cases:
+        n = len(x)
+        m = rng.random(n) + 0.2
+        eps = 0.02 * rng.random(n)
+        acc_s, cnt_s = set_based_bh(x, m, theta, leaf, eps=eps)
+        acc, _, aabs, cnt = oracle.bh(x, m, theta, eps=eps, leaf=leaf)
+        assert np.array_equal(cnt, cnt_s), (theta, leaf, np.abs(cnt - cnt_s).max())
+        err = np.linalg.norm(acc - acc_s, axis=1)
+        assert np.all(err <= 1e-12 * aabs), (theta, leaf, (err / aabs).max())
+
+
+def pin_tree_structure():
+    """Node table invariants: children partition the parent's segment in octant
+    order, leaves obey the bucket rule, every body lies in its leaf's cube,
+    and the root holds the total mass at the global centre of mass."""
+    for s, leaf in ((ics.uniform_ball(5000, seed=8), 8), (ics.plummer(3000, seed=9), 1),
+                    (ics.uniform_cube(2000, seed=10), 16)):
+        x, m = s.pos, s.mass * (1 + np.arange(s.n) % 3)
+        T = oracle.Tree(x, m, leaf=leaf)
+        t = T.export()
+        box = T.box()
+        L, x0 = box["L"], box["x0"]
+        assert sorted(t["order"].tolist()) == list(range(s.n))
+        assert t["level"][0] == 0 and t["first"][0] == 0 and t["count"][0] == s.n
+        ms = m.sum()
+        assert abs(t["mass"][0] - ms) <= 1e-15 * ms
+        com = (m[:, None] * x).sum(0) / ms
+        assert np.abs(t["com"][0] - com).max() <= 1e-14 * L
+        for k in range(T.nnodes):
+            lvl, f, c, c0, nc = (int(t[a][k]) for a in ("level", "first", "count", "child0", "nchild"))
+            mem = t["order"][f:f + c]
+            if nc == 0:
+                assert c <= leaf or lvl == 21
+                side = L / 2 ** lvl
+                cell = t["q"][mem[0]] >> (21 - lvl)
+                lo_c = x0 + cell * side
+                assert np.all(x[mem] >= lo_c - 1e-12 * L) and np.all(x[mem] <= lo_c + side + 1e-12 * L)
+                assert np.all((t["q"][mem] >> (21 - lvl)) == cell)
+            else:
+                assert c > leaf and lvl < 21 and 1 <= nc <= 8
+                ch = range(c0, c0 + nc)
+                assert t["first"][c0] == f
+                assert sum(int(t["count"][j]) for j in ch) == c
+                for j in ch:
+                    assert t["level"][j] == lvl + 1
+                    assert t["count"][j] > 0
+                octs = [int(((t["q"][t["order"][t["first"][j]]] >> (20 - lvl)) & 1) @ [4, 2, 1])
+                        for j in ch]
+                assert octs == sorted(set(octs))
+                for a, b in zip(ch, list(ch)[1:]):
+                    assert t["first"][b] == t["first"][a] + t["count"][a]
+            mm = m[mem].sum()
+            assert abs(t["mass"][k] - mm) <= 1e-14 * mm
+            assert np.abs(t["com"][k] - (m[mem, None] * x[mem]).sum(0) / mm).max() <= 1e-14 * L
+
+
+def pin_theta_zero_is_direct():
+    """theta = 0 opens every node: the same pair set as the direct sum."""
+    s = ics.uniform_ball(1500, seed=12)
+    eps = 0.01 * (1 + np.arange(s.n) % 5)
+    for e in (None, eps):
+        acc_d, phi_d, aabs = oracle.direct(s.pos, s.mass, softening=1e-3, eps=e)
+        acc_t, phi_t, _, cnt = oracle.bh(s.pos, s.mass, 0.0, softening=1e-3, eps=e, leaf=4)
+        assert np.all(cnt[:, 0] == 0) and np.all(cnt[:, 1] == s.n - 1)
+        assert np.all(np.linalg.norm(acc_t - acc_d, axis=1) <= 1e-13 * aabs)
+        np.testing.assert_allclose(phi_t, phi_d, rtol=1e-13)
+
+
+def pin_leaf_ge_n_is_direct():
+    s = ics.plummer(700, seed=13)
+    acc_d, _, aabs = oracle.direct(s.pos, s.mass, softening=1e-2)
+    acc_t, _, _, cnt = oracle.bh(s.pos, s.mass, 0.9, softening=1e-2, leaf=700)
+    assert np.all(cnt[:, 1] == s.n - 1)
+    assert np.all(np.linalg.norm(acc_t - acc_d, axis=1) <= 1e-13 * aabs)
+
+
+def pin_error_monotone_in_theta():
+    """RMS force error against the direct sum grows with theta, roughly as
+    theta^2 for a monopole about the centre of mass."""
+    s = ics.uniform_ball(6000, seed=14)
+    acc_d, _, _ = oracle.direct(s.pos, s.mass, softening=1e-3)
+    norm = np.linalg.norm(acc_d, axis=1)
+    errs = []
+    for th in (0.2, 0.4, 0.6, 0.8):
+        acc_t, _, _, _ = oracle.bh(s.pos, s.mass, th, softening=1e-3, leaf=8)
+        errs.append(math.sqrt(np.mean((np.linalg.norm(acc_t - acc_d, axis=1) / norm) ** 2)))
+    assert all(a < b for a, b in zip(errs, errs[1:])), errs
+    assert errs[0] < 1e-3 and errs[-1] < 0.1, errs
+    assert errs[-1] / errs[0] > 4.0, errs
+
+
+def pin_coincident_and_tiny():
+    """n = 1 gives zero; bodies that share one point end in one level-21 leaf
+    and, softened, pull each other with zero force."""
+    acc, phi, _, cnt = oracle.bh(np.array([[0.3, -0.2, 0.1]]), np.array([2.0]), 0.5,
+                                 softening=0.1, leaf=1)
+    assert np.all(acc == 0) and np.all(cnt == 0) and phi[0] == 0
+    x = np.vstack([np.tile([[0.1, 0.2, 0.3]], (40, 1)), [[1.0, 1.0, 1.0]]])
+    m = np.ones(41)
+    T = oracle.Tree(x, m, leaf=16)
+    t = T.export()
+    leaves = t["nchild"] == 0
+    assert t["count"][leaves].max() == 40 and t["level"][leaves].max() == 21
+    acc, phi, _, cnt = T.accel(0.5, softening=0.01)
+    d = np.array([0.9, 0.8, 0.7])
+    a_far = d / (d @ d + 1e-4) ** 1.5
+    np.testing.assert_allclose(acc[0], a_far, rtol=1e-6)
+
+
+# ------------------------------------------------------------------ leapfrog
+
+def pin_leapfrog_circular_orbit():
+    """Circular two-body orbit returns to its start after one period
+    2 pi sqrt(a^3 / (G M)); the phase error is O(dt^2)."""
+    s = ics.two_body_circular(0.7, 0.3, 1.0)
+    period = 2 * math.pi * math.sqrt(1.0 / 1.0)
+    errs = []
+    for nsteps in (400, 800):
+        dt = period / nsteps
+        x, v, a = oracle.leapfrog(s.pos, s.vel, s.mass, dt, nsteps)
+        errs.append(np.linalg.norm(x - s.pos))
+    assert errs[0] < 2e-3, errs
+    assert 3.5 < errs[0] / errs[1] < 4.5, errs
+
+
+def pin_leapfrog_reversible():
+    """n steps forward, reverse the velocities, n steps back: the start again."""
+    s = ics.plummer(64, seed=15)
+    x, v, a = oracle.leapfrog(s.pos, s.vel, s.mass, 1e-3, 200, softening=0.05)
+    x2, v2, _ = oracle.leapfrog(x, -v, s.mass, 1e-3, 200, softening=0.05, acc=a)
+    assert np.abs(x2 - s.pos).max() < 1e-12
+    assert np.abs(v2 + s.vel).max() < 1e-11
+
+
+def pin_leapfrog_conservation():
+    """Direct-sum leapfrog: momentum and angular momentum to round-off, energy
+    error bounded and oscillating with no secular drift."""
+    s = ics.plummer(48, seed=16)
+    e0 = oracle.diagnostics(s.pos, s.vel, s.mass, softening=0.05)
+    x, v, a = s.pos, s.vel, None
+    devs = []
+    for _ in range(8):
+        x, v, a = oracle.leapfrog(x, v, s.mass, 2e-3, 250, softening=0.05, acc=a)
+        d = oracle.diagnostics(x, v, s.mass, softening=0.05)
+        devs.append(abs((d[0] + d[1]) - (e0[0] + e0[1])) / abs(e0[0] + e0[1]))
+        assert np.abs(d[2:5] - e0[2:5]).max() < 1e-14
+        assert np.abs(d[5:8] - e0[5:8]).max() < 1e-13
+    assert max(devs) < 1e-3, devs
+    assert max(devs[4:]) < 3 * max(devs[:4]) + 1e-12, devs
+
+
+def pin_leapfrog_tree_theta0():
+    s = ics.uniform_ball(300, seed=17)
+    xd, vd, _ = oracle.leapfrog(s.pos, s.vel, s.mass, 1e-3, 5, softening=1e-2)
+    xt, vt, _ = oracle.leapfrog(s.pos, s.vel, s.mass, 1e-3, 5, softening=1e-2, theta=0.0, leaf=4)
+    assert np.abs(xt - xd).max() < 1e-13 and np.abs(vt - vd).max() < 1e-11
+
+
+def pin_diagnostics_two_body():
+    s = ics.two_body_circular(0.7, 0.3, 1.0)
+    d = oracle.diagnostics(s.pos, s.vel, s.mass)
+    mu = 0.7 * 0.3 / 1.0
+    np.testing.assert_allclose(d[1], -0.7 * 0.3, rtol=1e-15)
+    np.testing.assert_allclose(d[0], 0.5 * 0.7 * 0.3 / 1.0, rtol=1e-14)
+    np.testing.assert_allclose(d[7], mu * math.sqrt(1.0 * 1.0), rtol=1e-14)
+    assert np.abs(d[2:5]).max() < 1e-16
+
+
+ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

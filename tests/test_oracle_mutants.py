@@ -1,0 +1,74 @@
+"""Every planted mistake in the oracle must make at least one pin fail.
+
+Each mutant is a copy of the oracle's C source with one plausible mistake
+(a dropped term, a wrong sign or index, a swapped operand, a wrong constant),
+compiled to a temporary library; the pins run against it and at least one of
+them must raise. This checks that the pins fix the oracle, not only that the
+oracle agrees with itself.
+"""
+import os
+
+import pytest
+
+import _pins
+import oracle
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "bh_oracle.c")
+
+MUTANTS = {
+    "pair_sign": ("acc[0] += gm * dx * inv3;", "acc[0] -= gm * dx * inv3;"),
+    "pair_drop_z": ("double d2 = dx * dx + dy * dy + dz * dz;", "double d2 = dx * dx + dy * dy;"),
+    "r3_to_r2": ("double inv3 = 1.0 / (r2 * r);", "double inv3 = 1.0 / r2;"),
+    "direct_swap_ij": ("add_term(pos[3 * j] - pos[3 * i],", "add_term(pos[3 * i] - pos[3 * j],"),
+    "direct_self": ("if (j == i) continue; /* j != i in eq. (Newton) */", ""),
+    "soft_receiver_only": ("double e2 = eps ? 0.5 * (ei2 + eps[j] * eps[j]) : e02;",
+                           "double e2 = eps ? ei2 : e02;"),
+    "soft_no_half": ("0.5 * (st->eb2 + w->eps[j] * w->eps[j])", "(st->eb2 + w->eps[j] * w->eps[j])"),
+    "node_soft": ("0.5 * (st->eb2 + t->eps2[k])", "0.5 * (st->eb2 + st->eb2)"),
+    "mac_inverted": ("if (s * s < w->theta2 * D2) {", "if (s * s > w->theta2 * D2) {"),
+    "mac_drop_z": ("double D2 = dx * dx + dy * dy + dz * dz;\n    double s = ldexp",
+                   "double D2 = dx * dx + dy * dy;\n    double s = ldexp"),
+    "mac_half_side": ("double s = ldexp(t->L, -t->level[k]);\n    if",
+                      "double s = ldexp(t->L, -t->level[k] - 1);\n    if"),
+    "walk_self": ("if (j == st->b) continue;", ""),
+    "com_unweighted": ("mx += t->com[3 * c] * t->m[c];", "mx += t->com[3 * c];"),
+    "leaf_com_y_from_x": ("my += pos[3 * b + 1] * mass[b];", "my += pos[3 * b] * mass[b];"),
+    "octant_bit": ("int shift = ORC_MAX_LEVEL - 1 - level;", "int shift = ORC_MAX_LEVEL - level;"),
+    "octant_order": ("return (int)((((q[0] >> shift) & 1u) << 2) | (((q[1] >> shift) & 1u) << 1) |",
+                     "return (int)((((q[1] >> shift) & 1u) << 2) | (((q[0] >> shift) & 1u) << 1) |"),
+    "leaf_rule": ("if (count > t->leaf && level < ORC_MAX_LEVEL) {",
+                  "if (count >= t->leaf && level < ORC_MAX_LEVEL) {"),
+    "root_half_box": ("t->x0[a] = (t->lo[a] + t->hi[a]) * 0.5 - L * 0.5;",
+                      "t->x0[a] = t->lo[a] + L * 0.25;"),
+    "kick_full": ("double h = 0.5 * dt;", "double h = dt;"),
+    "drift_old_acc": ("for (int64_t i = 0; i < 3 * n; i++) pos[i] += dt * vel[i]; /* drift */",
+                      "for (int64_t i = 0; i < 3 * n; i++) pos[i] += dt * (vel[i] - 0.5 * dt * acc[i]);"),
+    "ekin_no_half": ("out[0] += 0.5 * m * (v[0] * v[0]", "out[0] += m * (v[0] * v[0]"),
+    "angmom_sign": ("out[7] += m * (x[0] * v[1] - x[1] * v[0]);", "out[7] += m * (x[1] * v[0] - x[0] * v[1]);"),
+}
+
+
+@pytest.fixture(scope="module")
+def source():
+    with open(SRC) as f:
+        return f.read()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, source, tmp_path):
+    old, new = MUTANTS[name]
+    assert source.count(old) == 1, f"mutation site for {name} not found exactly once"
+    mutated = tmp_path / "bh_oracle.c"
+    mutated.write_text(source.replace(old, new))
+    lib = oracle.compile_source(str(mutated), str(tmp_path / "liboracle_mutant.so"))
+    failed = []
+    try:
+        oracle.use_library(lib)
+        for pin in _pins.ALL_PINS:
+            try:
+                pin()
+            except Exception as e:  # an exception of any kind is a caught mutant
+                failed.append((pin.__name__, type(e).__name__))
+    finally:
+        oracle.use_library(None)
+    assert failed, f"mutant {name} passed every pin"
