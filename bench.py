@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Headline benchmark: one-GPU Barnes-Hut leapfrog on a 2^20-body rubble pile.
+
+Workload: N = 1,048,576 rubble-pile aggregation cloud (uniform ball of radius
+1, lognormal radii with median 1e-3 and log-sigma 0.3, mass ~ r^3 summing to 1,
+isotropic velocities at 0.1x virial plus solid-body spin 0.2 about z), G = 1,
+per-body softening = radius, theta = 0.5, leaf 16, FP32 pair terms with FP64
+state, kick-drift-kick steps of dt = 5e-4. A step is one whole hot path: tree
+rebuild (box, keys, sort, gather, build, moments), walk, and both kicks.
+
+Prints one JSON line: steps/s (value), Ginteractions/s, the direct N^2 and
+plain-FP64 comparisons on the same GPU, the force error against the FP64
+direct sum, the walk kernel's roofline fraction (HIP events on the launch
+stream), and the FP64 CPU oracle's throughput on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "steps/s & Ginteractions/s at N=1M, theta=0.5 vs direct N^2; force rel. err vs FP64"
+FLOPS_PER_INTERACTION = 20  # conventional count for one softened monopole/pair term
+PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=1 << 20, help="bodies (default 2^20)")
+    ap.add_argument("--theta", type=float, default=0.5)
+    ap.add_argument("--leaf", type=int, default=16)
+    ap.add_argument("--dt", type=float, default=5e-4)
+    ap.add_argument("--cpu-sample", type=int, default=131072,
+                    help="targets the oracle walks for the CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the timed steps (for profiler runs)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} (WORLD_SIZE={world}) is not "
+              "supported: this build runs the whole hot path on a single MI355X.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1912_04197_amd import ics
+    from paper_1912_04197_amd.api import Context
+
+    torch.cuda.set_device(0)
+    n, theta, leaf, dt = args.n, args.theta, args.leaf, args.dt
+    log(f"generating rubble pile n={n}")
+    scene = ics.rubble_pile(n, seed=33)
+    pos0 = torch.from_numpy(scene.pos).cuda()
+    vel0 = torch.from_numpy(scene.vel).cuda()
+    mass = torch.from_numpy(scene.mass).cuda()
+    eps = torch.from_numpy(scene.eps).cuda()
+
+    def run_steps(ctx, k, pos, vel, acc):
+        for _ in range(k):
+            ctx.step_leapfrog(pos, vel, mass, acc, dt, 1, theta=theta, eps=eps, sync=False)
+
+    # ---- headline: FP32C tree leapfrog
+    ctx = Context(n, leaf_size=leaf, precision="fp32c", timing=True)
+    pos, vel = pos0.clone(), vel0.clone()
+    acc = ctx.compute_accel(pos, mass, theta, eps=eps)
+    log(f"warmup {args.warmup} steps")
+    run_steps(ctx, args.warmup, pos, vel, acc)
+    ctx.sync()
+    ctx.timing_reset()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    t0 = time.perf_counter()
+    run_steps(ctx, args.steps, pos, vel, acc)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.sync()
+    st = ctx.stats()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    walk_ms = st["walk_ms"] / max(st["timed_evals"], 1)
+    build_ms = st["build_ms"] / max(st["timed_evals"], 1)
+    log(f"{ms_step:.3f} ms/step (walk {walk_ms:.3f} ms, build {build_ms:.3f} ms, "
+        f"{st['timed_evals']} timed evaluations)")
+
+    # interactions per step: counted at the first and the last timed state
+    cctx = Context(n, leaf_size=leaf, precision="fp32c", counts=True)
+    inter = []
+    for p in (pos0, pos):
+        cctx.compute_accel(p, mass, theta, eps=eps)
+        s2 = cctx.stats()
+        inter.append(s2["nodes_accepted"] + s2["leaf_pairs"])
+    interactions = 0.5 * (inter[0] + inter[1])
+    nnodes = cctx.stats()["nnodes"]
+    cctx.close()
+    gint_step = interactions / (ms_step * 1e-3) / 1e9
+    gint_walk = interactions / (walk_ms * 1e-3) / 1e9
+    achieved = FLOPS_PER_INTERACTION * interactions / (walk_ms * 1e-3) / 1e12
+
+    result = {
+        "metric": METRIC,
+        "value": round(1e3 / ms_step, 4),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair terms, f64 state",
+        "data": "synthetic",
+        "config": {
+            "workload": f"rubble_pile N={n} theta={theta} leaf={leaf} eps=radius dt={dt} "
+                        "kick-drift-kick, tree rebuilt every step",
+            "n": n, "theta": theta, "leaf": leaf, "dt": dt, "precision": "fp32c",
+        },
+        "ginteractions_per_s": round(gint_step, 3),
+        "ginteractions_per_s_walk": round(gint_walk, 3),
+        "interactions_per_step": int(interactions),
+        "interactions_per_body": round(interactions / n, 1),
+        "nodes": nnodes,
+        "walk_ms": round(walk_ms, 4),
+        "build_ms": round(build_ms, 4),
+        "roofline": {
+            "bound": "alu",
+            "achieved": round(achieved, 3),
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "traffic": None,
+            "kernel": "k_walk<fp32c, per-body eps>",
+            "flops_per_interaction": FLOPS_PER_INTERACTION,
+        },
+    }
+
+    if not args.no_extras:
+        # plain FP64 form of the same step
+        c64 = Context(n, leaf_size=leaf, precision="fp64", timing=True)
+        p64, v64 = pos0.clone(), vel0.clone()
+        a64 = c64.compute_accel(p64, mass, theta, eps=eps)
+        k64 = max(3, min(10, args.steps))
+        run_steps(c64, 1, p64, v64, a64)
+        c64.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_steps(c64, k64, p64, v64, a64)
+        torch.cuda.synchronize()
+        ms64 = (time.perf_counter() - t0) * 1e3 / k64
+        c64.sync()
+        log(f"fp64 tree step {ms64:.3f} ms")
+
+        # direct N^2 on the same GPU, and the force error against FP64 direct
+        def timed(fn):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            return out, (time.perf_counter() - t) * 1e3
+
+        a_dir64, ms_dir64 = timed(lambda: c64.compute_accel_direct(pos0, mass, eps=eps))
+        a_dir32, ms_dir32 = timed(lambda: ctx.compute_accel_direct(pos0, mass, eps=eps))
+        a_tree32 = ctx.compute_accel(pos0, mass, theta, eps=eps)
+        a_tree64 = c64.compute_accel(pos0, mass, theta, eps=eps)
+        log(f"direct fp32c {ms_dir32:.1f} ms, fp64 {ms_dir64:.1f} ms")
+
+        def err_stats(a, ref):
+            e = (torch.linalg.norm(a - ref, dim=1) / torch.linalg.norm(ref, dim=1)).cpu().numpy()
+            return {"rms": float(np.sqrt(np.mean(e ** 2))), "p99": float(np.quantile(e, 0.99)),
+                    "max": float(e.max())}
+
+        result["comparisons"] = {
+            "fp64_tree_ms_per_step": round(ms64, 4),
+            "speedup_vs_fp64_tree": round(ms64 / ms_step, 3),
+            "direct_fp32c_ms": round(ms_dir32, 3),
+            "direct_fp64_ms": round(ms_dir64, 3),
+            "direct_fp32c_ginteractions_per_s": round(n * (n - 1) / (ms_dir32 * 1e-3) / 1e9, 2),
+            "speedup_tree_step_vs_direct_fp32c_force": round(ms_dir32 / ms_step, 2),
+            "force_rel_err_vs_fp64_direct": {
+                "tree_fp32c": err_stats(a_tree32, a_dir64),
+                "tree_fp64": err_stats(a_tree64, a_dir64),
+                "direct_fp32c": err_stats(a_dir32, a_dir64),
+            },
+            "force_rel_err_fp32c_vs_fp64_tree": err_stats(a_tree32, a_tree64),
+        }
+        c64.close()
+
+    if not args.no_cpu:
+        import oracle
+
+        sample = min(args.cpu_sample, n)
+        rng = np.random.default_rng(7)
+        targets = np.sort(rng.choice(n, sample, replace=False))
+        log(f"cpu oracle: tree over {n} bodies, walk of {sample} targets")
+        t0 = time.perf_counter()
+        tree = oracle.Tree(scene.pos, scene.mass, eps=scene.eps, leaf=leaf)
+        t_build = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        tree.accel(theta, targets=targets)
+        t_walk = time.perf_counter() - t0
+        step_s = t_build + t_walk * n / sample
+        result["cpu_baseline"] = {
+            "value": round(1.0 / step_s, 6),
+            "unit": "steps/s",
+            "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": (f"FP64 oracle: full tree build of the 2^20-body initial state "
+                       f"({t_build:.2f} s) + walk of {sample} random targets "
+                       f"({t_walk:.2f} s), walk extrapolated x{n / sample:.1f} to all bodies"),
+            "cpu_model": cpu_model(),
+            "gpu_speedup": round(step_s * 1e3 / ms_step, 1),
+        }
+        log(f"cpu oracle step estimate {step_s:.2f} s on {oracle.num_threads()} threads")
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * bhx.h -- C ABI of the MI355X Barnes-Hut / direct-sum self-gravity library.
+ *
+ * What is computed follows Ferrari, Lavagna & Blazquez, "A parallel-GPU code
+ * for asteroid aggregation problems with angular particles" (MNRAS 2020),
+ * Section "Gravitational dynamics":
+ *   - the direct N^2 sum of eq. (Newton), every term softened as in
+ *     eq. (Force_rComp): a_i = G sum_{j != i} m_j d_ij / (|d_ij|^2 + eps_ij^2)^(3/2),
+ *     d_ij = x_j - x_i;
+ *   - an octree rebuilt on every call (subsection "Hierarchical treecode
+ *     algorithm"): a root cube around the bounding box, split homogeneously
+ *     into octants until a cell holds at most `leaf_size` bodies (or is 21
+ *     levels deep), with node mass and centre of mass from eq. (COMinternal);
+ *   - a per-body walk from the root (subsection "Force computation"): a leaf
+ *     adds its bodies one by one (eq. Force_leaf), an internal node of side s
+ *     at distance D = |COM - x_B| is accepted as one mass at its centre of mass
+ *     when s^2 < theta^2 D^2 (eqs. accuracy, Force_thetaTrue), otherwise all of
+ *     its children are visited;
+ *   - a kick-drift-kick leapfrog (Section "Numerical solvers" lists leapfrog
+ *     among the symplectic steppers).
+ * Outputs are accelerations (force / m_B). With per-body softening lengths
+ * eps_i the pair softening is eps_ij^2 = (eps_i^2 + eps_j^2) / 2 and a node
+ * term uses (eps_B^2 + <eps^2>_N) / 2, <eps^2>_N mass-weighted over the node.
+ *
+ * Memory: every array argument is a DEVICE pointer owned by the caller.
+ *   pos, vel, acc : n x 3 row-major float64 (x0 y0 z0 x1 y1 z1 ...)
+ *   mass          : n float64, >= 0
+ *   eps           : n float64 per-body softening lengths, or NULL to use the
+ *                   scalar `softening` for every term
+ *   phi           : n float64 potential (-G sum m_j / r), or NULL
+ * Outputs are written in the caller's body order.
+ *
+ * Execution: all compute calls are asynchronous on the context's HIP stream
+ * and return after enqueueing. Host-detectable argument errors return at once
+ * with nothing enqueued. Errors found on the device (non-finite input,
+ * negative mass, walk stack overflow, node table overflow) are latched in the
+ * context and returned by the next bh_sync(); outputs of a failed call are
+ * undefined. A context is not thread-safe; use one per stream.
+ */
+#ifndef BHX_H
+#define BHX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bh_ctx bh_ctx;
+
+typedef enum {
+    BH_OK = 0,
+    BH_E_INVALID = 1,   /* bad argument, found on the host; nothing enqueued */
+    BH_E_NONFINITE = 2, /* device found a NaN/Inf position, mass or softening, or a negative mass */
+    BH_E_CAPACITY = 3,  /* n > n_max, or the node table overflowed */
+    BH_E_OOM = 4,       /* device allocation failed */
+    BH_E_HIP = 5,       /* a HIP runtime call failed; see bh_last_error() */
+    BH_E_STACK = 6,     /* the tree walk overflowed its traversal stack */
+    BH_E_STATE = 7      /* call out of order, e.g. bh_tree_export() before any build */
+} bh_status;
+
+/* precision of the pairwise terms */
+enum { BH_FP64 = 0, BH_FP32C = 1 };
+
+/* bh_config.flags */
+enum {
+    BH_FLAG_COUNTS = 1u, /* keep per-body walk counts for bh_walk_counts() */
+    BH_FLAG_TIMING = 2u  /* record HIP events around every tree build and walk
+                            on the context's stream; totals in bh_stats() */
+};
+
+typedef struct {
+    int64_t n_max;     /* largest n any call will pass; workspace is sized for it */
+    int32_t leaf_size; /* bucket size: a cell with more bodies is split; 1..64 */
+    int32_t precision; /* BH_FP64: all FP64. BH_FP32C: FP32 pair terms on
+                          coordinates relative to the target group, FP32 partial
+                          sums flushed to FP64 accumulators; FP64 positions,
+                          opening test, moments and outputs */
+    double G;          /* gravitational constant */
+    uint32_t flags;    /* BH_FLAG_* */
+} bh_config;
+
+/* Creates a context on the current HIP device, bound to `hip_stream`
+ * (a hipStream_t; NULL = the null stream). Allocates the whole workspace for
+ * cfg->n_max bodies, including the worst-case node table, so later calls never
+ * allocate. Errors: BH_E_INVALID (NULL pointers, n_max < 0, leaf_size outside
+ * 1..64, precision unknown, G not finite), BH_E_OOM, BH_E_HIP. */
+bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out);
+
+/* Frees the context and its workspace after waiting for its stream. NULL is a no-op. */
+void bh_destroy(bh_ctx *ctx);
+
+/* Rebinds the context to another HIP stream (later calls enqueue there). */
+bh_status bh_set_stream(bh_ctx *ctx, void *hip_stream);
+
+/* Waits for the context's stream, then returns and clears the latched device
+ * status (BH_OK if every call since the last bh_sync succeeded). */
+bh_status bh_sync(bh_ctx *ctx);
+
+/* Text of the last error on this context (never NULL; "" when none). */
+const char *bh_last_error(const bh_ctx *ctx);
+
+/* Builds the octree of n bodies (bounding cube, Morton keys, stable radix
+ * sort, level-by-level octree, bottom-up moments by eq. COMinternal) and keeps
+ * it in the context until the next build. eps may be NULL (uniform softening:
+ * node softening moments are not formed). Errors: BH_E_INVALID (n < 0, NULL
+ * pointers with n > 0), BH_E_CAPACITY (n > n_max); device: BH_E_NONFINITE. */
+bh_status bh_build_tree(bh_ctx *ctx, const double *pos, const double *mass, const double *eps,
+                        int64_t n);
+
+/* Barnes-Hut accelerations: builds the tree as bh_build_tree() does, then walks
+ * it once per body with opening parameter theta (>= 0; 0 opens every node and
+ * gives the direct sum's pair set). softening >= 0 is used when eps == NULL.
+ * acc (n x 3) is overwritten; phi may be NULL. Errors: as bh_build_tree, plus
+ * BH_E_INVALID for theta or softening negative or not finite, acc == NULL;
+ * device: BH_E_STACK. */
+bh_status bh_compute_accel(bh_ctx *ctx, const double *pos, const double *mass, double softening,
+                           const double *eps, double theta, double *acc, double *phi, int64_t n);
+
+/* Direct N^2 accelerations (eq. Newton with softening), all pairs j != i.
+ * Same arguments and errors as bh_compute_accel without theta. */
+bh_status bh_compute_accel_direct(bh_ctx *ctx, const double *pos, const double *mass,
+                                  double softening, const double *eps, double *acc, double *phi,
+                                  int64_t n);
+
+/* nsteps kick-drift-kick leapfrog steps of dt, in place on pos and vel:
+ * v += dt/2 a; x += dt v; a = A(x); v += dt/2 a. `acc` must hold the
+ * acceleration at the input positions (e.g. from bh_compute_accel) and is
+ * updated, so consecutive calls do one force evaluation per step. theta >= 0
+ * selects the tree, theta < 0 the direct sum. Errors: as bh_compute_accel,
+ * plus BH_E_INVALID for nsteps < 0, dt not finite, vel == NULL. */
+bh_status bh_step_leapfrog(bh_ctx *ctx, double *pos, double *vel, const double *mass,
+                           double softening, const double *eps, double theta, double dt,
+                           int32_t nsteps, double *acc, int64_t n);
+
+/* Per-body walk counts of the last bh_compute_accel / bh_step_leapfrog force
+ * evaluation (tree mode), in caller order: counts[2i] = accepted internal
+ * nodes, counts[2i+1] = leaf body pairs. counts is a device pointer to n x 2
+ * int32. Needs BH_FLAG_COUNTS at creation (else BH_E_STATE); n must equal the
+ * last walk's n (else BH_E_INVALID). */
+bh_status bh_walk_counts(bh_ctx *ctx, int32_t *counts, int64_t n);
+
+/* Borrowed device view of the tree of the last build, valid until the next
+ * build or bh_destroy. Bodies are held in Morton order: order[s] is the caller
+ * index of the s-th sorted body and keys[s] its 63-bit Morton key (the three
+ * 21-bit integer cell coordinates interleaved, x bit most significant in each
+ * triplet). Node k, packed:
+ *   info[4k..4k+3] = {first, count, child0, level | (nchild << 8)}: the cell's
+ *     bodies are sorted positions first .. first+count-1; child0 is the index
+ *     of its first child (children are contiguous, in octant order) or -1 for
+ *     a leaf; level is 0..21 and nchild 0..8;
+ *   mom[4k..4k+3] = {centre of mass x, y, z, mass};
+ *   eps2[k] = <eps^2>_N, or eps2 == NULL when the build had no per-body eps.
+ * Node 0 is the root. box = {lo_x, lo_y, lo_z, x0_x, x0_y, x0_z, L, S}: the
+ * per-axis minimum, root cube corner, side, and quantisation scale 2^21 / L.
+ * nnodes and depth are read back from the device, so this call synchronises
+ * the stream. Errors: BH_E_STATE if no tree was built. */
+typedef struct {
+    int64_t n, nnodes;
+    int32_t depth, pad;
+    const int32_t *info;
+    const double *mom;
+    const double *eps2;
+    const uint32_t *order;
+    const uint64_t *keys;
+    double box[8];
+} bh_tree_view;
+bh_status bh_tree_export(bh_ctx *ctx, bh_tree_view *out);
+
+/* Summary (synchronises): node count and depth of the last build; totals of
+ * accepted nodes and leaf pairs over all bodies of the last walk (0 unless
+ * BH_FLAG_COUNTS); with BH_FLAG_TIMING, the number of tree force evaluations
+ * and the summed device time (ms, HIP events on the context's stream) of their
+ * build and walk phases since creation or the last bh_timing_reset(). */
+typedef struct {
+    int64_t nnodes;
+    int32_t depth;
+    int32_t pad;
+    int64_t total_nodes_accepted, total_leaf_pairs;
+    int64_t timed_evals;
+    double build_ms, walk_ms;
+} bh_stats_t;
+bh_status bh_stats(bh_ctx *ctx, bh_stats_t *out);
+
+/* Zeroes the BH_FLAG_TIMING totals (synchronises). */
+bh_status bh_timing_reset(bh_ctx *ctx);
+
+/* Energy and momenta of a state, by FP64 reductions on the device:
+ * out (host, 8 doubles) = {E_kin, E_pot, Px, Py, Pz, Lx, Ly, Lz}, with
+ * E_pot = 1/2 sum m_i phi_i from the direct sum and L about the origin.
+ * Synchronises. Errors: as bh_compute_accel_direct. */
+bh_status bh_diagnostics(bh_ctx *ctx, const double *pos, const double *vel, const double *mass,
+                         double softening, const double *eps, double out[8], int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BHX_H */

@@ -1,0 +1,26 @@
+"""MI355X-native Barnes-Hut / direct-sum self-gravity (gfx950 HIP kernels).
+
+Implements the gravity hot path of Ferrari, Lavagna & Blazquez, "A
+parallel-GPU code for asteroid aggregation problems with angular particles"
+(MNRAS 2020): octree Barnes-Hut accelerations rebuilt every step, the direct
+N^2 sum, and a kick-drift-kick leapfrog. The kernels live in libbhx.so
+(C ABI in include/bhx.h); this package only marshals torch tensors.
+"""
+from __future__ import annotations
+
+__all__ = ["Context", "BHError", "load_library"]
+
+
+def load_library():
+    """Loads libbhx.so (raises if it has not been built)."""
+    from . import _lib
+
+    return _lib.load()
+
+
+def __getattr__(name):
+    if name in ("Context", "BHError"):
+        from . import api
+
+        return getattr(api, name)
+    raise AttributeError(name)

@@ -1,0 +1,228 @@
+"""Python entry points over libbhx: torch tensors in, torch tensors out.
+
+torch supplies device memory and the current HIP stream; every step of the
+computation runs in the library's HIP kernels. There is no CPU fallback: a
+missing library or a non-GPU tensor raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+
+
+_hip = None
+
+
+def _hip_copy_d2d(dst: int, src: int, nbytes: int):
+    """Synchronous device-to-device copy through the HIP runtime."""
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        _hip.hipMemcpy.restype = C.c_int
+    rc = _hip.hipMemcpy(C.c_void_p(dst), C.c_void_p(src), C.c_size_t(nbytes), 3)
+    if rc != 0:
+        raise RuntimeError(f"hipMemcpy failed ({rc})")
+
+
+class BHError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        name = L.STATUS_NAMES[status] if 0 <= status < len(L.STATUS_NAMES) else str(status)
+        super().__init__(f"{name}: {msg}")
+        self.status = status
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check_f64(name, t, shape, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor (got {t.device})")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64 (got {t.dtype})")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)} (got {tuple(t.shape)})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+@dataclass
+class TreeView:
+    n: int
+    nnodes: int
+    depth: int
+    info: torch.Tensor   # (nnodes, 4) int32: first, count, child0, level | nchild << 8
+    mom: torch.Tensor    # (nnodes, 4) float64: com x, y, z, mass
+    eps2: torch.Tensor | None
+    order: torch.Tensor  # (n,) int64 caller index of each sorted body
+    keys: torch.Tensor   # (n,) int64 Morton keys
+    box: list
+
+
+class Context:
+    """One library context: workspace for up to ``n_max`` bodies on the current device.
+
+    precision: "fp64" (all FP64) or "fp32c" (FP32 pair terms with FP32 partial
+    sums flushed to FP64, FP64 state and opening test).
+    """
+
+    def __init__(self, n_max: int, leaf_size: int = 16, precision: str = "fp32c", G: float = 1.0,
+                 counts: bool = False, timing: bool = False):
+        self._lib = L.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: libbhx runs on the GPU only")
+        prec = {"fp64": L.BH_FP64, "fp32c": L.BH_FP32C}[precision]
+        flags = (L.BH_FLAG_COUNTS if counts else 0) | (L.BH_FLAG_TIMING if timing else 0)
+        cfg = L.bh_config(int(n_max), int(leaf_size), prec, float(G), flags)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.n_max, self.leaf_size, self.precision, self.G = int(n_max), int(leaf_size), precision, float(G)
+        h = C.c_void_p()
+        rc = self._lib.bh_create(C.byref(cfg), C.c_void_p(self._stream()), C.byref(h))
+        if rc != 0:
+            raise BHError(rc, "bh_create failed")
+        self._h = h
+
+    # -- plumbing
+    def _stream(self) -> int:
+        return torch.cuda.current_stream().cuda_stream
+
+    def _bind(self):
+        self._lib.bh_set_stream(self._h, C.c_void_p(self._stream()))
+
+    def _rc(self, rc):
+        if rc != 0:
+            raise BHError(rc, self._lib.bh_last_error(self._h).decode())
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.bh_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sync(self):
+        """Waits for queued work and raises on a latched device error."""
+        self._rc(self._lib.bh_sync(self._h))
+
+    def _bodies(self, pos, mass, eps):
+        n = int(pos.shape[0]) if pos.dim() == 2 else -1
+        _check_f64("pos", pos, (n, 3), self.device)
+        _check_f64("mass", mass, (n,), self.device)
+        if eps is not None:
+            _check_f64("eps", eps, (n,), self.device)
+        return n
+
+    # -- entry points
+    def build_tree(self, pos, mass, eps=None, sync=True):
+        n = self._bodies(pos, mass, eps)
+        self._bind()
+        self._rc(self._lib.bh_build_tree(self._h, _ptr(pos), _ptr(mass), _ptr(eps), n))
+        if sync:
+            self.sync()
+
+    def compute_accel(self, pos, mass, theta, softening=0.0, eps=None, out=None, potential=False,
+                      sync=True):
+        """Barnes-Hut accelerations (n, 3); with potential=True returns (acc, phi)."""
+        n = self._bodies(pos, mass, eps)
+        acc = out if out is not None else torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        _check_f64("out", acc, (n, 3), self.device)
+        phi = torch.empty(n, dtype=torch.float64, device=self.device) if potential else None
+        self._bind()
+        self._rc(self._lib.bh_compute_accel(self._h, _ptr(pos), _ptr(mass), float(softening),
+                                            _ptr(eps), float(theta), _ptr(acc), _ptr(phi), n))
+        if sync:
+            self.sync()
+        return (acc, phi) if potential else acc
+
+    def compute_accel_direct(self, pos, mass, softening=0.0, eps=None, out=None, potential=False,
+                             sync=True):
+        """Direct N^2 accelerations (n, 3); with potential=True returns (acc, phi)."""
+        n = self._bodies(pos, mass, eps)
+        acc = out if out is not None else torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        _check_f64("out", acc, (n, 3), self.device)
+        phi = torch.empty(n, dtype=torch.float64, device=self.device) if potential else None
+        self._bind()
+        self._rc(self._lib.bh_compute_accel_direct(self._h, _ptr(pos), _ptr(mass), float(softening),
+                                                   _ptr(eps), _ptr(acc), _ptr(phi), n))
+        if sync:
+            self.sync()
+        return (acc, phi) if potential else acc
+
+    def step_leapfrog(self, pos, vel, mass, acc, dt, nsteps, theta=0.5, softening=0.0, eps=None,
+                      sync=True):
+        """nsteps KDK steps in place on pos, vel and acc (theta < 0: direct sum)."""
+        n = self._bodies(pos, mass, eps)
+        _check_f64("vel", vel, (n, 3), self.device)
+        _check_f64("acc", acc, (n, 3), self.device)
+        self._bind()
+        self._rc(self._lib.bh_step_leapfrog(self._h, _ptr(pos), _ptr(vel), _ptr(mass),
+                                            float(softening), _ptr(eps), float(theta), float(dt),
+                                            int(nsteps), _ptr(acc), n))
+        if sync:
+            self.sync()
+
+    def walk_counts(self, n):
+        """(n, 2) int32 per-body counts of the last tree walk: accepted nodes, leaf pairs."""
+        out = torch.empty((n, 2), dtype=torch.int32, device=self.device)
+        self._bind()
+        self._rc(self._lib.bh_walk_counts(self._h, _ptr(out), int(n)))
+        self.sync()
+        return out
+
+    def tree(self) -> TreeView:
+        """Copies of the last built tree (synchronises)."""
+        self._bind()
+        v = L.bh_tree_view()
+        self._rc(self._lib.bh_tree_export(self._h, C.byref(v)))
+        nn, n = int(v.nnodes), int(v.n)
+
+        def dev(ptr, count, dtype):
+            out = torch.empty(count, dtype=dtype, device=self.device)
+            if count:
+                torch.cuda.synchronize()
+                _hip_copy_d2d(out.data_ptr(), ptr, count * out.element_size())
+            return out
+
+        info = dev(v.info, 4 * nn, torch.int32).view(nn, 4)
+        mom = dev(v.mom, 4 * nn, torch.float64).view(nn, 4)
+        eps2 = dev(v.eps2, nn, torch.float64) if v.eps2 else None
+        order = dev(v.order, n, torch.int32).to(torch.int64) & 0xFFFFFFFF
+        keys = dev(v.keys, n, torch.int64)
+        return TreeView(n, nn, int(v.depth), info, mom, eps2, order, keys, list(v.box))
+
+    def stats(self) -> dict:
+        s = L.bh_stats_t()
+        self._bind()
+        self._rc(self._lib.bh_stats(self._h, C.byref(s)))
+        return {"nnodes": int(s.nnodes), "depth": int(s.depth),
+                "nodes_accepted": int(s.total_nodes_accepted), "leaf_pairs": int(s.total_leaf_pairs),
+                "timed_evals": int(s.timed_evals), "build_ms": float(s.build_ms),
+                "walk_ms": float(s.walk_ms)}
+
+    def timing_reset(self):
+        self._bind()
+        self._rc(self._lib.bh_timing_reset(self._h))
+
+    def diagnostics(self, pos, vel, mass, softening=0.0, eps=None):
+        """[E_kin, E_pot, Px, Py, Pz, Lx, Ly, Lz] (host floats)."""
+        n = self._bodies(pos, mass, eps)
+        _check_f64("vel", vel, (n, 3), self.device)
+        out = (C.c_double * 8)()
+        self._bind()
+        self._rc(self._lib.bh_diagnostics(self._h, _ptr(pos), _ptr(vel), _ptr(mass),
+                                          float(softening), _ptr(eps), out, n))
+        return [float(x) for x in out]

@@ -1,0 +1,121 @@
+// Internal declarations shared by the HIP translation units of libbhx.
+// Device data layout, the tree header, and the kernel launchers each unit
+// provides. Nothing here is part of the C ABI (include/bhx.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bhx.h"
+
+namespace bhx {
+
+constexpr int kMaxLevel = 21;           // cells on a 2^21 grid per axis
+constexpr int kLevels = kMaxLevel + 1;  // levels 0..21
+constexpr uint32_t kQMax = 2097151u;    // 2^21 - 1
+
+// Device status bits, latched until bh_sync().
+enum : uint32_t { ST_NONFINITE = 1u, ST_CAPACITY = 2u, ST_STACK = 4u };
+
+// One body in Morton order: position and mass (32 B, one aligned load pair).
+struct alignas(32) Body {
+    double x, y, z, m;
+};
+
+// One node's moments: centre of mass and mass.
+struct alignas(32) NodeMom {
+    double x, y, z, m;
+};
+
+// One node's structure: sorted body range, first child (-1 for a leaf),
+// level in bits 0..7 and number of children in bits 8..15.
+struct alignas(16) NodeInfo {
+    int32_t first, count, child0, lvl_nch;
+};
+
+__host__ __device__ inline int node_level(const NodeInfo &i) { return i.lvl_nch & 0xff; }
+__host__ __device__ inline int node_nchild(const NodeInfo &i) { return (i.lvl_nch >> 8) & 0xff; }
+
+// Tree header, written on the device by the build and read by later kernels,
+// so a whole force evaluation runs without host round trips.
+struct TreeHeader {
+    double lo[3], hi[3];  // per-axis bounding box
+    double L, S;          // root cube side and quantisation scale 2^21 / L
+    double x0[3];         // root cube corner
+    double s2[kLevels];   // squared cell side per level
+    int32_t level_count[kLevels + 1];  // nodes created per level
+    uint32_t status;                   // ST_* bits
+    int32_t pad;
+};
+
+// Workspace owned by a context; sized once for n_max bodies.
+struct Workspace {
+    int64_t n_cap = 0, node_cap = 0;
+    int sort_blocks_cap = 0, bbox_blocks = 0;
+    uint64_t *keys[2] = {nullptr, nullptr};
+    uint32_t *idx[2] = {nullptr, nullptr};
+    uint32_t *sort_counts = nullptr;  // [256][sort blocks], scanned per digit row
+    uint32_t *sort_totals = nullptr;  // [256]
+    Body *body = nullptr;             // sorted bodies
+    double *beps2 = nullptr;          // sorted eps^2
+    NodeInfo *ninfo = nullptr;
+    NodeMom *nmom = nullptr;
+    double *neps2 = nullptr;
+    double *bbox_part = nullptr;  // [bbox blocks][6]
+    TreeHeader *hdr = nullptr;
+    int32_t *counts = nullptr;    // [n_cap][2] per-body walk counts, caller order
+    double *scratch = nullptr;    // [n_cap] potential for diagnostics
+    double *red_part = nullptr;   // [reduction blocks][8]
+};
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kBboxBlocks = 512;
+constexpr int kRedBlocks = 512;
+
+// Upper bound on the node count of a tree of n bodies with the given bucket
+// size: every level below the root holds at most min(n, 8 n / (leaf + 1))
+// nodes, because its nodes are disjoint non-empty children of cells holding
+// more than `leaf` bodies.
+inline int64_t node_capacity(int64_t n, int leaf)
+{
+    if (n <= 0) return 1;
+    int64_t internal = n / (leaf + 1);
+    int64_t per_level = 8 * internal < n ? 8 * internal : n;
+    return 1 + (int64_t)kMaxLevel * per_level;
+}
+
+// Launchers (tree.hip). All enqueue on `s` and never synchronise.
+hipError_t launch_build(const Workspace &w, hipStream_t s, const double *pos, const double *mass,
+                        const double *eps, int64_t n, int leaf);
+
+struct WalkParams {
+    int64_t n;
+    double th2;     // theta^2
+    double eps0sq;  // uniform softening squared (per-body eps not given)
+    double G;
+    double *acc;    // caller order, n x 3
+    double *phi;    // caller order or nullptr
+    int32_t *counts;  // caller order n x 2 or nullptr
+    bool per_body_eps;
+    int precision;
+};
+// walk.hip
+hipError_t launch_walk(const Workspace &w, hipStream_t s, const WalkParams &p);
+
+// direct.hip
+hipError_t launch_direct(hipStream_t s, const double *pos, const double *mass, const double *eps,
+                         int64_t n, double eps0sq, double G, int precision, double *acc,
+                         double *phi);
+
+// integrate.hip
+hipError_t launch_kick_drift(hipStream_t s, double *pos, double *vel, const double *acc, int64_t n,
+                             double dt);
+hipError_t launch_kick(hipStream_t s, double *vel, const double *acc, int64_t n, double dt);
+hipError_t launch_diag_reduce(hipStream_t s, const double *pos, const double *vel,
+                              const double *mass, const double *phi, int64_t n, double *part,
+                              double *out8_device);
+
+}  // namespace bhx

@@ -1,0 +1,414 @@
+// C ABI of libbhx (declared in include/bhx.h): context and workspace
+// ownership, host-side argument checks, launch sequencing on the caller's
+// stream, and the device status latch.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bhx_impl.h"
+
+using bhx::Workspace;
+
+struct bh_ctx {
+    bh_config cfg{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    Workspace w;
+    std::string err;
+    int64_t tree_n = -1;   // n of the last build, -1 before any
+    bool tree_eps = false; // the last build had per-body eps
+    int64_t walk_n = -1;   // n of the last walk that wrote counts
+    double *diag_out = nullptr;
+    // BH_FLAG_TIMING: event triples (build start, walk start, walk end) not
+    // yet folded into the totals
+    std::vector<hipEvent_t> ev_pool;
+    int ev_used = 0;
+    int64_t timed_evals = 0;
+    double build_ms = 0.0, walk_ms = 0.0;
+};
+
+namespace {
+
+bh_status fail(bh_ctx *c, bh_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+bh_status hip_fail(bh_ctx *c, hipError_t e, const char *what)
+{
+    return fail(c, BH_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define BHX_HIP(c, call)                                   \
+    do {                                                   \
+        hipError_t e_ = (call);                            \
+        if (e_ != hipSuccess) return hip_fail(c, e_, #call); \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(T **p, int64_t count)
+{
+    if (count < 1) count = 1;
+    return hipMalloc((void **)p, (size_t)count * sizeof(T));
+}
+
+void free_ws(Workspace &w)
+{
+    void *ptrs[] = {w.keys[0], w.keys[1], w.idx[0],  w.idx[1],      w.sort_counts,
+                    w.sort_totals, w.body, w.beps2, w.ninfo, w.nmom, w.neps2, w.bbox_part,
+                    w.hdr, w.counts, w.scratch, w.red_part};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    w = Workspace{};
+}
+
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+bh_status check_bodies(bh_ctx *c, const double *pos, const double *mass, int64_t n)
+{
+    if (!c) return BH_E_INVALID;
+    if (n < 0) return fail(c, BH_E_INVALID, "n < 0");
+    if (n > c->w.n_cap) return fail(c, BH_E_CAPACITY, "n exceeds the context's n_max");
+    if (n > 0 && (!pos || !mass)) return fail(c, BH_E_INVALID, "NULL pos or mass with n > 0");
+    return BH_OK;
+}
+
+constexpr int kEvTriples = 256;
+
+// Adds the elapsed times of the recorded event triples to the totals.
+bh_status fold_timing(bh_ctx *c)
+{
+    if (c->ev_used == 0) return BH_OK;
+    BHX_HIP(c, hipEventSynchronize(c->ev_pool[3 * c->ev_used - 1]));
+    for (int t = 0; t < c->ev_used; t++) {
+        float b = 0.f, w = 0.f;
+        BHX_HIP(c, hipEventElapsedTime(&b, c->ev_pool[3 * t], c->ev_pool[3 * t + 1]));
+        BHX_HIP(c, hipEventElapsedTime(&w, c->ev_pool[3 * t + 1], c->ev_pool[3 * t + 2]));
+        c->build_ms += b;
+        c->walk_ms += w;
+        c->timed_evals++;
+    }
+    c->ev_used = 0;
+    return BH_OK;
+}
+
+bh_status record(bh_ctx *c, int which)
+{
+    if (!(c->cfg.flags & BH_FLAG_TIMING)) return BH_OK;
+    if (which == 0 && c->ev_used == kEvTriples) {
+        bh_status s = fold_timing(c);
+        if (s) return s;
+    }
+    BHX_HIP(c, hipEventRecord(c->ev_pool[3 * c->ev_used + which], c->stream));
+    if (which == 2) c->ev_used++;
+    return BH_OK;
+}
+
+bh_status force_tree(bh_ctx *c, const double *pos, const double *mass, double softening,
+                     const double *eps, double theta, double *acc, double *phi, int64_t n)
+{
+    Workspace &w = c->w;
+    bh_status st = record(c, 0);
+    if (st) return st;
+    BHX_HIP(c, bhx::launch_build(w, c->stream, pos, mass, eps, n, c->cfg.leaf_size));
+    st = record(c, 1);
+    if (st) return st;
+    c->tree_n = n;
+    c->tree_eps = eps != nullptr;
+    bhx::WalkParams p;
+    p.n = n;
+    p.th2 = theta * theta;
+    p.eps0sq = softening * softening;
+    p.G = c->cfg.G;
+    p.acc = acc;
+    p.phi = phi;
+    p.counts = (c->cfg.flags & BH_FLAG_COUNTS) ? w.counts : nullptr;
+    p.per_body_eps = eps != nullptr;
+    p.precision = c->cfg.precision;
+    BHX_HIP(c, bhx::launch_walk(w, c->stream, p));
+    if (p.counts) c->walk_n = n;
+    return record(c, 2);
+}
+
+bh_status force_direct(bh_ctx *c, const double *pos, const double *mass, double softening,
+                       const double *eps, double *acc, double *phi, int64_t n, int precision)
+{
+    BHX_HIP(c, bhx::launch_direct(c->stream, pos, mass, eps, n, softening * softening, c->cfg.G,
+                                  precision, acc, phi));
+    return BH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
+{
+    if (!cfg || !out) return BH_E_INVALID;
+    *out = nullptr;
+    if (cfg->n_max < 0 || cfg->n_max > ((int64_t)1 << 30)) return BH_E_INVALID;
+    if (cfg->leaf_size < 1 || cfg->leaf_size > 64) return BH_E_INVALID;
+    if (cfg->precision != BH_FP64 && cfg->precision != BH_FP32C) return BH_E_INVALID;
+    if (!std::isfinite(cfg->G)) return BH_E_INVALID;
+    if (cfg->flags & ~(uint32_t)(BH_FLAG_COUNTS | BH_FLAG_TIMING)) return BH_E_INVALID;
+
+    bh_ctx *c = new (std::nothrow) bh_ctx();
+    if (!c) return BH_E_OOM;
+    c->cfg = *cfg;
+    c->stream = (hipStream_t)hip_stream;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
+        delete c;
+        return BH_E_HIP;
+    }
+    Workspace &w = c->w;
+    const int64_t n = cfg->n_max > 0 ? cfg->n_max : 1;
+    w.n_cap = cfg->n_max;
+    int64_t node_cap = bhx::node_capacity(n, cfg->leaf_size);
+    if (node_cap > INT32_MAX - 16) node_cap = INT32_MAX - 16;
+    w.node_cap = node_cap;
+    w.sort_blocks_cap = (int)((n + bhx::kSortTile - 1) / bhx::kSortTile);
+    w.bbox_blocks = bhx::kBboxBlocks;
+    hipError_t r = hipSuccess;
+    auto A = [&](hipError_t x) {
+        if (r == hipSuccess) r = x;
+    };
+    A(dalloc(&w.keys[0], n));
+    A(dalloc(&w.keys[1], n));
+    A(dalloc(&w.idx[0], n));
+    A(dalloc(&w.idx[1], n));
+    A(dalloc(&w.sort_counts, (int64_t)256 * w.sort_blocks_cap));
+    A(dalloc(&w.sort_totals, 256));
+    A(dalloc(&w.body, n));
+    A(dalloc(&w.beps2, n));
+    A(dalloc(&w.ninfo, node_cap));
+    A(dalloc(&w.nmom, node_cap));
+    A(dalloc(&w.neps2, node_cap));
+    A(dalloc(&w.bbox_part, (int64_t)bhx::kBboxBlocks * 6));
+    A(dalloc(&w.hdr, 1));
+    if (cfg->flags & BH_FLAG_COUNTS) A(dalloc(&w.counts, 2 * n));
+    A(dalloc(&w.scratch, 4 * n));
+    A(dalloc(&w.red_part, (int64_t)bhx::kRedBlocks * 8));
+    A(dalloc(&c->diag_out, 8));
+    if (cfg->flags & BH_FLAG_TIMING) {
+        c->ev_pool.resize(3 * kEvTriples, nullptr);
+        for (auto &ev : c->ev_pool)
+            if (r == hipSuccess) r = hipEventCreate(&ev);
+    }
+    if (r == hipSuccess) r = hipMemset(w.hdr, 0, sizeof(bhx::TreeHeader));
+    if (r == hipSuccess) r = hipDeviceSynchronize();
+    if (r != hipSuccess) {
+        bh_status st = (r == hipErrorOutOfMemory) ? BH_E_OOM : BH_E_HIP;
+        free_ws(w);
+        if (c->diag_out) (void)hipFree(c->diag_out);
+        for (auto ev : c->ev_pool)
+            if (ev) (void)hipEventDestroy(ev);
+        delete c;
+        return st;
+    }
+    *out = c;
+    return BH_OK;
+}
+
+void bh_destroy(bh_ctx *c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_ws(c->w);
+    if (c->diag_out) (void)hipFree(c->diag_out);
+    for (auto ev : c->ev_pool)
+        if (ev) (void)hipEventDestroy(ev);
+    delete c;
+}
+
+bh_status bh_set_stream(bh_ctx *c, void *hip_stream)
+{
+    if (!c) return BH_E_INVALID;
+    c->stream = (hipStream_t)hip_stream;
+    return BH_OK;
+}
+
+const char *bh_last_error(const bh_ctx *c) { return c ? c->err.c_str() : "NULL context"; }
+
+bh_status bh_sync(bh_ctx *c)
+{
+    if (!c) return BH_E_INVALID;
+    uint32_t st = 0;
+    BHX_HIP(c, hipMemcpyAsync(&st, &c->w.hdr->status, sizeof(st), hipMemcpyDeviceToHost,
+                              c->stream));
+    BHX_HIP(c, hipStreamSynchronize(c->stream));
+    if (st == 0) return BH_OK;
+    const uint32_t zero = 0;
+    BHX_HIP(c, hipMemcpyAsync(&c->w.hdr->status, &zero, sizeof(zero), hipMemcpyHostToDevice,
+                              c->stream));
+    BHX_HIP(c, hipStreamSynchronize(c->stream));
+    if (st & bhx::ST_NONFINITE)
+        return fail(c, BH_E_NONFINITE, "non-finite position, mass or softening, or negative mass");
+    if (st & bhx::ST_CAPACITY) return fail(c, BH_E_CAPACITY, "node table overflow");
+    return fail(c, BH_E_STACK, "tree walk stack overflow");
+}
+
+bh_status bh_build_tree(bh_ctx *c, const double *pos, const double *mass, const double *eps,
+                        int64_t n)
+{
+    bh_status s = check_bodies(c, pos, mass, n);
+    if (s) return s;
+    BHX_HIP(c, bhx::launch_build(c->w, c->stream, pos, mass, eps, n, c->cfg.leaf_size));
+    c->tree_n = n;
+    c->tree_eps = eps != nullptr;
+    return BH_OK;
+}
+
+bh_status bh_compute_accel(bh_ctx *c, const double *pos, const double *mass, double softening,
+                           const double *eps, double theta, double *acc, double *phi, int64_t n)
+{
+    bh_status s = check_bodies(c, pos, mass, n);
+    if (s) return s;
+    if (!finite_nonneg(theta)) return fail(c, BH_E_INVALID, "theta must be finite and >= 0");
+    if (!finite_nonneg(softening)) return fail(c, BH_E_INVALID, "softening must be finite and >= 0");
+    if (n > 0 && !acc) return fail(c, BH_E_INVALID, "NULL acc");
+    return force_tree(c, pos, mass, softening, eps, theta, acc, phi, n);
+}
+
+bh_status bh_compute_accel_direct(bh_ctx *c, const double *pos, const double *mass,
+                                  double softening, const double *eps, double *acc, double *phi,
+                                  int64_t n)
+{
+    bh_status s = check_bodies(c, pos, mass, n);
+    if (s) return s;
+    if (!finite_nonneg(softening)) return fail(c, BH_E_INVALID, "softening must be finite and >= 0");
+    if (n > 0 && !acc) return fail(c, BH_E_INVALID, "NULL acc");
+    return force_direct(c, pos, mass, softening, eps, acc, phi, n, c->cfg.precision);
+}
+
+bh_status bh_step_leapfrog(bh_ctx *c, double *pos, double *vel, const double *mass,
+                           double softening, const double *eps, double theta, double dt,
+                           int32_t nsteps, double *acc, int64_t n)
+{
+    bh_status s = check_bodies(c, pos, mass, n);
+    if (s) return s;
+    if (std::isnan(theta) || std::isinf(theta)) return fail(c, BH_E_INVALID, "theta not finite");
+    if (!finite_nonneg(softening)) return fail(c, BH_E_INVALID, "softening must be finite and >= 0");
+    if (!std::isfinite(dt)) return fail(c, BH_E_INVALID, "dt not finite");
+    if (nsteps < 0) return fail(c, BH_E_INVALID, "nsteps < 0");
+    if (n > 0 && (!vel || !acc)) return fail(c, BH_E_INVALID, "NULL vel or acc");
+    for (int32_t k = 0; k < nsteps && n > 0; k++) {
+        BHX_HIP(c, bhx::launch_kick_drift(c->stream, pos, vel, acc, n, dt));
+        s = theta >= 0.0 ? force_tree(c, pos, mass, softening, eps, theta, acc, nullptr, n)
+                         : force_direct(c, pos, mass, softening, eps, acc, nullptr, n,
+                                        c->cfg.precision);
+        if (s) return s;
+        BHX_HIP(c, bhx::launch_kick(c->stream, vel, acc, n, dt));
+    }
+    return BH_OK;
+}
+
+bh_status bh_walk_counts(bh_ctx *c, int32_t *counts, int64_t n)
+{
+    if (!c) return BH_E_INVALID;
+    if (!(c->cfg.flags & BH_FLAG_COUNTS) || c->walk_n < 0)
+        return fail(c, BH_E_STATE, "no walk counts (BH_FLAG_COUNTS unset or no tree walk yet)");
+    if (n != c->walk_n) return fail(c, BH_E_INVALID, "n differs from the last walk");
+    if (n > 0 && !counts) return fail(c, BH_E_INVALID, "NULL counts");
+    if (n > 0)
+        BHX_HIP(c, hipMemcpyAsync(counts, c->w.counts, (size_t)n * 2 * sizeof(int32_t),
+                                  hipMemcpyDeviceToDevice, c->stream));
+    return BH_OK;
+}
+
+bh_status bh_tree_export(bh_ctx *c, bh_tree_view *out)
+{
+    if (!c || !out) return BH_E_INVALID;
+    if (c->tree_n < 0) return fail(c, BH_E_STATE, "no tree has been built");
+    bhx::TreeHeader h;
+    BHX_HIP(c, hipMemcpyAsync(&h, c->w.hdr, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    BHX_HIP(c, hipStreamSynchronize(c->stream));
+    int64_t nn = 0;
+    int depth = 0;
+    for (int l = 0; l < bhx::kLevels; l++) {
+        int64_t cnt = h.level_count[l];
+        if (cnt > c->w.node_cap - nn) cnt = c->w.node_cap - nn;
+        nn += cnt;
+        if (cnt > 0) depth = l;
+    }
+    std::memset(out, 0, sizeof(*out));
+    out->n = c->tree_n;
+    out->nnodes = nn;
+    out->depth = depth;
+    out->info = (const int32_t *)c->w.ninfo;
+    out->mom = (const double *)c->w.nmom;
+    out->eps2 = c->tree_eps ? c->w.neps2 : nullptr;
+    out->order = c->w.idx[0];
+    out->keys = c->w.keys[0];
+    for (int a = 0; a < 3; a++) {
+        out->box[a] = h.lo[a];
+        out->box[3 + a] = h.x0[a];
+    }
+    out->box[6] = h.L;
+    out->box[7] = h.S;
+    return BH_OK;
+}
+
+bh_status bh_stats(bh_ctx *c, bh_stats_t *out)
+{
+    if (!c || !out) return BH_E_INVALID;
+    bh_tree_view v;
+    bh_status s = bh_tree_export(c, &v);
+    if (s) return s;
+    std::memset(out, 0, sizeof(*out));
+    out->nnodes = v.nnodes;
+    out->depth = v.depth;
+    if (c->walk_n > 0) {
+        std::vector<int32_t> h((size_t)c->walk_n * 2);
+        BHX_HIP(c, hipMemcpyAsync(h.data(), c->w.counts, h.size() * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, c->stream));
+        BHX_HIP(c, hipStreamSynchronize(c->stream));
+        for (size_t i = 0; i < h.size(); i += 2) {
+            out->total_nodes_accepted += h[i];
+            out->total_leaf_pairs += h[i + 1];
+        }
+    }
+    s = fold_timing(c);
+    if (s) return s;
+    out->timed_evals = c->timed_evals;
+    out->build_ms = c->build_ms;
+    out->walk_ms = c->walk_ms;
+    return BH_OK;
+}
+
+bh_status bh_timing_reset(bh_ctx *c)
+{
+    if (!c) return BH_E_INVALID;
+    bh_status s = fold_timing(c);
+    if (s) return s;
+    c->timed_evals = 0;
+    c->build_ms = c->walk_ms = 0.0;
+    return BH_OK;
+}
+
+bh_status bh_diagnostics(bh_ctx *c, const double *pos, const double *vel, const double *mass,
+                         double softening, const double *eps, double out[8], int64_t n)
+{
+    bh_status s = check_bodies(c, pos, mass, n);
+    if (s) return s;
+    if (!out) return fail(c, BH_E_INVALID, "NULL out");
+    if (!finite_nonneg(softening)) return fail(c, BH_E_INVALID, "softening must be finite and >= 0");
+    if (n > 0 && !vel) return fail(c, BH_E_INVALID, "NULL vel");
+    for (int k = 0; k < 8; k++) out[k] = 0.0;
+    if (n == 0) return BH_OK;
+    double *acc_tmp = c->w.scratch, *phi = c->w.scratch + 3 * n;
+    s = force_direct(c, pos, mass, softening, eps, acc_tmp, phi, n, BH_FP64);
+    if (s) return s;
+    BHX_HIP(c, bhx::launch_diag_reduce(c->stream, pos, vel, mass, phi, n, c->w.red_part,
+                                       c->diag_out));
+    BHX_HIP(c, hipMemcpyAsync(out, c->diag_out, 8 * sizeof(double), hipMemcpyDeviceToHost,
+                              c->stream));
+    BHX_HIP(c, hipStreamSynchronize(c->stream));
+    return BH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,126 @@
+// Direct N^2 sum, eq. (Newton) with every term softened as in
+// eq. (Force_rComp): a_i = G sum_{j != i} m_j d_ij / (|d_ij|^2 + eps_ij^2)^(3/2).
+//
+// One thread per target, 256 targets per block; sources stream through LDS in
+// tiles of 256 (positions in FP64 so that d_ij is formed in FP64 even in FP32C
+// mode, where only the pair arithmetic after the difference is FP32 and each
+// tile's FP32 partial sums are added into FP64 accumulators).
+#include <type_traits>
+
+#include "bhx_impl.h"
+
+namespace bhx {
+namespace {
+
+constexpr int kTile = 256;
+
+template <int PREC, bool PEPS, bool PHI>
+__global__ __launch_bounds__(kTile) void k_direct(const double *__restrict__ pos,
+                                                  const double *__restrict__ mass,
+                                                  const double *__restrict__ eps, int64_t n,
+                                                  double eps0sq, double G,
+                                                  double *__restrict__ acc,
+                                                  double *__restrict__ phi)
+{
+    __shared__ double sx[kTile], sy[kTile], sz[kTile], sm[kTile], se[kTile];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * kTile + tid;
+    const bool valid = i < n;
+    const double xi = valid ? pos[3 * i] : 0.0, yi = valid ? pos[3 * i + 1] : 0.0,
+                 zi = valid ? pos[3 * i + 2] : 0.0;
+    double ei2 = 0.0;
+    if (PEPS && valid) {
+        const double e = eps[i];
+        ei2 = e * e;
+    }
+    const float e2hB = (float)(0.5 * ei2);
+    const float eps0f = (float)eps0sq;
+    double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+
+    for (int64_t base = 0; base < n; base += kTile) {
+        const int64_t j = base + tid;
+        if (j < n) {
+            sx[tid] = pos[3 * j];
+            sy[tid] = pos[3 * j + 1];
+            sz[tid] = pos[3 * j + 2];
+            sm[tid] = mass[j];
+            if (PEPS) {
+                const double e = eps[j];
+                se[tid] = PREC == BH_FP64 ? e * e : 0.5 * (e * e);
+            }
+        }
+        __syncthreads();
+        const int cnt = (int)((n - base) < kTile ? (n - base) : kTile);
+        const int skip = (valid && i >= base && i < base + cnt) ? (int)(i - base) : -1;
+        if constexpr (PREC == BH_FP64) {
+            for (int jj = 0; jj < cnt; jj++) {
+                const double dx = sx[jj] - xi, dy = sy[jj] - yi, dz = sz[jj] - zi;
+                const double e2 = PEPS ? 0.5 * (ei2 + se[jj]) : eps0sq;
+                const double r2 = dx * dx + dy * dy + dz * dz + e2;
+                if (jj != skip && r2 > 0.0) {
+                    const double r = sqrt(r2);
+                    const double inv3 = 1.0 / (r2 * r);
+                    ax += sm[jj] * dx * inv3;
+                    ay += sm[jj] * dy * inv3;
+                    az += sm[jj] * dz * inv3;
+                    if (PHI) ph -= sm[jj] / r;
+                }
+            }
+        } else {
+            float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
+#pragma unroll 4
+            for (int jj = 0; jj < cnt; jj++) {
+                const float dx = (float)(sx[jj] - xi), dy = (float)(sy[jj] - yi),
+                            dz = (float)(sz[jj] - zi);
+                const float e2 = PEPS ? (float)se[jj] + e2hB : eps0f;
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, e2)));
+                const float rinv = (jj != skip && r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;
+                const float mr = (float)sm[jj] * rinv;
+                const float mr3 = mr * rinv * rinv;
+                fx = fmaf(mr3, dx, fx);
+                fy = fmaf(mr3, dy, fy);
+                fz = fmaf(mr3, dz, fz);
+                if (PHI) fp -= mr;
+            }
+            ax += (double)fx;
+            ay += (double)fy;
+            az += (double)fz;
+            if (PHI) ph += (double)fp;
+        }
+        __syncthreads();
+    }
+    if (valid) {
+        acc[3 * i] = G * ax;
+        acc[3 * i + 1] = G * ay;
+        acc[3 * i + 2] = G * az;
+        if (PHI) phi[i] = G * ph;
+    }
+}
+
+template <int PREC, bool PEPS>
+hipError_t launch_p(hipStream_t s, const double *pos, const double *mass, const double *eps,
+                    int64_t n, double eps0sq, double G, double *acc, double *phi)
+{
+    const unsigned grid = (unsigned)((n + kTile - 1) / kTile);
+    if (phi)
+        k_direct<PREC, PEPS, true><<<grid, kTile, 0, s>>>(pos, mass, eps, n, eps0sq, G, acc, phi);
+    else
+        k_direct<PREC, PEPS, false><<<grid, kTile, 0, s>>>(pos, mass, eps, n, eps0sq, G, acc, phi);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_direct(hipStream_t s, const double *pos, const double *mass, const double *eps,
+                         int64_t n, double eps0sq, double G, int precision, double *acc,
+                         double *phi)
+{
+    if (n <= 0) return hipSuccess;
+    if (precision == BH_FP64)
+        return eps ? launch_p<BH_FP64, true>(s, pos, mass, eps, n, eps0sq, G, acc, phi)
+                   : launch_p<BH_FP64, false>(s, pos, mass, eps, n, eps0sq, G, acc, phi);
+    return eps ? launch_p<BH_FP32C, true>(s, pos, mass, eps, n, eps0sq, G, acc, phi)
+               : launch_p<BH_FP32C, false>(s, pos, mass, eps, n, eps0sq, G, acc, phi);
+}
+
+}  // namespace bhx

@@ -1,0 +1,513 @@
+// Octree construction on the device, rebuilt on every force evaluation
+// (subsection "Hierarchical treecode algorithm"; the five GPU stages of
+// subsection "CUDA implementation of GPU-parallel Barnes-Hut" are prior art,
+// this is a Morton-key design for CDNA4):
+//   1. bounding box of all bodies -> root cube (and input validation),
+//   2. 63-bit Morton keys on a 2^21 grid,
+//   3. stable LSD radix sort of (key, index), 8-bit digits, LDS ranking,
+//   4. gather of positions, masses and softening into Morton order,
+//   5. top-down octree, one launch per level: each split cell finds its
+//      octant ranges by binary search in the sorted keys,
+//   6. bottom-up moments, one launch per level: mass and centre of mass from
+//      the children by eq. (COMinternal), leaves from their bodies.
+// Every launch reads its sizes from the device tree header, so the sequence
+// needs no host round trip and can be captured in a graph.
+#include <cmath>
+
+#include "bhx_impl.h"
+
+namespace bhx {
+namespace {
+
+constexpr double kInf = __builtin_huge_val();
+
+__device__ inline uint64_t lanemask_lt(int lane) { return (1ull << lane) - 1ull; }
+
+template <typename T>
+__device__ inline T wave_min(T v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+template <typename T>
+__device__ inline T wave_max(T v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Inclusive scan over a 256-thread block (4 waves).
+__device__ inline uint32_t block_incl_scan_256(uint32_t v, uint32_t *lds4, uint32_t *total)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    if (lane == 63) lds4[wave] = v;
+    __syncthreads();
+    uint32_t add = 0, tot = 0;
+    for (int w = 0; w < 4; w++) {
+        uint32_t x = lds4[w];
+        if (w < wave) add += x;
+        tot += x;
+    }
+    __syncthreads();
+    *total = tot;
+    return v + add;
+}
+
+// ---------------------------------------------------------------- 1. box
+
+__global__ __launch_bounds__(256) void k_bbox_partial(const double *__restrict__ pos,
+                                                      const double *__restrict__ mass,
+                                                      const double *__restrict__ eps, int64_t n,
+                                                      double *__restrict__ part,
+                                                      TreeHeader *__restrict__ hdr)
+{
+    double lo[3] = {kInf, kInf, kInf}, hi[3] = {-kInf, -kInf, -kInf};
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256) {
+        double x[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+        double m = mass[i];
+        bad |= !(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]));
+        bad |= !(isfinite(m) && m >= 0.0);
+        if (eps) {
+            double e = eps[i];
+            bad |= !(isfinite(e) && e >= 0.0);
+        }
+        for (int a = 0; a < 3; a++) {
+            lo[a] = fmin(lo[a], x[a]);
+            hi[a] = fmax(hi[a], x[a]);
+        }
+    }
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&hdr->status, ST_NONFINITE);
+    __shared__ double red[4][6];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int a = 0; a < 3; a++) {
+        double l = wave_min(lo[a]), h = wave_max(hi[a]);
+        if (lane == 0) {
+            red[wave][a] = l;
+            red[wave][3 + a] = h;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        int a = threadIdx.x;
+        double v = red[0][a];
+        for (int w = 1; w < 4; w++) v = a < 3 ? fmin(v, red[w][a]) : fmax(v, red[w][a]);
+        part[blockIdx.x * 6 + a] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bbox_final(const double *__restrict__ part, int nblk,
+                                                    int64_t n, TreeHeader *__restrict__ hdr,
+                                                    NodeInfo *__restrict__ ninfo)
+{
+#pragma clang fp contract(off)
+    double lo[3] = {kInf, kInf, kInf}, hi[3] = {-kInf, -kInf, -kInf};
+    for (int b = threadIdx.x; b < nblk; b += 256)
+        for (int a = 0; a < 3; a++) {
+            lo[a] = fmin(lo[a], part[b * 6 + a]);
+            hi[a] = fmax(hi[a], part[b * 6 + 3 + a]);
+        }
+    __shared__ double red[4][6];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int a = 0; a < 3; a++) {
+        double l = wave_min(lo[a]), h = wave_max(hi[a]);
+        if (lane == 0) {
+            red[wave][a] = l;
+            red[wave][3 + a] = h;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int a = 0; a < 6; a++) {
+        double v = red[0][a];
+        for (int w = 1; w < 4; w++) v = a < 3 ? fmin(v, red[w][a]) : fmax(v, red[w][a]);
+        if (a < 3)
+            lo[a] = v;
+        else
+            hi[a - 3] = v;
+    }
+    if (n == 0)
+        for (int a = 0; a < 3; a++) lo[a] = hi[a] = 0.0;
+    // Root cube: side = largest extent (1 if all bodies coincide), centred
+    // on the bounding box.
+    double L = 0.0;
+    for (int a = 0; a < 3; a++) {
+        double e = hi[a] - lo[a];
+        if (e > L) L = e;
+    }
+    if (L == 0.0) L = 1.0;
+    for (int a = 0; a < 3; a++) {
+        hdr->lo[a] = lo[a];
+        hdr->hi[a] = hi[a];
+        hdr->x0[a] = (lo[a] + hi[a]) * 0.5 - L * 0.5;
+    }
+    hdr->L = L;
+    hdr->S = 2097152.0 / L;
+    for (int l = 0; l < kLevels; l++) {
+        double s = ldexp(L, -l);
+        hdr->s2[l] = s * s;
+    }
+    for (int l = 0; l <= kLevels; l++) hdr->level_count[l] = 0;
+    if (n > 0) {
+        hdr->level_count[0] = 1;
+        ninfo[0] = NodeInfo{0, (int32_t)n, -1, 0};
+    }
+}
+
+// --------------------------------------------------------------- 2. keys
+
+// Spreads the low 21 bits of v so that bit i lands on bit 3i.
+__device__ inline uint64_t spread3(uint64_t v)
+{
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+// Inverse of spread3.
+__device__ inline uint32_t compact3(uint64_t v)
+{
+    v &= 0x1249249249249249ull;
+    v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
+    v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
+    v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
+    v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
+    v = (v ^ (v >> 32)) & 0x1fffffull;
+    return (uint32_t)v;
+}
+
+// Integer cell coordinate: clamp(floor((x - x0) * S), 0, 2^21 - 1), rounded
+// exactly as written so every implementation of the cell definition agrees.
+__device__ inline uint32_t quantise(double x, double x0, double S)
+{
+#pragma clang fp contract(off)
+    double f = floor((x - x0) * S);
+    if (!(f >= 0.0)) return 0u;
+    if (f > (double)kQMax) return kQMax;
+    return (uint32_t)f;
+}
+
+__global__ __launch_bounds__(256) void k_keys(const double *__restrict__ pos, int64_t n,
+                                              const TreeHeader *__restrict__ hdr,
+                                              uint64_t *__restrict__ keys,
+                                              uint32_t *__restrict__ idx)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double S = hdr->S;
+    uint32_t qx = quantise(pos[3 * i], hdr->x0[0], S);
+    uint32_t qy = quantise(pos[3 * i + 1], hdr->x0[1], S);
+    uint32_t qz = quantise(pos[3 * i + 2], hdr->x0[2], S);
+    keys[i] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+    idx[i] = (uint32_t)i;
+}
+
+// --------------------------------------------------------------- 3. sort
+
+// Per-tile digit histogram, written digit-major: counts[d * nblk + tile].
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint64_t *__restrict__ keys,
+                                                            int64_t n, int shift,
+                                                            uint32_t *__restrict__ counts,
+                                                            int nblk)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; r++) {
+        int64_t i = base + r * kSortThreads + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of one digit's row of tile counts; one block per digit.
+__global__ __launch_bounds__(256) void k_sort_scan(uint32_t *__restrict__ counts,
+                                                   uint32_t *__restrict__ totals, int nblk)
+{
+    __shared__ uint32_t lds4[4];
+    uint32_t *row = counts + (int64_t)blockIdx.x * nblk;
+    uint32_t carry = 0;
+    for (int b0 = 0; b0 < nblk; b0 += 256) {
+        int b = b0 + threadIdx.x;
+        uint32_t v = b < nblk ? row[b] : 0u, tot;
+        uint32_t incl = block_incl_scan_256(v, lds4, &tot);
+        if (b < nblk) row[b] = carry + incl - v;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
+// Stable scatter of one tile: the rank of each key among equal digits follows
+// tile order (round r, thread t) == input order.
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
+    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+    uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
+    const uint32_t *__restrict__ counts, const uint32_t *__restrict__ totals, int nblk)
+{
+    __shared__ uint32_t digit_base[256];
+    __shared__ uint32_t running[256];
+    __shared__ uint32_t wcnt[4][256];
+    __shared__ uint32_t wpre[4][256];
+    __shared__ uint32_t lds4[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    uint32_t tot;
+    uint32_t t = totals[tid];
+    uint32_t incl = block_incl_scan_256(t, lds4, &tot);
+    digit_base[tid] = incl - t + counts[(int64_t)tid * nblk + blockIdx.x];
+    running[tid] = 0;
+    for (int w = 0; w < 4; w++) wcnt[w][tid] = 0;
+
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    uint64_t k[kSortItems];
+    uint32_t v[kSortItems], dst[kSortItems];
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) {
+        int64_t i = base + r * kSortThreads + tid;
+        k[r] = i < n ? kin[i] : 0ull;
+        v[r] = i < n ? vin[i] : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) {
+        const bool valid = base + r * kSortThreads + tid < n;
+        const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bal = __ballot(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        const uint64_t lower = peers & lanemask_lt(lane);
+        if (valid && lower == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        uint32_t run = running[tid];
+        for (int w = 0; w < 4; w++) {
+            uint32_t c = wcnt[w][tid];
+            wpre[w][tid] = run;
+            run += c;
+            wcnt[w][tid] = 0;
+        }
+        running[tid] = run;
+        __syncthreads();
+        dst[r] = digit_base[d] + wpre[wave][d] + (uint32_t)__popcll(lower);
+    }
+#pragma unroll
+    for (int r = 0; r < kSortItems; r++) {
+        if (base + r * kSortThreads + tid < n) {
+            kout[dst[r]] = k[r];
+            vout[dst[r]] = v[r];
+        }
+    }
+}
+
+// ------------------------------------------------------------- 4. gather
+
+__global__ __launch_bounds__(256) void k_gather(const double *__restrict__ pos,
+                                                const double *__restrict__ mass,
+                                                const double *__restrict__ eps,
+                                                const uint32_t *__restrict__ idx, int64_t n,
+                                                Body *__restrict__ body,
+                                                double *__restrict__ beps2)
+{
+    int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    uint32_t i = idx[s];
+    body[s] = Body{pos[3 * (int64_t)i], pos[3 * (int64_t)i + 1], pos[3 * (int64_t)i + 2], mass[i]};
+    if (eps) {
+        double e = eps[i];
+        beps2[s] = e * e;
+    }
+}
+
+// -------------------------------------------------------------- 5. build
+
+// First node and node count of `level`, clamped to the node table: after an
+// overflow (flagged ST_CAPACITY) a level counter can exceed what was written.
+__device__ inline void level_range(const TreeHeader *hdr, int level, int64_t node_cap,
+                                   int32_t *beg, int32_t *cnt)
+{
+    int64_t b = 0;
+    for (int l = 0; l < level; l++) {
+        int64_t c = hdr->level_count[l];
+        b += c < node_cap - b ? c : node_cap - b;
+    }
+    int64_t c = hdr->level_count[level];
+    *beg = (int32_t)b;
+    *cnt = (int32_t)(c < node_cap - b ? c : node_cap - b);
+}
+
+// Splits every node of `level` holding more than `leaf` bodies. Eight lanes
+// per node: lane o binary-searches the first body of octant o, the group
+// reserves its non-empty children with one atomic on the next level's count
+// and writes them contiguously in octant order.
+__global__ __launch_bounds__(256) void k_build_level(int level, const uint64_t *__restrict__ keys,
+                                                     TreeHeader *__restrict__ hdr,
+                                                     NodeInfo *__restrict__ ninfo,
+                                                     int64_t node_cap, int leaf)
+{
+    int32_t beg, cnt;
+    level_range(hdr, level, node_cap, &beg, &cnt);
+    const int32_t next_beg = beg + cnt;
+    const int lane = threadIdx.x & 63, o = threadIdx.x & 7, gl = lane & ~7;
+    const int shift = 60 - 3 * level;  // bits of the child octant at level + 1
+    const int64_t stride = (int64_t)gridDim.x * 32;
+    for (int64_t g = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3); g < cnt; g += stride) {
+        const int32_t k = beg + (int32_t)g;
+        const NodeInfo info = ninfo[k];
+        if (!(info.count > leaf && level < kMaxLevel)) continue;
+        int32_t a = info.first, b = info.first + info.count;
+        while (a < b) {
+            int32_t m = (a + b) >> 1;
+            if ((int)((keys[m] >> shift) & 7ull) < o)
+                a = m + 1;
+            else
+                b = m;
+        }
+        const int32_t start = a;
+        int32_t end = __shfl_down(start, 1, 8);
+        if (o == 7) end = info.first + info.count;
+        const bool nonempty = end > start;
+        const uint32_t gm = (uint32_t)(__ballot(nonempty) >> gl) & 0xffu;
+        const int nch = __popc(gm);
+        const int rank = __popc(gm & ((1u << o) - 1u));
+        int32_t slot = 0;
+        if (o == 0) slot = atomicAdd(&hdr->level_count[level + 1], nch);
+        slot = __shfl(slot, gl);
+        const int64_t c0 = (int64_t)next_beg + slot;
+        if (c0 + nch > node_cap) {
+            if (o == 0) atomicOr(&hdr->status, ST_CAPACITY);
+            continue;
+        }
+        if (nonempty) ninfo[c0 + rank] = NodeInfo{start, end - start, -1, level + 1};
+        if (o == 0) {
+            ninfo[k].child0 = (int32_t)c0;
+            ninfo[k].lvl_nch = level | (nch << 8);
+        }
+    }
+}
+
+// ------------------------------------------------------------ 6. moments
+
+// Mass, centre of mass and mass-weighted softening of every node of `level`,
+// by eq. (COMinternal): from the children of an internal node, from the
+// bodies of a leaf. Products and sums are rounded as written.
+__global__ __launch_bounds__(256) void k_moments_level(
+    int level, const TreeHeader *__restrict__ hdr, const NodeInfo *__restrict__ ninfo,
+    const Body *__restrict__ body, const double *__restrict__ beps2,
+    const uint64_t *__restrict__ keys, NodeMom *__restrict__ nmom, double *__restrict__ neps2,
+    int64_t node_cap, int use_eps)
+{
+#pragma clang fp contract(off)
+    int32_t beg, cnt;
+    level_range(hdr, level, node_cap, &beg, &cnt);
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < cnt;
+         g += (int64_t)gridDim.x * 256) {
+        const int32_t k = beg + (int32_t)g;
+        const NodeInfo info = ninfo[k];
+        double ms = 0.0, mx = 0.0, my = 0.0, mz = 0.0, me = 0.0;
+        if (info.child0 < 0) {
+            for (int32_t s = info.first; s < info.first + info.count; s++) {
+                const Body b = body[s];
+                ms += b.m;
+                mx += b.x * b.m;
+                my += b.y * b.m;
+                mz += b.z * b.m;
+                if (use_eps) me += beps2[s] * b.m;
+            }
+        } else {
+            const int nch = node_nchild(info);
+            for (int32_t c = info.child0; c < info.child0 + nch; c++) {
+                const NodeMom cm = nmom[c];
+                ms += cm.m;
+                mx += cm.x * cm.m;
+                my += cm.y * cm.m;
+                mz += cm.z * cm.m;
+                if (use_eps) me += neps2[c] * cm.m;
+            }
+        }
+        NodeMom out;
+        double e2 = 0.0;
+        if (ms > 0.0) {
+            out = NodeMom{mx / ms, my / ms, mz / ms, ms};
+            e2 = use_eps ? me / ms : 0.0;
+        } else {
+            // massless cell: its centre
+            const uint64_t key = keys[info.first];
+            const int sh = kMaxLevel - level;
+            const double s = ldexp(hdr->L, -level);
+            out.x = hdr->x0[0] + ((double)(compact3(key >> 2) >> sh) + 0.5) * s;
+            out.y = hdr->x0[1] + ((double)(compact3(key >> 1) >> sh) + 0.5) * s;
+            out.z = hdr->x0[2] + ((double)(compact3(key) >> sh) + 0.5) * s;
+            out.m = 0.0;
+        }
+        nmom[k] = out;
+        if (use_eps) neps2[k] = e2;
+    }
+}
+
+inline unsigned blocks_for(int64_t items, int per_block, unsigned cap)
+{
+    int64_t b = (items + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    return (unsigned)(b < (int64_t)cap ? b : cap);
+}
+
+// Upper bound on the nodes of one level: at most 8^level and at most n.
+inline int64_t level_bound(int level, int64_t n)
+{
+    int64_t b = 1;
+    for (int l = 0; l < level && b < n; l++) b *= 8;
+    return b < n ? b : n;
+}
+
+}  // namespace
+
+hipError_t launch_build(const Workspace &w, hipStream_t s, const double *pos, const double *mass,
+                        const double *eps, int64_t n, int leaf)
+{
+    const unsigned nb_box = blocks_for(n, 256 * 4, kBboxBlocks);
+    k_bbox_partial<<<nb_box, 256, 0, s>>>(pos, mass, eps, n, w.bbox_part, w.hdr);
+    k_bbox_final<<<1, 256, 0, s>>>(w.bbox_part, (int)nb_box, n, w.hdr, w.ninfo);
+    if (n == 0) return hipGetLastError();
+
+    const unsigned nb = blocks_for(n, 256, 1u << 30);
+    k_keys<<<nb, 256, 0, s>>>(pos, n, w.hdr, w.keys[0], w.idx[0]);
+
+    const int nblk = (int)((n + kSortTile - 1) / kSortTile);
+    for (int pass = 0; pass < 8; pass++) {
+        const int shift = 8 * pass;
+        const int src = pass & 1, dst = src ^ 1;
+        k_sort_hist<<<nblk, kSortThreads, 0, s>>>(w.keys[src], n, shift, w.sort_counts, nblk);
+        k_sort_scan<<<256, 256, 0, s>>>(w.sort_counts, w.sort_totals, nblk);
+        k_sort_scatter<<<nblk, kSortThreads, 0, s>>>(w.keys[src], w.idx[src], w.keys[dst],
+                                                     w.idx[dst], n, shift, w.sort_counts,
+                                                     w.sort_totals, nblk);
+    }
+    k_gather<<<nb, 256, 0, s>>>(pos, mass, eps, w.idx[0], n, w.body, w.beps2);
+
+    for (int level = 0; level < kMaxLevel; level++) {
+        const unsigned g = blocks_for(level_bound(level, n) * 8, 256, 4096);
+        k_build_level<<<g, 256, 0, s>>>(level, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
+    }
+    for (int level = kMaxLevel; level >= 0; level--) {
+        const unsigned g = blocks_for(level_bound(level, n), 256, 4096);
+        k_moments_level<<<g, 256, 0, s>>>(level, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0],
+                                          w.nmom, w.neps2, w.node_cap, eps != nullptr);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bhx

@@ -1,0 +1,90 @@
+"""The C-ABI library loads and exports every symbol include/bhx.h declares,
+and host-side argument checks reject bad calls without touching a GPU."""
+import ctypes as C
+import os
+import subprocess
+
+import pytest
+
+from paper_1912_04197_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libbhx.so is not built (run __graft_entry__.build())")
+    return L.load()
+
+
+def test_header_symbols_exported(lib):
+    declared = L.header_symbols()
+    assert len(declared) >= 13
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = [s for s in declared if s not in exported]
+    assert not missing, missing
+    for s in declared:
+        assert hasattr(lib, s)
+    assert set(declared) == set(L.SIGNATURES), "binding and header disagree"
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors agree with the C compiler's layout of include/bhx.h."""
+    fields = {"bh_config": L.bh_config, "bh_tree_view": L.bh_tree_view, "bh_stats_t": L.bh_stats_t}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bhx.h"', "int main(void){"]
+    for sname, cls in fields.items():
+        lines.append(f'printf("%zu\\n", sizeof({sname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({sname}, {fname}));')
+    lines.append("return 0;}")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    want = []
+    for cls in fields.values():
+        want.append(C.sizeof(cls))
+        want += [getattr(cls, f).offset for f, _ in cls._fields_]
+    assert got == want
+
+
+def _cfg(**kw):
+    d = dict(n_max=100, leaf_size=16, precision=L.BH_FP32C, G=1.0, flags=0)
+    d.update(kw)
+    return L.bh_config(d["n_max"], d["leaf_size"], d["precision"], d["G"], d["flags"])
+
+
+@pytest.mark.parametrize("bad", [dict(n_max=-1), dict(leaf_size=0), dict(leaf_size=65),
+                                 dict(precision=7), dict(G=float("nan")), dict(flags=8)])
+def test_create_rejects_bad_config(lib, bad):
+    h = C.c_void_p(123)
+    rc = lib.bh_create(C.byref(_cfg(**bad)), None, C.byref(h))
+    assert rc == L.BH_E_INVALID
+    assert not h.value
+
+
+def test_null_context_calls(lib):
+    assert lib.bh_create(None, None, None) == L.BH_E_INVALID
+    assert lib.bh_sync(None) == L.BH_E_INVALID
+    assert lib.bh_compute_accel(None, None, None, 0.0, None, 0.5, None, None, 0) == L.BH_E_INVALID
+    assert lib.bh_compute_accel_direct(None, None, None, 0.0, None, None, None, 0) == L.BH_E_INVALID
+    assert lib.bh_step_leapfrog(None, None, None, None, 0.0, None, 0.5, 1e-3, 1, None, 0) == L.BH_E_INVALID
+    assert lib.bh_build_tree(None, None, None, None, 0) == L.BH_E_INVALID
+    assert lib.bh_walk_counts(None, None, 0) == L.BH_E_INVALID
+    assert lib.bh_tree_export(None, None) == L.BH_E_INVALID
+    assert lib.bh_stats(None, None) == L.BH_E_INVALID
+    assert lib.bh_set_stream(None, None) == L.BH_E_INVALID
+    assert lib.bh_last_error(None) == b"NULL context"
+    lib.bh_destroy(None)
+
+
+def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(L, "_lib", None)
+    with pytest.raises(L.ExtensionMissing):
+        L.load()
