@@ -3,8 +3,8 @@
 //
 // One thread per target, 256 targets per block; sources stream through LDS in
 // tiles of 256 (positions in FP64 so that d_ij is formed in FP64 even in FP32C
-// mode, where only the pair arithmetic after the difference is FP32 and each
-// tile's FP32 partial sums are added into FP64 accumulators).
+// mode, where only the pair arithmetic after the difference is FP32 and FP32
+// partial sums over at most 32 sources are added into FP64 accumulators).
 #include <type_traits>
 
 #include "bhx_impl.h"
@@ -67,25 +67,29 @@ __global__ __launch_bounds__(kTile) void k_direct(const double *__restrict__ pos
                 }
             }
         } else {
-            float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
+            for (int j0 = 0; j0 < cnt; j0 += 32) {
+                const int jn = j0 + 32 < cnt ? j0 + 32 : cnt;
+                float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
 #pragma unroll 4
-            for (int jj = 0; jj < cnt; jj++) {
-                const float dx = (float)(sx[jj] - xi), dy = (float)(sy[jj] - yi),
-                            dz = (float)(sz[jj] - zi);
-                const float e2 = PEPS ? (float)se[jj] + e2hB : eps0f;
-                const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, e2)));
-                const float rinv = (jj != skip && r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;
-                const float mr = (float)sm[jj] * rinv;
-                const float mr3 = mr * rinv * rinv;
-                fx = fmaf(mr3, dx, fx);
-                fy = fmaf(mr3, dy, fy);
-                fz = fmaf(mr3, dz, fz);
-                if (PHI) fp -= mr;
+                for (int jj = j0; jj < jn; jj++) {
+                    const float dx = (float)(sx[jj] - xi), dy = (float)(sy[jj] - yi),
+                                dz = (float)(sz[jj] - zi);
+                    const float e2 = PEPS ? (float)se[jj] + e2hB : eps0f;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, e2)));
+                    const float rinv =
+                        (jj != skip && r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;
+                    const float mr = (float)sm[jj] * rinv;
+                    const float mr3 = mr * rinv * rinv;
+                    fx = fmaf(mr3, dx, fx);
+                    fy = fmaf(mr3, dy, fy);
+                    fz = fmaf(mr3, dz, fz);
+                    if (PHI) fp -= mr;
+                }
+                ax += (double)fx;
+                ay += (double)fy;
+                az += (double)fz;
+                if (PHI) ph += (double)fp;
             }
-            ax += (double)fx;
-            ay += (double)fy;
-            az += (double)fz;
-            if (PHI) ph += (double)fp;
         }
         __syncthreads();
     }
