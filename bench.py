@@ -47,6 +47,21 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
+def walk_traffic():
+    """HBM bytes per walk launch from the committed rocprofv3 counter runs, or
+    None when the walk kernel's source has changed since they were taken."""
+    import hashlib
+
+    try:
+        with open(os.path.join(ROOT, "profiles", "walk_counters.json")) as f:
+            rec = json.load(f)
+        with open(os.path.join(ROOT, "paper_1912_04197_amd", "csrc", "walk.hip"), "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()[:16]
+    except (OSError, ValueError):
+        return None
+    return rec["hbm_bytes_per_launch"] if rec.get("walk_source_sha256_16") == h else None
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,6 +76,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed steps (for profiler runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (to scale HBM counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -76,6 +93,15 @@ def main():
     from paper_1912_04197_amd.api import Context
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 5}))
+        return
     n, theta, leaf, dt = args.n, args.theta, args.leaf, args.dt
     log(f"generating rubble pile n={n}")
     scene = ics.rubble_pile(n, seed=33)
@@ -155,7 +181,7 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-            "traffic": None,
+            "traffic": walk_traffic(),
             "kernel": "k_walk<fp32c, per-body eps>",
             "flops_per_interaction": FLOPS_PER_INTERACTION,
         },
