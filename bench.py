@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--theta", type=float, default=0.5)
     ap.add_argument("--leaf", type=int, default=16)
     ap.add_argument("--dt", type=float, default=5e-4)
+    ap.add_argument("--walk-group", type=int, default=0,
+                    help="target bodies per wavefront in the walk (16/32/64; 0 = library default)")
     ap.add_argument("--cpu-sample", type=int, default=131072,
                     help="targets the oracle walks for the CPU baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -115,7 +117,7 @@ def main():
             ctx.step_leapfrog(pos, vel, mass, acc, dt, 1, theta=theta, eps=eps, sync=False)
 
     # ---- headline: FP32C tree leapfrog
-    ctx = Context(n, leaf_size=leaf, precision="fp32c", timing=True)
+    ctx = Context(n, leaf_size=leaf, precision="fp32c", timing=True, walk_group=args.walk_group)
     pos, vel = pos0.clone(), vel0.clone()
     acc = ctx.compute_accel(pos, mass, theta, eps=eps)
     log(f"warmup {args.warmup} steps")
@@ -167,6 +169,7 @@ def main():
             "workload": f"rubble_pile N={n} theta={theta} leaf={leaf} eps=radius dt={dt} "
                         "kick-drift-kick, tree rebuilt every step",
             "n": n, "theta": theta, "leaf": leaf, "dt": dt, "precision": "fp32c",
+            "walk_group": args.walk_group or "default",
         },
         "ginteractions_per_s": round(gint_step, 3),
         "ginteractions_per_s_walk": round(gint_walk, 3),
@@ -189,7 +192,7 @@ def main():
 
     if not args.no_extras:
         # plain FP64 form of the same step
-        c64 = Context(n, leaf_size=leaf, precision="fp64", timing=True)
+        c64 = Context(n, leaf_size=leaf, precision="fp64", timing=True, walk_group=args.walk_group)
         p64, v64 = pos0.clone(), vel0.clone()
         a64 = c64.compute_accel(p64, mass, theta, eps=eps)
         k64 = max(3, min(10, args.steps))

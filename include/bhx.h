@@ -78,13 +78,18 @@ typedef struct {
                           opening test, moments and outputs */
     double G;          /* gravitational constant */
     uint32_t flags;    /* BH_FLAG_* */
+    int32_t walk_group; /* target bodies served by one wavefront in the tree
+                           walk: 64, 32 or 16 (64/walk_group lanes per body);
+                           0 = the library's default. Results do not depend on
+                           it beyond rounding. */
 } bh_config;
 
 /* Creates a context on the current HIP device, bound to `hip_stream`
  * (a hipStream_t; NULL = the null stream). Allocates the whole workspace for
  * cfg->n_max bodies, including the worst-case node table, so later calls never
  * allocate. Errors: BH_E_INVALID (NULL pointers, n_max < 0, leaf_size outside
- * 1..64, precision unknown, G not finite), BH_E_OOM, BH_E_HIP. */
+ * 1..64, precision unknown, G not finite, unknown flags, walk_group not in
+ * {0, 16, 32, 64}), BH_E_OOM, BH_E_HIP. */
 bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out);
 
 /* Frees the context and its workspace after waiting for its stream. NULL is a no-op. */

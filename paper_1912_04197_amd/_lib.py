@@ -19,7 +19,7 @@ BH_FLAG_TIMING = 2
 
 class bh_config(C.Structure):
     _fields_ = [("n_max", C.c_int64), ("leaf_size", C.c_int32), ("precision", C.c_int32),
-                ("G", C.c_double), ("flags", C.c_uint32)]
+                ("G", C.c_double), ("flags", C.c_uint32), ("walk_group", C.c_int32)]
 
 
 class bh_tree_view(C.Structure):

@@ -76,13 +76,13 @@ class Context:
     """
 
     def __init__(self, n_max: int, leaf_size: int = 16, precision: str = "fp32c", G: float = 1.0,
-                 counts: bool = False, timing: bool = False):
+                 counts: bool = False, timing: bool = False, walk_group: int = 0):
         self._lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: libbhx runs on the GPU only")
         prec = {"fp64": L.BH_FP64, "fp32c": L.BH_FP32C}[precision]
         flags = (L.BH_FLAG_COUNTS if counts else 0) | (L.BH_FLAG_TIMING if timing else 0)
-        cfg = L.bh_config(int(n_max), int(leaf_size), prec, float(G), flags)
+        cfg = L.bh_config(int(n_max), int(leaf_size), prec, float(G), flags, int(walk_group))
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.n_max, self.leaf_size, self.precision, self.G = int(n_max), int(leaf_size), precision, float(G)
         h = C.c_void_p()

@@ -101,7 +101,9 @@ struct WalkParams {
     int32_t *counts;  // caller order n x 2 or nullptr
     bool per_body_eps;
     int precision;
+    int group;  // target bodies per wavefront: 64, 32 or 16
 };
+constexpr int kDefaultWalkGroup = 64;
 // walk.hip
 hipError_t launch_walk(const Workspace &w, hipStream_t s, const WalkParams &p);
 

@@ -129,6 +129,7 @@ bh_status force_tree(bh_ctx *c, const double *pos, const double *mass, double so
     p.counts = (c->cfg.flags & BH_FLAG_COUNTS) ? w.counts : nullptr;
     p.per_body_eps = eps != nullptr;
     p.precision = c->cfg.precision;
+    p.group = c->cfg.walk_group ? c->cfg.walk_group : bhx::kDefaultWalkGroup;
     BHX_HIP(c, bhx::launch_walk(w, c->stream, p));
     if (p.counts) c->walk_n = n;
     return record(c, 2);
@@ -155,6 +156,9 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
     if (cfg->precision != BH_FP64 && cfg->precision != BH_FP32C) return BH_E_INVALID;
     if (!std::isfinite(cfg->G)) return BH_E_INVALID;
     if (cfg->flags & ~(uint32_t)(BH_FLAG_COUNTS | BH_FLAG_TIMING)) return BH_E_INVALID;
+    if (cfg->walk_group != 0 && cfg->walk_group != 16 && cfg->walk_group != 32 &&
+        cfg->walk_group != 64)
+        return BH_E_INVALID;
 
     bh_ctx *c = new (std::nothrow) bh_ctx();
     if (!c) return BH_E_OOM;

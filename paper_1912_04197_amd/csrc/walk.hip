@@ -1,30 +1,38 @@
-// Barnes-Hut walk (subsection "Force computation"), one wavefront per group
-// of 64 Morton-consecutive target bodies.
+// Barnes-Hut walk (subsection "Force computation"): one wavefront serves a
+// group of GB Morton-consecutive target bodies (GB = 64, 32 or 16), with
+// 64 / GB lanes per body.
 //
-// The paper gives each body its own thread and its own traversal. Here the 64
+// The paper gives each body its own thread and its own traversal. Here the
 // lanes of a wave walk the tree together, but every stack entry carries a
-// 64-bit lane mask: the lanes whose own traversal reaches that node. At an
-// internal node each lane evaluates its own opening test in FP64
-// (s^2 < theta^2 D^2, eq. accuracy); the lanes that accept it queue the node
+// GB-bit body mask: the bodies whose own traversal reaches that node. At an
+// internal node each body evaluates its own opening test in FP64
+// (s^2 < theta^2 D^2, eq. accuracy); the bodies that accept it take the node
 // as one interaction (eq. Force_thetaTrue) and the others carry on into the
-// children. A leaf queues its bodies for the lanes that reached it
-// (eq. Force_leaf), each lane's own body excluded from its mask. So each body
-// gets exactly the interaction set of its own walk; only the summation order
-// differs from a depth-first walk.
+// children. A leaf contributes its bodies one by one (eq. Force_leaf) to the
+// bodies that reached it, each body's own index cleared from its mask. So each
+// body gets exactly the interaction set of its own walk; only the summation
+// order differs from a depth-first walk.
 //
-// Traversal: a stack entry is the child range of one opened node with the
-// mask of the lanes that opened it. Each round pops up to 8 ranges (up to 64
-// nodes), the lanes load those nodes in parallel into LDS (one memory latency
-// per round instead of one per node), and the wave then decides them one after
-// another from LDS. A round pops only as many ranges as can be expanded while
-// leaving room for a depth-first descent, so the stack cannot overflow.
+// Traversal rounds: a stack entry is the child range of one opened node with
+// its body mask. A round pops up to 8 ranges (up to 64 nodes); the lanes load
+// those nodes in parallel (one memory latency per round), test them against
+// the group (64 / GB nodes per instruction), and then do the bookkeeping for
+// all popped nodes at once: lane p handles popped node p, and prefix sums over
+// the lanes place the pushed child ranges and the queued interactions. A round
+// pops only as many ranges as can be expanded while keeping room for a
+// depth-first descent, so the stack cannot overflow.
 //
-// Evaluation: interactions are queued in LDS and evaluated 64 at a time: lane
-// k fetches queue item k and stages it, then every lane sweeps the staged
-// items. In FP32C mode each pair offset x_j - x_B is formed in FP64 and
-// rounded once to FP32 (close pairs keep full FP32 precision whatever the
-// group's extent), the rest of the pair term is FP32, and FP32 partial sums
-// over at most 16 items are added into FP64 accumulators.
+// Evaluation: the interaction queue holds descriptors (a leaf's body range or
+// one accepted node, with a body mask). Whenever 64 items are queued, lane k
+// expands item k (binary search over the descriptors' item offsets), loads it
+// and stages it in LDS; then the lanes of each body sweep the staged items,
+// each taking every (64 / GB)-th one. In FP32C mode each pair offset
+// x_j - x_B is formed in FP64 and rounded once to FP32 (close pairs keep full
+// FP32 precision whatever the group's extent), the rest of the pair term is
+// FP32, and FP32 partial sums over at most 16 items per lane are added into
+// FP64 accumulators. The per-lane FP64 sums of a body are added at the end in
+// a fixed order, so results are deterministic.
+#include <cstddef>
 #include <type_traits>
 
 #include "bhx_impl.h"
@@ -36,9 +44,9 @@ constexpr int kStack = 320;    // LDS traversal stack of child ranges
 constexpr int kReserve = 150;  // a depth-first descent adds <= 7 ranges per level
 constexpr int kRanges = 8;     // ranges popped per round (<= 8 nodes each)
 constexpr int kPop = 8 * kRanges;
-constexpr int kQueue = 128;  // a flush happens at 64; a leaf chunk adds <= 64
-constexpr int kBatch = 64;
-constexpr int kFlush = 16;   // FP32 partial sums span at most this many items
+constexpr int kRing = 128;     // interaction descriptors: <= 64 left over + 64 new
+constexpr int kBatch = 64;     // items staged per evaluation batch
+constexpr int kFlush = 16;     // FP32 partial sums span at most this many items per lane
 
 struct alignas(16) ItemF {  // FP32C staged source
     double x, y, z;
@@ -55,21 +63,32 @@ struct alignas(16) ItemD {  // FP64 staged source
     int32_t src, pad0;
     int64_t pad1;
 };
-struct alignas(16) PopNode {  // a popped stack entry with its node loaded
-    double x, y, z, s2;
+struct alignas(16) PopCom {  // popped node as the opening test needs it
+    double x, y, z, s2;      // s2 = +inf for a leaf (never accepted)
+};
+struct alignas(16) PopData {  // popped node as the bookkeeping needs it
     uint64_t mask;
-    int32_t first, count, child0, nch;  // child0 < 0: leaf
-    int32_t node, pad0;
-    int64_t pad1;
+    int32_t node, first, count, child0;  // child0 < 0: leaf
+    int32_t nch, pad;
 };
 
-__device__ inline uint64_t uniform64(uint64_t v)
-{
-    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
 __device__ inline int32_t uniform32(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline uint32_t lanes_below(uint64_t m)  // set bits of m below this lane
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Inclusive prefix sum over the 64 lanes (exact, integer).
+__device__ inline uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
 
 // The opening test, rounded exactly as written: accept iff s^2 < theta^2 D^2.
 __device__ inline bool accept_node(double cx, double cy, double cz, double bx, double by,
@@ -81,24 +100,41 @@ __device__ inline bool accept_node(double cx, double cy, double cz, double bx, d
     return s2 < th2 * D2;
 }
 
-template <int PREC, bool PEPS, bool PHI, bool CNT>
+template <int PREC, bool PEPS, bool PHI, bool CNT, int GB>
 __global__ __launch_bounds__(64) void k_walk(
     const Body *__restrict__ body, const double *__restrict__ beps2,
     const NodeInfo *__restrict__ ninfo, const NodeMom *__restrict__ nmom,
     const double *__restrict__ neps2, const uint32_t *__restrict__ idx,
-    const TreeHeader *__restrict__ hdr, int64_t n, int ngroups,
-    int per_xcd, double th2, double eps0sq, double G, double *__restrict__ acc,
-    double *__restrict__ phi, int32_t *__restrict__ counts)
+    const TreeHeader *__restrict__ hdr, int64_t n, int ngroups, int per_xcd, double th2,
+    double eps0sq, double G, double *__restrict__ acc, double *__restrict__ phi,
+    int32_t *__restrict__ counts)
 {
+    static_assert(GB == 64 || GB == 32 || GB == 16, "group size");
+    constexpr int LPB = 64 / GB;  // lanes per body
+    constexpr uint64_t kBodyMask = GB == 64 ? ~0ull : ((1ull << GB) - 1ull);
     using Item = typename std::conditional<PREC == BH_FP64, ItemD, ItemF>::type;
+
     __shared__ int32_t st_c0[kStack];
     __shared__ int32_t st_n[kStack];
     __shared__ uint64_t st_mask[kStack];
-    __shared__ PopNode pn[kPop];
-    __shared__ int32_t q_src[kQueue];
-    __shared__ uint64_t q_mask[kQueue];
-    __shared__ Item items[kBatch];
+    __shared__ int32_t dq_a[kRing];      // leaf: first body; node: ~node
+    __shared__ int32_t dq_n[kRing];      // items in the descriptor
+    __shared__ uint32_t dq_at[kRing];    // running item number of its first item
+    __shared__ uint64_t dq_mask[kRing];
     __shared__ double s2tab[kLevels];
+    // The popped nodes are read only before a round's evaluations and the
+    // staged items only during them, so the two share one LDS region.
+    union Shared {
+        struct {
+            PopCom pc[kPop];
+            PopData pd[kPop];
+        } pop;
+        Item items[kBatch];
+    };
+    __shared__ Shared sh;
+    PopCom *const pc = sh.pop.pc;
+    PopData *const pd = sh.pop.pd;
+    Item *const items = sh.items;
 
     // Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous
     // (so spatially compact) range of groups to share its L2.
@@ -106,23 +142,27 @@ __global__ __launch_bounds__(64) void k_walk(
     if (grp >= ngroups) return;
 
     const int lane = threadIdx.x;
-    const int64_t g0 = (int64_t)grp * 64;
-    const int64_t s = g0 + lane;
+    const int bq = GB == 64 ? lane : lane % GB;  // body of this lane within the group
+    const int sub = GB == 64 ? 0 : lane / GB;    // which share of the items it sweeps
+    const int64_t g0 = (int64_t)grp * GB;
+    const int64_t s = g0 + bq;
     const bool valid = s < n;
     const Body me = body[valid ? s : g0];
     const double eb2 = PEPS ? beps2[valid ? s : g0] : 0.0;
-    const uint64_t active = __ballot(valid);
+    const uint64_t active = __ballot(valid) & kBodyMask;
     if (lane < kLevels) s2tab[lane] = hdr->s2[lane];
 
     const float e2hB = (float)(0.5 * eb2);
     const float eps0f = (float)eps0sq;
-    const bool lane_hi = lane >= 32;
-    const uint32_t lbit = 1u << (lane & 31);
+    const int woff = (int)offsetof(ItemF, mlo) + (bq >= 32 ? 4 : 0);
 
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
     int32_t cnode = 0, cpair = 0;
 
-    int sp = 1, qn = 0;
+    int sp = 1;              // stack entries
+    int dq_head = 0, dq_tail = 0;
+    uint32_t queued = 0;     // items ever queued
+    uint32_t consumed = 0;   // items ever evaluated
     if (lane == 0) {
         st_c0[0] = 0;  // the root, as a range of one
         st_n[0] = 1;
@@ -130,20 +170,35 @@ __global__ __launch_bounds__(64) void k_walk(
     }
     __syncthreads();
 
-    // Evaluates the first c queued items, then shifts the rest down.
-    auto flush = [&](int c) {
+    // Stages the next c queued items and sweeps them.
+    auto evaluate = [&](int c) {
         if (lane < c) {
-            const int32_t src = q_src[lane];
-            const uint64_t mk = q_mask[lane];
+            const uint32_t q = consumed + (uint32_t)lane;
+            int lo = 0, hi = dq_tail - dq_head - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (dq_at[(dq_head + mid) % kRing] <= q)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            const int d = (dq_head + lo) % kRing;
+            const int32_t a = dq_a[d];
+            uint64_t mk = dq_mask[d];
+            int32_t src;
             double x, y, z, m, e2;
-            if (src >= 0) {
+            if (a >= 0) {
+                src = a + (int32_t)(q - dq_at[d]);
+                const int64_t rel = (int64_t)src - g0;
+                if (rel >= 0 && rel < GB) mk &= ~(1ull << rel);  // not itself
                 const Body b = body[src];
                 x = b.x, y = b.y, z = b.z, m = b.m;
                 e2 = PEPS ? beps2[src] : 0.0;
             } else {
-                const NodeMom nm = nmom[~src];
+                src = a;
+                const NodeMom nm = nmom[~a];
                 x = nm.x, y = nm.y, z = nm.z, m = nm.m;
-                e2 = PEPS ? neps2[~src] : 0.0;
+                e2 = PEPS ? neps2[~a] : 0.0;
             }
             if constexpr (PREC == BH_FP64) {
                 items[lane] = ItemD{x, y, z, m, e2, mk, src, 0, 0};
@@ -155,9 +210,10 @@ __global__ __launch_bounds__(64) void k_walk(
         __syncthreads();
         if constexpr (PREC == BH_FP64) {
 #pragma unroll 1
-            for (int j = 0; j < c; j++) {
-                const ItemD it = items[j];
-                const bool on = (it.mask >> lane) & 1ull;
+            for (int jj = 0; jj < c; jj += LPB) {
+                const int j = jj + sub;
+                const ItemD it = items[j < c ? j : jj];
+                const bool on = j < c && ((it.mask >> bq) & 1ull);
                 const double dx = it.x - me.x, dy = it.y - me.y, dz = it.z - me.z;
                 const double e2 = PEPS ? 0.5 * (eb2 + it.e2) : eps0sq;
                 const double r2 = dx * dx + dy * dy + dz * dz + e2;
@@ -178,13 +234,22 @@ __global__ __launch_bounds__(64) void k_walk(
             }
         } else {
 #pragma unroll 1
-            for (int j0 = 0; j0 < c; j0 += kFlush) {
-                const int jn = min(c, j0 + kFlush);
+            for (int j0 = 0; j0 < c; j0 += kFlush * LPB) {
+                const int jn = min(c, j0 + kFlush * LPB);
                 float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
+                // jj is the same on every lane; lane share `sub` takes item jj + sub
 #pragma unroll 2
-                for (int j = j0; j < jn; j++) {
-                    const ItemF it = items[j];
-                    const bool on = (lane_hi ? it.mhi : it.mlo) & lbit;
+                for (int jj = j0; jj < jn; jj += LPB) {
+                    const int j = jj + sub;
+                    const ItemF it = items[j < jn ? j : jj];
+                    bool on;
+                    if constexpr (GB == 64) {
+                        // lanes 32..63 read the high word of the body mask
+                        const uint32_t w = *(const uint32_t *)((const char *)&items[jj] + woff);
+                        on = (w >> (bq & 31)) & 1u;
+                    } else {
+                        on = j < jn && ((it.mlo >> bq) & 1u);
+                    }
                     const float dx = (float)(it.x - me.x), dy = (float)(it.y - me.y),
                                 dz = (float)(it.z - me.z);
                     const float e2 = PEPS ? it.e2h + e2hB : eps0f;
@@ -209,19 +274,14 @@ __global__ __launch_bounds__(64) void k_walk(
                 if (PHI) ph += (double)fp;
             }
         }
-        const int rem = qn - c;
-        int32_t t_src = 0;
-        uint64_t t_mask = 0;
-        if (lane < rem) {
-            t_src = q_src[c + lane];
-            t_mask = q_mask[c + lane];
+        consumed += (uint32_t)c;
+        // retire fully evaluated descriptors
+        while (dq_head < dq_tail) {
+            const int d = dq_head % kRing;
+            const uint32_t end = (uint32_t)uniform32((int32_t)(dq_at[d] + (uint32_t)dq_n[d]));
+            if (end > consumed) break;
+            dq_head++;
         }
-        __syncthreads();
-        if (lane < rem) {
-            q_src[lane] = t_src;
-            q_mask[lane] = t_mask;
-        }
-        qn = rem;
         __syncthreads();
     };
 
@@ -233,10 +293,10 @@ __global__ __launch_bounds__(64) void k_walk(
         const int room = (kStack - kReserve - sp) / 7;
         if (cr > room) cr = room > 1 ? room : 1;
         const int base = sp - cr;
+        int32_t k = -1;
+        uint64_t mk = 0;
         {
             const int r = lane >> 3, o = lane & 7;
-            int32_t k = -1;
-            uint64_t mk = 0;
             if (r < cr) {
                 const int e = base + r;
                 if (o < st_n[e]) {
@@ -244,74 +304,87 @@ __global__ __launch_bounds__(64) void k_walk(
                     mk = st_mask[e];
                 }
             }
-            PopNode p;
-            p.node = k;
-            if (k >= 0) {
-                const NodeInfo info = ninfo[k];
-                const NodeMom nm = nmom[k];
-                p.x = nm.x, p.y = nm.y, p.z = nm.z;
-                p.s2 = s2tab[node_level(info)];
-                p.mask = mk;
-                p.first = info.first, p.count = info.count, p.child0 = info.child0;
-                p.nch = node_nchild(info);
-            }
-            pn[lane] = p;
+        }
+        // compact the popped nodes into slots 0..nv-1
+        const uint64_t vb = __ballot(k >= 0);
+        const int nv = __popcll(vb);
+        if (k >= 0) {
+            const int slot = (int)lanes_below(vb);
+            const NodeInfo info = ninfo[k];
+            const NodeMom nm = nmom[k];
+            const bool leaf = info.child0 < 0;
+            pc[slot] = PopCom{nm.x, nm.y, nm.z,
+                              leaf ? __builtin_huge_val() : s2tab[node_level(info)]};
+            pd[slot] = PopData{mk, k, info.first, info.count, info.child0, node_nchild(info), 0};
         }
         sp = base;
         __syncthreads();
+
+        // Opening tests: 64 / GB popped nodes per step, one per share of
+        // lanes. The group's GB-bit result for popped node p goes to lane p.
+        uint64_t accepted = 0;
 #pragma unroll 1
-        for (int j = 0; j < kPop; j++) {
-            if (uniform32(pn[j].node) < 0) continue;
-            const uint64_t M = uniform64(pn[j].mask);
-            const int32_t child0 = uniform32(pn[j].child0);
-            if (child0 < 0) {
-                // leaf: its bodies, for the lanes that reached it
-                const int32_t first = uniform32(pn[j].first);
-                const int32_t count = uniform32(pn[j].count);
-                for (int off = 0; off < count; off += 64) {
-                    const int cc = min(64, count - off);
-                    if (lane < cc) {
-                        const int32_t src = first + off + lane;
-                        const int64_t rel = (int64_t)src - g0;
-                        uint64_t mk = M;
-                        if (rel >= 0 && rel < 64) mk &= ~(1ull << rel);  // not itself
-                        q_src[qn + lane] = src;
-                        q_mask[qn + lane] = mk;
-                    }
-                    qn += cc;
-                    __syncthreads();
-                    if (qn >= kBatch) flush(kBatch);
-                }
-            } else {
-                const bool ok = accept_node(pn[j].x, pn[j].y, pn[j].z, me.x, me.y, me.z,
-                                            pn[j].s2, th2);
-                const uint64_t A = __ballot(ok) & M;
-                const uint64_t O = M & ~A;
-                if (A) {
-                    // accepted by the lanes in A: one monopole interaction
-                    if (lane == 0) {
-                        q_src[qn] = ~pn[j].node;
-                        q_mask[qn] = A;
-                    }
-                    qn++;
-                }
-                if (O) {
-                    // opened by the lanes in O: visit all of its children
-                    if (lane == 0) {
-                        st_c0[sp] = child0;
-                        st_n[sp] = pn[j].nch;
-                        st_mask[sp] = O;
-                    }
-                    sp++;
-                }
-                __syncthreads();
-                if (qn >= kBatch) flush(kBatch);
+        for (int p0 = 0; p0 < nv; p0 += LPB) {
+            const int p = p0 + sub;
+            const PopCom q = pc[p < nv ? p : 0];
+            const bool ok = p < nv && accept_node(q.x, q.y, q.z, me.x, me.y, me.z, q.s2, th2);
+            const uint64_t bal = __ballot(ok);
+#pragma unroll
+            for (int t = 0; t < LPB; t++) {
+                const uint64_t field = (bal >> (t * GB)) & kBodyMask;
+                if (lane == p0 + t) accepted = field;
             }
         }
-    }
-    while (qn > 0) flush(min(qn, kBatch));
 
-    if (valid) {
+        // Bookkeeping for popped node `lane`, all lanes at once.
+        const bool mine = lane < nv;
+        PopData my = PopData{0ull, 0, 0, 0, 0, 0, 0};
+        if (mine) my = pd[lane];
+        const bool leaf = mine && my.child0 < 0;
+        const uint64_t M = my.mask;
+        const uint64_t A = (mine && !leaf) ? (accepted & M) : 0ull;
+        const uint64_t O = (mine && !leaf) ? (M & ~accepted) : 0ull;
+        // opened by the bodies in O: push the child range
+        const uint64_t pushb = __ballot(O != 0);
+        if (O != 0) {
+            const int e = sp + (int)lanes_below(pushb);
+            st_c0[e] = my.child0;
+            st_n[e] = my.nch;
+            st_mask[e] = O;
+        }
+        sp += __popcll(pushb);
+        // a leaf, or accepted by the bodies in A: queue a descriptor
+        const bool hasq = leaf || A != 0;
+        const uint64_t qb = __ballot(hasq);
+        const uint32_t nitems = leaf ? (uint32_t)my.count : (A != 0 ? 1u : 0u);
+        const uint32_t incl = wave_incl_scan(nitems);
+        if (hasq) {
+            const int d = (dq_tail + (int)lanes_below(qb)) % kRing;
+            dq_a[d] = leaf ? my.first : ~my.node;
+            dq_n[d] = (int32_t)nitems;
+            dq_at[d] = queued + incl - nitems;
+            dq_mask[d] = leaf ? M : A;
+        }
+        dq_tail += __popcll(qb);
+        queued += (uint32_t)__shfl(incl, 63);
+        __syncthreads();
+        while (queued - consumed >= (uint32_t)kBatch) evaluate(kBatch);
+    }
+    while (queued != consumed) evaluate((int)min(queued - consumed, (uint32_t)kBatch));
+
+    // add the lanes' partial sums of each body in a fixed order
+#pragma unroll
+    for (int o = GB; o < 64; o <<= 1) {
+        ax += __shfl_xor(ax, o);
+        ay += __shfl_xor(ay, o);
+        az += __shfl_xor(az, o);
+        if (PHI) ph += __shfl_xor(ph, o);
+        if (CNT) {
+            cnode += __shfl_xor(cnode, o);
+            cpair += __shfl_xor(cpair, o);
+        }
+    }
+    if (valid && sub == 0) {
         const int64_t o = idx[s];
         acc[3 * o] = G * ax;
         acc[3 * o + 1] = G * ay;
@@ -324,25 +397,35 @@ __global__ __launch_bounds__(64) void k_walk(
     }
 }
 
-template <int PREC, bool PEPS, bool PHI, bool CNT>
+template <int PREC, bool PEPS, bool PHI, bool CNT, int GB>
 hipError_t launch_t(const Workspace &w, hipStream_t s, const WalkParams &p)
 {
-    const int ngroups = (int)((p.n + 63) / 64);
+    const int ngroups = (int)((p.n + GB - 1) / GB);
     const int per_xcd = (ngroups + 7) / 8;
-    k_walk<PREC, PEPS, PHI, CNT><<<8 * per_xcd, 64, 0, s>>>(
-        w.body, w.beps2, w.ninfo, w.nmom, w.neps2, w.idx[0], w.hdr, p.n, ngroups,
-        per_xcd, p.th2, p.eps0sq, p.G, p.acc, p.phi, p.counts);
+    k_walk<PREC, PEPS, PHI, CNT, GB><<<8 * per_xcd, 64, 0, s>>>(
+        w.body, w.beps2, w.ninfo, w.nmom, w.neps2, w.idx[0], w.hdr, p.n, ngroups, per_xcd, p.th2,
+        p.eps0sq, p.G, p.acc, p.phi, p.counts);
     return hipGetLastError();
+}
+
+template <int PREC, bool PEPS, bool PHI, bool CNT>
+hipError_t launch_g(const Workspace &w, hipStream_t s, const WalkParams &p)
+{
+    switch (p.group) {
+        case 64: return launch_t<PREC, PEPS, PHI, CNT, 64>(w, s, p);
+        case 32: return launch_t<PREC, PEPS, PHI, CNT, 32>(w, s, p);
+        default: return launch_t<PREC, PEPS, PHI, CNT, 16>(w, s, p);
+    }
 }
 
 template <int PREC, bool PEPS>
 hipError_t launch_p(const Workspace &w, hipStream_t s, const WalkParams &p)
 {
     const bool phi = p.phi != nullptr, cnt = p.counts != nullptr;
-    if (phi && cnt) return launch_t<PREC, PEPS, true, true>(w, s, p);
-    if (phi) return launch_t<PREC, PEPS, true, false>(w, s, p);
-    if (cnt) return launch_t<PREC, PEPS, false, true>(w, s, p);
-    return launch_t<PREC, PEPS, false, false>(w, s, p);
+    if (phi && cnt) return launch_g<PREC, PEPS, true, true>(w, s, p);
+    if (phi) return launch_g<PREC, PEPS, true, false>(w, s, p);
+    if (cnt) return launch_g<PREC, PEPS, false, true>(w, s, p);
+    return launch_g<PREC, PEPS, false, false>(w, s, p);
 }
 
 }  // namespace

@@ -54,13 +54,15 @@ def test_struct_layouts_match_header(tmp_path):
 
 
 def _cfg(**kw):
-    d = dict(n_max=100, leaf_size=16, precision=L.BH_FP32C, G=1.0, flags=0)
+    d = dict(n_max=100, leaf_size=16, precision=L.BH_FP32C, G=1.0, flags=0, walk_group=0)
     d.update(kw)
-    return L.bh_config(d["n_max"], d["leaf_size"], d["precision"], d["G"], d["flags"])
+    return L.bh_config(d["n_max"], d["leaf_size"], d["precision"], d["G"], d["flags"],
+                       d["walk_group"])
 
 
 @pytest.mark.parametrize("bad", [dict(n_max=-1), dict(leaf_size=0), dict(leaf_size=65),
-                                 dict(precision=7), dict(G=float("nan")), dict(flags=8)])
+                                 dict(precision=7), dict(G=float("nan")), dict(flags=8),
+                                 dict(walk_group=8), dict(walk_group=48)])
 def test_create_rejects_bad_config(lib, bad):
     h = C.c_void_p(123)
     rc = lib.bh_create(C.byref(_cfg(**bad)), None, C.byref(h))

@@ -36,8 +36,9 @@ def api():
     return A
 
 
-def _ctx(api, n, leaf=16, precision="fp64", counts=True, G=1.0):
-    return api.Context(max(n, 1), leaf_size=leaf, precision=precision, G=G, counts=counts)
+def _ctx(api, n, leaf=16, precision="fp64", counts=True, G=1.0, group=0):
+    return api.Context(max(n, 1), leaf_size=leaf, precision=precision, G=G, counts=counts,
+                       walk_group=group)
 
 
 def _check_acc(acc_gpu, acc_ref, aabs, tol, label):
@@ -171,15 +172,16 @@ WALK_CASES = [
 ]
 
 
+@pytest.mark.parametrize("group", [16, 32, 64])
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 @pytest.mark.parametrize("name,make,theta,leaf,soft,per_body", WALK_CASES,
                          ids=[c[0] for c in WALK_CASES])
-def test_walk_parity(api, name, make, theta, leaf, soft, per_body, precision):
+def test_walk_parity(api, name, make, theta, leaf, soft, per_body, precision, group):
     s = make()
     eps = s.eps if per_body else None
     ref_acc, ref_phi, aabs, ref_cnt = oracle.bh(s.pos, s.mass, theta, softening=soft, eps=eps,
                                                 leaf=leaf, G=0.7)
-    ctx = _ctx(api, s.n, leaf=leaf, precision=precision, G=0.7)
+    ctx = _ctx(api, s.n, leaf=leaf, precision=precision, G=0.7, group=group)
     acc, phi = ctx.compute_accel(_dev(s.pos), _dev(s.mass), theta, softening=soft,
                                  eps=None if eps is None else _dev(eps), potential=True)
     cnt = ctx.walk_counts(s.n).cpu().numpy()
@@ -202,9 +204,10 @@ def test_walk_coincident_bodies(api):
     assert ctx.tree().depth == 21
 
 
-def test_walk_deterministic(api):
+@pytest.mark.parametrize("group", [16, 32, 64])
+def test_walk_deterministic(api, group):
     s = ics.plummer(50000, seed=15)
-    ctx = _ctx(api, s.n, precision="fp32c", counts=False)
+    ctx = _ctx(api, s.n, precision="fp32c", counts=False, group=group)
     p, m = _dev(s.pos), _dev(s.mass)
     a1 = ctx.compute_accel(p, m, 0.5, softening=1e-3).cpu().numpy()
     a2 = ctx.compute_accel(p, m, 0.5, softening=1e-3).cpu().numpy()
@@ -221,8 +224,9 @@ def test_zero_bodies(api):
 
 # ------------------------------------------------------------ full sizes
 
+@pytest.mark.parametrize("group", [16, 64])
 @pytest.mark.parametrize("precision", ["fp32c", "fp64"])
-def test_headline_size_sampled(api, precision):
+def test_headline_size_sampled(api, precision, group):
     """N = 2^20 rubble pile, theta 0.5, leaf 16, per-body softening = radius:
     the oracle walks 1024 sampled bodies through its own full-size tree."""
     n = 1 << 20
@@ -230,7 +234,7 @@ def test_headline_size_sampled(api, precision):
     rng = np.random.default_rng(1)
     sample = np.sort(rng.choice(n, 1024, replace=False))
     ref_acc, _, aabs, ref_cnt = oracle.Tree(x, m, eps=eps, leaf=16).accel(0.5, targets=sample)
-    ctx = _ctx(api, n, leaf=16, precision=precision)
+    ctx = _ctx(api, n, leaf=16, precision=precision, group=group)
     acc = ctx.compute_accel(_dev(x), _dev(m), 0.5, eps=_dev(eps)).cpu().numpy()[sample]
     cnt = ctx.walk_counts(n).cpu().numpy()[sample]
     assert np.array_equal(cnt, ref_cnt)
