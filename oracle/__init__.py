@@ -84,6 +84,12 @@ def _load(path: str | None = None):
     lib.orc_leapfrog.restype = C.c_int
     lib.orc_diagnostics.argtypes = [I64, P, P, P, P, D, D, P]
     lib.orc_diagnostics.restype = C.c_int
+    lib.orc_direct_vjp.argtypes = [I64, P, P, P, D, D, P, P, P]
+    lib.orc_direct_vjp.restype = C.c_int
+    lib.orc_tree_vjp.argtypes = [P, P, P, P, D, D, D, P, P, P]
+    lib.orc_tree_vjp.restype = C.c_int
+    lib.orc_rollout_grad.argtypes = [I64, P, P, P, P, D, D, D, I32, D, I32, P, P, P, P, P]
+    lib.orc_rollout_grad.restype = C.c_int
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = C.c_int
     _lib = lib
@@ -190,6 +196,52 @@ class Tree:
                                       float(softening), float(G), float(theta), _ptr(t), nt,
                                       _ptr(acc), _ptr(phi), _ptr(aabs), _ptr(cnt)))
         return acc, phi, aabs, cnt
+
+
+def direct_vjp(pos, mass, lam, softening=0.0, eps=None, G=1.0):
+    """(g_pos, g_mass): gradient of sum_i lam_i . a_i for the direct sum."""
+    lib = _load()
+    pos = _f64(pos)
+    n = pos.shape[0]
+    mass = _f64(mass, (n,))
+    lam = _f64(lam, (n, 3))
+    eps = None if eps is None else _f64(eps, (n,))
+    gx = np.zeros((n, 3))
+    gm = np.zeros(n)
+    _check(lib.orc_direct_vjp(n, _ptr(pos), _ptr(mass), _ptr(eps), float(softening), float(G),
+                              _ptr(lam), _ptr(gx), _ptr(gm)))
+    return gx, gm
+
+
+def tree_vjp(pos, mass, lam, theta, softening=0.0, eps=None, leaf=16, G=1.0):
+    """(g_pos, g_mass) for the Barnes-Hut force map with its decisions held fixed."""
+    T = Tree(pos, mass, eps, leaf)
+    lam = _f64(lam, (T.n, 3))
+    gx = np.zeros((T.n, 3))
+    gm = np.zeros(T.n)
+    _check(_load().orc_tree_vjp(T._h, _ptr(T.pos), _ptr(T.mass), _ptr(T.eps), float(softening),
+                                float(G), float(theta), _ptr(lam), _ptr(gx), _ptr(gm)))
+    return gx, gm
+
+
+def rollout_grad(pos0, vel0, mass, dt, nsteps, xbar, vbar, softening=0.0, eps=None,
+                 theta=-1.0, leaf=16, G=1.0):
+    """(gx0, gv0, gm) of a loss with dL/dx_T = xbar, dL/dv_T = vbar through
+    nsteps KDK steps from (pos0, vel0), a0 = A(pos0); theta < 0: direct sum."""
+    lib = _load()
+    pos0 = _f64(pos0)
+    n = pos0.shape[0]
+    vel0 = _f64(vel0, (n, 3))
+    mass = _f64(mass, (n,))
+    xbar = _f64(xbar, (n, 3))
+    vbar = _f64(vbar, (n, 3))
+    eps = None if eps is None else _f64(eps, (n,))
+    gx, gv, gm = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros(n)
+    _check(lib.orc_rollout_grad(n, _ptr(pos0), _ptr(vel0), _ptr(mass), _ptr(eps),
+                                float(softening), float(G), float(theta), int(leaf), float(dt),
+                                int(nsteps), _ptr(xbar), _ptr(vbar), _ptr(gx), _ptr(gv),
+                                _ptr(gm)))
+    return gx, gv, gm
 
 
 def bh(pos, mass, theta, softening=0.0, eps=None, leaf=16, G=1.0, targets=None):

@@ -515,3 +515,231 @@ int orc_diagnostics(int64_t n, const double *pos, const double *vel, const doubl
     free(acc);
     return rc;
 }
+
+/* ------------------------------------------------------------------- VJPs */
+
+/* Adjoint of one softened term t = G m_s d / r^3, d = X_s - x_i,
+ * r^2 = |d|^2 + e2, for upstream l (the target's lambda):
+ *   dt/dd = G m_s K, K = I / r^3 - 3 d d^T / r^5;  dt/dm_s = G d / r^3;
+ *   dt/de2 = -3/2 G m_s d / r^5.
+ * Writes gd = G m_s K l (so g_x_i -= gd, g_X_s += gd), gm = G l.d / r^3
+ * and ge2 = -3/2 G m_s (l.d) / r^5. A term with r^2 = 0 contributes 0. */
+static void term_vjp(const double d[3], double e2, double G, double ms, const double l[3],
+                     double gd[3], double *gm, double *ge2)
+{
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + e2;
+    gd[0] = gd[1] = gd[2] = 0.0;
+    *gm = 0.0;
+    *ge2 = 0.0;
+    if (r2 == 0.0) return;
+    double r = sqrt(r2);
+    double inv3 = 1.0 / (r2 * r);
+    double inv5 = inv3 / r2;
+    double ld = l[0] * d[0] + l[1] * d[1] + l[2] * d[2];
+    for (int a = 0; a < 3; a++) gd[a] = G * ms * (l[a] * inv3 - 3.0 * d[a] * ld * inv5);
+    *gm = G * ld * inv3;
+    *ge2 = -1.5 * G * ms * ld * inv5;
+}
+
+int orc_direct_vjp(int64_t n, const double *pos, const double *mass, const double *eps,
+                   double eps0, double G, const double *lambda, double *g_pos, double *g_mass)
+{
+    int rc = check_bodies(n, pos, mass, eps, eps0);
+    if (rc) return rc;
+    if (n > 0 && (!lambda || !g_pos || !g_mass)) return 1;
+    double e02 = eps0 * eps0;
+    for (int64_t i = 0; i < n; i++) {
+        const double *l = lambda + 3 * i;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            double d[3] = {pos[3 * j] - pos[3 * i], pos[3 * j + 1] - pos[3 * i + 1],
+                           pos[3 * j + 2] - pos[3 * i + 2]};
+            double e2 = eps ? 0.5 * (eps[i] * eps[i] + eps[j] * eps[j]) : e02;
+            double gd[3], gm, ge2;
+            term_vjp(d, e2, G, mass[j], l, gd, &gm, &ge2);
+            for (int a = 0; a < 3; a++) {
+                g_pos[3 * i + a] -= gd[a];
+                g_pos[3 * j + a] += gd[a];
+            }
+            g_mass[j] += gm;
+        }
+    }
+    return 0;
+}
+
+typedef struct {
+    const orc_tree *t;
+    const double *pos, *mass, *eps, *lambda;
+    double e02, G, theta2;
+    double *g_pos, *g_mass;     /* body adjoints */
+    double *nX, *nm, *ne2;      /* node adjoints: centre of mass, mass, <eps^2> */
+} vjp_ctx;
+
+static void vjp_node(vjp_ctx *w, int64_t b, const double xb[3], double eb2, const double l[3],
+                     int64_t k)
+{
+    const orc_tree *t = w->t;
+    double gd[3], gm, ge2;
+    if (t->nchild[k] == 0) {
+        for (int64_t s = t->first[k]; s < t->first[k] + t->count[k]; s++) {
+            int64_t j = t->order[s];
+            if (j == b) continue;
+            double d[3] = {w->pos[3 * j] - xb[0], w->pos[3 * j + 1] - xb[1],
+                           w->pos[3 * j + 2] - xb[2]};
+            double e2 = w->eps ? 0.5 * (eb2 + w->eps[j] * w->eps[j]) : w->e02;
+            term_vjp(d, e2, w->G, w->mass[j], l, gd, &gm, &ge2);
+            for (int a = 0; a < 3; a++) {
+                w->g_pos[3 * b + a] -= gd[a];
+                w->g_pos[3 * j + a] += gd[a];
+            }
+            w->g_mass[j] += gm;
+        }
+        return;
+    }
+    double d[3] = {t->com[3 * k] - xb[0], t->com[3 * k + 1] - xb[1], t->com[3 * k + 2] - xb[2]};
+    double D2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    double sd = ldexp(t->L, -t->level[k]);
+    if (sd * sd < w->theta2 * D2) {
+        double e2 = w->eps ? 0.5 * (eb2 + t->eps2[k]) : w->e02;
+        term_vjp(d, e2, w->G, t->m[k], l, gd, &gm, &ge2);
+        for (int a = 0; a < 3; a++) {
+            w->g_pos[3 * b + a] -= gd[a];
+            w->nX[3 * k + a] += gd[a];
+        }
+        w->nm[k] += gm;
+        if (w->eps) w->ne2[k] += 0.5 * ge2; /* e2 = (eps_B^2 + <eps^2>_N) / 2 */
+        return;
+    }
+    for (int64_t c = t->child0[k]; c < t->child0[k] + t->nchild[k]; c++) vjp_node(w, b, xb, eb2, l, c);
+}
+
+int orc_tree_vjp(const orc_tree *t, const double *pos, const double *mass, const double *eps,
+                 double eps0, double G, double theta, const double *lambda, double *g_pos,
+                 double *g_mass)
+{
+    if (!t) return 1;
+    int64_t n = t->n;
+    if (!(theta >= 0.0) || !isfinite(theta)) return 1;
+    if (!eps && !(eps0 >= 0.0 && isfinite(eps0))) return 1;
+    if ((eps != NULL) != (t->has_eps != 0)) return 1;
+    if (n > 0 && (!lambda || !g_pos || !g_mass)) return 1;
+    if (n == 0) return 0;
+    int64_t nn = t->nn;
+    double *nX = (double *)calloc((size_t)nn * 3, sizeof(double));
+    double *nm = (double *)calloc((size_t)nn, sizeof(double));
+    double *ne2 = (double *)calloc((size_t)nn, sizeof(double));
+    if (!nX || !nm || !ne2) {
+        free(nX);
+        free(nm);
+        free(ne2);
+        return 4;
+    }
+    vjp_ctx w = {t, pos, mass, eps, lambda, eps0 * eps0, G, theta * theta, g_pos, g_mass,
+                 nX, nm, ne2};
+    for (int64_t b = 0; b < n; b++) {
+        double eb2 = eps ? eps[b] * eps[b] : 0.0;
+        vjp_node(&w, b, pos + 3 * b, eb2, lambda + 3 * b, 0);
+    }
+    /* A node's centre of mass X_N = sum m_j x_j / m_N, its mass m_N = sum m_j
+     * and softening <eps^2>_N = sum m_j eps_j^2 / m_N depend on every member:
+     *   dX_N/dx_j = m_j / m_N,  dX_N/dm_j = (x_j - X_N) / m_N,  dm_N/dm_j = 1,
+     *   d<eps^2>_N/dm_j = (eps_j^2 - <eps^2>_N) / m_N. */
+    for (int64_t k = 0; k < nn; k++) {
+        double mN = t->m[k];
+        for (int64_t s = t->first[k]; s < t->first[k] + t->count[k]; s++) {
+            int64_t j = t->order[s];
+            g_mass[j] += nm[k];
+            if (!(mN > 0.0)) continue;
+            double dot = 0.0;
+            for (int a = 0; a < 3; a++) {
+                g_pos[3 * j + a] += mass[j] / mN * nX[3 * k + a];
+                dot += (pos[3 * j + a] - t->com[3 * k + a]) * nX[3 * k + a];
+            }
+            g_mass[j] += dot / mN;
+            if (eps) g_mass[j] += ne2[k] * (eps[j] * eps[j] - t->eps2[k]) / mN;
+        }
+    }
+    free(nX);
+    free(nm);
+    free(ne2);
+    return 0;
+}
+
+/* VJP of A at pos for upstream lam: adds into gx and gm. */
+static int accel_vjp(int64_t n, const double *pos, const double *mass, const double *eps,
+                     double eps0, double G, double theta, int32_t leaf, const double *lam,
+                     double *gx, double *gm)
+{
+    if (theta < 0.0) return orc_direct_vjp(n, pos, mass, eps, eps0, G, lam, gx, gm);
+    int err = 0;
+    orc_tree *t = orc_tree_build(n, pos, mass, eps, leaf, &err);
+    if (!t) return err;
+    int rc = orc_tree_vjp(t, pos, mass, eps, eps0, G, theta, lam, gx, gm);
+    orc_tree_free(t);
+    return rc;
+}
+
+int orc_rollout_grad(int64_t n, const double *pos0, const double *vel0, const double *mass,
+                     const double *eps, double eps0, double G, double theta, int32_t leaf,
+                     double dt, int32_t nsteps, const double *xbar, const double *vbar,
+                     double *gx0, double *gv0, double *gm)
+{
+    if (n < 0 || nsteps < 0 || !isfinite(dt)) return 1;
+    if (n == 0) return 0;
+    size_t n3 = (size_t)n * 3;
+    /* forward: positions x_0..x_T (each step's acceleration is A(x_k)) */
+    double *X = (double *)malloc((size_t)(nsteps + 1) * n3 * sizeof(double));
+    double *v = (double *)malloc(n3 * sizeof(double));
+    double *a = (double *)malloc(n3 * sizeof(double));
+    double *xb = (double *)malloc(n3 * sizeof(double));
+    double *vb = (double *)malloc(n3 * sizeof(double));
+    double *ab = (double *)malloc(n3 * sizeof(double));
+    int rc = 0;
+    if (!X || !v || !a || !xb || !vb || !ab) {
+        rc = 4;
+        goto done;
+    }
+    memcpy(X, pos0, n3 * sizeof(double));
+    memcpy(v, vel0, n3 * sizeof(double));
+    rc = accel_all(n, X, mass, eps, eps0, G, theta, leaf, a);
+    if (rc) goto done;
+    double h = 0.5 * dt;
+    for (int32_t s = 0; s < nsteps; s++) {
+        double *x = X + (size_t)s * n3, *xn = X + (size_t)(s + 1) * n3;
+        for (size_t i = 0; i < n3; i++) v[i] += h * a[i];
+        for (size_t i = 0; i < n3; i++) xn[i] = x[i] + dt * v[i];
+        rc = accel_all(n, xn, mass, eps, eps0, G, theta, leaf, a);
+        if (rc) goto done;
+        for (size_t i = 0; i < n3; i++) v[i] += h * a[i];
+    }
+    /* Reverse mode. Step s maps (x_s, v_s, a_s) to (x_{s+1}, v_{s+1}, a_{s+1}):
+     *   u = v_s + h a_s;  x_{s+1} = x_s + dt u;  a_{s+1} = A(x_{s+1});
+     *   v_{s+1} = u + h a_{s+1}.
+     * a_{s+1} feeds this step's second kick and step s+1's first kick, so its
+     * adjoint is complete after this step's second kick has been added, and
+     * one VJP per step is applied at x_{s+1}; a_0 = A(x_0) takes one more. */
+    memcpy(xb, xbar, n3 * sizeof(double));
+    memcpy(vb, vbar, n3 * sizeof(double));
+    for (size_t i = 0; i < n3; i++) ab[i] = 0.0;
+    for (size_t i = 0; i < (size_t)n; i++) gm[i] = 0.0;
+    for (int32_t s = nsteps - 1; s >= 0; s--) {
+        const double *xn = X + (size_t)(s + 1) * n3;
+        for (size_t i = 0; i < n3; i++) ab[i] += h * vb[i];          /* second kick */
+        rc = accel_vjp(n, xn, mass, eps, eps0, G, theta, leaf, ab, xb, gm);
+        if (rc) goto done;
+        for (size_t i = 0; i < n3; i++) vb[i] += dt * xb[i];         /* drift: u-bar */
+        for (size_t i = 0; i < n3; i++) ab[i] = h * vb[i];           /* first kick */
+    }
+    rc = accel_vjp(n, X, mass, eps, eps0, G, theta, leaf, ab, xb, gm);
+    if (rc) goto done;
+    memcpy(gx0, xb, n3 * sizeof(double));
+    memcpy(gv0, vb, n3 * sizeof(double));
+done:
+    free(X);
+    free(v);
+    free(a);
+    free(xb);
+    free(vb);
+    free(ab);
+    return rc;
+}

@@ -72,6 +72,28 @@ int orc_leapfrog(int64_t n, double *pos, double *vel, const double *mass,
 int orc_diagnostics(int64_t n, const double *pos, const double *vel, const double *mass,
                     const double *eps, double eps0, double G, double out[8]);
 
+/* Vector-Jacobian products of the force map, with the tree and every opening
+ * decision held fixed (they are piecewise constant in the inputs). For an
+ * upstream lambda (nt x 3, one row per body), ADDS to g_pos (n x 3) and
+ * g_mass (n) the gradient of sum_i lambda_i . a_i. The direct form sums all
+ * pairs; the tree form walks the same interaction lists as orc_tree_accel and
+ * carries node adjoints to the node's members through the centre of mass,
+ * the node mass and the mass-weighted softening. Single-threaded. */
+int orc_direct_vjp(int64_t n, const double *pos, const double *mass, const double *eps,
+                   double eps0, double G, const double *lambda, double *g_pos, double *g_mass);
+int orc_tree_vjp(const orc_tree *t, const double *pos, const double *mass, const double *eps,
+                 double eps0, double G, double theta, const double *lambda, double *g_pos,
+                 double *g_mass);
+
+/* Gradient of a scalar loss through nsteps kick-drift-kick steps that start
+ * from (pos0, vel0) with a0 = A(pos0): given xbar, vbar = dL/dx_T, dL/dv_T,
+ * writes gx0 = dL/dx0, gv0 = dL/dv0 and gm = dL/dm (all decisions of every
+ * tree fixed). Reverse mode over the stored trajectory. */
+int orc_rollout_grad(int64_t n, const double *pos0, const double *vel0, const double *mass,
+                     const double *eps, double eps0, double G, double theta, int32_t leaf,
+                     double dt, int32_t nsteps, const double *xbar, const double *vbar,
+                     double *gx0, double *gv0, double *gm);
+
 /* Number of OpenMP threads the oracle uses. */
 int orc_num_threads(void);
 

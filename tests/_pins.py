@@ -394,4 +394,192 @@ def pin_diagnostics_two_body():
     assert np.abs(d[2:5]).max() < 1e-16
 
 
+# ------------------------------------------------------------------- adjoint
+
+def _fd_case(seed=21, n=160):
+    s = ics.uniform_ball(n, seed=seed)
+    rng = np.random.default_rng(seed)
+    m = s.mass * (1.0 + rng.random(n))
+    eps = 0.02 + 0.02 * rng.random(n)
+    lam = rng.standard_normal((n, 3))
+    return s.pos, m, eps, lam, rng
+
+
+def _frozen(x1, x2, m1, m2, eps, theta, leaf):
+    """True when the tree and every opening decision agree for two inputs."""
+    t1, t2 = oracle.Tree(x1, m1, eps, leaf), oracle.Tree(x2, m2, eps, leaf)
+    e1, e2 = t1.export(), t2.export()
+    if t1.nnodes != t2.nnodes:
+        return False
+    for k in ("level", "first", "count", "nchild"):
+        if not np.array_equal(e1[k], e2[k]):
+            return False
+    return np.array_equal(t1.accel(theta)[3], t2.accel(theta)[3])
+
+
+def _check_fd(f, grad_x, grad_m, x, m, coords, mcoords, tol, freeze=None):
+    checked = 0
+    for (i, a) in coords:
+        h = 1e-6
+        xp, xm = x.copy(), x.copy()
+        xp[i, a] += h
+        xm[i, a] -= h
+        if freeze is not None and not (freeze(xp, x, m, m) and freeze(xm, x, m, m)):
+            continue
+        fd = (f(xp, m) - f(xm, m)) / (2 * h)
+        assert abs(grad_x[i, a] - fd) <= tol * max(abs(fd), 1e-3), (i, a, grad_x[i, a], fd)
+        checked += 1
+    for i in mcoords:
+        h = 1e-5 * m[i]
+        mp, mm = m.copy(), m.copy()
+        mp[i] += h
+        mm[i] -= h
+        if freeze is not None and not (freeze(x, x, mp, m) and freeze(x, x, mm, m)):
+            continue
+        fd = (f(x, mp) - f(x, mm)) / (2 * h)
+        assert abs(grad_m[i] - fd) <= tol * max(abs(fd), 1e-3), (i, grad_m[i], fd)
+        checked += 1
+    assert checked >= 12, checked
+
+
+def pin_vjp_direct_finite_differences():
+    """Direct-sum VJP against central differences of lambda . a(x, m)."""
+    x, m, eps, lam, rng = _fd_case()
+    f = lambda xx, mm: float((lam * oracle.direct(xx, mm, eps=eps, G=1.3)[0]).sum())
+    gx, gm = oracle.direct_vjp(x, m, lam, eps=eps, G=1.3)
+    coords = [(int(rng.integers(len(x))), int(rng.integers(3))) for _ in range(12)]
+    _check_fd(f, gx, gm, x, m, coords, rng.integers(len(x), size=6), 1e-6)
+
+
+def pin_vjp_tree_finite_differences():
+    """Tree VJP (decisions fixed) against central differences of the tree
+    force map; a coordinate whose +-h moves a cell boundary or flips an
+    opening decision is skipped."""
+    x, m, eps, lam, rng = _fd_case(seed=22)
+    theta, leaf = 0.65, 4
+    f = lambda xx, mm: float((lam * oracle.bh(xx, mm, theta, eps=eps, leaf=leaf)[0]).sum())
+    gx, gm = oracle.tree_vjp(x, m, lam, theta, eps=eps, leaf=leaf)
+    freeze = lambda x1, x2, m1, m2: _frozen(x1, x2, m1, m2, eps, theta, leaf)
+    coords = [(int(rng.integers(len(x))), int(rng.integers(3))) for _ in range(14)]
+    _check_fd(f, gx, gm, x, m, coords, rng.integers(len(x), size=6), 1e-6, freeze)
+
+
+def pin_vjp_invariants():
+    """Translation invariance (sum_i g_x_i = 0) and degree-1 homogeneity in the
+    masses (sum_j m_j g_m_j = lambda . a), for the direct sum and the tree."""
+    x, m, eps, lam, _ = _fd_case(seed=23, n=400)
+    for theta in (None, 0.4, 0.8):
+        if theta is None:
+            gx, gm = oracle.direct_vjp(x, m, lam, eps=eps)
+            a = oracle.direct(x, m, eps=eps)[0]
+        else:
+            gx, gm = oracle.tree_vjp(x, m, lam, theta, eps=eps, leaf=8)
+            a = oracle.bh(x, m, theta, eps=eps, leaf=8)[0]
+        scale = float(np.abs(gx).sum())
+        assert np.abs(gx.sum(0)).max() <= 1e-13 * scale, theta
+        la = float((lam * a).sum())
+        assert abs(float((m * gm).sum()) - la) <= 1e-12 * float(np.abs(lam * a).sum()), theta
+
+
+def pin_vjp_theta_zero_is_direct():
+    x, m, eps, lam, _ = _fd_case(seed=24, n=300)
+    for e in (None, eps):
+        gd = oracle.direct_vjp(x, m, lam, softening=0.01, eps=e)
+        gt = oracle.tree_vjp(x, m, lam, 0.0, softening=0.01, eps=e, leaf=3)
+        np.testing.assert_allclose(gt[0], gd[0], rtol=1e-11, atol=1e-11 * np.abs(gd[0]).max())
+        np.testing.assert_allclose(gt[1], gd[1], rtol=1e-11, atol=1e-11 * np.abs(gd[1]).max())
+
+
+def pin_vjp_direct_torch_autograd():
+    """Direct VJP against torch autograd of an all-pairs FP64 force (CPU)."""
+    import torch
+
+    x, m, eps, lam, _ = _fd_case(seed=25, n=120)
+    xt = torch.tensor(x, requires_grad=True)
+    mt = torch.tensor(m, requires_grad=True)
+    e = torch.tensor(eps)
+    d = xt[None, :, :] - xt[:, None, :]
+    r2 = (d * d).sum(-1) + 0.5 * (e[:, None] ** 2 + e[None, :] ** 2)
+    eye = torch.eye(len(x), dtype=torch.bool)
+    inv3 = torch.where(eye, torch.zeros_like(r2), r2.clamp_min(1e-300) ** -1.5)
+    acc = (mt[None, :, None] * d * inv3[..., None]).sum(1)
+    (acc * torch.tensor(lam)).sum().backward()
+    gx, gm = oracle.direct_vjp(x, m, lam, eps=eps)
+    np.testing.assert_allclose(gx, xt.grad.numpy(), rtol=1e-10, atol=1e-12 * np.abs(gx).max())
+    np.testing.assert_allclose(gm, mt.grad.numpy(), rtol=1e-10, atol=1e-12 * np.abs(gm).max())
+
+
+def _rollout_case():
+    s = ics.plummer(40, seed=26)
+    rng = np.random.default_rng(26)
+    m = s.mass * (1.0 + rng.random(40))
+    xt = s.pos + 0.01 * rng.standard_normal(s.pos.shape)
+    return s, m, xt, rng
+
+
+def pin_rollout_grad_finite_differences():
+    """Reverse-mode rollout gradient against central differences of
+    L = sum |x_T - x*|^2 + 0.3 sum |v_T|^2 through 10 KDK steps."""
+    s, m, xt, rng = _rollout_case()
+    dt, T, soft = 2e-3, 10, 0.05
+    for theta in (-1.0, 0.6):
+        def loss(x0, v0, mm):
+            x, v, _ = oracle.leapfrog(x0, v0, mm, dt, T, softening=soft, theta=theta, leaf=4)
+            return float(((x - xt) ** 2).sum() + 0.3 * (v ** 2).sum())
+        x, v, _ = oracle.leapfrog(s.pos, s.vel, m, dt, T, softening=soft, theta=theta, leaf=4)
+        gx, gv, gm = oracle.rollout_grad(s.pos, s.vel, m, dt, T, 2 * (x - xt), 0.6 * v,
+                                         softening=soft, theta=theta, leaf=4)
+        for (i, a) in [(3, 0), (21, 1), (39, 2)]:
+            for arr, g in ((s.pos, gx), (s.vel, gv)):
+                h = 1e-6
+                p, q = arr.copy(), arr.copy()
+                p[i, a] += h
+                q[i, a] -= h
+                if arr is s.pos:
+                    fd = (loss(p, s.vel, m) - loss(q, s.vel, m)) / (2 * h)
+                else:
+                    fd = (loss(s.pos, p, m) - loss(s.pos, q, m)) / (2 * h)
+                assert abs(g[i, a] - fd) <= 1e-5 * max(abs(fd), 1e-4), (theta, i, a, g[i, a], fd)
+        for i in (2, 30):
+            h = 1e-4 * m[i]
+            p, q = m.copy(), m.copy()
+            p[i] += h
+            q[i] -= h
+            fd = (loss(s.pos, s.vel, p) - loss(s.pos, s.vel, q)) / (2 * h)
+            assert abs(gm[i] - fd) <= 1e-4 * max(abs(fd), 1e-4), (theta, i, gm[i], fd)
+
+
+def pin_rollout_grad_torch_autograd():
+    """Direct-sum rollout gradient against torch autograd of the same KDK
+    steps written with torch FP64 CPU ops."""
+    import torch
+
+    s, m, xt, _ = _rollout_case()
+    dt, T, soft = 2e-3, 8, 0.05
+    x0 = torch.tensor(s.pos, requires_grad=True)
+    v0 = torch.tensor(s.vel, requires_grad=True)
+    mt = torch.tensor(m, requires_grad=True)
+
+    def accel(x):
+        d = x[None, :, :] - x[:, None, :]
+        inv3 = ((d * d).sum(-1) + soft * soft) ** -1.5
+        inv3 = inv3 * (1 - torch.eye(len(m), dtype=x.dtype))
+        return (mt[None, :, None] * d * inv3[..., None]).sum(1)
+
+    x, v, a = x0, v0, accel(x0)
+    for _ in range(T):
+        v = v + 0.5 * dt * a
+        x = x + dt * v
+        a = accel(x)
+        v = v + 0.5 * dt * a
+    loss = ((x - torch.tensor(xt)) ** 2).sum() + 0.3 * (v ** 2).sum()
+    loss.backward()
+    xf, vf, _ = oracle.leapfrog(s.pos, s.vel, m, dt, T, softening=soft)
+    gx, gv, gm = oracle.rollout_grad(s.pos, s.vel, m, dt, T, 2 * (xf - xt), 0.6 * vf,
+                                     softening=soft)
+    np.testing.assert_allclose(gx, x0.grad.numpy(), rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(gv, v0.grad.numpy(), rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(gm, mt.grad.numpy(), rtol=1e-9, atol=1e-12)
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]
