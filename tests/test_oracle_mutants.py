@@ -40,7 +40,8 @@ MUTANTS = {
                   "if (count >= t->leaf && level < ORC_MAX_LEVEL) {"),
     "root_half_box": ("t->x0[a] = (t->lo[a] + t->hi[a]) * 0.5 - L * 0.5;",
                       "t->x0[a] = t->lo[a] + L * 0.25;"),
-    "kick_full": ("double h = 0.5 * dt;", "double h = dt;"),
+    "kick_full": ("vel[i] += h * acc[i]; /* kick */\n        for (int64_t i = 0; i < 3 * n; i++) pos[i]",
+                  "vel[i] += dt * acc[i]; /* kick */\n        for (int64_t i = 0; i < 3 * n; i++) pos[i]"),
     "drift_old_acc": ("for (int64_t i = 0; i < 3 * n; i++) pos[i] += dt * vel[i]; /* drift */",
                       "for (int64_t i = 0; i < 3 * n; i++) pos[i] += dt * (vel[i] - 0.5 * dt * acc[i]);"),
     "ekin_no_half": ("out[0] += 0.5 * m * (v[0] * v[0]", "out[0] += m * (v[0] * v[0]"),
