@@ -18,7 +18,7 @@ SRC = os.path.join(os.path.dirname(oracle.__file__), "bh_oracle.c")
 MUTANTS = {
     "pair_sign": ("acc[0] += gm * dx * inv3;", "acc[0] -= gm * dx * inv3;"),
     "pair_drop_z": ("double d2 = dx * dx + dy * dy + dz * dz;", "double d2 = dx * dx + dy * dy;"),
-    "r3_to_r2": ("double inv3 = 1.0 / (r2 * r);", "double inv3 = 1.0 / r2;"),
+    "r3_to_r2": ("double inv3 = 1.0 / (r2 * r);\n    acc[0]", "double inv3 = 1.0 / r2;\n    acc[0]"),
     "direct_swap_ij": ("add_term(pos[3 * j] - pos[3 * i],", "add_term(pos[3 * i] - pos[3 * j],"),
     "direct_self": ("if (j == i) continue; /* j != i in eq. (Newton) */", ""),
     "soft_receiver_only": ("double e2 = eps ? 0.5 * (ei2 + eps[j] * eps[j]) : e02;",
