@@ -65,8 +65,10 @@ enum { BH_FP64 = 0, BH_FP32C = 1 };
 /* bh_config.flags */
 enum {
     BH_FLAG_COUNTS = 1u, /* keep per-body walk counts for bh_walk_counts() */
-    BH_FLAG_TIMING = 2u  /* record HIP events around every tree build and walk
+    BH_FLAG_TIMING = 2u, /* record HIP events around every tree build and walk
                             on the context's stream; totals in bh_stats() */
+    BH_FLAG_ADJOINT = 4u /* allocate the workspace of bh_accel_vjp and
+                            bh_leapfrog_vjp at creation */
 };
 
 typedef struct {
@@ -144,6 +146,40 @@ bh_status bh_step_leapfrog(bh_ctx *ctx, double *pos, double *vel, const double *
  * int32. Needs BH_FLAG_COUNTS at creation (else BH_E_STATE); n must equal the
  * last walk's n (else BH_E_INVALID). */
 bh_status bh_walk_counts(bh_ctx *ctx, int32_t *counts, int64_t n);
+
+/* Vector-Jacobian product of the force map: ADDS to g_pos (n x 3) and g_mass
+ * (n) the gradient of sum_i lambda_i . a_i with respect to the positions and
+ * masses, lambda being n x 3 in caller order. theta >= 0 differentiates the
+ * Barnes-Hut map of bh_compute_accel with its tree and every opening decision
+ * held fixed (both are piecewise constant in the inputs): a node term passes
+ * its adjoint to the node's members through the centre of mass, the node
+ * mass and the mass-weighted softening (eq. COMinternal). theta < 0
+ * differentiates the direct sum. Computed in FP64 whatever the precision; the
+ * tree form adds source-side terms with atomics, so its last bits depend on
+ * scheduling. Needs BH_FLAG_ADJOINT (else BH_E_STATE). Errors: as
+ * bh_compute_accel, plus BH_E_INVALID for NULL lambda, g_pos or g_mass. */
+bh_status bh_accel_vjp(bh_ctx *ctx, const double *pos, const double *mass, double softening,
+                       const double *eps, double theta, const double *lambda, double *g_pos,
+                       double *g_mass, int64_t n);
+
+/* Backward pass over one segment of kick-drift-kick steps, for a gradient
+ * through bh_step_leapfrog with checkpointing. The segment starts from pos,
+ * vel and acc = A(pos) (the checkpoint, unchanged) and takes nsteps steps of
+ * dt; the positions after each step are recomputed into traj (caller-owned,
+ * nsteps x n x 3 float64) with the context's precision, exactly as
+ * bh_step_leapfrog computes them. On entry xbar, vbar (n x 3) hold the
+ * gradient with respect to the segment's final positions and velocities and
+ * abar (n x 3) the gradient with respect to its final acceleration; on return
+ * they hold the gradient with respect to pos, vel and acc. One
+ * bh_accel_vjp-equivalent product is taken per step (at the positions after
+ * it) and its mass gradient ADDED to g_mass. The dependence of acc on pos is
+ * left to the caller (a bh_accel_vjp at the rollout's first positions with
+ * the final abar). Needs BH_FLAG_ADJOINT. Errors: as bh_step_leapfrog, plus
+ * BH_E_INVALID for NULL traj, xbar, vbar, abar or g_mass. */
+bh_status bh_leapfrog_vjp(bh_ctx *ctx, const double *pos, const double *vel, const double *acc,
+                          const double *mass, double softening, const double *eps, double theta,
+                          double dt, int32_t nsteps, double *traj, double *xbar, double *vbar,
+                          double *abar, double *g_mass, int64_t n);
 
 /* Borrowed device view of the tree of the last build, valid until the next
  * build or bh_destroy. Bodies are held in Morton order: order[s] is the caller

@@ -15,6 +15,7 @@ STATUS_NAMES = ["BH_OK", "BH_E_INVALID", "BH_E_NONFINITE", "BH_E_CAPACITY", "BH_
 BH_FP64, BH_FP32C = 0, 1
 BH_FLAG_COUNTS = 1
 BH_FLAG_TIMING = 2
+BH_FLAG_ADJOINT = 4
 
 
 class bh_config(C.Structure):
@@ -51,6 +52,8 @@ SIGNATURES = {
     "bh_stats": ([P, C.POINTER(bh_stats_t)], C.c_int),
     "bh_diagnostics": ([P, P, P, P, D, P, P, I64], C.c_int),
     "bh_timing_reset": ([P], C.c_int),
+    "bh_accel_vjp": ([P, P, P, D, P, D, P, P, P, I64], C.c_int),
+    "bh_leapfrog_vjp": ([P, P, P, P, P, D, P, D, D, I32, P, P, P, P, P, I64], C.c_int),
 }
 
 _lib = None

@@ -76,12 +76,14 @@ class Context:
     """
 
     def __init__(self, n_max: int, leaf_size: int = 16, precision: str = "fp32c", G: float = 1.0,
-                 counts: bool = False, timing: bool = False, walk_group: int = 0):
+                 counts: bool = False, timing: bool = False, walk_group: int = 0,
+                 adjoint: bool = False):
         self._lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: libbhx runs on the GPU only")
         prec = {"fp64": L.BH_FP64, "fp32c": L.BH_FP32C}[precision]
-        flags = (L.BH_FLAG_COUNTS if counts else 0) | (L.BH_FLAG_TIMING if timing else 0)
+        flags = ((L.BH_FLAG_COUNTS if counts else 0) | (L.BH_FLAG_TIMING if timing else 0)
+                 | (L.BH_FLAG_ADJOINT if adjoint else 0))
         cfg = L.bh_config(int(n_max), int(leaf_size), prec, float(G), flags, int(walk_group))
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.n_max, self.leaf_size, self.precision, self.G = int(n_max), int(leaf_size), precision, float(G)
@@ -172,6 +174,42 @@ class Context:
         self._rc(self._lib.bh_step_leapfrog(self._h, _ptr(pos), _ptr(vel), _ptr(mass),
                                             float(softening), _ptr(eps), float(theta), float(dt),
                                             int(nsteps), _ptr(acc), n))
+        if sync:
+            self.sync()
+
+    def accel_vjp(self, pos, mass, lam, theta=0.5, softening=0.0, eps=None, g_pos=None,
+                  g_mass=None, sync=True):
+        """Adds the gradient of sum lam_i . a_i into (g_pos, g_mass) and returns them
+        (new zero tensors when not given). theta < 0: direct sum."""
+        n = self._bodies(pos, mass, eps)
+        _check_f64("lam", lam, (n, 3), self.device)
+        g_pos = torch.zeros((n, 3), dtype=torch.float64, device=self.device) if g_pos is None else g_pos
+        g_mass = torch.zeros(n, dtype=torch.float64, device=self.device) if g_mass is None else g_mass
+        _check_f64("g_pos", g_pos, (n, 3), self.device)
+        _check_f64("g_mass", g_mass, (n,), self.device)
+        self._bind()
+        self._rc(self._lib.bh_accel_vjp(self._h, _ptr(pos), _ptr(mass), float(softening), _ptr(eps),
+                                        float(theta), _ptr(lam), _ptr(g_pos), _ptr(g_mass), n))
+        if sync:
+            self.sync()
+        return g_pos, g_mass
+
+    def leapfrog_vjp(self, pos, vel, acc, mass, dt, nsteps, traj, xbar, vbar, abar, g_mass,
+                     theta=0.5, softening=0.0, eps=None, sync=True):
+        """Backward over one checkpoint segment (see bh_leapfrog_vjp); updates
+        xbar, vbar, abar in place and adds into g_mass."""
+        n = self._bodies(pos, mass, eps)
+        for name, t in (("vel", vel), ("acc", acc), ("xbar", xbar), ("vbar", vbar), ("abar", abar)):
+            _check_f64(name, t, (n, 3), self.device)
+        _check_f64("g_mass", g_mass, (n,), self.device)
+        if nsteps > 0:
+            if traj.dtype != torch.float64 or not traj.is_contiguous() or traj.numel() < nsteps * n * 3:
+                raise ValueError("traj must be a contiguous float64 GPU buffer of nsteps x n x 3")
+        self._bind()
+        self._rc(self._lib.bh_leapfrog_vjp(self._h, _ptr(pos), _ptr(vel), _ptr(acc), _ptr(mass),
+                                           float(softening), _ptr(eps), float(theta), float(dt),
+                                           int(nsteps), _ptr(traj), _ptr(xbar), _ptr(vbar),
+                                           _ptr(abar), _ptr(g_mass), n))
         if sync:
             self.sync()
 

@@ -1,0 +1,606 @@
+// Vector-Jacobian products of the force map (the gradient of
+// sum_i lambda_i . a_i with respect to positions and masses), with the tree
+// and every opening decision held fixed, and the elementwise parts of the
+// kick-drift-kick adjoint.
+//
+// For one softened term t = G m_s d / r^3 (d = X_s - x_i, r^2 = |d|^2 + e2)
+// and the target's upstream lambda:
+//   dt/dd = G m_s K, K = I / r^3 - 3 d d^T / r^5   (x_i gets -K lambda, X_s +K lambda)
+//   dt/dm_s = G d / r^3,   dt/de2 = -3/2 G m_s d / r^5.
+// A node source passes its adjoints to its members through its centre of mass
+// X_N = sum m_j x_j / m_N, its mass m_N = sum m_j and its mass-weighted
+// softening <eps^2>_N = sum m_j eps_j^2 / m_N.
+//
+// Tree VJP, on the GPU:
+//   1. the same build as the forward evaluation (deterministic, so the same
+//      tree and decisions);
+//   2. a walk with the forward walk's traversal (one wave per 64 Morton-
+//      consecutive targets, per-lane masks, batched rounds and staged
+//      items); per interaction each lane adds its target-side term to
+//      registers, and the wave sums the source-side terms and adds them with
+//      one FP64 atomic per (group, source) into the body or node adjoints;
+//   3. node adjoints become per-node coefficients (A = gX / m_N,
+//      E = ge2 / m_N, C = gm - X.A - <eps^2> E), summed top-down over each
+//      body's ancestors, one launch per level;
+//   4. per body: g_x += m_j sum A, g_m += sum C + x_j . sum A + eps_j^2 sum E,
+//      plus its own target and source terms, added into the caller's arrays.
+// Source-side atomics make the last bits of the gradients order-dependent.
+#include "bhx_impl.h"
+
+namespace bhx {
+namespace {
+
+constexpr int kStack = 320;
+constexpr int kReserve = 150;
+constexpr int kRanges = 8;
+constexpr int kPop = 8 * kRanges;
+constexpr int kRing = 128;
+constexpr int kBatch = 64;
+
+struct alignas(16) ItemV {  // staged source
+    double x, y, z, m;
+    double e2;      // source's squared softening (eps_j^2 or <eps^2>_N)
+    uint64_t mask;
+    int32_t src;    // sorted body index, or ~node
+    int32_t pad0;
+    int64_t pad1;
+};
+struct alignas(16) PopCom {
+    double x, y, z, s2;
+};
+struct alignas(16) PopData {
+    uint64_t mask;
+    int32_t node, first, count, child0;
+    int32_t nch, pad;
+};
+
+__device__ inline uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ inline uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+__device__ inline double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ inline bool accept_node(double cx, double cy, double cz, double bx, double by,
+                                   double bz, double s2, double th2)
+{
+#pragma clang fp contract(off)
+    double dx = cx - bx, dy = cy - by, dz = cz - bz;
+    double D2 = dx * dx + dy * dy + dz * dz;
+    return s2 < th2 * D2;
+}
+
+// badj: per sorted body {gX x, y, z, gm}; nadj: per node {gX x, y, z, gm, ge2}.
+template <bool PEPS>
+__global__ __launch_bounds__(64) void k_vjp_walk(
+    const Body *__restrict__ body, const double *__restrict__ beps2,
+    const NodeInfo *__restrict__ ninfo, const NodeMom *__restrict__ nmom,
+    const double *__restrict__ neps2, const uint32_t *__restrict__ idx,
+    const TreeHeader *__restrict__ hdr, int64_t n, int ngroups, int per_xcd, double th2,
+    double eps0sq, double G, const double *__restrict__ lambda, double *__restrict__ gt,
+    double *__restrict__ badj, double *__restrict__ nadj)
+{
+    __shared__ int32_t st_c0[kStack];
+    __shared__ int32_t st_n[kStack];
+    __shared__ uint64_t st_mask[kStack];
+    __shared__ int32_t dq_a[kRing];
+    __shared__ int32_t dq_n[kRing];
+    __shared__ uint32_t dq_at[kRing];
+    __shared__ uint64_t dq_mask[kRing];
+    __shared__ double s2tab[kLevels];
+    union Shared {
+        struct {
+            PopCom pc[kPop];
+            PopData pd[kPop];
+        } pop;
+        ItemV items[kBatch];
+    };
+    __shared__ Shared sh;
+    PopCom *const pc = sh.pop.pc;
+    PopData *const pd = sh.pop.pd;
+    ItemV *const items = sh.items;
+
+    const int grp = (int)(blockIdx.x & 7u) * per_xcd + (int)(blockIdx.x >> 3);
+    if (grp >= ngroups) return;
+    const int lane = threadIdx.x;
+    const int64_t g0 = (int64_t)grp * 64;
+    const int64_t s = g0 + lane;
+    const bool valid = s < n;
+    const Body me = body[valid ? s : g0];
+    const double eb2 = PEPS ? beps2[valid ? s : g0] : 0.0;
+    double lx = 0.0, ly = 0.0, lz = 0.0;
+    if (valid) {
+        const int64_t o = idx[s];
+        lx = lambda[3 * o];
+        ly = lambda[3 * o + 1];
+        lz = lambda[3 * o + 2];
+    }
+    const uint64_t active = __ballot(valid);
+    if (lane < kLevels) s2tab[lane] = hdr->s2[lane];
+
+    double gx = 0.0, gy = 0.0, gz = 0.0;  // target-side gradient of this lane's body
+    int sp = 1, dq_head = 0, dq_tail = 0;
+    uint32_t queued = 0, consumed = 0;
+    if (lane == 0) {
+        st_c0[0] = 0;
+        st_n[0] = 1;
+        st_mask[0] = active;
+    }
+    __syncthreads();
+
+    auto evaluate = [&](int c) {
+        if (lane < c) {
+            const uint32_t q = consumed + (uint32_t)lane;
+            int lo = 0, hi = dq_tail - dq_head - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (dq_at[(dq_head + mid) % kRing] <= q)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            const int d = (dq_head + lo) % kRing;
+            const int32_t a = dq_a[d];
+            uint64_t mk = dq_mask[d];
+            ItemV it;
+            if (a >= 0) {
+                const int32_t src = a + (int32_t)(q - dq_at[d]);
+                const int64_t rel = (int64_t)src - g0;
+                if (rel >= 0 && rel < 64) mk &= ~(1ull << rel);
+                const Body b = body[src];
+                it = ItemV{b.x, b.y, b.z, b.m, PEPS ? beps2[src] : 0.0, mk, src, 0, 0};
+            } else {
+                const NodeMom nm = nmom[~a];
+                it = ItemV{nm.x, nm.y, nm.z, nm.m, PEPS ? neps2[~a] : 0.0, mk, a, 0, 0};
+            }
+            items[lane] = it;
+        }
+        __syncthreads();
+#pragma unroll 1
+        for (int j = 0; j < c; j++) {
+            const ItemV it = items[j];
+            if (it.mask == 0) continue;  // uniform: nobody takes this item
+            const bool on = (it.mask >> lane) & 1ull;
+            const double dx = it.x - me.x, dy = it.y - me.y, dz = it.z - me.z;
+            const double e2 = PEPS ? 0.5 * (eb2 + it.e2) : eps0sq;
+            const double r2 = dx * dx + dy * dy + dz * dz + e2;
+            double tx = 0.0, ty = 0.0, tz = 0.0, tm = 0.0, te = 0.0;
+            if (on && r2 > 0.0) {
+                const double r = sqrt(r2);
+                const double inv3 = 1.0 / (r2 * r);
+                const double inv5 = inv3 / r2;
+                const double ld = lx * dx + ly * dy + lz * dz;
+                const double gms = G * it.m;
+                tx = gms * (lx * inv3 - 3.0 * dx * ld * inv5);
+                ty = gms * (ly * inv3 - 3.0 * dy * ld * inv5);
+                tz = gms * (lz * inv3 - 3.0 * dz * ld * inv5);
+                tm = G * ld * inv3;
+                te = -1.5 * gms * ld * inv5;
+            }
+            gx -= tx;
+            gy -= ty;
+            gz -= tz;
+            tx = wave_sum(tx);
+            ty = wave_sum(ty);
+            tz = wave_sum(tz);
+            tm = wave_sum(tm);
+            if (it.src >= 0) {
+                if (lane == 0) {
+                    double *b = badj + 4 * (int64_t)it.src;
+                    unsafeAtomicAdd(b, tx);
+                    unsafeAtomicAdd(b + 1, ty);
+                    unsafeAtomicAdd(b + 2, tz);
+                    unsafeAtomicAdd(b + 3, tm);
+                }
+            } else {
+                if (PEPS) te = wave_sum(te);
+                if (lane == 0) {
+                    double *b = nadj + 5 * (int64_t)(~it.src);
+                    unsafeAtomicAdd(b, tx);
+                    unsafeAtomicAdd(b + 1, ty);
+                    unsafeAtomicAdd(b + 2, tz);
+                    unsafeAtomicAdd(b + 3, tm);
+                    // e2 = (eps_B^2 + <eps^2>_N) / 2
+                    if (PEPS) unsafeAtomicAdd(b + 4, 0.5 * te);
+                }
+            }
+        }
+        consumed += (uint32_t)c;
+        while (dq_head < dq_tail) {
+            const int d = dq_head % kRing;
+            const uint32_t end =
+                (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(dq_at[d] + (uint32_t)dq_n[d]));
+            if (end > consumed) break;
+            dq_head++;
+        }
+        __syncthreads();
+    };
+
+    while (sp > 0) {
+        int cr = min(kRanges, sp);
+        const int room = (kStack - kReserve - sp) / 7;
+        if (cr > room) cr = room > 1 ? room : 1;
+        const int base = sp - cr;
+        int32_t k = -1;
+        uint64_t mk = 0;
+        {
+            const int r = lane >> 3, o = lane & 7;
+            if (r < cr) {
+                const int e = base + r;
+                if (o < st_n[e]) {
+                    k = st_c0[e] + o;
+                    mk = st_mask[e];
+                }
+            }
+        }
+        const uint64_t vb = __ballot(k >= 0);
+        const int nv = __popcll(vb);
+        if (k >= 0) {
+            const int slot = (int)lanes_below(vb);
+            const NodeInfo info = ninfo[k];
+            const NodeMom nm = nmom[k];
+            const bool leaf = info.child0 < 0;
+            pc[slot] = PopCom{nm.x, nm.y, nm.z,
+                              leaf ? __builtin_huge_val() : s2tab[node_level(info)]};
+            pd[slot] = PopData{mk, k, info.first, info.count, info.child0, node_nchild(info), 0};
+        }
+        sp = base;
+        __syncthreads();
+        uint64_t accepted = 0;
+#pragma unroll 1
+        for (int p = 0; p < nv; p++) {
+            const PopCom q = pc[p];
+            const uint64_t bal = __ballot(accept_node(q.x, q.y, q.z, me.x, me.y, me.z, q.s2, th2));
+            if (lane == p) accepted = bal;
+        }
+        const bool mine = lane < nv;
+        PopData my = PopData{0ull, 0, 0, 0, 0, 0, 0};
+        if (mine) my = pd[lane];
+        const bool leaf = mine && my.child0 < 0;
+        const uint64_t M = my.mask;
+        const uint64_t A = (mine && !leaf) ? (accepted & M) : 0ull;
+        const uint64_t O = (mine && !leaf) ? (M & ~accepted) : 0ull;
+        const uint64_t pushb = __ballot(O != 0);
+        if (O != 0) {
+            const int e = sp + (int)lanes_below(pushb);
+            st_c0[e] = my.child0;
+            st_n[e] = my.nch;
+            st_mask[e] = O;
+        }
+        sp += __popcll(pushb);
+        const bool hasq = leaf || A != 0;
+        const uint64_t qb = __ballot(hasq);
+        const uint32_t nitems = leaf ? (uint32_t)my.count : (A != 0 ? 1u : 0u);
+        const uint32_t incl = wave_incl_scan(nitems);
+        if (hasq) {
+            const int d = (dq_tail + (int)lanes_below(qb)) % kRing;
+            dq_a[d] = leaf ? my.first : ~my.node;
+            dq_n[d] = (int32_t)nitems;
+            dq_at[d] = queued + incl - nitems;
+            dq_mask[d] = leaf ? M : A;
+        }
+        dq_tail += __popcll(qb);
+        queued += (uint32_t)__shfl(incl, 63);
+        __syncthreads();
+        while (queued - consumed >= (uint32_t)kBatch) evaluate(kBatch);
+    }
+    while (queued != consumed) evaluate((int)min(queued - consumed, (uint32_t)kBatch));
+
+    if (valid) {
+        gt[3 * s] = gx;
+        gt[3 * s + 1] = gy;
+        gt[3 * s + 2] = gz;
+    }
+}
+
+// Zeroes body adjoints (4 per body) and the adjoints and prefix sums of the
+// nodes that exist (5 + 5 per node).
+__global__ __launch_bounds__(256) void k_vjp_clear(double *__restrict__ badj, int64_t n,
+                                                   double *__restrict__ nadj,
+                                                   double *__restrict__ npre,
+                                                   const TreeHeader *__restrict__ hdr,
+                                                   int64_t node_cap)
+{
+    int64_t nn = 0;
+    for (int l = 0; l < kLevels; l++) nn += hdr->level_count[l];
+    if (nn > node_cap) nn = node_cap;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < 4 * n; i += stride) badj[i] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < 5 * nn; i += stride) {
+        nadj[i] = 0.0;
+        npre[i] = 0.0;
+    }
+}
+
+// Per-node coefficients of the member update, from the node's adjoints.
+__device__ inline void node_coeffs(const double *__restrict__ nadj, const NodeMom &nm, double e2,
+                                   int64_t k, double out[5])
+{
+    const double *a = nadj + 5 * k;
+    if (nm.m > 0.0) {
+        const double inv = 1.0 / nm.m;
+        out[0] = a[0] * inv;
+        out[1] = a[1] * inv;
+        out[2] = a[2] * inv;
+        out[4] = a[4] * inv;
+        out[3] = a[3] - (nm.x * out[0] + nm.y * out[1] + nm.z * out[2]) - e2 * out[4];
+    } else {
+        out[0] = out[1] = out[2] = out[4] = 0.0;
+        out[3] = a[3];
+    }
+}
+
+__global__ void k_vjp_root(const double *__restrict__ nadj, const NodeMom *__restrict__ nmom,
+                           const double *__restrict__ neps2, int use_eps,
+                           double *__restrict__ npre)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double c[5];
+    node_coeffs(nadj, nmom[0], use_eps ? neps2[0] : 0.0, 0, c);
+    for (int q = 0; q < 5; q++) npre[q] = c[q];
+}
+
+// npre[child] = npre[node] + coefficients(child), for every node of `level`.
+__global__ __launch_bounds__(256) void k_vjp_push(int level, const TreeHeader *__restrict__ hdr,
+                                                  const NodeInfo *__restrict__ ninfo,
+                                                  const NodeMom *__restrict__ nmom,
+                                                  const double *__restrict__ neps2, int use_eps,
+                                                  const double *__restrict__ nadj,
+                                                  double *__restrict__ npre, int64_t node_cap)
+{
+    int64_t beg = 0;
+    for (int l = 0; l < level; l++) beg += hdr->level_count[l];
+    int64_t cnt = hdr->level_count[level];
+    if (beg + cnt > node_cap) cnt = node_cap - beg;
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < cnt;
+         g += (int64_t)gridDim.x * 256) {
+        const int64_t k = beg + g;
+        const NodeInfo info = ninfo[k];
+        if (info.child0 < 0) continue;
+        const double *p = npre + 5 * k;
+        for (int32_t c = info.child0; c < info.child0 + node_nchild(info); c++) {
+            double cf[5];
+            node_coeffs(nadj, nmom[c], use_eps ? neps2[c] : 0.0, c, cf);
+            for (int q = 0; q < 5; q++) npre[5 * (int64_t)c + q] = p[q] + cf[q];
+        }
+    }
+}
+
+// Every leaf hands the ancestor sums to its members and adds the members'
+// own terms into the caller's gradient arrays (caller order, +=).
+__global__ __launch_bounds__(256) void k_vjp_finish(
+    const TreeHeader *__restrict__ hdr, const NodeInfo *__restrict__ ninfo,
+    const Body *__restrict__ body, const double *__restrict__ beps2, int use_eps,
+    const uint32_t *__restrict__ idx, const double *__restrict__ npre,
+    const double *__restrict__ gt, const double *__restrict__ badj, double *__restrict__ g_pos,
+    double *__restrict__ g_mass, int64_t node_cap)
+{
+    int64_t nn = 0;
+    for (int l = 0; l < kLevels; l++) nn += hdr->level_count[l];
+    if (nn > node_cap) nn = node_cap;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nn;
+         k += (int64_t)gridDim.x * 256) {
+        const NodeInfo info = ninfo[k];
+        if (info.child0 >= 0) continue;
+        const double *p = npre + 5 * k;
+        for (int32_t s = info.first; s < info.first + info.count; s++) {
+            const Body b = body[s];
+            const double e2 = use_eps ? beps2[s] : 0.0;
+            const int64_t o = idx[s];
+            const double *ba = badj + 4 * (int64_t)s;
+            g_pos[3 * o] += gt[3 * s] + ba[0] + b.m * p[0];
+            g_pos[3 * o + 1] += gt[3 * s + 1] + ba[1] + b.m * p[1];
+            g_pos[3 * o + 2] += gt[3 * s + 2] + ba[2] + b.m * p[2];
+            g_mass[o] += ba[3] + p[3] + b.x * p[0] + b.y * p[1] + b.z * p[2] + e2 * p[4];
+        }
+    }
+}
+
+// Direct-sum VJP, gathered per body p (no atomics):
+//   g_x_p += G sum_{q != p} K(d_pq) (m_p lambda_q - m_q lambda_p)
+//   g_m_p += G sum_{q != p} lambda_q . (x_p - x_q) / r^3
+template <bool PEPS>
+__global__ __launch_bounds__(256) void k_direct_vjp(const double *__restrict__ pos,
+                                                    const double *__restrict__ mass,
+                                                    const double *__restrict__ eps, int64_t n,
+                                                    double eps0sq, double G,
+                                                    const double *__restrict__ lambda,
+                                                    double *__restrict__ g_pos,
+                                                    double *__restrict__ g_mass)
+{
+    constexpr int T = 256;
+    __shared__ double sx[T], sy[T], sz[T], sm[T], se[T], slx[T], sly[T], slz[T];
+    const int tid = threadIdx.x;
+    const int64_t p = (int64_t)blockIdx.x * T + tid;
+    const bool valid = p < n;
+    const double xp = valid ? pos[3 * p] : 0.0, yp = valid ? pos[3 * p + 1] : 0.0,
+                 zp = valid ? pos[3 * p + 2] : 0.0, mp = valid ? mass[p] : 0.0;
+    const double lpx = valid ? lambda[3 * p] : 0.0, lpy = valid ? lambda[3 * p + 1] : 0.0,
+                 lpz = valid ? lambda[3 * p + 2] : 0.0;
+    double ep2 = 0.0;
+    if (PEPS && valid) ep2 = eps[p] * eps[p];
+    double gx = 0.0, gy = 0.0, gz = 0.0, gm = 0.0;
+    for (int64_t base = 0; base < n; base += T) {
+        const int64_t q = base + tid;
+        if (q < n) {
+            sx[tid] = pos[3 * q];
+            sy[tid] = pos[3 * q + 1];
+            sz[tid] = pos[3 * q + 2];
+            sm[tid] = mass[q];
+            slx[tid] = lambda[3 * q];
+            sly[tid] = lambda[3 * q + 1];
+            slz[tid] = lambda[3 * q + 2];
+            if (PEPS) se[tid] = eps[q] * eps[q];
+        }
+        __syncthreads();
+        const int cnt = (int)((n - base) < T ? (n - base) : T);
+        for (int j = 0; j < cnt; j++) {
+            if (base + j == p) continue;
+            const double dx = sx[j] - xp, dy = sy[j] - yp, dz = sz[j] - zp;
+            const double e2 = PEPS ? 0.5 * (ep2 + se[j]) : eps0sq;
+            const double r2 = dx * dx + dy * dy + dz * dz + e2;
+            if (!(r2 > 0.0)) continue;
+            const double r = sqrt(r2);
+            const double inv3 = 1.0 / (r2 * r);
+            const double inv5 = inv3 / r2;
+            // w = m_p lambda_q - m_q lambda_p ; K w = w / r^3 - 3 d (d.w) / r^5
+            const double wx = mp * slx[j] - sm[j] * lpx, wy = mp * sly[j] - sm[j] * lpy,
+                         wz = mp * slz[j] - sm[j] * lpz;
+            const double dw = dx * wx + dy * wy + dz * wz;
+            gx += wx * inv3 - 3.0 * dx * dw * inv5;
+            gy += wy * inv3 - 3.0 * dy * dw * inv5;
+            gz += wz * inv3 - 3.0 * dz * dw * inv5;
+            gm -= (slx[j] * dx + sly[j] * dy + slz[j] * dz) * inv3;
+        }
+        __syncthreads();
+    }
+    if (valid) {
+        g_pos[3 * p] += G * gx;
+        g_pos[3 * p + 1] += G * gy;
+        g_pos[3 * p + 2] += G * gz;
+        g_mass[p] += G * gm;
+    }
+}
+
+// Adjoint of the second kick: abar += dt/2 vbar.
+__global__ __launch_bounds__(256) void k_adj_kick(double *__restrict__ abar,
+                                                  const double *__restrict__ vbar, int64_t n3,
+                                                  double h)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n3) abar[i] += h * vbar[i];
+}
+
+// Adjoint of the drift and the first kick: vbar += dt xbar; abar = dt/2 vbar.
+__global__ __launch_bounds__(256) void k_adj_drift_kick(double *__restrict__ vbar,
+                                                        double *__restrict__ abar,
+                                                        const double *__restrict__ xbar,
+                                                        int64_t n3, double dt, double h)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n3) return;
+    const double v = vbar[i] + dt * xbar[i];
+    vbar[i] = v;
+    abar[i] = h * v;
+}
+
+// x_out = x_in + dt (v + dt/2 a); v += dt/2 a (kick and drift into a new buffer)
+__global__ __launch_bounds__(256) void k_kick_drift_to(const double *__restrict__ x_in,
+                                                       double *__restrict__ v,
+                                                       const double *__restrict__ a,
+                                                       double *__restrict__ x_out, int64_t n3,
+                                                       double h, double dt)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n3) return;
+    const double u = v[i] + h * a[i];
+    v[i] = u;
+    x_out[i] = x_in[i] + dt * u;
+}
+
+__global__ __launch_bounds__(256) void k_copy(double *__restrict__ dst,
+                                              const double *__restrict__ src, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+inline unsigned blocks(int64_t items, unsigned cap = 1u << 30)
+{
+    int64_t b = (items + 255) / 256;
+    if (b < 1) b = 1;
+    return (unsigned)(b < (int64_t)cap ? b : cap);
+}
+
+}  // namespace
+
+hipError_t launch_tree_vjp(const Workspace &w, const AdjointWork &aw, hipStream_t s,
+                           const WalkParams &p, const double *lambda, double *g_pos,
+                           double *g_mass)
+{
+    if (p.n <= 0) return hipSuccess;
+    k_vjp_clear<<<1024, 256, 0, s>>>(aw.badj, p.n, aw.nadj, aw.npre, w.hdr, w.node_cap);
+    const int ngroups = (int)((p.n + 63) / 64);
+    const int per_xcd = (ngroups + 7) / 8;
+    if (p.per_body_eps)
+        k_vjp_walk<true><<<8 * per_xcd, 64, 0, s>>>(w.body, w.beps2, w.ninfo, w.nmom, w.neps2,
+                                                     w.idx[0], w.hdr, p.n, ngroups, per_xcd, p.th2,
+                                                     p.eps0sq, p.G, lambda, aw.gt, aw.badj,
+                                                     aw.nadj);
+    else
+        k_vjp_walk<false><<<8 * per_xcd, 64, 0, s>>>(w.body, w.beps2, w.ninfo, w.nmom, w.neps2,
+                                                      w.idx[0], w.hdr, p.n, ngroups, per_xcd,
+                                                      p.th2, p.eps0sq, p.G, lambda, aw.gt,
+                                                      aw.badj, aw.nadj);
+    const int use_eps = p.per_body_eps ? 1 : 0;
+    k_vjp_root<<<1, 64, 0, s>>>(aw.nadj, w.nmom, w.neps2, use_eps, aw.npre);
+    int64_t bound = 1;
+    for (int level = 0; level < kMaxLevel; level++) {
+        const unsigned g = blocks(bound < p.n ? bound : p.n, 4096);
+        k_vjp_push<<<g, 256, 0, s>>>(level, w.hdr, w.ninfo, w.nmom, w.neps2, use_eps, aw.nadj,
+                                     aw.npre, w.node_cap);
+        if (bound < p.n) bound *= 8;
+    }
+    k_vjp_finish<<<blocks(p.n, 4096), 256, 0, s>>>(w.hdr, w.ninfo, w.body, w.beps2, use_eps,
+                                                   w.idx[0], aw.npre, aw.gt, aw.badj, g_pos,
+                                                   g_mass, w.node_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_direct_vjp(hipStream_t s, const double *pos, const double *mass,
+                             const double *eps, int64_t n, double eps0sq, double G,
+                             const double *lambda, double *g_pos, double *g_mass)
+{
+    if (n <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)((n + 255) / 256);
+    if (eps)
+        k_direct_vjp<true><<<grid, 256, 0, s>>>(pos, mass, eps, n, eps0sq, G, lambda, g_pos, g_mass);
+    else
+        k_direct_vjp<false><<<grid, 256, 0, s>>>(pos, mass, eps, n, eps0sq, G, lambda, g_pos,
+                                                 g_mass);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_kick(hipStream_t s, double *abar, const double *vbar, int64_t n, double dt)
+{
+    if (n <= 0) return hipSuccess;
+    k_adj_kick<<<blocks(3 * n), 256, 0, s>>>(abar, vbar, 3 * n, 0.5 * dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_drift_kick(hipStream_t s, double *vbar, double *abar, const double *xbar,
+                                 int64_t n, double dt)
+{
+    if (n <= 0) return hipSuccess;
+    k_adj_drift_kick<<<blocks(3 * n), 256, 0, s>>>(vbar, abar, xbar, 3 * n, dt, 0.5 * dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_kick_drift_to(hipStream_t s, const double *x_in, double *v, const double *a,
+                                double *x_out, int64_t n, double dt)
+{
+    if (n <= 0) return hipSuccess;
+    k_kick_drift_to<<<blocks(3 * n), 256, 0, s>>>(x_in, v, a, x_out, 3 * n, 0.5 * dt, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(hipStream_t s, double *dst, const double *src, int64_t count)
+{
+    if (count <= 0) return hipSuccess;
+    k_copy<<<blocks(count), 256, 0, s>>>(dst, src, count);
+    return hipGetLastError();
+}
+
+}  // namespace bhx

@@ -112,6 +112,28 @@ hipError_t launch_direct(hipStream_t s, const double *pos, const double *mass, c
                          int64_t n, double eps0sq, double G, int precision, double *acc,
                          double *phi);
 
+// adjoint.hip: workspace of the VJPs (BH_FLAG_ADJOINT)
+struct AdjointWork {
+    double *gt = nullptr;    // [n_cap][3] target-side gradients, sorted order
+    double *badj = nullptr;  // [n_cap][4] source-side body adjoints, sorted order
+    double *nadj = nullptr;  // [node_cap][5] node adjoints: gX, gm, g<eps^2>
+    double *npre = nullptr;  // [node_cap][5] ancestor sums of the node coefficients
+    double *vwork = nullptr; // [n_cap][3] velocity while a segment is recomputed
+    double *awork = nullptr; // [n_cap][3] acceleration while a segment is recomputed
+};
+hipError_t launch_tree_vjp(const Workspace &w, const AdjointWork &aw, hipStream_t s,
+                           const WalkParams &p, const double *lambda, double *g_pos,
+                           double *g_mass);
+hipError_t launch_direct_vjp(hipStream_t s, const double *pos, const double *mass,
+                             const double *eps, int64_t n, double eps0sq, double G,
+                             const double *lambda, double *g_pos, double *g_mass);
+hipError_t launch_adj_kick(hipStream_t s, double *abar, const double *vbar, int64_t n, double dt);
+hipError_t launch_adj_drift_kick(hipStream_t s, double *vbar, double *abar, const double *xbar,
+                                 int64_t n, double dt);
+hipError_t launch_kick_drift_to(hipStream_t s, const double *x_in, double *v, const double *a,
+                                double *x_out, int64_t n, double dt);
+hipError_t launch_copy(hipStream_t s, double *dst, const double *src, int64_t count);
+
 // integrate.hip
 hipError_t launch_kick_drift(hipStream_t s, double *pos, double *vel, const double *acc, int64_t n,
                              double dt);

@@ -22,6 +22,7 @@ struct bh_ctx {
     bool tree_eps = false; // the last build had per-body eps
     int64_t walk_n = -1;   // n of the last walk that wrote counts
     double *diag_out = nullptr;
+    bhx::AdjointWork aw;
     // BH_FLAG_TIMING: event triples (build start, walk start, walk end) not
     // yet folded into the totals
     std::vector<hipEvent_t> ev_pool;
@@ -54,6 +55,14 @@ hipError_t dalloc(T **p, int64_t count)
 {
     if (count < 1) count = 1;
     return hipMalloc((void **)p, (size_t)count * sizeof(T));
+}
+
+void free_aw(bhx::AdjointWork &a)
+{
+    void *ptrs[] = {a.gt, a.badj, a.nadj, a.npre, a.vwork, a.awork};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    a = bhx::AdjointWork{};
 }
 
 void free_ws(Workspace &w)
@@ -143,6 +152,36 @@ bh_status force_direct(bh_ctx *c, const double *pos, const double *mass, double 
     return BH_OK;
 }
 
+// VJP of the force map at pos (tree when theta >= 0, else direct), added
+// into g_pos and g_mass.
+bh_status vjp(bh_ctx *c, const double *pos, const double *mass, double softening,
+              const double *eps, double theta, const double *lambda, double *g_pos,
+              double *g_mass, int64_t n)
+{
+    if (n == 0) return BH_OK;
+    if (theta >= 0.0) {
+        BHX_HIP(c, bhx::launch_build(c->w, c->stream, pos, mass, eps, n, c->cfg.leaf_size));
+        c->tree_n = n;
+        c->tree_eps = eps != nullptr;
+        bhx::WalkParams p;
+        p.n = n;
+        p.th2 = theta * theta;
+        p.eps0sq = softening * softening;
+        p.G = c->cfg.G;
+        p.acc = nullptr;
+        p.phi = nullptr;
+        p.counts = nullptr;
+        p.per_body_eps = eps != nullptr;
+        p.precision = BH_FP64;
+        p.group = 64;
+        BHX_HIP(c, bhx::launch_tree_vjp(c->w, c->aw, c->stream, p, lambda, g_pos, g_mass));
+    } else {
+        BHX_HIP(c, bhx::launch_direct_vjp(c->stream, pos, mass, eps, n, softening * softening,
+                                          c->cfg.G, lambda, g_pos, g_mass));
+    }
+    return BH_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -155,7 +194,8 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
     if (cfg->leaf_size < 1 || cfg->leaf_size > 64) return BH_E_INVALID;
     if (cfg->precision != BH_FP64 && cfg->precision != BH_FP32C) return BH_E_INVALID;
     if (!std::isfinite(cfg->G)) return BH_E_INVALID;
-    if (cfg->flags & ~(uint32_t)(BH_FLAG_COUNTS | BH_FLAG_TIMING)) return BH_E_INVALID;
+    if (cfg->flags & ~(uint32_t)(BH_FLAG_COUNTS | BH_FLAG_TIMING | BH_FLAG_ADJOINT))
+        return BH_E_INVALID;
     if (cfg->walk_group != 0 && cfg->walk_group != 16 && cfg->walk_group != 32 &&
         cfg->walk_group != 64)
         return BH_E_INVALID;
@@ -198,6 +238,14 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
     A(dalloc(&w.scratch, 4 * n));
     A(dalloc(&w.red_part, (int64_t)bhx::kRedBlocks * 8));
     A(dalloc(&c->diag_out, 8));
+    if (cfg->flags & BH_FLAG_ADJOINT) {
+        A(dalloc(&c->aw.gt, 3 * n));
+        A(dalloc(&c->aw.badj, 4 * n));
+        A(dalloc(&c->aw.nadj, 5 * node_cap));
+        A(dalloc(&c->aw.npre, 5 * node_cap));
+        A(dalloc(&c->aw.vwork, 3 * n));
+        A(dalloc(&c->aw.awork, 3 * n));
+    }
     if (cfg->flags & BH_FLAG_TIMING) {
         c->ev_pool.resize(3 * kEvTriples, nullptr);
         for (auto &ev : c->ev_pool)
@@ -208,6 +256,7 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
     if (r != hipSuccess) {
         bh_status st = (r == hipErrorOutOfMemory) ? BH_E_OOM : BH_E_HIP;
         free_ws(w);
+        free_aw(c->aw);
         if (c->diag_out) (void)hipFree(c->diag_out);
         for (auto ev : c->ev_pool)
             if (ev) (void)hipEventDestroy(ev);
@@ -223,6 +272,7 @@ void bh_destroy(bh_ctx *c)
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     free_ws(c->w);
+    free_aw(c->aw);
     if (c->diag_out) (void)hipFree(c->diag_out);
     for (auto ev : c->ev_pool)
         if (ev) (void)hipEventDestroy(ev);
@@ -307,6 +357,62 @@ bh_status bh_step_leapfrog(bh_ctx *c, double *pos, double *vel, const double *ma
                                         c->cfg.precision);
         if (s) return s;
         BHX_HIP(c, bhx::launch_kick(c->stream, vel, acc, n, dt));
+    }
+    return BH_OK;
+}
+
+bh_status bh_accel_vjp(bh_ctx *c, const double *pos, const double *mass, double softening,
+                       const double *eps, double theta, const double *lambda, double *g_pos,
+                       double *g_mass, int64_t n)
+{
+    bh_status s = check_bodies(c, pos, mass, n);
+    if (s) return s;
+    if (!(c->cfg.flags & BH_FLAG_ADJOINT))
+        return fail(c, BH_E_STATE, "the context was created without BH_FLAG_ADJOINT");
+    if (std::isnan(theta) || std::isinf(theta)) return fail(c, BH_E_INVALID, "theta not finite");
+    if (!finite_nonneg(softening)) return fail(c, BH_E_INVALID, "softening must be finite and >= 0");
+    if (n > 0 && (!lambda || !g_pos || !g_mass))
+        return fail(c, BH_E_INVALID, "NULL lambda, g_pos or g_mass");
+    return vjp(c, pos, mass, softening, eps, theta, lambda, g_pos, g_mass, n);
+}
+
+bh_status bh_leapfrog_vjp(bh_ctx *c, const double *pos, const double *vel, const double *acc,
+                          const double *mass, double softening, const double *eps, double theta,
+                          double dt, int32_t nsteps, double *traj, double *xbar, double *vbar,
+                          double *abar, double *g_mass, int64_t n)
+{
+    bh_status s = check_bodies(c, pos, mass, n);
+    if (s) return s;
+    if (!(c->cfg.flags & BH_FLAG_ADJOINT))
+        return fail(c, BH_E_STATE, "the context was created without BH_FLAG_ADJOINT");
+    if (std::isnan(theta) || std::isinf(theta)) return fail(c, BH_E_INVALID, "theta not finite");
+    if (!finite_nonneg(softening)) return fail(c, BH_E_INVALID, "softening must be finite and >= 0");
+    if (!std::isfinite(dt)) return fail(c, BH_E_INVALID, "dt not finite");
+    if (nsteps < 0) return fail(c, BH_E_INVALID, "nsteps < 0");
+    if (n > 0 && (!vel || !acc || !xbar || !vbar || !abar || !g_mass || (nsteps > 0 && !traj)))
+        return fail(c, BH_E_INVALID, "NULL vel, acc, traj, xbar, vbar, abar or g_mass");
+    if (n == 0 || nsteps == 0) return BH_OK;
+    const int64_t n3 = 3 * n;
+    bhx::AdjointWork &aw = c->aw;
+    // recompute the segment's positions exactly as bh_step_leapfrog does
+    BHX_HIP(c, bhx::launch_copy(c->stream, aw.vwork, vel, n3));
+    BHX_HIP(c, bhx::launch_copy(c->stream, aw.awork, acc, n3));
+    for (int32_t k = 0; k < nsteps; k++) {
+        const double *x_in = k == 0 ? pos : traj + (int64_t)(k - 1) * n3;
+        double *x_out = traj + (int64_t)k * n3;
+        BHX_HIP(c, bhx::launch_kick_drift_to(c->stream, x_in, aw.vwork, aw.awork, x_out, n, dt));
+        s = theta >= 0.0 ? force_tree(c, x_out, mass, softening, eps, theta, aw.awork, nullptr, n)
+                         : force_direct(c, x_out, mass, softening, eps, aw.awork, nullptr, n,
+                                        c->cfg.precision);
+        if (s) return s;
+        BHX_HIP(c, bhx::launch_kick(c->stream, aw.vwork, aw.awork, n, dt));
+    }
+    // reverse: second kick, force VJP at the step's end positions, drift, first kick
+    for (int32_t k = nsteps - 1; k >= 0; k--) {
+        BHX_HIP(c, bhx::launch_adj_kick(c->stream, abar, vbar, n, dt));
+        s = vjp(c, traj + (int64_t)k * n3, mass, softening, eps, theta, abar, xbar, g_mass, n);
+        if (s) return s;
+        BHX_HIP(c, bhx::launch_adj_drift_kick(c->stream, vbar, abar, xbar, n, dt));
     }
     return BH_OK;
 }
