@@ -67,8 +67,13 @@ enum {
     BH_FLAG_COUNTS = 1u, /* keep per-body walk counts for bh_walk_counts() */
     BH_FLAG_TIMING = 2u, /* record HIP events around every tree build and walk
                             on the context's stream; totals in bh_stats() */
-    BH_FLAG_ADJOINT = 4u /* allocate the workspace of bh_accel_vjp and
-                            bh_leapfrog_vjp at creation */
+    BH_FLAG_ADJOINT = 4u, /* allocate the workspace of bh_accel_vjp and
+                             bh_leapfrog_vjp at creation */
+    BH_FLAG_GRAPH = 8u    /* bh_step_leapfrog and bh_batched_step capture one
+                             step in a HIP graph (once per set of arguments)
+                             and replay it nsteps times on a stream of the
+                             context, ordered after and before the caller's
+                             stream by events */
 };
 
 typedef struct {
@@ -84,6 +89,7 @@ typedef struct {
                            walk: 64, 32 or 16 (64/walk_group lanes per body);
                            0 = the library's default. Results do not depend on
                            it beyond rounding. */
+    int32_t max_scenes; /* largest n_scenes of bh_batched_*; 0 means 1 */
 } bh_config;
 
 /* Creates a context on the current HIP device, bound to `hip_stream`
@@ -146,6 +152,23 @@ bh_status bh_step_leapfrog(bh_ctx *ctx, double *pos, double *vel, const double *
  * int32. Needs BH_FLAG_COUNTS at creation (else BH_E_STATE); n must equal the
  * last walk's n (else BH_E_INVALID). */
 bh_status bh_walk_counts(bh_ctx *ctx, int32_t *counts, int64_t n);
+
+/* Many independent scenes in one call: n_scenes clouds stored back to back,
+ * scene k being bodies offsets[k] .. offsets[k+1]-1 (offsets: HOST array of
+ * n_scenes + 1 int64, offsets[0] = 0, every scene non-empty, total <= n_max,
+ * n_scenes <= max_scenes). Each scene gets its own root cube and tree and its
+ * bodies feel only the bodies of their own scene; one launch of each build and
+ * walk kernel serves all scenes. The tables of a layout are uploaded once and
+ * reused while the offsets stay the same. bh_batched_accel is
+ * bh_compute_accel per scene; bh_batched_step is bh_step_leapfrog per scene
+ * (graph-captured with BH_FLAG_GRAPH). Errors: as bh_compute_accel /
+ * bh_step_leapfrog, plus BH_E_INVALID for a bad layout. */
+bh_status bh_batched_accel(bh_ctx *ctx, int32_t n_scenes, const int64_t *offsets,
+                           const double *pos, const double *mass, double softening,
+                           const double *eps, double theta, double *acc, double *phi);
+bh_status bh_batched_step(bh_ctx *ctx, int32_t n_scenes, const int64_t *offsets, double *pos,
+                          double *vel, const double *mass, double softening, const double *eps,
+                          double theta, double dt, int32_t nsteps, double *acc);
 
 /* Vector-Jacobian product of the force map: ADDS to g_pos (n x 3) and g_mass
  * (n) the gradient of sum_i lambda_i . a_i with respect to the positions and

@@ -16,11 +16,13 @@ BH_FP64, BH_FP32C = 0, 1
 BH_FLAG_COUNTS = 1
 BH_FLAG_TIMING = 2
 BH_FLAG_ADJOINT = 4
+BH_FLAG_GRAPH = 8
 
 
 class bh_config(C.Structure):
     _fields_ = [("n_max", C.c_int64), ("leaf_size", C.c_int32), ("precision", C.c_int32),
-                ("G", C.c_double), ("flags", C.c_uint32), ("walk_group", C.c_int32)]
+                ("G", C.c_double), ("flags", C.c_uint32), ("walk_group", C.c_int32),
+                ("max_scenes", C.c_int32)]
 
 
 class bh_tree_view(C.Structure):
@@ -53,6 +55,8 @@ SIGNATURES = {
     "bh_diagnostics": ([P, P, P, P, D, P, P, I64], C.c_int),
     "bh_timing_reset": ([P], C.c_int),
     "bh_accel_vjp": ([P, P, P, D, P, D, P, P, P, I64], C.c_int),
+    "bh_batched_accel": ([P, I32, P, P, P, D, P, D, P, P], C.c_int),
+    "bh_batched_step": ([P, I32, P, P, P, P, D, P, D, D, I32, P], C.c_int),
     "bh_leapfrog_vjp": ([P, P, P, P, P, D, P, D, D, I32, P, P, P, P, P, I64], C.c_int),
 }
 

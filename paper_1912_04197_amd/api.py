@@ -77,14 +77,15 @@ class Context:
 
     def __init__(self, n_max: int, leaf_size: int = 16, precision: str = "fp32c", G: float = 1.0,
                  counts: bool = False, timing: bool = False, walk_group: int = 0,
-                 adjoint: bool = False):
+                 adjoint: bool = False, max_scenes: int = 1, graph: bool = False):
         self._lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: libbhx runs on the GPU only")
         prec = {"fp64": L.BH_FP64, "fp32c": L.BH_FP32C}[precision]
         flags = ((L.BH_FLAG_COUNTS if counts else 0) | (L.BH_FLAG_TIMING if timing else 0)
-                 | (L.BH_FLAG_ADJOINT if adjoint else 0))
-        cfg = L.bh_config(int(n_max), int(leaf_size), prec, float(G), flags, int(walk_group))
+                 | (L.BH_FLAG_ADJOINT if adjoint else 0) | (L.BH_FLAG_GRAPH if graph else 0))
+        cfg = L.bh_config(int(n_max), int(leaf_size), prec, float(G), flags, int(walk_group),
+                          int(max_scenes))
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.n_max, self.leaf_size, self.precision, self.G = int(n_max), int(leaf_size), precision, float(G)
         h = C.c_void_p()
@@ -174,6 +175,48 @@ class Context:
         self._rc(self._lib.bh_step_leapfrog(self._h, _ptr(pos), _ptr(vel), _ptr(mass),
                                             float(softening), _ptr(eps), float(theta), float(dt),
                                             int(nsteps), _ptr(acc), n))
+        if sync:
+            self.sync()
+
+    @staticmethod
+    def _offsets(offsets):
+        import numpy as np
+
+        o = np.ascontiguousarray(offsets, dtype=np.int64)
+        return o, int(o.shape[0]) - 1
+
+    def batched_accel(self, offsets, pos, mass, theta, softening=0.0, eps=None, out=None,
+                      potential=False, sync=True):
+        """Per-scene Barnes-Hut accelerations of scenes stored back to back;
+        offsets (host, n_scenes + 1) delimit the scenes."""
+        o, ns = self._offsets(offsets)
+        n = self._bodies(pos, mass, eps)
+        if int(o[-1]) != n:
+            raise ValueError("offsets[-1] must equal the number of bodies")
+        acc = out if out is not None else torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        _check_f64("out", acc, (n, 3), self.device)
+        phi = torch.empty(n, dtype=torch.float64, device=self.device) if potential else None
+        self._bind()
+        self._rc(self._lib.bh_batched_accel(self._h, ns, o.ctypes.data_as(C.c_void_p), _ptr(pos),
+                                            _ptr(mass), float(softening), _ptr(eps), float(theta),
+                                            _ptr(acc), _ptr(phi)))
+        if sync:
+            self.sync()
+        return (acc, phi) if potential else acc
+
+    def batched_step(self, offsets, pos, vel, mass, acc, dt, nsteps, theta=0.5, softening=0.0,
+                     eps=None, sync=True):
+        """nsteps KDK steps of every scene, in place (see bh_batched_step)."""
+        o, ns = self._offsets(offsets)
+        n = self._bodies(pos, mass, eps)
+        if int(o[-1]) != n:
+            raise ValueError("offsets[-1] must equal the number of bodies")
+        _check_f64("vel", vel, (n, 3), self.device)
+        _check_f64("acc", acc, (n, 3), self.device)
+        self._bind()
+        self._rc(self._lib.bh_batched_step(self._h, ns, o.ctypes.data_as(C.c_void_p), _ptr(pos),
+                                           _ptr(vel), _ptr(mass), float(softening), _ptr(eps),
+                                           float(theta), float(dt), int(nsteps), _ptr(acc)))
         if sync:
             self.sync()
 

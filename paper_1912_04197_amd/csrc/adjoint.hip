@@ -88,7 +88,7 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
     const Body *__restrict__ body, const double *__restrict__ beps2,
     const NodeInfo *__restrict__ ninfo, const NodeMom *__restrict__ nmom,
     const double *__restrict__ neps2, const uint32_t *__restrict__ idx,
-    const TreeHeader *__restrict__ hdr, int64_t n, int ngroups, int per_xcd, double th2,
+    const SceneBox *__restrict__ box, int64_t n, int ngroups, int per_xcd, double th2,
     double eps0sq, double G, const double *__restrict__ lambda, double *__restrict__ gt,
     double *__restrict__ badj, double *__restrict__ nadj)
 {
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
         lz = lambda[3 * o + 2];
     }
     const uint64_t active = __ballot(valid);
-    if (lane < kLevels) s2tab[lane] = hdr->s2[lane];
+    if (lane < kLevels) s2tab[lane] = box[0].s2[lane];
 
     double gx = 0.0, gy = 0.0, gz = 0.0;  // target-side gradient of this lane's body
     int sp = 1, dq_head = 0, dq_tail = 0;
@@ -536,12 +536,12 @@ hipError_t launch_tree_vjp(const Workspace &w, const AdjointWork &aw, hipStream_
     const int per_xcd = (ngroups + 7) / 8;
     if (p.per_body_eps)
         k_vjp_walk<true><<<8 * per_xcd, 64, 0, s>>>(w.body, w.beps2, w.ninfo, w.nmom, w.neps2,
-                                                     w.idx[0], w.hdr, p.n, ngroups, per_xcd, p.th2,
+                                                     w.idx[0], w.box, p.n, ngroups, per_xcd, p.th2,
                                                      p.eps0sq, p.G, lambda, aw.gt, aw.badj,
                                                      aw.nadj);
     else
         k_vjp_walk<false><<<8 * per_xcd, 64, 0, s>>>(w.body, w.beps2, w.ninfo, w.nmom, w.neps2,
-                                                      w.idx[0], w.hdr, p.n, ngroups, per_xcd,
+                                                      w.idx[0], w.box, p.n, ngroups, per_xcd,
                                                       p.th2, p.eps0sq, p.G, lambda, aw.gt,
                                                       aw.badj, aw.nadj);
     const int use_eps = p.per_body_eps ? 1 : 0;

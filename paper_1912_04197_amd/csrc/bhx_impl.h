@@ -29,30 +29,59 @@ struct alignas(32) NodeMom {
 };
 
 // One node's structure: sorted body range, first child (-1 for a leaf),
-// level in bits 0..7 and number of children in bits 8..15.
+// level in bits 0..7, number of children in bits 8..15 and the scene the
+// node belongs to in bits 16..31.
 struct alignas(16) NodeInfo {
     int32_t first, count, child0, lvl_nch;
 };
 
 __host__ __device__ inline int node_level(const NodeInfo &i) { return i.lvl_nch & 0xff; }
 __host__ __device__ inline int node_nchild(const NodeInfo &i) { return (i.lvl_nch >> 8) & 0xff; }
+__host__ __device__ inline int node_scene(const NodeInfo &i)
+{
+    return (int)((uint32_t)i.lvl_nch >> 16);
+}
+constexpr int kMaxScenes = 65535;
 
-// Tree header, written on the device by the build and read by later kernels,
-// so a whole force evaluation runs without host round trips.
-struct TreeHeader {
+// Root cube of one scene. lo_enc / hi_enc hold the per-axis minimum and
+// maximum as order-preserving integers while the box is being reduced.
+struct SceneBox {
+    unsigned long long lo_enc[3], hi_enc[3];
     double lo[3], hi[3];  // per-axis bounding box
     double L, S;          // root cube side and quantisation scale 2^21 / L
     double x0[3];         // root cube corner
     double s2[kLevels];   // squared cell side per level
-    int32_t level_count[kLevels + 1];  // nodes created per level
+};
+
+// Tree header, written on the device by the build and read by later kernels,
+// so a whole force evaluation runs without host round trips.
+struct TreeHeader {
+    int32_t level_count[kLevels + 1];  // nodes created per level (all scenes)
     uint32_t status;                   // ST_* bits
     int32_t pad;
 };
 
+// Body layout of one call: n bodies in n_scenes contiguous scenes. For one
+// scene every table is implicit (nullptr); otherwise scene_of gives each
+// body's scene, chunks the bbox work items {scene, first, end} (none crosses
+// a scene) and groups the walk groups {first, count, scene} (at most 64
+// bodies, none crosses a scene), all in device memory.
+struct Layout {
+    int64_t n = 0;
+    int n_scenes = 1;
+    const int64_t *offsets = nullptr;  // device, n_scenes + 1
+    const uint16_t *scene_of = nullptr;
+    const int32_t *chunks = nullptr;   // [n_chunks][3]
+    int n_chunks = 0;
+    const int32_t *groups = nullptr;   // [n_groups][3]
+    int n_groups = 0;
+};
+constexpr int kBoxChunk = 4096;  // bodies per bbox work item
+
 // Workspace owned by a context; sized once for n_max bodies.
 struct Workspace {
     int64_t n_cap = 0, node_cap = 0;
-    int sort_blocks_cap = 0, bbox_blocks = 0;
+    int sort_blocks_cap = 0, max_scenes = 1;
     uint64_t *keys[2] = {nullptr, nullptr};
     uint32_t *idx[2] = {nullptr, nullptr};
     uint32_t *sort_counts = nullptr;  // [256][sort blocks], scanned per digit row
@@ -62,7 +91,7 @@ struct Workspace {
     NodeInfo *ninfo = nullptr;
     NodeMom *nmom = nullptr;
     double *neps2 = nullptr;
-    double *bbox_part = nullptr;  // [bbox blocks][6]
+    SceneBox *box = nullptr;      // [max_scenes]
     TreeHeader *hdr = nullptr;
     int32_t *counts = nullptr;    // [n_cap][2] per-body walk counts, caller order
     double *scratch = nullptr;    // [n_cap] potential for diagnostics
@@ -72,27 +101,31 @@ struct Workspace {
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;
-constexpr int kBboxBlocks = 512;
 constexpr int kRedBlocks = 512;
 
-// Upper bound on the node count of a tree of n bodies with the given bucket
-// size: every level below the root holds at most min(n, 8 n / (leaf + 1))
-// nodes, because its nodes are disjoint non-empty children of cells holding
-// more than `leaf` bodies.
-inline int64_t node_capacity(int64_t n, int leaf)
+// Upper bound on the node count of the trees of n bodies in up to `scenes`
+// scenes with the given bucket size: one root per scene, and every level
+// below holds at most min(n, 8 n / (leaf + 1)) nodes, because its nodes are
+// disjoint non-empty children of cells holding more than `leaf` bodies.
+inline int64_t node_capacity(int64_t n, int leaf, int scenes = 1)
 {
-    if (n <= 0) return 1;
+    if (n <= 0) return scenes > 1 ? scenes : 1;
     int64_t internal = n / (leaf + 1);
     int64_t per_level = 8 * internal < n ? 8 * internal : n;
-    return 1 + (int64_t)kMaxLevel * per_level;
+    return (int64_t)(scenes > 1 ? scenes : 1) + (int64_t)kMaxLevel * per_level;
 }
 
 // Launchers (tree.hip). All enqueue on `s` and never synchronise.
-hipError_t launch_build(const Workspace &w, hipStream_t s, const double *pos, const double *mass,
-                        const double *eps, int64_t n, int leaf);
+hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, const double *pos,
+                        const double *mass, const double *eps, int leaf);
+// scene_of[i] = scene of body i, from device offsets of n_scenes scenes
+hipError_t launch_scene_of(hipStream_t s, const int64_t *offsets, int n_scenes,
+                           uint16_t *scene_of);
 
 struct WalkParams {
     int64_t n;
+    const int32_t *groups = nullptr;  // walk groups of a multi-scene layout
+    int n_groups = 0;
     double th2;     // theta^2
     double eps0sq;  // uniform softening squared (per-body eps not given)
     double G;

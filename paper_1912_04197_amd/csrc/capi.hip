@@ -1,6 +1,8 @@
 // C ABI of libbhx (declared in include/bhx.h): context and workspace
 // ownership, host-side argument checks, launch sequencing on the caller's
-// stream, and the device status latch.
+// stream, the device status latch, multi-scene layouts and graph capture of
+// integration steps.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -29,6 +31,22 @@ struct bh_ctx {
     int ev_used = 0;
     int64_t timed_evals = 0;
     double build_ms = 0.0, walk_ms = 0.0;
+    // several scenes: device tables of the current layout and their host copies
+    int64_t *d_offsets = nullptr;
+    uint16_t *d_scene_of = nullptr;
+    int32_t *d_chunks = nullptr, *d_groups = nullptr;
+    int64_t max_chunks = 0, max_groups = 0;
+    std::vector<int64_t> h_offsets;
+    std::vector<int32_t> h_chunks, h_groups;
+    int layout_group = 0;
+    bhx::Layout batch;
+    // BH_FLAG_GRAPH: one captured step, replayed on a stream of the context
+    hipStream_t cstream = nullptr;
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<double> gkey;
+    bool capturing = false;
 };
 
 namespace {
@@ -68,11 +86,25 @@ void free_aw(bhx::AdjointWork &a)
 void free_ws(Workspace &w)
 {
     void *ptrs[] = {w.keys[0], w.keys[1], w.idx[0],  w.idx[1],      w.sort_counts,
-                    w.sort_totals, w.body, w.beps2, w.ninfo, w.nmom, w.neps2, w.bbox_part,
+                    w.sort_totals, w.body, w.beps2, w.ninfo, w.nmom, w.neps2, w.box,
                     w.hdr, w.counts, w.scratch, w.red_part};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     w = Workspace{};
+}
+
+void free_extras(bh_ctx *c)
+{
+    void *ptrs[] = {c->d_offsets, c->d_scene_of, c->d_chunks, c->d_groups, c->diag_out};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (auto ev : c->gev)
+        if (ev) (void)hipEventDestroy(ev);
+    if (c->cstream) (void)hipStreamDestroy(c->cstream);
+    for (auto ev : c->ev_pool)
+        if (ev) (void)hipEventDestroy(ev);
 }
 
 bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
@@ -107,7 +139,7 @@ bh_status fold_timing(bh_ctx *c)
 
 bh_status record(bh_ctx *c, int which)
 {
-    if (!(c->cfg.flags & BH_FLAG_TIMING)) return BH_OK;
+    if (!(c->cfg.flags & BH_FLAG_TIMING) || c->capturing) return BH_OK;
     if (which == 0 && c->ev_used == kEvTriples) {
         bh_status s = fold_timing(c);
         if (s) return s;
@@ -117,13 +149,26 @@ bh_status record(bh_ctx *c, int which)
     return BH_OK;
 }
 
-bh_status force_tree(bh_ctx *c, const double *pos, const double *mass, double softening,
-                     const double *eps, double theta, double *acc, double *phi, int64_t n)
+int walk_group(const bh_ctx *c)
+{
+    return c->cfg.walk_group ? c->cfg.walk_group : bhx::kDefaultWalkGroup;
+}
+
+bhx::Layout single(int64_t n)
+{
+    bhx::Layout L;
+    L.n = n;
+    return L;
+}
+
+bh_status force_tree(bh_ctx *c, const bhx::Layout &lay, const double *pos, const double *mass,
+                     double softening, const double *eps, double theta, double *acc, double *phi)
 {
     Workspace &w = c->w;
+    const int64_t n = lay.n;
     bh_status st = record(c, 0);
     if (st) return st;
-    BHX_HIP(c, bhx::launch_build(w, c->stream, pos, mass, eps, n, c->cfg.leaf_size));
+    BHX_HIP(c, bhx::launch_build(w, c->stream, lay, pos, mass, eps, c->cfg.leaf_size));
     st = record(c, 1);
     if (st) return st;
     c->tree_n = n;
@@ -138,7 +183,9 @@ bh_status force_tree(bh_ctx *c, const double *pos, const double *mass, double so
     p.counts = (c->cfg.flags & BH_FLAG_COUNTS) ? w.counts : nullptr;
     p.per_body_eps = eps != nullptr;
     p.precision = c->cfg.precision;
-    p.group = c->cfg.walk_group ? c->cfg.walk_group : bhx::kDefaultWalkGroup;
+    p.group = walk_group(c);
+    p.groups = lay.groups;
+    p.n_groups = lay.n_groups;
     BHX_HIP(c, bhx::launch_walk(w, c->stream, p));
     if (p.counts) c->walk_n = n;
     return record(c, 2);
@@ -160,7 +207,7 @@ bh_status vjp(bh_ctx *c, const double *pos, const double *mass, double softening
 {
     if (n == 0) return BH_OK;
     if (theta >= 0.0) {
-        BHX_HIP(c, bhx::launch_build(c->w, c->stream, pos, mass, eps, n, c->cfg.leaf_size));
+        BHX_HIP(c, bhx::launch_build(c->w, c->stream, single(n), pos, mass, eps, c->cfg.leaf_size));
         c->tree_n = n;
         c->tree_eps = eps != nullptr;
         bhx::WalkParams p;
@@ -182,6 +229,128 @@ bh_status vjp(bh_ctx *c, const double *pos, const double *mass, double softening
     return BH_OK;
 }
 
+// Uploads the tables of a layout of n_scenes contiguous scenes (host
+// offsets), unless the context already holds the same layout.
+bh_status set_layout(bh_ctx *c, int32_t n_scenes, const int64_t *offsets)
+{
+    if (n_scenes < 1 || n_scenes > c->w.max_scenes || !offsets)
+        return fail(c, BH_E_INVALID, "n_scenes outside 1..max_scenes, or NULL offsets");
+    if (offsets[0] != 0) return fail(c, BH_E_INVALID, "offsets[0] must be 0");
+    for (int32_t k = 0; k < n_scenes; k++)
+        if (offsets[k + 1] <= offsets[k])
+            return fail(c, BH_E_INVALID, "every scene needs at least one body");
+    const int64_t n = offsets[n_scenes];
+    if (n > c->w.n_cap) return fail(c, BH_E_CAPACITY, "total bodies exceed n_max");
+    const int gb = walk_group(c);
+    if (c->layout_group == gb && (int64_t)c->h_offsets.size() == n_scenes + 1 &&
+        std::equal(c->h_offsets.begin(), c->h_offsets.end(), offsets))
+        return BH_OK;
+    c->h_offsets.assign(offsets, offsets + n_scenes + 1);
+    c->h_chunks.clear();
+    c->h_groups.clear();
+    for (int32_t k = 0; k < n_scenes; k++) {
+        for (int64_t f = offsets[k]; f < offsets[k + 1]; f += bhx::kBoxChunk) {
+            const int64_t e = std::min(offsets[k + 1], f + bhx::kBoxChunk);
+            c->h_chunks.insert(c->h_chunks.end(), {k, (int32_t)f, (int32_t)e});
+        }
+        for (int64_t f = offsets[k]; f < offsets[k + 1]; f += gb) {
+            const int64_t e = std::min(offsets[k + 1], f + gb);
+            c->h_groups.insert(c->h_groups.end(), {(int32_t)f, (int32_t)(e - f), k});
+        }
+    }
+    const int64_t nchunks = (int64_t)c->h_chunks.size() / 3, ngroups = (int64_t)c->h_groups.size() / 3;
+    if (nchunks > c->max_chunks || ngroups > c->max_groups)
+        return fail(c, BH_E_CAPACITY, "layout tables exceed the context's capacity");
+    // pageable sources: the copies complete before the calls return
+    BHX_HIP(c, hipMemcpy(c->d_offsets, offsets, (size_t)(n_scenes + 1) * sizeof(int64_t),
+                         hipMemcpyHostToDevice));
+    BHX_HIP(c, hipMemcpy(c->d_chunks, c->h_chunks.data(), c->h_chunks.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice));
+    BHX_HIP(c, hipMemcpy(c->d_groups, c->h_groups.data(), c->h_groups.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice));
+    BHX_HIP(c, bhx::launch_scene_of(c->stream, c->d_offsets, n_scenes, c->d_scene_of));
+    c->layout_group = gb;
+    bhx::Layout &L = c->batch;
+    L.n = n;
+    L.n_scenes = n_scenes;
+    L.offsets = c->d_offsets;
+    L.scene_of = c->d_scene_of;
+    L.chunks = c->d_chunks;
+    L.n_chunks = (int)nchunks;
+    L.groups = c->d_groups;
+    L.n_groups = (int)ngroups;
+    return BH_OK;
+}
+
+// One kick-drift-kick step of the bodies of `lay` on the context's stream.
+bh_status kdk_step(bh_ctx *c, const bhx::Layout &lay, double *pos, double *vel,
+                   const double *mass, double softening, const double *eps, double theta,
+                   double dt, double *acc)
+{
+    BHX_HIP(c, bhx::launch_kick_drift(c->stream, pos, vel, acc, lay.n, dt));
+    bh_status s = theta >= 0.0
+                      ? force_tree(c, lay, pos, mass, softening, eps, theta, acc, nullptr)
+                      : force_direct(c, pos, mass, softening, eps, acc, nullptr, lay.n,
+                                     c->cfg.precision);
+    if (s) return s;
+    BHX_HIP(c, bhx::launch_kick(c->stream, vel, acc, lay.n, dt));
+    return BH_OK;
+}
+
+// nsteps steps. With BH_FLAG_GRAPH one step is captured once per argument set
+// on the context's own stream and replayed; that stream is ordered after the
+// caller's stream and the caller's stream after it, with events.
+bh_status run_steps(bh_ctx *c, const bhx::Layout &lay, double *pos, double *vel,
+                    const double *mass, double softening, const double *eps, double theta,
+                    double dt, int32_t nsteps, double *acc)
+{
+    if (nsteps <= 0 || lay.n == 0) return BH_OK;
+    if (!(c->cfg.flags & BH_FLAG_GRAPH)) {
+        for (int32_t k = 0; k < nsteps; k++) {
+            bh_status s = kdk_step(c, lay, pos, vel, mass, softening, eps, theta, dt, acc);
+            if (s) return s;
+        }
+        return BH_OK;
+    }
+    std::vector<double> key = {(double)(uintptr_t)pos, (double)(uintptr_t)vel,
+                               (double)(uintptr_t)mass, (double)(uintptr_t)eps,
+                               (double)(uintptr_t)acc, (double)lay.n, (double)(uintptr_t)lay.groups,
+                               (double)lay.n_scenes, softening, theta, dt};
+    hipStream_t caller = c->stream;
+    if (!c->gexec || key != c->gkey) {
+        if (c->gexec) {
+            (void)hipGraphExecDestroy(c->gexec);
+            c->gexec = nullptr;
+        }
+        if (c->graph) {
+            (void)hipGraphDestroy(c->graph);
+            c->graph = nullptr;
+        }
+        BHX_HIP(c, hipStreamBeginCapture(c->cstream, hipStreamCaptureModeThreadLocal));
+        c->stream = c->cstream;
+        c->capturing = true;
+        bh_status s = kdk_step(c, lay, pos, vel, mass, softening, eps, theta, dt, acc);
+        c->capturing = false;
+        c->stream = caller;
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->cstream, &g);
+        if (s) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return hip_fail(c, e, "hipStreamEndCapture");
+        c->graph = g;
+        BHX_HIP(c, hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
+        c->gkey = key;
+    }
+    BHX_HIP(c, hipEventRecord(c->gev[0], caller));
+    BHX_HIP(c, hipStreamWaitEvent(c->cstream, c->gev[0], 0));
+    for (int32_t k = 0; k < nsteps; k++) BHX_HIP(c, hipGraphLaunch(c->gexec, c->cstream));
+    BHX_HIP(c, hipEventRecord(c->gev[1], c->cstream));
+    BHX_HIP(c, hipStreamWaitEvent(caller, c->gev[1], 0));
+    return BH_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -194,8 +363,10 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
     if (cfg->leaf_size < 1 || cfg->leaf_size > 64) return BH_E_INVALID;
     if (cfg->precision != BH_FP64 && cfg->precision != BH_FP32C) return BH_E_INVALID;
     if (!std::isfinite(cfg->G)) return BH_E_INVALID;
-    if (cfg->flags & ~(uint32_t)(BH_FLAG_COUNTS | BH_FLAG_TIMING | BH_FLAG_ADJOINT))
+    if (cfg->flags &
+        ~(uint32_t)(BH_FLAG_COUNTS | BH_FLAG_TIMING | BH_FLAG_ADJOINT | BH_FLAG_GRAPH))
         return BH_E_INVALID;
+    if (cfg->max_scenes < 0 || cfg->max_scenes > bhx::kMaxScenes) return BH_E_INVALID;
     if (cfg->walk_group != 0 && cfg->walk_group != 16 && cfg->walk_group != 32 &&
         cfg->walk_group != 64)
         return BH_E_INVALID;
@@ -212,11 +383,12 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
     Workspace &w = c->w;
     const int64_t n = cfg->n_max > 0 ? cfg->n_max : 1;
     w.n_cap = cfg->n_max;
-    int64_t node_cap = bhx::node_capacity(n, cfg->leaf_size);
+    const int max_scenes = cfg->max_scenes > 0 ? cfg->max_scenes : 1;
+    int64_t node_cap = bhx::node_capacity(n, cfg->leaf_size, max_scenes);
     if (node_cap > INT32_MAX - 16) node_cap = INT32_MAX - 16;
     w.node_cap = node_cap;
     w.sort_blocks_cap = (int)((n + bhx::kSortTile - 1) / bhx::kSortTile);
-    w.bbox_blocks = bhx::kBboxBlocks;
+    w.max_scenes = max_scenes;
     hipError_t r = hipSuccess;
     auto A = [&](hipError_t x) {
         if (r == hipSuccess) r = x;
@@ -232,7 +404,20 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
     A(dalloc(&w.ninfo, node_cap));
     A(dalloc(&w.nmom, node_cap));
     A(dalloc(&w.neps2, node_cap));
-    A(dalloc(&w.bbox_part, (int64_t)bhx::kBboxBlocks * 6));
+    A(dalloc(&w.box, max_scenes));
+    if (max_scenes > 1) {
+        c->max_chunks = n / bhx::kBoxChunk + max_scenes;
+        c->max_groups = n / 16 + max_scenes;
+        A(dalloc(&c->d_offsets, max_scenes + 1));
+        A(dalloc(&c->d_scene_of, n));
+        A(dalloc(&c->d_chunks, 3 * c->max_chunks));
+        A(dalloc(&c->d_groups, 3 * c->max_groups));
+    }
+    if (cfg->flags & BH_FLAG_GRAPH) {
+        A(hipStreamCreateWithFlags(&c->cstream, hipStreamNonBlocking));
+        A(hipEventCreateWithFlags(&c->gev[0], hipEventDisableTiming));
+        A(hipEventCreateWithFlags(&c->gev[1], hipEventDisableTiming));
+    }
     A(dalloc(&w.hdr, 1));
     if (cfg->flags & BH_FLAG_COUNTS) A(dalloc(&w.counts, 2 * n));
     A(dalloc(&w.scratch, 4 * n));
@@ -257,9 +442,7 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
         bh_status st = (r == hipErrorOutOfMemory) ? BH_E_OOM : BH_E_HIP;
         free_ws(w);
         free_aw(c->aw);
-        if (c->diag_out) (void)hipFree(c->diag_out);
-        for (auto ev : c->ev_pool)
-            if (ev) (void)hipEventDestroy(ev);
+        free_extras(c);
         delete c;
         return st;
     }
@@ -271,11 +454,10 @@ void bh_destroy(bh_ctx *c)
 {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    if (c->cstream) (void)hipStreamSynchronize(c->cstream);
     free_ws(c->w);
     free_aw(c->aw);
-    if (c->diag_out) (void)hipFree(c->diag_out);
-    for (auto ev : c->ev_pool)
-        if (ev) (void)hipEventDestroy(ev);
+    free_extras(c);
     delete c;
 }
 
@@ -311,7 +493,7 @@ bh_status bh_build_tree(bh_ctx *c, const double *pos, const double *mass, const 
 {
     bh_status s = check_bodies(c, pos, mass, n);
     if (s) return s;
-    BHX_HIP(c, bhx::launch_build(c->w, c->stream, pos, mass, eps, n, c->cfg.leaf_size));
+    BHX_HIP(c, bhx::launch_build(c->w, c->stream, single(n), pos, mass, eps, c->cfg.leaf_size));
     c->tree_n = n;
     c->tree_eps = eps != nullptr;
     return BH_OK;
@@ -325,7 +507,7 @@ bh_status bh_compute_accel(bh_ctx *c, const double *pos, const double *mass, dou
     if (!finite_nonneg(theta)) return fail(c, BH_E_INVALID, "theta must be finite and >= 0");
     if (!finite_nonneg(softening)) return fail(c, BH_E_INVALID, "softening must be finite and >= 0");
     if (n > 0 && !acc) return fail(c, BH_E_INVALID, "NULL acc");
-    return force_tree(c, pos, mass, softening, eps, theta, acc, phi, n);
+    return force_tree(c, single(n), pos, mass, softening, eps, theta, acc, phi);
 }
 
 bh_status bh_compute_accel_direct(bh_ctx *c, const double *pos, const double *mass,
@@ -350,15 +532,41 @@ bh_status bh_step_leapfrog(bh_ctx *c, double *pos, double *vel, const double *ma
     if (!std::isfinite(dt)) return fail(c, BH_E_INVALID, "dt not finite");
     if (nsteps < 0) return fail(c, BH_E_INVALID, "nsteps < 0");
     if (n > 0 && (!vel || !acc)) return fail(c, BH_E_INVALID, "NULL vel or acc");
-    for (int32_t k = 0; k < nsteps && n > 0; k++) {
-        BHX_HIP(c, bhx::launch_kick_drift(c->stream, pos, vel, acc, n, dt));
-        s = theta >= 0.0 ? force_tree(c, pos, mass, softening, eps, theta, acc, nullptr, n)
-                         : force_direct(c, pos, mass, softening, eps, acc, nullptr, n,
-                                        c->cfg.precision);
-        if (s) return s;
-        BHX_HIP(c, bhx::launch_kick(c->stream, vel, acc, n, dt));
-    }
-    return BH_OK;
+    return run_steps(c, single(n), pos, vel, mass, softening, eps, theta, dt, nsteps, acc);
+}
+
+bh_status bh_batched_accel(bh_ctx *c, int32_t n_scenes, const int64_t *offsets, const double *pos,
+                           const double *mass, double softening, const double *eps, double theta,
+                           double *acc, double *phi)
+{
+    if (!c) return BH_E_INVALID;
+    bh_status s = set_layout(c, n_scenes, offsets);
+    if (s) return s;
+    const int64_t n = c->batch.n;
+    s = check_bodies(c, pos, mass, n);
+    if (s) return s;
+    if (!finite_nonneg(theta)) return fail(c, BH_E_INVALID, "theta must be finite and >= 0");
+    if (!finite_nonneg(softening)) return fail(c, BH_E_INVALID, "softening must be finite and >= 0");
+    if (!acc) return fail(c, BH_E_INVALID, "NULL acc");
+    return force_tree(c, c->batch, pos, mass, softening, eps, theta, acc, phi);
+}
+
+bh_status bh_batched_step(bh_ctx *c, int32_t n_scenes, const int64_t *offsets, double *pos,
+                          double *vel, const double *mass, double softening, const double *eps,
+                          double theta, double dt, int32_t nsteps, double *acc)
+{
+    if (!c) return BH_E_INVALID;
+    bh_status s = set_layout(c, n_scenes, offsets);
+    if (s) return s;
+    const int64_t n = c->batch.n;
+    s = check_bodies(c, pos, mass, n);
+    if (s) return s;
+    if (!finite_nonneg(theta)) return fail(c, BH_E_INVALID, "theta must be finite and >= 0");
+    if (!finite_nonneg(softening)) return fail(c, BH_E_INVALID, "softening must be finite and >= 0");
+    if (!std::isfinite(dt)) return fail(c, BH_E_INVALID, "dt not finite");
+    if (nsteps < 0) return fail(c, BH_E_INVALID, "nsteps < 0");
+    if (!vel || !acc) return fail(c, BH_E_INVALID, "NULL vel or acc");
+    return run_steps(c, c->batch, pos, vel, mass, softening, eps, theta, dt, nsteps, acc);
 }
 
 bh_status bh_accel_vjp(bh_ctx *c, const double *pos, const double *mass, double softening,
@@ -401,9 +609,10 @@ bh_status bh_leapfrog_vjp(bh_ctx *c, const double *pos, const double *vel, const
         const double *x_in = k == 0 ? pos : traj + (int64_t)(k - 1) * n3;
         double *x_out = traj + (int64_t)k * n3;
         BHX_HIP(c, bhx::launch_kick_drift_to(c->stream, x_in, aw.vwork, aw.awork, x_out, n, dt));
-        s = theta >= 0.0 ? force_tree(c, x_out, mass, softening, eps, theta, aw.awork, nullptr, n)
-                         : force_direct(c, x_out, mass, softening, eps, aw.awork, nullptr, n,
-                                        c->cfg.precision);
+        s = theta >= 0.0
+                ? force_tree(c, single(n), x_out, mass, softening, eps, theta, aw.awork, nullptr)
+                : force_direct(c, x_out, mass, softening, eps, aw.awork, nullptr, n,
+                               c->cfg.precision);
         if (s) return s;
         BHX_HIP(c, bhx::launch_kick(c->stream, aw.vwork, aw.awork, n, dt));
     }
@@ -435,7 +644,9 @@ bh_status bh_tree_export(bh_ctx *c, bh_tree_view *out)
     if (!c || !out) return BH_E_INVALID;
     if (c->tree_n < 0) return fail(c, BH_E_STATE, "no tree has been built");
     bhx::TreeHeader h;
+    bhx::SceneBox b;
     BHX_HIP(c, hipMemcpyAsync(&h, c->w.hdr, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    BHX_HIP(c, hipMemcpyAsync(&b, c->w.box, sizeof(b), hipMemcpyDeviceToHost, c->stream));
     BHX_HIP(c, hipStreamSynchronize(c->stream));
     int64_t nn = 0;
     int depth = 0;
@@ -455,11 +666,11 @@ bh_status bh_tree_export(bh_ctx *c, bh_tree_view *out)
     out->order = c->w.idx[0];
     out->keys = c->w.keys[0];
     for (int a = 0; a < 3; a++) {
-        out->box[a] = h.lo[a];
-        out->box[3 + a] = h.x0[a];
+        out->box[a] = b.lo[a];
+        out->box[3 + a] = b.x0[a];
     }
-    out->box[6] = h.L;
-    out->box[7] = h.S;
+    out->box[6] = b.L;
+    out->box[7] = b.S;
     return BH_OK;
 }
 

@@ -2,9 +2,12 @@
 // (subsection "Hierarchical treecode algorithm"; the five GPU stages of
 // subsection "CUDA implementation of GPU-parallel Barnes-Hut" are prior art,
 // this is a Morton-key design for CDNA4):
-//   1. bounding box of all bodies -> root cube (and input validation),
+//   1. bounding box of each scene's bodies -> its root cube (and input
+//      validation); a call may hold many independent scenes, stored as
+//      contiguous body ranges, each with its own root,
 //   2. 63-bit Morton keys on a 2^21 grid,
-//   3. stable LSD radix sort of (key, index), 8-bit digits, LDS ranking,
+//   3. stable LSD radix sort of (key, index), 8-bit digits, LDS ranking, then
+//      (several scenes) two stable passes on the scene index,
 //   4. gather of positions, masses and softening into Morton order,
 //   5. top-down octree, one launch per level: each split cell finds its
 //      octant ranges by binary search in the sorted keys,
@@ -59,16 +62,50 @@ __device__ inline uint32_t block_incl_scan_256(uint32_t v, uint32_t *lds4, uint3
 
 // ---------------------------------------------------------------- 1. box
 
-__global__ __launch_bounds__(256) void k_bbox_partial(const double *__restrict__ pos,
-                                                      const double *__restrict__ mass,
-                                                      const double *__restrict__ eps, int64_t n,
-                                                      double *__restrict__ part,
-                                                      TreeHeader *__restrict__ hdr)
+// Order-preserving map of doubles to unsigned integers, so integer atomics
+// give the exact minimum and maximum whatever the order of the updates.
+__device__ inline unsigned long long order_enc(double x)
 {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ inline double order_dec(unsigned long long e)
+{
+    const unsigned long long b = (e >> 63) ? (e & 0x7fffffffffffffffull) : ~e;
+    return __longlong_as_double((long long)b);
+}
+
+__global__ __launch_bounds__(256) void k_box_init(SceneBox *__restrict__ box, int n_scenes)
+{
+    const int sc = blockIdx.x * 256 + threadIdx.x;
+    if (sc >= n_scenes) return;
+    for (int a = 0; a < 3; a++) {
+        box[sc].lo_enc[a] = ~0ull;
+        box[sc].hi_enc[a] = 0ull;
+    }
+}
+
+// One work item: a chunk of at most kBoxChunk bodies of one scene (for one
+// scene, chunk c is bodies c*kBoxChunk onwards). Reduces its box in the block
+// and merges it into the scene's with integer atomics; flags bad input.
+__global__ __launch_bounds__(256) void k_box_chunk(const double *__restrict__ pos,
+                                                   const double *__restrict__ mass,
+                                                   const double *__restrict__ eps, int64_t n,
+                                                   const int32_t *__restrict__ chunks,
+                                                   SceneBox *__restrict__ box,
+                                                   TreeHeader *__restrict__ hdr)
+{
+    int sc = 0;
+    int64_t first = (int64_t)blockIdx.x * kBoxChunk, end = first + kBoxChunk;
+    if (chunks) {
+        sc = chunks[3 * blockIdx.x];
+        first = chunks[3 * blockIdx.x + 1];
+        end = chunks[3 * blockIdx.x + 2];
+    }
+    if (end > n) end = n;
     double lo[3] = {kInf, kInf, kInf}, hi[3] = {-kInf, -kInf, -kInf};
     bool bad = false;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * 256) {
+    for (int64_t i = first + threadIdx.x; i < end; i += 256) {
         double x[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
         double m = mass[i];
         bad |= !(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]));
@@ -94,45 +131,38 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const double *__restrict__
     }
     __syncthreads();
     if (threadIdx.x < 6) {
-        int a = threadIdx.x;
-        double v = red[0][a];
-        for (int w = 1; w < 4; w++) v = a < 3 ? fmin(v, red[w][a]) : fmax(v, red[w][a]);
-        part[blockIdx.x * 6 + a] = v;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_bbox_final(const double *__restrict__ part, int nblk,
-                                                    int64_t n, TreeHeader *__restrict__ hdr,
-                                                    NodeInfo *__restrict__ ninfo)
-{
-#pragma clang fp contract(off)
-    double lo[3] = {kInf, kInf, kInf}, hi[3] = {-kInf, -kInf, -kInf};
-    for (int b = threadIdx.x; b < nblk; b += 256)
-        for (int a = 0; a < 3; a++) {
-            lo[a] = fmin(lo[a], part[b * 6 + a]);
-            hi[a] = fmax(hi[a], part[b * 6 + 3 + a]);
-        }
-    __shared__ double red[4][6];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int a = 0; a < 3; a++) {
-        double l = wave_min(lo[a]), h = wave_max(hi[a]);
-        if (lane == 0) {
-            red[wave][a] = l;
-            red[wave][3 + a] = h;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    for (int a = 0; a < 6; a++) {
+        const int a = threadIdx.x;
         double v = red[0][a];
         for (int w = 1; w < 4; w++) v = a < 3 ? fmin(v, red[w][a]) : fmax(v, red[w][a]);
         if (a < 3)
-            lo[a] = v;
+            atomicMin(&box[sc].lo_enc[a], order_enc(v));
         else
-            hi[a - 3] = v;
+            atomicMax(&box[sc].hi_enc[a - 3], order_enc(v));
     }
-    if (n == 0)
-        for (int a = 0; a < 3; a++) lo[a] = hi[a] = 0.0;
+}
+
+// One thread per scene: root cube from the box, and the scene's root node
+// (level 0, its bodies' whole range in sorted order). Thread 0 also resets
+// the per-level node counts.
+__global__ __launch_bounds__(256) void k_box_final(SceneBox *__restrict__ box, int n_scenes,
+                                                   const int64_t *__restrict__ offsets, int64_t n,
+                                                   TreeHeader *__restrict__ hdr,
+                                                   NodeInfo *__restrict__ ninfo)
+{
+#pragma clang fp contract(off)
+    const int sc = blockIdx.x * 256 + threadIdx.x;
+    if (sc == 0) {
+        for (int l = 0; l <= kLevels; l++) hdr->level_count[l] = 0;
+        hdr->level_count[0] = n > 0 ? n_scenes : 0;
+    }
+    if (sc >= n_scenes) return;
+    const int64_t first = offsets ? offsets[sc] : 0, end = offsets ? offsets[sc + 1] : n;
+    SceneBox &b = box[sc];
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; a++) {
+        lo[a] = end > first ? order_dec(b.lo_enc[a]) : 0.0;
+        hi[a] = end > first ? order_dec(b.hi_enc[a]) : 0.0;
+    }
     // Root cube: side = largest extent (1 if all bodies coincide), centred
     // on the bounding box.
     double L = 0.0;
@@ -142,21 +172,18 @@ __global__ __launch_bounds__(256) void k_bbox_final(const double *__restrict__ p
     }
     if (L == 0.0) L = 1.0;
     for (int a = 0; a < 3; a++) {
-        hdr->lo[a] = lo[a];
-        hdr->hi[a] = hi[a];
-        hdr->x0[a] = (lo[a] + hi[a]) * 0.5 - L * 0.5;
+        b.lo[a] = lo[a];
+        b.hi[a] = hi[a];
+        b.x0[a] = (lo[a] + hi[a]) * 0.5 - L * 0.5;
     }
-    hdr->L = L;
-    hdr->S = 2097152.0 / L;
+    b.L = L;
+    b.S = 2097152.0 / L;
     for (int l = 0; l < kLevels; l++) {
-        double s = ldexp(L, -l);
-        hdr->s2[l] = s * s;
+        double sd = ldexp(L, -l);
+        b.s2[l] = sd * sd;
     }
-    for (int l = 0; l <= kLevels; l++) hdr->level_count[l] = 0;
-    if (n > 0) {
-        hdr->level_count[0] = 1;
-        ninfo[0] = NodeInfo{0, (int32_t)n, -1, 0};
-    }
+    if (end > first)
+        ninfo[sc] = NodeInfo{(int32_t)first, (int32_t)(end - first), -1, (int32_t)(sc << 16)};
 }
 
 // --------------------------------------------------------------- 2. keys
@@ -197,24 +224,37 @@ __device__ inline uint32_t quantise(double x, double x0, double S)
 }
 
 __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ pos, int64_t n,
-                                              const TreeHeader *__restrict__ hdr,
+                                              const SceneBox *__restrict__ box,
+                                              const uint16_t *__restrict__ scene_of,
                                               uint64_t *__restrict__ keys,
                                               uint32_t *__restrict__ idx)
 {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    const double S = hdr->S;
-    uint32_t qx = quantise(pos[3 * i], hdr->x0[0], S);
-    uint32_t qy = quantise(pos[3 * i + 1], hdr->x0[1], S);
-    uint32_t qz = quantise(pos[3 * i + 2], hdr->x0[2], S);
+    const SceneBox &b = box[scene_of ? scene_of[i] : 0];
+    const double S = b.S;
+    uint32_t qx = quantise(pos[3 * i], b.x0[0], S);
+    uint32_t qy = quantise(pos[3 * i + 1], b.x0[1], S);
+    uint32_t qz = quantise(pos[3 * i + 2], b.x0[2], S);
     keys[i] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
     idx[i] = (uint32_t)i;
 }
 
 // --------------------------------------------------------------- 3. sort
 
+// Sort digit of one element: 8 bits of its key, or for shift >= 64 8 bits of
+// its scene index (shift - 64 = 0 or 8).
+__device__ inline uint32_t sort_digit(uint64_t key, uint32_t val, int shift,
+                                      const uint16_t *__restrict__ scene_of)
+{
+    if (shift < 64) return (uint32_t)(key >> shift) & 255u;
+    return ((uint32_t)scene_of[val] >> (shift - 64)) & 255u;
+}
+
 // Per-tile digit histogram, written digit-major: counts[d * nblk + tile].
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint64_t *__restrict__ keys,
+                                                            const uint32_t *__restrict__ vals,
+                                                            const uint16_t *__restrict__ scene_of,
                                                             int64_t n, int shift,
                                                             uint32_t *__restrict__ counts,
                                                             int nblk)
@@ -225,7 +265,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint64_t *__re
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     for (int r = 0; r < kSortItems; r++) {
         int64_t i = base + r * kSortThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        if (i < n) atomicAdd(&h[sort_digit(keys[i], vals[i], shift, scene_of)], 1u);
     }
     __syncthreads();
     counts[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
@@ -252,6 +292,7 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t *__restrict__ counts
 // tile order (round r, thread t) == input order.
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+    const uint16_t *__restrict__ scene_of,
     uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
     const uint32_t *__restrict__ counts, const uint32_t *__restrict__ totals, int nblk)
 {
@@ -282,7 +323,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
         const bool valid = base + r * kSortThreads + tid < n;
-        const uint32_t d = (uint32_t)(k[r] >> shift) & 255u;
+        const uint32_t d = valid ? sort_digit(k[r], v[r], shift, scene_of) : 0u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
@@ -391,10 +432,11 @@ __global__ __launch_bounds__(256) void k_build_level(int level, const uint64_t *
             if (o == 0) atomicOr(&hdr->status, ST_CAPACITY);
             continue;
         }
-        if (nonempty) ninfo[c0 + rank] = NodeInfo{start, end - start, -1, level + 1};
+        const int32_t scene_bits = info.lvl_nch & (int32_t)0xffff0000;
+        if (nonempty) ninfo[c0 + rank] = NodeInfo{start, end - start, -1, (level + 1) | scene_bits};
         if (o == 0) {
             ninfo[k].child0 = (int32_t)c0;
-            ninfo[k].lvl_nch = level | (nch << 8);
+            ninfo[k].lvl_nch = level | (nch << 8) | scene_bits;
         }
     }
 }
@@ -407,8 +449,8 @@ __global__ __launch_bounds__(256) void k_build_level(int level, const uint64_t *
 __global__ __launch_bounds__(256) void k_moments_level(
     int level, const TreeHeader *__restrict__ hdr, const NodeInfo *__restrict__ ninfo,
     const Body *__restrict__ body, const double *__restrict__ beps2,
-    const uint64_t *__restrict__ keys, NodeMom *__restrict__ nmom, double *__restrict__ neps2,
-    int64_t node_cap, int use_eps)
+    const uint64_t *__restrict__ keys, const SceneBox *__restrict__ box,
+    NodeMom *__restrict__ nmom, double *__restrict__ neps2, int64_t node_cap, int use_eps)
 {
 #pragma clang fp contract(off)
     int32_t beg, cnt;
@@ -446,11 +488,12 @@ __global__ __launch_bounds__(256) void k_moments_level(
         } else {
             // massless cell: its centre
             const uint64_t key = keys[info.first];
+            const SceneBox &b = box[node_scene(info)];
             const int sh = kMaxLevel - level;
-            const double s = ldexp(hdr->L, -level);
-            out.x = hdr->x0[0] + ((double)(compact3(key >> 2) >> sh) + 0.5) * s;
-            out.y = hdr->x0[1] + ((double)(compact3(key >> 1) >> sh) + 0.5) * s;
-            out.z = hdr->x0[2] + ((double)(compact3(key) >> sh) + 0.5) * s;
+            const double s = ldexp(b.L, -level);
+            out.x = b.x0[0] + ((double)(compact3(key >> 2) >> sh) + 0.5) * s;
+            out.y = b.x0[1] + ((double)(compact3(key >> 1) >> sh) + 0.5) * s;
+            out.z = b.x0[2] + ((double)(compact3(key) >> sh) + 0.5) * s;
             out.m = 0.0;
         }
         nmom[k] = out;
@@ -465,46 +508,73 @@ inline unsigned blocks_for(int64_t items, int per_block, unsigned cap)
     return (unsigned)(b < (int64_t)cap ? b : cap);
 }
 
-// Upper bound on the nodes of one level: at most 8^level and at most n.
-inline int64_t level_bound(int level, int64_t n)
+// Upper bound on the nodes of one level: at most 8^level per scene and at
+// most n in all.
+inline int64_t level_bound(int level, int64_t n, int scenes)
 {
-    int64_t b = 1;
+    int64_t b = scenes;
     for (int l = 0; l < level && b < n; l++) b *= 8;
     return b < n ? b : n;
 }
 
+// One block per scene fills its body range.
+__global__ __launch_bounds__(256) void k_scene_of(const int64_t *__restrict__ offsets,
+                                                  uint16_t *__restrict__ scene_of)
+{
+    const int sc = blockIdx.x;
+    for (int64_t i = offsets[sc] + threadIdx.x; i < offsets[sc + 1]; i += 256)
+        scene_of[i] = (uint16_t)sc;
+}
+
 }  // namespace
 
-hipError_t launch_build(const Workspace &w, hipStream_t s, const double *pos, const double *mass,
-                        const double *eps, int64_t n, int leaf)
+hipError_t launch_scene_of(hipStream_t s, const int64_t *offsets, int n_scenes,
+                           uint16_t *scene_of)
 {
-    const unsigned nb_box = blocks_for(n, 256 * 4, kBboxBlocks);
-    k_bbox_partial<<<nb_box, 256, 0, s>>>(pos, mass, eps, n, w.bbox_part, w.hdr);
-    k_bbox_final<<<1, 256, 0, s>>>(w.bbox_part, (int)nb_box, n, w.hdr, w.ninfo);
+    k_scene_of<<<n_scenes, 256, 0, s>>>(offsets, scene_of);
+    return hipGetLastError();
+}
+
+hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, const double *pos,
+                        const double *mass, const double *eps, int leaf)
+{
+    const int64_t n = lay.n;
+    const int ns = lay.n_scenes;
+    const unsigned sb = (unsigned)((ns + 255) / 256);
+    k_box_init<<<sb, 256, 0, s>>>(w.box, ns);
+    const int nchunks = lay.chunks ? lay.n_chunks : (int)((n + kBoxChunk - 1) / kBoxChunk);
+    if (nchunks > 0)
+        k_box_chunk<<<nchunks, 256, 0, s>>>(pos, mass, eps, n, lay.chunks, w.box, w.hdr);
+    k_box_final<<<sb, 256, 0, s>>>(w.box, ns, lay.offsets, n, w.hdr, w.ninfo);
     if (n == 0) return hipGetLastError();
 
     const unsigned nb = blocks_for(n, 256, 1u << 30);
-    k_keys<<<nb, 256, 0, s>>>(pos, n, w.hdr, w.keys[0], w.idx[0]);
+    k_keys<<<nb, 256, 0, s>>>(pos, n, w.box, lay.scene_of, w.keys[0], w.idx[0]);
 
+    // 8 passes on the Morton key, then (several scenes) 2 on the scene
+    // index; an even number of passes leaves the result in buffer 0.
     const int nblk = (int)((n + kSortTile - 1) / kSortTile);
-    for (int pass = 0; pass < 8; pass++) {
-        const int shift = 8 * pass;
+    const int passes = ns > 1 ? 10 : 8;
+    for (int pass = 0; pass < passes; pass++) {
+        const int shift = pass < 8 ? 8 * pass : 64 + 8 * (pass - 8);
         const int src = pass & 1, dst = src ^ 1;
-        k_sort_hist<<<nblk, kSortThreads, 0, s>>>(w.keys[src], n, shift, w.sort_counts, nblk);
+        k_sort_hist<<<nblk, kSortThreads, 0, s>>>(w.keys[src], w.idx[src], lay.scene_of, n, shift,
+                                                  w.sort_counts, nblk);
         k_sort_scan<<<256, 256, 0, s>>>(w.sort_counts, w.sort_totals, nblk);
-        k_sort_scatter<<<nblk, kSortThreads, 0, s>>>(w.keys[src], w.idx[src], w.keys[dst],
-                                                     w.idx[dst], n, shift, w.sort_counts,
-                                                     w.sort_totals, nblk);
+        k_sort_scatter<<<nblk, kSortThreads, 0, s>>>(w.keys[src], w.idx[src], lay.scene_of,
+                                                     w.keys[dst], w.idx[dst], n, shift,
+                                                     w.sort_counts, w.sort_totals, nblk);
     }
     k_gather<<<nb, 256, 0, s>>>(pos, mass, eps, w.idx[0], n, w.body, w.beps2);
 
+    // the largest scene bounds the number of nodes of a level per scene
     for (int level = 0; level < kMaxLevel; level++) {
-        const unsigned g = blocks_for(level_bound(level, n) * 8, 256, 4096);
+        const unsigned g = blocks_for(level_bound(level, n, ns) * 8, 256, 4096);
         k_build_level<<<g, 256, 0, s>>>(level, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
     }
     for (int level = kMaxLevel; level >= 0; level--) {
-        const unsigned g = blocks_for(level_bound(level, n), 256, 4096);
-        k_moments_level<<<g, 256, 0, s>>>(level, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0],
+        const unsigned g = blocks_for(level_bound(level, n, ns), 256, 4096);
+        k_moments_level<<<g, 256, 0, s>>>(level, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0], w.box,
                                           w.nmom, w.neps2, w.node_cap, eps != nullptr);
     }
     return hipGetLastError();

@@ -105,9 +105,9 @@ __global__ __launch_bounds__(64) void k_walk(
     const Body *__restrict__ body, const double *__restrict__ beps2,
     const NodeInfo *__restrict__ ninfo, const NodeMom *__restrict__ nmom,
     const double *__restrict__ neps2, const uint32_t *__restrict__ idx,
-    const TreeHeader *__restrict__ hdr, int64_t n, int ngroups, int per_xcd, double th2,
-    double eps0sq, double G, double *__restrict__ acc, double *__restrict__ phi,
-    int32_t *__restrict__ counts)
+    const SceneBox *__restrict__ box, const int32_t *__restrict__ groups, int64_t n,
+    int ngroups, int per_xcd, double th2, double eps0sq, double G, double *__restrict__ acc,
+    double *__restrict__ phi, int32_t *__restrict__ counts)
 {
     static_assert(GB == 64 || GB == 32 || GB == 16, "group size");
     constexpr int LPB = 64 / GB;  // lanes per body
@@ -144,13 +144,21 @@ __global__ __launch_bounds__(64) void k_walk(
     const int lane = threadIdx.x;
     const int bq = GB == 64 ? lane : lane % GB;  // body of this lane within the group
     const int sub = GB == 64 ? 0 : lane / GB;    // which share of the items it sweeps
-    const int64_t g0 = (int64_t)grp * GB;
+    // the group: up to GB consecutive sorted bodies of one scene
+    int64_t g0 = (int64_t)grp * GB;
+    int gcount = (int)min((int64_t)GB, n - g0);
+    int scene = 0;
+    if (groups) {
+        g0 = groups[3 * grp];
+        gcount = groups[3 * grp + 1];
+        scene = groups[3 * grp + 2];
+    }
     const int64_t s = g0 + bq;
-    const bool valid = s < n;
+    const bool valid = bq < gcount;
     const Body me = body[valid ? s : g0];
     const double eb2 = PEPS ? beps2[valid ? s : g0] : 0.0;
     const uint64_t active = __ballot(valid) & kBodyMask;
-    if (lane < kLevels) s2tab[lane] = hdr->s2[lane];
+    if (lane < kLevels) s2tab[lane] = box[scene].s2[lane];
 
     const float e2hB = (float)(0.5 * eb2);
     const float eps0f = (float)eps0sq;
@@ -164,7 +172,7 @@ __global__ __launch_bounds__(64) void k_walk(
     uint32_t queued = 0;     // items ever queued
     uint32_t consumed = 0;   // items ever evaluated
     if (lane == 0) {
-        st_c0[0] = 0;  // the root, as a range of one
+        st_c0[0] = scene;  // the scene's root (node `scene`), as a range of one
         st_n[0] = 1;
         st_mask[0] = active;
     }
@@ -400,11 +408,12 @@ __global__ __launch_bounds__(64) void k_walk(
 template <int PREC, bool PEPS, bool PHI, bool CNT, int GB>
 hipError_t launch_t(const Workspace &w, hipStream_t s, const WalkParams &p)
 {
-    const int ngroups = (int)((p.n + GB - 1) / GB);
+    const int ngroups = p.groups ? p.n_groups : (int)((p.n + GB - 1) / GB);
     const int per_xcd = (ngroups + 7) / 8;
+    if (ngroups == 0) return hipSuccess;
     k_walk<PREC, PEPS, PHI, CNT, GB><<<8 * per_xcd, 64, 0, s>>>(
-        w.body, w.beps2, w.ninfo, w.nmom, w.neps2, w.idx[0], w.hdr, p.n, ngroups, per_xcd, p.th2,
-        p.eps0sq, p.G, p.acc, p.phi, p.counts);
+        w.body, w.beps2, w.ninfo, w.nmom, w.neps2, w.idx[0], w.box, p.groups, p.n, ngroups,
+        per_xcd, p.th2, p.eps0sq, p.G, p.acc, p.phi, p.counts);
     return hipGetLastError();
 }
 

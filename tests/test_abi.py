@@ -54,14 +54,16 @@ def test_struct_layouts_match_header(tmp_path):
 
 
 def _cfg(**kw):
-    d = dict(n_max=100, leaf_size=16, precision=L.BH_FP32C, G=1.0, flags=0, walk_group=0)
+    d = dict(n_max=100, leaf_size=16, precision=L.BH_FP32C, G=1.0, flags=0, walk_group=0,
+             max_scenes=0)
     d.update(kw)
     return L.bh_config(d["n_max"], d["leaf_size"], d["precision"], d["G"], d["flags"],
-                       d["walk_group"])
+                       d["walk_group"], d["max_scenes"])
 
 
 @pytest.mark.parametrize("bad", [dict(n_max=-1), dict(leaf_size=0), dict(leaf_size=65),
-                                 dict(precision=7), dict(G=float("nan")), dict(flags=8),
+                                 dict(precision=7), dict(G=float("nan")), dict(flags=16),
+                                 dict(max_scenes=-1), dict(max_scenes=70000),
                                  dict(walk_group=8), dict(walk_group=48)])
 def test_create_rejects_bad_config(lib, bad):
     h = C.c_void_p(123)
@@ -81,6 +83,8 @@ def test_null_context_calls(lib):
     assert lib.bh_tree_export(None, None) == L.BH_E_INVALID
     assert lib.bh_stats(None, None) == L.BH_E_INVALID
     assert lib.bh_set_stream(None, None) == L.BH_E_INVALID
+    assert lib.bh_batched_accel(None, 1, None, None, None, 0.0, None, 0.5, None, None) == L.BH_E_INVALID
+    assert lib.bh_batched_step(None, 1, None, None, None, None, 0.0, None, 0.5, 1e-3, 1, None) == L.BH_E_INVALID
     assert lib.bh_last_error(None) == b"NULL context"
     lib.bh_destroy(None)
 

@@ -1,0 +1,140 @@
+"""Many independent scenes per call, and graph-captured steps.
+
+Bars: per scene, the same bars as the single-scene parity tests (counts exact;
+FP64 1e-12 A_i; FP32C 64u A_i). A batched call gives every scene the same
+tree, groups and interaction order as a call on that scene alone, so the two
+must agree bit for bit; a replayed step graph must agree bit for bit with the
+same steps run eagerly.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1912_04197_amd import ics
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+FP64_TOL = 1e-12
+FP32C_TOL = 64 * 2.0 ** -24
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    from paper_1912_04197_amd import api as A
+
+    return A
+
+
+def _scenes(k, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    ns = np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), k))).astype(int)
+    sc = [ics.uniform_ball(int(n), seed=seed * 100 + i) for i, n in enumerate(ns)]
+    offsets = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    pos = np.vstack([s.pos for s in sc])
+    mass = np.concatenate([s.mass for s in sc])
+    return sc, offsets, pos, mass
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_batched_accel_parity(api, precision):
+    sc, off, pos, mass = _scenes(12, 60, 5000, 7)
+    ctx = api.Context(len(mass), leaf_size=8, precision=precision, counts=True, max_scenes=16)
+    acc = ctx.batched_accel(off, _dev(pos), _dev(mass), 0.5, softening=1e-3).cpu().numpy()
+    cnt = ctx.walk_counts(len(mass)).cpu().numpy()
+    tol = FP64_TOL if precision == "fp64" else FP32C_TOL
+    for k, s in enumerate(sc):
+        a, b = off[k], off[k + 1]
+        ref, _, aabs, rc = oracle.bh(s.pos, s.mass, 0.5, softening=1e-3, leaf=8)
+        assert np.array_equal(cnt[a:b], rc), k
+        err = np.linalg.norm(acc[a:b] - ref, axis=1)
+        assert np.all(err <= tol * aabs), (k, (err / aabs).max())
+
+
+@pytest.mark.parametrize("group", [64, 16])
+def test_batched_equals_single_scene_calls(api, group):
+    sc, off, pos, mass = _scenes(9, 30, 3000, 8)
+    ctx = api.Context(len(mass), leaf_size=16, precision="fp32c", max_scenes=9, walk_group=group)
+    acc = ctx.batched_accel(off, _dev(pos), _dev(mass), 0.6, softening=1e-3).cpu().numpy()
+    single = api.Context(len(mass), leaf_size=16, precision="fp32c", walk_group=group)
+    for k, s in enumerate(sc):
+        a1 = single.compute_accel(_dev(s.pos), _dev(s.mass), 0.6, softening=1e-3).cpu().numpy()
+        assert np.array_equal(acc[off[k]:off[k + 1]], a1), k
+
+
+def test_batched_step_graph_replays(api):
+    """Graph-captured batched steps, replayed in several calls with other GPU
+    work and synchronisations in between, equal the eager steps bit for bit."""
+    sc, off, pos, mass = _scenes(8, 100, 4000, 9)
+    rng = np.random.default_rng(9)
+    vel = 0.1 * rng.standard_normal(pos.shape)
+    n = len(mass)
+    eager = api.Context(n, leaf_size=8, precision="fp32c", max_scenes=8)
+    graph = api.Context(n, leaf_size=8, precision="fp32c", max_scenes=8, graph=True)
+    other = api.Context(4096, leaf_size=16)
+    s_other = ics.plummer(4096, seed=3)
+    state = []
+    for ctx in (eager, graph):
+        p, v, m = _dev(pos), _dev(vel), _dev(mass)
+        a = ctx.batched_accel(off, p, m, 0.5, softening=1e-3)
+        state.append((ctx, p, v, m, a))
+    for rep in range(4):
+        for ctx, p, v, m, a in state:
+            ctx.batched_step(off, p, v, m, a, 1e-3, 3, theta=0.5, softening=1e-3)
+        other.compute_accel(_dev(s_other.pos), _dev(s_other.mass), 0.5, softening=1e-3)
+        torch.cuda.synchronize()
+        (_, p0, v0, _, a0), (_, p1, v1, _, a1) = state
+        assert torch.equal(p0, p1) and torch.equal(v0, v1) and torch.equal(a0, a1), rep
+
+
+def test_step_leapfrog_graph_replays(api):
+    s = ics.plummer(30000, seed=10)
+    eager = api.Context(s.n, precision="fp32c")
+    graph = api.Context(s.n, precision="fp32c", graph=True)
+    st = []
+    for ctx in (eager, graph):
+        p, v, m = _dev(s.pos), _dev(s.vel), _dev(s.mass)
+        st.append((ctx, p, v, m, ctx.compute_accel(p, m, 0.5, softening=1e-3)))
+    for rep in range(3):
+        for ctx, p, v, m, a in st:
+            ctx.step_leapfrog(p, v, m, a, 1e-3, 4, theta=0.5, softening=1e-3)
+        torch.cuda.synchronize()
+        assert torch.equal(st[0][1], st[1][1]) and torch.equal(st[0][2], st[1][2]), rep
+
+
+def test_batched_256_scene_workload(api):
+    """The batched workload at full size: 256 uniform balls, N log-uniform in
+    [1024, 65536] (about 4 million bodies), theta 0.5, leaf 16, FP32C; eight
+    scenes are checked against the oracle on 256 sampled targets each."""
+    scenes = ics.batched_scenes(256, seed=44)
+    ns = np.array([s.n for s in scenes])
+    off = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    n = int(off[-1])
+    ctx = api.Context(n, leaf_size=16, precision="fp32c", counts=True, max_scenes=256)
+    pos = _dev(np.vstack([s.pos for s in scenes]))
+    mass = _dev(np.concatenate([s.mass for s in scenes]))
+    acc = ctx.batched_accel(off, pos, mass, 0.5, softening=1e-3).cpu().numpy()
+    cnt = ctx.walk_counts(n).cpu().numpy()
+    rng = np.random.default_rng(4)
+    for k in rng.choice(256, 8, replace=False):
+        s = scenes[k]
+        t = np.sort(rng.choice(s.n, min(256, s.n), replace=False))
+        ref, _, aabs, rc = oracle.Tree(s.pos, s.mass, leaf=16).accel(0.5, softening=1e-3, targets=t)
+        a = acc[off[k]:off[k + 1]][t]
+        assert np.array_equal(cnt[off[k]:off[k + 1]][t], rc), k
+        assert np.all(np.linalg.norm(a - ref, axis=1) <= FP32C_TOL * aabs), k
+
+
+def test_batched_layout_errors(api):
+    ctx = api.Context(100, max_scenes=4)
+    p = torch.zeros((100, 3), dtype=torch.float64, device="cuda")
+    m = torch.ones(100, dtype=torch.float64, device="cuda")
+    for bad in ([0, 50, 50, 100], [1, 50, 100], [0, 20, 40, 60, 80, 100]):
+        with pytest.raises((api.BHError, ValueError)):
+            ctx.batched_accel(np.array(bad), p, m, 0.5)
