@@ -62,6 +62,136 @@ def walk_traffic():
     return rec["hbm_bytes_per_launch"] if rec.get("walk_source_sha256_16") == h else None
 
 
+def _sync_time(fn):
+    import torch
+
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) * 1e3
+
+
+def bench_batched(args, n_scenes=256, steps=10, theta=0.5, dt=1e-3, soft=1e-3):
+    """Many independent scenes at once: 256 uniform balls with N log-uniform in
+    [1024, 65536], FP32C, KDK steps of every scene captured into one graph per
+    call, with the bucket and walk-group sizes picked by the autotuner; against
+    the same steps run scene by scene and against FP64."""
+    import numpy as np
+    import torch
+
+    from paper_1912_04197_amd import ics
+    from paper_1912_04197_amd.api import Context, autotune
+
+    scenes = ics.batched_scenes(n_scenes, seed=44)
+    ns = np.array([sc.n for sc in scenes])
+    off = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    n = int(off[-1])
+    log(f"batched: {n_scenes} scenes, {n} bodies")
+    pos0 = torch.from_numpy(np.vstack([sc.pos for sc in scenes])).cuda()
+    vel0 = torch.from_numpy(np.vstack([sc.vel for sc in scenes])).cuda()
+    mass = torch.from_numpy(np.concatenate([sc.mass for sc in scenes])).cuda()
+    t = time.perf_counter()
+    leaf, group, tune_ms = autotune(off, pos0, vel0, mass, theta=theta, dt=dt, softening=soft,
+                                    steps=3)
+    tune_s = time.perf_counter() - t
+    log(f"autotune: leaf {leaf}, group {group} ({tune_ms:.2f} ms/step, {tune_s:.1f} s)")
+
+    def graph_steps(lf, gr, prec):
+        ctx = Context(n, leaf_size=lf, precision=prec, walk_group=gr, max_scenes=n_scenes,
+                      graph=True)
+        p, v = pos0.clone(), vel0.clone()
+        a = ctx.batched_accel(off, p, mass, theta, softening=soft)
+        ctx.batched_step(off, p, v, mass, a, dt, steps, theta=theta, softening=soft)
+        ms = _sync_time(lambda: ctx.batched_step(off, p, v, mass, a, dt, steps, theta=theta,
+                                                 softening=soft, sync=False)) / steps
+        ctx.close()
+        return ms
+
+    ms_tuned = graph_steps(leaf, group, "fp32c")
+    ms_default = graph_steps(16, 64, "fp32c")
+    ms_fp64 = graph_steps(leaf, group, "fp64")
+    cctx = Context(n, leaf_size=leaf, precision="fp32c", counts=True, max_scenes=n_scenes,
+                   walk_group=group)
+    cctx.batched_accel(off, pos0, mass, theta, softening=soft)
+    st = cctx.stats()
+    inter = st["nodes_accepted"] + st["leaf_pairs"]
+    cctx.close()
+
+    # the same steps issued scene by scene from one context (no graph)
+    one = Context(int(ns.max()), leaf_size=leaf, precision="fp32c", walk_group=group)
+    p, v = pos0.clone(), vel0.clone()
+    a = torch.empty_like(p)
+    views = [(p[off[k]:off[k + 1]], v[off[k]:off[k + 1]], mass[off[k]:off[k + 1]],
+              a[off[k]:off[k + 1]]) for k in range(n_scenes)]
+    for pk, vk, mk, ak in views:
+        one.compute_accel(pk, mk, theta, softening=soft, out=ak, sync=False)
+
+    def loop():
+        for pk, vk, mk, ak in views:
+            one.step_leapfrog(pk, vk, mk, ak, dt, 1, theta=theta, softening=soft, sync=False)
+
+    loop()
+    ms_loop = _sync_time(loop)
+    one.close()
+    log(f"batched: graph {ms_tuned:.2f} ms/step (default 16/64 {ms_default:.2f}, fp64 "
+        f"{ms_fp64:.2f}), scene-by-scene {ms_loop:.2f} ms/step")
+    return {
+        "workload": f"{n_scenes} uniform balls, N log-uniform in [1024, 65536], {n} bodies, "
+                    f"theta={theta} eps={soft} dt={dt}, FP32C, {steps} KDK steps per graph call",
+        "bodies": n,
+        "autotune": {"leaf": leaf, "walk_group": group, "ms_per_step": round(tune_ms, 4),
+                     "seconds": round(tune_s, 2)},
+        "ms_per_step": round(ms_tuned, 4),
+        "body_steps_per_s": round(n / (ms_tuned * 1e-3), 1),
+        "ginteractions_per_s": round(inter / (ms_tuned * 1e-3) / 1e9, 3),
+        "interactions_per_body": round(inter / n, 1),
+        "ms_per_step_leaf16_group64": round(ms_default, 4),
+        "ms_per_step_fp64": round(ms_fp64, 4),
+        "ms_per_step_scene_by_scene": round(ms_loop, 4),
+        "speedup_vs_scene_by_scene": round(ms_loop / ms_tuned, 2),
+    }
+
+
+def bench_adjoint(n=65536, nsteps=20, every=10, theta=0.5, dt=1e-3, soft=1e-3):
+    """Differentiable rollout: forward KDK steps with checkpoints, then the
+    hand-written adjoint back to (x0, v0, m), against the forward alone."""
+    import torch
+
+    from paper_1912_04197_amd import ics
+    from paper_1912_04197_amd.api import Context
+    from paper_1912_04197_amd.autograd import rollout
+
+    s = ics.uniform_ball(n, seed=55)
+    xt = torch.from_numpy(ics.perturbed_target(s.pos, seed=56)).cuda()
+    out = {"workload": f"uniform ball N={n} theta={theta} eps={soft} dt={dt}, {nsteps} KDK "
+                       f"steps, checkpoint every {every}, loss sum |x_T - x*|^2"}
+    for prec in ("fp32c", "fp64"):
+        ctx = Context(n, leaf_size=16, precision=prec, adjoint=True)
+        x0 = torch.from_numpy(s.pos).cuda().requires_grad_(True)
+        v0 = torch.from_numpy(s.vel).cuda().requires_grad_(True)
+        m = torch.from_numpy(s.mass).cuda().requires_grad_(True)
+
+        def fwd():
+            with torch.no_grad():
+                rollout(x0, v0, m, ctx, dt, nsteps, theta=theta, softening=soft,
+                        checkpoint_every=every)
+
+        def fwd_bwd():
+            x, _ = rollout(x0, v0, m, ctx, dt, nsteps, theta=theta, softening=soft,
+                           checkpoint_every=every)
+            ((x - xt) ** 2).sum().backward()
+
+        fwd_bwd()
+        t_f = _sync_time(fwd)
+        t_fb = _sync_time(fwd_bwd)
+        ctx.close()
+        out[prec] = {"forward_ms": round(t_f, 3), "forward_backward_ms": round(t_fb, 3),
+                     "backward_over_forward": round((t_fb - t_f) / t_f, 2)}
+        log(f"adjoint {prec}: forward {t_f:.1f} ms, forward+backward {t_fb:.1f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,6 +370,8 @@ def main():
             "force_rel_err_fp32c_vs_fp64_tree": err_stats(a_tree32, a_tree64),
         }
         c64.close()
+        result["batched"] = bench_batched(args)
+        result["adjoint"] = bench_adjoint()
 
     if not args.no_cpu:
         import oracle

@@ -170,6 +170,26 @@ bh_status bh_batched_step(bh_ctx *ctx, int32_t n_scenes, const int64_t *offsets,
                           double *vel, const double *mass, double softening, const double *eps,
                           double theta, double dt, int32_t nsteps, double *acc);
 
+/* Autotuner for bh_batched_step: times every bucket size in {4, 8, 16, 32}
+ * and walk group size in {16, 32, 64} (other settings from *base) on scratch
+ * copies of the given state (the caller's arrays are not modified): one
+ * graph-captured warm-up step, then `steps` steps timed with HIP events. Each
+ * candidate gets a context of its own, so this call allocates and frees
+ * device memory; it synchronises hip_stream first and returns when done.
+ * With the BHX_AUTOTUNE_CACHE environment variable naming a file, results
+ * are read from and appended to it (JSON lines keyed by the layout, the
+ * precision and the physical parameters). out receives the fastest choice
+ * and its time per step. Errors: BH_E_INVALID for bad arguments, BH_E_OOM if
+ * no candidate fits, or any error of the calls it makes. */
+typedef struct {
+    int32_t leaf_size, walk_group;
+    double ms_per_step;
+} bh_tune_result;
+bh_status bh_autotune(const bh_config *base, void *hip_stream, int32_t n_scenes,
+                      const int64_t *offsets, const double *pos, const double *vel,
+                      const double *mass, double softening, const double *eps, double theta,
+                      double dt, int32_t steps, bh_tune_result *out);
+
 /* Vector-Jacobian product of the force map: ADDS to g_pos (n x 3) and g_mass
  * (n) the gradient of sum_i lambda_i . a_i with respect to the positions and
  * masses, lambda being n x 3 in caller order. theta >= 0 differentiates the

@@ -38,6 +38,10 @@ class bh_stats_t(C.Structure):
                 ("timed_evals", C.c_int64), ("build_ms", C.c_double), ("walk_ms", C.c_double)]
 
 
+class bh_tune_result(C.Structure):
+    _fields_ = [("leaf_size", C.c_int32), ("walk_group", C.c_int32), ("ms_per_step", C.c_double)]
+
+
 P, I64, I32, D = C.c_void_p, C.c_int64, C.c_int32, C.c_double
 SIGNATURES = {
     "bh_create": ([C.POINTER(bh_config), P, C.POINTER(P)], C.c_int),
@@ -56,6 +60,8 @@ SIGNATURES = {
     "bh_timing_reset": ([P], C.c_int),
     "bh_accel_vjp": ([P, P, P, D, P, D, P, P, P, I64], C.c_int),
     "bh_batched_accel": ([P, I32, P, P, P, D, P, D, P, P], C.c_int),
+    "bh_autotune": ([C.POINTER(bh_config), P, I32, P, P, P, P, D, P, D, D, I32,
+                     C.POINTER(bh_tune_result)], C.c_int),
     "bh_batched_step": ([P, I32, P, P, P, P, D, P, D, D, I32, P], C.c_int),
     "bh_leapfrog_vjp": ([P, P, P, P, P, D, P, D, D, I32, P, P, P, P, P, I64], C.c_int),
 }

@@ -307,3 +307,30 @@ class Context:
         self._rc(self._lib.bh_diagnostics(self._h, _ptr(pos), _ptr(vel), _ptr(mass),
                                           float(softening), _ptr(eps), out, n))
         return [float(x) for x in out]
+
+
+def autotune(offsets, pos, vel, mass, theta=0.5, dt=1e-3, softening=0.0, eps=None,
+             precision="fp32c", G=1.0, steps=3):
+    """Fastest (leaf_size, walk_group, ms_per_step) for bh_batched_step on these
+    scenes (see bh_autotune); the state tensors are not modified."""
+    import numpy as np
+
+    lib = L.load()
+    o = np.ascontiguousarray(offsets, dtype=np.int64)
+    ns = int(o.shape[0]) - 1
+    n = int(o[-1])
+    dev = pos.device
+    for name, t, shape in (("pos", pos, (n, 3)), ("vel", vel, (n, 3)), ("mass", mass, (n,))):
+        _check_f64(name, t, shape, dev)
+    if eps is not None:
+        _check_f64("eps", eps, (n,), dev)
+    prec = {"fp64": L.BH_FP64, "fp32c": L.BH_FP32C}[precision]
+    cfg = L.bh_config(n, 16, prec, float(G), 0, 0, ns)
+    out = L.bh_tune_result()
+    rc = lib.bh_autotune(C.byref(cfg), C.c_void_p(torch.cuda.current_stream().cuda_stream), ns,
+                         o.ctypes.data_as(C.c_void_p), _ptr(pos), _ptr(vel), _ptr(mass),
+                         float(softening), _ptr(eps), float(theta), float(dt), int(steps),
+                         C.byref(out))
+    if rc != 0:
+        raise BHError(rc, "bh_autotune failed")
+    return int(out.leaf_size), int(out.walk_group), float(out.ms_per_step)

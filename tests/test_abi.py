@@ -33,7 +33,8 @@ def test_header_symbols_exported(lib):
 
 def test_struct_layouts_match_header(tmp_path):
     """The ctypes mirrors agree with the C compiler's layout of include/bhx.h."""
-    fields = {"bh_config": L.bh_config, "bh_tree_view": L.bh_tree_view, "bh_stats_t": L.bh_stats_t}
+    fields = {"bh_config": L.bh_config, "bh_tree_view": L.bh_tree_view, "bh_stats_t": L.bh_stats_t,
+              "bh_tune_result": L.bh_tune_result}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "bhx.h"', "int main(void){"]
     for sname, cls in fields.items():
         lines.append(f'printf("%zu\\n", sizeof({sname}));')
@@ -84,6 +85,7 @@ def test_null_context_calls(lib):
     assert lib.bh_stats(None, None) == L.BH_E_INVALID
     assert lib.bh_set_stream(None, None) == L.BH_E_INVALID
     assert lib.bh_batched_accel(None, 1, None, None, None, 0.0, None, 0.5, None, None) == L.BH_E_INVALID
+    assert lib.bh_autotune(None, None, 1, None, None, None, None, 0.0, None, 0.5, 1e-3, 1, None) == L.BH_E_INVALID
     assert lib.bh_batched_step(None, 1, None, None, None, None, 0.0, None, 0.5, 1e-3, 1, None) == L.BH_E_INVALID
     assert lib.bh_last_error(None) == b"NULL context"
     lib.bh_destroy(None)

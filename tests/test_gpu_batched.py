@@ -138,3 +138,18 @@ def test_batched_layout_errors(api):
     for bad in ([0, 50, 50, 100], [1, 50, 100], [0, 20, 40, 60, 80, 100]):
         with pytest.raises((api.BHError, ValueError)):
             ctx.batched_accel(np.array(bad), p, m, 0.5)
+
+
+def test_autotune_picks_a_candidate_and_caches(api, tmp_path, monkeypatch):
+    sc, off, pos, mass = _scenes(6, 200, 3000, 11)
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("BHX_AUTOTUNE_CACHE", str(cache))
+    P, V, M = _dev(pos), _dev(np.zeros_like(pos)), _dev(mass)
+    before = P.clone()
+    leaf, group, ms = api.autotune(off, P, V, M, theta=0.5, dt=1e-3, softening=1e-3, steps=2)
+    assert leaf in (4, 8, 16, 32) and group in (16, 32, 64) and ms > 0
+    assert torch.equal(P, before)
+    assert cache.read_text().count("\"leaf\"") == 1
+    again = api.autotune(off, P, V, M, theta=0.5, dt=1e-3, softening=1e-3, steps=2)
+    assert again == (leaf, group, ms)
+    assert cache.read_text().count("\"leaf\"") == 1
