@@ -79,10 +79,11 @@ enum {
 typedef struct {
     int64_t n_max;     /* largest n any call will pass; workspace is sized for it */
     int32_t leaf_size; /* bucket size: a cell with more bodies is split; 1..64 */
-    int32_t precision; /* BH_FP64: all FP64. BH_FP32C: FP32 pair terms on
-                          coordinates relative to the target group, FP32 partial
-                          sums flushed to FP64 accumulators; FP64 positions,
-                          opening test, moments and outputs */
+    int32_t precision; /* BH_FP64: all FP64. BH_FP32C: each pair offset is
+                          formed in FP64 and rounded once to FP32, the rest of
+                          the pair term is FP32, and FP32 partial sums are
+                          flushed to FP64 accumulators; FP64 positions, opening
+                          test, moments and outputs */
     double G;          /* gravitational constant */
     uint32_t flags;    /* BH_FLAG_* */
     int32_t walk_group; /* target bodies served by one wavefront in the tree
