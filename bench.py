@@ -153,9 +153,11 @@ def bench_batched(args, n_scenes=256, steps=10, theta=0.5, dt=1e-3, soft=1e-3):
     }
 
 
-def bench_adjoint(n=65536, nsteps=20, every=10, theta=0.5, dt=1e-3, soft=1e-3):
+def bench_adjoint(n=65536, nsteps=200, every=20, theta=0.5, dt=1e-3, soft=1e-3):
     """Differentiable rollout: forward KDK steps with checkpoints, then the
-    hand-written adjoint back to (x0, v0, m), against the forward alone."""
+    hand-written adjoint back to (x0, v0, m), against the forward alone; the
+    tree gradient against the FP64 direct-sum gradient, and FP32C against
+    FP64."""
     import torch
 
     from paper_1912_04197_amd import ics
@@ -166,7 +168,9 @@ def bench_adjoint(n=65536, nsteps=20, every=10, theta=0.5, dt=1e-3, soft=1e-3):
     xt = torch.from_numpy(ics.perturbed_target(s.pos, seed=56)).cuda()
     out = {"workload": f"uniform ball N={n} theta={theta} eps={soft} dt={dt}, {nsteps} KDK "
                        f"steps, checkpoint every {every}, loss sum |x_T - x*|^2"}
-    for prec in ("fp32c", "fp64"):
+    grads = {}
+    for label, prec, th in (("fp32c", "fp32c", theta), ("fp64", "fp64", theta),
+                            ("direct_fp64", "fp64", -1.0)):
         ctx = Context(n, leaf_size=16, precision=prec, adjoint=True)
         x0 = torch.from_numpy(s.pos).cuda().requires_grad_(True)
         v0 = torch.from_numpy(s.vel).cuda().requires_grad_(True)
@@ -174,22 +178,120 @@ def bench_adjoint(n=65536, nsteps=20, every=10, theta=0.5, dt=1e-3, soft=1e-3):
 
         def fwd():
             with torch.no_grad():
-                rollout(x0, v0, m, ctx, dt, nsteps, theta=theta, softening=soft,
+                rollout(x0, v0, m, ctx, dt, nsteps, theta=th, softening=soft,
                         checkpoint_every=every)
 
         def fwd_bwd():
-            x, _ = rollout(x0, v0, m, ctx, dt, nsteps, theta=theta, softening=soft,
+            for t in (x0, v0, m):
+                t.grad = None
+            x, _ = rollout(x0, v0, m, ctx, dt, nsteps, theta=th, softening=soft,
                            checkpoint_every=every)
             ((x - xt) ** 2).sum().backward()
 
-        fwd_bwd()
-        t_f = _sync_time(fwd)
+        torch.cuda.reset_peak_memory_stats()
         t_fb = _sync_time(fwd_bwd)
+        t_f = _sync_time(fwd)
+        peak = torch.cuda.max_memory_allocated()
+        grads[label] = [t.grad.detach().clone() for t in (x0, v0, m)]
         ctx.close()
-        out[prec] = {"forward_ms": round(t_f, 3), "forward_backward_ms": round(t_fb, 3),
-                     "backward_over_forward": round((t_fb - t_f) / t_f, 2)}
-        log(f"adjoint {prec}: forward {t_f:.1f} ms, forward+backward {t_fb:.1f} ms")
+        out[label] = {"forward_ms": round(t_f, 2), "forward_backward_ms": round(t_fb, 2),
+                      "backward_over_forward": round((t_fb - t_f) / t_f, 2),
+                      "torch_peak_mib": round(peak / 2**20, 1)}
+        log(f"adjoint {label}: forward {t_f:.1f} ms, forward+backward {t_fb:.1f} ms")
+
+    def gap(a, b):
+        return [round(float(torch.linalg.norm(x - y) / torch.linalg.norm(y)), 8)
+                for x, y in zip(a, b)]
+
+    out["rel_l2_gap_x0_v0_m"] = {
+        "tree_fp64_vs_direct_fp64": gap(grads["fp64"], grads["direct_fp64"]),
+        "tree_fp32c_vs_tree_fp64": gap(grads["fp32c"], grads["fp64"]),
+    }
     return out
+
+
+def bench_plummer(n=131072, nsteps=500, every=100, dt=1e-3, soft=1e-3, thetas=(0.3, 0.5, 0.7)):
+    """Plummer sphere, leaf 16, FP32C forces: steps/s per theta, the force error
+    against the FP64 direct sum every 100 steps, the FP32C-vs-FP64 tree gap and
+    the relative energy drift over the run."""
+    import numpy as np
+    import torch
+
+    from paper_1912_04197_amd import ics
+    from paper_1912_04197_amd.api import Context
+
+    sc = ics.plummer(n, seed=22)
+    mass = torch.from_numpy(sc.mass).cuda()
+    c32 = Context(n, leaf_size=16, precision="fp32c", graph=True)
+    c64 = Context(n, leaf_size=16, precision="fp64")
+    out = {"workload": f"Plummer N={n} a=1 M=1, leaf 16, eps={soft}, {nsteps} KDK steps of "
+                       f"dt={dt}, FP32C forces, FP64 state"}
+
+    def err(a, ref):
+        e = (torch.linalg.norm(a - ref, dim=1) / torch.linalg.norm(ref, dim=1)).cpu().numpy()
+        return {"rms": float(np.sqrt(np.mean(e ** 2))), "p99": float(np.quantile(e, 0.99))}
+
+    def energy(p, v):
+        d = c64.diagnostics(p, v, mass, softening=soft)
+        return d[0] + d[1]
+
+    for th in thetas:
+        p = torch.from_numpy(sc.pos).cuda()
+        v = torch.from_numpy(sc.vel).cuda()
+        a = c32.compute_accel(p, mass, th, softening=soft)
+        e0 = energy(p, v)
+        errs, ms = [], 0.0
+        for k in range(0, nsteps + 1, every):
+            ref = c64.compute_accel_direct(p, mass, softening=soft)
+            t32 = c32.compute_accel(p, mass, th, softening=soft)
+            t64 = c64.compute_accel(p, mass, th, softening=soft)
+            errs.append({"step": k, "tree_fp32c": err(t32, ref),
+                         "fp32c_vs_fp64_tree": err(t32, t64)})
+            if k < nsteps:
+                ms += _sync_time(lambda: c32.step_leapfrog(p, v, mass, a, dt, every, theta=th,
+                                                           softening=soft, sync=False))
+        e1 = energy(p, v)
+        out[f"theta_{th}"] = {"steps_per_s": round(nsteps / (ms * 1e-3), 1),
+                              "ms_per_step": round(ms / nsteps, 4),
+                              "energy_rel_drift": float((e1 - e0) / abs(e0)),
+                              "force_error": errs}
+        log(f"plummer theta {th}: {ms / nsteps:.3f} ms/step, dE/E {(e1 - e0) / abs(e0):.2e}")
+    c32.close()
+    c64.close()
+    return out
+
+
+def bench_crossover(ns=(1000, 4000, 16000, 64000), thetas=(0.25, 0.5, 0.75), soft=1e-3):
+    """The paper's timing experiment on this GPU: one FP64 force evaluation
+    (tree rebuilt) against the FP64 direct sum on uniform random cubes."""
+    import torch
+
+    from paper_1912_04197_amd import ics
+    from paper_1912_04197_amd.api import Context
+
+    rows = []
+    for n in ns:
+        sc = ics.uniform_cube(n, seed=12)
+        p = torch.from_numpy(sc.pos).cuda()
+        m = torch.from_numpy(sc.mass).cuda()
+        ctx = Context(n, leaf_size=1, precision="fp64")
+        ctx.compute_accel_direct(p, m, softening=soft)
+        reps = 5
+        t_dir = _sync_time(lambda: [ctx.compute_accel_direct(p, m, softening=soft, sync=False)
+                                    for _ in range(reps)]) / reps
+        row = {"n": n, "direct_ms": round(t_dir, 4)}
+        for th in thetas:
+            ctx.compute_accel(p, m, th, softening=soft)
+            t = _sync_time(lambda: [ctx.compute_accel(p, m, th, softening=soft, sync=False)
+                                    for _ in range(reps)]) / reps
+            row[f"tree_ms_theta_{th}"] = round(t, 4)
+            row[f"speedup_theta_{th}"] = round(t_dir / t, 2)
+        ctx.close()
+        rows.append(row)
+        log(f"crossover n={n}: {row}")
+    return {"workload": "uniform random cube, leaf 1 (the paper's one-body leaves), eps "
+                        f"{soft}, FP64, one force evaluation with the tree rebuilt",
+            "rows": rows}
 
 
 def main():
@@ -372,6 +474,8 @@ def main():
         c64.close()
         result["batched"] = bench_batched(args)
         result["adjoint"] = bench_adjoint()
+        result["plummer"] = bench_plummer()
+        result["crossover"] = bench_crossover()
 
     if not args.no_cpu:
         import oracle

@@ -14,11 +14,11 @@
 // Tree VJP, on the GPU:
 //   1. the same build as the forward evaluation (deterministic, so the same
 //      tree and decisions);
-//   2. a walk with the forward walk's traversal (one wave per 64 Morton-
-//      consecutive targets, per-lane masks, batched rounds and staged
-//      items); per interaction each lane adds its target-side term to
-//      registers, and the wave sums the source-side terms and adds them with
-//      one FP64 atomic per (group, source) into the body or node adjoints;
+//   2. a walk with the forward walk's traversal and decisions (one wave per
+//      64 Morton-consecutive targets, per-lane masks, batched rounds, staged
+//      items split into dense items and pairs); each target's terms are
+//      summed in registers and LDS, each source's terms are summed over the
+//      group and added with FP64 atomics into the body or node adjoints;
 //   3. node adjoints become per-node coefficients (A = gX / m_N,
 //      E = ge2 / m_N, C = gm - X.A - <eps^2> E), summed top-down over each
 //      body's ancestors, one launch per level;
@@ -68,11 +68,6 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v)
     }
     return v;
 }
-__device__ inline double wave_sum(double v)
-{
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
 __device__ inline bool accept_node(double cx, double cy, double cz, double bx, double by,
                                    double bz, double s2, double th2)
 {
@@ -82,7 +77,39 @@ __device__ inline bool accept_node(double cx, double cy, double cz, double bx, d
     return s2 < th2 * D2;
 }
 
+// Lane exchanges inside a row of 16 lanes (DPP): quad_perm [1,0,3,2] is
+// lane ^ 1, quad_perm [2,3,0,1] is lane ^ 2, row_ror:4 and row_ror:8 rotate
+// the row by 4 and 8 lanes.
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppRor4 = 0x124, kDppRor8 = 0x128;
+template <int CTRL>
+__device__ inline double dpp(double v)
+{
+    const uint64_t u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// The group's bounding box decides a node for every body when the opening
+// test comes out the same anywhere in the box by this relative margin (the
+// per-body test's own rounding is below 1e-15).
+constexpr double kMacMargin = 1e-12;
+constexpr int kSparse = 16;    // items reaching at most this many bodies go to pair mode
+constexpr int kPairCap = 448;  // pairs per batch
+
 // badj: per sorted body {gX x, y, z, gm}; nadj: per node {gX x, y, z, gm, ge2}.
+//
+// The traversal and the opening decisions are those of the forward walk. A
+// staged batch is split like the forward walk's: a dense item (reaching
+// more than kSparse of the group's bodies) is swept by the lanes of its
+// bodies, eight items at a time; each lane takes the eight in an order set by
+// its lane bits so that three halving exchanges (lane ^ 1, ^ 2, ^ 32) leave
+// lane L with one item's source-side terms summed over eight lanes, and three
+// more (rotations by 4 and 8 inside a row, lane ^ 16) complete the sum over
+// the group; then eight lanes add the eight sums to the item's adjoints with
+// FP64 atomics. A sparse item becomes (item, body) pairs, one per lane, whose
+// target-side terms go to per-body and whose source-side terms go to per-item
+// FP64 sums in LDS, flushed to the adjoints once per batch.
 template <bool PEPS>
 __global__ __launch_bounds__(64) void k_vjp_walk(
     const Body *__restrict__ body, const double *__restrict__ beps2,
@@ -92,8 +119,9 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
     double eps0sq, double G, const double *__restrict__ lambda, double *__restrict__ gt,
     double *__restrict__ badj, double *__restrict__ nadj)
 {
+    constexpr int NC = PEPS ? 5 : 4;  // source-side components: gX (3), gm, g<eps^2>
     __shared__ int32_t st_c0[kStack];
-    __shared__ int32_t st_n[kStack];
+    __shared__ uint8_t st_n[kStack];
     __shared__ uint64_t st_mask[kStack];
     __shared__ int32_t dq_a[kRing];
     __shared__ int32_t dq_n[kRing];
@@ -105,12 +133,18 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
             PopCom pc[kPop];
             PopData pd[kPop];
         } pop;
-        ItemV items[kBatch];
+        struct {
+            ItemV items[kBatch];     // dense items first, then the sparse ones
+            uint16_t rec[kPairCap];  // pair: item slot << 6 | body
+        } ev;
     };
     __shared__ Shared sh;
+    __shared__ double tacc[3 * 64];      // pair target-side sums per body
+    __shared__ double sacc[5 * kBatch];  // pair source-side sums per staged item
     PopCom *const pc = sh.pop.pc;
     PopData *const pd = sh.pop.pd;
-    ItemV *const items = sh.items;
+    ItemV *const items = sh.ev.items;
+    uint16_t *const rec = sh.ev.rec;
 
     const int grp = (int)(blockIdx.x & 7u) * per_xcd + (int)(blockIdx.x >> 3);
     if (grp >= ngroups) return;
@@ -129,6 +163,20 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
     }
     const uint64_t active = __ballot(valid);
     if (lane < kLevels) s2tab[lane] = box[0].s2[lane];
+    double glo_x = valid ? me.x : __builtin_huge_val(), ghi_x = valid ? me.x : -__builtin_huge_val();
+    double glo_y = valid ? me.y : __builtin_huge_val(), ghi_y = valid ? me.y : -__builtin_huge_val();
+    double glo_z = valid ? me.z : __builtin_huge_val(), ghi_z = valid ? me.z : -__builtin_huge_val();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        glo_x = fmin(glo_x, __shfl_xor(glo_x, o));
+        ghi_x = fmax(ghi_x, __shfl_xor(ghi_x, o));
+        glo_y = fmin(glo_y, __shfl_xor(glo_y, o));
+        ghi_y = fmax(ghi_y, __shfl_xor(ghi_y, o));
+        glo_z = fmin(glo_z, __shfl_xor(glo_z, o));
+        ghi_z = fmax(ghi_z, __shfl_xor(ghi_z, o));
+    }
+    // this lane's order of the eight items of a dense step
+    const int perm = ((lane & 1) << 2) | (lane & 2) | (lane >> 5);
 
     double gx = 0.0, gy = 0.0, gz = 0.0;  // target-side gradient of this lane's body
     int sp = 1, dq_head = 0, dq_tail = 0;
@@ -138,9 +186,52 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
         st_n[0] = 1;
         st_mask[0] = active;
     }
+    for (int i = lane; i < 3 * 64; i += 64) tacc[i] = 0.0;
     __syncthreads();
 
+    // One softened term of source (x, y, z, m, e2) on a target at (bx, by, bz)
+    // with softening eb and upstream (ux, uy, uz): the target-side gradient is
+    // minus the first three source-side components.
+    auto term = [&](const ItemV &it, double bx, double by, double bz, double eb, double ux,
+                    double uy, double uz, bool on, double out[5]) {
+        const double dx = it.x - bx, dy = it.y - by, dz = it.z - bz;
+        const double e2 = PEPS ? 0.5 * (eb + it.e2) : eps0sq;
+        const double r2 = dx * dx + dy * dy + dz * dz + e2;
+        out[0] = out[1] = out[2] = out[3] = out[4] = 0.0;
+        if (on && r2 > 0.0) {
+            const double r = sqrt(r2);
+            const double inv3 = 1.0 / (r2 * r);
+            const double inv5 = inv3 / r2;
+            const double ld = ux * dx + uy * dy + uz * dz;
+            const double gms = G * it.m;
+            out[0] = gms * (ux * inv3 - 3.0 * dx * ld * inv5);
+            out[1] = gms * (uy * inv3 - 3.0 * dy * ld * inv5);
+            out[2] = gms * (uz * inv3 - 3.0 * dz * ld * inv5);
+            out[3] = G * ld * inv3;
+            out[4] = -1.5 * gms * ld * inv5;
+        }
+    };
+    // adds a source-side sum to the item's adjoints (e2 = (eps_B^2 + <eps^2>_N) / 2)
+    auto flush = [&](int32_t src, const double v[5]) {
+        if (src >= 0) {
+            double *b = badj + 4 * (int64_t)src;
+            unsafeAtomicAdd(b, v[0]);
+            unsafeAtomicAdd(b + 1, v[1]);
+            unsafeAtomicAdd(b + 2, v[2]);
+            unsafeAtomicAdd(b + 3, v[3]);
+        } else {
+            double *b = nadj + 5 * (int64_t)(~src);
+            unsafeAtomicAdd(b, v[0]);
+            unsafeAtomicAdd(b + 1, v[1]);
+            unsafeAtomicAdd(b + 2, v[2]);
+            unsafeAtomicAdd(b + 3, v[3]);
+            if (PEPS) unsafeAtomicAdd(b + 4, 0.5 * v[4]);
+        }
+    };
+
     auto evaluate = [&](int c) {
+        uint64_t mk = 0;
+        ItemV ld_it{0.0, 0.0, 0.0, 0.0, 0.0, 0ull, 0, 0, 0};
         if (lane < c) {
             const uint32_t q = consumed + (uint32_t)lane;
             int lo = 0, hi = dq_tail - dq_head - 1;
@@ -153,70 +244,121 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
             }
             const int d = (dq_head + lo) % kRing;
             const int32_t a = dq_a[d];
-            uint64_t mk = dq_mask[d];
-            ItemV it;
+            mk = dq_mask[d];
             if (a >= 0) {
                 const int32_t src = a + (int32_t)(q - dq_at[d]);
                 const int64_t rel = (int64_t)src - g0;
                 if (rel >= 0 && rel < 64) mk &= ~(1ull << rel);
                 const Body b = body[src];
-                it = ItemV{b.x, b.y, b.z, b.m, PEPS ? beps2[src] : 0.0, mk, src, 0, 0};
+                ld_it = ItemV{b.x, b.y, b.z, b.m, PEPS ? beps2[src] : 0.0, mk, src, 0, 0};
             } else {
                 const NodeMom nm = nmom[~a];
-                it = ItemV{nm.x, nm.y, nm.z, nm.m, PEPS ? neps2[~a] : 0.0, mk, a, 0, 0};
+                ld_it = ItemV{nm.x, nm.y, nm.z, nm.m, PEPS ? neps2[~a] : 0.0, mk, a, 0, 0};
             }
-            items[lane] = it;
+        }
+        const int pk = __popcll(mk);
+        const bool sparse = lane < c && pk <= kSparse;
+        const uint32_t pv = sparse ? (uint32_t)pk : 0u;
+        const uint32_t pend = wave_incl_scan(pv);
+        const bool fits = sparse && pend <= (uint32_t)kPairCap;
+        const bool dense = lane < c && !fits;
+        const uint64_t db = __ballot(dense);
+        const uint64_t fb = __ballot(fits && pk > 0);
+        const int nd = __popcll(db);
+        const int ns = __popcll(fb);
+        const int np = fb ? __builtin_amdgcn_readlane((int)pend, 63 - __builtin_clzll(fb)) : 0;
+        if (dense || (fits && pk > 0)) {
+            const int slot = dense ? (int)lanes_below(db) : nd + (int)lanes_below(fb);
+            items[slot] = ld_it;
+            if (fits) {
+#pragma unroll
+                for (int q = 0; q < 5; q++) sacc[5 * slot + q] = 0.0;
+                uint64_t bits = mk;
+                uint32_t at = pend - pv;
+                while (bits) {
+                    rec[at++] = (uint16_t)(slot << 6 | __builtin_ctzll(bits));
+                    bits &= bits - 1;
+                }
+            }
         }
         __syncthreads();
+
+        // dense items, eight per step
 #pragma unroll 1
-        for (int j = 0; j < c; j++) {
-            const ItemV it = items[j];
-            if (it.mask == 0) continue;  // uniform: nobody takes this item
-            const bool on = (it.mask >> lane) & 1ull;
-            const double dx = it.x - me.x, dy = it.y - me.y, dz = it.z - me.z;
-            const double e2 = PEPS ? 0.5 * (eb2 + it.e2) : eps0sq;
-            const double r2 = dx * dx + dy * dy + dz * dz + e2;
-            double tx = 0.0, ty = 0.0, tz = 0.0, tm = 0.0, te = 0.0;
-            if (on && r2 > 0.0) {
-                const double r = sqrt(r2);
-                const double inv3 = 1.0 / (r2 * r);
-                const double inv5 = inv3 / r2;
-                const double ld = lx * dx + ly * dy + lz * dz;
-                const double gms = G * it.m;
-                tx = gms * (lx * inv3 - 3.0 * dx * ld * inv5);
-                ty = gms * (ly * inv3 - 3.0 * dy * ld * inv5);
-                tz = gms * (lz * inv3 - 3.0 * dz * ld * inv5);
-                tm = G * ld * inv3;
-                te = -1.5 * gms * ld * inv5;
+        for (int j0 = 0; j0 < nd; j0 += 8) {
+            double v[8][NC];
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                const int j = j0 + (t ^ perm);
+                const ItemV it = items[j < nd ? j : j0];
+                const bool on = j < nd && ((it.mask >> lane) & 1ull);
+                double o[5];
+                term(it, me.x, me.y, me.z, eb2, lx, ly, lz, on, o);
+                gx -= o[0];
+                gy -= o[1];
+                gz -= o[2];
+#pragma unroll
+                for (int q = 0; q < NC; q++) v[t][q] = o[q];
             }
-            gx -= tx;
-            gy -= ty;
-            gz -= tz;
-            tx = wave_sum(tx);
-            ty = wave_sum(ty);
-            tz = wave_sum(tz);
-            tm = wave_sum(tm);
-            if (it.src >= 0) {
-                if (lane == 0) {
-                    double *b = badj + 4 * (int64_t)it.src;
-                    unsafeAtomicAdd(b, tx);
-                    unsafeAtomicAdd(b + 1, ty);
-                    unsafeAtomicAdd(b + 2, tz);
-                    unsafeAtomicAdd(b + 3, tm);
-                }
-            } else {
-                if (PEPS) te = wave_sum(te);
-                if (lane == 0) {
-                    double *b = nadj + 5 * (int64_t)(~it.src);
-                    unsafeAtomicAdd(b, tx);
-                    unsafeAtomicAdd(b + 1, ty);
-                    unsafeAtomicAdd(b + 2, tz);
-                    unsafeAtomicAdd(b + 3, tm);
-                    // e2 = (eps_B^2 + <eps^2>_N) / 2
-                    if (PEPS) unsafeAtomicAdd(b + 4, 0.5 * te);
-                }
+#pragma unroll
+            for (int t = 0; t < 4; t++)
+#pragma unroll
+                for (int q = 0; q < NC; q++) v[t][q] += dpp<kDppXor1>(v[t + 4][q]);
+#pragma unroll
+            for (int t = 0; t < 2; t++)
+#pragma unroll
+                for (int q = 0; q < NC; q++) v[t][q] += dpp<kDppXor2>(v[t + 2][q]);
+#pragma unroll
+            for (int q = 0; q < NC; q++) {
+                double w = v[0][q] + __shfl_xor(v[1][q], 32);
+                w += dpp<kDppRor4>(w);
+                w += dpp<kDppRor8>(w);
+                w += __shfl_xor(w, 16);
+                v[0][q] = w;
+            }
+            // lanes 0-3 and 32-35 hold the sums of items j0 + perm
+            const int j = j0 + perm;
+            if ((lane & 28) == 0 && j < nd) {
+                double o[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int q = 0; q < NC; q++) o[q] = v[0][q];
+                flush(items[j].src, o);
             }
         }
+
+        // sparse items as pairs
+#pragma unroll 1
+        for (int i0 = 0; i0 < np; i0 += 64) {
+            const int i = i0 + lane;
+            const bool on = i < np;
+            const uint32_t r = rec[on ? i : i0];
+            const int k = (int)(r >> 6), b = (int)(r & 63u);
+            const double bx = __shfl(me.x, b), by = __shfl(me.y, b), bz = __shfl(me.z, b);
+            const double eb = PEPS ? __shfl(eb2, b) : 0.0;
+            const double ux = __shfl(lx, b), uy = __shfl(ly, b), uz = __shfl(lz, b);
+            const ItemV it = items[k];
+            double o[5];
+            term(it, bx, by, bz, eb, ux, uy, uz, on, o);
+            if (on) {
+#pragma unroll
+                for (int q = 0; q < 3; q++)
+                    __hip_atomic_fetch_add(&tacc[3 * b + q], -o[q], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+                for (int q = 0; q < NC; q++)
+                    __hip_atomic_fetch_add(&sacc[5 * k + q], o[q], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+        __syncthreads();
+        if (lane < ns) {
+            const int k = nd + lane;
+            double o[5];
+#pragma unroll
+            for (int q = 0; q < 5; q++) o[q] = sacc[5 * k + q];
+            flush(items[k].src, o);
+        }
+
         consumed += (uint32_t)c;
         while (dq_head < dq_tail) {
             const int d = dq_head % kRing;
@@ -258,9 +400,32 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
         }
         sp = base;
         __syncthreads();
+        // opening tests: the group-box bound first, then every body for the
+        // nodes it leaves open (as in the forward walk)
         uint64_t accepted = 0;
+        bool mixed = false;
+        if (lane < nv) {
+            const PopCom q = pc[lane];
+            if (q.s2 < __builtin_huge_val()) {
+                const double ex = fmax(0.0, fmax(glo_x - q.x, q.x - ghi_x));
+                const double ey = fmax(0.0, fmax(glo_y - q.y, q.y - ghi_y));
+                const double ez = fmax(0.0, fmax(glo_z - q.z, q.z - ghi_z));
+                const double fx = fmax(fabs(q.x - glo_x), fabs(q.x - ghi_x));
+                const double fy = fmax(fabs(q.y - glo_y), fabs(q.y - ghi_y));
+                const double fz = fmax(fabs(q.z - glo_z), fabs(q.z - ghi_z));
+                const double dmin2 = ex * ex + ey * ey + ez * ez;
+                const double dmax2 = fx * fx + fy * fy + fz * fz;
+                if (q.s2 < th2 * dmin2 * (1.0 - kMacMargin))
+                    accepted = ~0ull;
+                else if (!(q.s2 > th2 * dmax2 * (1.0 + kMacMargin)))
+                    mixed = true;
+            }
+        }
+        uint64_t mb = __ballot(mixed);
 #pragma unroll 1
-        for (int p = 0; p < nv; p++) {
+        while (mb) {
+            const int p = __builtin_ctzll(mb);
+            mb &= mb - 1;
             const PopCom q = pc[p];
             const uint64_t bal = __ballot(accept_node(q.x, q.y, q.z, me.x, me.y, me.z, q.s2, th2));
             if (lane == p) accepted = bal;
@@ -276,7 +441,7 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
         if (O != 0) {
             const int e = sp + (int)lanes_below(pushb);
             st_c0[e] = my.child0;
-            st_n[e] = my.nch;
+            st_n[e] = (uint8_t)my.nch;
             st_mask[e] = O;
         }
         sp += __popcll(pushb);
@@ -299,9 +464,9 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
     while (queued != consumed) evaluate((int)min(queued - consumed, (uint32_t)kBatch));
 
     if (valid) {
-        gt[3 * s] = gx;
-        gt[3 * s + 1] = gy;
-        gt[3 * s + 2] = gz;
+        gt[3 * s] = gx + tacc[3 * lane];
+        gt[3 * s + 1] = gy + tacc[3 * lane + 1];
+        gt[3 * s + 2] = gz + tacc[3 * lane + 2];
     }
 }
 

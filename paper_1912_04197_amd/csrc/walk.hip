@@ -15,23 +15,31 @@
 //
 // Traversal rounds: a stack entry is the child range of one opened node with
 // its body mask. A round pops up to 8 ranges (up to 64 nodes); the lanes load
-// those nodes in parallel (one memory latency per round), test them against
-// the group (64 / GB nodes per instruction), and then do the bookkeeping for
-// all popped nodes at once: lane p handles popped node p, and prefix sums over
-// the lanes place the pushed child ranges and the queued interactions. A round
-// pops only as many ranges as can be expanded while keeping room for a
-// depth-first descent, so the stack cannot overflow.
+// those nodes in parallel (one memory latency per round). Lane p bounds the
+// distance from popped node p to the group's bounding box; where the opening
+// test comes out the same for the whole box (by a margin far above rounding)
+// that is every body's decision, and only the remaining "mixed" nodes are
+// tested body by body (64 / GB nodes per instruction). Then the bookkeeping
+// for all popped nodes runs at once: lane p handles popped node p, and prefix
+// sums over the lanes place the pushed child ranges and the queued
+// interactions. A round pops only as many ranges as can be expanded while
+// keeping room for a depth-first descent, so the stack cannot overflow.
 //
 // Evaluation: the interaction queue holds descriptors (a leaf's body range or
 // one accepted node, with a body mask). Whenever 64 items are queued, lane k
-// expands item k (binary search over the descriptors' item offsets), loads it
-// and stages it in LDS; then the lanes of each body sweep the staged items,
-// each taking every (64 / GB)-th one. In FP32C mode each pair offset
+// expands item k (binary search over the descriptors' item offsets) and loads
+// it. An item that reaches more than GB / 4 bodies of the group is dense: the
+// dense items are staged in LDS and the lanes of each body sweep them, each
+// taking every (64 / GB)-th one. A sparse item becomes (item, body) pairs, one
+// pair per lane, whose terms are added into per-body FP64 sums in LDS; most
+// leaf bodies near the group's edge reach only a few of its bodies, and a
+// sweep would leave most lanes idle on them. In FP32C mode each pair offset
 // x_j - x_B is formed in FP64 and rounded once to FP32 (close pairs keep full
 // FP32 precision whatever the group's extent), the rest of the pair term is
-// FP32, and FP32 partial sums over at most 16 items per lane are added into
-// FP64 accumulators. The per-lane FP64 sums of a body are added at the end in
-// a fixed order, so results are deterministic.
+// FP32, and in the sweep FP32 partial sums over at most 16 items per lane are
+// added into FP64 accumulators. The per-lane FP64 sums of a body and its pair
+// sums are added at the end in a fixed order; the pair sums are LDS atomics of
+// a single wave, applied in a fixed order, so results are deterministic.
 #include <cstddef>
 #include <type_traits>
 
@@ -47,6 +55,11 @@ constexpr int kPop = 8 * kRanges;
 constexpr int kRing = 128;     // interaction descriptors: <= 64 left over + 64 new
 constexpr int kBatch = 64;     // items staged per evaluation batch
 constexpr int kFlush = 16;     // FP32 partial sums span at most this many items per lane
+constexpr int kPairCap = 448;  // body pairs evaluated one per lane in one batch
+// Relative margin of the group-box opening test. The per-body test's D^2
+// and theta^2 D^2 carry a relative rounding error below 1e-15, so a box
+// bound that clears the threshold by this margin decides every body alike.
+constexpr double kMacMargin = 1e-12;
 
 struct alignas(16) ItemF {  // FP32C staged source
     double x, y, z;
@@ -114,8 +127,13 @@ __global__ __launch_bounds__(64) void k_walk(
     constexpr uint64_t kBodyMask = GB == 64 ? ~0ull : ((1ull << GB) - 1ull);
     using Item = typename std::conditional<PREC == BH_FP64, ItemD, ItemF>::type;
 
+    // Items that reach at most kSparse bodies of the group are evaluated as
+    // (item, body) pairs, one pair per lane, into per-body FP64 sums in LDS.
+    constexpr int kSparse = GB / 4;
+    constexpr int kSweepUnroll = GB == 64 ? 2 : 1;
+
     __shared__ int32_t st_c0[kStack];
-    __shared__ int32_t st_n[kStack];
+    __shared__ uint8_t st_n[kStack];
     __shared__ uint64_t st_mask[kStack];
     __shared__ int32_t dq_a[kRing];      // leaf: first body; node: ~node
     __shared__ int32_t dq_n[kRing];      // items in the descriptor
@@ -129,12 +147,19 @@ __global__ __launch_bounds__(64) void k_walk(
             PopCom pc[kPop];
             PopData pd[kPop];
         } pop;
-        Item items[kBatch];
+        struct {
+            Item items[kBatch];      // dense items first, then the sparse ones
+            uint16_t rec[kPairCap];  // pair: item slot << 6 | body
+        } ev;
     };
     __shared__ Shared sh;
+    __shared__ double pacc[3 * GB];  // pair sums per body: x, y, z
+    __shared__ double pphi[PHI ? GB : 1];
+    __shared__ int32_t pcnt[CNT ? 2 * GB : 1];
     PopCom *const pc = sh.pop.pc;
     PopData *const pd = sh.pop.pd;
-    Item *const items = sh.items;
+    Item *const items = sh.ev.items;
+    uint16_t *const rec = sh.ev.rec;
 
     // Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous
     // (so spatially compact) range of groups to share its L2.
@@ -158,6 +183,19 @@ __global__ __launch_bounds__(64) void k_walk(
     const Body me = body[valid ? s : g0];
     const double eb2 = PEPS ? beps2[valid ? s : g0] : 0.0;
     const uint64_t active = __ballot(valid) & kBodyMask;
+    // the group's bounding box (exact: min and max of its bodies' coordinates)
+    double glo_x = valid ? me.x : __builtin_huge_val(), ghi_x = valid ? me.x : -__builtin_huge_val();
+    double glo_y = valid ? me.y : __builtin_huge_val(), ghi_y = valid ? me.y : -__builtin_huge_val();
+    double glo_z = valid ? me.z : __builtin_huge_val(), ghi_z = valid ? me.z : -__builtin_huge_val();
+#pragma unroll
+    for (int o = 1; o < GB; o <<= 1) {
+        glo_x = fmin(glo_x, __shfl_xor(glo_x, o));
+        ghi_x = fmax(ghi_x, __shfl_xor(ghi_x, o));
+        glo_y = fmin(glo_y, __shfl_xor(glo_y, o));
+        ghi_y = fmax(ghi_y, __shfl_xor(ghi_y, o));
+        glo_z = fmin(glo_z, __shfl_xor(glo_z, o));
+        ghi_z = fmax(ghi_z, __shfl_xor(ghi_z, o));
+    }
     if (lane < kLevels) s2tab[lane] = box[scene].s2[lane];
 
     const float e2hB = (float)(0.5 * eb2);
@@ -176,10 +214,20 @@ __global__ __launch_bounds__(64) void k_walk(
         st_n[0] = 1;
         st_mask[0] = active;
     }
+    for (int i = lane; i < 3 * GB; i += 64) pacc[i] = 0.0;
+    if (PHI && lane < GB) pphi[lane] = 0.0;
+    if (CNT)
+        for (int i = lane; i < 2 * GB; i += 64) pcnt[i] = 0;
     __syncthreads();
 
-    // Stages the next c queued items and sweeps them.
+    // Stages the next c queued items and evaluates them: the dense ones by
+    // a sweep of the lanes of each body, the sparse ones as pairs.
     auto evaluate = [&](int c) {
+        // Load item `lane` and its body mask; the split below decides where
+        // in LDS it goes.
+        uint64_t mk = 0;
+        int32_t src = 0;
+        double x = 0.0, y = 0.0, z = 0.0, m = 0.0, e2 = 0.0;
         if (lane < c) {
             const uint32_t q = consumed + (uint32_t)lane;
             int lo = 0, hi = dq_tail - dq_head - 1;
@@ -192,9 +240,7 @@ __global__ __launch_bounds__(64) void k_walk(
             }
             const int d = (dq_head + lo) % kRing;
             const int32_t a = dq_a[d];
-            uint64_t mk = dq_mask[d];
-            int32_t src;
-            double x, y, z, m, e2;
+            mk = dq_mask[d];
             if (a >= 0) {
                 src = a + (int32_t)(q - dq_at[d]);
                 const int64_t rel = (int64_t)src - g0;
@@ -208,20 +254,43 @@ __global__ __launch_bounds__(64) void k_walk(
                 x = nm.x, y = nm.y, z = nm.z, m = nm.m;
                 e2 = PEPS ? neps2[~a] : 0.0;
             }
+        }
+        // Split the batch: an item reaching at most kSparse bodies becomes
+        // that many (item, body) pairs while they fit in the pair list; the
+        // others are dense and go to slots 0..nd-1, the sparse ones after.
+        const int pk = __popcll(mk);
+        const bool sparse = lane < c && pk <= kSparse;
+        const uint32_t pv = sparse ? (uint32_t)pk : 0u;
+        const uint32_t pend = wave_incl_scan(pv);
+        const bool fits = sparse && pend <= (uint32_t)kPairCap;
+        const bool dense = lane < c && !fits;
+        const uint64_t db = __ballot(dense);
+        const uint64_t fb = __ballot(fits && pk > 0);
+        const int nd = __popcll(db);
+        const int np = fb ? __builtin_amdgcn_readlane((int)pend, 63 - __builtin_clzll(fb)) : 0;
+        if (dense || (fits && pk > 0)) {
+            const int slot = dense ? (int)lanes_below(db) : nd + (int)lanes_below(fb);
             if constexpr (PREC == BH_FP64) {
-                items[lane] = ItemD{x, y, z, m, e2, mk, src, 0, 0};
+                items[slot] = ItemD{x, y, z, m, e2, mk, src, 0, 0};
             } else {
-                items[lane] = ItemF{x,   y, z, (float)m, (float)(0.5 * e2), (uint32_t)mk,
+                items[slot] = ItemF{x,   y, z, (float)m, (float)(0.5 * e2), (uint32_t)mk,
                                     (uint32_t)(mk >> 32), src, 0};
+            }
+            if (fits) {
+                uint64_t bits = mk;
+                uint32_t at = pend - pv;
+                while (bits) {
+                    rec[at++] = (uint16_t)(slot << 6 | __builtin_ctzll(bits));
+                    bits &= bits - 1;
+                }
             }
         }
         __syncthreads();
         if constexpr (PREC == BH_FP64) {
 #pragma unroll 1
-            for (int jj = 0; jj < c; jj += LPB) {
-                const int j = jj + sub;
-                const ItemD it = items[j < c ? j : jj];
-                const bool on = j < c && ((it.mask >> bq) & 1ull);
+            for (int jj = 0; jj < nd; jj += LPB) {
+                const ItemD it = items[jj + sub < nd ? jj + sub : jj];
+                const bool on = jj + sub < nd && ((it.mask >> bq) & 1ull);
                 const double dx = it.x - me.x, dy = it.y - me.y, dz = it.z - me.z;
                 const double e2 = PEPS ? 0.5 * (eb2 + it.e2) : eps0sq;
                 const double r2 = dx * dx + dy * dy + dz * dz + e2;
@@ -242,11 +311,11 @@ __global__ __launch_bounds__(64) void k_walk(
             }
         } else {
 #pragma unroll 1
-            for (int j0 = 0; j0 < c; j0 += kFlush * LPB) {
-                const int jn = min(c, j0 + kFlush * LPB);
+            for (int j0 = 0; j0 < nd; j0 += kFlush * LPB) {
+                const int jn = min(nd, j0 + kFlush * LPB);
                 float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
                 // jj is the same on every lane; lane share `sub` takes item jj + sub
-#pragma unroll 2
+#pragma unroll kSweepUnroll
                 for (int jj = j0; jj < jn; jj += LPB) {
                     const int j = jj + sub;
                     const ItemF it = items[j < jn ? j : jj];
@@ -280,6 +349,58 @@ __global__ __launch_bounds__(64) void k_walk(
                 ay += (double)fy;
                 az += (double)fz;
                 if (PHI) ph += (double)fp;
+            }
+        }
+        // Pairs: lane i takes pair i of the list; its body's coordinates come
+        // from that body's lane. Each pair term goes into the body's FP64 sums.
+#pragma unroll 1
+        for (int i0 = 0; i0 < np; i0 += 64) {
+            const int i = i0 + lane;
+            const bool on = i < np;
+            const uint32_t r = rec[on ? i : i0];
+            const int k = (int)(r >> 6), b = (int)(r & 63u);
+            const double tx = __shfl(me.x, b), ty = __shfl(me.y, b), tz = __shfl(me.z, b);
+            double fx = 0.0, fy = 0.0, fz = 0.0, fp = 0.0;
+            bool src_node;
+            if constexpr (PREC == BH_FP64) {
+                const double te = __shfl(eb2, b);
+                const ItemD it = items[k];
+                src_node = it.src < 0;
+                const double dx = it.x - tx, dy = it.y - ty, dz = it.z - tz;
+                const double e2 = PEPS ? 0.5 * (te + it.e2) : eps0sq;
+                const double r2 = dx * dx + dy * dy + dz * dz + e2;
+                if (on && r2 > 0.0) {
+                    const double rr = sqrt(r2);
+                    const double inv3 = 1.0 / (r2 * rr);
+                    fx = it.m * dx * inv3;
+                    fy = it.m * dy * inv3;
+                    fz = it.m * dz * inv3;
+                    if (PHI) fp = -it.m / rr;
+                }
+            } else {
+                const float te = __shfl(e2hB, b);
+                const ItemF it = items[k];
+                src_node = it.src < 0;
+                const float dx = (float)(it.x - tx), dy = (float)(it.y - ty), dz = (float)(it.z - tz);
+                const float e2 = PEPS ? it.e2h + te : eps0f;
+                const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, e2)));
+                const float rinv = (on && r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;
+                const float mr = it.m * rinv;
+                const float mr3 = mr * rinv * rinv;
+                fx = (double)(mr3 * dx);
+                fy = (double)(mr3 * dy);
+                fz = (double)(mr3 * dz);
+                if (PHI) fp = -(double)mr;
+            }
+            if (on) {
+                __hip_atomic_fetch_add(&pacc[3 * b], fx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(&pacc[3 * b + 1], fy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                __hip_atomic_fetch_add(&pacc[3 * b + 2], fz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (PHI)
+                    __hip_atomic_fetch_add(&pphi[b], fp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (CNT)
+                    __hip_atomic_fetch_add(&pcnt[2 * b + (src_node ? 0 : 1)], 1, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
         consumed += (uint32_t)c;
@@ -328,19 +449,52 @@ __global__ __launch_bounds__(64) void k_walk(
         sp = base;
         __syncthreads();
 
-        // Opening tests: 64 / GB popped nodes per step, one per share of
-        // lanes. The group's GB-bit result for popped node p goes to lane p.
+        // Opening tests. Lane p first bounds popped node p's distance to the
+        // group's bounding box: when the test comes out the same for every
+        // point of the box, with a margin far above the rounding of the
+        // per-body test, that is the decision of every body. The other
+        // ("mixed") internal nodes are tested by every body, 64 / GB nodes per
+        // step, one per share of lanes; the group's GB-bit result for popped
+        // node p goes to lane p.
         uint64_t accepted = 0;
+        bool mixed = false;
+        if (lane < nv) {
+            const PopCom q = pc[lane];
+            if (q.s2 < __builtin_huge_val()) {
+                const double ex = fmax(0.0, fmax(glo_x - q.x, q.x - ghi_x));
+                const double ey = fmax(0.0, fmax(glo_y - q.y, q.y - ghi_y));
+                const double ez = fmax(0.0, fmax(glo_z - q.z, q.z - ghi_z));
+                const double fx = fmax(fabs(q.x - glo_x), fabs(q.x - ghi_x));
+                const double fy = fmax(fabs(q.y - glo_y), fabs(q.y - ghi_y));
+                const double fz = fmax(fabs(q.z - glo_z), fabs(q.z - ghi_z));
+                const double dmin2 = ex * ex + ey * ey + ez * ez;
+                const double dmax2 = fx * fx + fy * fy + fz * fz;
+                if (q.s2 < th2 * dmin2 * (1.0 - kMacMargin))
+                    accepted = kBodyMask;
+                else if (!(q.s2 > th2 * dmax2 * (1.0 + kMacMargin)))
+                    mixed = true;
+            }
+        }
+        uint64_t mb = __ballot(mixed);
 #pragma unroll 1
-        for (int p0 = 0; p0 < nv; p0 += LPB) {
-            const int p = p0 + sub;
-            const PopCom q = pc[p < nv ? p : 0];
-            const bool ok = p < nv && accept_node(q.x, q.y, q.z, me.x, me.y, me.z, q.s2, th2);
+        while (mb) {
+            int ps[LPB];
+#pragma unroll
+            for (int t = 0; t < LPB; t++) {
+                ps[t] = mb ? __builtin_ctzll(mb) : -1;
+                mb &= mb - 1;
+            }
+            int p = ps[0];
+#pragma unroll
+            for (int t = 1; t < LPB; t++)
+                if (sub == t) p = ps[t];
+            const PopCom q = pc[p < 0 ? 0 : p];
+            const bool ok = p >= 0 && accept_node(q.x, q.y, q.z, me.x, me.y, me.z, q.s2, th2);
             const uint64_t bal = __ballot(ok);
 #pragma unroll
             for (int t = 0; t < LPB; t++) {
                 const uint64_t field = (bal >> (t * GB)) & kBodyMask;
-                if (lane == p0 + t) accepted = field;
+                if (lane == ps[t]) accepted = field;
             }
         }
 
@@ -390,6 +544,17 @@ __global__ __launch_bounds__(64) void k_walk(
         if (CNT) {
             cnode += __shfl_xor(cnode, o);
             cpair += __shfl_xor(cpair, o);
+        }
+    }
+    // then the pair sums, which were complete at the last barrier
+    if (sub == 0) {
+        ax += pacc[3 * bq];
+        ay += pacc[3 * bq + 1];
+        az += pacc[3 * bq + 2];
+        if (PHI) ph += pphi[bq];
+        if (CNT) {
+            cnode += pcnt[2 * bq];
+            cpair += pcnt[2 * bq + 1];
         }
     }
     if (valid && sub == 0) {
