@@ -48,7 +48,7 @@
 namespace bhx {
 namespace {
 
-constexpr int kStack = 320;    // LDS traversal stack of child ranges
+constexpr int kStack = 256;    // LDS traversal stack of child ranges
 constexpr int kReserve = 150;  // a depth-first descent adds <= 7 ranges per level
 constexpr int kRanges = 8;     // ranges popped per round (<= 8 nodes each)
 constexpr int kPop = 8 * kRanges;
@@ -85,7 +85,6 @@ struct alignas(16) PopData {  // popped node as the bookkeeping needs it
     int32_t nch, pad;
 };
 
-__device__ inline int32_t uniform32(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ inline uint32_t lanes_below(uint64_t m)  // set bits of m below this lane
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
@@ -130,7 +129,7 @@ __global__ __launch_bounds__(64) void k_walk(
     // Items that reach at most kSparse bodies of the group are evaluated as
     // (item, body) pairs, one pair per lane, into per-body FP64 sums in LDS.
     constexpr int kSparse = GB / 4;
-    constexpr int kSweepUnroll = GB == 64 ? 2 : 1;
+    constexpr int kSweepUnroll = GB == 64 ? 4 : 1;
 
     __shared__ int32_t st_c0[kStack];
     __shared__ uint8_t st_n[kStack];
@@ -228,17 +227,31 @@ __global__ __launch_bounds__(64) void k_walk(
         uint64_t mk = 0;
         int32_t src = 0;
         double x = 0.0, y = 0.0, z = 0.0, m = 0.0, e2 = 0.0;
+        // The descriptor of item consumed + lane: each descriptor that starts
+        // inside the batch marks its first item, the head descriptor (which
+        // may start before the batch) marks item 0, and a running maximum over
+        // the lanes hands every item the last mark at or before it.
+        // Marks hold descriptor numbers relative to the head; they use the
+        // pair list's space, which is free until the items are split.
+        uint16_t *const mark = rec;
+        mark[lane] = 0;
+#pragma unroll
+        for (int h = 0; h < kRing; h += 64) {
+            if (h + lane < dq_tail - dq_head) {
+                const uint32_t rel = dq_at[(dq_head + h + lane) % kRing] - consumed;
+                if (rel < (uint32_t)c) mark[rel] = (uint16_t)(h + lane);
+            }
+        }
+        __syncthreads();
+        int dsel = mark[lane];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(dsel, o);
+            if (lane >= o) dsel = max(dsel, t);
+        }
         if (lane < c) {
             const uint32_t q = consumed + (uint32_t)lane;
-            int lo = 0, hi = dq_tail - dq_head - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (dq_at[(dq_head + mid) % kRing] <= q)
-                    lo = mid;
-                else
-                    hi = mid - 1;
-            }
-            const int d = (dq_head + lo) % kRing;
+            const int d = (dq_head + dsel) % kRing;
             const int32_t a = dq_a[d];
             mk = dq_mask[d];
             if (a >= 0) {
@@ -404,12 +417,16 @@ __global__ __launch_bounds__(64) void k_walk(
             }
         }
         consumed += (uint32_t)c;
-        // retire fully evaluated descriptors
-        while (dq_head < dq_tail) {
-            const int d = dq_head % kRing;
-            const uint32_t end = (uint32_t)uniform32((int32_t)(dq_at[d] + (uint32_t)dq_n[d]));
-            if (end > consumed) break;
-            dq_head++;
+        // retire the fully evaluated descriptors: they form a prefix of the
+        // queue, and one batch completes at most 64 of them
+        {
+            const int da = dq_head + lane;
+            bool done = false;
+            if (da < dq_tail) {
+                const int d = da % kRing;
+                done = dq_at[d] + (uint32_t)dq_n[d] <= consumed;
+            }
+            dq_head += __popcll(__ballot(done));
         }
         __syncthreads();
     };
