@@ -472,6 +472,19 @@ def main():
             "force_rel_err_fp32c_vs_fp64_tree": err_stats(a_tree32, a_tree64),
         }
         c64.close()
+
+        # the same FP32C step captured once in a HIP graph and replayed
+        cg = Context(n, leaf_size=leaf, precision="fp32c", walk_group=args.walk_group, graph=True)
+        pg, vg = pos0.clone(), vel0.clone()
+        ag = cg.compute_accel(pg, mass, theta, eps=eps)
+        run_steps(cg, 2, pg, vg, ag)
+        cg.sync()
+        kg = max(5, min(50, args.steps))
+        ms_graph = _sync_time(lambda: run_steps(cg, kg, pg, vg, ag)) / kg
+        cg.sync()
+        cg.close()
+        result["comparisons"]["graph_ms_per_step"] = round(ms_graph, 4)
+        log(f"graph-captured step {ms_graph:.3f} ms")
         result["batched"] = bench_batched(args)
         result["adjoint"] = bench_adjoint()
         result["plummer"] = bench_plummer()

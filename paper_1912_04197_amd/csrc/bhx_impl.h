@@ -96,6 +96,11 @@ struct Workspace {
     int32_t *counts = nullptr;    // [n_cap][2] per-body walk counts, caller order
     double *scratch = nullptr;    // [n_cap] potential for diagnostics
     double *red_part = nullptr;   // [reduction blocks][8]
+    // Deepest non-empty level of the last build, written by the device into
+    // pinned host memory (-1 before the first build): the next build launches
+    // the levels down to two below it one by one and the rest in one block.
+    int32_t *depth_host = nullptr;
+    int32_t *depth_dev = nullptr;  // the same memory as the device sees it
 };
 
 constexpr int kSortThreads = 256;

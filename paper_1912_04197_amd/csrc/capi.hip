@@ -90,6 +90,7 @@ void free_ws(Workspace &w)
                     w.hdr, w.counts, w.scratch, w.red_part};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    if (w.depth_host) (void)hipHostFree(w.depth_host);
     w = Workspace{};
 }
 
@@ -423,6 +424,11 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
     A(dalloc(&w.scratch, 4 * n));
     A(dalloc(&w.red_part, (int64_t)bhx::kRedBlocks * 8));
     A(dalloc(&c->diag_out, 8));
+    A(hipHostMalloc((void **)&w.depth_host, sizeof(int32_t), hipHostMallocMapped));
+    if (r == hipSuccess) {
+        *w.depth_host = -1;
+        r = hipHostGetDevicePointer((void **)&w.depth_dev, w.depth_host, 0);
+    }
     if (cfg->flags & BH_FLAG_ADJOINT) {
         A(dalloc(&c->aw.gt, 3 * n));
         A(dalloc(&c->aw.badj, 4 * n));

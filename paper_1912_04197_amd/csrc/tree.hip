@@ -377,15 +377,24 @@ __global__ __launch_bounds__(256) void k_gather(const double *__restrict__ pos,
 
 // First node and node count of `level`, clamped to the node table: after an
 // overflow (flagged ST_CAPACITY) a level counter can exceed what was written.
+template <bool FRESH = false>
+__device__ inline int32_t level_count(const TreeHeader *hdr, int l)
+{
+    if (FRESH)
+        return __hip_atomic_load(&hdr->level_count[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return hdr->level_count[l];
+}
+
+template <bool FRESH = false>
 __device__ inline void level_range(const TreeHeader *hdr, int level, int64_t node_cap,
                                    int32_t *beg, int32_t *cnt)
 {
     int64_t b = 0;
     for (int l = 0; l < level; l++) {
-        int64_t c = hdr->level_count[l];
+        int64_t c = level_count<FRESH>(hdr, l);
         b += c < node_cap - b ? c : node_cap - b;
     }
-    int64_t c = hdr->level_count[level];
+    int64_t c = level_count<FRESH>(hdr, level);
     *beg = (int32_t)b;
     *cnt = (int32_t)(c < node_cap - b ? c : node_cap - b);
 }
@@ -394,18 +403,17 @@ __device__ inline void level_range(const TreeHeader *hdr, int level, int64_t nod
 // per node: lane o binary-searches the first body of octant o, the group
 // reserves its non-empty children with one atomic on the next level's count
 // and writes them contiguously in octant order.
-__global__ __launch_bounds__(256) void k_build_level(int level, const uint64_t *__restrict__ keys,
-                                                     TreeHeader *__restrict__ hdr,
-                                                     NodeInfo *__restrict__ ninfo,
-                                                     int64_t node_cap, int leaf)
+template <bool FRESH>
+__device__ inline void build_nodes(int level, const uint64_t *__restrict__ keys,
+                                   TreeHeader *__restrict__ hdr, NodeInfo *__restrict__ ninfo,
+                                   int64_t node_cap, int leaf, int64_t g_first, int64_t stride)
 {
     int32_t beg, cnt;
-    level_range(hdr, level, node_cap, &beg, &cnt);
+    level_range<FRESH>(hdr, level, node_cap, &beg, &cnt);
     const int32_t next_beg = beg + cnt;
     const int lane = threadIdx.x & 63, o = threadIdx.x & 7, gl = lane & ~7;
     const int shift = 60 - 3 * level;  // bits of the child octant at level + 1
-    const int64_t stride = (int64_t)gridDim.x * 32;
-    for (int64_t g = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3); g < cnt; g += stride) {
+    for (int64_t g = g_first; g < cnt; g += stride) {
         const int32_t k = beg + (int32_t)g;
         const NodeInfo info = ninfo[k];
         if (!(info.count > leaf && level < kMaxLevel)) continue;
@@ -441,22 +449,47 @@ __global__ __launch_bounds__(256) void k_build_level(int level, const uint64_t *
     }
 }
 
+__global__ __launch_bounds__(256) void k_build_level(int level, const uint64_t *__restrict__ keys,
+                                                     TreeHeader *__restrict__ hdr,
+                                                     NodeInfo *__restrict__ ninfo,
+                                                     int64_t node_cap, int leaf)
+{
+    build_nodes<false>(level, keys, hdr, ninfo, node_cap, leaf,
+                       (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3), (int64_t)gridDim.x * 32);
+}
+
+// Levels from..kMaxLevel-1 in one block (deep levels hold few nodes). The
+// per-level node counts grow by atomics inside the loop, so they are read
+// past the L1 cache.
+__global__ __launch_bounds__(1024) void k_build_tail(int from, const uint64_t *__restrict__ keys,
+                                                     TreeHeader *__restrict__ hdr,
+                                                     NodeInfo *__restrict__ ninfo,
+                                                     int64_t node_cap, int leaf)
+{
+    for (int level = from; level < kMaxLevel; level++) {
+        build_nodes<true>(level, keys, hdr, ninfo, node_cap, leaf, threadIdx.x >> 3, 128);
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------ 6. moments
 
 // Mass, centre of mass and mass-weighted softening of every node of `level`,
 // by eq. (COMinternal): from the children of an internal node, from the
 // bodies of a leaf. Products and sums are rounded as written.
-__global__ __launch_bounds__(256) void k_moments_level(
-    int level, const TreeHeader *__restrict__ hdr, const NodeInfo *__restrict__ ninfo,
-    const Body *__restrict__ body, const double *__restrict__ beps2,
-    const uint64_t *__restrict__ keys, const SceneBox *__restrict__ box,
-    NodeMom *__restrict__ nmom, double *__restrict__ neps2, int64_t node_cap, int use_eps)
+__device__ inline void moments_nodes(int level, const TreeHeader *__restrict__ hdr,
+                                     const NodeInfo *__restrict__ ninfo,
+                                     const Body *__restrict__ body,
+                                     const double *__restrict__ beps2,
+                                     const uint64_t *__restrict__ keys,
+                                     const SceneBox *__restrict__ box, NodeMom *__restrict__ nmom,
+                                     double *__restrict__ neps2, int64_t node_cap, int use_eps,
+                                     int64_t g_first, int64_t stride)
 {
 #pragma clang fp contract(off)
     int32_t beg, cnt;
     level_range(hdr, level, node_cap, &beg, &cnt);
-    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < cnt;
-         g += (int64_t)gridDim.x * 256) {
+    for (int64_t g = g_first; g < cnt; g += stride) {
         const int32_t k = beg + (int32_t)g;
         const NodeInfo info = ninfo[k];
         double ms = 0.0, mx = 0.0, my = 0.0, mz = 0.0, me = 0.0;
@@ -498,6 +531,39 @@ __global__ __launch_bounds__(256) void k_moments_level(
         }
         nmom[k] = out;
         if (use_eps) neps2[k] = e2;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_moments_level(
+    int level, const TreeHeader *__restrict__ hdr, const NodeInfo *__restrict__ ninfo,
+    const Body *__restrict__ body, const double *__restrict__ beps2,
+    const uint64_t *__restrict__ keys, const SceneBox *__restrict__ box,
+    NodeMom *__restrict__ nmom, double *__restrict__ neps2, int64_t node_cap, int use_eps,
+    int32_t *__restrict__ depth_out)
+{
+    moments_nodes(level, hdr, ninfo, body, beps2, keys, box, nmom, neps2, node_cap, use_eps,
+                  (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
+    // the root level reports the deepest non-empty level, as a launch hint
+    // for the next build (pinned host memory)
+    if (level == 0 && depth_out && blockIdx.x == 0 && threadIdx.x == 0) {
+        int d = 0;
+        for (int l = 1; l <= kMaxLevel; l++)
+            if (hdr->level_count[l] > 0) d = l;
+        *depth_out = d;
+    }
+}
+
+// Levels kMaxLevel down to `to` in one block (deep levels hold few nodes).
+__global__ __launch_bounds__(1024) void k_moments_tail(
+    int to, const TreeHeader *__restrict__ hdr, const NodeInfo *__restrict__ ninfo,
+    const Body *__restrict__ body, const double *__restrict__ beps2,
+    const uint64_t *__restrict__ keys, const SceneBox *__restrict__ box,
+    NodeMom *__restrict__ nmom, double *__restrict__ neps2, int64_t node_cap, int use_eps)
+{
+    for (int level = kMaxLevel; level >= to; level--) {
+        moments_nodes(level, hdr, ninfo, body, beps2, keys, box, nmom, neps2, node_cap, use_eps,
+                      threadIdx.x, 1024);
+        __syncthreads();
     }
 }
 
@@ -567,15 +633,27 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
     }
     k_gather<<<nb, 256, 0, s>>>(pos, mass, eps, w.idx[0], n, w.body, w.beps2);
 
-    // the largest scene bounds the number of nodes of a level per scene
-    for (int level = 0; level < kMaxLevel; level++) {
+    // Levels below `deep` get a launch each, sized by the largest scene; the
+    // deeper ones, which the previous build on this workspace left (nearly)
+    // empty, are handled in one block. The split only affects speed.
+    int deep = kMaxLevel;
+    if (w.depth_host) {
+        const int prev = *(const volatile int32_t *)w.depth_host;
+        if (prev >= 0 && prev + 2 < deep) deep = prev + 2;
+    }
+    for (int level = 0; level < deep; level++) {
         const unsigned g = blocks_for(level_bound(level, n, ns) * 8, 256, 4096);
         k_build_level<<<g, 256, 0, s>>>(level, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
     }
-    for (int level = kMaxLevel; level >= 0; level--) {
+    if (deep < kMaxLevel)
+        k_build_tail<<<1, 1024, 0, s>>>(deep, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
+    const int use_eps = eps != nullptr;
+    k_moments_tail<<<1, 1024, 0, s>>>(deep, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0], w.box,
+                                      w.nmom, w.neps2, w.node_cap, use_eps);
+    for (int level = deep - 1; level >= 0; level--) {
         const unsigned g = blocks_for(level_bound(level, n, ns), 256, 4096);
         k_moments_level<<<g, 256, 0, s>>>(level, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0], w.box,
-                                          w.nmom, w.neps2, w.node_cap, eps != nullptr);
+                                          w.nmom, w.neps2, w.node_cap, use_eps, w.depth_dev);
     }
     return hipGetLastError();
 }
