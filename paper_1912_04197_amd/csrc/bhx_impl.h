@@ -98,7 +98,7 @@ struct Workspace {
     double *red_part = nullptr;   // [reduction blocks][8]
     // Deepest non-empty level of the last build, written by the device into
     // pinned host memory (-1 before the first build): the next build launches
-    // the levels down to two below it one by one and the rest in one block.
+    // the levels down to one below it one by one and the rest in one block.
     int32_t *depth_host = nullptr;
     int32_t *depth_dev = nullptr;  // the same memory as the device sees it
 };

@@ -289,7 +289,9 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t *__restrict__ counts
 }
 
 // Stable scatter of one tile: the rank of each key among equal digits follows
-// tile order (round r, thread t) == input order.
+// tile order (round r, thread t) == input order. The tile is first reordered
+// by digit in LDS, so that consecutive threads write consecutive addresses of
+// each digit's output run.
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     const uint16_t *__restrict__ scene_of,
@@ -301,6 +303,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     __shared__ uint32_t wcnt[4][256];
     __shared__ uint32_t wpre[4][256];
     __shared__ uint32_t lds4[4];
+    __shared__ uint32_t lstart[256];
+    __shared__ uint64_t skey[kSortTile];
+    __shared__ uint32_t sval[kSortTile];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     uint32_t tot;
@@ -312,7 +317,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
 
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     uint64_t k[kSortItems];
-    uint32_t v[kSortItems], dst[kSortItems];
+    uint32_t v[kSortItems], dst[kSortItems], dig[kSortItems];
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
         int64_t i = base + r * kSortThreads + tid;
@@ -343,14 +348,35 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
         }
         running[tid] = run;
         __syncthreads();
-        dst[r] = digit_base[d] + wpre[wave][d] + (uint32_t)__popcll(lower);
+        dst[r] = wpre[wave][d] + (uint32_t)__popcll(lower);  // rank among the tile's digit d
+        dig[r] = d;
     }
+    // running[] now holds the tile's count per digit: its exclusive scan
+    // gives each digit's run in the reordered tile
+    {
+        const uint32_t c = running[tid];
+        uint32_t ctot;
+        const uint32_t ci = block_incl_scan_256(c, lds4, &ctot);
+        lstart[tid] = ci - c;
+    }
+    __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
         if (base + r * kSortThreads + tid < n) {
-            kout[dst[r]] = k[r];
-            vout[dst[r]] = v[r];
+            const uint32_t lp = lstart[dig[r]] + dst[r];
+            skey[lp] = k[r];
+            sval[lp] = v[r];
         }
+    }
+    __syncthreads();
+    const int cnt = (int)(n - base < kSortTile ? n - base : kSortTile);
+    for (int lp = tid; lp < cnt; lp += kSortThreads) {
+        const uint64_t key = skey[lp];
+        const uint32_t val = sval[lp];
+        const uint32_t d = sort_digit(key, val, shift, scene_of);
+        const uint32_t o = digit_base[d] + (uint32_t)lp - lstart[d];
+        kout[o] = key;
+        vout[o] = val;
     }
 }
 
@@ -553,6 +579,42 @@ __global__ __launch_bounds__(256) void k_moments_level(
     }
 }
 
+// Levels 0..upto-1 of a single scene in one block (the top levels hold few
+// nodes); the counts grow by atomics inside the loop, so they are read past
+// the L1 cache.
+__global__ __launch_bounds__(1024) void k_build_head(int upto, const uint64_t *__restrict__ keys,
+                                                     TreeHeader *__restrict__ hdr,
+                                                     NodeInfo *__restrict__ ninfo,
+                                                     int64_t node_cap, int leaf)
+{
+    for (int level = 0; level < upto; level++) {
+        build_nodes<true>(level, keys, hdr, ninfo, node_cap, leaf, threadIdx.x >> 3, 128);
+        __syncthreads();
+    }
+}
+
+// Levels from-1 down to 0 of a single scene in one block, then the depth
+// report of k_moments_level at level 0.
+__global__ __launch_bounds__(1024) void k_moments_head(
+    int from, const TreeHeader *__restrict__ hdr, const NodeInfo *__restrict__ ninfo,
+    const Body *__restrict__ body, const double *__restrict__ beps2,
+    const uint64_t *__restrict__ keys, const SceneBox *__restrict__ box,
+    NodeMom *__restrict__ nmom, double *__restrict__ neps2, int64_t node_cap, int use_eps,
+    int32_t *__restrict__ depth_out)
+{
+    for (int level = from - 1; level >= 0; level--) {
+        moments_nodes(level, hdr, ninfo, body, beps2, keys, box, nmom, neps2, node_cap, use_eps,
+                      threadIdx.x, 1024);
+        __syncthreads();
+    }
+    if (depth_out && threadIdx.x == 0) {
+        int d = 0;
+        for (int l = 1; l <= kMaxLevel; l++)
+            if (hdr->level_count[l] > 0) d = l;
+        *depth_out = d;
+    }
+}
+
 // Levels kMaxLevel down to `to` in one block (deep levels hold few nodes).
 __global__ __launch_bounds__(1024) void k_moments_tail(
     int to, const TreeHeader *__restrict__ hdr, const NodeInfo *__restrict__ ninfo,
@@ -633,15 +695,19 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
     }
     k_gather<<<nb, 256, 0, s>>>(pos, mass, eps, w.idx[0], n, w.body, w.beps2);
 
-    // Levels below `deep` get a launch each, sized by the largest scene; the
-    // deeper ones, which the previous build on this workspace left (nearly)
-    // empty, are handled in one block. The split only affects speed.
+    // Levels head..deep-1 get a launch each, sized by the largest scene. The
+    // top levels of a single scene (levels 0..head-1, at most 585 nodes) and
+    // the levels from `deep` down, which the previous build on this workspace
+    // left empty but for one level of growth, are handled in one block each.
+    // The split only affects speed.
     int deep = kMaxLevel;
     if (w.depth_host) {
         const int prev = *(const volatile int32_t *)w.depth_host;
-        if (prev >= 0 && prev + 2 < deep) deep = prev + 2;
+        if (prev >= 0 && prev + 1 < deep) deep = prev + 1;
     }
-    for (int level = 0; level < deep; level++) {
+    const int head = ns == 1 ? (deep < 4 ? deep : 4) : 0;
+    if (head > 0) k_build_head<<<1, 1024, 0, s>>>(head, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
+    for (int level = head; level < deep; level++) {
         const unsigned g = blocks_for(level_bound(level, n, ns) * 8, 256, 4096);
         k_build_level<<<g, 256, 0, s>>>(level, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
     }
@@ -650,11 +716,14 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
     const int use_eps = eps != nullptr;
     k_moments_tail<<<1, 1024, 0, s>>>(deep, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0], w.box,
                                       w.nmom, w.neps2, w.node_cap, use_eps);
-    for (int level = deep - 1; level >= 0; level--) {
+    for (int level = deep - 1; level >= head; level--) {
         const unsigned g = blocks_for(level_bound(level, n, ns), 256, 4096);
         k_moments_level<<<g, 256, 0, s>>>(level, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0], w.box,
                                           w.nmom, w.neps2, w.node_cap, use_eps, w.depth_dev);
     }
+    if (head > 0)
+        k_moments_head<<<1, 1024, 0, s>>>(head, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0], w.box,
+                                          w.nmom, w.neps2, w.node_cap, use_eps, w.depth_dev);
     return hipGetLastError();
 }
 
