@@ -77,6 +77,7 @@ struct Layout {
     int n_groups = 0;
 };
 constexpr int kBoxChunk = 4096;  // bodies per bbox work item
+constexpr int64_t kSmallBuild = 4096;  // a single scene this small is built by one block
 
 // Workspace owned by a context; sized once for n_max bodies.
 struct Workspace {

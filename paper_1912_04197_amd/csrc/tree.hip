@@ -141,6 +141,30 @@ __global__ __launch_bounds__(256) void k_box_chunk(const double *__restrict__ po
     }
 }
 
+// Root cube: side = largest extent (1 if all bodies coincide), centred on the
+// bounding box; the quantisation scale and the squared cell side per level.
+__device__ inline void root_cube(SceneBox &b, const double lo[3], const double hi[3])
+{
+#pragma clang fp contract(off)
+    double L = 0.0;
+    for (int a = 0; a < 3; a++) {
+        double e = hi[a] - lo[a];
+        if (e > L) L = e;
+    }
+    if (L == 0.0) L = 1.0;
+    for (int a = 0; a < 3; a++) {
+        b.lo[a] = lo[a];
+        b.hi[a] = hi[a];
+        b.x0[a] = (lo[a] + hi[a]) * 0.5 - L * 0.5;
+    }
+    b.L = L;
+    b.S = 2097152.0 / L;
+    for (int l = 0; l < kLevels; l++) {
+        double sd = ldexp(L, -l);
+        b.s2[l] = sd * sd;
+    }
+}
+
 // One thread per scene: root cube from the box, and the scene's root node
 // (level 0, its bodies' whole range in sorted order). Thread 0 also resets
 // the per-level node counts.
@@ -163,25 +187,7 @@ __global__ __launch_bounds__(256) void k_box_final(SceneBox *__restrict__ box, i
         lo[a] = end > first ? order_dec(b.lo_enc[a]) : 0.0;
         hi[a] = end > first ? order_dec(b.hi_enc[a]) : 0.0;
     }
-    // Root cube: side = largest extent (1 if all bodies coincide), centred
-    // on the bounding box.
-    double L = 0.0;
-    for (int a = 0; a < 3; a++) {
-        double e = hi[a] - lo[a];
-        if (e > L) L = e;
-    }
-    if (L == 0.0) L = 1.0;
-    for (int a = 0; a < 3; a++) {
-        b.lo[a] = lo[a];
-        b.hi[a] = hi[a];
-        b.x0[a] = (lo[a] + hi[a]) * 0.5 - L * 0.5;
-    }
-    b.L = L;
-    b.S = 2097152.0 / L;
-    for (int l = 0; l < kLevels; l++) {
-        double sd = ldexp(L, -l);
-        b.s2[l] = sd * sd;
-    }
+    root_cube(b, lo, hi);
     if (end > first)
         ninfo[sc] = NodeInfo{(int32_t)first, (int32_t)(end - first), -1, (int32_t)(sc << 16)};
 }
@@ -223,6 +229,14 @@ __device__ inline uint32_t quantise(double x, double x0, double S)
     return (uint32_t)f;
 }
 
+__device__ inline uint64_t morton_key(const double *x, const SceneBox &b)
+{
+    const uint32_t qx = quantise(x[0], b.x0[0], b.S);
+    const uint32_t qy = quantise(x[1], b.x0[1], b.S);
+    const uint32_t qz = quantise(x[2], b.x0[2], b.S);
+    return (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+}
+
 __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ pos, int64_t n,
                                               const SceneBox *__restrict__ box,
                                               const uint16_t *__restrict__ scene_of,
@@ -231,12 +245,7 @@ __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ pos, in
 {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    const SceneBox &b = box[scene_of ? scene_of[i] : 0];
-    const double S = b.S;
-    uint32_t qx = quantise(pos[3 * i], b.x0[0], S);
-    uint32_t qy = quantise(pos[3 * i + 1], b.x0[1], S);
-    uint32_t qz = quantise(pos[3 * i + 2], b.x0[2], S);
-    keys[i] = (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
+    keys[i] = morton_key(pos + 3 * i, box[scene_of ? scene_of[i] : 0]);
     idx[i] = (uint32_t)i;
 }
 
@@ -629,6 +638,193 @@ __global__ __launch_bounds__(1024) void k_moments_tail(
     }
 }
 
+// ------------------------------------------------- whole build, small scene
+
+// The whole build of one scene of at most kSmallBuild bodies in one block:
+// box and input check, keys, an eight-pass stable radix sort of (key, index)
+// through global memory, gather, every level of the tree and the moments.
+// Each stage computes what the multi-launch path computes (the same stable
+// order, the same node set and moments); a small scene is bound by launch
+// latency, which this removes.
+constexpr int kSmallThreads = 1024;
+
+__global__ __launch_bounds__(kSmallThreads) void k_build_small(
+    const double *__restrict__ pos, const double *__restrict__ mass,
+    const double *__restrict__ eps, int64_t n, int leaf, SceneBox *__restrict__ box,
+    TreeHeader *__restrict__ hdr, uint64_t *__restrict__ k0, uint64_t *__restrict__ k1,
+    uint32_t *__restrict__ i0, uint32_t *__restrict__ i1, Body *__restrict__ body,
+    double *__restrict__ beps2, NodeInfo *__restrict__ ninfo, NodeMom *__restrict__ nmom,
+    double *__restrict__ neps2, int64_t node_cap, int32_t *__restrict__ depth_out)
+{
+    constexpr int W = kSmallThreads / 64;
+    __shared__ unsigned long long red_lo[3], red_hi[3];
+    __shared__ uint32_t hist[256], base[256], running[256];
+    __shared__ uint32_t wcnt[W][256];
+    __shared__ uint32_t wpre[W][256];
+    __shared__ uint32_t lds4[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    // 1. box and input check
+    if (tid < 3) {
+        red_lo[tid] = ~0ull;
+        red_hi[tid] = 0ull;
+    }
+    if (tid == 0) {
+        for (int l = 0; l <= kLevels; l++) hdr->level_count[l] = 0;
+        hdr->level_count[0] = 1;
+    }
+    for (int i = tid; i < W * 256; i += kSmallThreads) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+    {
+        unsigned long long lo[3] = {~0ull, ~0ull, ~0ull}, hi[3] = {0ull, 0ull, 0ull};
+        bool bad = false;
+        for (int64_t i = tid; i < n; i += kSmallThreads) {
+            const double x[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+            const double m = mass[i];
+            bad |= !(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]));
+            bad |= !(isfinite(m) && m >= 0.0);
+            if (eps) {
+                const double e = eps[i];
+                bad |= !(isfinite(e) && e >= 0.0);
+            }
+            for (int a = 0; a < 3; a++) {
+                const unsigned long long c = order_enc(x[a]);
+                lo[a] = c < lo[a] ? c : lo[a];
+                hi[a] = c > hi[a] ? c : hi[a];
+            }
+        }
+        if (__ballot(bad) && lane == 0) atomicOr(&hdr->status, ST_NONFINITE);
+        for (int a = 0; a < 3; a++) {
+            atomicMin(&red_lo[a], lo[a]);
+            atomicMax(&red_hi[a], hi[a]);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double lo[3], hi[3];
+        for (int a = 0; a < 3; a++) {
+            box[0].lo_enc[a] = red_lo[a];
+            box[0].hi_enc[a] = red_hi[a];
+            lo[a] = order_dec(red_lo[a]);
+            hi[a] = order_dec(red_hi[a]);
+        }
+        root_cube(box[0], lo, hi);
+        ninfo[0] = NodeInfo{0, (int32_t)n, -1, 0};
+    }
+    __syncthreads();
+
+    // 2. keys
+    for (int64_t i = tid; i < n; i += kSmallThreads) {
+        k0[i] = morton_key(pos + 3 * i, box[0]);
+        i0[i] = (uint32_t)i;
+    }
+    __syncthreads();
+
+    // 3. sort: per pass a digit histogram, then rounds of 1024 elements in
+    // input order, ranked among equal digits by wave ballots
+    uint64_t *kin = k0, *kout = k1;
+    uint32_t *vin = i0, *vout = i1;
+    for (int pass = 0; pass < 8; pass++) {
+        const int shift = 8 * pass;
+        if (tid < 256) {
+            hist[tid] = 0;
+            running[tid] = 0;
+        }
+        __syncthreads();
+        for (int64_t i = tid; i < n; i += kSmallThreads)
+            atomicAdd(&hist[(uint32_t)(kin[i] >> shift) & 255u], 1u);
+        __syncthreads();
+        // exclusive scan of the 256 digit counts by the first four waves; the
+        // barriers are reached by every thread of the block
+        {
+            const uint32_t h = tid < 256 ? hist[tid] : 0u;
+            uint32_t v = h;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = __shfl_up(v, o);
+                if (lane >= o) v += t;
+            }
+            if (lane == 63 && wave < 4) lds4[wave] = v;
+            __syncthreads();
+            if (tid < 256) {
+                uint32_t add = 0;
+                for (int w = 0; w < wave; w++) add += lds4[w];
+                base[tid] = add + v - h;
+            }
+        }
+        __syncthreads();
+        for (int64_t r0 = 0; r0 < n; r0 += kSmallThreads) {
+            const int64_t i = r0 + tid;
+            const bool valid = i < n;
+            const uint64_t key = valid ? kin[i] : 0ull;
+            const uint32_t val = valid ? vin[i] : 0u;
+            const uint32_t d = (uint32_t)(key >> shift) & 255u;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; b++) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bal = __ballot(bit);
+                peers &= bit ? bal : ~bal;
+            }
+            const uint64_t lower = peers & lanemask_lt(lane);
+            if (valid && lower == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
+            __syncthreads();
+            if (tid < 256) {
+                uint32_t run = running[tid];
+                for (int w = 0; w < W; w++) {
+                    const uint32_t c = wcnt[w][tid];
+                    wpre[w][tid] = run;
+                    run += c;
+                    wcnt[w][tid] = 0;
+                }
+                running[tid] = run;
+            }
+            __syncthreads();
+            if (valid) {
+                const uint32_t dst = base[d] + wpre[wave][d] + (uint32_t)__popcll(lower);
+                kout[dst] = key;
+                vout[dst] = val;
+            }
+        }
+        __syncthreads();
+        uint64_t *tk = kin;
+        kin = kout;
+        kout = tk;
+        uint32_t *tv = vin;
+        vin = vout;
+        vout = tv;
+    }
+
+    // 4. gather (eight passes leave the order in k0 / i0)
+    for (int64_t s = tid; s < n; s += kSmallThreads) {
+        const uint32_t i = i0[s];
+        body[s] = Body{pos[3 * (int64_t)i], pos[3 * (int64_t)i + 1], pos[3 * (int64_t)i + 2],
+                       mass[i]};
+        if (eps) {
+            const double e = eps[i];
+            beps2[s] = e * e;
+        }
+    }
+    __syncthreads();
+
+    // 5. tree, top-down
+    for (int level = 0; level < kMaxLevel; level++) {
+        build_nodes<true>(level, k0, hdr, ninfo, node_cap, leaf, tid >> 3, kSmallThreads / 8);
+        __syncthreads();
+    }
+    // 6. moments, bottom-up
+    for (int level = kMaxLevel; level >= 0; level--) {
+        moments_nodes(level, hdr, ninfo, body, beps2, k0, box, nmom, neps2, node_cap,
+                      eps != nullptr, tid, kSmallThreads);
+        __syncthreads();
+    }
+    if (depth_out && tid == 0) {
+        int d = 0;
+        for (int l = 1; l <= kMaxLevel; l++)
+            if (hdr->level_count[l] > 0) d = l;
+        *depth_out = d;
+    }
+}
+
 inline unsigned blocks_for(int64_t items, int per_block, unsigned cap)
 {
     int64_t b = (items + per_block - 1) / per_block;
@@ -668,6 +864,13 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
 {
     const int64_t n = lay.n;
     const int ns = lay.n_scenes;
+    if (ns == 1 && n >= 1 && n <= kSmallBuild) {
+        k_build_small<<<1, kSmallThreads, 0, s>>>(pos, mass, eps, n, leaf, w.box, w.hdr, w.keys[0],
+                                                  w.keys[1], w.idx[0], w.idx[1], w.body, w.beps2,
+                                                  w.ninfo, w.nmom, w.neps2, w.node_cap,
+                                                  w.depth_dev);
+        return hipGetLastError();
+    }
     const unsigned sb = (unsigned)((ns + 255) / 256);
     k_box_init<<<sb, 256, 0, s>>>(w.box, ns);
     const int nchunks = lay.chunks ? lay.n_chunks : (int)((n + kBoxChunk - 1) / kBoxChunk);

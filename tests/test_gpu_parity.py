@@ -105,18 +105,36 @@ TREE_CASES = [
     ("cube999_leaf1", lambda: ics.uniform_cube(999, seed=8), 1, False),
     ("rubble6000_leaf16_eps", lambda: ics.rubble_pile(6000, seed=9), 16, True),
     ("ball70000_leaf64", lambda: ics.uniform_ball(70000, seed=10), 64, False),
+    # the largest scene built by one block, and the smallest that is not
+    ("ball4096_leaf2", lambda: ics.uniform_ball(4096, seed=14), 2, False),
+    ("ball4097_leaf2", lambda: ics.uniform_ball(4097, seed=14), 2, False),
 ]
 
 
 @pytest.mark.parametrize("name,make,leaf,per_body", TREE_CASES, ids=[c[0] for c in TREE_CASES])
 def test_tree_parity(api, name, make, leaf, per_body):
     s = make()
+    ctx = _ctx(api, s.n, leaf=leaf, counts=False)
+    _check_tree(ctx, s, leaf, per_body)
+
+
+def test_tree_rebuilds_shallow_deep_shallow(api):
+    """One context builds a shallow tree, a much deeper one, then the shallow
+    one again: levels below the previous build's depth are split in one block
+    and must give the same tree as level-by-level launches."""
+    ctx = _ctx(api, 20000, leaf=4, counts=False)
+    shallow = ics.uniform_cube(20000, seed=15)
+    deep = ics.plummer(20000, seed=16)
+    for s in (shallow, deep, shallow, deep):
+        _check_tree(ctx, s, 4, False)
+
+
+def _check_tree(ctx, s, leaf, per_body):
     m = s.mass * (1.0 + (np.arange(s.n) % 3))  # unequal masses
     eps = s.eps if per_body else None
     T = oracle.Tree(s.pos, m, eps=eps, leaf=leaf)
     ref = T.export()
     box = T.box()
-    ctx = _ctx(api, s.n, leaf=leaf, counts=False)
     ctx.build_tree(_dev(s.pos), _dev(m), None if eps is None else _dev(eps))
     v = ctx.tree()
     # root cube and quantisation: bit-exact
