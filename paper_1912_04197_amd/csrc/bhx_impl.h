@@ -143,6 +143,7 @@ struct WalkParams {
     int group;  // target bodies per wavefront: 64, 32 or 16
 };
 constexpr int kDefaultWalkGroup = 64;
+constexpr int64_t kSmallWalk = 131072;  // below this many bodies the default group is 16
 // walk.hip
 hipError_t launch_walk(const Workspace &w, hipStream_t s, const WalkParams &p);
 

@@ -150,9 +150,13 @@ bh_status record(bh_ctx *c, int which)
     return BH_OK;
 }
 
-int walk_group(const bh_ctx *c)
+// Bodies per walk wavefront for a call on n bodies: the configured size, or
+// by default 64 for large calls and 16 below 2^17 bodies, where 64-body groups
+// leave too few wavefronts to fill the chip.
+int walk_group(const bh_ctx *c, int64_t n)
 {
-    return c->cfg.walk_group ? c->cfg.walk_group : bhx::kDefaultWalkGroup;
+    if (c->cfg.walk_group) return c->cfg.walk_group;
+    return n < bhx::kSmallWalk ? 16 : bhx::kDefaultWalkGroup;
 }
 
 bhx::Layout single(int64_t n)
@@ -184,7 +188,7 @@ bh_status force_tree(bh_ctx *c, const bhx::Layout &lay, const double *pos, const
     p.counts = (c->cfg.flags & BH_FLAG_COUNTS) ? w.counts : nullptr;
     p.per_body_eps = eps != nullptr;
     p.precision = c->cfg.precision;
-    p.group = walk_group(c);
+    p.group = walk_group(c, n);
     p.groups = lay.groups;
     p.n_groups = lay.n_groups;
     BHX_HIP(c, bhx::launch_walk(w, c->stream, p));
@@ -242,7 +246,7 @@ bh_status set_layout(bh_ctx *c, int32_t n_scenes, const int64_t *offsets)
             return fail(c, BH_E_INVALID, "every scene needs at least one body");
     const int64_t n = offsets[n_scenes];
     if (n > c->w.n_cap) return fail(c, BH_E_CAPACITY, "total bodies exceed n_max");
-    const int gb = walk_group(c);
+    const int gb = walk_group(c, n);
     if (c->layout_group == gb && (int64_t)c->h_offsets.size() == n_scenes + 1 &&
         std::equal(c->h_offsets.begin(), c->h_offsets.end(), offsets))
         return BH_OK;
