@@ -412,24 +412,15 @@ __global__ __launch_bounds__(256) void k_gather(const double *__restrict__ pos,
 
 // First node and node count of `level`, clamped to the node table: after an
 // overflow (flagged ST_CAPACITY) a level counter can exceed what was written.
-template <bool FRESH = false>
-__device__ inline int32_t level_count(const TreeHeader *hdr, int l)
-{
-    if (FRESH)
-        return __hip_atomic_load(&hdr->level_count[l], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return hdr->level_count[l];
-}
-
-template <bool FRESH = false>
-__device__ inline void level_range(const TreeHeader *hdr, int level, int64_t node_cap,
+__device__ inline void level_range(const int32_t *counts, int level, int64_t node_cap,
                                    int32_t *beg, int32_t *cnt)
 {
     int64_t b = 0;
     for (int l = 0; l < level; l++) {
-        int64_t c = level_count<FRESH>(hdr, l);
+        int64_t c = counts[l];
         b += c < node_cap - b ? c : node_cap - b;
     }
-    int64_t c = level_count<FRESH>(hdr, level);
+    int64_t c = counts[level];
     *beg = (int32_t)b;
     *cnt = (int32_t)(c < node_cap - b ? c : node_cap - b);
 }
@@ -438,13 +429,14 @@ __device__ inline void level_range(const TreeHeader *hdr, int level, int64_t nod
 // per node: lane o binary-searches the first body of octant o, the group
 // reserves its non-empty children with one atomic on the next level's count
 // and writes them contiguously in octant order.
-template <bool FRESH>
-__device__ inline void build_nodes(int level, const uint64_t *__restrict__ keys,
-                                   TreeHeader *__restrict__ hdr, NodeInfo *__restrict__ ninfo,
+// `counts` is the per-level node count array: the tree header's, or a copy
+// in LDS that a single-block kernel keeps and writes back.
+__device__ inline void build_nodes(int level, const uint64_t *__restrict__ keys, int32_t *counts,
+                                   uint32_t *status, NodeInfo *__restrict__ ninfo,
                                    int64_t node_cap, int leaf, int64_t g_first, int64_t stride)
 {
     int32_t beg, cnt;
-    level_range<FRESH>(hdr, level, node_cap, &beg, &cnt);
+    level_range(counts, level, node_cap, &beg, &cnt);
     const int32_t next_beg = beg + cnt;
     const int lane = threadIdx.x & 63, o = threadIdx.x & 7, gl = lane & ~7;
     const int shift = 60 - 3 * level;  // bits of the child octant at level + 1
@@ -468,11 +460,11 @@ __device__ inline void build_nodes(int level, const uint64_t *__restrict__ keys,
         const int nch = __popc(gm);
         const int rank = __popc(gm & ((1u << o) - 1u));
         int32_t slot = 0;
-        if (o == 0) slot = atomicAdd(&hdr->level_count[level + 1], nch);
+        if (o == 0) slot = atomicAdd(&counts[level + 1], nch);
         slot = __shfl(slot, gl);
         const int64_t c0 = (int64_t)next_beg + slot;
         if (c0 + nch > node_cap) {
-            if (o == 0) atomicOr(&hdr->status, ST_CAPACITY);
+            if (o == 0) atomicOr(status, ST_CAPACITY);
             continue;
         }
         const int32_t scene_bits = info.lvl_nch & (int32_t)0xffff0000;
@@ -489,22 +481,37 @@ __global__ __launch_bounds__(256) void k_build_level(int level, const uint64_t *
                                                      NodeInfo *__restrict__ ninfo,
                                                      int64_t node_cap, int leaf)
 {
-    build_nodes<false>(level, keys, hdr, ninfo, node_cap, leaf,
-                       (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3), (int64_t)gridDim.x * 32);
+    build_nodes(level, keys, hdr->level_count, &hdr->status, ninfo, node_cap, leaf,
+                (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3), (int64_t)gridDim.x * 32);
 }
 
-// Levels from..kMaxLevel-1 in one block (deep levels hold few nodes). The
-// per-level node counts grow by atomics inside the loop, so they are read
-// past the L1 cache.
+// Levels from..upto-1 in one block, on a copy of the node counts in LDS
+// (no other kernel runs meanwhile); stops at the first empty level.
+__device__ inline void build_levels_block(int from, int upto, const uint64_t *__restrict__ keys,
+                                          TreeHeader *__restrict__ hdr,
+                                          NodeInfo *__restrict__ ninfo, int64_t node_cap,
+                                          int leaf, int32_t *scnt)
+{
+    for (int level = from; level < upto; level++) {
+        if (scnt[level] == 0) break;
+        build_nodes(level, keys, scnt, &hdr->status, ninfo, node_cap, leaf, threadIdx.x >> 3,
+                    blockDim.x >> 3);
+        __syncthreads();
+    }
+}
+
+// Levels from..kMaxLevel-1 in one block (deep levels hold few nodes).
 __global__ __launch_bounds__(1024) void k_build_tail(int from, const uint64_t *__restrict__ keys,
                                                      TreeHeader *__restrict__ hdr,
                                                      NodeInfo *__restrict__ ninfo,
                                                      int64_t node_cap, int leaf)
 {
-    for (int level = from; level < kMaxLevel; level++) {
-        build_nodes<true>(level, keys, hdr, ninfo, node_cap, leaf, threadIdx.x >> 3, 128);
-        __syncthreads();
-    }
+    __shared__ int32_t scnt[kLevels + 1];
+    if (threadIdx.x <= kLevels) scnt[threadIdx.x] = hdr->level_count[threadIdx.x];
+    __syncthreads();
+    build_levels_block(from, kMaxLevel, keys, hdr, ninfo, node_cap, leaf, scnt);
+    __syncthreads();
+    if (threadIdx.x <= kLevels) hdr->level_count[threadIdx.x] = scnt[threadIdx.x];
 }
 
 // ------------------------------------------------------------ 6. moments
@@ -512,7 +519,7 @@ __global__ __launch_bounds__(1024) void k_build_tail(int from, const uint64_t *_
 // Mass, centre of mass and mass-weighted softening of every node of `level`,
 // by eq. (COMinternal): from the children of an internal node, from the
 // bodies of a leaf. Products and sums are rounded as written.
-__device__ inline void moments_nodes(int level, const TreeHeader *__restrict__ hdr,
+__device__ inline void moments_nodes(int level, const int32_t *counts,
                                      const NodeInfo *__restrict__ ninfo,
                                      const Body *__restrict__ body,
                                      const double *__restrict__ beps2,
@@ -523,7 +530,7 @@ __device__ inline void moments_nodes(int level, const TreeHeader *__restrict__ h
 {
 #pragma clang fp contract(off)
     int32_t beg, cnt;
-    level_range(hdr, level, node_cap, &beg, &cnt);
+    level_range(counts, level, node_cap, &beg, &cnt);
     for (int64_t g = g_first; g < cnt; g += stride) {
         const int32_t k = beg + (int32_t)g;
         const NodeInfo info = ninfo[k];
@@ -576,8 +583,8 @@ __global__ __launch_bounds__(256) void k_moments_level(
     NodeMom *__restrict__ nmom, double *__restrict__ neps2, int64_t node_cap, int use_eps,
     int32_t *__restrict__ depth_out)
 {
-    moments_nodes(level, hdr, ninfo, body, beps2, keys, box, nmom, neps2, node_cap, use_eps,
-                  (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
+    moments_nodes(level, hdr->level_count, ninfo, body, beps2, keys, box, nmom, neps2, node_cap,
+                  use_eps, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
     // the root level reports the deepest non-empty level, as a launch hint
     // for the next build (pinned host memory)
     if (level == 0 && depth_out && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -589,17 +596,18 @@ __global__ __launch_bounds__(256) void k_moments_level(
 }
 
 // Levels 0..upto-1 of a single scene in one block (the top levels hold few
-// nodes); the counts grow by atomics inside the loop, so they are read past
-// the L1 cache.
+// nodes).
 __global__ __launch_bounds__(1024) void k_build_head(int upto, const uint64_t *__restrict__ keys,
                                                      TreeHeader *__restrict__ hdr,
                                                      NodeInfo *__restrict__ ninfo,
                                                      int64_t node_cap, int leaf)
 {
-    for (int level = 0; level < upto; level++) {
-        build_nodes<true>(level, keys, hdr, ninfo, node_cap, leaf, threadIdx.x >> 3, 128);
-        __syncthreads();
-    }
+    __shared__ int32_t scnt[kLevels + 1];
+    if (threadIdx.x <= kLevels) scnt[threadIdx.x] = hdr->level_count[threadIdx.x];
+    __syncthreads();
+    build_levels_block(0, upto, keys, hdr, ninfo, node_cap, leaf, scnt);
+    __syncthreads();
+    if (threadIdx.x <= kLevels) hdr->level_count[threadIdx.x] = scnt[threadIdx.x];
 }
 
 // Levels from-1 down to 0 of a single scene in one block, then the depth
@@ -611,8 +619,11 @@ __global__ __launch_bounds__(1024) void k_moments_head(
     NodeMom *__restrict__ nmom, double *__restrict__ neps2, int64_t node_cap, int use_eps,
     int32_t *__restrict__ depth_out)
 {
+    __shared__ int32_t scnt[kLevels + 1];
+    if (threadIdx.x <= kLevels) scnt[threadIdx.x] = hdr->level_count[threadIdx.x];
+    __syncthreads();
     for (int level = from - 1; level >= 0; level--) {
-        moments_nodes(level, hdr, ninfo, body, beps2, keys, box, nmom, neps2, node_cap, use_eps,
+        moments_nodes(level, scnt, ninfo, body, beps2, keys, box, nmom, neps2, node_cap, use_eps,
                       threadIdx.x, 1024);
         __syncthreads();
     }
@@ -631,8 +642,12 @@ __global__ __launch_bounds__(1024) void k_moments_tail(
     const uint64_t *__restrict__ keys, const SceneBox *__restrict__ box,
     NodeMom *__restrict__ nmom, double *__restrict__ neps2, int64_t node_cap, int use_eps)
 {
+    __shared__ int32_t scnt[kLevels + 1];
+    if (threadIdx.x <= kLevels) scnt[threadIdx.x] = hdr->level_count[threadIdx.x];
+    __syncthreads();
     for (int level = kMaxLevel; level >= to; level--) {
-        moments_nodes(level, hdr, ninfo, body, beps2, keys, box, nmom, neps2, node_cap, use_eps,
+        if (scnt[level] == 0) continue;  // the same on every thread
+        moments_nodes(level, scnt, ninfo, body, beps2, keys, box, nmom, neps2, node_cap, use_eps,
                       threadIdx.x, 1024);
         __syncthreads();
     }
@@ -669,10 +684,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_build_small(
         red_lo[tid] = ~0ull;
         red_hi[tid] = 0ull;
     }
-    if (tid == 0) {
-        for (int l = 0; l <= kLevels; l++) hdr->level_count[l] = 0;
-        hdr->level_count[0] = 1;
-    }
+    __shared__ int32_t scnt[kLevels + 1];
+    if (tid <= kLevels) scnt[tid] = tid == 0 ? 1 : 0;
     for (int i = tid; i < W * 256; i += kSmallThreads) (&wcnt[0][0])[i] = 0;
     __syncthreads();
     {
@@ -806,21 +819,21 @@ __global__ __launch_bounds__(kSmallThreads) void k_build_small(
     }
     __syncthreads();
 
-    // 5. tree, top-down
-    for (int level = 0; level < kMaxLevel; level++) {
-        build_nodes<true>(level, k0, hdr, ninfo, node_cap, leaf, tid >> 3, kSmallThreads / 8);
-        __syncthreads();
-    }
+    // 5. tree, top-down, with the node counts in LDS
+    build_levels_block(0, kMaxLevel, k0, hdr, ninfo, node_cap, leaf, scnt);
+    __syncthreads();
     // 6. moments, bottom-up
     for (int level = kMaxLevel; level >= 0; level--) {
-        moments_nodes(level, hdr, ninfo, body, beps2, k0, box, nmom, neps2, node_cap,
+        if (scnt[level] == 0) continue;  // the same on every thread
+        moments_nodes(level, scnt, ninfo, body, beps2, k0, box, nmom, neps2, node_cap,
                       eps != nullptr, tid, kSmallThreads);
         __syncthreads();
     }
+    if (tid <= kLevels) hdr->level_count[tid] = scnt[tid];
     if (depth_out && tid == 0) {
         int d = 0;
         for (int l = 1; l <= kMaxLevel; l++)
-            if (hdr->level_count[l] > 0) d = l;
+            if (scnt[l] > 0) d = l;
         *depth_out = d;
     }
 }
