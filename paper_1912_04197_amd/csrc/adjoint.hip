@@ -233,27 +233,22 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
         uint64_t mk = 0;
         ItemV ld_it{0.0, 0.0, 0.0, 0.0, 0.0, 0ull, 0, 0, 0};
         // The descriptor of item consumed + lane: each descriptor that starts
-        // inside the batch marks its first item, the head descriptor (which
-        // may start before the batch) marks item 0, and a running maximum over
-        // the lanes hands every item the last mark at or before it.
-        // Marks hold descriptor numbers relative to the head; they use the
-        // pair list's space, which is free until the items are split.
-        uint16_t *const mark = rec;
-        mark[lane] = 0;
+        // inside the batch flags its first item (only the head descriptor can
+        // start at item 0, and it may also start before the batch), so item
+        // L belongs to the head plus as many descriptors as start in 1..L.
+        // The flags use the pair list's space, free until the items are split.
+        uint16_t *const flag = rec;
+        flag[lane] = 0;
 #pragma unroll
         for (int h = 0; h < kRing; h += 64) {
             if (h + lane < dq_tail - dq_head) {
                 const uint32_t rel = dq_at[(dq_head + h + lane) % kRing] - consumed;
-                if (rel < (uint32_t)c) mark[rel] = (uint16_t)(h + lane);
+                if (rel < (uint32_t)c) flag[rel] = 1;
             }
         }
         __syncthreads();
-        int dsel = mark[lane];
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int t = __shfl_up(dsel, o);
-            if (lane >= o) dsel = max(dsel, t);
-        }
+        const uint64_t starts = __ballot(flag[lane] != 0) & ~1ull;
+        const int dsel = (int)lanes_below(starts) + (int)((starts >> lane) & 1ull);
         if (lane < c) {
             const uint32_t q = consumed + (uint32_t)lane;
             const int d = (dq_head + dsel) % kRing;

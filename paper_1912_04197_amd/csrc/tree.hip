@@ -595,21 +595,6 @@ __global__ __launch_bounds__(256) void k_moments_level(
     }
 }
 
-// Levels 0..upto-1 of a single scene in one block (the top levels hold few
-// nodes).
-__global__ __launch_bounds__(1024) void k_build_head(int upto, const uint64_t *__restrict__ keys,
-                                                     TreeHeader *__restrict__ hdr,
-                                                     NodeInfo *__restrict__ ninfo,
-                                                     int64_t node_cap, int leaf)
-{
-    __shared__ int32_t scnt[kLevels + 1];
-    if (threadIdx.x <= kLevels) scnt[threadIdx.x] = hdr->level_count[threadIdx.x];
-    __syncthreads();
-    build_levels_block(0, upto, keys, hdr, ninfo, node_cap, leaf, scnt);
-    __syncthreads();
-    if (threadIdx.x <= kLevels) hdr->level_count[threadIdx.x] = scnt[threadIdx.x];
-}
-
 // Levels from-1 down to 0 of a single scene in one block, then the depth
 // report of k_moments_level at level 0.
 __global__ __launch_bounds__(1024) void k_moments_head(
@@ -911,19 +896,20 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
     }
     k_gather<<<nb, 256, 0, s>>>(pos, mass, eps, w.idx[0], n, w.body, w.beps2);
 
-    // Levels head..deep-1 get a launch each, sized by the largest scene. The
-    // top levels of a single scene (levels 0..head-1, at most 585 nodes) and
-    // the levels from `deep` down, which the previous build on this workspace
-    // left empty but for one level of growth, are handled in one block each.
-    // The split only affects speed.
+    // Splitting: levels 0..deep-1 get a launch each, sized by the largest
+    // scene; the levels from `deep` down, which the previous build on this
+    // workspace left empty but for one level of growth, are handled in one
+    // block. Moments: the same, and the top levels of a single scene (levels
+    // 0..head-1, at most 585 nodes) in one block too. (Splitting the top
+    // levels in one block was measured slower: its binary searches over all
+    // bodies run four passes deep there.) The split only affects speed.
     int deep = kMaxLevel;
     if (w.depth_host) {
         const int prev = *(const volatile int32_t *)w.depth_host;
         if (prev >= 0 && prev + 1 < deep) deep = prev + 1;
     }
     const int head = ns == 1 ? (deep < 4 ? deep : 4) : 0;
-    if (head > 0) k_build_head<<<1, 1024, 0, s>>>(head, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
-    for (int level = head; level < deep; level++) {
+    for (int level = 0; level < deep; level++) {
         const unsigned g = blocks_for(level_bound(level, n, ns) * 8, 256, 4096);
         k_build_level<<<g, 256, 0, s>>>(level, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
     }
