@@ -88,9 +88,10 @@ typedef struct {
     uint32_t flags;    /* BH_FLAG_* */
     int32_t walk_group; /* target bodies served by one wavefront in the tree
                            walk: 64, 32 or 16 (64/walk_group lanes per body);
-                           0 = the library's default (16 for calls on fewer
-                           than 2^17 bodies, else 64). Results do not depend on
-                           it beyond rounding. */
+                           0 = the library's default (forces: 16 for calls
+                           on fewer than 2^17 bodies, else 64; force VJPs: 16
+                           below 2^15, 32 below 2^19, else 64). Results do not
+                           depend on it beyond rounding. */
     int32_t max_scenes; /* largest n_scenes of bh_batched_*; 0 means 1 */
 } bh_config;
 

@@ -25,6 +25,8 @@
 //   4. per body: g_x += m_j sum A, g_m += sum C + x_j . sum A + eps_j^2 sum E,
 //      plus its own target and source terms, added into the caller's arrays.
 // Source-side atomics make the last bits of the gradients order-dependent.
+#include <type_traits>
+
 #include "bhx_impl.h"
 
 namespace bhx {
@@ -94,7 +96,6 @@ __device__ inline double dpp(double v)
 // test comes out the same anywhere in the box by this relative margin (the
 // per-body test's own rounding is below 1e-15).
 constexpr double kMacMargin = 1e-12;
-constexpr int kSparse = 16;    // items reaching at most this many bodies go to pair mode
 constexpr int kPairCap = 448;  // pairs per batch
 
 // badj: per sorted body {gX x, y, z, gm}; nadj: per node {gX x, y, z, gm, ge2}.
@@ -110,7 +111,7 @@ constexpr int kPairCap = 448;  // pairs per batch
 // FP64 atomics. A sparse item becomes (item, body) pairs, one per lane, whose
 // target-side terms go to per-body and whose source-side terms go to per-item
 // FP64 sums in LDS, flushed to the adjoints once per batch.
-template <bool PEPS>
+template <bool PEPS, int GB>
 __global__ __launch_bounds__(64) void k_vjp_walk(
     const Body *__restrict__ body, const double *__restrict__ beps2,
     const NodeInfo *__restrict__ ninfo, const NodeMom *__restrict__ nmom,
@@ -119,7 +120,11 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
     double eps0sq, double G, const double *__restrict__ lambda, double *__restrict__ gt,
     double *__restrict__ badj, double *__restrict__ nadj)
 {
+    static_assert(GB == 64 || GB == 32 || GB == 16, "group size");
     constexpr int NC = PEPS ? 5 : 4;  // source-side components: gX (3), gm, g<eps^2>
+    constexpr int LPB = 64 / GB;      // lanes per body
+    constexpr uint64_t kBodyMask = GB == 64 ? ~0ull : ((1ull << GB) - 1ull);
+    constexpr int kSparse = GB / 4;   // items reaching at most this many bodies go to pair mode
     __shared__ int32_t st_c0[kStack];
     __shared__ uint8_t st_n[kStack];
     __shared__ uint64_t st_mask[kStack];
@@ -139,7 +144,7 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
         } ev;
     };
     __shared__ Shared sh;
-    __shared__ double tacc[3 * 64];      // pair target-side sums per body
+    __shared__ double tacc[3 * GB];      // pair target-side sums per body
     __shared__ double sacc[5 * kBatch];  // pair source-side sums per staged item
     PopCom *const pc = sh.pop.pc;
     PopData *const pd = sh.pop.pd;
@@ -149,8 +154,10 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
     const int grp = (int)(blockIdx.x & 7u) * per_xcd + (int)(blockIdx.x >> 3);
     if (grp >= ngroups) return;
     const int lane = threadIdx.x;
-    const int64_t g0 = (int64_t)grp * 64;
-    const int64_t s = g0 + lane;
+    const int bq = GB == 64 ? lane : lane % GB;  // body of this lane within the group
+    const int sub = GB == 64 ? 0 : lane / GB;    // which share of the items it takes
+    const int64_t g0 = (int64_t)grp * GB;
+    const int64_t s = g0 + bq;
     const bool valid = s < n;
     const Body me = body[valid ? s : g0];
     const double eb2 = PEPS ? beps2[valid ? s : g0] : 0.0;
@@ -161,13 +168,13 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
         ly = lambda[3 * o + 1];
         lz = lambda[3 * o + 2];
     }
-    const uint64_t active = __ballot(valid);
+    const uint64_t active = __ballot(valid) & kBodyMask;
     if (lane < kLevels) s2tab[lane] = box[0].s2[lane];
     double glo_x = valid ? me.x : __builtin_huge_val(), ghi_x = valid ? me.x : -__builtin_huge_val();
     double glo_y = valid ? me.y : __builtin_huge_val(), ghi_y = valid ? me.y : -__builtin_huge_val();
     double glo_z = valid ? me.z : __builtin_huge_val(), ghi_z = valid ? me.z : -__builtin_huge_val();
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
+    for (int o = 1; o < GB; o <<= 1) {
         glo_x = fmin(glo_x, __shfl_xor(glo_x, o));
         ghi_x = fmax(ghi_x, __shfl_xor(ghi_x, o));
         glo_y = fmin(glo_y, __shfl_xor(glo_y, o));
@@ -175,8 +182,9 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
         glo_z = fmin(glo_z, __shfl_xor(glo_z, o));
         ghi_z = fmax(ghi_z, __shfl_xor(ghi_z, o));
     }
-    // this lane's order of the eight items of a dense step
-    const int perm = ((lane & 1) << 2) | (lane & 2) | (lane >> 5);
+    // This lane's order of its share's eight items of a dense step: slot bits
+    // 2 and 1 follow lane bits 0 and 1, slot bit 0 lane bit 5 (GB = 64) or 3.
+    const int perm = ((lane & 1) << 2) | (lane & 2) | (GB == 64 ? lane >> 5 : (lane >> 3) & 1);
 
     double gx = 0.0, gy = 0.0, gz = 0.0;  // target-side gradient of this lane's body
     int sp = 1, dq_head = 0, dq_tail = 0;
@@ -186,7 +194,7 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
         st_n[0] = 1;
         st_mask[0] = active;
     }
-    for (int i = lane; i < 3 * 64; i += 64) tacc[i] = 0.0;
+    for (int i = lane; i < 3 * GB; i += 64) tacc[i] = 0.0;
     __syncthreads();
 
     // One softened term of source (x, y, z, m, e2) on a target at (bx, by, bz)
@@ -257,7 +265,7 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
             if (a >= 0) {
                 const int32_t src = a + (int32_t)(q - dq_at[d]);
                 const int64_t rel = (int64_t)src - g0;
-                if (rel >= 0 && rel < 64) mk &= ~(1ull << rel);
+                if (rel >= 0 && rel < GB) mk &= ~(1ull << rel);
                 const Body b = body[src];
                 ld_it = ItemV{b.x, b.y, b.z, b.m, PEPS ? beps2[src] : 0.0, mk, src, 0, 0};
             } else {
@@ -292,15 +300,15 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
         }
         __syncthreads();
 
-        // dense items, eight per step
+        // dense items, eight per share of lanes per step
 #pragma unroll 1
-        for (int j0 = 0; j0 < nd; j0 += 8) {
+        for (int j0 = 0; j0 < nd; j0 += 8 * LPB) {
             double v[8][NC];
 #pragma unroll
             for (int t = 0; t < 8; t++) {
-                const int j = j0 + (t ^ perm);
+                const int j = j0 + 8 * sub + (t ^ perm);
                 const ItemV it = items[j < nd ? j : j0];
-                const bool on = j < nd && ((it.mask >> lane) & 1ull);
+                const bool on = j < nd && ((it.mask >> bq) & 1ull);
                 double o[5];
                 term(it, me.x, me.y, me.z, eb2, lx, ly, lz, on, o);
                 gx -= o[0];
@@ -319,15 +327,24 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
                 for (int q = 0; q < NC; q++) v[t][q] += dpp<kDppXor2>(v[t + 2][q]);
 #pragma unroll
             for (int q = 0; q < NC; q++) {
-                double w = v[0][q] + __shfl_xor(v[1][q], 32);
-                w += dpp<kDppRor4>(w);
-                w += dpp<kDppRor8>(w);
-                w += __shfl_xor(w, 16);
+                double w;
+                if constexpr (GB == 64) {
+                    w = v[0][q] + __shfl_xor(v[1][q], 32);
+                    w += dpp<kDppRor4>(w);
+                    w += dpp<kDppRor8>(w);
+                    w += __shfl_xor(w, 16);
+                } else {
+                    w = v[0][q] + dpp<kDppRor8>(v[1][q]);  // lane ^ 8 inside the row
+                    w += __shfl_xor(w, 4);
+                    if (GB == 32) w += __shfl_xor(w, 16);
+                }
                 v[0][q] = w;
             }
-            // lanes 0-3 and 32-35 hold the sums of items j0 + perm
-            const int j = j0 + perm;
-            if ((lane & 28) == 0 && j < nd) {
+            // each share's sums of items j0 + 8 sub + perm sit in its lanes with
+            // lane bits 2 and 3, 4 (GB = 64) or 2 (and 4 for GB = 32) clear
+            const int j = j0 + 8 * sub + perm;
+            const bool lead = GB == 64 ? (lane & 28) == 0 : GB == 32 ? (lane & 20) == 0 : (lane & 4) == 0;
+            if (lead && j < nd) {
                 double o[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int q = 0; q < NC; q++) o[q] = v[0][q];
@@ -429,7 +446,7 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
                 const double dmin2 = ex * ex + ey * ey + ez * ez;
                 const double dmax2 = fx * fx + fy * fy + fz * fz;
                 if (q.s2 < th2 * dmin2 * (1.0 - kMacMargin))
-                    accepted = ~0ull;
+                    accepted = kBodyMask;
                 else if (!(q.s2 > th2 * dmax2 * (1.0 + kMacMargin)))
                     mixed = true;
             }
@@ -437,11 +454,24 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
         uint64_t mb = __ballot(mixed);
 #pragma unroll 1
         while (mb) {
-            const int p = __builtin_ctzll(mb);
-            mb &= mb - 1;
-            const PopCom q = pc[p];
-            const uint64_t bal = __ballot(accept_node(q.x, q.y, q.z, me.x, me.y, me.z, q.s2, th2));
-            if (lane == p) accepted = bal;
+            int ps[LPB];
+#pragma unroll
+            for (int t = 0; t < LPB; t++) {
+                ps[t] = mb ? __builtin_ctzll(mb) : -1;
+                mb &= mb - 1;
+            }
+            int p = ps[0];
+#pragma unroll
+            for (int t = 1; t < LPB; t++)
+                if (sub == t) p = ps[t];
+            const PopCom q = pc[p < 0 ? 0 : p];
+            const bool ok = p >= 0 && accept_node(q.x, q.y, q.z, me.x, me.y, me.z, q.s2, th2);
+            const uint64_t bal = __ballot(ok);
+#pragma unroll
+            for (int t = 0; t < LPB; t++) {
+                const uint64_t field = (bal >> (t * GB)) & kBodyMask;
+                if (lane == ps[t]) accepted = field;
+            }
         }
         const bool mine = lane < nv;
         PopData my = PopData{0ull, 0, 0, 0, 0, 0, 0};
@@ -476,10 +506,17 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
     }
     while (queued != consumed) evaluate((int)min(queued - consumed, (uint32_t)kBatch));
 
-    if (valid) {
-        gt[3 * s] = gx + tacc[3 * lane];
-        gt[3 * s + 1] = gy + tacc[3 * lane + 1];
-        gt[3 * s + 2] = gz + tacc[3 * lane + 2];
+    // the lanes' shares of each body, in a fixed order, then its pair sums
+#pragma unroll
+    for (int o = GB; o < 64; o <<= 1) {
+        gx += __shfl_xor(gx, o);
+        gy += __shfl_xor(gy, o);
+        gz += __shfl_xor(gz, o);
+    }
+    if (valid && sub == 0) {
+        gt[3 * s] = gx + tacc[3 * bq];
+        gt[3 * s + 1] = gy + tacc[3 * bq + 1];
+        gt[3 * s + 2] = gz + tacc[3 * bq + 2];
     }
 }
 
@@ -710,18 +747,28 @@ hipError_t launch_tree_vjp(const Workspace &w, const AdjointWork &aw, hipStream_
 {
     if (p.n <= 0) return hipSuccess;
     k_vjp_clear<<<1024, 256, 0, s>>>(aw.badj, p.n, aw.nadj, aw.npre, w.hdr, w.node_cap);
-    const int ngroups = (int)((p.n + 63) / 64);
+    const int gb = p.group == 16 || p.group == 32 ? p.group : 64;
+    const int ngroups = (int)((p.n + gb - 1) / gb);
     const int per_xcd = (ngroups + 7) / 8;
-    if (p.per_body_eps)
-        k_vjp_walk<true><<<8 * per_xcd, 64, 0, s>>>(w.body, w.beps2, w.ninfo, w.nmom, w.neps2,
-                                                     w.idx[0], w.box, p.n, ngroups, per_xcd, p.th2,
-                                                     p.eps0sq, p.G, lambda, aw.gt, aw.badj,
-                                                     aw.nadj);
-    else
-        k_vjp_walk<false><<<8 * per_xcd, 64, 0, s>>>(w.body, w.beps2, w.ninfo, w.nmom, w.neps2,
-                                                      w.idx[0], w.box, p.n, ngroups, per_xcd,
-                                                      p.th2, p.eps0sq, p.G, lambda, aw.gt,
-                                                      aw.badj, aw.nadj);
+    auto walk = [&](auto peps, auto gbc) {
+        k_vjp_walk<decltype(peps)::value, decltype(gbc)::value><<<8 * per_xcd, 64, 0, s>>>(
+            w.body, w.beps2, w.ninfo, w.nmom, w.neps2, w.idx[0], w.box, p.n, ngroups, per_xcd,
+            p.th2, p.eps0sq, p.G, lambda, aw.gt, aw.badj, aw.nadj);
+    };
+    using T = std::true_type;
+    using F = std::false_type;
+    using I16 = std::integral_constant<int, 16>;
+    using I32 = std::integral_constant<int, 32>;
+    using I64 = std::integral_constant<int, 64>;
+    if (p.per_body_eps) {
+        if (gb == 16) walk(T{}, I16{});
+        else if (gb == 32) walk(T{}, I32{});
+        else walk(T{}, I64{});
+    } else {
+        if (gb == 16) walk(F{}, I16{});
+        else if (gb == 32) walk(F{}, I32{});
+        else walk(F{}, I64{});
+    }
     const int use_eps = p.per_body_eps ? 1 : 0;
     k_vjp_root<<<1, 64, 0, s>>>(aw.nadj, w.nmom, w.neps2, use_eps, aw.npre);
     int64_t bound = 1;
