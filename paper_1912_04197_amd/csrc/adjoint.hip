@@ -568,19 +568,18 @@ __global__ void k_vjp_root(const double *__restrict__ nadj, const NodeMom *__res
 }
 
 // npre[child] = npre[node] + coefficients(child), for every node of `level`.
-__global__ __launch_bounds__(256) void k_vjp_push(int level, const TreeHeader *__restrict__ hdr,
-                                                  const NodeInfo *__restrict__ ninfo,
-                                                  const NodeMom *__restrict__ nmom,
-                                                  const double *__restrict__ neps2, int use_eps,
-                                                  const double *__restrict__ nadj,
-                                                  double *__restrict__ npre, int64_t node_cap)
+__device__ inline void push_level(int level, const TreeHeader *__restrict__ hdr,
+                                  const NodeInfo *__restrict__ ninfo,
+                                  const NodeMom *__restrict__ nmom,
+                                  const double *__restrict__ neps2, int use_eps,
+                                  const double *__restrict__ nadj, double *__restrict__ npre,
+                                  int64_t node_cap, int64_t g_first, int64_t stride)
 {
     int64_t beg = 0;
     for (int l = 0; l < level; l++) beg += hdr->level_count[l];
     int64_t cnt = hdr->level_count[level];
     if (beg + cnt > node_cap) cnt = node_cap - beg;
-    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < cnt;
-         g += (int64_t)gridDim.x * 256) {
+    for (int64_t g = g_first; g < cnt; g += stride) {
         const int64_t k = beg + g;
         const NodeInfo info = ninfo[k];
         if (info.child0 < 0) continue;
@@ -590,6 +589,34 @@ __global__ __launch_bounds__(256) void k_vjp_push(int level, const TreeHeader *_
             node_coeffs(nadj, nmom[c], use_eps ? neps2[c] : 0.0, c, cf);
             for (int q = 0; q < 5; q++) npre[5 * (int64_t)c + q] = p[q] + cf[q];
         }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_vjp_push(int level, const TreeHeader *__restrict__ hdr,
+                                                  const NodeInfo *__restrict__ ninfo,
+                                                  const NodeMom *__restrict__ nmom,
+                                                  const double *__restrict__ neps2, int use_eps,
+                                                  const double *__restrict__ nadj,
+                                                  double *__restrict__ npre, int64_t node_cap)
+{
+    push_level(level, hdr, ninfo, nmom, neps2, use_eps, nadj, npre, node_cap,
+               (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
+}
+
+// Levels from..kMaxLevel-1 in one block, stopping at the first level with no
+// nodes (deep levels hold few nodes).
+__global__ __launch_bounds__(1024) void k_vjp_push_tail(int from, const TreeHeader *__restrict__ hdr,
+                                                        const NodeInfo *__restrict__ ninfo,
+                                                        const NodeMom *__restrict__ nmom,
+                                                        const double *__restrict__ neps2,
+                                                        int use_eps, const double *__restrict__ nadj,
+                                                        double *__restrict__ npre, int64_t node_cap)
+{
+    for (int level = from; level < kMaxLevel; level++) {
+        if (hdr->level_count[level] == 0) break;  // the same on every thread
+        push_level(level, hdr, ninfo, nmom, neps2, use_eps, nadj, npre, node_cap, threadIdx.x,
+                   1024);
+        __syncthreads();
     }
 }
 
@@ -771,13 +798,23 @@ hipError_t launch_tree_vjp(const Workspace &w, const AdjointWork &aw, hipStream_
     }
     const int use_eps = p.per_body_eps ? 1 : 0;
     k_vjp_root<<<1, 64, 0, s>>>(aw.nadj, w.nmom, w.neps2, use_eps, aw.npre);
+    // one launch per level down to one below the previous build's depth (a
+    // hint kept by the build), the rest in one block
+    int deep = kMaxLevel;
+    if (w.depth_host) {
+        const int prev = *(const volatile int32_t *)w.depth_host;
+        if (prev >= 0 && prev + 1 < deep) deep = prev + 1;
+    }
     int64_t bound = 1;
-    for (int level = 0; level < kMaxLevel; level++) {
+    for (int level = 0; level < deep; level++) {
         const unsigned g = blocks(bound < p.n ? bound : p.n, 4096);
         k_vjp_push<<<g, 256, 0, s>>>(level, w.hdr, w.ninfo, w.nmom, w.neps2, use_eps, aw.nadj,
                                      aw.npre, w.node_cap);
         if (bound < p.n) bound *= 8;
     }
+    if (deep < kMaxLevel)
+        k_vjp_push_tail<<<1, 1024, 0, s>>>(deep, w.hdr, w.ninfo, w.nmom, w.neps2, use_eps, aw.nadj,
+                                           aw.npre, w.node_cap);
     k_vjp_finish<<<blocks(p.n, 4096), 256, 0, s>>>(w.hdr, w.ninfo, w.body, w.beps2, use_eps,
                                                    w.idx[0], aw.npre, aw.gt, aw.badj, g_pos,
                                                    g_mass, w.node_cap);
