@@ -82,6 +82,8 @@ def _load(path: str | None = None):
     lib.orc_tree_accel.restype = C.c_int
     lib.orc_leapfrog.argtypes = [I64, P, P, P, P, D, D, D, I32, D, I32, P]
     lib.orc_leapfrog.restype = C.c_int
+    lib.orc_euler.argtypes = [I64, P, P, P, P, D, D, D, I32, D, I32, I32, P]
+    lib.orc_euler.restype = C.c_int
     lib.orc_diagnostics.argtypes = [I64, P, P, P, P, D, D, P]
     lib.orc_diagnostics.restype = C.c_int
     lib.orc_direct_vjp.argtypes = [I64, P, P, P, D, D, P, P, P]
@@ -266,6 +268,28 @@ def leapfrog(pos, vel, mass, dt, nsteps, softening=0.0, eps=None, theta=-1.0, le
     acc = _f64(acc, (n, 3)).copy()
     _check(lib.orc_leapfrog(n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(eps), float(softening),
                             float(G), float(theta), int(leaf), float(dt), int(nsteps), _ptr(acc)))
+    return pos, vel, acc
+
+
+def euler(pos, vel, mass, dt, nsteps, every=1, softening=0.0, eps=None, theta=-1.0, leaf=16,
+          G=1.0, acc=None):
+    """Semi-implicit Euler with gravity evaluated after every `every`-th substep;
+    theta < 0 uses the direct sum. Returns (pos, vel, acc) copies."""
+    lib = _load()
+    pos = _f64(pos).copy()
+    n = pos.shape[0]
+    vel = _f64(vel, (n, 3)).copy()
+    mass = _f64(mass, (n,))
+    eps = None if eps is None else _f64(eps, (n,))
+    if acc is None:
+        if theta < 0:
+            acc = direct(pos, mass, softening, eps, G)[0]
+        else:
+            acc = bh(pos, mass, theta, softening, eps, leaf, G)[0]
+    acc = _f64(acc, (n, 3)).copy()
+    _check(lib.orc_euler(n, _ptr(pos), _ptr(vel), _ptr(mass), _ptr(eps), float(softening),
+                         float(G), float(theta), int(leaf), float(dt), int(nsteps), int(every),
+                         _ptr(acc)))
     return pos, vel, acc
 
 

@@ -484,6 +484,23 @@ int orc_leapfrog(int64_t n, double *pos, double *vel, const double *mass, const 
     return 0;
 }
 
+int orc_euler(int64_t n, double *pos, double *vel, const double *mass, const double *eps,
+              double eps0, double G, double theta, int32_t leaf, double dt, int32_t nsteps,
+              int32_t every, double *acc)
+{
+    if (n < 0 || nsteps < 0 || every < 1 || !isfinite(dt)) return 1;
+    if (n > 0 && (!vel || !acc)) return 1;
+    for (int32_t s = 1; s <= nsteps; s++) {
+        for (int64_t i = 0; i < 3 * n; i++) vel[i] += dt * acc[i]; /* kick, held gravity */
+        for (int64_t i = 0; i < 3 * n; i++) pos[i] += dt * vel[i]; /* drift, new velocity */
+        if (s % every == 0) {
+            int rc = accel_all(n, pos, mass, eps, eps0, G, theta, leaf, acc);
+            if (rc) return rc;
+        }
+    }
+    return 0;
+}
+
 int orc_diagnostics(int64_t n, const double *pos, const double *vel, const double *mass,
                     const double *eps, double eps0, double G, double out[8])
 {

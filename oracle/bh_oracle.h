@@ -67,6 +67,16 @@ int orc_leapfrog(int64_t n, double *pos, double *vel, const double *mass,
                  const double *eps, double eps0, double G, double theta, int32_t leaf,
                  double dt, int32_t nsteps, double *acc);
 
+/* Semi-implicit (symplectic) Euler, the paper's preferred stepper (Section
+ * "Numerical solvers"), with the two-rate scheme of Section "The asteroid
+ * aggregation problem": every substep of dt kicks v += dt a then drifts
+ * x += dt v; gravity is evaluated (a = A(x)) only after every `every`-th
+ * substep and held constant in between. acc holds the acceleration of the
+ * last evaluation and is updated in place; theta < 0 selects the direct sum. */
+int orc_euler(int64_t n, double *pos, double *vel, const double *mass, const double *eps,
+              double eps0, double G, double theta, int32_t leaf, double dt, int32_t nsteps,
+              int32_t every, double *acc);
+
 /* out[0] kinetic energy, out[1] potential energy 1/2 sum m phi (direct sum),
  * out[2..4] linear momentum, out[5..7] angular momentum about the origin. */
 int orc_diagnostics(int64_t n, const double *pos, const double *vel, const double *mass,

@@ -384,6 +384,60 @@ def pin_leapfrog_tree_theta0():
     assert np.abs(xt - xd).max() < 1e-13 and np.abs(vt - vd).max() < 1e-11
 
 
+# ------------------------------------------------------------- semi-implicit Euler
+
+def pin_euler_held_gravity_closed_form():
+    """With gravity held over the whole call (every > nsteps) the substeps are
+    v_s = v0 + s dt a0 and x_s = x0 + s dt v0 + dt^2 a0 s (s + 1) / 2: the kick
+    comes first and the drift uses the new velocity."""
+    s = ics.plummer(40, seed=31)
+    rng = np.random.default_rng(31)
+    a0 = rng.standard_normal((40, 3))
+    for nsteps in (1, 2, 7):
+        dt = 1e-2
+        x, v, a = oracle.euler(s.pos, s.vel, s.mass, dt, nsteps, every=nsteps + 1, acc=a0)
+        k = nsteps
+        np.testing.assert_allclose(v, s.vel + k * dt * a0, rtol=0, atol=1e-15)
+        np.testing.assert_allclose(x, s.pos + k * dt * s.vel + dt * dt * a0 * k * (k + 1) / 2,
+                                   rtol=0, atol=1e-14)
+        assert np.array_equal(a, a0)
+
+
+def pin_euler_circular_orbit():
+    """Circular two-body orbit after one period. Semi-implicit Euler is the
+    leapfrog map with velocities taken half a step early (it is conjugate to
+    it), so over a closed orbit its position error falls as dt^2; its energy
+    error stays bounded (a symplectic map) instead of drifting, where an
+    explicit Euler step would spiral outwards."""
+    s = ics.two_body_circular(0.7, 0.3, 1.0)
+    period = 2 * math.pi
+    errs = []
+    for nsteps in (2000, 4000):
+        dt = period / nsteps
+        x, v, a = oracle.euler(s.pos, s.vel, s.mass, dt, nsteps)
+        errs.append(np.linalg.norm(x - s.pos))
+    assert errs[0] < 1e-4 and 3.5 < errs[0] / errs[1] < 4.5, errs
+    e0 = oracle.diagnostics(s.pos, s.vel, s.mass)
+    x, v, a = s.pos, s.vel, None
+    devs = []
+    for _ in range(10):
+        x, v, a = oracle.euler(x, v, s.mass, period / 500, 500, acc=a)
+        d = oracle.diagnostics(x, v, s.mass)
+        devs.append(abs((d[0] + d[1]) - (e0[0] + e0[1])) / abs(e0[0] + e0[1]))
+    # an explicit Euler step of this size changes the energy by ~40 % in ten orbits
+    assert max(devs) < 1e-6, devs
+
+
+def pin_euler_two_rate_momentum():
+    """Direct forces: total momentum is conserved to round-off whatever the
+    gravity rate (every term of sum m a cancels pairwise)."""
+    s = ics.plummer(48, seed=32)
+    e0 = oracle.diagnostics(s.pos, s.vel, s.mass, softening=0.05)
+    x, v, a = oracle.euler(s.pos, s.vel, s.mass, 2e-3, 300, every=4, softening=0.05)
+    d = oracle.diagnostics(x, v, s.mass, softening=0.05)
+    assert np.abs(d[2:5] - e0[2:5]).max() < 1e-14
+
+
 def pin_diagnostics_two_body():
     s = ics.two_body_circular(0.7, 0.3, 1.0)
     d = oracle.diagnostics(s.pos, s.vel, s.mass)

@@ -16,6 +16,9 @@ import oracle
 SRC = os.path.join(os.path.dirname(oracle.__file__), "bh_oracle.c")
 
 MUTANTS = {
+    "euler_drift_first": ("for (int64_t i = 0; i < 3 * n; i++) vel[i] += dt * acc[i]; /* kick, held gravity */\n        for (int64_t i = 0; i < 3 * n; i++) pos[i] += dt * vel[i]; /* drift, new velocity */",
+                          "for (int64_t i = 0; i < 3 * n; i++) pos[i] += dt * vel[i]; /* drift, new velocity */\n        for (int64_t i = 0; i < 3 * n; i++) vel[i] += dt * acc[i]; /* kick, held gravity */"),
+    "euler_every_ignored": ("if (s % every == 0) {", "if (1) {"),
     "pair_sign": ("acc[0] += gm * dx * inv3;", "acc[0] -= gm * dx * inv3;"),
     "pair_drop_z": ("double d2 = dx * dx + dy * dy + dz * dz;", "double d2 = dx * dx + dy * dy;"),
     "r3_to_r2": ("double inv3 = 1.0 / (r2 * r);\n    acc[0]", "double inv3 = 1.0 / r2;\n    acc[0]"),
