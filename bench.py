@@ -485,6 +485,27 @@ def main():
         cg.close()
         result["comparisons"]["graph_ms_per_step"] = round(ms_graph, 4)
         log(f"graph-captured step {ms_graph:.3f} ms")
+
+        # the paper's preferred stepper, semi-implicit Euler, with gravity every
+        # substep and (two-rate scheme) every 10th substep
+        ce = Context(n, leaf_size=leaf, precision="fp32c", walk_group=args.walk_group)
+        pe, ve = pos0.clone(), vel0.clone()
+        ae = ce.compute_accel(pe, mass, theta, eps=eps)
+        ce.step_euler(pe, ve, mass, ae, dt, 2, every=1, theta=theta, eps=eps)
+        ke = max(5, min(50, args.steps))
+        ms_e1 = _sync_time(lambda: ce.step_euler(pe, ve, mass, ae, dt, ke, every=1, theta=theta,
+                                                 eps=eps, sync=False)) / ke
+        ms_e10 = _sync_time(lambda: ce.step_euler(pe, ve, mass, ae, dt, 10 * ke, every=10,
+                                                  theta=theta, eps=eps, sync=False)) / (10 * ke)
+        ce.close()
+        result["euler"] = {
+            "workload": f"rubble_pile N={n} theta={theta} leaf={leaf} eps=radius, semi-implicit "
+                        f"Euler substeps of dt={dt}, FP32C forces",
+            "ms_per_substep_gravity_every_substep": round(ms_e1, 4),
+            "ms_per_substep_gravity_every_10": round(ms_e10, 4),
+            "substeps_per_s_gravity_every_10": round(1e3 / ms_e10, 1),
+        }
+        log(f"euler: {ms_e1:.3f} ms/substep (gravity each), {ms_e10:.3f} (gravity every 10th)")
         result["batched"] = bench_batched(args)
         result["adjoint"] = bench_adjoint()
         result["plummer"] = bench_plummer()

@@ -149,6 +149,20 @@ bh_status bh_step_leapfrog(bh_ctx *ctx, double *pos, double *vel, const double *
                            double softening, const double *eps, double theta, double dt,
                            int32_t nsteps, double *acc, int64_t n);
 
+/* nsteps semi-implicit (symplectic) Euler substeps of dt, in place, with the
+ * two-rate gravity scheme of Section "The asteroid aggregation problem" (the
+ * paper prefers this stepper, Section "Numerical solvers"): each substep
+ * kicks v += dt a and then drifts x += dt v with the new velocity, and gravity
+ * is evaluated (a = A(x), tree for theta >= 0, direct sum otherwise) only after
+ * every `every`-th substep of the call, the acceleration being held in
+ * between. every = 1 is plain semi-implicit Euler. `acc` holds the
+ * acceleration of the last evaluation on entry and on return. Runs eagerly
+ * (BH_FLAG_GRAPH does not apply). Errors: as bh_step_leapfrog, plus
+ * BH_E_INVALID for every < 1. */
+bh_status bh_step_euler(bh_ctx *ctx, double *pos, double *vel, const double *mass,
+                        double softening, const double *eps, double theta, double dt,
+                        int32_t nsteps, int32_t every, double *acc, int64_t n);
+
 /* Per-body walk counts of the last bh_compute_accel / bh_step_leapfrog force
  * evaluation (tree mode), in caller order: counts[2i] = accepted internal
  * nodes, counts[2i+1] = leaf body pairs. counts is a device pointer to n x 2

@@ -178,6 +178,20 @@ class Context:
         if sync:
             self.sync()
 
+    def step_euler(self, pos, vel, mass, acc, dt, nsteps, every=1, theta=0.5, softening=0.0,
+                   eps=None, sync=True):
+        """nsteps semi-implicit Euler substeps in place, gravity re-evaluated
+        after every `every`-th one (see bh_step_euler; theta < 0: direct sum)."""
+        n = self._bodies(pos, mass, eps)
+        _check_f64("vel", vel, (n, 3), self.device)
+        _check_f64("acc", acc, (n, 3), self.device)
+        self._bind()
+        self._rc(self._lib.bh_step_euler(self._h, _ptr(pos), _ptr(vel), _ptr(mass),
+                                         float(softening), _ptr(eps), float(theta), float(dt),
+                                         int(nsteps), int(every), _ptr(acc), n))
+        if sync:
+            self.sync()
+
     @staticmethod
     def _offsets(offsets):
         import numpy as np
@@ -334,3 +348,13 @@ def autotune(offsets, pos, vel, mass, theta=0.5, dt=1e-3, softening=0.0, eps=Non
     if rc != 0:
         raise BHError(rc, "bh_autotune failed")
     return int(out.leaf_size), int(out.walk_group), float(out.ms_per_step)
+
+
+def gravity_dt_bound(density, G=1.0):
+    """Largest gravity time step the paper allows (eq. dt_g): half the
+    characteristic time 1 / sqrt(G rho) of a body of mean density rho."""
+    import math
+
+    if not (density > 0 and G > 0):
+        raise ValueError("density and G must be positive")
+    return 0.5 / math.sqrt(G * density)

@@ -177,6 +177,8 @@ hipError_t launch_copy(hipStream_t s, double *dst, const double *src, int64_t co
 // integrate.hip
 hipError_t launch_kick_drift(hipStream_t s, double *pos, double *vel, const double *acc, int64_t n,
                              double dt);
+hipError_t launch_euler_substeps(hipStream_t s, double *pos, double *vel, const double *acc,
+                                 int64_t n, double dt, int k);
 hipError_t launch_kick(hipStream_t s, double *vel, const double *acc, int64_t n, double dt);
 hipError_t launch_diag_reduce(hipStream_t s, const double *pos, const double *vel,
                               const double *mass, const double *phi, int64_t n, double *part,

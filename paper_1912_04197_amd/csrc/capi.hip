@@ -553,6 +553,35 @@ bh_status bh_step_leapfrog(bh_ctx *c, double *pos, double *vel, const double *ma
     return run_steps(c, single(n), pos, vel, mass, softening, eps, theta, dt, nsteps, acc);
 }
 
+bh_status bh_step_euler(bh_ctx *c, double *pos, double *vel, const double *mass,
+                        double softening, const double *eps, double theta, double dt,
+                        int32_t nsteps, int32_t every, double *acc, int64_t n)
+{
+    bh_status s = check_bodies(c, pos, mass, n);
+    if (s) return s;
+    if (std::isnan(theta) || std::isinf(theta)) return fail(c, BH_E_INVALID, "theta not finite");
+    if (!finite_nonneg(softening)) return fail(c, BH_E_INVALID, "softening must be finite and >= 0");
+    if (!std::isfinite(dt)) return fail(c, BH_E_INVALID, "dt not finite");
+    if (nsteps < 0) return fail(c, BH_E_INVALID, "nsteps < 0");
+    if (every < 1) return fail(c, BH_E_INVALID, "every < 1");
+    if (n > 0 && (!vel || !acc)) return fail(c, BH_E_INVALID, "NULL vel or acc");
+    if (n == 0) return BH_OK;
+    // substeps in runs of `every` (one fused launch each), gravity after each
+    // full run
+    for (int32_t done = 0; done < nsteps;) {
+        const int32_t k = nsteps - done < every ? nsteps - done : every;
+        BHX_HIP(c, bhx::launch_euler_substeps(c->stream, pos, vel, acc, n, dt, k));
+        done += k;
+        if (k == every) {
+            s = theta >= 0.0 ? force_tree(c, single(n), pos, mass, softening, eps, theta, acc, nullptr)
+                             : force_direct(c, pos, mass, softening, eps, acc, nullptr, n,
+                                            c->cfg.precision);
+            if (s) return s;
+        }
+    }
+    return BH_OK;
+}
+
 bh_status bh_batched_accel(bh_ctx *c, int32_t n_scenes, const int64_t *offsets, const double *pos,
                            const double *mass, double softening, const double *eps, double theta,
                            double *acc, double *phi)

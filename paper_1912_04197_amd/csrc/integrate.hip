@@ -7,6 +7,26 @@
 namespace bhx {
 namespace {
 
+// k semi-implicit Euler substeps with the acceleration held: v += dt a, then
+// x += dt v, each rounded as written.
+__global__ __launch_bounds__(256) void k_euler_substeps(double *__restrict__ pos,
+                                                        double *__restrict__ vel,
+                                                        const double *__restrict__ acc,
+                                                        int64_t n3, double dt, int k)
+{
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n3) return;
+    const double a = acc[i];
+    double v = vel[i], x = pos[i];
+    for (int j = 0; j < k; j++) {
+        v = v + dt * a;
+        x = x + dt * v;
+    }
+    vel[i] = v;
+    pos[i] = x;
+}
+
 // v += dt/2 a ; x += dt v
 __global__ __launch_bounds__(256) void k_kick_drift(double *__restrict__ pos,
                                                     double *__restrict__ vel,
@@ -89,6 +109,14 @@ hipError_t launch_kick_drift(hipStream_t s, double *pos, double *vel, const doub
 {
     if (n <= 0) return hipSuccess;
     k_kick_drift<<<blocks(3 * n), 256, 0, s>>>(pos, vel, acc, 3 * n, 0.5 * dt, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_euler_substeps(hipStream_t s, double *pos, double *vel, const double *acc,
+                                 int64_t n, double dt, int k)
+{
+    if (n <= 0 || k <= 0) return hipSuccess;
+    k_euler_substeps<<<blocks(3 * n), 256, 0, s>>>(pos, vel, acc, 3 * n, dt, k);
     return hipGetLastError();
 }
 

@@ -86,6 +86,7 @@ def test_null_context_calls(lib):
     assert lib.bh_set_stream(None, None) == L.BH_E_INVALID
     assert lib.bh_batched_accel(None, 1, None, None, None, 0.0, None, 0.5, None, None) == L.BH_E_INVALID
     assert lib.bh_autotune(None, None, 1, None, None, None, None, 0.0, None, 0.5, 1e-3, 1, None) == L.BH_E_INVALID
+    assert lib.bh_step_euler(None, None, None, None, 0.0, None, 0.5, 1e-3, 1, 1, None, 0) == L.BH_E_INVALID
     assert lib.bh_batched_step(None, 1, None, None, None, None, 0.0, None, 0.5, 1e-3, 1, None) == L.BH_E_INVALID
     assert lib.bh_last_error(None) == b"NULL context"
     lib.bh_destroy(None)
@@ -96,3 +97,13 @@ def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(L, "_lib", None)
     with pytest.raises(L.ExtensionMissing):
         L.load()
+
+
+def test_gravity_dt_bound():
+    """eq. dt_g: dt_g < T_g / 2 = 1 / (2 sqrt(G rho))."""
+    from paper_1912_04197_amd.api import gravity_dt_bound
+
+    assert gravity_dt_bound(1.0) == 0.5
+    assert abs(gravity_dt_bound(3000.0, G=6.674e-11) - 0.5 / (6.674e-11 * 3000.0) ** 0.5) < 1e-9
+    with pytest.raises(ValueError):
+        gravity_dt_bound(0.0)

@@ -298,6 +298,28 @@ def test_leapfrog_parity(api, theta):
     _check_acc(a.cpu().numpy(), ar, aabs, 1e-11, "leapfrog acc")
 
 
+@pytest.mark.parametrize("every", [1, 3])
+@pytest.mark.parametrize("theta", [0.5, -1.0])
+def test_euler_parity(api, theta, every):
+    """2048-body uniform ball, 11 semi-implicit Euler substeps of dt = 1e-3 with
+    gravity after every `every`-th (11 is not a multiple of 3, so the call
+    ends on held gravity); tree theta 0.5 leaf 8, or direct; FP64."""
+    s = ics.uniform_ball(2048, seed=11)
+    xr, vr, ar = oracle.euler(s.pos, s.vel, s.mass, 1e-3, 11, every=every, softening=1e-3,
+                              theta=theta, leaf=8)
+    ctx = _ctx(api, s.n, leaf=8, precision="fp64", counts=False)
+    p, v, m = _dev(s.pos), _dev(s.vel), _dev(s.mass)
+    if theta >= 0:
+        a = ctx.compute_accel(p, m, theta, softening=1e-3)
+    else:
+        a = ctx.compute_accel_direct(p, m, softening=1e-3)
+    ctx.step_euler(p, v, m, a, 1e-3, 11, every=every, theta=theta, softening=1e-3)
+    assert np.abs(p.cpu().numpy() - xr).max() < 1e-13
+    assert np.abs(v.cpu().numpy() - vr).max() < 1e-11
+    _, _, aabs = oracle.direct(xr, s.mass, softening=1e-3)
+    _check_acc(a.cpu().numpy(), ar, aabs, 1e-11, "euler acc")
+
+
 def test_diagnostics(api):
     s = ics.plummer(3000, seed=16)
     ref = oracle.diagnostics(s.pos, s.vel, s.mass, softening=1e-2)
