@@ -261,7 +261,66 @@ def bench_plummer(n=131072, nsteps=500, every=100, dt=1e-3, soft=1e-3, thetas=(0
     return out
 
 
-def bench_crossover(ns=(1000, 4000, 16000, 64000), thetas=(0.25, 0.5, 0.75), soft=1e-3):
+def bench_cold_collapse(n=1000, thetas=(0.1, 0.25, 0.5, 0.75), soft=0.1, dt=1e-3, every=25):
+    """The paper's accuracy experiment: N bodies at rest, uniform in a cube,
+    collapse and re-expand (two free-fall times); the position of every body
+    under the tree is compared with the direct sum's through e_i(t) =
+    |r_BH - r_N2| / |r_N2| in percent: its maximum over bodies (the paper's
+    figure), and for context its 99th percentile and median, over the run and
+    at the end of the contraction (one free-fall time). Semi-implicit Euler,
+    FP64, one-body leaves."""
+    import math
+
+    import torch
+
+    from paper_1912_04197_amd import ics
+    from paper_1912_04197_amd.api import Context
+
+    sc = ics.uniform_cube(n, seed=12)
+    rho = 1.0 / 8.0  # unit mass in a cube of side 2
+    t_ff = math.sqrt(3.0 * math.pi / (32.0 * rho))
+    nsteps = int(round(2.0 * t_ff / dt / every)) * every
+    m = torch.from_numpy(sc.mass).cuda()
+
+    def run(theta):
+        ctx = Context(n, leaf_size=1, precision="fp64")
+        p = torch.from_numpy(sc.pos).cuda()
+        v = torch.zeros_like(p)
+        a = (ctx.compute_accel(p, m, theta, softening=soft) if theta >= 0
+             else ctx.compute_accel_direct(p, m, softening=soft))
+        snaps = []
+        for _ in range(nsteps // every):
+            ctx.step_euler(p, v, m, a, dt, every, theta=theta, softening=soft, sync=False)
+            snaps.append(p.clone())
+        ctx.sync()
+        ctx.close()
+        return snaps
+
+    t0 = time.perf_counter()
+    ref = run(-1.0)
+    half = len(ref) // 2 - 1
+    out = {"workload": f"uniform cube N={n} side 2 at rest, eps={soft}, semi-implicit Euler "
+                       f"dt={dt} for two free-fall times ({nsteps} steps), leaf 1, FP64",
+           "samples_every_steps": every}
+    for th in thetas:
+        snaps = run(th)
+        e = torch.stack([torch.linalg.norm(a - b, dim=1) / torch.linalg.norm(b, dim=1)
+                         for a, b in zip(snaps, ref)]) * 100
+        mx = e.max(dim=1).values
+        k = int(mx.argmax())
+        out[f"theta_{th}"] = {
+            "max_pct": round(float(mx[k]), 5), "at_fraction_of_run": round((k + 1) / len(mx), 3),
+            "p99_pct_peak": round(float(e.quantile(0.99, dim=1).max()), 5),
+            "median_pct_peak": round(float(e.median(dim=1).values.max()), 6),
+            "max_pct_end_of_contraction": round(float(mx[half]), 5),
+        }
+    peaks = [out[f"theta_{th}"]["max_pct"] for th in thetas]
+    out["error_increases_with_theta"] = all(x < y for x, y in zip(peaks, peaks[1:]))
+    log(f"cold collapse: peaks {peaks} ({time.perf_counter() - t0:.1f} s)")
+    return out
+
+
+def bench_crossover(ns=(1000, 2048, 4000, 16000, 64000), thetas=(0.25, 0.5, 0.75), soft=1e-3):
     """The paper's timing experiment on this GPU: one FP64 force evaluation
     (tree rebuilt) against the FP64 direct sum on uniform random cubes."""
     import torch
@@ -510,6 +569,7 @@ def main():
         result["adjoint"] = bench_adjoint()
         result["plummer"] = bench_plummer()
         result["crossover"] = bench_crossover()
+        result["cold_collapse"] = bench_cold_collapse()
 
     if not args.no_cpu:
         import oracle
