@@ -80,6 +80,12 @@ def _load(path: str | None = None):
     lib.orc_tree_export.restype = None
     lib.orc_tree_accel.argtypes = [P, P, P, P, D, D, D, P, I64, P, P, P, P]
     lib.orc_tree_accel.restype = C.c_int
+    lib.orc_tree_accel_q.argtypes = [P, P, P, P, D, D, D, P, I64, P, P, P, P, C.c_int]
+    lib.orc_tree_accel_q.restype = C.c_int
+    lib.orc_tree_quadrupoles.argtypes = [P, P, P]
+    lib.orc_tree_quadrupoles.restype = C.c_int
+    lib.orc_tree_quad_export.argtypes = [P, P]
+    lib.orc_tree_quad_export.restype = C.c_int
     lib.orc_leapfrog.argtypes = [I64, P, P, P, P, D, D, D, I32, D, I32, P]
     lib.orc_leapfrog.restype = C.c_int
     lib.orc_euler.argtypes = [I64, P, P, P, P, D, D, D, I32, D, I32, I32, P]
@@ -187,16 +193,32 @@ class Tree:
                                             "mass", "com", "eps2", "order", "q")])
         return out
 
-    def accel(self, theta, softening=0.0, G=1.0, targets=None):
-        """Barnes-Hut walk. Returns (acc, phi, absacc, counts (nt,2): accepted nodes, pairs)."""
+    def quadrupoles(self) -> np.ndarray:
+        """(nnodes, 6) traceless quadrupoles (xx, yy, zz, xy, xz, yz) about each
+        node's centre of mass, in the node order of export()."""
+        lib = _load()
+        if not getattr(self, "_has_quad", False):
+            _check(lib.orc_tree_quadrupoles(self._h, _ptr(self.pos), _ptr(self.mass)))
+            self._has_quad = True
+        out = np.zeros((self.nnodes, 6))
+        _check(lib.orc_tree_quad_export(self._h, _ptr(out)))
+        return out
+
+    def accel(self, theta, softening=0.0, G=1.0, targets=None, quad=False):
+        """Barnes-Hut walk. Returns (acc, phi, absacc, counts (nt,2): accepted nodes, pairs).
+        quad=True adds each accepted node's quadrupole term."""
         t, nt = _targets(self.n, targets)
         acc = np.zeros((nt, 3))
         phi = np.zeros(nt)
         aabs = np.zeros(nt)
         cnt = np.zeros((nt, 2), np.int64)
-        _check(_load().orc_tree_accel(self._h, _ptr(self.pos), _ptr(self.mass), _ptr(self.eps),
-                                      float(softening), float(G), float(theta), _ptr(t), nt,
-                                      _ptr(acc), _ptr(phi), _ptr(aabs), _ptr(cnt)))
+        lib = _load()
+        if quad and not getattr(self, "_has_quad", False):
+            _check(lib.orc_tree_quadrupoles(self._h, _ptr(self.pos), _ptr(self.mass)))
+            self._has_quad = True
+        _check(lib.orc_tree_accel_q(self._h, _ptr(self.pos), _ptr(self.mass), _ptr(self.eps),
+                                    float(softening), float(G), float(theta), _ptr(t), nt,
+                                    _ptr(acc), _ptr(phi), _ptr(aabs), _ptr(cnt), int(bool(quad))))
         return acc, phi, aabs, cnt
 
 
@@ -246,9 +268,9 @@ def rollout_grad(pos0, vel0, mass, dt, nsteps, xbar, vbar, softening=0.0, eps=No
     return gx, gv, gm
 
 
-def bh(pos, mass, theta, softening=0.0, eps=None, leaf=16, G=1.0, targets=None):
+def bh(pos, mass, theta, softening=0.0, eps=None, leaf=16, G=1.0, targets=None, quad=False):
     """Build the tree and walk it: (acc, phi, absacc, counts)."""
-    return Tree(pos, mass, eps, leaf).accel(theta, softening, G, targets)
+    return Tree(pos, mass, eps, leaf).accel(theta, softening, G, targets, quad=quad)
 
 
 def leapfrog(pos, vel, mass, dt, nsteps, softening=0.0, eps=None, theta=-1.0, leaf=16,

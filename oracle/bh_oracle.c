@@ -58,6 +58,7 @@ struct orc_tree {
     int64_t *first, *count, *child0;
     int32_t *nchild;
     double *m, *com, *eps2;
+    double *quad; /* nn x 6 traceless quadrupoles, after orc_tree_quadrupoles */
 };
 
 int orc_num_threads(void)
@@ -271,6 +272,7 @@ void orc_tree_free(orc_tree *t)
     free(t->m);
     free(t->com);
     free(t->eps2);
+    free(t->quad);
     free(t);
 }
 
@@ -373,10 +375,68 @@ void orc_tree_export(const orc_tree *t, int32_t *level, int64_t *first, int64_t 
     if (q) memcpy(q, t->q, n * 3 * sizeof(uint32_t));
 }
 
+/* Traceless quadrupole of every node about its centre of mass, from its
+ * definition over the node's bodies: Q = sum_j m_j (3 d_j d_j^T - |d_j|^2 I),
+ * d_j = x_j - COM_N, stored as (xx, yy, zz, xy, xz, yz). */
+int orc_tree_quadrupoles(orc_tree *t, const double *pos, const double *mass)
+{
+    if (!t || (t->n > 0 && (!pos || !mass))) return 1;
+    free(t->quad);
+    t->quad = (double *)calloc((size_t)(t->nn > 0 ? t->nn : 1) * 6, sizeof(double));
+    if (!t->quad) return 4;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t k = 0; k < t->nn; k++) {
+        double q[6] = {0, 0, 0, 0, 0, 0};
+        const double *c = t->com + 3 * k;
+        for (int64_t s = t->first[k]; s < t->first[k] + t->count[k]; s++) {
+            int64_t b = t->order[s];
+            double d[3] = {pos[3 * b] - c[0], pos[3 * b + 1] - c[1], pos[3 * b + 2] - c[2]};
+            double d2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            double m = mass[b];
+            q[0] += m * (3.0 * d[0] * d[0] - d2);
+            q[1] += m * (3.0 * d[1] * d[1] - d2);
+            q[2] += m * (3.0 * d[2] * d[2] - d2);
+            q[3] += m * 3.0 * d[0] * d[1];
+            q[4] += m * 3.0 * d[0] * d[2];
+            q[5] += m * 3.0 * d[1] * d[2];
+        }
+        for (int a = 0; a < 6; a++) t->quad[6 * k + a] = q[a];
+    }
+    return 0;
+}
+
+int orc_tree_quad_export(const orc_tree *t, double *out)
+{
+    if (!t || !t->quad || (t->nn > 0 && !out)) return 1;
+    memcpy(out, t->quad, (size_t)t->nn * 6 * sizeof(double));
+    return 0;
+}
+
+/* Quadrupole correction of an accepted node, d = COM_N - x_B, softened
+ * r^2 = |d|^2 + e2: from the potential -G (d^T Q d) / (2 r^5) the
+ * acceleration is G (-Q d / r^5 + 5/2 (d^T Q d) d / r^7). */
+static void add_quad_term(double dx, double dy, double dz, double e2, double G, const double *Q,
+                          double *acc, double *phi)
+{
+    double r2 = dx * dx + dy * dy + dz * dz + e2;
+    if (r2 == 0.0) return;
+    double qd[3] = {Q[0] * dx + Q[3] * dy + Q[4] * dz, Q[3] * dx + Q[1] * dy + Q[5] * dz,
+                    Q[4] * dx + Q[5] * dy + Q[2] * dz};
+    double dqd = dx * qd[0] + dy * qd[1] + dz * qd[2];
+    double r = sqrt(r2);
+    double inv5 = 1.0 / (r2 * r2 * r);
+    double inv7 = inv5 / r2;
+    acc[0] += G * (-qd[0] * inv5 + 2.5 * dqd * dx * inv7);
+    acc[1] += G * (-qd[1] * inv5 + 2.5 * dqd * dy * inv7);
+    acc[2] += G * (-qd[2] * inv5 + 2.5 * dqd * dz * inv7);
+    *phi -= 0.5 * G * dqd * inv5;
+}
+
 typedef struct {
     const orc_tree *t;
     const double *pos, *mass, *eps;
     double e02, G, theta2;
+    int quad; /* add the quadrupole term of accepted nodes */
 } walk_ctx;
 
 typedef struct {
@@ -412,6 +472,7 @@ static void walk_node(const walk_ctx *w, walk_state *st, int64_t k)
         /* accepted: monopole at the centre of mass (eq. Force_thetaTrue) */
         double e2 = w->eps ? 0.5 * (st->eb2 + t->eps2[k]) : w->e02;
         add_term(dx, dy, dz, e2, w->G * t->m[k], st->a, &st->phi, &st->aabs);
+        if (w->quad) add_quad_term(dx, dy, dz, e2, w->G, t->quad + 6 * k, st->a, &st->phi);
         st->nacc++;
         return;
     }
@@ -422,7 +483,16 @@ int orc_tree_accel(const orc_tree *t, const double *pos, const double *mass, con
                    double eps0, double G, double theta, const int64_t *targets, int64_t nt,
                    double *acc, double *phi, double *absacc, int64_t *counts)
 {
+    return orc_tree_accel_q(t, pos, mass, eps, eps0, G, theta, targets, nt, acc, phi, absacc,
+                            counts, 0);
+}
+
+int orc_tree_accel_q(const orc_tree *t, const double *pos, const double *mass, const double *eps,
+                     double eps0, double G, double theta, const int64_t *targets, int64_t nt,
+                     double *acc, double *phi, double *absacc, int64_t *counts, int quad)
+{
     if (!t) return 1;
+    if (quad && !t->quad) return 1;
     int64_t n = t->n;
     if (!(theta >= 0.0) || !isfinite(theta)) return 1;
     if (!eps && !(eps0 >= 0.0 && isfinite(eps0))) return 1;
@@ -432,7 +502,7 @@ int orc_tree_accel(const orc_tree *t, const double *pos, const double *mass, con
     if (targets)
         for (int64_t i = 0; i < nt; i++)
             if (targets[i] < 0 || targets[i] >= n) return 1;
-    walk_ctx w = {t, pos, mass, eps, eps0 * eps0, G, theta * theta};
+    walk_ctx w = {t, pos, mass, eps, eps0 * eps0, G, theta * theta, quad};
 
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t i = 0; i < nt; i++) {

@@ -59,6 +59,21 @@ int orc_tree_accel(const orc_tree *t, const double *pos, const double *mass,
                    const int64_t *targets, int64_t nt, double *acc, double *phi,
                    double *absacc, int64_t *counts);
 
+/* Traceless quadrupole moments of every node, Q = sum m (3 d d^T - |d|^2 I)
+ * about the node's centre of mass (an optional refinement beyond the paper's
+ * monopole nodes), computed from the definition over each node's bodies. */
+int orc_tree_quadrupoles(orc_tree *t, const double *pos, const double *mass);
+
+/* Copies the quadrupoles (nnodes x 6) in node order; needs orc_tree_quadrupoles. */
+int orc_tree_quad_export(const orc_tree *t, double *out);
+
+/* orc_tree_accel with, when quad != 0, each accepted node's quadrupole term
+ * added (orc_tree_quadrupoles must have run). Leaf pairs are unchanged. */
+int orc_tree_accel_q(const orc_tree *t, const double *pos, const double *mass,
+                     const double *eps, double eps0, double G, double theta,
+                     const int64_t *targets, int64_t nt, double *acc, double *phi,
+                     double *absacc, int64_t *counts, int quad);
+
 /* Kick-drift-kick leapfrog, nsteps steps of dt. acc holds the acceleration at
  * the input positions and is updated in place. theta < 0 selects the direct
  * sum, otherwise a Barnes-Hut tree with the given leaf size is rebuilt every

@@ -384,6 +384,79 @@ def pin_leapfrog_tree_theta0():
     assert np.abs(xt - xd).max() < 1e-13 and np.abs(vt - vd).max() < 1e-11
 
 
+# --------------------------------------------------------------- quadrupole
+
+def pin_quad_dumbbell_closed_form():
+    """Two masses m at +-h on z: Q_zz = 4 m h^2, Q_xx = Q_yy = -2 m h^2 about
+    their centre; on the axis at distance R the quadrupole correction is
+    -6 G m h^2 / R^4 (the 1/R^4 term of the exact 1/(R-h)^2 + 1/(R+h)^2)."""
+    m, h, R = 0.7, 0.05, 2.0
+    pos = np.array([[0, 0, h], [0, 0, -h], [0, 0, R]], float)
+    T = oracle.Tree(pos, np.array([m, m, 1e-30]), leaf=1)
+    q = T.quadrupoles()
+    ex = T.export()
+    k = [i for i in range(len(q)) if ex["count"][i] == 2 and ex["nchild"][i] > 0]
+    np.testing.assert_allclose(q[k[0]], [-2 * m * h * h, -2 * m * h * h, 4 * m * h * h, 0, 0, 0],
+                               rtol=1e-12, atol=1e-18)
+    a_mono = T.accel(0.9)[0][2, 2]
+    a_quad = T.accel(0.9, quad=True)[0][2, 2]
+    np.testing.assert_allclose(a_quad - a_mono, -6 * m * h * h / R ** 4, rtol=1e-12)
+
+
+def pin_quad_far_field_order():
+    """A compact cluster seen from distance R: the monopole's error falls as
+    R^-4 and with the quadrupole term as R^-5 (the dipole vanishes about the
+    centre of mass), each checked as the ratio between R and 2R."""
+    rng = np.random.default_rng(41)
+    cl = 0.05 * rng.standard_normal((30, 3))
+    m = rng.uniform(0.5, 1.5, 30)
+    direc = np.array([0.6, -0.48, 0.64])
+    errs = {False: [], True: []}
+    for R in (1.0, 2.0):
+        pos = np.vstack([cl, R * direc])
+        mass = np.append(m, 1e-30)
+        exact = oracle.direct(pos, mass)[0][30]
+        T = oracle.Tree(pos, mass, leaf=1)
+        for q in (False, True):
+            a, _, _, cnt = T.accel(0.9, quad=q)
+            assert cnt[30, 1] == 0  # the probe sees the cluster through nodes only
+            errs[q].append(np.linalg.norm(a[30] - exact))
+    r_mono = errs[False][0] / errs[False][1]
+    r_quad = errs[True][0] / errs[True][1]
+    assert 12 < r_mono < 20 and 26 < r_quad < 40, (r_mono, r_quad)
+    assert errs[True][0] < 0.2 * errs[False][0]
+
+
+def pin_quad_cubic_symmetry_vanishes():
+    """Equal masses on the six octahedron vertices have no quadrupole (cubic
+    symmetry), so the quadrupole walk equals the monopole walk."""
+    h = 0.05
+    v = h * np.vstack([np.eye(3), -np.eye(3)])
+    pos = np.vstack([v, [[1.3, 0.7, -0.9]]])
+    mass = np.append(np.ones(6), 1e-30)
+    T = oracle.Tree(pos, mass, leaf=1)
+    a0 = T.accel(0.9)[0][6]
+    a1 = T.accel(0.9, quad=True)[0][6]
+    assert np.abs(a1 - a0).max() < 1e-15 * np.abs(a0).max()
+
+
+def pin_quad_improves_accuracy():
+    """Plummer sphere, theta 0.5: adding the quadrupole term cuts the RMS force
+    error against the direct sum; theta 0 still equals the direct sum."""
+    s = ics.plummer(3000, seed=42)
+    ref = oracle.direct(s.pos, s.mass, softening=1e-3)[0]
+    T = oracle.Tree(s.pos, s.mass, leaf=8)
+
+    def rms(a):
+        return np.sqrt(np.mean(np.sum((a - ref) ** 2, 1) / np.sum(ref ** 2, 1)))
+
+    e_m = rms(T.accel(0.5, softening=1e-3)[0])
+    e_q = rms(T.accel(0.5, softening=1e-3, quad=True)[0])
+    assert e_q < 0.5 * e_m, (e_m, e_q)
+    a0 = T.accel(0.0, softening=1e-3, quad=True)[0]
+    assert np.abs(a0 - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
 # ------------------------------------------------------------- semi-implicit Euler
 
 def pin_euler_held_gravity_closed_form():

@@ -16,6 +16,11 @@ import oracle
 SRC = os.path.join(os.path.dirname(oracle.__file__), "bh_oracle.c")
 
 MUTANTS = {
+    "quad_sign": ("acc[0] += G * (-qd[0] * inv5 + 2.5 * dqd * dx * inv7);",
+                  "acc[0] += G * (qd[0] * inv5 + 2.5 * dqd * dx * inv7);"),
+    "quad_trace_kept": ("q[0] += m * (3.0 * d[0] * d[0] - d2);", "q[0] += m * (3.0 * d[0] * d[0]);"),
+    "quad_offdiag_factor": ("q[3] += m * 3.0 * d[0] * d[1];", "q[3] += m * d[0] * d[1];"),
+    "quad_r7": ("double inv7 = inv5 / r2;", "double inv7 = inv5 / r;"),
     "euler_drift_first": ("for (int64_t i = 0; i < 3 * n; i++) vel[i] += dt * acc[i]; /* kick, held gravity */\n        for (int64_t i = 0; i < 3 * n; i++) pos[i] += dt * vel[i]; /* drift, new velocity */",
                           "for (int64_t i = 0; i < 3 * n; i++) pos[i] += dt * vel[i]; /* drift, new velocity */\n        for (int64_t i = 0; i < 3 * n; i++) vel[i] += dt * acc[i]; /* kick, held gravity */"),
     "euler_every_ignored": ("if (s % every == 0) {", "if (1) {"),
