@@ -320,6 +320,41 @@ def bench_cold_collapse(n=1000, thetas=(0.1, 0.25, 0.5, 0.75), soft=0.1, dt=1e-3
     return out
 
 
+def bench_quadrupole(n=131072, thetas=(0.3, 0.5, 0.7, 0.9), soft=1e-3):
+    """Error against cost of quadrupole nodes: Plummer sphere, leaf 16, FP32C;
+    per theta the time of one force evaluation (tree rebuilt) and the RMS / p99
+    relative force error against the FP64 direct sum, monopole vs quadrupole."""
+    import numpy as np
+    import torch
+
+    from paper_1912_04197_amd import ics
+    from paper_1912_04197_amd.api import Context
+
+    sc = ics.plummer(n, seed=22)
+    p = torch.from_numpy(sc.pos).cuda()
+    m = torch.from_numpy(sc.mass).cuda()
+    c64 = Context(n, precision="fp64")
+    ref = c64.compute_accel_direct(p, m, softening=soft)
+    c64.close()
+    rn = torch.linalg.norm(ref, dim=1)
+    out = {"workload": f"Plummer N={n}, leaf 16, eps={soft}, FP32C, one force evaluation"}
+    for quad in (False, True):
+        ctx = Context(n, leaf_size=16, precision="fp32c", quad=quad)
+        for th in thetas:
+            a = ctx.compute_accel(p, m, th, softening=soft)
+            reps = 10
+            ms = _sync_time(lambda: [ctx.compute_accel(p, m, th, softening=soft, sync=False)
+                                     for _ in range(reps)]) / reps
+            e = (torch.linalg.norm(a - ref, dim=1) / rn).cpu().numpy()
+            out[f"{'quad' if quad else 'mono'}_theta_{th}"] = {
+                "ms": round(ms, 4), "rms": float(np.sqrt(np.mean(e ** 2))),
+                "p99": float(np.quantile(e, 0.99))}
+        ctx.close()
+    log("quadrupole: " + ", ".join(f"{k} {v['ms']:.2f} ms rms {v['rms']:.2e}"
+                                   for k, v in out.items() if k != "workload"))
+    return out
+
+
 def bench_crossover(ns=(1000, 2048, 4000, 16000, 64000), thetas=(0.25, 0.5, 0.75), soft=1e-3):
     """The paper's timing experiment on this GPU: one FP64 force evaluation
     (tree rebuilt) against the FP64 direct sum on uniform random cubes."""
@@ -570,6 +605,7 @@ def main():
         result["plummer"] = bench_plummer()
         result["crossover"] = bench_crossover()
         result["cold_collapse"] = bench_cold_collapse()
+        result["quadrupole"] = bench_quadrupole()
 
     if not args.no_cpu:
         import oracle

@@ -69,11 +69,19 @@ enum {
                             on the context's stream; totals in bh_stats() */
     BH_FLAG_ADJOINT = 4u, /* allocate the workspace of bh_accel_vjp and
                              bh_leapfrog_vjp at creation */
-    BH_FLAG_GRAPH = 8u    /* bh_step_leapfrog and bh_batched_step capture one
+    BH_FLAG_GRAPH = 8u,   /* bh_step_leapfrog and bh_batched_step capture one
                              step in a HIP graph (once per set of arguments)
                              and replay it nsteps times on a stream of the
                              context, ordered after and before the caller's
                              stream by events */
+    BH_FLAG_QUAD = 16u    /* beyond the paper's monopole nodes: keep each node's
+                             traceless quadrupole Q = sum m (3 d d^T - |d|^2 I)
+                             about its centre of mass, and add to every accepted
+                             node's term G (-Q d / r^5 + 5/2 (d.Q d) d / r^7),
+                             d = COM - x_B, r^2 = |d|^2 + eps^2 (potential
+                             -G (d.Q d) / (2 r^5)). Leaf pairs and opening
+                             decisions are unchanged. The force VJPs do not
+                             support it (BH_E_STATE). */
 };
 
 typedef struct {
@@ -265,6 +273,8 @@ typedef struct {
     const uint32_t *order;
     const uint64_t *keys;
     double box[8];
+    const double *quad; /* quad[6k..6k+5] = node k's (xx, yy, zz, xy, xz, yz)
+                           quadrupole, or NULL without BH_FLAG_QUAD */
 } bh_tree_view;
 bh_status bh_tree_export(bh_ctx *ctx, bh_tree_view *out);
 

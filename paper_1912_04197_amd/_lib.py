@@ -17,6 +17,7 @@ BH_FLAG_COUNTS = 1
 BH_FLAG_TIMING = 2
 BH_FLAG_ADJOINT = 4
 BH_FLAG_GRAPH = 8
+BH_FLAG_QUAD = 16
 
 
 class bh_config(C.Structure):
@@ -29,7 +30,7 @@ class bh_tree_view(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnodes", C.c_int64), ("depth", C.c_int32),
                 ("pad", C.c_int32), ("info", C.c_void_p), ("mom", C.c_void_p),
                 ("eps2", C.c_void_p), ("order", C.c_void_p), ("keys", C.c_void_p),
-                ("box", C.c_double * 8)]
+                ("box", C.c_double * 8), ("quad", C.c_void_p)]
 
 
 class bh_stats_t(C.Structure):

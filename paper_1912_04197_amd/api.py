@@ -66,6 +66,7 @@ class TreeView:
     order: torch.Tensor  # (n,) int64 caller index of each sorted body
     keys: torch.Tensor   # (n,) int64 Morton keys
     box: list
+    quad: torch.Tensor | None = None  # (nnodes, 6) xx, yy, zz, xy, xz, yz with quad=True
 
 
 class Context:
@@ -77,13 +78,15 @@ class Context:
 
     def __init__(self, n_max: int, leaf_size: int = 16, precision: str = "fp32c", G: float = 1.0,
                  counts: bool = False, timing: bool = False, walk_group: int = 0,
-                 adjoint: bool = False, max_scenes: int = 1, graph: bool = False):
+                 adjoint: bool = False, max_scenes: int = 1, graph: bool = False,
+                 quad: bool = False):
         self._lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: libbhx runs on the GPU only")
         prec = {"fp64": L.BH_FP64, "fp32c": L.BH_FP32C}[precision]
         flags = ((L.BH_FLAG_COUNTS if counts else 0) | (L.BH_FLAG_TIMING if timing else 0)
-                 | (L.BH_FLAG_ADJOINT if adjoint else 0) | (L.BH_FLAG_GRAPH if graph else 0))
+                 | (L.BH_FLAG_ADJOINT if adjoint else 0) | (L.BH_FLAG_GRAPH if graph else 0)
+                 | (L.BH_FLAG_QUAD if quad else 0))
         cfg = L.bh_config(int(n_max), int(leaf_size), prec, float(G), flags, int(walk_group),
                           int(max_scenes))
         self.device = torch.device("cuda", torch.cuda.current_device())
@@ -297,7 +300,8 @@ class Context:
         eps2 = dev(v.eps2, nn, torch.float64) if v.eps2 else None
         order = dev(v.order, n, torch.int32).to(torch.int64) & 0xFFFFFFFF
         keys = dev(v.keys, n, torch.int64)
-        return TreeView(n, nn, int(v.depth), info, mom, eps2, order, keys, list(v.box))
+        quad = dev(v.quad, 6 * nn, torch.float64).view(nn, 6) if v.quad else None
+        return TreeView(n, nn, int(v.depth), info, mom, eps2, order, keys, list(v.box), quad)
 
     def stats(self) -> dict:
         s = L.bh_stats_t()

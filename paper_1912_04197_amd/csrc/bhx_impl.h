@@ -92,6 +92,7 @@ struct Workspace {
     NodeInfo *ninfo = nullptr;
     NodeMom *nmom = nullptr;
     double *neps2 = nullptr;
+    double *nquad = nullptr;      // [node_cap][6] quadrupoles, only with BH_FLAG_QUAD
     SceneBox *box = nullptr;      // [max_scenes]
     TreeHeader *hdr = nullptr;
     int32_t *counts = nullptr;    // [n_cap][2] per-body walk counts, caller order
@@ -141,6 +142,7 @@ struct WalkParams {
     bool per_body_eps;
     int precision;
     int group;  // target bodies per wavefront: 64, 32 or 16
+    const double *nquad = nullptr;  // node quadrupoles: add their terms (or nullptr)
 };
 constexpr int kDefaultWalkGroup = 64;
 constexpr int64_t kSmallWalk = 131072;  // below this many bodies the default group is 16

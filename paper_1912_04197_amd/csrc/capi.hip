@@ -87,7 +87,7 @@ void free_ws(Workspace &w)
 {
     void *ptrs[] = {w.keys[0], w.keys[1], w.idx[0],  w.idx[1],      w.sort_counts,
                     w.sort_totals, w.body, w.beps2, w.ninfo, w.nmom, w.neps2, w.box,
-                    w.hdr, w.counts, w.scratch, w.red_part};
+                    w.hdr, w.counts, w.scratch, w.red_part, w.nquad};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (w.depth_host) (void)hipHostFree(w.depth_host);
@@ -197,6 +197,7 @@ bh_status force_tree(bh_ctx *c, const bhx::Layout &lay, const double *pos, const
     p.per_body_eps = eps != nullptr;
     p.precision = c->cfg.precision;
     p.group = walk_group(c, n);
+    p.nquad = w.nquad;
     p.groups = lay.groups;
     p.n_groups = lay.n_groups;
     BHX_HIP(c, bhx::launch_walk(w, c->stream, p));
@@ -377,7 +378,8 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
     if (cfg->precision != BH_FP64 && cfg->precision != BH_FP32C) return BH_E_INVALID;
     if (!std::isfinite(cfg->G)) return BH_E_INVALID;
     if (cfg->flags &
-        ~(uint32_t)(BH_FLAG_COUNTS | BH_FLAG_TIMING | BH_FLAG_ADJOINT | BH_FLAG_GRAPH))
+        ~(uint32_t)(BH_FLAG_COUNTS | BH_FLAG_TIMING | BH_FLAG_ADJOINT | BH_FLAG_GRAPH |
+                    BH_FLAG_QUAD))
         return BH_E_INVALID;
     if (cfg->max_scenes < 0 || cfg->max_scenes > bhx::kMaxScenes) return BH_E_INVALID;
     if (cfg->walk_group != 0 && cfg->walk_group != 16 && cfg->walk_group != 32 &&
@@ -433,6 +435,7 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
     }
     A(dalloc(&w.hdr, 1));
     if (cfg->flags & BH_FLAG_COUNTS) A(dalloc(&w.counts, 2 * n));
+    if (cfg->flags & BH_FLAG_QUAD) A(dalloc(&w.nquad, 6 * node_cap));
     A(dalloc(&w.scratch, 4 * n));
     A(dalloc(&w.red_part, (int64_t)bhx::kRedBlocks * 8));
     A(dalloc(&c->diag_out, 8));
@@ -624,6 +627,8 @@ bh_status bh_accel_vjp(bh_ctx *c, const double *pos, const double *mass, double 
     if (s) return s;
     if (!(c->cfg.flags & BH_FLAG_ADJOINT))
         return fail(c, BH_E_STATE, "the context was created without BH_FLAG_ADJOINT");
+    if ((c->cfg.flags & BH_FLAG_QUAD) && theta >= 0.0)
+        return fail(c, BH_E_STATE, "no VJP of the quadrupole walk (BH_FLAG_QUAD)");
     if (std::isnan(theta) || std::isinf(theta)) return fail(c, BH_E_INVALID, "theta not finite");
     if (!finite_nonneg(softening)) return fail(c, BH_E_INVALID, "softening must be finite and >= 0");
     if (n > 0 && (!lambda || !g_pos || !g_mass))
@@ -640,6 +645,8 @@ bh_status bh_leapfrog_vjp(bh_ctx *c, const double *pos, const double *vel, const
     if (s) return s;
     if (!(c->cfg.flags & BH_FLAG_ADJOINT))
         return fail(c, BH_E_STATE, "the context was created without BH_FLAG_ADJOINT");
+    if ((c->cfg.flags & BH_FLAG_QUAD) && theta >= 0.0)
+        return fail(c, BH_E_STATE, "no VJP of the quadrupole walk (BH_FLAG_QUAD)");
     if (std::isnan(theta) || std::isinf(theta)) return fail(c, BH_E_INVALID, "theta not finite");
     if (!finite_nonneg(softening)) return fail(c, BH_E_INVALID, "softening must be finite and >= 0");
     if (!std::isfinite(dt)) return fail(c, BH_E_INVALID, "dt not finite");
@@ -710,6 +717,7 @@ bh_status bh_tree_export(bh_ctx *c, bh_tree_view *out)
     out->info = (const int32_t *)c->w.ninfo;
     out->mom = (const double *)c->w.nmom;
     out->eps2 = c->tree_eps ? c->w.neps2 : nullptr;
+    out->quad = c->w.nquad;
     out->order = c->w.idx[0];
     out->keys = c->w.keys[0];
     for (int a = 0; a < 3; a++) {

@@ -525,8 +525,9 @@ __device__ inline void moments_nodes(int level, const int32_t *counts,
                                      const double *__restrict__ beps2,
                                      const uint64_t *__restrict__ keys,
                                      const SceneBox *__restrict__ box, NodeMom *__restrict__ nmom,
-                                     double *__restrict__ neps2, int64_t node_cap, int use_eps,
-                                     int64_t g_first, int64_t stride)
+                                     double *__restrict__ neps2, double *__restrict__ nquad,
+                                     int64_t node_cap, int use_eps, int64_t g_first,
+                                     int64_t stride)
 {
 #pragma clang fp contract(off)
     int32_t beg, cnt;
@@ -573,6 +574,34 @@ __device__ inline void moments_nodes(int level, const int32_t *counts,
         }
         nmom[k] = out;
         if (use_eps) neps2[k] = e2;
+        if (nquad) {
+            // traceless quadrupole about the centre of mass: from the bodies
+            // of a leaf, from the children by the parallel-axis shift
+            double q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            auto add = [&](double dx, double dy, double dz, double m) {
+                const double d2 = dx * dx + dy * dy + dz * dz;
+                q[0] += m * (3.0 * dx * dx - d2);
+                q[1] += m * (3.0 * dy * dy - d2);
+                q[2] += m * (3.0 * dz * dz - d2);
+                q[3] += m * 3.0 * dx * dy;
+                q[4] += m * 3.0 * dx * dz;
+                q[5] += m * 3.0 * dy * dz;
+            };
+            if (info.child0 < 0) {
+                for (int32_t s = info.first; s < info.first + info.count; s++) {
+                    const Body b = body[s];
+                    add(b.x - out.x, b.y - out.y, b.z - out.z, b.m);
+                }
+            } else {
+                const int nch = node_nchild(info);
+                for (int32_t c = info.child0; c < info.child0 + nch; c++) {
+                    const NodeMom cm = nmom[c];
+                    for (int a = 0; a < 6; a++) q[a] += nquad[6 * (int64_t)c + a];
+                    add(cm.x - out.x, cm.y - out.y, cm.z - out.z, cm.m);
+                }
+            }
+            for (int a = 0; a < 6; a++) nquad[6 * (int64_t)k + a] = q[a];
+        }
     }
 }
 
@@ -580,11 +609,11 @@ __global__ __launch_bounds__(256) void k_moments_level(
     int level, const TreeHeader *__restrict__ hdr, const NodeInfo *__restrict__ ninfo,
     const Body *__restrict__ body, const double *__restrict__ beps2,
     const uint64_t *__restrict__ keys, const SceneBox *__restrict__ box,
-    NodeMom *__restrict__ nmom, double *__restrict__ neps2, int64_t node_cap, int use_eps,
-    int32_t *__restrict__ depth_out)
+    NodeMom *__restrict__ nmom, double *__restrict__ neps2, double *__restrict__ nquad,
+    int64_t node_cap, int use_eps, int32_t *__restrict__ depth_out)
 {
-    moments_nodes(level, hdr->level_count, ninfo, body, beps2, keys, box, nmom, neps2, node_cap,
-                  use_eps, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
+    moments_nodes(level, hdr->level_count, ninfo, body, beps2, keys, box, nmom, neps2, nquad,
+                  node_cap, use_eps, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
     // the root level reports the deepest non-empty level, as a launch hint
     // for the next build (pinned host memory)
     if (level == 0 && depth_out && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -601,14 +630,15 @@ __global__ __launch_bounds__(1024) void k_moments_head(
     int from, const TreeHeader *__restrict__ hdr, const NodeInfo *__restrict__ ninfo,
     const Body *__restrict__ body, const double *__restrict__ beps2,
     const uint64_t *__restrict__ keys, const SceneBox *__restrict__ box,
-    NodeMom *__restrict__ nmom, double *__restrict__ neps2, int64_t node_cap, int use_eps,
-    int32_t *__restrict__ depth_out)
+    NodeMom *__restrict__ nmom, double *__restrict__ neps2, double *__restrict__ nquad,
+    int64_t node_cap, int use_eps, int32_t *__restrict__ depth_out)
 {
     __shared__ int32_t scnt[kLevels + 1];
     if (threadIdx.x <= kLevels) scnt[threadIdx.x] = hdr->level_count[threadIdx.x];
     __syncthreads();
     for (int level = from - 1; level >= 0; level--) {
-        moments_nodes(level, scnt, ninfo, body, beps2, keys, box, nmom, neps2, node_cap, use_eps,
+        moments_nodes(level, scnt, ninfo, body, beps2, keys, box, nmom, neps2, nquad, node_cap,
+                      use_eps,
                       threadIdx.x, 1024);
         __syncthreads();
     }
@@ -625,14 +655,16 @@ __global__ __launch_bounds__(1024) void k_moments_tail(
     int to, const TreeHeader *__restrict__ hdr, const NodeInfo *__restrict__ ninfo,
     const Body *__restrict__ body, const double *__restrict__ beps2,
     const uint64_t *__restrict__ keys, const SceneBox *__restrict__ box,
-    NodeMom *__restrict__ nmom, double *__restrict__ neps2, int64_t node_cap, int use_eps)
+    NodeMom *__restrict__ nmom, double *__restrict__ neps2, double *__restrict__ nquad,
+    int64_t node_cap, int use_eps)
 {
     __shared__ int32_t scnt[kLevels + 1];
     if (threadIdx.x <= kLevels) scnt[threadIdx.x] = hdr->level_count[threadIdx.x];
     __syncthreads();
     for (int level = kMaxLevel; level >= to; level--) {
         if (scnt[level] == 0) continue;  // the same on every thread
-        moments_nodes(level, scnt, ninfo, body, beps2, keys, box, nmom, neps2, node_cap, use_eps,
+        moments_nodes(level, scnt, ninfo, body, beps2, keys, box, nmom, neps2, nquad, node_cap,
+                      use_eps,
                       threadIdx.x, 1024);
         __syncthreads();
     }
@@ -654,7 +686,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_build_small(
     TreeHeader *__restrict__ hdr, uint64_t *__restrict__ k0, uint64_t *__restrict__ k1,
     uint32_t *__restrict__ i0, uint32_t *__restrict__ i1, Body *__restrict__ body,
     double *__restrict__ beps2, NodeInfo *__restrict__ ninfo, NodeMom *__restrict__ nmom,
-    double *__restrict__ neps2, int64_t node_cap, int32_t *__restrict__ depth_out)
+    double *__restrict__ neps2, double *__restrict__ nquad, int64_t node_cap,
+    int32_t *__restrict__ depth_out)
 {
     constexpr int W = kSmallThreads / 64;
     __shared__ unsigned long long red_lo[3], red_hi[3];
@@ -810,7 +843,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_build_small(
     // 6. moments, bottom-up
     for (int level = kMaxLevel; level >= 0; level--) {
         if (scnt[level] == 0) continue;  // the same on every thread
-        moments_nodes(level, scnt, ninfo, body, beps2, k0, box, nmom, neps2, node_cap,
+        moments_nodes(level, scnt, ninfo, body, beps2, k0, box, nmom, neps2, nquad, node_cap,
                       eps != nullptr, tid, kSmallThreads);
         __syncthreads();
     }
@@ -865,7 +898,7 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
     if (ns == 1 && n >= 1 && n <= kSmallBuild) {
         k_build_small<<<1, kSmallThreads, 0, s>>>(pos, mass, eps, n, leaf, w.box, w.hdr, w.keys[0],
                                                   w.keys[1], w.idx[0], w.idx[1], w.body, w.beps2,
-                                                  w.ninfo, w.nmom, w.neps2, w.node_cap,
+                                                  w.ninfo, w.nmom, w.neps2, w.nquad, w.node_cap,
                                                   w.depth_dev);
         return hipGetLastError();
     }
@@ -917,15 +950,17 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
         k_build_tail<<<1, 1024, 0, s>>>(deep, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
     const int use_eps = eps != nullptr;
     k_moments_tail<<<1, 1024, 0, s>>>(deep, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0], w.box,
-                                      w.nmom, w.neps2, w.node_cap, use_eps);
+                                      w.nmom, w.neps2, w.nquad, w.node_cap, use_eps);
     for (int level = deep - 1; level >= head; level--) {
         const unsigned g = blocks_for(level_bound(level, n, ns), 256, 4096);
         k_moments_level<<<g, 256, 0, s>>>(level, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0], w.box,
-                                          w.nmom, w.neps2, w.node_cap, use_eps, w.depth_dev);
+                                          w.nmom, w.neps2, w.nquad, w.node_cap, use_eps,
+                                          w.depth_dev);
     }
     if (head > 0)
         k_moments_head<<<1, 1024, 0, s>>>(head, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0], w.box,
-                                          w.nmom, w.neps2, w.node_cap, use_eps, w.depth_dev);
+                                          w.nmom, w.neps2, w.nquad, w.node_cap, use_eps,
+                                          w.depth_dev);
     return hipGetLastError();
 }
 

@@ -112,11 +112,31 @@ __device__ inline bool accept_node(double cx, double cy, double cz, double bx, d
     return s2 < th2 * D2;
 }
 
-template <int PREC, bool PEPS, bool PHI, bool CNT, int GB>
+// Quadrupole term of an accepted node with traceless Q (xx, yy, zz, xy, xz,
+// yz), d = COM - x_B, inv5 = 1/r^5 and ri2 = 1/r^2 of the softened distance:
+// a += -Q d / r^5 + 5/2 (d.Q d) d / r^7 and phi += -(d.Q d) / (2 r^5), before
+// the factor G.
+template <typename T>
+__device__ inline void quad_term(const T *Q, T dx, T dy, T dz, T inv5, T ri2, T &ax, T &ay, T &az,
+                                 T &ph)
+{
+    const T qx = Q[0] * dx + Q[3] * dy + Q[4] * dz;
+    const T qy = Q[3] * dx + Q[1] * dy + Q[5] * dz;
+    const T qz = Q[4] * dx + Q[5] * dy + Q[2] * dz;
+    const T dqd = dx * qx + dy * qy + dz * qz;
+    const T c = T(2.5) * dqd * inv5 * ri2;
+    ax += c * dx - qx * inv5;
+    ay += c * dy - qy * inv5;
+    az += c * dz - qz * inv5;
+    ph -= T(0.5) * dqd * inv5;
+}
+
+template <int PREC, bool PEPS, bool PHI, bool CNT, int GB, bool QUAD>
 __global__ __launch_bounds__(64) void k_walk(
     const Body *__restrict__ body, const double *__restrict__ beps2,
     const NodeInfo *__restrict__ ninfo, const NodeMom *__restrict__ nmom,
-    const double *__restrict__ neps2, const uint32_t *__restrict__ idx,
+    const double *__restrict__ neps2, const double *__restrict__ nquad,
+    const uint32_t *__restrict__ idx,
     const SceneBox *__restrict__ box, const int32_t *__restrict__ groups, int64_t n,
     int ngroups, int per_xcd, double th2, double eps0sq, double G, double *__restrict__ acc,
     double *__restrict__ phi, int32_t *__restrict__ counts)
@@ -125,6 +145,7 @@ __global__ __launch_bounds__(64) void k_walk(
     constexpr int LPB = 64 / GB;  // lanes per body
     constexpr uint64_t kBodyMask = GB == 64 ? ~0ull : ((1ull << GB) - 1ull);
     using Item = typename std::conditional<PREC == BH_FP64, ItemD, ItemF>::type;
+    using QT = typename std::conditional<PREC == BH_FP64, double, float>::type;
 
     // Items that reach at most kSparse bodies of the group are evaluated as
     // (item, body) pairs, one pair per lane, into per-body FP64 sums in LDS.
@@ -149,6 +170,7 @@ __global__ __launch_bounds__(64) void k_walk(
         struct {
             Item items[kBatch];      // dense items first, then the sparse ones
             uint16_t rec[kPairCap];  // pair: item slot << 6 | body
+            QT quad[QUAD ? 6 * kBatch : 1];  // node items' quadrupoles, by slot
         } ev;
     };
     __shared__ Shared sh;
@@ -159,6 +181,7 @@ __global__ __launch_bounds__(64) void k_walk(
     PopData *const pd = sh.pop.pd;
     Item *const items = sh.ev.items;
     uint16_t *const rec = sh.ev.rec;
+    QT *const qbuf = sh.ev.quad;
 
     // Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous
     // (so spatially compact) range of groups to share its L2.
@@ -227,6 +250,7 @@ __global__ __launch_bounds__(64) void k_walk(
         uint64_t mk = 0;
         int32_t src = 0;
         double x = 0.0, y = 0.0, z = 0.0, m = 0.0, e2 = 0.0;
+        double qn[QUAD ? 6 : 1] = {};
         // The descriptor of item consumed + lane: each descriptor that starts
         // inside the batch flags its first item (only the head descriptor can
         // start at item 0, and it may also start before the batch), so item
@@ -261,6 +285,8 @@ __global__ __launch_bounds__(64) void k_walk(
                 const NodeMom nm = nmom[~a];
                 x = nm.x, y = nm.y, z = nm.z, m = nm.m;
                 e2 = PEPS ? neps2[~a] : 0.0;
+                if constexpr (QUAD)
+                    for (int t = 0; t < 6; t++) qn[t] = nquad[6 * (int64_t)(~a) + t];
             }
         }
         // Split the batch: an item reaching at most kSparse bodies becomes
@@ -284,6 +310,9 @@ __global__ __launch_bounds__(64) void k_walk(
                 items[slot] = ItemF{x,   y, z, (float)m, (float)(0.5 * e2), (uint32_t)mk,
                                     (uint32_t)(mk >> 32), src, 0};
             }
+            if constexpr (QUAD)
+                if (src < 0)
+                    for (int t = 0; t < 6; t++) qbuf[6 * slot + t] = (QT)qn[t];
             if (fits) {
                 uint64_t bits = mk;
                 uint32_t at = pend - pv;
@@ -297,7 +326,8 @@ __global__ __launch_bounds__(64) void k_walk(
         if constexpr (PREC == BH_FP64) {
 #pragma unroll 1
             for (int jj = 0; jj < nd; jj += LPB) {
-                const ItemD it = items[jj + sub < nd ? jj + sub : jj];
+                const int j = jj + sub < nd ? jj + sub : jj;
+                const ItemD it = items[j];
                 const bool on = jj + sub < nd && ((it.mask >> bq) & 1ull);
                 const double dx = it.x - me.x, dy = it.y - me.y, dz = it.z - me.z;
                 const double e2 = PEPS ? 0.5 * (eb2 + it.e2) : eps0sq;
@@ -309,6 +339,9 @@ __global__ __launch_bounds__(64) void k_walk(
                     ay += it.m * dy * inv3;
                     az += it.m * dz * inv3;
                     if (PHI) ph -= it.m / r;
+                    if constexpr (QUAD)
+                        if (it.src < 0)
+                            quad_term(qbuf + 6 * j, dx, dy, dz, inv3 / r2, 1.0 / r2, ax, ay, az, ph);
                 }
                 if (CNT && on) {
                     if (it.src < 0)
@@ -346,6 +379,12 @@ __global__ __launch_bounds__(64) void k_walk(
                     fy = fmaf(mr3, dy, fy);
                     fz = fmaf(mr3, dz, fz);
                     if (PHI) fp -= mr;
+                    if constexpr (QUAD)
+                        if (it.src < 0) {
+                            const float ri2 = rinv * rinv;
+                            quad_term(qbuf + 6 * (j < jn ? j : jj), dx, dy, dz, ri2 * ri2 * rinv, ri2,
+                                      fx, fy, fz, fp);
+                        }
                     if (CNT && on) {
                         if (it.src < 0)
                             cnode++;
@@ -384,6 +423,9 @@ __global__ __launch_bounds__(64) void k_walk(
                     fy = it.m * dy * inv3;
                     fz = it.m * dz * inv3;
                     if (PHI) fp = -it.m / rr;
+                    if constexpr (QUAD)
+                        if (src_node)
+                            quad_term(qbuf + 6 * k, dx, dy, dz, inv3 / r2, 1.0 / r2, fx, fy, fz, fp);
                 }
             } else {
                 const float te = __shfl(e2hB, b);
@@ -395,10 +437,16 @@ __global__ __launch_bounds__(64) void k_walk(
                 const float rinv = (on && r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;
                 const float mr = it.m * rinv;
                 const float mr3 = mr * rinv * rinv;
-                fx = (double)(mr3 * dx);
-                fy = (double)(mr3 * dy);
-                fz = (double)(mr3 * dz);
-                if (PHI) fp = -(double)mr;
+                float gxf = mr3 * dx, gyf = mr3 * dy, gzf = mr3 * dz, gpf = -mr;
+                if constexpr (QUAD)
+                    if (src_node) {
+                        const float ri2 = rinv * rinv;
+                        quad_term(qbuf + 6 * k, dx, dy, dz, ri2 * ri2 * rinv, ri2, gxf, gyf, gzf, gpf);
+                    }
+                fx = (double)gxf;
+                fy = (double)gyf;
+                fz = (double)gzf;
+                if (PHI) fp = (double)gpf;
             }
             if (on) {
                 __hip_atomic_fetch_add(&pacc[3 * b], fx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -582,14 +630,14 @@ __global__ __launch_bounds__(64) void k_walk(
     }
 }
 
-template <int PREC, bool PEPS, bool PHI, bool CNT, int GB>
+template <int PREC, bool PEPS, bool PHI, bool CNT, int GB, bool QUAD>
 hipError_t launch_t(const Workspace &w, hipStream_t s, const WalkParams &p)
 {
     const int ngroups = p.groups ? p.n_groups : (int)((p.n + GB - 1) / GB);
     const int per_xcd = (ngroups + 7) / 8;
     if (ngroups == 0) return hipSuccess;
-    k_walk<PREC, PEPS, PHI, CNT, GB><<<8 * per_xcd, 64, 0, s>>>(
-        w.body, w.beps2, w.ninfo, w.nmom, w.neps2, w.idx[0], w.box, p.groups, p.n, ngroups,
+    k_walk<PREC, PEPS, PHI, CNT, GB, QUAD><<<8 * per_xcd, 64, 0, s>>>(
+        w.body, w.beps2, w.ninfo, w.nmom, w.neps2, p.nquad, w.idx[0], w.box, p.groups, p.n, ngroups,
         per_xcd, p.th2, p.eps0sq, p.G, p.acc, p.phi, p.counts);
     return hipGetLastError();
 }
@@ -598,9 +646,15 @@ template <int PREC, bool PEPS, bool PHI, bool CNT>
 hipError_t launch_g(const Workspace &w, hipStream_t s, const WalkParams &p)
 {
     switch (p.group) {
-        case 64: return launch_t<PREC, PEPS, PHI, CNT, 64>(w, s, p);
-        case 32: return launch_t<PREC, PEPS, PHI, CNT, 32>(w, s, p);
-        default: return launch_t<PREC, PEPS, PHI, CNT, 16>(w, s, p);
+        case 64:
+            return p.nquad ? launch_t<PREC, PEPS, PHI, CNT, 64, true>(w, s, p)
+                           : launch_t<PREC, PEPS, PHI, CNT, 64, false>(w, s, p);
+        case 32:
+            return p.nquad ? launch_t<PREC, PEPS, PHI, CNT, 32, true>(w, s, p)
+                           : launch_t<PREC, PEPS, PHI, CNT, 32, false>(w, s, p);
+        default:
+            return p.nquad ? launch_t<PREC, PEPS, PHI, CNT, 16, true>(w, s, p)
+                           : launch_t<PREC, PEPS, PHI, CNT, 16, false>(w, s, p);
     }
 }
 

@@ -63,7 +63,7 @@ def _cfg(**kw):
 
 
 @pytest.mark.parametrize("bad", [dict(n_max=-1), dict(leaf_size=0), dict(leaf_size=65),
-                                 dict(precision=7), dict(G=float("nan")), dict(flags=16),
+                                 dict(precision=7), dict(G=float("nan")), dict(flags=32),
                                  dict(max_scenes=-1), dict(max_scenes=70000),
                                  dict(walk_group=8), dict(walk_group=48)])
 def test_create_rejects_bad_config(lib, bad):
