@@ -90,6 +90,8 @@ def _load(path: str | None = None):
     lib.orc_leapfrog.restype = C.c_int
     lib.orc_euler.argtypes = [I64, P, P, P, P, D, D, D, I32, D, I32, I32, P]
     lib.orc_euler.restype = C.c_int
+    lib.orc_contact_components.argtypes = [I64, P, P, D, P, P, P]
+    lib.orc_contact_components.restype = C.c_int
     lib.orc_diagnostics.argtypes = [I64, P, P, P, P, D, D, P]
     lib.orc_diagnostics.restype = C.c_int
     lib.orc_direct_vjp.argtypes = [I64, P, P, P, D, D, P, P, P]
@@ -313,6 +315,21 @@ def euler(pos, vel, mass, dt, nsteps, every=1, softening=0.0, eps=None, theta=-1
                          float(G), float(theta), int(leaf), float(dt), int(nsteps), int(every),
                          _ptr(acc)))
     return pos, vel, acc
+
+
+def contact_components(pos, radius, skin=0.0):
+    """(label, n_contacts, n_aggregates): label[i] = smallest index of body i's
+    contact component (all pairs tested; O(N^2))."""
+    lib = _load()
+    pos = _f64(pos)
+    n = pos.shape[0]
+    radius = _f64(radius, (n,))
+    label = np.zeros(n, np.int32)
+    nc = C.c_int64(0)
+    na = C.c_int64(0)
+    _check(lib.orc_contact_components(n, _ptr(pos), _ptr(radius), float(skin), _ptr(label),
+                                      C.byref(nc), C.byref(na)))
+    return label, int(nc.value), int(na.value)
 
 
 def diagnostics(pos, vel, mass, softening=0.0, eps=None, G=1.0) -> np.ndarray:

@@ -571,6 +571,53 @@ int orc_euler(int64_t n, double *pos, double *vel, const double *mass, const dou
     return 0;
 }
 
+/* ------------------------------------------------------------- aggregates */
+
+static int64_t uf_find(int32_t *parent, int64_t x)
+{
+    while (parent[x] != x) x = parent[x];
+    return x;
+}
+
+int orc_contact_components(int64_t n, const double *pos, const double *radius, double skin,
+                           int32_t *label, int64_t *n_contacts, int64_t *n_aggregates)
+{
+    if (n < 0 || n > 2147483647 || !(skin >= 0.0) || !isfinite(skin)) return 1;
+    if (n > 0 && (!pos || !radius || !label || !n_contacts || !n_aggregates)) return 1;
+    for (int64_t i = 0; i < n; i++) label[i] = (int32_t)i;
+    int64_t contacts = 0;
+    for (int64_t i = 0; i < n; i++) {
+        for (int64_t j = i + 1; j < n; j++) {
+            double dx = pos[3 * j] - pos[3 * i];
+            double dy = pos[3 * j + 1] - pos[3 * i + 1];
+            double dz = pos[3 * j + 2] - pos[3 * i + 2];
+            double dist2 = dx * dx + dy * dy + dz * dz;
+            double R = radius[i] + radius[j] + skin;
+            if (dist2 <= R * R) {
+                contacts++;
+                /* union: the larger root is attached to the smaller */
+                int64_t a = uf_find(label, i), b = uf_find(label, j);
+                if (a != b) {
+                    if (a < b)
+                        label[b] = (int32_t)a;
+                    else
+                        label[a] = (int32_t)b;
+                }
+            }
+        }
+    }
+    int64_t *size = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    if (!size) return 4;
+    for (int64_t i = 0; i < n; i++) label[i] = (int32_t)uf_find(label, i);
+    for (int64_t i = 0; i < n; i++) size[label[i]]++;
+    int64_t agg = 0;
+    for (int64_t i = 0; i < n; i++) agg += size[i] > 1;
+    free(size);
+    *n_contacts = contacts;
+    *n_aggregates = agg;
+    return 0;
+}
+
 int orc_diagnostics(int64_t n, const double *pos, const double *vel, const double *mass,
                     const double *eps, double eps0, double G, double out[8])
 {

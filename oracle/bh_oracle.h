@@ -92,6 +92,17 @@ int orc_euler(int64_t n, double *pos, double *vel, const double *mass, const dou
               double eps0, double G, double theta, int32_t leaf, double dt, int32_t nsteps,
               int32_t every, double *acc);
 
+/* Aggregate identification (Section "Post-processing: aggregate
+ * identification"): bodies are the vertices of a graph whose edges are the
+ * contacts; aggregates are its connected components with more than one body.
+ * A contact here is two spheres of radii r_i, r_j closer than
+ * r_i + r_j + skin: |x_i - x_j|^2 <= (r_i + r_j + skin)^2 in FP64 as written.
+ * label[i] = smallest body index of i's component; *n_contacts = number of
+ * contact pairs; *n_aggregates = components with more than one body. All
+ * pairs are tested. */
+int orc_contact_components(int64_t n, const double *pos, const double *radius, double skin,
+                           int32_t *label, int64_t *n_contacts, int64_t *n_aggregates);
+
 /* out[0] kinetic energy, out[1] potential energy 1/2 sum m phi (direct sum),
  * out[2..4] linear momentum, out[5..7] angular momentum about the origin. */
 int orc_diagnostics(int64_t n, const double *pos, const double *vel, const double *mass,

@@ -457,6 +457,47 @@ def pin_quad_improves_accuracy():
     assert np.abs(a0 - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
+# --------------------------------------------------------------- aggregates
+
+def pin_contacts_hand_built():
+    """A chain of touching spheres (centre distance exactly r_i + r_j counts as
+    contact), a pair a hair too far apart, and two single bodies: components
+    and contact counts by hand; the skin closes the gap."""
+    r = np.array([0.5, 0.25, 0.25, 0.5, 1.0, 1.0, 0.1, 0.1])
+    pos = np.array([[0, 0, 0], [0.75, 0, 0], [1.25, 0, 0], [2.0, 0, 0],   # chain 0-1-2-3
+                    [10, 0, 0], [12.0 + 1e-9, 0, 0],                      # gap 1e-9
+                    [20, 0, 0], [30, 0, 0]], float)                       # singles
+    label, nc, na = oracle.contact_components(pos, r)
+    assert label.tolist() == [0, 0, 0, 0, 4, 5, 6, 7] and nc == 3 and na == 1
+    label, nc, na = oracle.contact_components(pos, r, skin=1e-6)
+    assert label.tolist() == [0, 0, 0, 0, 4, 4, 6, 7] and nc == 4 and na == 2
+
+
+def pin_contacts_scipy_components():
+    """Random spheres: the partition into components equals scipy's connected
+    components of the contact graph, labels are each component's smallest
+    index, and aggregates are the components with more than one body."""
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+
+    rng = np.random.default_rng(61)
+    n = 500
+    pos = rng.random((n, 3))
+    r = 0.02 * rng.random(n) + 0.01
+    label, nc, na = oracle.contact_components(pos, r)
+    d2 = ((pos[:, None, :] - pos[None, :, :]) ** 2).sum(-1)
+    R = r[:, None] + r[None, :]
+    i, j = np.nonzero(np.triu(d2 <= R * R, 1))
+    assert nc == len(i) > 0
+    k, comp = connected_components(coo_matrix((np.ones(len(i)), (i, j)), shape=(n, n)),
+                                   directed=False)
+    for c in range(k):
+        members = np.nonzero(comp == c)[0]
+        assert np.all(label[members] == members.min())
+    sizes = np.bincount(comp)
+    assert na == int((sizes > 1).sum()) and len(np.unique(label)) == k
+
+
 # ------------------------------------------------------------- semi-implicit Euler
 
 def pin_euler_held_gravity_closed_form():

@@ -16,6 +16,10 @@ import oracle
 SRC = os.path.join(os.path.dirname(oracle.__file__), "bh_oracle.c")
 
 MUTANTS = {
+    "contact_strict": ("if (dist2 <= R * R) {", "if (dist2 < R * R) {"),
+    "contact_union_larger": ("label[b] = (int32_t)a;\n                    else\n                        label[a] = (int32_t)b;",
+                             "label[a] = (int32_t)b;\n                    else\n                        label[b] = (int32_t)a;"),
+    "contact_aggregate_singles": ("agg += size[i] > 1;", "agg += size[i] > 0;"),
     "quad_sign": ("acc[0] += G * (-qd[0] * inv5 + 2.5 * dqd * dx * inv7);",
                   "acc[0] += G * (qd[0] * inv5 + 2.5 * dqd * dx * inv7);"),
     "quad_trace_kept": ("q[0] += m * (3.0 * d[0] * d[0] - d2);", "q[0] += m * (3.0 * d[0] * d[0]);"),
