@@ -355,6 +355,43 @@ def bench_quadrupole(n=131072, thetas=(0.3, 0.5, 0.7, 0.9), soft=1e-3):
     return out
 
 
+def bench_contacts(n=1 << 20, scale=4.0, n_small=20000):
+    """Aggregate identification: contact graph of the rubble pile's spheres
+    (radii scaled so that contacts exist) and its connected components; the
+    O(N^2) oracle is timed beside it on a smaller pile."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1912_04197_amd import ics
+    from paper_1912_04197_amd.api import Context
+
+    out = {}
+    for label, size in (("large", n), ("small", n_small)):
+        sc = ics.rubble_pile(size, seed=33)
+        r = scale * sc.eps
+        ctx = Context(size)
+        P, M, R = (torch.from_numpy(a).cuda() for a in (sc.pos, sc.mass, r))
+        lab, nc, na = ctx.contact_components(P, M, R)
+        reps = 5
+        ms = _sync_time(lambda: [ctx.contact_components(P, M, R) for _ in range(reps)]) / reps
+        ctx.close()
+        sizes = np.bincount(lab.cpu().numpy())
+        row = {"n": size, "ms": round(ms, 3), "contacts": nc, "aggregates": na,
+               "largest_aggregate": int(sizes.max())}
+        if label == "small":
+            t0 = time.perf_counter()
+            lab_ref, nc_ref, na_ref = oracle.contact_components(sc.pos, r)
+            row["oracle_s"] = round(time.perf_counter() - t0, 3)
+            row["matches_oracle"] = bool(nc_ref == nc and na_ref == na and
+                                         np.array_equal(lab_ref, lab.cpu().numpy()))
+        out[label] = row
+    out["workload"] = (f"rubble pile (seed 33) spheres of radius {scale} x eps, contact iff "
+                       "|x_i - x_j| <= r_i + r_j; tree build + contact search + union-find")
+    log(f"contacts: {out['large']}")
+    return out
+
+
 def bench_crossover(ns=(1000, 2048, 4000, 16000, 64000), thetas=(0.25, 0.5, 0.75), soft=1e-3):
     """The paper's timing experiment on this GPU: one FP64 force evaluation
     (tree rebuilt) against the FP64 direct sum on uniform random cubes."""
@@ -606,6 +643,7 @@ def main():
         result["crossover"] = bench_crossover()
         result["cold_collapse"] = bench_cold_collapse()
         result["quadrupole"] = bench_quadrupole()
+        result["contacts"] = bench_contacts()
 
     if not args.no_cpu:
         import oracle

@@ -195,6 +195,22 @@ bh_status bh_batched_step(bh_ctx *ctx, int32_t n_scenes, const int64_t *offsets,
                           double *vel, const double *mass, double softening, const double *eps,
                           double theta, double dt, int32_t nsteps, double *acc);
 
+/* Aggregate identification (Section "Post-processing: aggregate
+ * identification"): the graph whose vertices are the bodies and whose edges
+ * are their contacts, and its connected components. A contact is two spheres
+ * (radius: n float64, >= 0, device) whose centres are within
+ * r_i + r_j + skin: |x_i - x_j|^2 <= (r_i + r_j + skin)^2 in FP64 as written.
+ * label (n int32, device, caller order) receives for every body the smallest
+ * index of its component; *n_contacts the number of contact pairs and
+ * *n_aggregates the number of components with more than one body (host
+ * outputs). Builds the tree of pos/mass (the build's checks apply to radius as
+ * a softening array) and synchronises. Errors: as bh_build_tree, plus
+ * BH_E_INVALID for a NULL radius, label or count output, skin negative or not
+ * finite; BH_E_CAPACITY for n >= 2^31. */
+bh_status bh_contact_components(bh_ctx *ctx, const double *pos, const double *mass,
+                                const double *radius, double skin, int32_t *label,
+                                int64_t *n_contacts, int64_t *n_aggregates, int64_t n);
+
 /* Autotuner for bh_batched_step: times every bucket size in {4, 8, 16, 32}
  * and walk group size in {16, 32, 64} (other settings from *base) on scratch
  * copies of the given state (the caller's arrays are not modified): one

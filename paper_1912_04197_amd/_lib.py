@@ -55,6 +55,7 @@ SIGNATURES = {
     "bh_compute_accel_direct": ([P, P, P, D, P, P, P, I64], C.c_int),
     "bh_step_leapfrog": ([P, P, P, P, D, P, D, D, I32, P, I64], C.c_int),
     "bh_step_euler": ([P, P, P, P, D, P, D, D, I32, I32, P, I64], C.c_int),
+    "bh_contact_components": ([P, P, P, P, D, P, C.POINTER(I64), C.POINTER(I64), I64], C.c_int),
     "bh_walk_counts": ([P, P, I64], C.c_int),
     "bh_tree_export": ([P, C.POINTER(bh_tree_view)], C.c_int),
     "bh_stats": ([P, C.POINTER(bh_stats_t)], C.c_int),

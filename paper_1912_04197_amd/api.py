@@ -195,6 +195,18 @@ class Context:
         if sync:
             self.sync()
 
+    def contact_components(self, pos, mass, radius, skin=0.0):
+        """(label (n,) int32 tensor, n_contacts, n_aggregates); see
+        bh_contact_components."""
+        n = self._bodies(pos, mass, radius)
+        label = torch.empty(n, dtype=torch.int32, device=self.device)
+        nc, na = C.c_int64(0), C.c_int64(0)
+        self._bind()
+        self._rc(self._lib.bh_contact_components(self._h, _ptr(pos), _ptr(mass), _ptr(radius),
+                                                 float(skin), _ptr(label), C.byref(nc),
+                                                 C.byref(na), n))
+        return label, int(nc.value), int(na.value)
+
     @staticmethod
     def _offsets(offsets):
         import numpy as np

@@ -79,6 +79,32 @@ struct Layout {
 constexpr int kBoxChunk = 4096;  // bodies per bbox work item
 constexpr int64_t kSmallBuild = 4096;  // a single scene this small is built by one block
 
+// Morton interleave of 21-bit cell coordinates (x in the highest bit of
+// each triplet) and its inverse.
+// Spreads the low 21 bits of v so that bit i lands on bit 3i.
+__device__ inline uint64_t spread3(uint64_t v)
+{
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+// Inverse of spread3.
+__device__ inline uint32_t compact3(uint64_t v)
+{
+    v &= 0x1249249249249249ull;
+    v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
+    v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
+    v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
+    v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
+    v = (v ^ (v >> 32)) & 0x1fffffull;
+    return (uint32_t)v;
+}
+
 // Workspace owned by a context; sized once for n_max bodies.
 struct Workspace {
     int64_t n_cap = 0, node_cap = 0;
@@ -179,6 +205,11 @@ hipError_t launch_copy(hipStream_t s, double *dst, const double *src, int64_t co
 // integrate.hip
 hipError_t launch_kick_drift(hipStream_t s, double *pos, double *vel, const double *acc, int64_t n,
                              double dt);
+// contacts.hip: contact components of the bodies of the last build (label
+// in caller order, size: n int32 scratch, counters: 3 device words).
+hipError_t launch_contacts(const Workspace &w, hipStream_t s, const double *radius, int64_t n,
+                           double skin, int32_t *label, int32_t *size,
+                           unsigned long long *counters);
 hipError_t launch_euler_substeps(hipStream_t s, double *pos, double *vel, const double *acc,
                                  int64_t n, double dt, int k);
 hipError_t launch_kick(hipStream_t s, double *vel, const double *acc, int64_t n, double dt);

@@ -585,6 +585,33 @@ bh_status bh_step_euler(bh_ctx *c, double *pos, double *vel, const double *mass,
     return BH_OK;
 }
 
+bh_status bh_contact_components(bh_ctx *c, const double *pos, const double *mass,
+                                const double *radius, double skin, int32_t *label,
+                                int64_t *n_contacts, int64_t *n_aggregates, int64_t n)
+{
+    bh_status s = check_bodies(c, pos, mass, n);
+    if (s) return s;
+    if (!finite_nonneg(skin)) return fail(c, BH_E_INVALID, "skin must be finite and >= 0");
+    if (!n_contacts || !n_aggregates) return fail(c, BH_E_INVALID, "NULL count outputs");
+    if (n > 0 && (!radius || !label)) return fail(c, BH_E_INVALID, "NULL radius or label");
+    if (n > INT32_MAX) return fail(c, BH_E_CAPACITY, "labels are int32");
+    *n_contacts = 0;
+    *n_aggregates = 0;
+    if (n == 0) return BH_OK;
+    BHX_HIP(c, bhx::launch_build(c->w, c->stream, single(n), pos, mass, radius, c->cfg.leaf_size));
+    c->tree_n = n;
+    c->tree_eps = true;
+    auto *counters = (unsigned long long *)c->diag_out;
+    BHX_HIP(c, bhx::launch_contacts(c->w, c->stream, radius, n, skin, label,
+                                    (int32_t *)c->w.scratch, counters));
+    unsigned long long h[2];
+    BHX_HIP(c, hipMemcpyAsync(h, counters, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    BHX_HIP(c, hipStreamSynchronize(c->stream));
+    *n_contacts = (int64_t)h[0];
+    *n_aggregates = (int64_t)h[1];
+    return bh_sync(c);
+}
+
 bh_status bh_batched_accel(bh_ctx *c, int32_t n_scenes, const int64_t *offsets, const double *pos,
                            const double *mass, double softening, const double *eps, double theta,
                            double *acc, double *phi)

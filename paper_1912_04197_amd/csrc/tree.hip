@@ -194,30 +194,6 @@ __global__ __launch_bounds__(256) void k_box_final(SceneBox *__restrict__ box, i
 
 // --------------------------------------------------------------- 2. keys
 
-// Spreads the low 21 bits of v so that bit i lands on bit 3i.
-__device__ inline uint64_t spread3(uint64_t v)
-{
-    v &= 0x1fffffull;
-    v = (v | (v << 32)) & 0x1f00000000ffffull;
-    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
-    v = (v | (v << 8)) & 0x100f00f00f00f00full;
-    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
-    v = (v | (v << 2)) & 0x1249249249249249ull;
-    return v;
-}
-
-// Inverse of spread3.
-__device__ inline uint32_t compact3(uint64_t v)
-{
-    v &= 0x1249249249249249ull;
-    v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
-    v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
-    v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
-    v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
-    v = (v ^ (v >> 32)) & 0x1fffffull;
-    return (uint32_t)v;
-}
-
 // Integer cell coordinate: clamp(floor((x - x0) * S), 0, 2^21 - 1), rounded
 // exactly as written so every implementation of the cell definition agrees.
 __device__ inline uint32_t quantise(double x, double x0, double S)

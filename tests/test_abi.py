@@ -87,6 +87,7 @@ def test_null_context_calls(lib):
     assert lib.bh_batched_accel(None, 1, None, None, None, 0.0, None, 0.5, None, None) == L.BH_E_INVALID
     assert lib.bh_autotune(None, None, 1, None, None, None, None, 0.0, None, 0.5, 1e-3, 1, None) == L.BH_E_INVALID
     assert lib.bh_step_euler(None, None, None, None, 0.0, None, 0.5, 1e-3, 1, 1, None, 0) == L.BH_E_INVALID
+    assert lib.bh_contact_components(None, None, None, None, 0.0, None, None, None, 0) == L.BH_E_INVALID
     assert lib.bh_batched_step(None, 1, None, None, None, None, 0.0, None, 0.5, 1e-3, 1, None) == L.BH_E_INVALID
     assert lib.bh_last_error(None) == b"NULL context"
     lib.bh_destroy(None)
