@@ -105,6 +105,30 @@ __device__ inline uint32_t compact3(uint64_t v)
     return (uint32_t)v;
 }
 
+// Number of set bits of m below this lane.
+__device__ inline uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave (exact, integer), by DPP
+// lane moves: four shifts within each row of 16 lanes, then the last lane of
+// row 0 is added to row 1 and of row 2 to row 3, and the last lane of row 1
+// to rows 2 and 3. Every lane of the wave must be active.
+__device__ inline uint32_t wave_incl_scan(uint32_t v)
+{
+    constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+    int x = (int)v;
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 1, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 2, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 4, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowShr + 8, 0xf, 0xf, true);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowBcast15, 0xa, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kRowBcast31, 0xc, 0xf, false);
+    return (uint32_t)x;
+}
+
 // Workspace owned by a context; sized once for n_max bodies.
 struct Workspace {
     int64_t n_cap = 0, node_cap = 0;

@@ -43,10 +43,7 @@ __device__ inline T wave_max(T v)
 __device__ inline uint32_t block_incl_scan_256(uint32_t v, uint32_t *lds4, uint32_t *total)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t t = __shfl_up(v, o);
-        if (lane >= o) v += t;
-    }
+    v = wave_incl_scan(v);
     if (lane == 63) lds4[wave] = v;
     __syncthreads();
     uint32_t add = 0, tot = 0;
@@ -745,11 +742,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_build_small(
         // barriers are reached by every thread of the block
         {
             const uint32_t h = tid < 256 ? hist[tid] : 0u;
-            uint32_t v = h;
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t t = __shfl_up(v, o);
-                if (lane >= o) v += t;
-            }
+            const uint32_t v = wave_incl_scan(h);
             if (lane == 63 && wave < 4) lds4[wave] = v;
             __syncthreads();
             if (tid < 256) {

@@ -53,6 +53,7 @@ constexpr int kReserve = 150;  // a depth-first descent adds <= 7 ranges per lev
 constexpr int kRanges = 8;     // ranges popped per round (<= 8 nodes each)
 constexpr int kPop = 8 * kRanges;
 constexpr int kRing = 128;     // interaction descriptors: <= 64 left over + 64 new
+static_assert((kRing & (kRing - 1)) == 0, "ring indices wrap by masking");
 constexpr int kBatch = 64;     // items staged per evaluation batch
 constexpr int kFlush = 16;     // FP32 partial sums span at most this many items per lane
 constexpr int kPairCap = 448;  // body pairs evaluated one per lane in one batch
@@ -84,23 +85,6 @@ struct alignas(16) PopData {  // popped node as the bookkeeping needs it
     int32_t node, first, count, child0;  // child0 < 0: leaf
     int32_t nch, pad;
 };
-
-__device__ inline uint32_t lanes_below(uint64_t m)  // set bits of m below this lane
-{
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-// Inclusive prefix sum over the 64 lanes (exact, integer).
-__device__ inline uint32_t wave_incl_scan(uint32_t v)
-{
-    const int lane = threadIdx.x;
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t t = __shfl_up(v, o);
-        if (lane >= o) v += t;
-    }
-    return v;
-}
 
 // The opening test, rounded exactly as written: accept iff s^2 < theta^2 D^2.
 __device__ inline bool accept_node(double cx, double cy, double cz, double bx, double by,
@@ -261,7 +245,7 @@ __global__ __launch_bounds__(64) void k_walk(
 #pragma unroll
         for (int h = 0; h < kRing; h += 64) {
             if (h + lane < dq_tail - dq_head) {
-                const uint32_t rel = dq_at[(dq_head + h + lane) % kRing] - consumed;
+                const uint32_t rel = dq_at[(dq_head + h + lane) & (kRing - 1)] - consumed;
                 if (rel < (uint32_t)c) flag[rel] = 1;
             }
         }
@@ -270,7 +254,7 @@ __global__ __launch_bounds__(64) void k_walk(
         const int dsel = (int)lanes_below(starts) + (int)((starts >> lane) & 1ull);
         if (lane < c) {
             const uint32_t q = consumed + (uint32_t)lane;
-            const int d = (dq_head + dsel) % kRing;
+            const int d = (dq_head + dsel) & (kRing - 1);
             const int32_t a = dq_a[d];
             mk = dq_mask[d];
             if (a >= 0) {
@@ -466,7 +450,7 @@ __global__ __launch_bounds__(64) void k_walk(
             const int da = dq_head + lane;
             bool done = false;
             if (da < dq_tail) {
-                const int d = da % kRing;
+                const int d = da & (kRing - 1);
                 done = dq_at[d] + (uint32_t)dq_n[d] <= consumed;
             }
             dq_head += __popcll(__ballot(done));
@@ -581,7 +565,7 @@ __global__ __launch_bounds__(64) void k_walk(
         const uint32_t nitems = leaf ? (uint32_t)my.count : (A != 0 ? 1u : 0u);
         const uint32_t incl = wave_incl_scan(nitems);
         if (hasq) {
-            const int d = (dq_tail + (int)lanes_below(qb)) % kRing;
+            const int d = (dq_tail + (int)lanes_below(qb)) & (kRing - 1);
             dq_a[d] = leaf ? my.first : ~my.node;
             dq_n[d] = (int32_t)nitems;
             dq_at[d] = queued + incl - nitems;
