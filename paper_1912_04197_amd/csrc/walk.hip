@@ -27,8 +27,9 @@
 //
 // Evaluation: the interaction queue holds descriptors (a leaf's body range or
 // one accepted node, with a body mask). Whenever 64 items are queued, lane k
-// expands item k (binary search over the descriptors' item offsets) and loads
-// it. An item that reaches more than GB / 4 bodies of the group is dense: the
+// expands item k (each descriptor starting inside the batch flags its first
+// item; a ballot of the flags gives every item its descriptor) and loads it.
+// An item that reaches more than GB / 6 bodies of the group is dense: the
 // dense items are staged in LDS and the lanes of each body sweep them, each
 // taking every (64 / GB)-th one. A sparse item becomes (item, body) pairs, one
 // pair per lane, whose terms are added into per-body FP64 sums in LDS; most
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(64) void k_walk(
 
     // Items that reach at most kSparse bodies of the group are evaluated as
     // (item, body) pairs, one pair per lane, into per-body FP64 sums in LDS.
-    constexpr int kSparse = GB / 4;
+    constexpr int kSparse = GB / 6;
     constexpr int kSweepUnroll = GB == 64 ? 4 : 1;
 
     __shared__ int32_t st_c0[kStack];
