@@ -55,7 +55,8 @@ typedef enum {
     BH_E_CAPACITY = 3,  /* n > n_max, or the node table overflowed */
     BH_E_OOM = 4,       /* device allocation failed */
     BH_E_HIP = 5,       /* a HIP runtime call failed; see bh_last_error() */
-    BH_E_STACK = 6,     /* the tree walk overflowed its traversal stack */
+    BH_E_STACK = 6,     /* reserved: an unknown device status; the walk's traversal stack is
+                           sized so that trees of at most 21 levels cannot overflow it */
     BH_E_STATE = 7      /* call out of order, e.g. bh_tree_export() before any build */
 } bh_status;
 
@@ -136,8 +137,7 @@ bh_status bh_build_tree(bh_ctx *ctx, const double *pos, const double *mass, cons
  * it once per body with opening parameter theta (>= 0; 0 opens every node and
  * gives the direct sum's pair set). softening >= 0 is used when eps == NULL.
  * acc (n x 3) is overwritten; phi may be NULL. Errors: as bh_build_tree, plus
- * BH_E_INVALID for theta or softening negative or not finite, acc == NULL;
- * device: BH_E_STACK. */
+ * BH_E_INVALID for theta or softening negative or not finite, acc == NULL. */
 bh_status bh_compute_accel(bh_ctx *ctx, const double *pos, const double *mass, double softening,
                            const double *eps, double theta, double *acc, double *phi, int64_t n);
 

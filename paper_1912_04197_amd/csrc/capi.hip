@@ -506,7 +506,7 @@ bh_status bh_sync(bh_ctx *c)
     if (st & bhx::ST_NONFINITE)
         return fail(c, BH_E_NONFINITE, "non-finite position, mass or softening, or negative mass");
     if (st & bhx::ST_CAPACITY) return fail(c, BH_E_CAPACITY, "node table overflow");
-    return fail(c, BH_E_STACK, "tree walk stack overflow");
+    return fail(c, BH_E_STACK, "unknown device status");
 }
 
 bh_status bh_build_tree(bh_ctx *c, const double *pos, const double *mass, const double *eps,
