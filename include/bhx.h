@@ -33,7 +33,7 @@
  * Execution: all compute calls are asynchronous on the context's HIP stream
  * and return after enqueueing. Host-detectable argument errors return at once
  * with nothing enqueued. Errors found on the device (non-finite input,
- * negative mass, walk stack overflow, node table overflow) are latched in the
+ * negative mass, node table overflow) are latched in the
  * context and returned by the next bh_sync(); outputs of a failed call are
  * undefined. A context is not thread-safe; use one per stream.
  */
