@@ -30,6 +30,21 @@ if ROOT not in sys.path:
 METRIC = "steps/s & Ginteractions/s at N=1M, theta=0.5 vs direct N^2; force rel. err vs FP64"
 FLOPS_PER_INTERACTION = 20  # conventional count for one softened monopole/pair term
 PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak
+PEAK_HBM_TBS = 8.0           # MI355X published HBM3E bandwidth
+# Algorithmic HBM bytes per body of each phase of a step (reads and writes the
+# phase cannot avoid, once each; node tables counted at 0.16 nodes per body,
+# leaf 16).
+BYTES_PER_BODY = {
+    # box (pos, mass, eps read) 40 + keys (pos read, key and index written) 36
+    # + sort (one read and one write of key and index) 24 + gather (pos, mass,
+    # eps, index read; body and eps^2 written) 84 + octree (keys searched,
+    # nodes written) 11 + moments (bodies and eps^2 read, nodes written) 46
+    "build": 241,
+    # target body and eps^2 40, index 4, acceleration written 24, tree read once 9
+    "walk": 77,
+    # kick (v, a read; v written) 72 + kick-drift (x, v, a read; x, v written) 120
+    "integrate": 192,
+}
 
 
 def log(msg):
@@ -425,6 +440,58 @@ def bench_crossover(ns=(1000, 2048, 4000, 16000, 64000), thetas=(0.25, 0.5, 0.75
             "rows": rows}
 
 
+def step_phases(n, interactions, ms_step, build_ms, walk_ms):
+    """Per-phase roofline of one step: each phase's floor is its algorithmic
+    HBM bytes at the HBM peak or, for the walk, its flops at the FP32 vector
+    peak if that is longer; the step fraction is the sum of the floors over
+    the measured step time. Build and walk are HIP-event times; `integrate` is
+    the rest of the step (two kicks, the drift and the gaps between launches)."""
+    out = {}
+    floor_total = 0.0
+    measured = {"build": build_ms, "walk": walk_ms,
+                "integrate": max(ms_step - build_ms - walk_ms, 1e-6)}
+    for ph, ms in measured.items():
+        nbytes = BYTES_PER_BODY[ph] * n
+        floor_ms = nbytes / (PEAK_HBM_TBS * 1e12) * 1e3
+        bound = "hbm"
+        if ph == "walk":
+            alu_ms = FLOPS_PER_INTERACTION * interactions / (PEAK_FP32_TFLOPS * 1e12) * 1e3
+            if alu_ms > floor_ms:
+                floor_ms, bound = alu_ms, "alu"
+        floor_total += floor_ms
+        out[ph] = {"ms": round(ms, 4), "bound": bound, "floor_ms": round(floor_ms, 4),
+                   "frac": round(floor_ms / ms, 4),
+                   "algorithmic_bytes": nbytes,
+                   "achieved_gb_s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+    out["step_floor_ms"] = round(floor_total, 4)
+    out["step_roofline_frac"] = round(floor_total / ms_step, 4)
+    return out
+
+
+def direct_only(args):
+    """One FP32C and one FP64 direct N^2 evaluation on the headline bodies, for
+    profiler runs of the direct kernel."""
+    import torch
+
+    from paper_1912_04197_amd import ics
+    from paper_1912_04197_amd.api import Context
+
+    n = args.n
+    scene = ics.rubble_pile(n, seed=33)
+    pos = torch.from_numpy(scene.pos).cuda()
+    mass = torch.from_numpy(scene.mass).cuda()
+    eps = torch.from_numpy(scene.eps).cuda()
+    out = {"workload": f"rubble_pile N={n} eps=radius, direct N^2", "n": n}
+    for prec in ("fp32c", "fp64"):
+        ctx = Context(n, precision=prec)
+        ms = _sync_time(lambda: ctx.compute_accel_direct(pos, mass, eps=eps))
+        out[f"{prec}_ms"] = round(ms, 3)
+        out[f"{prec}_ginteractions_per_s"] = round(n * (n - 1) / (ms * 1e-3) / 1e9, 2)
+        ctx.close()
+        log(f"direct {prec}: {ms:.1f} ms")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -441,6 +508,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed steps (for profiler runs)")
+    ap.add_argument("--direct-only", action="store_true",
+                    help="only one FP32C and one FP64 direct evaluation (for profiler runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (to scale HBM counters)")
     args = ap.parse_args()
@@ -466,6 +535,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 5}))
+        return
+    if args.direct_only:
+        direct_only(args)
         return
     n, theta, leaf, dt = args.n, args.theta, args.leaf, args.dt
     log(f"generating rubble pile n={n}")
@@ -551,6 +623,7 @@ def main():
             "kernel": "k_walk<fp32c, per-body eps>",
             "flops_per_interaction": FLOPS_PER_INTERACTION,
         },
+        "phases": step_phases(n, interactions, ms_step, build_ms, walk_ms),
     }
 
     if not args.no_extras:
