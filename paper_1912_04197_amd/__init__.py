@@ -8,7 +8,8 @@ N^2 sum, and a kick-drift-kick leapfrog. The kernels live in libbhx.so
 """
 from __future__ import annotations
 
-__all__ = ["Context", "BHError", "load_library"]
+__all__ = ["Context", "BHError", "load_library", "compute_accel", "compute_accel_direct",
+           "step_leapfrog", "autotune", "gravity_dt_bound", "rollout"]
 
 
 def load_library():
@@ -19,8 +20,13 @@ def load_library():
 
 
 def __getattr__(name):
-    if name in ("Context", "BHError"):
+    if name in ("Context", "BHError", "compute_accel", "compute_accel_direct", "step_leapfrog",
+                "autotune", "gravity_dt_bound"):
         from . import api
 
         return getattr(api, name)
+    if name == "rollout":
+        from . import autograd
+
+        return autograd.rollout
     raise AttributeError(name)

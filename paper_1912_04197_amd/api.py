@@ -374,3 +374,44 @@ def gravity_dt_bound(density, G=1.0):
     if not (density > 0 and G > 0):
         raise ValueError("density and G must be positive")
     return 0.5 / math.sqrt(G * density)
+
+
+# -- functional forms: one cached context per (device, leaf, precision, G),
+# re-created with a larger workspace when a call needs more bodies
+_CONTEXTS: dict = {}
+
+
+def _context_for(n, leaf, precision, G):
+    dev = torch.cuda.current_device()
+    key = (dev, int(leaf), precision, float(G))
+    ctx = _CONTEXTS.get(key)
+    if ctx is None or ctx.n_max < n:
+        if ctx is not None:
+            ctx.close()
+        cap = 1 << max(10, (max(int(n), 1) - 1).bit_length())  # next power of two, >= 1024
+        ctx = Context(cap, leaf_size=leaf, precision=precision, G=G)
+        _CONTEXTS[key] = ctx
+    return ctx
+
+
+def compute_accel(pos, mass, softening=0.0, theta=0.5, *, eps=None, leaf=16, precision="fp32c",
+                  G=1.0, potential=False):
+    """Barnes-Hut accelerations of the bodies (pos (n, 3), mass (n,), float64
+    on the GPU) with a context cached per device, leaf size, precision and G."""
+    ctx = _context_for(pos.shape[0], leaf, precision, G)
+    return ctx.compute_accel(pos, mass, theta, softening=softening, eps=eps, potential=potential)
+
+
+def compute_accel_direct(pos, mass, softening=0.0, *, eps=None, precision="fp32c", G=1.0,
+                         potential=False):
+    """Direct N^2 accelerations, as compute_accel."""
+    ctx = _context_for(pos.shape[0], 16, precision, G)
+    return ctx.compute_accel_direct(pos, mass, softening=softening, eps=eps, potential=potential)
+
+
+def step_leapfrog(pos, vel, mass, acc, dt, nsteps, theta=0.5, softening=0.0, *, eps=None, leaf=16,
+                  precision="fp32c", G=1.0):
+    """nsteps kick-drift-kick steps in place on pos, vel and acc (acc must hold
+    the accelerations at pos on entry; theta < 0: direct sum)."""
+    ctx = _context_for(pos.shape[0], leaf, precision, G)
+    ctx.step_leapfrog(pos, vel, mass, acc, dt, nsteps, theta=theta, softening=softening, eps=eps)

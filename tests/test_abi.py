@@ -108,3 +108,20 @@ def test_gravity_dt_bound():
     assert abs(gravity_dt_bound(3000.0, G=6.674e-11) - 0.5 / (6.674e-11 * 3000.0) ** 0.5) < 1e-9
     with pytest.raises(ValueError):
         gravity_dt_bound(0.0)
+
+
+def test_functional_forms_need_a_gpu():
+    """The package-level forms have no CPU path: without a visible GPU they
+    raise instead of computing anything."""
+    import torch
+
+    import paper_1912_04197_amd as P
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is visible")
+    p = torch.zeros((4, 3), dtype=torch.float64)
+    m = torch.ones(4, dtype=torch.float64)
+    with pytest.raises(RuntimeError):
+        P.compute_accel(p, m, 0.0, 0.5)
+    with pytest.raises(RuntimeError):
+        P.compute_accel_direct(p, m)
