@@ -270,20 +270,23 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t *__restrict__ counts
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
-// Stable scatter of one tile: the rank of each key among equal digits follows
-// tile order (round r, thread t) == input order. The tile is first reordered
-// by digit in LDS, so that consecutive threads write consecutive addresses of
-// each digit's output run.
+// Stable scatter of one tile. Wave w holds the tile's keys w*512 .. w*512+511
+// (round r, lane l: key w*512 + r*64 + l, so tile order is (wave, round,
+// lane) order). Each wave ranks its keys among equal digits with ballots and
+// a per-wave digit count in LDS, without block barriers; one exclusive scan
+// over the waves and one over the digits then place every key in a copy of
+// the tile reordered by digit, so that consecutive threads write consecutive
+// addresses of each digit's output run.
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
     const uint16_t *__restrict__ scene_of,
     uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
     const uint32_t *__restrict__ counts, const uint32_t *__restrict__ totals, int nblk)
 {
+    static_assert(kSortThreads == 256 && kSortItems == 8, "four waves of eight rounds");
+    constexpr int kWaveKeys = 64 * kSortItems;
     __shared__ uint32_t digit_base[256];
-    __shared__ uint32_t running[256];
-    __shared__ uint32_t wcnt[4][256];
-    __shared__ uint32_t wpre[4][256];
+    __shared__ uint32_t whist[4][256];  // per-wave digit counts, then per-wave digit offsets
     __shared__ uint32_t lds4[4];
     __shared__ uint32_t lstart[256];
     __shared__ uint64_t skey[kSortTile];
@@ -291,25 +294,26 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     uint32_t tot;
-    uint32_t t = totals[tid];
-    uint32_t incl = block_incl_scan_256(t, lds4, &tot);
+    const uint32_t t = totals[tid];
+    const uint32_t incl = block_incl_scan_256(t, lds4, &tot);
     digit_base[tid] = incl - t + counts[(int64_t)tid * nblk + blockIdx.x];
-    running[tid] = 0;
-    for (int w = 0; w < 4; w++) wcnt[w][tid] = 0;
+    for (int w = 0; w < 4; w++) whist[w][tid] = 0;
+    __syncthreads();
 
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    const int64_t wbase = base + wave * kWaveKeys;
     uint64_t k[kSortItems];
-    uint32_t v[kSortItems], dst[kSortItems], dig[kSortItems];
+    uint32_t v[kSortItems], rank[kSortItems], dig[kSortItems];
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
-        int64_t i = base + r * kSortThreads + tid;
+        const int64_t i = wbase + r * 64 + lane;
         k[r] = i < n ? kin[i] : 0ull;
         v[r] = i < n ? vin[i] : 0u;
     }
-    __syncthreads();
+    uint32_t *const wh = whist[wave];
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
-        const bool valid = base + r * kSortThreads + tid < n;
+        const bool valid = wbase + r * 64 + lane < n;
         const uint32_t d = valid ? sort_digit(k[r], v[r], shift, scene_of) : 0u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -319,35 +323,35 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
             peers &= bit ? bal : ~bal;
         }
         const uint64_t lower = peers & lanemask_lt(lane);
-        if (valid && lower == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        uint32_t run = running[tid];
-        for (int w = 0; w < 4; w++) {
-            uint32_t c = wcnt[w][tid];
-            wpre[w][tid] = run;
-            run += c;
-            wcnt[w][tid] = 0;
-        }
-        running[tid] = run;
-        __syncthreads();
-        dst[r] = wpre[wave][d] + (uint32_t)__popcll(lower);  // rank among the tile's digit d
+        // keys of this digit ranked by earlier rounds of this wave, read by
+        // every peer before the lowest one adds this round's peers
+        const uint32_t before = valid ? wh[d] : 0u;
+        if (valid && lower == 0) wh[d] = before + (uint32_t)__popcll(peers);
+        rank[r] = before + (uint32_t)__popcll(lower);
         dig[r] = d;
     }
-    // running[] now holds the tile's count per digit: its exclusive scan
-    // gives each digit's run in the reordered tile
+    __syncthreads();
+    // digit tid: exclusive offsets of the waves, and its total in the tile
     {
-        const uint32_t c = running[tid];
+        uint32_t run = 0;
+        for (int w = 0; w < 4; w++) {
+            const uint32_t c = whist[w][tid];
+            whist[w][tid] = run;
+            run += c;
+        }
         uint32_t ctot;
-        const uint32_t ci = block_incl_scan_256(c, lds4, &ctot);
-        lstart[tid] = ci - c;
+        const uint32_t ci = block_incl_scan_256(run, lds4, &ctot);
+        lstart[tid] = ci - run;
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
-        if (base + r * kSortThreads + tid < n) {
-            const uint32_t lp = lstart[dig[r]] + dst[r];
-            skey[lp] = k[r];
-            sval[lp] = v[r];
+        if (wbase + r * 64 + lane < n) {
+            const uint32_t lp = lstart[dig[r]] + wh[dig[r]] + rank[r];
+            if (lp < (uint32_t)kSortTile) {
+                skey[lp] = k[r];
+                sval[lp] = v[r];
+            }
         }
     }
     __syncthreads();
@@ -356,9 +360,11 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
         const uint64_t key = skey[lp];
         const uint32_t val = sval[lp];
         const uint32_t d = sort_digit(key, val, shift, scene_of);
-        const uint32_t o = digit_base[d] + (uint32_t)lp - lstart[d];
-        kout[o] = key;
-        vout[o] = val;
+        const int64_t o = (int64_t)digit_base[d] + lp - lstart[d];
+        if (o >= 0 && o < n) {
+            kout[o] = key;
+            vout[o] = val;
+        }
     }
 }
 
