@@ -193,10 +193,10 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
         const double e2 = PEPS ? 0.5 * (eb + it.e2) : eps0sq;
         const double r2 = dx * dx + dy * dy + dz * dz + e2;
         out[0] = out[1] = out[2] = out[3] = out[4] = 0.0;
-        if (on && r2 > 0.0) {
-            const double r = sqrt(r2);
-            const double inv3 = 1.0 / (r2 * r);
-            const double inv5 = inv3 / r2;
+        if (on && positive_normal(r2)) {
+            const double rinv = rsqrt_f64(r2), inv2 = rinv * rinv;
+            const double inv3 = inv2 * rinv;
+            const double inv5 = inv3 * inv2;
             const double ld = ux * dx + uy * dy + uz * dz;
             const double gms = G * it.m;
             out[0] = gms * (ux * inv3 - 3.0 * dx * ld * inv5);
@@ -680,10 +680,10 @@ __global__ __launch_bounds__(256) void k_direct_vjp(const double *__restrict__ p
             const double dx = sx[j] - xp, dy = sy[j] - yp, dz = sz[j] - zp;
             const double e2 = PEPS ? 0.5 * (ep2 + se[j]) : eps0sq;
             const double r2 = dx * dx + dy * dy + dz * dz + e2;
-            if (!(r2 > 0.0)) continue;
-            const double r = sqrt(r2);
-            const double inv3 = 1.0 / (r2 * r);
-            const double inv5 = inv3 / r2;
+            if (!positive_normal(r2)) continue;
+            const double rinv = rsqrt_f64(r2), inv2 = rinv * rinv;
+            const double inv3 = inv2 * rinv;
+            const double inv5 = inv3 * inv2;
             // w = m_p lambda_q - m_q lambda_p ; K w = w / r^3 - 3 d (d.w) / r^5
             const double wx = mp * slx[j] - sm[j] * lpx, wy = mp * sly[j] - sm[j] * lpy,
                          wz = mp * slz[j] - sm[j] * lpz;

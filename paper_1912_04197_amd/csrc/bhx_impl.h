@@ -129,6 +129,24 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v)
     return (uint32_t)x;
 }
 
+// 1 / sqrt(r2) in FP64 for a positive normal r2: the hardware estimate
+// (relative error about 2^-24) refined by two Newton-Raphson steps on
+// f(y) = y^-2 - r2, y <- y + y (1 - r2 y^2) / 2, each step squaring the
+// relative error; on the whole normal range the result is within one ulp of
+// the exact value. Cheaper than a correctly rounded sqrt followed by
+// divisions, and well inside the FP64 parity bars.
+__device__ inline double rsqrt_f64(double r2)
+{
+    double y = __builtin_amdgcn_rsq(r2);
+    double e = fma(-(r2 * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-(r2 * y), y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
+// r2 is a positive normal number (not 0, subnormal, infinite or NaN).
+__device__ inline bool positive_normal(double r2) { return __builtin_amdgcn_class(r2, 0x100); }
+
 // Workspace owned by a context; sized once for n_max bodies.
 struct Workspace {
     int64_t n_cap = 0, node_cap = 0;

@@ -57,13 +57,13 @@ __global__ __launch_bounds__(kTile) void k_direct(const double *__restrict__ pos
                 const double dx = sx[jj] - xi, dy = sy[jj] - yi, dz = sz[jj] - zi;
                 const double e2 = PEPS ? 0.5 * (ei2 + se[jj]) : eps0sq;
                 const double r2 = dx * dx + dy * dy + dz * dz + e2;
-                if (jj != skip && r2 > 0.0) {
-                    const double r = sqrt(r2);
-                    const double inv3 = 1.0 / (r2 * r);
+                if (jj != skip && positive_normal(r2)) {
+                    const double rinv = rsqrt_f64(r2);
+                    const double inv3 = rinv * rinv * rinv;
                     ax += sm[jj] * dx * inv3;
                     ay += sm[jj] * dy * inv3;
                     az += sm[jj] * dz * inv3;
-                    if (PHI) ph -= sm[jj] / r;
+                    if (PHI) ph -= sm[jj] * rinv;
                 }
             }
         } else {

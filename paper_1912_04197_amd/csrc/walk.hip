@@ -317,16 +317,16 @@ __global__ __launch_bounds__(64) void k_walk(
                 const double dx = it.x - me.x, dy = it.y - me.y, dz = it.z - me.z;
                 const double e2 = PEPS ? 0.5 * (eb2 + it.e2) : eps0sq;
                 const double r2 = dx * dx + dy * dy + dz * dz + e2;
-                if (on && r2 > 0.0) {
-                    const double r = sqrt(r2);
-                    const double inv3 = 1.0 / (r2 * r);
+                if (on && positive_normal(r2)) {
+                    const double rinv = rsqrt_f64(r2), inv2 = rinv * rinv;
+                    const double inv3 = inv2 * rinv;
                     ax += it.m * dx * inv3;
                     ay += it.m * dy * inv3;
                     az += it.m * dz * inv3;
-                    if (PHI) ph -= it.m / r;
+                    if (PHI) ph -= it.m * rinv;
                     if constexpr (QUAD)
                         if (it.src < 0)
-                            quad_term(qbuf + 6 * j, dx, dy, dz, inv3 / r2, 1.0 / r2, ax, ay, az, ph);
+                            quad_term(qbuf + 6 * j, dx, dy, dz, inv3 * inv2, inv2, ax, ay, az, ph);
                 }
                 if (CNT && on) {
                     if (it.src < 0)
@@ -401,16 +401,16 @@ __global__ __launch_bounds__(64) void k_walk(
                 const double dx = it.x - tx, dy = it.y - ty, dz = it.z - tz;
                 const double e2 = PEPS ? 0.5 * (te + it.e2) : eps0sq;
                 const double r2 = dx * dx + dy * dy + dz * dz + e2;
-                if (on && r2 > 0.0) {
-                    const double rr = sqrt(r2);
-                    const double inv3 = 1.0 / (r2 * rr);
+                if (on && positive_normal(r2)) {
+                    const double rinv = rsqrt_f64(r2), inv2 = rinv * rinv;
+                    const double inv3 = inv2 * rinv;
                     fx = it.m * dx * inv3;
                     fy = it.m * dy * inv3;
                     fz = it.m * dz * inv3;
-                    if (PHI) fp = -it.m / rr;
+                    if (PHI) fp = -it.m * rinv;
                     if constexpr (QUAD)
                         if (src_node)
-                            quad_term(qbuf + 6 * k, dx, dy, dz, inv3 / r2, 1.0 / r2, fx, fy, fz, fp);
+                            quad_term(qbuf + 6 * k, dx, dy, dz, inv3 * inv2, inv2, fx, fy, fz, fp);
                 }
             } else {
                 const float te = __shfl(e2hB, b);
