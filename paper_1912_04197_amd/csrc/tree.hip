@@ -405,25 +405,36 @@ __device__ inline void level_range(const int32_t *counts, int level, int64_t nod
 }
 
 // Splits every node of `level` holding more than `leaf` bodies. Eight lanes
-// per node: lane o binary-searches the first body of octant o, the group
-// reserves its non-empty children with one atomic on the next level's count
-// and writes them contiguously in octant order.
-// `counts` is the per-level node count array: the tree header's, or a copy
-// in LDS that a single-block kernel keeps and writes back.
+// per node: lane o binary-searches the first body of octant o; the non-empty
+// children are written contiguously in octant order. All nodes a block holds
+// in one loop step reserve their children with a single atomic on the next
+// level's count (scans over the wave and over the block's waves give each
+// node its offset): on a level of many nodes, one atomic per node or per wave
+// serialises on that counter. Must be called by every thread of the block
+// (a multiple of 64 threads, at most 1024); every thread runs the same loop
+// iterations. `counts` is the per-level node count array: the tree header's,
+// or a copy in LDS that a single-block kernel keeps and writes back. g_first
+// is the node of this thread's group of eight, stride the nodes per step.
 __device__ inline void build_nodes(int level, const uint64_t *__restrict__ keys, int32_t *counts,
                                    uint32_t *status, NodeInfo *__restrict__ ninfo,
                                    int64_t node_cap, int leaf, int64_t g_first, int64_t stride)
 {
+    __shared__ uint32_t s_wtot[16];
+    __shared__ int32_t s_base;
     int32_t beg, cnt;
     level_range(counts, level, node_cap, &beg, &cnt);
     const int32_t next_beg = beg + cnt;
-    const int lane = threadIdx.x & 63, o = threadIdx.x & 7, gl = lane & ~7;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int o = threadIdx.x & 7, gl = lane & ~7;
     const int shift = 60 - 3 * level;  // bits of the child octant at level + 1
-    for (int64_t g = g_first; g < cnt; g += stride) {
-        const int32_t k = beg + (int32_t)g;
+    const int64_t b_first = g_first - (threadIdx.x >> 3);  // first node of this block's step
+    for (int64_t gb = b_first; gb < cnt; gb += stride) {
+        const int64_t g = gb + (threadIdx.x >> 3);
+        const bool live = g < cnt;
+        const int32_t k = beg + (int32_t)(live ? g : gb);
         const NodeInfo info = ninfo[k];
-        if (!(info.count > leaf && level < kMaxLevel)) continue;
-        int32_t a = info.first, b = info.first + info.count;
+        const bool split = live && info.count > leaf && level < kMaxLevel;
+        int32_t a = info.first, b = split ? info.first + info.count : info.first;
         while (a < b) {
             int32_t m = (a + b) >> 1;
             if ((int)((keys[m] >> shift) & 7ull) < o)
@@ -434,13 +445,27 @@ __device__ inline void build_nodes(int level, const uint64_t *__restrict__ keys,
         const int32_t start = a;
         int32_t end = __shfl_down(start, 1, 8);
         if (o == 7) end = info.first + info.count;
-        const bool nonempty = end > start;
+        const bool nonempty = split && end > start;
         const uint32_t gm = (uint32_t)(__ballot(nonempty) >> gl) & 0xffu;
         const int nch = __popc(gm);
         const int rank = __popc(gm & ((1u << o) - 1u));
-        int32_t slot = 0;
-        if (o == 0) slot = atomicAdd(&counts[level + 1], nch);
-        slot = __shfl(slot, gl);
+        const uint32_t mine = o == 0 ? (uint32_t)nch : 0u;
+        const uint32_t incl = wave_incl_scan(mine);
+        if (lane == 63) s_wtot[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0, btot = 0;
+        for (int w = 0; w < nwaves; w++) {
+            const uint32_t t = s_wtot[w];
+            if (w < wave) before += t;
+            btot += t;
+        }
+        if (threadIdx.x == 0 && btot > 0) s_base = atomicAdd(&counts[level + 1], (int32_t)btot);
+        __syncthreads();
+        const int32_t base = btot > 0 ? s_base : 0;
+        const int32_t slot =
+            base + (int32_t)(before + __shfl(incl, gl) - __shfl(mine, gl));
+        __syncthreads();  // s_wtot and s_base are rewritten by the next step
+        if (!split) continue;
         const int64_t c0 = (int64_t)next_beg + slot;
         if (c0 + nch > node_cap) {
             if (o == 0) atomicOr(status, ST_CAPACITY);
@@ -455,13 +480,14 @@ __device__ inline void build_nodes(int level, const uint64_t *__restrict__ keys,
     }
 }
 
-__global__ __launch_bounds__(256) void k_build_level(int level, const uint64_t *__restrict__ keys,
-                                                     TreeHeader *__restrict__ hdr,
-                                                     NodeInfo *__restrict__ ninfo,
-                                                     int64_t node_cap, int leaf)
+__global__ __launch_bounds__(1024) void k_build_level(int level, const uint64_t *__restrict__ keys,
+                                                      TreeHeader *__restrict__ hdr,
+                                                      NodeInfo *__restrict__ ninfo,
+                                                      int64_t node_cap, int leaf)
 {
+    const int64_t per_block = blockDim.x >> 3;  // nodes per block and step
     build_nodes(level, keys, hdr->level_count, &hdr->status, ninfo, node_cap, leaf,
-                (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3), (int64_t)gridDim.x * 32);
+                (int64_t)blockIdx.x * per_block + (threadIdx.x >> 3), (int64_t)gridDim.x * per_block);
 }
 
 // Levels from..upto-1 in one block, on a copy of the node counts in LDS
@@ -918,8 +944,12 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
     }
     const int head = ns == 1 ? (deep < 4 ? deep : 4) : 0;
     for (int level = 0; level < deep; level++) {
-        const unsigned g = blocks_for(level_bound(level, n, ns) * 8, 256, 4096);
-        k_build_level<<<g, 256, 0, s>>>(level, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
+        // levels of many nodes take 1024-thread blocks (fewer reservations on
+        // the level counter), small ones 256 (more CUs for their searches)
+        const int64_t threads = level_bound(level, n, ns) * 8;
+        const int bs = threads >= 65536 ? 1024 : 256;
+        const unsigned g = blocks_for(threads, bs, bs == 1024 ? 1024 : 4096);
+        k_build_level<<<g, bs, 0, s>>>(level, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
     }
     if (deep < kMaxLevel)
         k_build_tail<<<1, 1024, 0, s>>>(deep, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
