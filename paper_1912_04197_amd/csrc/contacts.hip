@@ -108,45 +108,49 @@ __global__ __launch_bounds__(256) void k_contacts(const Body *__restrict__ body,
 {
 #pragma clang fp contract(off)
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (s >= n) return;
-    const int level = (int)counters[2];
-    const int drop = kMaxLevel - level;  // bits below the level's cell coordinate
-    const uint64_t key = keys[s];
-    const int32_t c[3] = {(int32_t)(compact3(key >> 2) >> drop),
-                          (int32_t)(compact3(key >> 1) >> drop), (int32_t)(compact3(key) >> drop)};
-    const int32_t ncell = 1 << level;
-    const Body me = body[s];
-    const int32_t is = (int32_t)idx[s];
-    const double rs = radius[is];
     unsigned long long found = 0;
-    for (int dx = -1; dx <= 1; dx++) {
-        const int32_t x = c[0] + dx;
-        if (x < 0 || x >= ncell) continue;
-        for (int dy = -1; dy <= 1; dy++) {
-            const int32_t y = c[1] + dy;
-            if (y < 0 || y >= ncell) continue;
-            for (int dz = -1; dz <= 1; dz++) {
-                const int32_t z = c[2] + dz;
-                if (z < 0 || z >= ncell) continue;
-                const uint64_t cell = (spread3((uint64_t)x) << 2) | (spread3((uint64_t)y) << 1) |
-                                      spread3((uint64_t)z);
-                const int64_t lo = lower_bound(keys, n, cell << (3 * drop));
-                const int64_t hi = lower_bound(keys, n, (cell + 1) << (3 * drop));
-                for (int64_t t = lo > s + 1 ? lo : s + 1; t < hi; t++) {
-                    const Body o = body[t];
-                    const int32_t it = (int32_t)idx[t];
-                    const double ex = o.x - me.x, ey = o.y - me.y, ez = o.z - me.z;
-                    const double d2 = ex * ex + ey * ey + ez * ez;
-                    const double R = rs + radius[it] + skin;
-                    if (d2 <= R * R) {
-                        found++;
-                        uf_union(parent, is, it);
+    if (s < n) {
+        const int level = (int)counters[2];
+        const int drop = kMaxLevel - level;  // bits below the level's cell coordinate
+        const uint64_t key = keys[s];
+        const int32_t c[3] = {(int32_t)(compact3(key >> 2) >> drop),
+                              (int32_t)(compact3(key >> 1) >> drop),
+                              (int32_t)(compact3(key) >> drop)};
+        const int32_t ncell = 1 << level;
+        const Body me = body[s];
+        const int32_t is = (int32_t)idx[s];
+        const double rs = radius[is];
+        for (int dx = -1; dx <= 1; dx++) {
+            const int32_t x = c[0] + dx;
+            if (x < 0 || x >= ncell) continue;
+            for (int dy = -1; dy <= 1; dy++) {
+                const int32_t y = c[1] + dy;
+                if (y < 0 || y >= ncell) continue;
+                for (int dz = -1; dz <= 1; dz++) {
+                    const int32_t z = c[2] + dz;
+                    if (z < 0 || z >= ncell) continue;
+                    const uint64_t cell = (spread3((uint64_t)x) << 2) |
+                                          (spread3((uint64_t)y) << 1) | spread3((uint64_t)z);
+                    const int64_t lo = lower_bound(keys, n, cell << (3 * drop));
+                    const int64_t hi = lower_bound(keys, n, (cell + 1) << (3 * drop));
+                    for (int64_t t = lo > s + 1 ? lo : s + 1; t < hi; t++) {
+                        const Body o = body[t];
+                        const int32_t it = (int32_t)idx[t];
+                        const double ex = o.x - me.x, ey = o.y - me.y, ez = o.z - me.z;
+                        const double d2 = ex * ex + ey * ey + ez * ez;
+                        const double R = rs + radius[it] + skin;
+                        if (d2 <= R * R) {
+                            found++;
+                            uf_union(parent, is, it);
+                        }
                     }
                 }
             }
         }
     }
-    if (found) atomicAdd(counters, found);
+    // one atomic per wave on the contact counter
+    for (int o = 32; o > 0; o >>= 1) found += __shfl_xor(found, o);
+    if ((threadIdx.x & 63) == 0 && found) atomicAdd(counters, found);
 }
 
 __global__ __launch_bounds__(256) void k_size_clear(int32_t *__restrict__ size, int64_t n)
@@ -169,9 +173,14 @@ __global__ __launch_bounds__(256) void k_uf_finish(int32_t *__restrict__ label, 
                                                    unsigned long long *__restrict__ counters)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    label[i] = uf_find(label, (int32_t)i);
-    if (size[i] > 1) atomicAdd(counters + 1, 1ull);
+    bool agg = false;
+    if (i < n) {
+        label[i] = uf_find(label, (int32_t)i);
+        agg = size[i] > 1;
+    }
+    // one atomic per wave on the aggregate counter
+    const uint64_t b = __ballot(agg);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(counters + 1, (unsigned long long)__popcll(b));
 }
 
 inline unsigned grid(int64_t n) { return (unsigned)((n + 255) / 256); }
