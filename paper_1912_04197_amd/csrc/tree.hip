@@ -911,16 +911,17 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
     k_box_final<<<sb, 256, 0, s>>>(w.box, ns, lay.offsets, n, w.hdr, w.ninfo);
     if (n == 0) return hipGetLastError();
 
-    const unsigned nb = blocks_for(n, 256, 1u << 30);
-    k_keys<<<nb, 256, 0, s>>>(pos, n, w.box, lay.scene_of, w.keys[0], w.idx[0]);
-
-    // 8 passes on the Morton key, then (several scenes) 2 on the scene
-    // index; an even number of passes leaves the result in buffer 0.
+    // 8 passes on the Morton key, then (several scenes) one on each byte of
+    // the scene index that is not always zero; the keys start in the buffer
+    // that makes the last pass write buffer 0.
     const int nblk = (int)((n + kSortTile - 1) / kSortTile);
-    const int passes = ns > 1 ? 10 : 8;
+    const int passes = ns > 256 ? 10 : ns > 1 ? 9 : 8;
+    const int first = passes & 1;
+    const unsigned nb = blocks_for(n, 256, 1u << 30);
+    k_keys<<<nb, 256, 0, s>>>(pos, n, w.box, lay.scene_of, w.keys[first], w.idx[first]);
     for (int pass = 0; pass < passes; pass++) {
         const int shift = pass < 8 ? 8 * pass : 64 + 8 * (pass - 8);
-        const int src = pass & 1, dst = src ^ 1;
+        const int src = (pass + first) & 1, dst = src ^ 1;
         k_sort_hist<<<nblk, kSortThreads, 0, s>>>(w.keys[src], w.idx[src], lay.scene_of, n, shift,
                                                   w.sort_counts, nblk);
         k_sort_scan<<<256, 256, 0, s>>>(w.sort_counts, w.sort_totals, nblk);
