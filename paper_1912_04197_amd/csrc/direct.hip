@@ -23,6 +23,7 @@ __global__ __launch_bounds__(kTile) void k_direct(const double *__restrict__ pos
                                                   double *__restrict__ phi)
 {
     __shared__ double sx[kTile], sy[kTile], sz[kTile], sm[kTile], se[kTile];
+    __shared__ float sm32[PREC == BH_FP64 ? 1 : kTile], se32[PREC == BH_FP64 ? 1 : kTile];
     const int tid = threadIdx.x;
     const int64_t i = (int64_t)blockIdx.x * kTile + tid;
     const bool valid = i < n;
@@ -33,7 +34,8 @@ __global__ __launch_bounds__(kTile) void k_direct(const double *__restrict__ pos
         const double e = eps[i];
         ei2 = e * e;
     }
-    const float e2hB = (float)(0.5 * ei2);
+    const double ehi = 0.5 * ei2;  // (eps_i^2 + eps_j^2) / 2 = ehi + eps_j^2 / 2 exactly
+    const float e2hB = (float)ehi;
     const float eps0f = (float)eps0sq;
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
 
@@ -46,7 +48,11 @@ __global__ __launch_bounds__(kTile) void k_direct(const double *__restrict__ pos
             sm[tid] = mass[j];
             if (PEPS) {
                 const double e = eps[j];
-                se[tid] = PREC == BH_FP64 ? e * e : 0.5 * (e * e);
+                se[tid] = 0.5 * (e * e);
+            }
+            if constexpr (PREC != BH_FP64) {  // the FP32 operands, rounded once per source
+                sm32[tid] = (float)sm[tid];
+                se32[tid] = PEPS ? (float)se[tid] : 0.f;
             }
         }
         __syncthreads();
@@ -55,7 +61,7 @@ __global__ __launch_bounds__(kTile) void k_direct(const double *__restrict__ pos
         if constexpr (PREC == BH_FP64) {
             for (int jj = 0; jj < cnt; jj++) {
                 const double dx = sx[jj] - xi, dy = sy[jj] - yi, dz = sz[jj] - zi;
-                const double e2 = PEPS ? 0.5 * (ei2 + se[jj]) : eps0sq;
+                const double e2 = PEPS ? ehi + se[jj] : eps0sq;
                 const double r2 = dx * dx + dy * dy + dz * dz + e2;
                 if (jj != skip && positive_normal(r2)) {
                     const double rinv = rsqrt_f64(r2);
@@ -74,11 +80,11 @@ __global__ __launch_bounds__(kTile) void k_direct(const double *__restrict__ pos
                 for (int jj = j0; jj < jn; jj++) {
                     const float dx = (float)(sx[jj] - xi), dy = (float)(sy[jj] - yi),
                                 dz = (float)(sz[jj] - zi);
-                    const float e2 = PEPS ? (float)se[jj] + e2hB : eps0f;
+                    const float e2 = PEPS ? se32[jj] + e2hB : eps0f;
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, e2)));
                     const float rinv =
                         (jj != skip && r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;
-                    const float mr = (float)sm[jj] * rinv;
+                    const float mr = sm32[jj] * rinv;
                     const float mr3 = mr * rinv * rinv;
                     fx = fmaf(mr3, dx, fx);
                     fy = fmaf(mr3, dy, fy);

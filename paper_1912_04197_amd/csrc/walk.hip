@@ -73,7 +73,7 @@ struct alignas(16) ItemF {  // FP32C staged source
 };
 struct alignas(16) ItemD {  // FP64 staged source
     double x, y, z, m;
-    double e2;  // source's squared softening (eps_j^2 or <eps^2>_N)
+    double e2h;  // half the source's squared softening (eps_j^2 or <eps^2>_N)
     uint64_t mask;
     int32_t src, pad0;
     int64_t pad1;
@@ -189,6 +189,7 @@ __global__ __launch_bounds__(64) void k_walk(
     const bool valid = bq < gcount;
     const Body me = body[valid ? s : g0];
     const double eb2 = PEPS ? beps2[valid ? s : g0] : 0.0;
+    const double ebh = 0.5 * eb2;  // (eps_B^2 + e_j^2) / 2 = ebh + e_j^2 / 2 exactly
     const uint64_t active = __ballot(valid) & kBodyMask;
     // the group's bounding box (exact: min and max of its bodies' coordinates)
     double glo_x = valid ? me.x : __builtin_huge_val(), ghi_x = valid ? me.x : -__builtin_huge_val();
@@ -290,7 +291,7 @@ __global__ __launch_bounds__(64) void k_walk(
         if (dense || (fits && pk > 0)) {
             const int slot = dense ? (int)lanes_below(db) : nd + (int)lanes_below(fb);
             if constexpr (PREC == BH_FP64) {
-                items[slot] = ItemD{x, y, z, m, e2, mk, src, 0, 0};
+                items[slot] = ItemD{x, y, z, m, 0.5 * e2, mk, src, 0, 0};
             } else {
                 items[slot] = ItemF{x,   y, z, (float)m, (float)(0.5 * e2), (uint32_t)mk,
                                     (uint32_t)(mk >> 32), src, 0};
@@ -315,7 +316,7 @@ __global__ __launch_bounds__(64) void k_walk(
                 const ItemD it = items[j];
                 const bool on = jj + sub < nd && ((it.mask >> bq) & 1ull);
                 const double dx = it.x - me.x, dy = it.y - me.y, dz = it.z - me.z;
-                const double e2 = PEPS ? 0.5 * (eb2 + it.e2) : eps0sq;
+                const double e2 = PEPS ? ebh + it.e2h : eps0sq;
                 const double r2 = dx * dx + dy * dy + dz * dz + e2;
                 if (on && positive_normal(r2)) {
                     const double rinv = rsqrt_f64(r2), inv2 = rinv * rinv;
@@ -395,11 +396,11 @@ __global__ __launch_bounds__(64) void k_walk(
             double fx = 0.0, fy = 0.0, fz = 0.0, fp = 0.0;
             bool src_node;
             if constexpr (PREC == BH_FP64) {
-                const double te = __shfl(eb2, b);
+                const double te = __shfl(ebh, b);
                 const ItemD it = items[k];
                 src_node = it.src < 0;
                 const double dx = it.x - tx, dy = it.y - ty, dz = it.z - tz;
-                const double e2 = PEPS ? 0.5 * (te + it.e2) : eps0sq;
+                const double e2 = PEPS ? te + it.e2h : eps0sq;
                 const double r2 = dx * dx + dy * dy + dz * dz + e2;
                 if (on && positive_normal(r2)) {
                     const double rinv = rsqrt_f64(r2), inv2 = rinv * rinv;
