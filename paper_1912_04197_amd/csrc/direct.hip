@@ -14,6 +14,16 @@ namespace {
 
 constexpr int kTile = 256;
 
+// One source as a tile holds it in LDS: one record per source, so a sweep
+// reads it from a single address with immediate offsets.
+struct alignas(16) SrcD {  // FP64: position, mass, half the squared softening
+    double x, y, z, m, eh, pad;
+};
+struct alignas(16) SrcF {  // FP32C: FP64 position; FP32 mass and half squared softening
+    double x, y, z;
+    float m, eh;
+};
+
 template <int PREC, bool PEPS, bool PHI>
 __global__ __launch_bounds__(kTile) void k_direct(const double *__restrict__ pos,
                                                   const double *__restrict__ mass,
@@ -22,8 +32,8 @@ __global__ __launch_bounds__(kTile) void k_direct(const double *__restrict__ pos
                                                   double *__restrict__ acc,
                                                   double *__restrict__ phi)
 {
-    __shared__ double sx[kTile], sy[kTile], sz[kTile], sm[kTile], se[kTile];
-    __shared__ float sm32[PREC == BH_FP64 ? 1 : kTile], se32[PREC == BH_FP64 ? 1 : kTile];
+    using Src = typename std::conditional<PREC == BH_FP64, SrcD, SrcF>::type;
+    __shared__ Src src[kTile];
     const int tid = threadIdx.x;
     const int64_t i = (int64_t)blockIdx.x * kTile + tid;
     const bool valid = i < n;
@@ -42,34 +52,34 @@ __global__ __launch_bounds__(kTile) void k_direct(const double *__restrict__ pos
     for (int64_t base = 0; base < n; base += kTile) {
         const int64_t j = base + tid;
         if (j < n) {
-            sx[tid] = pos[3 * j];
-            sy[tid] = pos[3 * j + 1];
-            sz[tid] = pos[3 * j + 2];
-            sm[tid] = mass[j];
+            double eh = 0.0;
             if (PEPS) {
                 const double e = eps[j];
-                se[tid] = 0.5 * (e * e);
+                eh = 0.5 * (e * e);
             }
-            if constexpr (PREC != BH_FP64) {  // the FP32 operands, rounded once per source
-                sm32[tid] = (float)sm[tid];
-                se32[tid] = PEPS ? (float)se[tid] : 0.f;
-            }
+            if constexpr (PREC == BH_FP64)
+                src[tid] = SrcD{pos[3 * j], pos[3 * j + 1], pos[3 * j + 2], mass[j], eh, 0.0};
+            else  // the FP32 operands, rounded once per source
+                src[tid] = SrcF{pos[3 * j], pos[3 * j + 1], pos[3 * j + 2], (float)mass[j],
+                                (float)eh};
         }
         __syncthreads();
         const int cnt = (int)((n - base) < kTile ? (n - base) : kTile);
         const int skip = (valid && i >= base && i < base + cnt) ? (int)(i - base) : -1;
         if constexpr (PREC == BH_FP64) {
+#pragma unroll 4
             for (int jj = 0; jj < cnt; jj++) {
-                const double dx = sx[jj] - xi, dy = sy[jj] - yi, dz = sz[jj] - zi;
-                const double e2 = PEPS ? ehi + se[jj] : eps0sq;
+                const SrcD q = src[jj];
+                const double dx = q.x - xi, dy = q.y - yi, dz = q.z - zi;
+                const double e2 = PEPS ? ehi + q.eh : eps0sq;
                 const double r2 = dx * dx + dy * dy + dz * dz + e2;
                 if (jj != skip && positive_normal(r2)) {
                     const double rinv = rsqrt_f64(r2);
                     const double inv3 = rinv * rinv * rinv;
-                    ax += sm[jj] * dx * inv3;
-                    ay += sm[jj] * dy * inv3;
-                    az += sm[jj] * dz * inv3;
-                    if (PHI) ph -= sm[jj] * rinv;
+                    ax += q.m * dx * inv3;
+                    ay += q.m * dy * inv3;
+                    az += q.m * dz * inv3;
+                    if (PHI) ph -= q.m * rinv;
                 }
             }
         } else {
@@ -78,13 +88,14 @@ __global__ __launch_bounds__(kTile) void k_direct(const double *__restrict__ pos
                 float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
 #pragma unroll 4
                 for (int jj = j0; jj < jn; jj++) {
-                    const float dx = (float)(sx[jj] - xi), dy = (float)(sy[jj] - yi),
-                                dz = (float)(sz[jj] - zi);
-                    const float e2 = PEPS ? se32[jj] + e2hB : eps0f;
+                    const SrcF q = src[jj];
+                    const float dx = (float)(q.x - xi), dy = (float)(q.y - yi),
+                                dz = (float)(q.z - zi);
+                    const float e2 = PEPS ? q.eh + e2hB : eps0f;
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, e2)));
                     const float rinv =
                         (jj != skip && r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;
-                    const float mr = sm32[jj] * rinv;
+                    const float mr = q.m * rinv;
                     const float mr3 = mr * rinv * rinv;
                     fx = fmaf(mr3, dx, fx);
                     fy = fmaf(mr3, dy, fy);
