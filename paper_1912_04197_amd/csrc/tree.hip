@@ -85,7 +85,8 @@ __global__ __launch_bounds__(256) void k_box_init(SceneBox *__restrict__ box, in
 // One work item: a chunk of at most kBoxChunk bodies of one scene (for one
 // scene, chunk c is bodies c*kBoxChunk onwards). Reduces its box in the block
 // and merges it into the scene's with integer atomics; flags bad input.
-__global__ __launch_bounds__(256) void k_box_chunk(const double *__restrict__ pos,
+constexpr int kBoxThreads = 1024;  // one block per chunk: 4 bodies per thread
+__global__ __launch_bounds__(kBoxThreads) void k_box_chunk(const double *__restrict__ pos,
                                                    const double *__restrict__ mass,
                                                    const double *__restrict__ eps, int64_t n,
                                                    const int32_t *__restrict__ chunks,
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(256) void k_box_chunk(const double *__restrict__ po
     if (end > n) end = n;
     double lo[3] = {kInf, kInf, kInf}, hi[3] = {-kInf, -kInf, -kInf};
     bool bad = false;
-    for (int64_t i = first + threadIdx.x; i < end; i += 256) {
+    for (int64_t i = first + threadIdx.x; i < end; i += kBoxThreads) {
         double x[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
         double m = mass[i];
         bad |= !(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]));
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(256) void k_box_chunk(const double *__restrict__ po
         }
     }
     if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&hdr->status, ST_NONFINITE);
-    __shared__ double red[4][6];
+    __shared__ double red[kBoxThreads / 64][6];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int a = 0; a < 3; a++) {
         double l = wave_min(lo[a]), h = wave_max(hi[a]);
@@ -130,7 +131,8 @@ __global__ __launch_bounds__(256) void k_box_chunk(const double *__restrict__ po
     if (threadIdx.x < 6) {
         const int a = threadIdx.x;
         double v = red[0][a];
-        for (int w = 1; w < 4; w++) v = a < 3 ? fmin(v, red[w][a]) : fmax(v, red[w][a]);
+        for (int w = 1; w < kBoxThreads / 64; w++)
+            v = a < 3 ? fmin(v, red[w][a]) : fmax(v, red[w][a]);
         if (a < 3)
             atomicMin(&box[sc].lo_enc[a], order_enc(v));
         else
@@ -907,7 +909,7 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
     k_box_init<<<sb, 256, 0, s>>>(w.box, ns);
     const int nchunks = lay.chunks ? lay.n_chunks : (int)((n + kBoxChunk - 1) / kBoxChunk);
     if (nchunks > 0)
-        k_box_chunk<<<nchunks, 256, 0, s>>>(pos, mass, eps, n, lay.chunks, w.box, w.hdr);
+        k_box_chunk<<<nchunks, kBoxThreads, 0, s>>>(pos, mass, eps, n, lay.chunks, w.box, w.hdr);
     k_box_final<<<sb, 256, 0, s>>>(w.box, ns, lay.offsets, n, w.hdr, w.ninfo);
     if (n == 0) return hipGetLastError();
 
