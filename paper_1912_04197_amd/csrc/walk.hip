@@ -62,6 +62,9 @@ constexpr int kPairCap = 448;  // body pairs evaluated one per lane in one batch
 // and theta^2 D^2 carry a relative rounding error below 1e-15, so a box
 // bound that clears the threshold by this margin decides every body alike.
 constexpr double kMacMargin = 1e-12;
+// Items per unrolled step of the dense sweep, by group size.
+template <int GB>
+constexpr int kSweepUnroll = GB == 64 ? 4 : 1;
 
 struct alignas(16) ItemF {  // FP32C staged source
     double x, y, z;
@@ -135,7 +138,6 @@ __global__ __launch_bounds__(64) void k_walk(
     // Items that reach at most kSparse bodies of the group are evaluated as
     // (item, body) pairs, one pair per lane, into per-body FP64 sums in LDS.
     constexpr int kSparse = GB / 6;
-    constexpr int kSweepUnroll = GB == 64 ? 4 : 1;
 
     __shared__ int32_t st_c0[kStack];
     __shared__ uint8_t st_n[kStack];
@@ -208,6 +210,8 @@ __global__ __launch_bounds__(64) void k_walk(
 
     const float e2hB = (float)(0.5 * eb2);
     const float eps0f = (float)eps0sq;
+    // every body of the wave has a positive FP32 softening (the sweep's r^2 > 0 test is moot)
+    const bool soft_all = __ballot(!valid || (PEPS ? e2hB > 0.f : eps0f > 0.f)) == ~0ull;
     const int woff = (int)offsetof(ItemF, mlo) + (bq >= 32 ? 4 : 0);
 
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
@@ -337,12 +341,15 @@ __global__ __launch_bounds__(64) void k_walk(
                 }
             }
         } else {
+          // With every body of the wave softened (its FP32 half eps^2 > 0),
+          // r^2 >= that softening > 0 for every pair, and the test is dropped.
+          auto sweep = [&](auto all_soft) {
 #pragma unroll 1
             for (int j0 = 0; j0 < nd; j0 += kFlush * LPB) {
                 const int jn = min(nd, j0 + kFlush * LPB);
                 float fx = 0.f, fy = 0.f, fz = 0.f, fp = 0.f;
                 // jj is the same on every lane; lane share `sub` takes item jj + sub
-#pragma unroll kSweepUnroll
+#pragma unroll kSweepUnroll<GB>
                 for (int jj = j0; jj < jn; jj += LPB) {
                     const int j = jj + sub;
                     const ItemF it = items[j < jn ? j : jj];
@@ -358,7 +365,8 @@ __global__ __launch_bounds__(64) void k_walk(
                                 dz = (float)(it.z - me.z);
                     const float e2 = PEPS ? it.e2h + e2hB : eps0f;
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, e2)));
-                    const float rinv = (on && r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;
+                    const bool live = decltype(all_soft)::value ? on : (on && r2 > 0.f);
+                    const float rinv = live ? __builtin_amdgcn_rsqf(r2) : 0.f;
                     const float mr = it.m * rinv;
                     const float mr3 = mr * rinv * rinv;
                     fx = fmaf(mr3, dx, fx);
@@ -383,6 +391,11 @@ __global__ __launch_bounds__(64) void k_walk(
                 az += (double)fz;
                 if (PHI) ph += (double)fp;
             }
+          };
+          if (soft_all)
+              sweep(std::true_type{});
+          else
+              sweep(std::false_type{});
         }
         // Pairs: lane i takes pair i of the list; its body's coordinates come
         // from that body's lane. Each pair term goes into the body's FP64 sums.
