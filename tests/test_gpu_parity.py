@@ -187,7 +187,15 @@ WALK_CASES = [
     ("tiny1", lambda: ics.uniform_ball(1, seed=1), 0.5, 16, 1e-3, False),
     ("tiny2", lambda: ics.uniform_ball(2, seed=2), 0.5, 1, 0.0, False),
     ("tiny65", lambda: ics.uniform_ball(65, seed=3), 0.5, 4, 1e-3, False),
+    # every 97th body unsoftened: waves with and without an unsoftened body in one launch
+    ("rubble8000_some_eps0", lambda: _some_unsoftened(ics.rubble_pile(8000, seed=34), 97), 0.5,
+     16, 0.0, True),
 ]
+
+
+def _some_unsoftened(scene, every):
+    scene.eps[::every] = 0.0
+    return scene
 
 
 @pytest.mark.parametrize("group", [16, 32, 64])
