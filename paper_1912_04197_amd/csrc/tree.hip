@@ -489,7 +489,8 @@ __global__ __launch_bounds__(1024) void k_build_level(int level, const uint64_t 
 {
     const int64_t per_block = blockDim.x >> 3;  // nodes per block and step
     build_nodes(level, keys, hdr->level_count, &hdr->status, ninfo, node_cap, leaf,
-                (int64_t)blockIdx.x * per_block + (threadIdx.x >> 3), (int64_t)gridDim.x * per_block);
+                (int64_t)blockIdx.x * per_block + (threadIdx.x >> 3),
+                (int64_t)gridDim.x * per_block);
 }
 
 // Levels from..upto-1 in one block, on a copy of the node counts in LDS
@@ -620,7 +621,8 @@ __global__ __launch_bounds__(256) void k_moments_level(
     int64_t node_cap, int use_eps, int32_t *__restrict__ depth_out)
 {
     moments_nodes(level, hdr->level_count, ninfo, body, beps2, keys, box, nmom, neps2, nquad,
-                  node_cap, use_eps, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
+                  node_cap, use_eps, (int64_t)blockIdx.x * 256 + threadIdx.x,
+                  (int64_t)gridDim.x * 256);
     // the root level reports the deepest non-empty level, as a launch hint
     // for the next build (pinned host memory)
     if (level == 0 && depth_out && blockIdx.x == 0 && threadIdx.x == 0) {
@@ -681,7 +683,7 @@ __global__ __launch_bounds__(1024) void k_moments_tail(
 
 // The whole build of one scene of at most kSmallBuild bodies in one block:
 // box and input check, keys, an eight-pass stable radix sort of (key, index)
-// through global memory, gather, every level of the tree and the moments.
+// held in LDS, gather, every level of the tree and the moments.
 // Each stage computes what the multi-launch path computes (the same stable
 // order, the same node set and moments); a small scene is bound by launch
 // latency, which this removes.
@@ -690,18 +692,22 @@ constexpr int kSmallThreads = 1024;
 __global__ __launch_bounds__(kSmallThreads) void k_build_small(
     const double *__restrict__ pos, const double *__restrict__ mass,
     const double *__restrict__ eps, int64_t n, int leaf, SceneBox *__restrict__ box,
-    TreeHeader *__restrict__ hdr, uint64_t *__restrict__ k0, uint64_t *__restrict__ k1,
-    uint32_t *__restrict__ i0, uint32_t *__restrict__ i1, Body *__restrict__ body,
+    TreeHeader *__restrict__ hdr, uint64_t *__restrict__ k0, uint32_t *__restrict__ i0,
+    Body *__restrict__ body,
     double *__restrict__ beps2, NodeInfo *__restrict__ ninfo, NodeMom *__restrict__ nmom,
     double *__restrict__ neps2, double *__restrict__ nquad, int64_t node_cap,
     int32_t *__restrict__ depth_out)
 {
     constexpr int W = kSmallThreads / 64;
+    constexpr int kChunk = kSmallBuild / W;  // keys per wave in the sort (4 rounds of 64)
+    static_assert(kChunk % 64 == 0, "whole rounds per wave");
     __shared__ unsigned long long red_lo[3], red_hi[3];
-    __shared__ uint32_t hist[256], base[256], running[256];
-    __shared__ uint32_t wcnt[W][256];
-    __shared__ uint32_t wpre[W][256];
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t whist[W][256];  // per-wave digit counts, then per-wave digit offsets
     __shared__ uint32_t lds4[4];
+    // the keys and indices, sorted in LDS (ping-pong)
+    __shared__ uint64_t skey[2][kSmallBuild];
+    __shared__ uint32_t sval[2][kSmallBuild];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 
     // 1. box and input check
@@ -711,7 +717,6 @@ __global__ __launch_bounds__(kSmallThreads) void k_build_small(
     }
     __shared__ int32_t scnt[kLevels + 1];
     if (tid <= kLevels) scnt[tid] = tid == 0 ? 1 : 0;
-    for (int i = tid; i < W * 256; i += kSmallThreads) (&wcnt[0][0])[i] = 0;
     __syncthreads();
     {
         unsigned long long lo[3] = {~0ull, ~0ull, ~0ull}, hi[3] = {0ull, 0ull, 0ull};
@@ -751,47 +756,27 @@ __global__ __launch_bounds__(kSmallThreads) void k_build_small(
     }
     __syncthreads();
 
-    // 2. keys
+    // 2. keys, in LDS
     for (int64_t i = tid; i < n; i += kSmallThreads) {
-        k0[i] = morton_key(pos + 3 * i, box[0]);
-        i0[i] = (uint32_t)i;
+        skey[0][i] = morton_key(pos + 3 * i, box[0]);
+        sval[0][i] = (uint32_t)i;
     }
     __syncthreads();
 
-    // 3. sort: per pass a digit histogram, then rounds of 1024 elements in
-    // input order, ranked among equal digits by wave ballots
-    uint64_t *kin = k0, *kout = k1;
-    uint32_t *vin = i0, *vout = i1;
+    // 3. sort, in LDS: wave w holds keys w*kChunk .. (w+1)*kChunk-1 of the
+    // current order and ranks them among equal digits with ballots and a
+    // per-wave digit count (tile order = wave, round, lane = input order);
+    // scans over the waves and over the digits then place every key.
     for (int pass = 0; pass < 8; pass++) {
-        const int shift = 8 * pass;
-        if (tid < 256) {
-            hist[tid] = 0;
-            running[tid] = 0;
-        }
+        const int shift = 8 * pass, src = pass & 1, dst = src ^ 1;
+        for (int i = tid; i < W * 256; i += kSmallThreads) (&whist[0][0])[i] = 0;
         __syncthreads();
-        for (int64_t i = tid; i < n; i += kSmallThreads)
-            atomicAdd(&hist[(uint32_t)(kin[i] >> shift) & 255u], 1u);
-        __syncthreads();
-        // exclusive scan of the 256 digit counts by the first four waves; the
-        // barriers are reached by every thread of the block
-        {
-            const uint32_t h = tid < 256 ? hist[tid] : 0u;
-            const uint32_t v = wave_incl_scan(h);
-            if (lane == 63 && wave < 4) lds4[wave] = v;
-            __syncthreads();
-            if (tid < 256) {
-                uint32_t add = 0;
-                for (int w = 0; w < wave; w++) add += lds4[w];
-                base[tid] = add + v - h;
-            }
-        }
-        __syncthreads();
-        for (int64_t r0 = 0; r0 < n; r0 += kSmallThreads) {
-            const int64_t i = r0 + tid;
+        uint32_t rank[kChunk / 64], dig[kChunk / 64];
+#pragma unroll
+        for (int r = 0; r < kChunk / 64; r++) {
+            const int i = wave * kChunk + r * 64 + lane;
             const bool valid = i < n;
-            const uint64_t key = valid ? kin[i] : 0ull;
-            const uint32_t val = valid ? vin[i] : 0u;
-            const uint32_t d = (uint32_t)(key >> shift) & 255u;
+            const uint32_t d = valid ? (uint32_t)(skey[src][i] >> shift) & 255u : 0u;
             uint64_t peers = __ballot(valid);
 #pragma unroll
             for (int b = 0; b < 8; b++) {
@@ -800,37 +785,54 @@ __global__ __launch_bounds__(kSmallThreads) void k_build_small(
                 peers &= bit ? bal : ~bal;
             }
             const uint64_t lower = peers & lanemask_lt(lane);
-            if (valid && lower == 0) wcnt[wave][d] = (uint32_t)__popcll(peers);
+            const uint32_t before = valid ? whist[wave][d] : 0u;
+            if (valid && lower == 0) whist[wave][d] = before + (uint32_t)__popcll(peers);
+            rank[r] = before + (uint32_t)__popcll(lower);
+            dig[r] = d;
+        }
+        __syncthreads();
+        // digit tid (first four waves): offsets of the waves, and the exclusive
+        // scan of the digit totals; the barriers are reached by every thread
+        {
+            uint32_t run = 0;
+            if (tid < 256)
+                for (int w = 0; w < W; w++) {
+                    const uint32_t c = whist[w][tid];
+                    whist[w][tid] = run;
+                    run += c;
+                }
+            const uint32_t v = wave_incl_scan(run);
+            if (lane == 63 && wave < 4) lds4[wave] = v;
             __syncthreads();
             if (tid < 256) {
-                uint32_t run = running[tid];
-                for (int w = 0; w < W; w++) {
-                    const uint32_t c = wcnt[w][tid];
-                    wpre[w][tid] = run;
-                    run += c;
-                    wcnt[w][tid] = 0;
-                }
-                running[tid] = run;
-            }
-            __syncthreads();
-            if (valid) {
-                const uint32_t dst = base[d] + wpre[wave][d] + (uint32_t)__popcll(lower);
-                kout[dst] = key;
-                vout[dst] = val;
+                uint32_t add = 0;
+                for (int w = 0; w < wave; w++) add += lds4[w];
+                base[tid] = add + v - run;
             }
         }
         __syncthreads();
-        uint64_t *tk = kin;
-        kin = kout;
-        kout = tk;
-        uint32_t *tv = vin;
-        vin = vout;
-        vout = tv;
+#pragma unroll
+        for (int r = 0; r < kChunk / 64; r++) {
+            const int i = wave * kChunk + r * 64 + lane;
+            if (i < n) {
+                const uint32_t o = base[dig[r]] + whist[wave][dig[r]] + rank[r];
+                skey[dst][o] = skey[src][i];
+                sval[dst][o] = sval[src][i];
+            }
+        }
+        __syncthreads();
     }
+    // eight passes leave the order in buffer 0; the walk and the tree export
+    // read the sorted keys and indices from global memory
+    for (int64_t i = tid; i < n; i += kSmallThreads) {
+        k0[i] = skey[0][i];
+        i0[i] = sval[0][i];
+    }
+    __syncthreads();
 
-    // 4. gather (eight passes leave the order in k0 / i0)
+    // 4. gather
     for (int64_t s = tid; s < n; s += kSmallThreads) {
-        const uint32_t i = i0[s];
+        const uint32_t i = sval[0][s];
         body[s] = Body{pos[3 * (int64_t)i], pos[3 * (int64_t)i + 1], pos[3 * (int64_t)i + 2],
                        mass[i]};
         if (eps) {
@@ -840,13 +842,13 @@ __global__ __launch_bounds__(kSmallThreads) void k_build_small(
     }
     __syncthreads();
 
-    // 5. tree, top-down, with the node counts in LDS
-    build_levels_block(0, kMaxLevel, k0, hdr, ninfo, node_cap, leaf, scnt);
+    // 5. tree, top-down, with the node counts and the sorted keys in LDS
+    build_levels_block(0, kMaxLevel, skey[0], hdr, ninfo, node_cap, leaf, scnt);
     __syncthreads();
     // 6. moments, bottom-up
     for (int level = kMaxLevel; level >= 0; level--) {
         if (scnt[level] == 0) continue;  // the same on every thread
-        moments_nodes(level, scnt, ninfo, body, beps2, k0, box, nmom, neps2, nquad, node_cap,
+        moments_nodes(level, scnt, ninfo, body, beps2, skey[0], box, nmom, neps2, nquad, node_cap,
                       eps != nullptr, tid, kSmallThreads);
         __syncthreads();
     }
@@ -900,9 +902,8 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
     const int ns = lay.n_scenes;
     if (ns == 1 && n >= 1 && n <= kSmallBuild) {
         k_build_small<<<1, kSmallThreads, 0, s>>>(pos, mass, eps, n, leaf, w.box, w.hdr, w.keys[0],
-                                                  w.keys[1], w.idx[0], w.idx[1], w.body, w.beps2,
-                                                  w.ninfo, w.nmom, w.neps2, w.nquad, w.node_cap,
-                                                  w.depth_dev);
+                                                  w.idx[0], w.body, w.beps2, w.ninfo, w.nmom,
+                                                  w.neps2, w.nquad, w.node_cap, w.depth_dev);
         return hipGetLastError();
     }
     const unsigned sb = (unsigned)((ns + 255) / 256);
