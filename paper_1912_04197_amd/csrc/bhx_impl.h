@@ -166,6 +166,7 @@ struct Workspace {
     int32_t *counts = nullptr;    // [n_cap][2] per-body walk counts, caller order
     double *scratch = nullptr;    // [n_cap] potential for diagnostics
     double *red_part = nullptr;   // [reduction blocks][8]
+    double *dpart = nullptr;      // [kDirectPart] partial direct sums of split source ranges
     // Deepest non-empty level of the last build, written by the device into
     // pinned host memory (-1 before the first build): the next build launches
     // the levels down to one below it one by one and the rest in one block.
@@ -173,6 +174,13 @@ struct Workspace {
     int32_t *depth_dev = nullptr;  // the same memory as the device sees it
 };
 
+// The direct sum splits its sources over up to kDirectSplits block rows when
+// the targets alone give fewer than kDirectBlocks blocks; each row's partial
+// sums (4 doubles per target) go to a workspace buffer of kDirectPart doubles
+// and are added in row order.
+constexpr int kDirectBlocks = 1024;
+constexpr int kDirectSplits = 64;
+constexpr int64_t kDirectPart = (int64_t)kDirectBlocks * 256 * 4;
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;
@@ -220,7 +228,7 @@ hipError_t launch_walk(const Workspace &w, hipStream_t s, const WalkParams &p);
 // direct.hip
 hipError_t launch_direct(hipStream_t s, const double *pos, const double *mass, const double *eps,
                          int64_t n, double eps0sq, double G, int precision, double *acc,
-                         double *phi);
+                         double *phi, double *part);
 
 // adjoint.hip: workspace of the VJPs (BH_FLAG_ADJOINT)
 struct AdjointWork {

@@ -87,7 +87,7 @@ void free_ws(Workspace &w)
 {
     void *ptrs[] = {w.keys[0], w.keys[1], w.idx[0],  w.idx[1],      w.sort_counts,
                     w.sort_totals, w.body, w.beps2, w.ninfo, w.nmom, w.neps2, w.box,
-                    w.hdr, w.counts, w.scratch, w.red_part, w.nquad};
+                    w.hdr, w.counts, w.scratch, w.red_part, w.nquad, w.dpart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (w.depth_host) (void)hipHostFree(w.depth_host);
@@ -209,7 +209,7 @@ bh_status force_direct(bh_ctx *c, const double *pos, const double *mass, double 
                        const double *eps, double *acc, double *phi, int64_t n, int precision)
 {
     BHX_HIP(c, bhx::launch_direct(c->stream, pos, mass, eps, n, softening * softening, c->cfg.G,
-                                  precision, acc, phi));
+                                  precision, acc, phi, c->w.dpart));
     return BH_OK;
 }
 
@@ -438,6 +438,7 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
     if (cfg->flags & BH_FLAG_QUAD) A(dalloc(&w.nquad, 6 * node_cap));
     A(dalloc(&w.scratch, 4 * n));
     A(dalloc(&w.red_part, (int64_t)bhx::kRedBlocks * 8));
+    A(dalloc(&w.dpart, bhx::kDirectPart));
     A(dalloc(&c->diag_out, 8));
     A(hipHostMalloc((void **)&w.depth_host, sizeof(int32_t), hipHostMallocMapped));
     if (r == hipSuccess) {

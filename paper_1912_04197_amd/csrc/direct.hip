@@ -5,6 +5,9 @@
 // tiles of 256 (positions in FP64 so that d_ij is formed in FP64 even in FP32C
 // mode, where only the pair arithmetic after the difference is FP32 and FP32
 // partial sums over at most 32 sources are added into FP64 accumulators).
+// When the targets give too few blocks to fill the GPU, block row y sums only
+// the y-th range of source tiles into a partial buffer, and a second kernel
+// adds the rows in order (so the result does not depend on scheduling).
 #include <type_traits>
 
 #include "bhx_impl.h"
@@ -30,7 +33,8 @@ __global__ __launch_bounds__(kTile) void k_direct(const double *__restrict__ pos
                                                   const double *__restrict__ eps, int64_t n,
                                                   double eps0sq, double G,
                                                   double *__restrict__ acc,
-                                                  double *__restrict__ phi)
+                                                  double *__restrict__ phi, int64_t chunk,
+                                                  double *__restrict__ part)
 {
     using Src = typename std::conditional<PREC == BH_FP64, SrcD, SrcF>::type;
     __shared__ Src src[kTile];
@@ -49,9 +53,12 @@ __global__ __launch_bounds__(kTile) void k_direct(const double *__restrict__ pos
     const float eps0f = (float)eps0sq;
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
 
-    for (int64_t base = 0; base < n; base += kTile) {
+    // this block row's sources: [s_lo, s_hi)
+    const int64_t s_lo = (int64_t)blockIdx.y * chunk;
+    const int64_t s_hi = s_lo + chunk < n ? s_lo + chunk : n;
+    for (int64_t base = s_lo; base < s_hi; base += kTile) {
         const int64_t j = base + tid;
-        if (j < n) {
+        if (j < s_hi) {
             double eh = 0.0;
             if (PEPS) {
                 const double e = eps[j];
@@ -64,7 +71,7 @@ __global__ __launch_bounds__(kTile) void k_direct(const double *__restrict__ pos
                                 (float)eh};
         }
         __syncthreads();
-        const int cnt = (int)((n - base) < kTile ? (n - base) : kTile);
+        const int cnt = (int)((s_hi - base) < kTile ? (s_hi - base) : kTile);
         const int skip = (valid && i >= base && i < base + cnt) ? (int)(i - base) : -1;
         if constexpr (PREC == BH_FP64) {
 #pragma unroll 4
@@ -110,23 +117,66 @@ __global__ __launch_bounds__(kTile) void k_direct(const double *__restrict__ pos
         }
         __syncthreads();
     }
-    if (valid) {
+    if (valid && gridDim.y == 1) {
         acc[3 * i] = G * ax;
         acc[3 * i + 1] = G * ay;
         acc[3 * i + 2] = G * az;
         if (PHI) phi[i] = G * ph;
+    } else if (valid) {
+        double *q = part + 4 * ((int64_t)blockIdx.y * n + i);
+        q[0] = ax;
+        q[1] = ay;
+        q[2] = az;
+        q[3] = ph;
     }
+}
+
+// acc_i = G * sum over the block rows of their partial sums, in row order.
+__global__ __launch_bounds__(256) void k_direct_reduce(const double *__restrict__ part,
+                                                       int64_t n, int rows, double G,
+                                                       double *__restrict__ acc,
+                                                       double *__restrict__ phi)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
+    for (int r = 0; r < rows; r++) {
+        const double *q = part + 4 * ((int64_t)r * n + i);
+        ax += q[0];
+        ay += q[1];
+        az += q[2];
+        ph += q[3];
+    }
+    acc[3 * i] = G * ax;
+    acc[3 * i + 1] = G * ay;
+    acc[3 * i + 2] = G * az;
+    if (phi) phi[i] = G * ph;
 }
 
 template <int PREC, bool PEPS>
 hipError_t launch_p(hipStream_t s, const double *pos, const double *mass, const double *eps,
-                    int64_t n, double eps0sq, double G, double *acc, double *phi)
+                    int64_t n, double eps0sq, double G, double *acc, double *phi, double *part)
 {
-    const unsigned grid = (unsigned)((n + kTile - 1) / kTile);
+    // rows of source ranges (whole tiles) so that targets x rows reaches
+    // kDirectBlocks; rows * n <= kDirectBlocks * kTile fits the partial buffer
+    const int64_t tb = (n + kTile - 1) / kTile;
+    int64_t rows = tb >= kDirectBlocks ? 1 : kDirectBlocks / tb;
+    if (rows > kDirectSplits) rows = kDirectSplits;
+    if (rows > tb) rows = tb;  // at least one source tile per row
+    const int64_t tiles = (tb + rows - 1) / rows;
+    const int64_t chunk = tiles * kTile;
+    rows = (tb + tiles - 1) / tiles;
+    if (!part) rows = 1;
+    const dim3 grid((unsigned)tb, (unsigned)rows);
+    const int64_t ch = rows == 1 ? n : chunk;
     if (phi)
-        k_direct<PREC, PEPS, true><<<grid, kTile, 0, s>>>(pos, mass, eps, n, eps0sq, G, acc, phi);
+        k_direct<PREC, PEPS, true>
+            <<<grid, kTile, 0, s>>>(pos, mass, eps, n, eps0sq, G, acc, phi, ch, part);
     else
-        k_direct<PREC, PEPS, false><<<grid, kTile, 0, s>>>(pos, mass, eps, n, eps0sq, G, acc, phi);
+        k_direct<PREC, PEPS, false>
+            <<<grid, kTile, 0, s>>>(pos, mass, eps, n, eps0sq, G, acc, phi, ch, part);
+    if (rows > 1)
+        k_direct_reduce<<<(unsigned)tb, 256, 0, s>>>(part, n, (int)rows, G, acc, phi);
     return hipGetLastError();
 }
 
@@ -134,14 +184,14 @@ hipError_t launch_p(hipStream_t s, const double *pos, const double *mass, const 
 
 hipError_t launch_direct(hipStream_t s, const double *pos, const double *mass, const double *eps,
                          int64_t n, double eps0sq, double G, int precision, double *acc,
-                         double *phi)
+                         double *phi, double *part)
 {
     if (n <= 0) return hipSuccess;
     if (precision == BH_FP64)
-        return eps ? launch_p<BH_FP64, true>(s, pos, mass, eps, n, eps0sq, G, acc, phi)
-                   : launch_p<BH_FP64, false>(s, pos, mass, eps, n, eps0sq, G, acc, phi);
-    return eps ? launch_p<BH_FP32C, true>(s, pos, mass, eps, n, eps0sq, G, acc, phi)
-               : launch_p<BH_FP32C, false>(s, pos, mass, eps, n, eps0sq, G, acc, phi);
+        return eps ? launch_p<BH_FP64, true>(s, pos, mass, eps, n, eps0sq, G, acc, phi, part)
+                   : launch_p<BH_FP64, false>(s, pos, mass, eps, n, eps0sq, G, acc, phi, part);
+    return eps ? launch_p<BH_FP32C, true>(s, pos, mass, eps, n, eps0sq, G, acc, phi, part)
+               : launch_p<BH_FP32C, false>(s, pos, mass, eps, n, eps0sq, G, acc, phi, part);
 }
 
 }  // namespace bhx
