@@ -647,7 +647,8 @@ __global__ __launch_bounds__(256) void k_direct_vjp(const double *__restrict__ p
                                                     double eps0sq, double G,
                                                     const double *__restrict__ lambda,
                                                     double *__restrict__ g_pos,
-                                                    double *__restrict__ g_mass)
+                                                    double *__restrict__ g_mass, int64_t chunk,
+                                                    double *__restrict__ part)
 {
     constexpr int T = 256;
     __shared__ double sx[T], sy[T], sz[T], sm[T], se[T], slx[T], sly[T], slz[T];
@@ -661,9 +662,14 @@ __global__ __launch_bounds__(256) void k_direct_vjp(const double *__restrict__ p
     double ep2 = 0.0;
     if (PEPS && valid) ep2 = eps[p] * eps[p];
     double gx = 0.0, gy = 0.0, gz = 0.0, gm = 0.0;
-    for (int64_t base = 0; base < n; base += T) {
+    // this block row's sources: [s_lo, s_hi) (one row unless the targets
+    // alone give too few blocks; the rows' partial sums are then added in
+    // row order by k_direct_vjp_reduce)
+    const int64_t s_lo = (int64_t)blockIdx.y * chunk;
+    const int64_t s_hi = s_lo + chunk < n ? s_lo + chunk : n;
+    for (int64_t base = s_lo; base < s_hi; base += T) {
         const int64_t q = base + tid;
-        if (q < n) {
+        if (q < s_hi) {
             sx[tid] = pos[3 * q];
             sy[tid] = pos[3 * q + 1];
             sz[tid] = pos[3 * q + 2];
@@ -674,7 +680,7 @@ __global__ __launch_bounds__(256) void k_direct_vjp(const double *__restrict__ p
             if (PEPS) se[tid] = eps[q] * eps[q];
         }
         __syncthreads();
-        const int cnt = (int)((n - base) < T ? (n - base) : T);
+        const int cnt = (int)((s_hi - base) < T ? (s_hi - base) : T);
         for (int j = 0; j < cnt; j++) {
             if (base + j == p) continue;
             const double dx = sx[j] - xp, dy = sy[j] - yp, dz = sz[j] - zp;
@@ -695,12 +701,40 @@ __global__ __launch_bounds__(256) void k_direct_vjp(const double *__restrict__ p
         }
         __syncthreads();
     }
-    if (valid) {
+    if (valid && gridDim.y == 1) {
         g_pos[3 * p] += G * gx;
         g_pos[3 * p + 1] += G * gy;
         g_pos[3 * p + 2] += G * gz;
         g_mass[p] += G * gm;
+    } else if (valid) {
+        double *o = part + 4 * ((int64_t)blockIdx.y * n + p);
+        o[0] = gx;
+        o[1] = gy;
+        o[2] = gz;
+        o[3] = gm;
     }
+}
+
+// Adds G times the rows' partial sums, in row order, into the gradients.
+__global__ __launch_bounds__(256) void k_direct_vjp_reduce(const double *__restrict__ part,
+                                                           int64_t n, int rows, double G,
+                                                           double *__restrict__ g_pos,
+                                                           double *__restrict__ g_mass)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    double gx = 0.0, gy = 0.0, gz = 0.0, gm = 0.0;
+    for (int r = 0; r < rows; r++) {
+        const double *o = part + 4 * ((int64_t)r * n + p);
+        gx += o[0];
+        gy += o[1];
+        gz += o[2];
+        gm += o[3];
+    }
+    g_pos[3 * p] += G * gx;
+    g_pos[3 * p + 1] += G * gy;
+    g_pos[3 * p + 2] += G * gz;
+    g_mass[p] += G * gm;
 }
 
 // Adjoint of the second kick: abar += dt/2 vbar.
@@ -810,15 +844,28 @@ hipError_t launch_tree_vjp(const Workspace &w, const AdjointWork &aw, hipStream_
 
 hipError_t launch_direct_vjp(hipStream_t s, const double *pos, const double *mass,
                              const double *eps, int64_t n, double eps0sq, double G,
-                             const double *lambda, double *g_pos, double *g_mass)
+                             const double *lambda, double *g_pos, double *g_mass, double *part)
 {
     if (n <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)((n + 255) / 256);
+    // rows of source tiles as in the direct sum: targets x rows reaches
+    // kDirectBlocks, and rows * n <= kDirectBlocks * 256 fits the buffer
+    const int64_t tb = (n + 255) / 256;
+    int64_t rows = tb >= kDirectBlocks ? 1 : kDirectBlocks / tb;
+    if (rows > kDirectSplits) rows = kDirectSplits;
+    if (rows > tb) rows = tb;
+    const int64_t tiles = (tb + rows - 1) / rows;
+    rows = (tb + tiles - 1) / tiles;
+    if (!part) rows = 1;
+    const int64_t chunk = rows == 1 ? n : tiles * 256;
+    const dim3 grid((unsigned)tb, (unsigned)rows);
     if (eps)
-        k_direct_vjp<true><<<grid, 256, 0, s>>>(pos, mass, eps, n, eps0sq, G, lambda, g_pos, g_mass);
+        k_direct_vjp<true><<<grid, 256, 0, s>>>(pos, mass, eps, n, eps0sq, G, lambda, g_pos,
+                                                g_mass, chunk, part);
     else
         k_direct_vjp<false><<<grid, 256, 0, s>>>(pos, mass, eps, n, eps0sq, G, lambda, g_pos,
-                                                 g_mass);
+                                                 g_mass, chunk, part);
+    if (rows > 1)
+        k_direct_vjp_reduce<<<(unsigned)tb, 256, 0, s>>>(part, n, (int)rows, G, g_pos, g_mass);
     return hipGetLastError();
 }
 

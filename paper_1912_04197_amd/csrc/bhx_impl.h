@@ -244,7 +244,7 @@ hipError_t launch_tree_vjp(const Workspace &w, const AdjointWork &aw, hipStream_
                            double *g_mass);
 hipError_t launch_direct_vjp(hipStream_t s, const double *pos, const double *mass,
                              const double *eps, int64_t n, double eps0sq, double G,
-                             const double *lambda, double *g_pos, double *g_mass);
+                             const double *lambda, double *g_pos, double *g_mass, double *part);
 hipError_t launch_adj_kick(hipStream_t s, double *abar, const double *vbar, int64_t n, double dt);
 hipError_t launch_adj_drift_kick(hipStream_t s, double *vbar, double *abar, const double *xbar,
                                  int64_t n, double dt);

@@ -238,7 +238,7 @@ bh_status vjp(bh_ctx *c, const double *pos, const double *mass, double softening
         BHX_HIP(c, bhx::launch_tree_vjp(c->w, c->aw, c->stream, p, lambda, g_pos, g_mass));
     } else {
         BHX_HIP(c, bhx::launch_direct_vjp(c->stream, pos, mass, eps, n, softening * softening,
-                                          c->cfg.G, lambda, g_pos, g_mass));
+                                          c->cfg.G, lambda, g_pos, g_mass, c->w.dpart));
     }
     return BH_OK;
 }
