@@ -125,3 +125,28 @@ def test_functional_forms_need_a_gpu():
         P.compute_accel(p, m, 0.0, 0.5)
     with pytest.raises(RuntimeError):
         P.compute_accel_direct(p, m)
+
+
+def test_bench_phase_floors():
+    """bench.py's per-phase roofline: each floor is the phase's algorithmic bytes
+    at 8 TB/s (the walk: its flops at 157.3 TFLOP/s when longer), and the step
+    fraction is the sum of the floors over the step time."""
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, root)
+    import bench
+
+    n, inter = 1 << 20, 2.7e9
+    out = bench.step_phases(n, inter, 4.0, 0.4, 3.5)
+    # the JSON values are rounded to 4 decimals
+    assert out["build"]["floor_ms"] == pytest.approx(bench.BYTES_PER_BODY["build"] * n / 8e9,
+                                                     abs=1e-4)
+    walk_alu = 20 * inter / 157.3e12 * 1e3
+    assert out["walk"]["bound"] == "alu"
+    assert out["walk"]["floor_ms"] == pytest.approx(walk_alu, abs=1e-4)
+    assert out["integrate"]["ms"] == pytest.approx(0.1)
+    floors = sum(out[k]["floor_ms"] for k in ("build", "walk", "integrate"))
+    assert out["step_roofline_frac"] == pytest.approx(floors / 4.0, abs=1e-4)
+    # a walk with few interactions is bound by its bytes instead
+    assert bench.step_phases(n, 1e3, 4.0, 0.4, 3.5)["walk"]["bound"] == "hbm"
