@@ -226,30 +226,59 @@ __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ pos, in
 
 // --------------------------------------------------------------- 3. sort
 
+// Scene index of caller index v: for at most kLdsScenes scenes a binary
+// search of the scene offsets staged in LDS (soff), else scene_of[v].
+constexpr int kLdsScenes = 256;
+__device__ inline uint32_t scene_index(const int64_t *soff, int ns,
+                                       const uint16_t *__restrict__ scene_of, uint32_t v)
+{
+    if (ns > kLdsScenes) return scene_of[v];
+    int lo = 0, hi = ns;  // soff[lo] <= v < soff[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (soff[mid] <= (int64_t)v)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return (uint32_t)lo;
+}
+
 // Sort digit of one element: 8 bits of its key, or for shift >= 64 8 bits of
 // its scene index (shift - 64 = 0 or 8).
-__device__ inline uint32_t sort_digit(uint64_t key, uint32_t val, int shift,
-                                      const uint16_t *__restrict__ scene_of)
+__device__ inline uint32_t sort_digit(uint64_t key, uint32_t val, int shift, const int64_t *soff,
+                                      int ns, const uint16_t *__restrict__ scene_of)
 {
     if (shift < 64) return (uint32_t)(key >> shift) & 255u;
-    return ((uint32_t)scene_of[val] >> (shift - 64)) & 255u;
+    return (scene_index(soff, ns, scene_of, val) >> (shift - 64)) & 255u;
+}
+
+// Stages the scene offsets in LDS for the scene passes (before a barrier).
+__device__ inline void stage_offsets(int64_t *soff, const int64_t *__restrict__ offsets, int ns,
+                                     int shift)
+{
+    if (shift >= 64 && ns <= kLdsScenes)
+        for (int i = threadIdx.x; i <= ns; i += blockDim.x) soff[i] = offsets[i];
 }
 
 // Per-tile digit histogram, written digit-major: counts[d * nblk + tile].
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint64_t *__restrict__ keys,
                                                             const uint32_t *__restrict__ vals,
                                                             const uint16_t *__restrict__ scene_of,
-                                                            int64_t n, int shift,
+                                                            const int64_t *__restrict__ offsets,
+                                                            int ns, int64_t n, int shift,
                                                             uint32_t *__restrict__ counts,
                                                             int nblk)
 {
     __shared__ uint32_t h[256];
+    __shared__ int64_t soff[kLdsScenes + 1];
     h[threadIdx.x] = 0;
+    stage_offsets(soff, offsets, ns, shift);
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     for (int r = 0; r < kSortItems; r++) {
         int64_t i = base + r * kSortThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[sort_digit(keys[i], vals[i], shift, scene_of)], 1u);
+        if (i < n) atomicAdd(&h[sort_digit(keys[i], vals[i], shift, soff, ns, scene_of)], 1u);
     }
     __syncthreads();
     counts[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
@@ -281,7 +310,7 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t *__restrict__ counts
 // addresses of each digit's output run.
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
-    const uint16_t *__restrict__ scene_of,
+    const uint16_t *__restrict__ scene_of, const int64_t *__restrict__ offsets, int ns,
     uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, int64_t n, int shift,
     const uint32_t *__restrict__ counts, const uint32_t *__restrict__ totals, int nblk)
 {
@@ -293,7 +322,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     __shared__ uint32_t lstart[256];
     __shared__ uint64_t skey[kSortTile];
     __shared__ uint32_t sval[kSortTile];
+    __shared__ uint8_t sdig[kSortTile];  // digits of the reordered tile
+    __shared__ int64_t soff[kLdsScenes + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    stage_offsets(soff, offsets, ns, shift);  // read after the barrier below
 
     uint32_t tot;
     const uint32_t t = totals[tid];
@@ -316,7 +348,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
 #pragma unroll
     for (int r = 0; r < kSortItems; r++) {
         const bool valid = wbase + r * 64 + lane < n;
-        const uint32_t d = valid ? sort_digit(k[r], v[r], shift, scene_of) : 0u;
+        const uint32_t d = valid ? sort_digit(k[r], v[r], shift, soff, ns, scene_of) : 0u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
@@ -353,6 +385,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
             if (lp < (uint32_t)kSortTile) {
                 skey[lp] = k[r];
                 sval[lp] = v[r];
+                sdig[lp] = (uint8_t)dig[r];
             }
         }
     }
@@ -361,7 +394,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     for (int lp = tid; lp < cnt; lp += kSortThreads) {
         const uint64_t key = skey[lp];
         const uint32_t val = sval[lp];
-        const uint32_t d = sort_digit(key, val, shift, scene_of);
+        const uint32_t d = sdig[lp];
         const int64_t o = (int64_t)digit_base[d] + lp - lstart[d];
         if (o >= 0 && o < n) {
             kout[o] = key;
@@ -925,12 +958,12 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
     for (int pass = 0; pass < passes; pass++) {
         const int shift = pass < 8 ? 8 * pass : 64 + 8 * (pass - 8);
         const int src = (pass + first) & 1, dst = src ^ 1;
-        k_sort_hist<<<nblk, kSortThreads, 0, s>>>(w.keys[src], w.idx[src], lay.scene_of, n, shift,
-                                                  w.sort_counts, nblk);
+        k_sort_hist<<<nblk, kSortThreads, 0, s>>>(w.keys[src], w.idx[src], lay.scene_of,
+                                                  lay.offsets, ns, n, shift, w.sort_counts, nblk);
         k_sort_scan<<<256, 256, 0, s>>>(w.sort_counts, w.sort_totals, nblk);
         k_sort_scatter<<<nblk, kSortThreads, 0, s>>>(w.keys[src], w.idx[src], lay.scene_of,
-                                                     w.keys[dst], w.idx[dst], n, shift,
-                                                     w.sort_counts, w.sort_totals, nblk);
+                                                     lay.offsets, ns, w.keys[dst], w.idx[dst], n,
+                                                     shift, w.sort_counts, w.sort_totals, nblk);
     }
     k_gather<<<nb, 256, 0, s>>>(pos, mass, eps, w.idx[0], n, w.body, w.beps2);
 
