@@ -440,6 +440,45 @@ def bench_crossover(ns=(1000, 2048, 4000, 16000, 64000), thetas=(0.25, 0.5, 0.75
             "rows": rows}
 
 
+def ceilings(walk_tflops):
+    """Achievable ceilings measured on this GPU beside the datasheet ones: HBM
+    by a device-to-device copy of 1 GiB (bytes read + written, best of 5),
+    vector FP32 (non-packed) and FP64 by the library's FMA probe."""
+    import torch
+
+    from paper_1912_04197_amd.api import probe_fma
+
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    copy_tbs = 2 * n * 8 / (best * 1e-3) / 1e12
+    del src, dst
+    fp32 = probe_fma("fp32")
+    fp64 = probe_fma("fp64")
+    log(f"ceilings: copy {copy_tbs:.2f} TB/s, FMA fp32 {fp32:.1f} fp64 {fp64:.1f} TFLOP/s")
+    return {
+        "hbm_copy_tb_s": round(copy_tbs, 3),
+        "hbm_datasheet_tb_s": PEAK_HBM_TBS,
+        "fp32_fma_tflops": round(fp32, 2),
+        "fp32_datasheet_tflops": PEAK_FP32_TFLOPS,
+        "fp32_datasheet_nonpacked_tflops": round(PEAK_FP32_TFLOPS / 2, 2),
+        "fp64_fma_tflops": round(fp64, 2),
+        "fp64_datasheet_tflops": 78.6,
+        "walk_frac_of_measured_fp32": round(walk_tflops / fp32, 4) if fp32 > 0 else None,
+        "how": "copy: torch device-to-device copy of 1 GiB, best of 5; FMA: 8 independent "
+               "chains per lane, 8 wavefronts per SIMD on every CU (bh_probe_fma)",
+    }
+
+
 def step_phases(n, interactions, ms_step, build_ms, walk_ms):
     """Per-phase roofline of one step: each phase's floor is its algorithmic
     HBM bytes at the HBM peak or, for the walk, its flops at the FP32 vector
@@ -624,6 +663,7 @@ def main():
             "flops_per_interaction": FLOPS_PER_INTERACTION,
         },
         "phases": step_phases(n, interactions, ms_step, build_ms, walk_ms),
+        "ceilings": ceilings(achieved),
     }
 
     if not args.no_extras:

@@ -319,6 +319,19 @@ bh_status bh_timing_reset(bh_ctx *ctx);
 bh_status bh_diagnostics(bh_ctx *ctx, const double *pos, const double *vel, const double *mass,
                          double softening, const double *eps, double out[8], int64_t n);
 
+/* Measured vector FMA rate of the current device: the achievable ceiling
+ * reported beside the datasheet peak for the walk and the direct sum, which
+ * are bound by plain VALU arithmetic. One launch of 8 wavefronts per SIMD on
+ * every compute unit; each lane runs 8 independent fused multiply-add chains
+ * of `iters` steps, in FP32 (precision BH_FP32C; non-packed instructions, as
+ * the library's kernels use) or FP64 (BH_FP64). *tflops (host) receives
+ * 2 x FMAs / device time of that launch (HIP events on hip_stream, NULL = the
+ * default stream), timed after one shorter untimed launch. Allocates and frees
+ * its own output (4 or 8 bytes per thread); synchronises. Errors: BH_E_INVALID
+ * for a NULL tflops, iters outside [1, 2^32] or another precision; BH_E_OOM;
+ * BH_E_HIP. */
+bh_status bh_probe_fma(void *hip_stream, int32_t precision, int64_t iters, double *tflops);
+
 #ifdef __cplusplus
 }
 #endif

@@ -9,7 +9,7 @@ N^2 sum, and a kick-drift-kick leapfrog. The kernels live in libbhx.so
 from __future__ import annotations
 
 __all__ = ["Context", "BHError", "load_library", "compute_accel", "compute_accel_direct",
-           "step_leapfrog", "autotune", "gravity_dt_bound", "rollout"]
+           "step_leapfrog", "autotune", "gravity_dt_bound", "probe_fma", "rollout"]
 
 
 def load_library():
@@ -21,7 +21,7 @@ def load_library():
 
 def __getattr__(name):
     if name in ("Context", "BHError", "compute_accel", "compute_accel_direct", "step_leapfrog",
-                "autotune", "gravity_dt_bound"):
+                "autotune", "gravity_dt_bound", "probe_fma"):
         from . import api
 
         return getattr(api, name)

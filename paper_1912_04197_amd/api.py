@@ -366,6 +366,22 @@ def autotune(offsets, pos, vel, mass, theta=0.5, dt=1e-3, softening=0.0, eps=Non
     return int(out.leaf_size), int(out.walk_group), float(out.ms_per_step)
 
 
+def probe_fma(precision="fp32", iters=65536):
+    """Measured vector FMA rate of the current GPU in TFLOP/s (2 flops per
+    FMA): 8 independent FMA chains per lane on 8 wavefronts per SIMD, in FP32
+    (non-packed) or FP64; the achievable ceiling of VALU-bound kernels."""
+    lib = L.load()
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: libbhx runs on the GPU only")
+    prec = {"fp64": L.BH_FP64, "fp32": L.BH_FP32C}[precision]
+    out = C.c_double(0.0)
+    rc = lib.bh_probe_fma(C.c_void_p(torch.cuda.current_stream().cuda_stream), prec, int(iters),
+                          C.byref(out))
+    if rc != 0:
+        raise BHError(rc, "bh_probe_fma failed")
+    return float(out.value)
+
+
 def gravity_dt_bound(density, G=1.0):
     """Largest gravity time step the paper allows (eq. dt_g): half the
     characteristic time 1 / sqrt(G rho) of a body of mean density rho."""

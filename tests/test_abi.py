@@ -91,6 +91,11 @@ def test_null_context_calls(lib):
     assert lib.bh_batched_step(None, 1, None, None, None, None, 0.0, None, 0.5, 1e-3, 1, None) == L.BH_E_INVALID
     assert lib.bh_last_error(None) == b"NULL context"
     lib.bh_destroy(None)
+    # the FMA probe checks its arguments before any device call
+    r = C.c_double(-1.0)
+    assert lib.bh_probe_fma(None, L.BH_FP32C, 100, None) == L.BH_E_INVALID
+    assert lib.bh_probe_fma(None, L.BH_FP32C, 0, C.byref(r)) == L.BH_E_INVALID
+    assert lib.bh_probe_fma(None, 7, 100, C.byref(r)) == L.BH_E_INVALID
 
 
 def test_package_fails_loudly_without_library(tmp_path, monkeypatch):

@@ -55,3 +55,12 @@ def test_functional_direct_and_leapfrog(P):
     P.step_leapfrog(p, v, m, a0, 1e-3, 5, theta=0.5, softening=1e-3)
     ctx.step_leapfrog(p1, v1, m, a1, 1e-3, 5, theta=0.5, softening=1e-3)
     assert torch.equal(p, p1) and torch.equal(v, v1) and torch.equal(a0, a1)
+
+
+def test_probe_fma_rates(P):
+    """The measured FMA rates are positive and within the datasheet peaks
+    (FP32 non-packed issues at the FP64 rate: half the packed 157.3)."""
+    fp32 = P.probe_fma("fp32", iters=4096)
+    fp64 = P.probe_fma("fp64", iters=4096)
+    assert 5.0 < fp32 <= 1.05 * 157.3 / 2
+    assert 5.0 < fp64 <= 1.05 * 78.6
