@@ -328,7 +328,8 @@ bh_status bh_diagnostics(bh_ctx *ctx, const double *pos, const double *vel, cons
  * 2 x FMAs / device time of that launch (HIP events on hip_stream, NULL = the
  * default stream), timed after one shorter untimed launch. Allocates and frees
  * its own output (4 or 8 bytes per thread); synchronises. Errors: BH_E_INVALID
- * for a NULL tflops, iters outside [1, 2^32] or another precision; BH_E_OOM;
+ * for a NULL tflops, iters outside [1, 2^24] (a launch of at most about 2 s)
+ * or another precision; BH_E_OOM;
  * BH_E_HIP. */
 bh_status bh_probe_fma(void *hip_stream, int32_t precision, int64_t iters, double *tflops);
 

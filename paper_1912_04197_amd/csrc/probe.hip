@@ -77,7 +77,7 @@ hipError_t probe(hipStream_t s, int64_t iters, double *tflops)
 extern "C" bh_status bh_probe_fma(void *hip_stream, int32_t precision, int64_t iters,
                                   double *tflops)
 {
-    if (!tflops || iters < 1 || iters > (int64_t)1 << 32) return BH_E_INVALID;
+    if (!tflops || iters < 1 || iters > (int64_t)1 << 24) return BH_E_INVALID;  // <= about 2 s
     if (precision != BH_FP64 && precision != BH_FP32C) return BH_E_INVALID;
     *tflops = 0.0;
     const hipStream_t s = (hipStream_t)hip_stream;
