@@ -556,7 +556,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} (WORLD_SIZE={world}) is not "
-              "supported: this build runs the whole hot path on a single MI355X.", file=sys.stderr)
+              "supported: the library runs the whole step on a single MI355X.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
