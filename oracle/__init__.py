@@ -100,6 +100,8 @@ def _load(path: str | None = None):
     lib.orc_tree_vjp.restype = C.c_int
     lib.orc_rollout_grad.argtypes = [I64, P, P, P, P, D, D, D, I32, D, I32, P, P, P, P, P]
     lib.orc_rollout_grad.restype = C.c_int
+    lib.orc_gravity_dt_bound.argtypes = [I64, P, P, D, P]
+    lib.orc_gravity_dt_bound.restype = C.c_int
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = C.c_int
     _lib = lib
@@ -330,6 +332,17 @@ def contact_components(pos, radius, skin=0.0):
     _check(lib.orc_contact_components(n, _ptr(pos), _ptr(radius), float(skin), _ptr(label),
                                       C.byref(nc), C.byref(na)))
     return label, int(nc.value), int(na.value)
+
+
+def gravity_dt_bound(mass, radius, G=1.0) -> float:
+    """Largest gravity time step of eq. (dt_g) for bodies of these masses and
+    radii: 1 / (2 sqrt(G rho)) with rho the largest body density."""
+    mass = _f64(mass)
+    n = mass.shape[0]
+    radius = _f64(radius, (n,))
+    out = np.zeros(1)
+    _check(_load().orc_gravity_dt_bound(n, _ptr(mass), _ptr(radius), float(G), _ptr(out)))
+    return float(out[0])
 
 
 def diagnostics(pos, vel, mass, softening=0.0, eps=None, G=1.0) -> np.ndarray:

@@ -37,6 +37,7 @@
  */
 #include "bh_oracle.h"
 
+#include <float.h>
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
@@ -86,6 +87,13 @@ static int check_bodies(int64_t n, const double *pos, const double *mass, const 
     return 0;
 }
 
+/* A term contributes only when its squared softened distance is a positive
+ * normal double. r^2 = 0 is two coincident unsoftened bodies (eq. Force_rComp
+ * exists to keep such forces finite); a subnormal r^2 (|d| below 1.5e-154 with
+ * no softening) is the same coincidence below the double range, where
+ * 1 / r^3 is not representable; both are read as contributing nothing. */
+static int term_counts(double r2) { return r2 >= DBL_MIN; }
+
 /* One softened term from a source of mass gm/G at offset d from the target.
  * Adds G m d / r^3 to acc, -G m / r to *phi and G m |d| / r^3 to *aabs. */
 static void add_term(double dx, double dy, double dz, double e2, double gm, double *acc,
@@ -93,7 +101,7 @@ static void add_term(double dx, double dy, double dz, double e2, double gm, doub
 {
     double d2 = dx * dx + dy * dy + dz * dz;
     double r2 = d2 + e2;
-    if (r2 == 0.0) return;
+    if (!term_counts(r2)) return;
     double r = sqrt(r2);
     double inv3 = 1.0 / (r2 * r);
     acc[0] += gm * dx * inv3;
@@ -419,7 +427,7 @@ static void add_quad_term(double dx, double dy, double dz, double e2, double G, 
                           double *acc, double *phi)
 {
     double r2 = dx * dx + dy * dy + dz * dz + e2;
-    if (r2 == 0.0) return;
+    if (!term_counts(r2)) return;
     double qd[3] = {Q[0] * dx + Q[3] * dy + Q[4] * dz, Q[3] * dx + Q[1] * dy + Q[5] * dz,
                     Q[4] * dx + Q[5] * dy + Q[2] * dz};
     double dqd = dx * qd[0] + dy * qd[1] + dz * qd[2];
@@ -650,6 +658,31 @@ int orc_diagnostics(int64_t n, const double *pos, const double *vel, const doubl
     return rc;
 }
 
+/* eq. (dt_g): the gravity time step must satisfy Delta t_g < T_g / 2 =
+ * 1 / (2 sqrt(G rho)), rho the material density of the bodies. For a set of
+ * bodies the bound is the one of the densest body, rho_i = m_i / V_i with
+ * V_i = (4/3) pi r_i^3 (the shortest characteristic time). Massless bodies are
+ * skipped; with none left the bound is +inf, and a massive body of radius 0
+ * (infinite density) gives 0. */
+int orc_gravity_dt_bound(int64_t n, const double *mass, const double *radius, double G,
+                         double *dt)
+{
+    if (n < 0 || !dt || (n > 0 && (!mass || !radius)) || !(G > 0.0) || !isfinite(G)) return 1;
+    double rho_max = -1.0;
+    for (int64_t i = 0; i < n; i++) {
+        double m = mass[i], r = radius[i];
+        if (!isfinite(m) || !isfinite(r)) return 2;
+        if (m < 0.0) return 3;
+        if (r < 0.0) return 1;
+        if (m == 0.0) continue;
+        double vol = (4.0 / 3.0) * 3.141592653589793 * (r * r * r);
+        double rho = m / vol; /* +inf for r = 0 */
+        if (rho > rho_max) rho_max = rho;
+    }
+    *dt = rho_max < 0.0 ? INFINITY : 0.5 / sqrt(G * rho_max);
+    return 0;
+}
+
 /* ------------------------------------------------------------------- VJPs */
 
 /* Adjoint of one softened term t = G m_s d / r^3, d = X_s - x_i,
@@ -657,7 +690,8 @@ int orc_diagnostics(int64_t n, const double *pos, const double *vel, const doubl
  *   dt/dd = G m_s K, K = I / r^3 - 3 d d^T / r^5;  dt/dm_s = G d / r^3;
  *   dt/de2 = -3/2 G m_s d / r^5.
  * Writes gd = G m_s K l (so g_x_i -= gd, g_X_s += gd), gm = G l.d / r^3
- * and ge2 = -3/2 G m_s (l.d) / r^5. A term with r^2 = 0 contributes 0. */
+ * and ge2 = -3/2 G m_s (l.d) / r^5. A term whose r^2 is not a positive normal
+ * double contributes 0 (as in add_term). */
 static void term_vjp(const double d[3], double e2, double G, double ms, const double l[3],
                      double gd[3], double *gm, double *ge2)
 {
@@ -665,7 +699,7 @@ static void term_vjp(const double d[3], double e2, double G, double ms, const do
     gd[0] = gd[1] = gd[2] = 0.0;
     *gm = 0.0;
     *ge2 = 0.0;
-    if (r2 == 0.0) return;
+    if (!term_counts(r2)) return;
     double r = sqrt(r2);
     double inv3 = 1.0 / (r2 * r);
     double inv5 = inv3 / r2;

@@ -103,6 +103,12 @@ int orc_euler(int64_t n, double *pos, double *vel, const double *mass, const dou
 int orc_contact_components(int64_t n, const double *pos, const double *radius, double skin,
                            int32_t *label, int64_t *n_contacts, int64_t *n_aggregates);
 
+/* Largest gravity time step of eq. (dt_g), 1 / (2 sqrt(G rho_max)), with
+ * rho_max the largest density m_i / ((4/3) pi r_i^3) over the massive bodies
+ * (+inf when none is massive, 0 when a massive body has radius 0). */
+int orc_gravity_dt_bound(int64_t n, const double *mass, const double *radius, double G,
+                         double *dt);
+
 /* out[0] kinetic energy, out[1] potential energy 1/2 sum m phi (direct sum),
  * out[2..4] linear momentum, out[5..7] angular momentum about the origin. */
 int orc_diagnostics(int64_t n, const double *pos, const double *vel, const double *mass,

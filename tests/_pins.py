@@ -552,6 +552,46 @@ def pin_euler_two_rate_momentum():
     assert np.abs(d[2:5] - e0[2:5]).max() < 1e-14
 
 
+def pin_gravity_dt_bound():
+    """eq. (dt_g): 1 / (2 sqrt(G rho)) for one body of each density the paper
+    quotes for asteroid material (golden, SI units; of the order of thousands
+    of seconds), the densest body decides for a mixed set, massless bodies are
+    skipped, and a massive point (radius 0) allows no step."""
+    rows = _golden("dt_g.txt")
+    for G, rho, r, bound in rows:
+        m = rho * (4.0 / 3.0) * math.pi * r ** 3
+        got = oracle.gravity_dt_bound([m], [r], G=G)
+        assert abs(got - bound) <= 1e-13 * bound, (rho, got, bound)
+        assert 500.0 < got < 5000.0
+    # mixed set: the 4 g/cm^3 body decides whatever the order and sizes
+    G = rows[0][0]
+    m = [1000 * (4 / 3) * math.pi * 7.0 ** 3, 4000 * (4 / 3) * math.pi * 2.0 ** 3, 0.0]
+    r = [7.0, 2.0, 0.5]
+    for perm in ([0, 1, 2], [2, 1, 0], [1, 2, 0]):
+        got = oracle.gravity_dt_bound([m[i] for i in perm], [r[i] for i in perm], G=G)
+        assert abs(got - rows[1][3]) <= 1e-13 * rows[1][3]
+    assert oracle.gravity_dt_bound([0.0, 0.0], [1.0, 2.0]) == math.inf
+    assert oracle.gravity_dt_bound([1.0, 1e-3], [1.0, 0.0]) == 0.0
+
+
+def pin_coincident_below_double_range():
+    """Two unsoftened bodies 1e-100 apart attract as G m / d^2 (1e200 here, in
+    range); 1e-160 apart their squared distance is below the smallest normal
+    double, 1 / r^3 is not representable, and (like r^2 = 0) the pair adds
+    nothing: direct sum, tree walk and VJP alike."""
+    for d, want in ((1e-100, 1e200), (1e-160, 0.0)):
+        x = np.array([[0.0, 0.0, 0.0], [d, 0.0, 0.0]])
+        m = np.array([1.0, 1.0])
+        a, _, _ = oracle.direct(x, m)
+        assert abs(a[0, 0] - want) <= 1e-15 * want and a[0, 1] == a[0, 2] == 0.0, (d, a)
+        assert a[1, 0] == -a[0, 0]
+        at = oracle.bh(x, m, 0.5, leaf=2)[0]
+        assert np.array_equal(at, a), d
+        if want == 0.0:
+            gx, gm = oracle.direct_vjp(x, m, np.ones((2, 3)))
+            assert np.all(gx == 0.0) and np.all(gm == 0.0)
+
+
 def pin_diagnostics_two_body():
     s = ics.two_body_circular(0.7, 0.3, 1.0)
     d = oracle.diagnostics(s.pos, s.vel, s.mass)

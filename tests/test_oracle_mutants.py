@@ -16,6 +16,14 @@ import oracle
 SRC = os.path.join(os.path.dirname(oracle.__file__), "bh_oracle.c")
 
 MUTANTS = {
+    "subnormal_r2_counts": ("static int term_counts(double r2) { return r2 >= DBL_MIN; }",
+                            "static int term_counts(double r2) { return r2 > 0.0; }"),
+    "dt_g_no_half": ("*dt = rho_max < 0.0 ? INFINITY : 0.5 / sqrt(G * rho_max);",
+                     "*dt = rho_max < 0.0 ? INFINITY : 1.0 / sqrt(G * rho_max);"),
+    "dt_g_least_dense": ("if (rho > rho_max) rho_max = rho;",
+                         "if (rho_max < 0.0 || rho < rho_max) rho_max = rho;"),
+    "dt_g_radius_squared": ("double vol = (4.0 / 3.0) * 3.141592653589793 * (r * r * r);",
+                            "double vol = (4.0 / 3.0) * 3.141592653589793 * (r * r);"),
     "contact_strict": ("if (dist2 <= R * R) {", "if (dist2 < R * R) {"),
     "contact_union_larger": ("label[b] = (int32_t)a;\n                    else\n                        label[a] = (int32_t)b;",
                              "label[a] = (int32_t)b;\n                    else\n                        label[b] = (int32_t)a;"),
