@@ -312,7 +312,20 @@ bh_status bh_stats(bh_ctx *ctx, bh_stats_t *out);
 /* Zeroes the BH_FLAG_TIMING totals (synchronises). */
 bh_status bh_timing_reset(bh_ctx *ctx);
 
-/* Energy and momenta of a state, by FP64 reductions on the device:
+/* Largest gravity time step allowed by eq. (dt_g) (Section "The asteroid
+ * aggregation problem", "Gravitational dynamics"): Delta t_g < T_g / 2 =
+ * 1 / (2 sqrt(G rho)), rho the material density of the bodies and G the
+ * context's. Bodies of different densities are bounded by the densest one,
+ * rho_i = mass_i / ((4/3) pi radius_i^3) (mass, radius: n float64 device
+ * arrays, radius >= 0; massless bodies are skipped). *dt_out (host) receives
+ * the bound: +inf when no body is massive, 0 when a massive body has radius 0.
+ * Synchronises. Errors: BH_E_INVALID (NULL dt_out, n < 0, NULL arrays with
+ * n > 0, G <= 0); device: BH_E_NONFINITE (a non-finite or negative mass or
+ * radius). */
+bh_status bh_gravity_dt_bound(bh_ctx *ctx, const double *mass, const double *radius, int64_t n,
+                              double *dt_out);
+
+/* Energy and momenta of a state, by compensated FP64 reductions on the device:
  * out (host, 8 doubles) = {E_kin, E_pot, Px, Py, Pz, Lx, Ly, Lz}, with
  * E_pot = 1/2 sum m_i phi_i from the direct sum and L about the origin.
  * Synchronises. Errors: as bh_compute_accel_direct. */

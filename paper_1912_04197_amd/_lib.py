@@ -60,6 +60,7 @@ SIGNATURES = {
     "bh_tree_export": ([P, C.POINTER(bh_tree_view)], C.c_int),
     "bh_stats": ([P, C.POINTER(bh_stats_t)], C.c_int),
     "bh_diagnostics": ([P, P, P, P, D, P, P, I64], C.c_int),
+    "bh_gravity_dt_bound": ([P, P, P, I64, C.POINTER(D)], C.c_int),
     "bh_timing_reset": ([P], C.c_int),
     "bh_accel_vjp": ([P, P, P, D, P, D, P, P, P, I64], C.c_int),
     "bh_batched_accel": ([P, I32, P, P, P, D, P, D, P, P], C.c_int),

@@ -328,6 +328,19 @@ class Context:
         self._bind()
         self._rc(self._lib.bh_timing_reset(self._h))
 
+    def gravity_dt_bound(self, mass, radius):
+        """Largest gravity time step of eq. (dt_g) for bodies of these masses
+        and radii (float64 GPU tensors): 1 / (2 sqrt(G rho)), rho the largest
+        body density (see bh_gravity_dt_bound)."""
+        n = int(mass.shape[0]) if mass.dim() == 1 else -1
+        _check_f64("mass", mass, (n,), self.device)
+        _check_f64("radius", radius, (n,), self.device)
+        out = C.c_double(0.0)
+        self._bind()
+        self._rc(self._lib.bh_gravity_dt_bound(self._h, _ptr(mass), _ptr(radius), n,
+                                               C.byref(out)))
+        return float(out.value)
+
     def diagnostics(self, pos, vel, mass, softening=0.0, eps=None):
         """[E_kin, E_pot, Px, Py, Pz, Lx, Ly, Lz] (host floats)."""
         n = self._bodies(pos, mass, eps)
@@ -340,7 +353,7 @@ class Context:
 
 
 def autotune(offsets, pos, vel, mass, theta=0.5, dt=1e-3, softening=0.0, eps=None,
-             precision="fp32c", G=1.0, steps=3):
+             precision="fp32c", G=1.0, steps=3, quad=False):
     """Fastest (leaf_size, walk_group, ms_per_step) for bh_batched_step on these
     scenes (see bh_autotune); the state tensors are not modified."""
     import numpy as np
@@ -355,7 +368,7 @@ def autotune(offsets, pos, vel, mass, theta=0.5, dt=1e-3, softening=0.0, eps=Non
     if eps is not None:
         _check_f64("eps", eps, (n,), dev)
     prec = {"fp64": L.BH_FP64, "fp32c": L.BH_FP32C}[precision]
-    cfg = L.bh_config(n, 16, prec, float(G), 0, 0, ns)
+    cfg = L.bh_config(n, 16, prec, float(G), L.BH_FLAG_QUAD if quad else 0, 0, ns)
     out = L.bh_tune_result()
     rc = lib.bh_autotune(C.byref(cfg), C.c_void_p(torch.cuda.current_stream().cuda_stream), ns,
                          o.ctypes.data_as(C.c_void_p), _ptr(pos), _ptr(vel), _ptr(mass),
@@ -380,16 +393,6 @@ def probe_fma(precision="fp32", iters=65536):
     if rc != 0:
         raise BHError(rc, "bh_probe_fma failed")
     return float(out.value)
-
-
-def gravity_dt_bound(density, G=1.0):
-    """Largest gravity time step the paper allows (eq. dt_g): half the
-    characteristic time 1 / sqrt(G rho) of a body of mean density rho."""
-    import math
-
-    if not (density > 0 and G > 0):
-        raise ValueError("density and G must be positive")
-    return 0.5 / math.sqrt(G * density)
 
 
 # -- functional forms: one cached context per (device, leaf, precision, G),
@@ -423,6 +426,13 @@ def compute_accel_direct(pos, mass, softening=0.0, *, eps=None, precision="fp32c
     """Direct N^2 accelerations, as compute_accel."""
     ctx = _context_for(pos.shape[0], 16, precision, G)
     return ctx.compute_accel_direct(pos, mass, softening=softening, eps=eps, potential=potential)
+
+
+def gravity_dt_bound(mass, radius, G=1.0):
+    """Largest gravity time step of eq. (dt_g) for bodies of these masses and
+    radii, with a context cached per device and G (see Context.gravity_dt_bound)."""
+    ctx = _context_for(1, 16, "fp64", G)
+    return ctx.gravity_dt_bound(mass, radius)
 
 
 def step_leapfrog(pos, vel, mass, acc, dt, nsteps, theta=0.5, softening=0.0, *, eps=None, leaf=16,

@@ -31,10 +31,12 @@ std::string cache_key(const bh_config *base, int32_t n_scenes, const int64_t *of
         }
     }
     char buf[256];
-    std::snprintf(buf, sizeof buf, "scenes=%d;n=%lld;layout=%016llx;prec=%d;G=%.17g;soft=%.17g;"
-                                   "eps=%d;theta=%.17g;dt=%.17g",
+    // flags that change the timed kernels (quadrupole nodes) are part of the key
+    const unsigned kflags = base->flags & (uint32_t)BH_FLAG_QUAD;
+    std::snprintf(buf, sizeof buf, "scenes=%d;n=%lld;layout=%016llx;prec=%d;flags=%u;G=%.17g;"
+                                   "soft=%.17g;eps=%d;theta=%.17g;dt=%.17g",
                   n_scenes, (long long)offsets[n_scenes], (unsigned long long)h, base->precision,
-                  base->G, softening, per_body_eps ? 1 : 0, theta, dt);
+                  kflags, base->G, softening, per_body_eps ? 1 : 0, theta, dt);
     return buf;
 }
 

@@ -144,8 +144,15 @@ __device__ inline double rsqrt_f64(double r2)
     return fma(0.5 * y, e, y);
 }
 
+// A pair term counts only when its squared softened distance is a positive
+// normal number in the precision it is computed in: r^2 = 0 (coincident
+// unsoftened bodies) and subnormal r^2 (the same coincidence below the
+// number range, where 1 / r^3 overflows) contribute nothing.
 // r2 is a positive normal number (not 0, subnormal, infinite or NaN).
 __device__ inline bool positive_normal(double r2) { return __builtin_amdgcn_class(r2, 0x100); }
+// The FP32 pair terms' form of the same test (finite r2 at or above FLT_MIN).
+constexpr float kFltMin = __FLT_MIN__;
+__device__ inline bool positive_normal_f(float r2) { return r2 >= kFltMin; }
 
 // Workspace owned by a context; sized once for n_max bodies.
 struct Workspace {
@@ -165,7 +172,7 @@ struct Workspace {
     TreeHeader *hdr = nullptr;
     int32_t *counts = nullptr;    // [n_cap][2] per-body walk counts, caller order
     double *scratch = nullptr;    // [n_cap] potential for diagnostics
-    double *red_part = nullptr;   // [reduction blocks][8]
+    double *red_part = nullptr;   // [reduction blocks][8][2] compensated partial sums
     double *dpart = nullptr;      // [kDirectPart] partial direct sums of split source ranges
     // Deepest non-empty level of the last build, written by the device into
     // pinned host memory (-1 before the first build): the next build launches
@@ -199,8 +206,11 @@ inline int64_t node_capacity(int64_t n, int leaf, int scenes = 1)
 }
 
 // Launchers (tree.hip). All enqueue on `s` and never synchronise.
+// all_levels: launch every tree level instead of stopping one level below the
+// previous build's depth (the depth hint is a host read, frozen in a captured
+// graph; with all levels, a replay builds any tree depth at full width).
 hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, const double *pos,
-                        const double *mass, const double *eps, int leaf);
+                        const double *mass, const double *eps, int leaf, bool all_levels = false);
 // scene_of[i] = scene of body i, from device offsets of n_scenes scenes
 hipError_t launch_scene_of(hipStream_t s, const int64_t *offsets, int n_scenes,
                            uint16_t *scene_of);
@@ -263,6 +273,11 @@ hipError_t launch_contacts(const Workspace &w, hipStream_t s, const double *radi
 hipError_t launch_euler_substeps(hipStream_t s, double *pos, double *vel, const double *acc,
                                  int64_t n, double dt, int k);
 hipError_t launch_kick(hipStream_t s, double *vel, const double *acc, int64_t n, double dt);
+// Largest body density m / ((4/3) pi r^3) over the massive bodies and the
+// gravity time-step bound 1 / (2 sqrt(G rho)) of eq. (dt_g) into out[0]
+// (+inf with no massive body); work[0] is scratch; bad input sets ST_NONFINITE.
+hipError_t launch_dt_bound(hipStream_t s, const double *mass, const double *radius, int64_t n,
+                           double G, long long *work, double *out, uint32_t *status);
 hipError_t launch_diag_reduce(hipStream_t s, const double *pos, const double *vel,
                               const double *mass, const double *phi, int64_t n, double *part,
                               double *out8_device);

@@ -39,6 +39,7 @@ struct bh_ctx {
     std::vector<int64_t> h_offsets;
     std::vector<int32_t> h_chunks, h_groups;
     int layout_group = 0;
+    uint64_t layout_gen = 0;  // bumped whenever the layout tables are re-uploaded
     bhx::Layout batch;
     // BH_FLAG_GRAPH: one captured step, replayed on a stream of the context
     hipStream_t cstream = nullptr;
@@ -181,7 +182,8 @@ bh_status force_tree(bh_ctx *c, const bhx::Layout &lay, const double *pos, const
     const int64_t n = lay.n;
     bh_status st = record(c, 0);
     if (st) return st;
-    BHX_HIP(c, bhx::launch_build(w, c->stream, lay, pos, mass, eps, c->cfg.leaf_size));
+    BHX_HIP(c, bhx::launch_build(w, c->stream, lay, pos, mass, eps, c->cfg.leaf_size,
+                                 c->capturing));
     st = record(c, 1);
     if (st) return st;
     c->tree_n = n;
@@ -259,6 +261,19 @@ bh_status set_layout(bh_ctx *c, int32_t n_scenes, const int64_t *offsets)
     if (c->layout_group == gb && (int64_t)c->h_offsets.size() == n_scenes + 1 &&
         std::equal(c->h_offsets.begin(), c->h_offsets.end(), offsets))
         return BH_OK;
+    // The tables are rewritten in place: wait until no queued or replayed step
+    // still reads them, and drop a graph captured with the old layout.
+    BHX_HIP(c, hipStreamSynchronize(c->stream));
+    if (c->cstream) BHX_HIP(c, hipStreamSynchronize(c->cstream));
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    if (c->graph) {
+        (void)hipGraphDestroy(c->graph);
+        c->graph = nullptr;
+    }
+    c->layout_gen++;
     c->h_offsets.assign(offsets, offsets + n_scenes + 1);
     c->h_chunks.clear();
     c->h_groups.clear();
@@ -326,10 +341,14 @@ bh_status run_steps(bh_ctx *c, const bhx::Layout &lay, double *pos, double *vel,
         }
         return BH_OK;
     }
+    // everything a captured step bakes in: pointers, sizes, the layout tables'
+    // generation (their contents and the grid sizes derived from them) and the
+    // physical parameters
     std::vector<double> key = {(double)(uintptr_t)pos, (double)(uintptr_t)vel,
                                (double)(uintptr_t)mass, (double)(uintptr_t)eps,
                                (double)(uintptr_t)acc, (double)lay.n, (double)(uintptr_t)lay.groups,
-                               (double)lay.n_scenes, softening, theta, dt};
+                               (double)lay.n_scenes, (double)lay.n_groups, (double)lay.n_chunks,
+                               (double)(lay.groups ? c->layout_gen : 0), softening, theta, dt};
     hipStream_t caller = c->stream;
     if (!c->gexec || key != c->gkey) {
         if (c->gexec) {
@@ -437,7 +456,7 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
     if (cfg->flags & BH_FLAG_COUNTS) A(dalloc(&w.counts, 2 * n));
     if (cfg->flags & BH_FLAG_QUAD) A(dalloc(&w.nquad, 6 * node_cap));
     A(dalloc(&w.scratch, 4 * n));
-    A(dalloc(&w.red_part, (int64_t)bhx::kRedBlocks * 8));
+    A(dalloc(&w.red_part, (int64_t)bhx::kRedBlocks * 16));
     A(dalloc(&w.dpart, bhx::kDirectPart));
     A(dalloc(&c->diag_out, 8));
     A(hipHostMalloc((void **)&w.depth_host, sizeof(int32_t), hipHostMallocMapped));
@@ -791,6 +810,26 @@ bh_status bh_timing_reset(bh_ctx *c)
     if (s) return s;
     c->timed_evals = 0;
     c->build_ms = c->walk_ms = 0.0;
+    return BH_OK;
+}
+
+bh_status bh_gravity_dt_bound(bh_ctx *c, const double *mass, const double *radius, int64_t n,
+                              double *dt_out)
+{
+    if (!c) return BH_E_INVALID;
+    if (!dt_out) return fail(c, BH_E_INVALID, "NULL dt_out");
+    if (n < 0) return fail(c, BH_E_INVALID, "n < 0");
+    if (n > 0 && (!mass || !radius)) return fail(c, BH_E_INVALID, "NULL mass or radius with n > 0");
+    if (!(c->cfg.G > 0.0)) return fail(c, BH_E_INVALID, "the context's G must be positive");
+    auto *work = (long long *)c->diag_out;
+    double *out = c->diag_out + 1;
+    BHX_HIP(c, bhx::launch_dt_bound(c->stream, mass, radius, n, c->cfg.G, work, out,
+                                    &c->w.hdr->status));
+    double dt = 0.0;
+    BHX_HIP(c, hipMemcpyAsync(&dt, out, sizeof(dt), hipMemcpyDeviceToHost, c->stream));
+    bh_status st = bh_sync(c);
+    if (st) return st;
+    *dt_out = dt;
     return BH_OK;
 }
 

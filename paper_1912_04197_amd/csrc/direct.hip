@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kTile) void k_direct(const double *__restrict__ pos
                     const float e2 = PEPS ? q.eh + e2hB : eps0f;
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, e2)));
                     const float rinv =
-                        (jj != skip && r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;
+                        (jj != skip && positive_normal_f(r2)) ? __builtin_amdgcn_rsqf(r2) : 0.f;
                     const float mr = q.m * rinv;
                     const float mr3 = mr * rinv * rinv;
                     fx = fmaf(mr3, dx, fx);

@@ -211,7 +211,8 @@ __global__ __launch_bounds__(64) void k_walk(
     const float e2hB = (float)(0.5 * eb2);
     const float eps0f = (float)eps0sq;
     // every body of the wave has a positive FP32 softening (the sweep's r^2 > 0 test is moot)
-    const bool soft_all = __ballot(!valid || (PEPS ? e2hB > 0.f : eps0f > 0.f)) == ~0ull;
+    const bool soft_all =
+        __ballot(!valid || positive_normal_f(PEPS ? e2hB : eps0f)) == ~0ull;
     const int woff = (int)offsetof(ItemF, mlo) + (bq >= 32 ? 4 : 0);
 
     double ax = 0.0, ay = 0.0, az = 0.0, ph = 0.0;
@@ -341,8 +342,9 @@ __global__ __launch_bounds__(64) void k_walk(
                 }
             }
         } else {
-          // With every body of the wave softened (its FP32 half eps^2 > 0),
-          // r^2 >= that softening > 0 for every pair, and the test is dropped.
+          // With every body of the wave softened (its FP32 half eps^2 a normal
+          // number), r^2 >= that softening for every pair, so r^2 is a
+          // positive normal number and the test is dropped.
           auto sweep = [&](auto all_soft) {
 #pragma unroll 1
             for (int j0 = 0; j0 < nd; j0 += kFlush * LPB) {
@@ -365,7 +367,8 @@ __global__ __launch_bounds__(64) void k_walk(
                                 dz = (float)(it.z - me.z);
                     const float e2 = PEPS ? it.e2h + e2hB : eps0f;
                     const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, e2)));
-                    const bool live = decltype(all_soft)::value ? on : (on && r2 > 0.f);
+                    const bool live =
+                        decltype(all_soft)::value ? on : (on && positive_normal_f(r2));
                     const float rinv = live ? __builtin_amdgcn_rsqf(r2) : 0.f;
                     const float mr = it.m * rinv;
                     const float mr3 = mr * rinv * rinv;
@@ -433,7 +436,7 @@ __global__ __launch_bounds__(64) void k_walk(
                 const float dx = (float)(it.x - tx), dy = (float)(it.y - ty), dz = (float)(it.z - tz);
                 const float e2 = PEPS ? it.e2h + te : eps0f;
                 const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, e2)));
-                const float rinv = (on && r2 > 0.f) ? __builtin_amdgcn_rsqf(r2) : 0.f;
+                const float rinv = (on && positive_normal_f(r2)) ? __builtin_amdgcn_rsqf(r2) : 0.f;
                 const float mr = it.m * rinv;
                 const float mr3 = mr * rinv * rinv;
                 float gxf = mr3 * dx, gyf = mr3 * dy, gzf = mr3 * dz, gpf = -mr;

@@ -89,6 +89,8 @@ def test_null_context_calls(lib):
     assert lib.bh_step_euler(None, None, None, None, 0.0, None, 0.5, 1e-3, 1, 1, None, 0) == L.BH_E_INVALID
     assert lib.bh_contact_components(None, None, None, None, 0.0, None, None, None, 0) == L.BH_E_INVALID
     assert lib.bh_batched_step(None, 1, None, None, None, None, 0.0, None, 0.5, 1e-3, 1, None) == L.BH_E_INVALID
+    r0 = C.c_double(0.0)
+    assert lib.bh_gravity_dt_bound(None, None, None, 0, C.byref(r0)) == L.BH_E_INVALID
     assert lib.bh_last_error(None) == b"NULL context"
     lib.bh_destroy(None)
     # the FMA probe checks its arguments before any device call
@@ -103,16 +105,6 @@ def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(L, "_lib", None)
     with pytest.raises(L.ExtensionMissing):
         L.load()
-
-
-def test_gravity_dt_bound():
-    """eq. dt_g: dt_g < T_g / 2 = 1 / (2 sqrt(G rho))."""
-    from paper_1912_04197_amd.api import gravity_dt_bound
-
-    assert gravity_dt_bound(1.0) == 0.5
-    assert abs(gravity_dt_bound(3000.0, G=6.674e-11) - 0.5 / (6.674e-11 * 3000.0) ** 0.5) < 1e-9
-    with pytest.raises(ValueError):
-        gravity_dt_bound(0.0)
 
 
 def test_functional_forms_need_a_gpu():

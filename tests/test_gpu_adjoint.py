@@ -127,6 +127,33 @@ def test_rollout_gradient_parity(api, theta):
     _close(Mt.grad.cpu().numpy(), gm, 1e-9, "gm")
 
 
+@pytest.mark.parametrize("theta", [0.5, -1.0])
+def test_rollout_gradient_parity_4096(api, theta):
+    """The differentiable-rollout case at the size the CPU oracle can still
+    follow: N = 4096 uniform ball (equal masses), eps 1e-3, 50 KDK steps of
+    dt = 1e-3, checkpoints every 20 steps, loss sum |x_T - x*|^2, FP64; every
+    component of the gradients with respect to x0, v0 and m against the
+    oracle's reverse sweep (tree: theta 0.5, leaf 16, decisions held fixed)."""
+    from paper_1912_04197_amd.autograd import rollout
+
+    n, T, dt, soft = 4096, 50, 1e-3, 1e-3
+    s = ics.uniform_ball(n, seed=55)
+    xt = ics.perturbed_target(s.pos, seed=56)
+    ctx = api.Context(n, leaf_size=16, precision="fp64", adjoint=True)
+    X0 = _dev(s.pos).requires_grad_(True)
+    V0 = _dev(s.vel).requires_grad_(True)
+    Mt = _dev(s.mass).requires_grad_(True)
+    x, _ = rollout(X0, V0, Mt, ctx, dt, T, theta=theta, softening=soft, checkpoint_every=20)
+    ((x - _dev(xt)) ** 2).sum().backward()
+    xf, vf, _ = oracle.leapfrog(s.pos, s.vel, s.mass, dt, T, softening=soft, theta=theta, leaf=16)
+    assert np.abs(x.detach().cpu().numpy() - xf).max() < 1e-12
+    gx, gv, gm = oracle.rollout_grad(s.pos, s.vel, s.mass, dt, T, 2 * (xf - xt), np.zeros_like(vf),
+                                     softening=soft, theta=theta, leaf=16)
+    _close(X0.grad.cpu().numpy(), gx, 1e-9, "gx0")
+    _close(V0.grad.cpu().numpy(), gv, 1e-9, "gv0")
+    _close(Mt.grad.cpu().numpy(), gm, 1e-9, "gm")
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 def test_rollout_65536_properties(api, precision):
     """The differentiable-rollout workload at full size: N = 65536 uniform

@@ -93,6 +93,30 @@ def test_batched_step_graph_replays(api):
         assert torch.equal(p0, p1) and torch.equal(v0, v1) and torch.equal(a0, a1), rep
 
 
+def test_batched_step_graph_follows_layout_changes(api):
+    """A graph captured for one scene layout is not replayed for another with
+    the same body count, scene count and arrays but different walk groups:
+    graph-captured steps equal eager ones bit for bit across layout changes."""
+    s = ics.uniform_ball(4000, seed=19)
+    rng = np.random.default_rng(19)
+    vel = 0.05 * rng.standard_normal(s.pos.shape)
+    layouts = [np.array([0, 1000, 4000]), np.array([0, 2000, 4000]), np.array([0, 1000, 4000])]
+    eager = api.Context(s.n, leaf_size=8, precision="fp64", max_scenes=2, walk_group=64)
+    graph = api.Context(s.n, leaf_size=8, precision="fp64", max_scenes=2, walk_group=64,
+                        graph=True)
+    st = []
+    for ctx in (eager, graph):
+        p, v, m = _dev(s.pos), _dev(vel), _dev(s.mass)
+        st.append((ctx, p, v, m, ctx.batched_accel(layouts[0], p, m, 0.5, softening=1e-3)))
+    for k, off in enumerate(layouts):
+        for ctx, p, v, m, a in st:
+            ctx.batched_accel(off, p, m, 0.5, softening=1e-3, out=a)
+            ctx.batched_step(off, p, v, m, a, 1e-3, 3, theta=0.5, softening=1e-3)
+        torch.cuda.synchronize()
+        (_, p0, v0, _, a0), (_, p1, v1, _, a1) = st
+        assert torch.equal(p0, p1) and torch.equal(v0, v1) and torch.equal(a0, a1), k
+
+
 def test_step_leapfrog_graph_replays(api):
     s = ics.plummer(30000, seed=10)
     eager = api.Context(s.n, precision="fp32c")
@@ -108,15 +132,19 @@ def test_step_leapfrog_graph_replays(api):
         assert torch.equal(st[0][1], st[1][1]) and torch.equal(st[0][2], st[1][2]), rep
 
 
-def test_batched_256_scene_workload(api):
+@pytest.mark.parametrize("leaf,group", [(16, 0), (4, 64)])
+def test_batched_256_scene_workload(api, leaf, group):
     """The batched workload at full size: 256 uniform balls, N log-uniform in
-    [1024, 65536] (about 4 million bodies), theta 0.5, leaf 16, FP32C; eight
+    [1024, 65536] (about 4 million bodies), theta 0.5, FP32C, at leaf 16 with
+    the default walk group and at the bucket and group sizes the autotuner
+    picks for this workload on an MI355X (leaf 4, 64-body groups); eight
     scenes are checked against the oracle on 256 sampled targets each."""
     scenes = ics.batched_scenes(256, seed=44)
     ns = np.array([s.n for s in scenes])
     off = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
     n = int(off[-1])
-    ctx = api.Context(n, leaf_size=16, precision="fp32c", counts=True, max_scenes=256)
+    ctx = api.Context(n, leaf_size=leaf, precision="fp32c", counts=True, max_scenes=256,
+                      walk_group=group)
     pos = _dev(np.vstack([s.pos for s in scenes]))
     mass = _dev(np.concatenate([s.mass for s in scenes]))
     acc = ctx.batched_accel(off, pos, mass, 0.5, softening=1e-3).cpu().numpy()
@@ -125,7 +153,8 @@ def test_batched_256_scene_workload(api):
     for k in rng.choice(256, 8, replace=False):
         s = scenes[k]
         t = np.sort(rng.choice(s.n, min(256, s.n), replace=False))
-        ref, _, aabs, rc = oracle.Tree(s.pos, s.mass, leaf=16).accel(0.5, softening=1e-3, targets=t)
+        ref, _, aabs, rc = oracle.Tree(s.pos, s.mass, leaf=leaf).accel(0.5, softening=1e-3,
+                                                                       targets=t)
         a = acc[off[k]:off[k + 1]][t]
         assert np.array_equal(cnt[off[k]:off[k + 1]][t], rc), k
         assert np.all(np.linalg.norm(a - ref, axis=1) <= FP32C_TOL * aabs), k
@@ -153,3 +182,6 @@ def test_autotune_picks_a_candidate_and_caches(api, tmp_path, monkeypatch):
     again = api.autotune(off, P, V, M, theta=0.5, dt=1e-3, softening=1e-3, steps=2)
     assert again == (leaf, group, ms)
     assert cache.read_text().count("\"leaf\"") == 1
+    # quadrupole nodes time other kernels: a separate entry, not the monopole one
+    api.autotune(off, P, V, M, theta=0.5, dt=1e-3, softening=1e-3, steps=2, quad=True)
+    assert cache.read_text().count("\"leaf\"") == 2

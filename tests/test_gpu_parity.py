@@ -306,6 +306,38 @@ def test_leapfrog_parity(api, theta):
     _check_acc(a.cpu().numpy(), ar, aabs, 1e-11, "leapfrog acc")
 
 
+@pytest.mark.parametrize("theta", [0.5, -1.0])
+def test_leapfrog_parity_fp32c(api, theta):
+    """The FP32C rollout against the FP64 oracle's: 2048-body uniform ball, 10 KDK
+    steps of dt = 1e-3. Each force evaluation may differ from FP64 by up to
+    64u A_i (the FP32C force bar); carried through k KDK steps this moves a
+    body by at most dt^2 k^2 / 2 and its velocity by dt k times that, and the
+    bar below allows four times it (the mean field's feedback over 10 steps of
+    a unit-density ball is a few per cent) with A_i the larger of its values at
+    the first and last states."""
+    s = ics.uniform_ball(2048, seed=11)
+    dt, k = 1e-3, 10
+    xr, vr, _ = oracle.leapfrog(s.pos, s.vel, s.mass, dt, k, softening=1e-3, theta=theta, leaf=8)
+    ctx = _ctx(api, s.n, leaf=8, precision="fp32c", counts=False)
+    p, v, m = _dev(s.pos), _dev(s.vel), _dev(s.mass)
+    if theta >= 0:
+        a = ctx.compute_accel(p, m, theta, softening=1e-3)
+    else:
+        a = ctx.compute_accel_direct(p, m, softening=1e-3)
+    ctx.step_leapfrog(p, v, m, a, dt, k, theta=theta, softening=1e-3)
+    a0 = oracle.direct(s.pos, s.mass, softening=1e-3)[2]
+    a1 = oracle.direct(xr, s.mass, softening=1e-3)[2]
+    amax = np.maximum(a0, a1)
+    dx = np.linalg.norm(p.cpu().numpy() - xr, axis=1)
+    dv = np.linalg.norm(v.cpu().numpy() - vr, axis=1)
+    bx = 4.0 * 0.5 * (dt * k) ** 2 * FP32C_TOL * amax
+    bv = 4.0 * dt * k * FP32C_TOL * amax
+    assert np.all(dx <= bx), (dx / bx).max()
+    assert np.all(dv <= bv), (dv / bv).max()
+    # and FP32C is really FP32 (not FP64 by accident): it differs from FP64
+    assert dx.max() > 0.0
+
+
 @pytest.mark.parametrize("every", [1, 3])
 @pytest.mark.parametrize("theta", [0.5, -1.0])
 def test_euler_parity(api, theta, every):
@@ -338,6 +370,74 @@ def test_diagnostics(api):
     assert np.abs(got[2:5] - ref[2:5]).max() < 1e-14 * scale
     lscale = float((s.mass * np.linalg.norm(np.cross(s.pos, s.vel), axis=1)).sum())
     assert np.abs(got[5:] - ref[5:]).max() < 1e-14 * lscale
+
+
+def test_diagnostics_compensated(api):
+    """Momenta whose total is tiny against their terms: 4096 bodies moving at
+    +-1e8 in opposite pairs plus O(1) residues. The compensated device sums give
+    the exactly rounded sum of the same per-body terms (math.fsum) to within a
+    few ulp of the result; a plain sum would be off by about u * sum |terms|,
+    some 1e-8 here."""
+    n = 4096
+    rng = np.random.default_rng(61)
+    pos = rng.standard_normal((n, 3))
+    vel = rng.standard_normal((n, 3))
+    vel[0::2] += 1e8
+    vel[1::2] -= 1e8
+    mass = np.full(n, 1.0 / n) * (1.0 + rng.random(n) * 1e-3)
+    ctx = _ctx(api, n, counts=False)
+    got = ctx.diagnostics(_dev(pos), _dev(vel), _dev(mass), softening=1e-2)
+    for k in range(3):
+        want = math.fsum((mass * vel[:, k]).tolist())
+        assert abs(got[2 + k] - want) <= 8 * 2.0 ** -53 * abs(want) + 1e-18, (k, got[2 + k], want)
+    lz = mass * (pos[:, 0] * vel[:, 1] - pos[:, 1] * vel[:, 0])
+    want = math.fsum(lz.tolist())
+    assert abs(got[7] - want) <= 8 * 2.0 ** -53 * abs(want) + 1e-18
+
+
+def test_gravity_dt_bound(api):
+    """eq. dt_g on the device against the oracle: the rubble-pile bodies (radius
+    = softening length), one body per quoted asteroid density in SI units, and
+    the edge cases (no massive body: +inf; a massive point: 0)."""
+    s = ics.rubble_pile(100003, seed=33)
+    ctx = _ctx(api, 16, counts=False)
+    got = ctx.gravity_dt_bound(_dev(s.mass), _dev(s.eps))
+    want = oracle.gravity_dt_bound(s.mass, s.eps)
+    assert abs(got - want) <= 2 * 2.0 ** -52 * want
+    si = _ctx(api, 16, counts=False, G=6.674e-11)
+    for rho, r in ((1000.0, 1500.0), (4000.0, 250.0)):
+        m = np.array([rho * (4.0 / 3.0) * math.pi * r ** 3, 0.0])
+        rad = np.array([r, 1.0])
+        got = si.gravity_dt_bound(_dev(m), _dev(rad))
+        want = oracle.gravity_dt_bound(m, rad, G=6.674e-11)
+        assert abs(got - want) <= 2 * 2.0 ** -52 * want
+        assert 500.0 < got < 5000.0
+    assert ctx.gravity_dt_bound(_dev(np.zeros(5)), _dev(np.ones(5))) == math.inf
+    assert ctx.gravity_dt_bound(_dev(np.array([1.0, 2.0])), _dev(np.array([1.0, 0.0]))) == 0.0
+    with pytest.raises(api.BHError, match="BH_E_NONFINITE"):
+        ctx.gravity_dt_bound(_dev(np.ones(3)), _dev(np.array([1.0, -1.0, 1.0])))
+    # the latch was cleared by the failed call
+    want = oracle.gravity_dt_bound(s.mass, s.eps)
+    assert abs(ctx.gravity_dt_bound(_dev(s.mass), _dev(s.eps)) - want) <= 2 * 2.0 ** -52 * want
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32c"])
+def test_coincident_below_double_range(api, precision):
+    """Two unsoftened bodies 1e-160 apart: r^2 is below the smallest normal
+    double and the pair contributes nothing (as r^2 = 0 does), in the direct
+    sum and the walk alike; 1e-100 apart (FP64 only: 1e-100 is below FP32's
+    range) they attract as G m / d^2 = 1e200, as the oracle computes."""
+    cases = [(1e-160, 0.0)] + ([(1e-100, 1e200)] if precision == "fp64" else [])
+    ctx = _ctx(api, 2, leaf=2, precision=precision, counts=False)
+    for d, want in cases:
+        x = np.array([[0.0, 0.0, 0.0], [d, 0.0, 0.0]])
+        m = np.array([1.0, 1.0])
+        ref = oracle.direct(x, m)[0]
+        assert ref[0, 0] == pytest.approx(want, rel=1e-15, abs=0.0)
+        for a in (ctx.compute_accel_direct(_dev(x), _dev(m)), ctx.compute_accel(_dev(x), _dev(m), 0.5)):
+            a = a.cpu().numpy()
+            assert np.all(np.isfinite(a)), (d, a)
+            assert np.allclose(a, ref, rtol=1e-15, atol=0.0), (d, a, ref)
 
 
 # ---------------------------------------------------------------- errors
