@@ -58,8 +58,6 @@ struct SceneBox {
 struct TreeHeader {
     int32_t level_count[kLevels + 1];  // nodes created per level (all scenes)
     uint32_t status;                   // ST_* bits
-    uint32_t box_ticket;               // blocks of the bounding-box launch that have finished
-    int32_t n_internal;                // internal nodes listed by the flat build
     int32_t pad;
 };
 
@@ -79,7 +77,6 @@ struct Layout {
     int n_groups = 0;
 };
 constexpr int kBoxChunk = 4096;  // bodies per bbox work item
-constexpr int kFlatTile = 1024;  // sorted bodies per block of the flat octree build
 constexpr int64_t kSmallBuild = 4096;  // a single scene this small is built by one block
 
 // Morton interleave of 21-bit cell coordinates (x in the highest bit of
@@ -177,15 +174,6 @@ struct Workspace {
     double *scratch = nullptr;    // [n_cap] potential for diagnostics
     double *red_part = nullptr;   // [reduction blocks][8][2] compensated partial sums
     double *dpart = nullptr;      // [kDirectPart] partial direct sums of split source ranges
-    // flat octree build (more than kSmallBuild bodies or several scenes)
-    uint8_t *blvl = nullptr;      // [n_cap] level at which each sorted body starts a cell
-    uint8_t *bleaf = nullptr;     // [n_cap] deepest level of the nodes it starts (255: none)
-    int32_t *tile_cnt = nullptr;  // [kLevels][flat tiles] node starts per tile, then prefixes
-    int32_t *leafnode = nullptr;  // [n_cap] leaf node a body starts, or -1
-    int32_t *nparent = nullptr;   // [node_cap] parent node (-1 for roots)
-    int32_t *narrive = nullptr;   // [node_cap] children whose moments are done
-    int32_t *ilist = nullptr;     // [node_cap] internal nodes of the last build
-    int flat_tiles_cap = 0;
     // Deepest non-empty level of the last build, written by the device into
     // pinned host memory (-1 before the first build): the next build launches
     // the levels down to one below it one by one and the rest in one block.
@@ -218,13 +206,11 @@ inline int64_t node_capacity(int64_t n, int leaf, int scenes = 1)
 }
 
 // Launchers (tree.hip). All enqueue on `s` and never synchronise.
-// The build's launch sequence does not depend on the tree it builds (no
-// per-level launches), so a captured graph replays any tree.
+// all_levels: launch every tree level instead of stopping one level below the
+// previous build's depth (the depth hint is a host read, frozen in a captured
+// graph; with all levels, a replay builds any tree depth at full width).
 hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, const double *pos,
-                        const double *mass, const double *eps, int leaf);
-// Puts every scene's bounding-box accumulators in their empty state (once at
-// context creation; each build leaves them so).
-hipError_t launch_box_reset(hipStream_t s, SceneBox *box, int n_scenes);
+                        const double *mass, const double *eps, int leaf, bool all_levels = false);
 // scene_of[i] = scene of body i, from device offsets of n_scenes scenes
 hipError_t launch_scene_of(hipStream_t s, const int64_t *offsets, int n_scenes,
                            uint16_t *scene_of);

@@ -88,8 +88,7 @@ void free_ws(Workspace &w)
 {
     void *ptrs[] = {w.keys[0], w.keys[1], w.idx[0],  w.idx[1],      w.sort_counts,
                     w.sort_totals, w.body, w.beps2, w.ninfo, w.nmom, w.neps2, w.box,
-                    w.hdr, w.counts, w.scratch, w.red_part, w.nquad, w.dpart,
-                    w.blvl, w.bleaf, w.tile_cnt, w.leafnode, w.nparent, w.narrive, w.ilist};
+                    w.hdr, w.counts, w.scratch, w.red_part, w.nquad, w.dpart};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (w.depth_host) (void)hipHostFree(w.depth_host);
@@ -183,7 +182,8 @@ bh_status force_tree(bh_ctx *c, const bhx::Layout &lay, const double *pos, const
     const int64_t n = lay.n;
     bh_status st = record(c, 0);
     if (st) return st;
-    BHX_HIP(c, bhx::launch_build(w, c->stream, lay, pos, mass, eps, c->cfg.leaf_size));
+    BHX_HIP(c, bhx::launch_build(w, c->stream, lay, pos, mass, eps, c->cfg.leaf_size,
+                                 c->capturing));
     st = record(c, 1);
     if (st) return st;
     c->tree_n = n;
@@ -439,14 +439,6 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
     A(dalloc(&w.nmom, node_cap));
     A(dalloc(&w.neps2, node_cap));
     A(dalloc(&w.box, max_scenes));
-    w.flat_tiles_cap = (int)((n + bhx::kFlatTile - 1) / bhx::kFlatTile);
-    A(dalloc(&w.blvl, n));
-    A(dalloc(&w.bleaf, n));
-    A(dalloc(&w.tile_cnt, (int64_t)bhx::kLevels * w.flat_tiles_cap));
-    A(dalloc(&w.leafnode, n));
-    A(dalloc(&w.nparent, node_cap));
-    A(dalloc(&w.narrive, node_cap));
-    A(dalloc(&w.ilist, node_cap));
     if (max_scenes > 1) {
         c->max_chunks = n / bhx::kBoxChunk + max_scenes;
         c->max_groups = n / 16 + max_scenes;
@@ -486,7 +478,6 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
             if (r == hipSuccess) r = hipEventCreate(&ev);
     }
     if (r == hipSuccess) r = hipMemset(w.hdr, 0, sizeof(bhx::TreeHeader));
-    if (r == hipSuccess) r = bhx::launch_box_reset(c->stream, w.box, max_scenes);
     if (r == hipSuccess) r = hipDeviceSynchronize();
     if (r != hipSuccess) {
         bh_status st = (r == hipErrorOutOfMemory) ? BH_E_OOM : BH_E_HIP;

@@ -3,25 +3,18 @@
 // subsection "CUDA implementation of GPU-parallel Barnes-Hut" are prior art,
 // this is a Morton-key design for CDNA4):
 //   1. bounding box of each scene's bodies -> its root cube (and input
-//      validation), one launch: the last block to finish finalises every
-//      scene; a call may hold many independent scenes, stored as contiguous
-//      body ranges, each with its own root,
+//      validation); a call may hold many independent scenes, stored as
+//      contiguous body ranges, each with its own root,
 //   2. 63-bit Morton keys on a 2^21 grid,
 //   3. stable LSD radix sort of (key, index), 8-bit digits, LDS ranking, then
 //      (several scenes) two stable passes on the scene index,
 //   4. gather of positions, masses and softening into Morton order,
-//   5. the octree from the sorted keys without a launch per level: a body
-//      that opens a cell at level l (its key first differs from its
-//      predecessor's there) owns the nodes of that cell down to the level
-//      where the cell starting at it holds at most `leaf` bodies; per-level
-//      prefix sums over the bodies number the nodes level by level in key
-//      order (so siblings are contiguous, in octant order),
-//   6. moments bottom-up in one launch: each leaf from its bodies, then the
-//      last child to finish computes its parent from the children by
-//      eq. (COMinternal), up to the root.
+//   5. top-down octree, one launch per level: each split cell finds its
+//      octant ranges by binary search in the sorted keys,
+//   6. bottom-up moments, one launch per level: mass and centre of mass from
+//      the children by eq. (COMinternal), leaves from their bodies.
 // Every launch reads its sizes from the device tree header, so the sequence
-// needs no host round trip and can be captured in a graph. A single scene of
-// at most kSmallBuild bodies is built by one block instead.
+// needs no host round trip and can be captured in a graph.
 #include <cmath>
 
 #include "bhx_impl.h"
@@ -79,65 +72,27 @@ __device__ inline double order_dec(unsigned long long e)
     return __longlong_as_double((long long)b);
 }
 
-// The empty state of a scene's box accumulators (every build leaves them so).
-__device__ inline void box_clear(SceneBox &b)
-{
-    for (int a = 0; a < 3; a++) {
-        b.lo_enc[a] = ~0ull;
-        b.hi_enc[a] = 0ull;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_box_reset(SceneBox *__restrict__ box, int n_scenes)
+__global__ __launch_bounds__(256) void k_box_init(SceneBox *__restrict__ box, int n_scenes)
 {
     const int sc = blockIdx.x * 256 + threadIdx.x;
-    if (sc < n_scenes) box_clear(box[sc]);
-}
-
-// Root cube: side = largest extent (1 if all bodies coincide), centred on the
-// bounding box; the quantisation scale and the squared cell side per level.
-__device__ inline void root_cube(SceneBox &b, const double lo[3], const double hi[3])
-{
-#pragma clang fp contract(off)
-    double L = 0.0;
+    if (sc >= n_scenes) return;
     for (int a = 0; a < 3; a++) {
-        double e = hi[a] - lo[a];
-        if (e > L) L = e;
-    }
-    if (L == 0.0) L = 1.0;
-    for (int a = 0; a < 3; a++) {
-        b.lo[a] = lo[a];
-        b.hi[a] = hi[a];
-        b.x0[a] = (lo[a] + hi[a]) * 0.5 - L * 0.5;
-    }
-    b.L = L;
-    b.S = 2097152.0 / L;
-    for (int l = 0; l < kLevels; l++) {
-        double sd = ldexp(L, -l);
-        b.s2[l] = sd * sd;
+        box[sc].lo_enc[a] = ~0ull;
+        box[sc].hi_enc[a] = 0ull;
     }
 }
-
-
-constexpr int kBoxThreads = 1024;  // one block per chunk: 4 bodies per thread
 
 // One work item: a chunk of at most kBoxChunk bodies of one scene (for one
 // scene, chunk c is bodies c*kBoxChunk onwards). Reduces its box in the block
-// and merges it into the scene's with integer atomics; flags bad input. The
-// last block to finish (a ticket taken after a device-wide fence) turns every
-// scene's box into its root cube and root node, resets the per-level node
-// counts and leaves the accumulators and the ticket empty for the next build.
-__global__ __launch_bounds__(kBoxThreads) void k_box(const double *__restrict__ pos,
-                                                     const double *__restrict__ mass,
-                                                     const double *__restrict__ eps, int64_t n,
-                                                     const int32_t *__restrict__ chunks,
-                                                     int nchunks, int n_scenes,
-                                                     const int64_t *__restrict__ offsets,
-                                                     SceneBox *__restrict__ box,
-                                                     TreeHeader *__restrict__ hdr,
-                                                     NodeInfo *__restrict__ ninfo)
+// and merges it into the scene's with integer atomics; flags bad input.
+constexpr int kBoxThreads = 1024;  // one block per chunk: 4 bodies per thread
+__global__ __launch_bounds__(kBoxThreads) void k_box_chunk(const double *__restrict__ pos,
+                                                   const double *__restrict__ mass,
+                                                   const double *__restrict__ eps, int64_t n,
+                                                   const int32_t *__restrict__ chunks,
+                                                   SceneBox *__restrict__ box,
+                                                   TreeHeader *__restrict__ hdr)
 {
-#pragma clang fp contract(off)
     int sc = 0;
     int64_t first = (int64_t)blockIdx.x * kBoxChunk, end = first + kBoxChunk;
     if (chunks) {
@@ -164,7 +119,6 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(const double *__restrict__ 
     }
     if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&hdr->status, ST_NONFINITE);
     __shared__ double red[kBoxThreads / 64][6];
-    __shared__ bool last;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int a = 0; a < 3; a++) {
         double l = wave_min(lo[a]), h = wave_max(hi[a]);
@@ -174,7 +128,7 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(const double *__restrict__ 
         }
     }
     __syncthreads();
-    if (threadIdx.x < 6 && end > first) {
+    if (threadIdx.x < 6) {
         const int a = threadIdx.x;
         double v = red[0][a];
         for (int w = 1; w < kBoxThreads / 64; w++)
@@ -184,32 +138,57 @@ __global__ __launch_bounds__(kBoxThreads) void k_box(const double *__restrict__ 
         else
             atomicMax(&box[sc].hi_enc[a - 3], order_enc(v));
     }
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(&hdr->box_ticket, 1u) == (unsigned)(nchunks - 1);
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    if (threadIdx.x == 0) {
+}
+
+// Root cube: side = largest extent (1 if all bodies coincide), centred on the
+// bounding box; the quantisation scale and the squared cell side per level.
+__device__ inline void root_cube(SceneBox &b, const double lo[3], const double hi[3])
+{
+#pragma clang fp contract(off)
+    double L = 0.0;
+    for (int a = 0; a < 3; a++) {
+        double e = hi[a] - lo[a];
+        if (e > L) L = e;
+    }
+    if (L == 0.0) L = 1.0;
+    for (int a = 0; a < 3; a++) {
+        b.lo[a] = lo[a];
+        b.hi[a] = hi[a];
+        b.x0[a] = (lo[a] + hi[a]) * 0.5 - L * 0.5;
+    }
+    b.L = L;
+    b.S = 2097152.0 / L;
+    for (int l = 0; l < kLevels; l++) {
+        double sd = ldexp(L, -l);
+        b.s2[l] = sd * sd;
+    }
+}
+
+// One thread per scene: root cube from the box, and the scene's root node
+// (level 0, its bodies' whole range in sorted order). Thread 0 also resets
+// the per-level node counts.
+__global__ __launch_bounds__(256) void k_box_final(SceneBox *__restrict__ box, int n_scenes,
+                                                   const int64_t *__restrict__ offsets, int64_t n,
+                                                   TreeHeader *__restrict__ hdr,
+                                                   NodeInfo *__restrict__ ninfo)
+{
+#pragma clang fp contract(off)
+    const int sc = blockIdx.x * 256 + threadIdx.x;
+    if (sc == 0) {
         for (int l = 0; l <= kLevels; l++) hdr->level_count[l] = 0;
         hdr->level_count[0] = n > 0 ? n_scenes : 0;
-        hdr->box_ticket = 0u;
     }
-    for (int s = threadIdx.x; s < n_scenes; s += kBoxThreads) {
-        const int64_t f = offsets ? offsets[s] : 0, e = offsets ? offsets[s + 1] : n;
-        SceneBox &b = box[s];
-        double blo[3], bhi[3];
-        for (int a = 0; a < 3; a++) {
-            // atomic reads: the other blocks' updates were made by atomics
-            const unsigned long long le = atomicOr(&b.lo_enc[a], 0ull);
-            const unsigned long long he = atomicOr(&b.hi_enc[a], 0ull);
-            blo[a] = e > f ? order_dec(le) : 0.0;
-            bhi[a] = e > f ? order_dec(he) : 0.0;
-        }
-        root_cube(b, blo, bhi);
-        box_clear(b);
-        if (e > f) ninfo[s] = NodeInfo{(int32_t)f, (int32_t)(e - f), -1, (int32_t)(s << 16)};
+    if (sc >= n_scenes) return;
+    const int64_t first = offsets ? offsets[sc] : 0, end = offsets ? offsets[sc + 1] : n;
+    SceneBox &b = box[sc];
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; a++) {
+        lo[a] = end > first ? order_dec(b.lo_enc[a]) : 0.0;
+        hi[a] = end > first ? order_dec(b.hi_enc[a]) : 0.0;
     }
+    root_cube(b, lo, hi);
+    if (end > first)
+        ninfo[sc] = NodeInfo{(int32_t)first, (int32_t)(end - first), -1, (int32_t)(sc << 16)};
 }
 
 // --------------------------------------------------------------- 2. keys
@@ -536,6 +515,16 @@ __device__ inline void build_nodes(int level, const uint64_t *__restrict__ keys,
     }
 }
 
+__global__ __launch_bounds__(1024) void k_build_level(int level, const uint64_t *__restrict__ keys,
+                                                      TreeHeader *__restrict__ hdr,
+                                                      NodeInfo *__restrict__ ninfo,
+                                                      int64_t node_cap, int leaf)
+{
+    const int64_t per_block = blockDim.x >> 3;  // nodes per block and step
+    build_nodes(level, keys, hdr->level_count, &hdr->status, ninfo, node_cap, leaf,
+                (int64_t)blockIdx.x * per_block + (threadIdx.x >> 3),
+                (int64_t)gridDim.x * per_block);
+}
 
 // Levels from..upto-1 in one block, on a copy of the node counts in LDS
 // (no other kernel runs meanwhile); stops at the first empty level.
@@ -552,91 +541,25 @@ __device__ inline void build_levels_block(int from, int upto, const uint64_t *__
     }
 }
 
-// ------------------------------------------------------------ 6. moments
-
-// Mass, centre of mass and mass-weighted softening of node k at `level`, by
-// eq. (COMinternal): from the children of an internal node, from the bodies
-// of a leaf. Products and sums are rounded as written.
-__device__ inline void node_moments(int32_t k, int level, const NodeInfo *__restrict__ ninfo,
-                                    const Body *__restrict__ body,
-                                    const double *__restrict__ beps2,
-                                    const uint64_t *__restrict__ keys,
-                                    const SceneBox *__restrict__ box, NodeMom *__restrict__ nmom,
-                                    double *__restrict__ neps2, double *__restrict__ nquad,
-                                    int use_eps)
+// Levels from..kMaxLevel-1 in one block (deep levels hold few nodes).
+__global__ __launch_bounds__(1024) void k_build_tail(int from, const uint64_t *__restrict__ keys,
+                                                     TreeHeader *__restrict__ hdr,
+                                                     NodeInfo *__restrict__ ninfo,
+                                                     int64_t node_cap, int leaf)
 {
-#pragma clang fp contract(off)
-    const NodeInfo info = ninfo[k];
-    double ms = 0.0, mx = 0.0, my = 0.0, mz = 0.0, me = 0.0;
-    if (info.child0 < 0) {
-        for (int32_t s = info.first; s < info.first + info.count; s++) {
-            const Body b = body[s];
-            ms += b.m;
-            mx += b.x * b.m;
-            my += b.y * b.m;
-            mz += b.z * b.m;
-            if (use_eps) me += beps2[s] * b.m;
-        }
-    } else {
-        const int nch = node_nchild(info);
-        for (int32_t c = info.child0; c < info.child0 + nch; c++) {
-            const NodeMom cm = nmom[c];
-            ms += cm.m;
-            mx += cm.x * cm.m;
-            my += cm.y * cm.m;
-            mz += cm.z * cm.m;
-            if (use_eps) me += neps2[c] * cm.m;
-        }
-    }
-    NodeMom out;
-    double e2 = 0.0;
-    if (ms > 0.0) {
-        out = NodeMom{mx / ms, my / ms, mz / ms, ms};
-        e2 = use_eps ? me / ms : 0.0;
-    } else {
-        // massless cell: its centre
-        const uint64_t key = keys[info.first];
-        const SceneBox &b = box[node_scene(info)];
-        const int sh = kMaxLevel - level;
-        const double s = ldexp(b.L, -level);
-        out.x = b.x0[0] + ((double)(compact3(key >> 2) >> sh) + 0.5) * s;
-        out.y = b.x0[1] + ((double)(compact3(key >> 1) >> sh) + 0.5) * s;
-        out.z = b.x0[2] + ((double)(compact3(key) >> sh) + 0.5) * s;
-        out.m = 0.0;
-    }
-    nmom[k] = out;
-    if (use_eps) neps2[k] = e2;
-    if (nquad) {
-        // traceless quadrupole about the centre of mass: from the bodies
-        // of a leaf, from the children by the parallel-axis shift
-        double q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        auto add = [&](double dx, double dy, double dz, double m) {
-            const double d2 = dx * dx + dy * dy + dz * dz;
-            q[0] += m * (3.0 * dx * dx - d2);
-            q[1] += m * (3.0 * dy * dy - d2);
-            q[2] += m * (3.0 * dz * dz - d2);
-            q[3] += m * 3.0 * dx * dy;
-            q[4] += m * 3.0 * dx * dz;
-            q[5] += m * 3.0 * dy * dz;
-        };
-        if (info.child0 < 0) {
-            for (int32_t s = info.first; s < info.first + info.count; s++) {
-                const Body b = body[s];
-                add(b.x - out.x, b.y - out.y, b.z - out.z, b.m);
-            }
-        } else {
-            const int nch = node_nchild(info);
-            for (int32_t c = info.child0; c < info.child0 + nch; c++) {
-                const NodeMom cm = nmom[c];
-                for (int a = 0; a < 6; a++) q[a] += nquad[6 * (int64_t)c + a];
-                add(cm.x - out.x, cm.y - out.y, cm.z - out.z, cm.m);
-            }
-        }
-        for (int a = 0; a < 6; a++) nquad[6 * (int64_t)k + a] = q[a];
-    }
+    __shared__ int32_t scnt[kLevels + 1];
+    if (threadIdx.x <= kLevels) scnt[threadIdx.x] = hdr->level_count[threadIdx.x];
+    __syncthreads();
+    build_levels_block(from, kMaxLevel, keys, hdr, ninfo, node_cap, leaf, scnt);
+    __syncthreads();
+    if (threadIdx.x <= kLevels) hdr->level_count[threadIdx.x] = scnt[threadIdx.x];
 }
 
-// The moments of every node of `level` (stride loop over the level's nodes).
+// ------------------------------------------------------------ 6. moments
+
+// Mass, centre of mass and mass-weighted softening of every node of `level`,
+// by eq. (COMinternal): from the children of an internal node, from the
+// bodies of a leaf. Products and sums are rounded as written.
 __device__ inline void moments_nodes(int level, const int32_t *counts,
                                      const NodeInfo *__restrict__ ninfo,
                                      const Body *__restrict__ body,
@@ -647,370 +570,145 @@ __device__ inline void moments_nodes(int level, const int32_t *counts,
                                      int64_t node_cap, int use_eps, int64_t g_first,
                                      int64_t stride)
 {
+#pragma clang fp contract(off)
     int32_t beg, cnt;
     level_range(counts, level, node_cap, &beg, &cnt);
-    for (int64_t g = g_first; g < cnt; g += stride)
-        node_moments(beg + (int32_t)g, level, ninfo, body, beps2, keys, box, nmom, neps2, nquad,
-                     use_eps);
-}
-
-// ------------------------------------------- 5. octree from the sorted keys
-
-constexpr int kHalo = 64;     // bucket sizes are at most 64
-constexpr int kNoNode = 255;  // bleaf of a body that starts no node
-
-// Scene of sorted body j: scenes stay contiguous and in order through the
-// sort, so a binary search of the scene offsets (staged in LDS for at most
-// kLdsScenes scenes) finds it.
-__device__ inline int sorted_scene(int64_t j, const int64_t *soff, int ns,
-                                   const int64_t *__restrict__ offsets)
-{
-    if (ns == 1) return 0;
-    const int64_t *o = ns <= kLdsScenes ? soff : offsets;
-    int lo = 0, hi = ns;  // o[lo] <= j < o[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (o[mid] <= j)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
-__device__ inline int64_t scene_bound(int k, const int64_t *soff, int ns,
-                                      const int64_t *__restrict__ offsets, int64_t n)
-{
-    if (ns == 1) return k == 0 ? 0 : n;
-    return ns <= kLdsScenes ? soff[k] : offsets[k];
-}
-
-// The shallowest level at which sorted body j starts a new cell: 0 for the
-// first body of a scene, else the first level whose cell differs from body
-// j-1's (the highest differing key bit picks it), or 22 when its key equals
-// body j-1's (it starts no cell). Positions outside 0..n-1 bound every cell
-// (0), and so does a scene's first body.
-__device__ inline int start_level(const uint64_t *__restrict__ keys, int64_t j, int64_t n,
-                                  const int64_t *soff, int ns, const int64_t *__restrict__ offsets)
-{
-    if (j <= 0 || j >= n) return 0;
-    if (ns > 1 && scene_bound(sorted_scene(j, soff, ns, offsets), soff, ns, offsets, n) == j)
-        return 0;
-    const uint64_t x = keys[j] ^ keys[j - 1];
-    if (x == 0) return kMaxLevel + 1;
-    return (__builtin_clzll(x) - 1) / 3 + 1;  // keys use bits 0..62
-}
-
-__device__ inline void stage_offsets_all(int64_t *soff, const int64_t *__restrict__ offsets,
-                                         int ns)
-{
-    if (ns > 1 && ns <= kLdsScenes)
-        for (int k = threadIdx.x; k <= ns; k += blockDim.x) soff[k] = offsets[k];
-}
-
-// Per sorted body i: its start level l, and whether it starts nodes at all.
-// A body with l >= 1 lies with its predecessor in a cell of level l - 1;
-// that cell is a node split further (so the body starts the nodes of its own
-// cells from level l down) when it holds more than `leaf` bodies, which the
-// nearest bodies at or above its level before and after i decide within
-// `leaf` places. A body that starts nodes owns the cells beginning at it from
-// level l down to its leaf: the first level at which some body among the next
-// `leaf` opens a cell of that level or above, i.e. the cell starting at i
-// holds at most `leaf` bodies (level 21 cells are leaves whatever their
-// count). Also counts each level's node starts per tile.
-__global__ __launch_bounds__(kFlatTile) void k_flat_start(
-    const uint64_t *__restrict__ keys, int64_t n, const int64_t *__restrict__ offsets, int ns,
-    int leaf, uint8_t *__restrict__ blvl, uint8_t *__restrict__ bleaf,
-    int32_t *__restrict__ tile_cnt, int ntiles)
-{
-    __shared__ uint8_t lv[kFlatTile + 2 * kHalo + 1];  // bodies t0 - kHalo .. t0 + kFlatTile + kHalo
-    __shared__ int64_t soff[kLdsScenes + 1];
-    __shared__ int32_t wcnt[kLevels][kFlatTile / 64];
-    const int64_t t0 = (int64_t)blockIdx.x * kFlatTile;
-    stage_offsets_all(soff, offsets, ns);
-    __syncthreads();
-    for (int k = threadIdx.x; k < kFlatTile + 2 * kHalo + 1; k += kFlatTile)
-        lv[k] = (uint8_t)start_level(keys, t0 - kHalo + k, n, soff, ns, offsets);
-    __syncthreads();
-    const int64_t i = t0 + threadIdx.x;
-    const int c = kHalo + (int)threadIdx.x;
-    const int l = lv[c];
-    int L = kNoNode;
-    if (i < n) {
-        bool starts = l == 0;
-        if (l >= 1 && l <= kMaxLevel) {
-            const int t = l - 1;
-            int db = leaf + 1, df = leaf + 1;
-            for (int p = 1; p <= leaf; p++)
-                if (lv[c - p] <= t) {
-                    db = p;
-                    break;
-                }
-            for (int q = 1; q <= leaf; q++)
-                if (lv[c + q] <= t) {
-                    df = q;
-                    break;
-                }
-            starts = db + df > leaf;
-        }
-        if (starts) {
-            int m = kMaxLevel;
-            for (int q = 1; q <= leaf; q++) m = min(m, (int)lv[c + q]);
-            L = max(l, m);
-        }
-        blvl[i] = (uint8_t)l;
-        bleaf[i] = (uint8_t)L;
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int lev = 0; lev < kLevels; lev++) {
-        const uint64_t b = __ballot(L != kNoNode && l <= lev && lev <= L);
-        if (lane == 0) wcnt[lev][wave] = __popcll(b);
-    }
-    __syncthreads();
-    if (threadIdx.x < kLevels) {
-        int32_t tot = 0;
-        for (int w = 0; w < kFlatTile / 64; w++) tot += wcnt[threadIdx.x][w];
-        tile_cnt[(int64_t)threadIdx.x * ntiles + blockIdx.x] = tot;
-    }
-}
-
-// One block per level: exclusive prefix sums of the level's node starts over
-// the tiles (in place), and the level's node count in the tree header.
-__global__ __launch_bounds__(1024) void k_flat_scan(int32_t *__restrict__ tile_cnt, int ntiles,
-                                                    TreeHeader *__restrict__ hdr)
-{
-    __shared__ int32_t wsum[16];
-    const int lev = blockIdx.x;
-    int32_t *row = tile_cnt + (int64_t)lev * ntiles;
-    int32_t carry = 0;
-    for (int b0 = 0; b0 < ntiles; b0 += 1024) {
-        const int b = b0 + (int)threadIdx.x;
-        const int32_t v = b < ntiles ? row[b] : 0;
-        const int32_t x = (int32_t)wave_incl_scan((uint32_t)v);
-        if ((threadIdx.x & 63) == 63) wsum[threadIdx.x >> 6] = x;
-        __syncthreads();
-        int32_t add = 0, tot = 0;
-        for (int w = 0; w < 16; w++) {
-            const int32_t t = wsum[w];
-            if (w < (int)(threadIdx.x >> 6)) add += t;
-            tot += t;
-        }
-        __syncthreads();
-        if (b < ntiles) row[b] = carry + add + x - v;
-        carry += tot;
-    }
-    if (threadIdx.x == 0) {
-        hdr->level_count[lev] = carry;
-        if (lev == 0) {
-            hdr->level_count[kLevels] = 0;
-            hdr->n_internal = 0;
-        }
-    }
-}
-
-// First j in [lo, hi) whose level-lev prefix differs from body i's (hi if
-// none); the bodies of body i's cell are contiguous from i on.
-__device__ inline int64_t cell_end(const uint64_t *__restrict__ keys, int64_t i, int64_t lo,
-                                   int64_t hi, int lev)
-{
-    const int shift = 63 - 3 * lev;
-    const uint64_t pref = keys[i] >> shift;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if ((keys[mid] >> shift) == pref)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
-// Writes the nodes every body starts. Node numbering is level by level, and
-// within a level in body order (the rank of the starting body among the
-// level's starts: the tile's prefix plus the ranks inside the tile), so the
-// nodes of a level are in key order and every node's children are
-// contiguous, in octant order. A node's first child is the node its own
-// first body starts one level down. Counts: a root holds its scene; a leaf
-// ends at the next body that opens a cell of its level or above (within
-// `leaf` places, except for crowded level-21 cells); an internal node's end
-// is found by a binary search of the keys. Internal nodes are listed for
-// the linking pass, and each body records the leaf it starts.
-__global__ __launch_bounds__(kFlatTile) void k_flat_nodes(
-    const uint64_t *__restrict__ keys, int64_t n, const int64_t *__restrict__ offsets, int ns,
-    int leaf, const uint8_t *__restrict__ blvl, const uint8_t *__restrict__ bleaf,
-    const int32_t *__restrict__ tile_pre, int ntiles, TreeHeader *__restrict__ hdr,
-    NodeInfo *__restrict__ ninfo, int32_t *__restrict__ leafnode, int32_t *__restrict__ nparent,
-    int32_t *__restrict__ narrive, int32_t *__restrict__ ilist, int64_t node_cap)
-{
-    __shared__ int64_t soff[kLdsScenes + 1];
-    __shared__ uint8_t lv[kFlatTile + kHalo + 1];  // bodies t0 .. t0 + kFlatTile + kHalo
-    __shared__ int32_t base[kLevels];
-    __shared__ int32_t woff[kLevels][kFlatTile / 64];
-    __shared__ int32_t wint[kFlatTile / 64];
-    __shared__ int32_t int_base;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t t0 = (int64_t)blockIdx.x * kFlatTile;
-    const int64_t i = t0 + threadIdx.x;
-    stage_offsets_all(soff, offsets, ns);
-    for (int k = threadIdx.x; k < kFlatTile + kHalo + 1; k += kFlatTile) {
-        const int64_t j = t0 + k;
-        lv[k] = j < n ? blvl[j] : (uint8_t)0;
-    }
-    if (threadIdx.x == 0) {
-        int64_t b = 0;
-        for (int lev = 0; lev < kLevels; lev++) {
-            base[lev] = (int32_t)(b < node_cap ? b : node_cap);
-            b += hdr->level_count[lev];
-        }
-        if (b > node_cap && blockIdx.x == 0) atomicOr(&hdr->status, ST_CAPACITY);
-    }
-    const int l = i < n ? (int)blvl[i] : 0;
-    const int L = i < n ? (int)bleaf[i] : kNoNode;
-    for (int lev = 0; lev < kLevels; lev++) {
-        const uint64_t b = __ballot(L != kNoNode && l <= lev && lev <= L);
-        if (lane == 0) woff[lev][wave] = __popcll(b);
-    }
-    // internal nodes of this body (levels l .. L-1): places in the list, one
-    // reservation per block
-    const uint32_t nint = L != kNoNode ? (uint32_t)(L - l) : 0u;
-    const uint32_t iincl = wave_incl_scan(nint);
-    if (lane == 63) wint[wave] = (int32_t)iincl;
-    __syncthreads();
-    if (threadIdx.x < kLevels) {
-        int32_t run = 0;
-        for (int w = 0; w < kFlatTile / 64; w++) {
-            const int32_t c = woff[threadIdx.x][w];
-            woff[threadIdx.x][w] = run;
-            run += c;
-        }
-    }
-    if (threadIdx.x == 0) {
-        int32_t tot = 0;
-        for (int w = 0; w < kFlatTile / 64; w++) tot += wint[w];
-        int_base = tot > 0 ? atomicAdd(&hdr->n_internal, tot) : 0;
-    }
-    __syncthreads();
-    int32_t ipos = int_base + (int32_t)(iincl - nint);
-    for (int w = 0; w < wave; w++) ipos += wint[w];
-
-    int sc = 0;
-    int64_t sc_end = n;
-    if (L != kNoNode && ns > 1) {
-        sc = sorted_scene(i, soff, ns, offsets);
-        sc_end = scene_bound(sc + 1, soff, ns, offsets, n);
-    }
-    const int c = (int)threadIdx.x;
-    int32_t child = -1;  // the node this body starts one level down
-    for (int lev = kMaxLevel; lev >= 0; lev--) {
-        const bool s = L != kNoNode && l <= lev && lev <= L;
-        const uint64_t bal = __ballot(s);
-        if (!s) continue;
-        const int32_t id = base[lev] + tile_pre[(int64_t)lev * ntiles + blockIdx.x] +
-                           woff[lev][wave] + (int32_t)__popcll(bal & lanemask_lt(lane));
-        int64_t cnt;
-        if (lev == 0) {
-            cnt = sc_end - i;
-        } else {
-            int64_t e = -1;
-            if (lev == L)
-                for (int q = 1; q <= leaf; q++)
-                    if (lv[c + q] <= lev) {
-                        e = i + q;
-                        break;
-                    }
-            if (e < 0) {
-                const int64_t lo = i + leaf + 1 < sc_end ? i + leaf + 1 : sc_end;
-                e = cell_end(keys, i, lo, sc_end, lev);
+    for (int64_t g = g_first; g < cnt; g += stride) {
+        const int32_t k = beg + (int32_t)g;
+        const NodeInfo info = ninfo[k];
+        double ms = 0.0, mx = 0.0, my = 0.0, mz = 0.0, me = 0.0;
+        if (info.child0 < 0) {
+            for (int32_t s = info.first; s < info.first + info.count; s++) {
+                const Body b = body[s];
+                ms += b.m;
+                mx += b.x * b.m;
+                my += b.y * b.m;
+                mz += b.z * b.m;
+                if (use_eps) me += beps2[s] * b.m;
             }
-            cnt = e - i;
+        } else {
+            const int nch = node_nchild(info);
+            for (int32_t c = info.child0; c < info.child0 + nch; c++) {
+                const NodeMom cm = nmom[c];
+                ms += cm.m;
+                mx += cm.x * cm.m;
+                my += cm.y * cm.m;
+                mz += cm.z * cm.m;
+                if (use_eps) me += neps2[c] * cm.m;
+            }
         }
-        if (id < node_cap) {
-            ninfo[id] = NodeInfo{(int32_t)i, (int32_t)cnt, lev < L ? child : -1, lev | (sc << 16)};
-            narrive[id] = 0;
-            if (lev == 0) nparent[id] = -1;
-            if (lev < L && child >= 0 && child < node_cap) nparent[child] = id;
-            if (lev < L) ilist[ipos++] = id;
+        NodeMom out;
+        double e2 = 0.0;
+        if (ms > 0.0) {
+            out = NodeMom{mx / ms, my / ms, mz / ms, ms};
+            e2 = use_eps ? me / ms : 0.0;
+        } else {
+            // massless cell: its centre
+            const uint64_t key = keys[info.first];
+            const SceneBox &b = box[node_scene(info)];
+            const int sh = kMaxLevel - level;
+            const double s = ldexp(b.L, -level);
+            out.x = b.x0[0] + ((double)(compact3(key >> 2) >> sh) + 0.5) * s;
+            out.y = b.x0[1] + ((double)(compact3(key >> 1) >> sh) + 0.5) * s;
+            out.z = b.x0[2] + ((double)(compact3(key) >> sh) + 0.5) * s;
+            out.m = 0.0;
         }
-        if (lev == L) leafnode[i] = id < node_cap ? id : -1;
-        child = id;
+        nmom[k] = out;
+        if (use_eps) neps2[k] = e2;
+        if (nquad) {
+            // traceless quadrupole about the centre of mass: from the bodies
+            // of a leaf, from the children by the parallel-axis shift
+            double q[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            auto add = [&](double dx, double dy, double dz, double m) {
+                const double d2 = dx * dx + dy * dy + dz * dz;
+                q[0] += m * (3.0 * dx * dx - d2);
+                q[1] += m * (3.0 * dy * dy - d2);
+                q[2] += m * (3.0 * dz * dz - d2);
+                q[3] += m * 3.0 * dx * dy;
+                q[4] += m * 3.0 * dx * dz;
+                q[5] += m * 3.0 * dy * dz;
+            };
+            if (info.child0 < 0) {
+                for (int32_t s = info.first; s < info.first + info.count; s++) {
+                    const Body b = body[s];
+                    add(b.x - out.x, b.y - out.y, b.z - out.z, b.m);
+                }
+            } else {
+                const int nch = node_nchild(info);
+                for (int32_t c = info.child0; c < info.child0 + nch; c++) {
+                    const NodeMom cm = nmom[c];
+                    for (int a = 0; a < 6; a++) q[a] += nquad[6 * (int64_t)c + a];
+                    add(cm.x - out.x, cm.y - out.y, cm.z - out.z, cm.m);
+                }
+            }
+            for (int a = 0; a < 6; a++) nquad[6 * (int64_t)k + a] = q[a];
+        }
     }
-    if (i < n && L == kNoNode) leafnode[i] = -1;
 }
 
-// Links every internal node to its children (the next level's nodes from
-// its first child on that begin inside its body range, at most eight) and
-// stores their number; reports the deepest non-empty level as a launch hint.
-__global__ __launch_bounds__(256) void k_flat_link(const TreeHeader *__restrict__ hdr,
-                                                   const int32_t *__restrict__ ilist,
-                                                   NodeInfo *__restrict__ ninfo,
-                                                   int32_t *__restrict__ nparent,
-                                                   int64_t node_cap,
-                                                   int32_t *__restrict__ depth_out)
-{
-    __shared__ int64_t lend[kLevels + 1];  // end of each level in the node table
-    if (threadIdx.x == 0) {
-        int64_t b = 0;
-        for (int lev = 0; lev < kLevels; lev++) {
-            b += hdr->level_count[lev];
-            lend[lev] = b < node_cap ? b : node_cap;
-        }
-        lend[kLevels] = lend[kLevels - 1];
-        if (blockIdx.x == 0 && depth_out) {
-            int d = 0;
-            for (int lev = 1; lev < kLevels; lev++)
-                if (hdr->level_count[lev] > 0) d = lev;
-            *depth_out = d;
-        }
-    }
-    __syncthreads();
-    const int64_t ni = hdr->n_internal < node_cap ? hdr->n_internal : node_cap;
-    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < ni;
-         g += (int64_t)gridDim.x * 256) {
-        const int32_t p = ilist[g];
-        if (p < 0 || p >= node_cap) continue;
-        const NodeInfo info = ninfo[p];
-        const int lev = node_level(info);
-        const int64_t end = (int64_t)info.first + info.count;
-        int nch = 0;
-        for (int k = 0; k < 8; k++) {
-            const int64_t ch = (int64_t)info.child0 + k;
-            if (ch >= lend[lev + 1] || ninfo[ch].first >= end) break;
-            nparent[ch] = p;
-            nch++;
-        }
-        ninfo[p].lvl_nch = lev | (nch << 8) | (info.lvl_nch & (int32_t)0xffff0000);
-    }
-}
-
-// Moments bottom-up in one launch: the body that starts a leaf computes the
-// leaf from its bodies, then climbs: after a device-wide fence each finished
-// node counts itself in at its parent, and the child that arrives last (all
-// its siblings are done) computes the parent from the children, in child
-// order, so every node's moments are the same whatever the schedule.
-__global__ __launch_bounds__(256) void k_flat_moments(
-    int64_t n, const int32_t *__restrict__ leafnode, const int32_t *__restrict__ nparent,
-    int32_t *__restrict__ narrive, const NodeInfo *__restrict__ ninfo,
+__global__ __launch_bounds__(256) void k_moments_level(
+    int level, const TreeHeader *__restrict__ hdr, const NodeInfo *__restrict__ ninfo,
     const Body *__restrict__ body, const double *__restrict__ beps2,
     const uint64_t *__restrict__ keys, const SceneBox *__restrict__ box,
     NodeMom *__restrict__ nmom, double *__restrict__ neps2, double *__restrict__ nquad,
-    int use_eps)
+    int64_t node_cap, int use_eps, int32_t *__restrict__ depth_out)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    int32_t k = leafnode[i];
-    if (k < 0) return;
-    node_moments(k, node_level(ninfo[k]), ninfo, body, beps2, keys, box, nmom, neps2, nquad,
-                 use_eps);
-    for (;;) {
-        const int32_t p = nparent[k];
-        if (p < 0) break;
-        __threadfence();  // this node's moments are visible before it counts itself in
-        const int nch = node_nchild(ninfo[p]);
-        if (atomicAdd(&narrive[p], 1) != nch - 1) break;
-        __threadfence();  // and the siblings' are visible to the last one
-        node_moments(p, node_level(ninfo[p]), ninfo, body, beps2, keys, box, nmom, neps2, nquad,
-                     use_eps);
-        k = p;
+    moments_nodes(level, hdr->level_count, ninfo, body, beps2, keys, box, nmom, neps2, nquad,
+                  node_cap, use_eps, (int64_t)blockIdx.x * 256 + threadIdx.x,
+                  (int64_t)gridDim.x * 256);
+    // the root level reports the deepest non-empty level, as a launch hint
+    // for the next build (pinned host memory)
+    if (level == 0 && depth_out && blockIdx.x == 0 && threadIdx.x == 0) {
+        int d = 0;
+        for (int l = 1; l <= kMaxLevel; l++)
+            if (hdr->level_count[l] > 0) d = l;
+        *depth_out = d;
+    }
+}
+
+// Levels from-1 down to 0 of a single scene in one block, then the depth
+// report of k_moments_level at level 0.
+__global__ __launch_bounds__(1024) void k_moments_head(
+    int from, const TreeHeader *__restrict__ hdr, const NodeInfo *__restrict__ ninfo,
+    const Body *__restrict__ body, const double *__restrict__ beps2,
+    const uint64_t *__restrict__ keys, const SceneBox *__restrict__ box,
+    NodeMom *__restrict__ nmom, double *__restrict__ neps2, double *__restrict__ nquad,
+    int64_t node_cap, int use_eps, int32_t *__restrict__ depth_out)
+{
+    __shared__ int32_t scnt[kLevels + 1];
+    if (threadIdx.x <= kLevels) scnt[threadIdx.x] = hdr->level_count[threadIdx.x];
+    __syncthreads();
+    for (int level = from - 1; level >= 0; level--) {
+        moments_nodes(level, scnt, ninfo, body, beps2, keys, box, nmom, neps2, nquad, node_cap,
+                      use_eps,
+                      threadIdx.x, 1024);
+        __syncthreads();
+    }
+    if (depth_out && threadIdx.x == 0) {
+        int d = 0;
+        for (int l = 1; l <= kMaxLevel; l++)
+            if (hdr->level_count[l] > 0) d = l;
+        *depth_out = d;
+    }
+}
+
+// Levels kMaxLevel down to `to` in one block (deep levels hold few nodes).
+__global__ __launch_bounds__(1024) void k_moments_tail(
+    int to, const TreeHeader *__restrict__ hdr, const NodeInfo *__restrict__ ninfo,
+    const Body *__restrict__ body, const double *__restrict__ beps2,
+    const uint64_t *__restrict__ keys, const SceneBox *__restrict__ box,
+    NodeMom *__restrict__ nmom, double *__restrict__ neps2, double *__restrict__ nquad,
+    int64_t node_cap, int use_eps)
+{
+    __shared__ int32_t scnt[kLevels + 1];
+    if (threadIdx.x <= kLevels) scnt[threadIdx.x] = hdr->level_count[threadIdx.x];
+    __syncthreads();
+    for (int level = kMaxLevel; level >= to; level--) {
+        if (scnt[level] == 0) continue;  // the same on every thread
+        moments_nodes(level, scnt, ninfo, body, beps2, keys, box, nmom, neps2, nquad, node_cap,
+                      use_eps,
+                      threadIdx.x, 1024);
+        __syncthreads();
     }
 }
 
@@ -1081,11 +779,12 @@ __global__ __launch_bounds__(kSmallThreads) void k_build_small(
     if (tid == 0) {
         double lo[3], hi[3];
         for (int a = 0; a < 3; a++) {
+            box[0].lo_enc[a] = red_lo[a];
+            box[0].hi_enc[a] = red_hi[a];
             lo[a] = order_dec(red_lo[a]);
             hi[a] = order_dec(red_hi[a]);
         }
         root_cube(box[0], lo, hi);
-        box_clear(box[0]);
         ninfo[0] = NodeInfo{0, (int32_t)n, -1, 0};
     }
     __syncthreads();
@@ -1194,11 +893,21 @@ __global__ __launch_bounds__(kSmallThreads) void k_build_small(
         *depth_out = d;
     }
 }
+
 inline unsigned blocks_for(int64_t items, int per_block, unsigned cap)
 {
     int64_t b = (items + per_block - 1) / per_block;
     if (b < 1) b = 1;
     return (unsigned)(b < (int64_t)cap ? b : cap);
+}
+
+// Upper bound on the nodes of one level: at most 8^level per scene and at
+// most n in all.
+inline int64_t level_bound(int level, int64_t n, int scenes)
+{
+    int64_t b = scenes;
+    for (int l = 0; l < level && b < n; l++) b *= 8;
+    return b < n ? b : n;
 }
 
 // One block per scene fills its body range.
@@ -1212,12 +921,6 @@ __global__ __launch_bounds__(256) void k_scene_of(const int64_t *__restrict__ of
 
 }  // namespace
 
-hipError_t launch_box_reset(hipStream_t s, SceneBox *box, int n_scenes)
-{
-    k_box_reset<<<(unsigned)((n_scenes + 255) / 256), 256, 0, s>>>(box, n_scenes);
-    return hipGetLastError();
-}
-
 hipError_t launch_scene_of(hipStream_t s, const int64_t *offsets, int n_scenes,
                            uint16_t *scene_of)
 {
@@ -1226,7 +929,7 @@ hipError_t launch_scene_of(hipStream_t s, const int64_t *offsets, int n_scenes,
 }
 
 hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, const double *pos,
-                        const double *mass, const double *eps, int leaf)
+                        const double *mass, const double *eps, int leaf, bool all_levels)
 {
     const int64_t n = lay.n;
     const int ns = lay.n_scenes;
@@ -1236,10 +939,12 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
                                                   w.neps2, w.nquad, w.node_cap, w.depth_dev);
         return hipGetLastError();
     }
-    int nchunks = lay.chunks ? lay.n_chunks : (int)((n + kBoxChunk - 1) / kBoxChunk);
-    if (nchunks < 1) nchunks = 1;  // n = 0: one empty block still finalises the box
-    k_box<<<nchunks, kBoxThreads, 0, s>>>(pos, mass, eps, n, lay.chunks, nchunks, ns, lay.offsets,
-                                          w.box, w.hdr, w.ninfo);
+    const unsigned sb = (unsigned)((ns + 255) / 256);
+    k_box_init<<<sb, 256, 0, s>>>(w.box, ns);
+    const int nchunks = lay.chunks ? lay.n_chunks : (int)((n + kBoxChunk - 1) / kBoxChunk);
+    if (nchunks > 0)
+        k_box_chunk<<<nchunks, kBoxThreads, 0, s>>>(pos, mass, eps, n, lay.chunks, w.box, w.hdr);
+    k_box_final<<<sb, 256, 0, s>>>(w.box, ns, lay.offsets, n, w.hdr, w.ninfo);
     if (n == 0) return hipGetLastError();
 
     // 8 passes on the Morton key, then (several scenes) one on each byte of
@@ -1262,19 +967,42 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
     }
     k_gather<<<nb, 256, 0, s>>>(pos, mass, eps, w.idx[0], n, w.body, w.beps2);
 
-    // the octree and its moments from the sorted keys, five launches
-    const int ntiles = (int)((n + kFlatTile - 1) / kFlatTile);
-    k_flat_start<<<ntiles, kFlatTile, 0, s>>>(w.keys[0], n, lay.offsets, ns, leaf, w.blvl, w.bleaf,
-                                              w.tile_cnt, ntiles);
-    k_flat_scan<<<kLevels, 1024, 0, s>>>(w.tile_cnt, ntiles, w.hdr);
-    k_flat_nodes<<<ntiles, kFlatTile, 0, s>>>(w.keys[0], n, lay.offsets, ns, leaf, w.blvl, w.bleaf,
-                                              w.tile_cnt, ntiles, w.hdr, w.ninfo, w.leafnode,
-                                              w.nparent, w.narrive, w.ilist, w.node_cap);
-    k_flat_link<<<blocks_for(n / 8 + 1, 256, 2048), 256, 0, s>>>(w.hdr, w.ilist, w.ninfo,
-                                                                w.nparent, w.node_cap, w.depth_dev);
-    k_flat_moments<<<nb, 256, 0, s>>>(n, w.leafnode, w.nparent, w.narrive, w.ninfo, w.body,
-                                      w.beps2, w.keys[0], w.box, w.nmom, w.neps2, w.nquad,
-                                      eps != nullptr ? 1 : 0);
+    // Splitting: levels 0..deep-1 get a launch each, sized by the largest
+    // scene; the levels from `deep` down, which the previous build on this
+    // workspace left empty but for one level of growth, are handled in one
+    // block. Moments: the same, and the top levels of a single scene (levels
+    // 0..head-1, at most 585 nodes) in one block too. (Splitting the top
+    // levels in one block was measured slower: its binary searches over all
+    // bodies run four passes deep there.) The split only affects speed.
+    int deep = kMaxLevel;
+    if (w.depth_host && !all_levels) {
+        const int prev = *(const volatile int32_t *)w.depth_host;
+        if (prev >= 0 && prev + 1 < deep) deep = prev + 1;
+    }
+    const int head = ns == 1 ? (deep < 4 ? deep : 4) : 0;
+    for (int level = 0; level < deep; level++) {
+        // levels of many nodes take 1024-thread blocks (fewer reservations on
+        // the level counter), small ones 256 (more CUs for their searches)
+        const int64_t threads = level_bound(level, n, ns) * 8;
+        const int bs = threads >= 65536 ? 1024 : 256;
+        const unsigned g = blocks_for(threads, bs, bs == 1024 ? 1024 : 4096);
+        k_build_level<<<g, bs, 0, s>>>(level, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
+    }
+    if (deep < kMaxLevel)
+        k_build_tail<<<1, 1024, 0, s>>>(deep, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
+    const int use_eps = eps != nullptr;
+    k_moments_tail<<<1, 1024, 0, s>>>(deep, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0], w.box,
+                                      w.nmom, w.neps2, w.nquad, w.node_cap, use_eps);
+    for (int level = deep - 1; level >= head; level--) {
+        const unsigned g = blocks_for(level_bound(level, n, ns), 256, 4096);
+        k_moments_level<<<g, 256, 0, s>>>(level, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0], w.box,
+                                          w.nmom, w.neps2, w.nquad, w.node_cap, use_eps,
+                                          w.depth_dev);
+    }
+    if (head > 0)
+        k_moments_head<<<1, 1024, 0, s>>>(head, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0], w.box,
+                                          w.nmom, w.neps2, w.nquad, w.node_cap, use_eps,
+                                          w.depth_dev);
     return hipGetLastError();
 }
 
