@@ -147,6 +147,30 @@ bh_status bh_compute_accel_direct(bh_ctx *ctx, const double *pos, const double *
                                   double softening, const double *eps, double *acc, double *phi,
                                   int64_t n);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the direct
+ * sum of bh_compute_accel_direct without a context, computed by the same
+ * kernels in `precision` (BH_FP64 or BH_FP32C) with gravitational constant G,
+ * on hip_stream (NULL = the default stream), asynchronously. It allocates
+ * nothing: when the targets alone give too few blocks to fill the GPU
+ * (n < 262144), the split-row partial sums go to a library-owned device array
+ * of 2^20 doubles (8 MiB) on each device, reserved with the library's code
+ * and held until the process ends. Every call on a device shares that array
+ * and keeps the last call's contents, so calls that overlap on one device
+ * (different streams, or host threads without ordering) race and give
+ * undefined results; calls ordered on one stream are safe. Every partial sum
+ * a call reads it has written first, so the array needs no clearing.
+ * Arguments and layout as bh_compute_accel_direct (device pointers, outputs
+ * in caller order); there is no device-side check of the inputs.
+ * Errors (no side effects): BH_E_CAPACITY for n < 0 or n > BH_NOALLOC_MAX_N;
+ * BH_E_INVALID for another precision, G not finite, softening negative or not
+ * finite, NULL pos, mass or acc with n > 0; BH_E_HIP when the array's device
+ * address cannot be obtained or the launch fails. n = 0 is a no-op. */
+#define BH_NOALLOC_MAX_N ((int64_t)1 << 30)
+bh_status bh_compute_accel_direct_noalloc(void *hip_stream, int32_t precision, double G,
+                                          const double *pos, const double *mass, double softening,
+                                          const double *eps, double *acc, double *phi, int64_t n);
+
 /* nsteps kick-drift-kick leapfrog steps of dt, in place on pos and vel:
  * v += dt/2 a; x += dt v; a = A(x); v += dt/2 a. `acc` must hold the
  * acceleration at the input positions (e.g. from bh_compute_accel) and is

@@ -428,6 +428,36 @@ def compute_accel_direct(pos, mass, softening=0.0, *, eps=None, precision="fp32c
     return ctx.compute_accel_direct(pos, mass, softening=softening, eps=eps, potential=potential)
 
 
+def compute_accel_direct_noalloc(pos, mass, softening=0.0, *, eps=None, precision="fp32c",
+                                 G=1.0, out=None, phi=None):
+    """Direct N^2 accelerations through the entry point that allocates nothing
+    on the device (bh_compute_accel_direct_noalloc): no context; the caller
+    passes the outputs (out (n, 3) and optionally phi (n,), float64 on the
+    GPU) and the library's own per-device array holds the partial sums.
+    Queued on the current stream without synchronising. Returns out."""
+    lib = L.load()
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible: libbhx runs on the GPU only")
+    n = int(pos.shape[0]) if pos.dim() == 2 else -1
+    dev = pos.device
+    _check_f64("pos", pos, (n, 3), dev)
+    _check_f64("mass", mass, (n,), dev)
+    if eps is not None:
+        _check_f64("eps", eps, (n,), dev)
+    if out is None:
+        raise ValueError("out is required: this entry point allocates nothing")
+    _check_f64("out", out, (n, 3), dev)
+    if phi is not None:
+        _check_f64("phi", phi, (n,), dev)
+    prec = {"fp64": L.BH_FP64, "fp32c": L.BH_FP32C}[precision]
+    rc = lib.bh_compute_accel_direct_noalloc(C.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                             prec, float(G), _ptr(pos), _ptr(mass),
+                                             float(softening), _ptr(eps), _ptr(out), _ptr(phi), n)
+    if rc != 0:
+        raise BHError(rc, "bh_compute_accel_direct_noalloc failed")
+    return out
+
+
 def gravity_dt_bound(mass, radius, G=1.0):
     """Largest gravity time step of eq. (dt_g) for bodies of these masses and
     radii, with a context cached per device and G (see Context.gravity_dt_bound)."""

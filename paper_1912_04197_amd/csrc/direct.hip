@@ -8,6 +8,8 @@
 // When the targets give too few blocks to fill the GPU, block row y sums only
 // the y-th range of source tiles into a partial buffer, and a second kernel
 // adds the rows in order (so the result does not depend on scheduling).
+#include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "bhx_impl.h"
@@ -195,3 +197,56 @@ hipError_t launch_direct(hipStream_t s, const double *pos, const double *mass, c
 }
 
 }  // namespace bhx
+
+// ------------------------------------------------- no-allocation entry point
+
+namespace {
+
+// The split-row partial sums of bh_compute_accel_direct_noalloc: one array
+// per device, held by the library until the process ends and shared by every
+// call on that device (calls that overlap on one device race on it).
+__device__ __align__(256) double scratch[bhx::kDirectPart];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
+
+// The device address of this device's scratch array (the array's name is
+// only a host-side stand-in), looked up once per device with it current.
+bh_status scratch_ptr(double **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return BH_E_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return BH_E_HIP;
+        g_scratch[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch[dev];
+    return BH_OK;
+}
+
+}  // namespace
+
+extern "C" bh_status bh_compute_accel_direct_noalloc(void *hip_stream, int32_t precision,
+                                                     double G, const double *pos,
+                                                     const double *mass, double softening,
+                                                     const double *eps, double *acc, double *phi,
+                                                     int64_t n)
+{
+    if (n < 0 || n > BH_NOALLOC_MAX_N) return BH_E_CAPACITY;
+    if (precision != BH_FP64 && precision != BH_FP32C) return BH_E_INVALID;
+    if (!std::isfinite(G)) return BH_E_INVALID;
+    if (!(std::isfinite(softening) && softening >= 0.0)) return BH_E_INVALID;
+    if (n > 0 && (!pos || !mass || !acc)) return BH_E_INVALID;
+    if (n == 0) return BH_OK;
+    double *part = nullptr;
+    const bh_status st = scratch_ptr(&part);
+    if (st != BH_OK) return st;
+    // every partial sum is written before it is read (no clearing needed):
+    // row r of the split writes 4 doubles for each of the n targets
+    const hipError_t e = bhx::launch_direct((hipStream_t)hip_stream, pos, mass, eps, n,
+                                            softening * softening, G, precision, acc, phi, part);
+    return e == hipSuccess ? BH_OK : BH_E_HIP;
+}
