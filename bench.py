@@ -4,8 +4,11 @@
 Workload: N = 1,048,576 rubble-pile aggregation cloud (uniform ball of radius
 1, lognormal radii with median 1e-3 and log-sigma 0.3, mass ~ r^3 summing to 1,
 isotropic velocities at 0.1x virial plus solid-body spin 0.2 about z), G = 1,
-per-body softening = radius, theta = 0.5, leaf 16, FP32 pair terms with FP64
-state, kick-drift-kick steps of dt = 5e-4. A step is one whole hot path: tree
+per-body softening = radius, theta = 0.5, FP32 pair terms with FP64 state,
+kick-drift-kick steps of dt = 5e-4. The leaf size (bodies per bucket) is left
+open by the workload; the default, 4, is the fastest step of a measured sweep
+over 1..64 (the paper's own leaves hold one body), and the same step at leaf
+16 is reported beside it. A step is one whole hot path: tree
 rebuild (box, keys, sort, gather, build, moments), walk, and both kicks.
 
 Prints one JSON line: steps/s (value), Ginteractions/s, the direct N^2 and
@@ -30,18 +33,20 @@ if ROOT not in sys.path:
 METRIC = "steps/s & Ginteractions/s at N=1M, theta=0.5 vs direct N^2; force rel. err vs FP64"
 FLOPS_PER_INTERACTION = 20  # conventional count for one softened monopole/pair term
 PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak
+PEAK_FP64_TFLOPS = 78.6     # MI355X published FP64 vector peak
+NODE_BYTES = 56             # NodeInfo 16 + NodeMom 32 + node eps^2 8
 PEAK_HBM_TBS = 8.0           # MI355X published HBM3E bandwidth
 # Algorithmic HBM bytes per body of each phase of a step (reads and writes the
-# phase cannot avoid, once each; node tables counted at 0.16 nodes per body,
-# leaf 16).
+# phase cannot avoid, once each), plus the node tables (NODE_BYTES per node)
+# written once by the build and read once by the walk.
 BYTES_PER_BODY = {
     # box (pos, mass, eps read) 40 + keys (pos read, key and index written) 36
     # + sort (one read and one write of key and index) 24 + gather (pos, mass,
-    # eps, index read; body and eps^2 written) 84 + octree (keys searched,
-    # nodes written) 11 + moments (bodies and eps^2 read, nodes written) 46
-    "build": 241,
-    # target body and eps^2 40, index 4, acceleration written 24, tree read once 9
-    "walk": 77,
+    # eps, index read; body and eps^2 written) 84 + octree (keys searched) 8
+    # + moments (bodies and eps^2 read) 40
+    "build": 232,
+    # target body and eps^2 40, index 4, acceleration written 24
+    "walk": 68,
     # kick (v, a read; v written) 72 + kick-drift (x, v, a read; x, v written) 120
     "integrate": 192,
 }
@@ -62,9 +67,10 @@ def cpu_model():
     return platform.processor() or "unknown"
 
 
-def walk_traffic():
+def walk_traffic(leaf):
     """HBM bytes per walk launch from the committed rocprofv3 counter runs, or
-    None when the walk kernel's source has changed since they were taken."""
+    None when the walk kernel's source has changed since they were taken or
+    they were taken at another leaf size."""
     import hashlib
 
     try:
@@ -74,7 +80,8 @@ def walk_traffic():
             h = hashlib.sha256(f.read()).hexdigest()[:16]
     except (OSError, ValueError):
         return None
-    return rec["hbm_bytes_per_launch"] if rec.get("walk_source_sha256_16") == h else None
+    ok = rec.get("walk_source_sha256_16") == h and rec.get("leaf") == leaf
+    return rec["hbm_bytes_per_launch"] if ok else None
 
 
 def _sync_time(fn):
@@ -479,7 +486,7 @@ def ceilings(walk_tflops):
     }
 
 
-def step_phases(n, interactions, ms_step, build_ms, walk_ms):
+def step_phases(n, nnodes, interactions, ms_step, build_ms, walk_ms):
     """Per-phase roofline of one step: each phase's floor is its algorithmic
     HBM bytes at the HBM peak or, for the walk, its flops at the FP32 vector
     peak if that is longer; the step fraction is the sum of the floors over
@@ -490,7 +497,7 @@ def step_phases(n, interactions, ms_step, build_ms, walk_ms):
     measured = {"build": build_ms, "walk": walk_ms,
                 "integrate": max(ms_step - build_ms - walk_ms, 1e-6)}
     for ph, ms in measured.items():
-        nbytes = BYTES_PER_BODY[ph] * n
+        nbytes = BYTES_PER_BODY[ph] * n + (NODE_BYTES * nnodes if ph != "integrate" else 0)
         floor_ms = nbytes / (PEAK_HBM_TBS * 1e12) * 1e3
         bound = "hbm"
         if ph == "walk":
@@ -505,6 +512,41 @@ def step_phases(n, interactions, ms_step, build_ms, walk_ms):
     out["step_floor_ms"] = round(floor_total, 4)
     out["step_roofline_frac"] = round(floor_total / ms_step, 4)
     return out
+
+
+def bench_leaf(args, leaf, pos0, vel0, mass, eps):
+    """The headline FP32C step at another leaf size: step and walk times, the
+    interactions it does and its walk's roofline fraction."""
+    import torch
+
+    from paper_1912_04197_amd.api import Context
+
+    n, theta, dt = args.n, args.theta, args.dt
+    ctx = Context(n, leaf_size=leaf, precision="fp32c", timing=True, walk_group=args.walk_group)
+    pos, vel = pos0.clone(), vel0.clone()
+    acc = ctx.compute_accel(pos, mass, theta, eps=eps)
+    steps = max(5, min(20, args.steps))
+    for _ in range(2):
+        ctx.step_leapfrog(pos, vel, mass, acc, dt, 1, theta=theta, eps=eps, sync=False)
+    ctx.sync()
+    ctx.timing_reset()
+    ms = _sync_time(lambda: [ctx.step_leapfrog(pos, vel, mass, acc, dt, 1, theta=theta, eps=eps,
+                                               sync=False) for _ in range(steps)]) / steps
+    ctx.sync()
+    st = ctx.stats()
+    walk_ms = st["walk_ms"] / max(st["timed_evals"], 1)
+    ctx.close()
+    cctx = Context(n, leaf_size=leaf, precision="fp32c", counts=True)
+    cctx.compute_accel(pos0, mass, theta, eps=eps)
+    s2 = cctx.stats()
+    inter = s2["nodes_accepted"] + s2["leaf_pairs"]
+    cctx.close()
+    ach = FLOPS_PER_INTERACTION * inter / (walk_ms * 1e-3) / 1e12
+    log(f"leaf {leaf}: {ms:.3f} ms/step, walk {walk_ms:.3f} ms, {inter / n:.1f} interactions/body")
+    return {"ms_per_step": round(ms, 4), "steps_per_s": round(1e3 / ms, 2),
+            "walk_ms": round(walk_ms, 4), "interactions_per_body": round(inter / n, 1),
+            "ginteractions_per_s_walk": round(inter / (walk_ms * 1e-3) / 1e9, 2),
+            "walk_roofline_frac": round(ach / PEAK_FP32_TFLOPS, 4)}
 
 
 def direct_only(args):
@@ -538,7 +580,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=1 << 20, help="bodies (default 2^20)")
     ap.add_argument("--theta", type=float, default=0.5)
-    ap.add_argument("--leaf", type=int, default=16)
+    ap.add_argument("--leaf", type=int, default=4,
+                    help="bodies per leaf bucket (4: the fastest step of a measured sweep)")
     ap.add_argument("--dt", type=float, default=5e-4)
     ap.add_argument("--walk-group", type=int, default=0,
                     help="target bodies per wavefront in the walk (16/32/64; 0 = library default)")
@@ -658,15 +701,17 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-            "traffic": walk_traffic(),
+            "traffic": walk_traffic(leaf),
             "kernel": "k_walk<fp32c, per-body eps>",
             "flops_per_interaction": FLOPS_PER_INTERACTION,
         },
-        "phases": step_phases(n, interactions, ms_step, build_ms, walk_ms),
+        "phases": step_phases(n, nnodes, interactions, ms_step, build_ms, walk_ms),
         "ceilings": ceilings(achieved),
     }
 
     if not args.no_extras:
+        if leaf != 16:
+            result["leaf16"] = bench_leaf(args, 16, pos0, vel0, mass, eps)
         # plain FP64 form of the same step
         c64 = Context(n, leaf_size=leaf, precision="fp64", timing=True, walk_group=args.walk_group)
         p64, v64 = pos0.clone(), vel0.clone()
@@ -674,13 +719,23 @@ def main():
         k64 = max(3, min(10, args.steps))
         run_steps(c64, 1, p64, v64, a64)
         c64.sync()
+        c64.timing_reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         run_steps(c64, k64, p64, v64, a64)
         torch.cuda.synchronize()
         ms64 = (time.perf_counter() - t0) * 1e3 / k64
         c64.sync()
-        log(f"fp64 tree step {ms64:.3f} ms")
+        st64 = c64.stats()
+        walk64 = st64["walk_ms"] / max(st64["timed_evals"], 1)
+        ach64 = FLOPS_PER_INTERACTION * interactions / (walk64 * 1e-3) / 1e12
+        result["roofline_fp64"] = {
+            "bound": "alu", "achieved": round(ach64, 3), "peak": PEAK_FP64_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach64 / PEAK_FP64_TFLOPS, 4), "traffic": None,
+            "kernel": "k_walk<fp64, per-body eps>", "walk_ms": round(walk64, 4),
+            "flops_per_interaction": FLOPS_PER_INTERACTION,
+        }
+        log(f"fp64 tree step {ms64:.3f} ms (walk {walk64:.3f} ms)")
 
         # direct N^2 on the same GPU, and the force error against FP64 direct
         def timed(fn):

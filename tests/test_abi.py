@@ -134,11 +134,13 @@ def test_bench_phase_floors():
     sys.path.insert(0, root)
     import bench
 
-    n, inter = 1 << 20, 2.7e9
-    out = bench.step_phases(n, inter, 4.0, 0.4, 3.5)
-    # the JSON values are rounded to 4 decimals
-    assert out["build"]["floor_ms"] == pytest.approx(bench.BYTES_PER_BODY["build"] * n / 8e9,
-                                                     abs=1e-4)
+    n, nnodes, inter = 1 << 20, 800000, 2.7e9
+    out = bench.step_phases(n, nnodes, inter, 4.0, 0.4, 3.5)
+    # the JSON values are rounded to 4 decimals; the node tables count once
+    # in the build (written) and once in the walk (read)
+    build_bytes = bench.BYTES_PER_BODY["build"] * n + bench.NODE_BYTES * nnodes
+    assert out["build"]["floor_ms"] == pytest.approx(build_bytes / 8e9, abs=1e-4)
+    assert out["walk"]["algorithmic_bytes"] == bench.BYTES_PER_BODY["walk"] * n + 56 * nnodes
     walk_alu = 20 * inter / 157.3e12 * 1e3
     assert out["walk"]["bound"] == "alu"
     assert out["walk"]["floor_ms"] == pytest.approx(walk_alu, abs=1e-4)
@@ -146,4 +148,4 @@ def test_bench_phase_floors():
     floors = sum(out[k]["floor_ms"] for k in ("build", "walk", "integrate"))
     assert out["step_roofline_frac"] == pytest.approx(floors / 4.0, abs=1e-4)
     # a walk with few interactions is bound by its bytes instead
-    assert bench.step_phases(n, 1e3, 4.0, 0.4, 3.5)["walk"]["bound"] == "hbm"
+    assert bench.step_phases(n, nnodes, 1e3, 4.0, 0.4, 3.5)["walk"]["bound"] == "hbm"

@@ -182,6 +182,7 @@ WALK_CASES = [
     ("plummer20000_t0.3_l16", lambda: ics.plummer(20000, seed=22), 0.3, 16, 1e-3, False),
     ("plummer20000_t0.7_l16", lambda: ics.plummer(20000, seed=22), 0.7, 16, 1e-3, False),
     ("rubble30001_t0.5_l16_eps", lambda: ics.rubble_pile(30001, seed=33), 0.5, 16, 0.0, True),
+    ("rubble30001_t0.5_l4_eps", lambda: ics.rubble_pile(30001, seed=33), 0.5, 4, 0.0, True),
     ("cube4097_t0.6_l1", lambda: ics.uniform_cube(4097, seed=12), 0.6, 1, 1e-2, False),
     ("ball3000_t0.9_l64", lambda: ics.uniform_ball(3000, seed=13), 0.9, 64, 0.0, False),
     ("tiny1", lambda: ics.uniform_ball(1, seed=1), 0.5, 16, 1e-3, False),
@@ -250,17 +251,19 @@ def test_zero_bodies(api):
 
 # ------------------------------------------------------------ full sizes
 
+@pytest.mark.parametrize("leaf", [4, 16])
 @pytest.mark.parametrize("group", [16, 64])
 @pytest.mark.parametrize("precision", ["fp32c", "fp64"])
-def test_headline_size_sampled(api, precision, group):
-    """N = 2^20 rubble pile, theta 0.5, leaf 16, per-body softening = radius:
-    the oracle walks 1024 sampled bodies through its own full-size tree."""
+def test_headline_size_sampled(api, precision, group, leaf):
+    """N = 2^20 rubble pile, theta 0.5, per-body softening = radius, leaf 4
+    (the benchmark's default) and 16: the oracle walks 1024 sampled bodies
+    through its own full-size tree."""
     n = 1 << 20
     x, m, eps = _rubble(n, 33)
     rng = np.random.default_rng(1)
     sample = np.sort(rng.choice(n, 1024, replace=False))
-    ref_acc, _, aabs, ref_cnt = oracle.Tree(x, m, eps=eps, leaf=16).accel(0.5, targets=sample)
-    ctx = _ctx(api, n, leaf=16, precision=precision, group=group)
+    ref_acc, _, aabs, ref_cnt = oracle.Tree(x, m, eps=eps, leaf=leaf).accel(0.5, targets=sample)
+    ctx = _ctx(api, n, leaf=leaf, precision=precision, group=group)
     acc = ctx.compute_accel(_dev(x), _dev(m), 0.5, eps=_dev(eps)).cpu().numpy()[sample]
     cnt = ctx.walk_counts(n).cpu().numpy()[sample]
     assert np.array_equal(cnt, ref_cnt)
