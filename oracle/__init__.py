@@ -98,6 +98,8 @@ def _load(path: str | None = None):
     lib.orc_direct_vjp.restype = C.c_int
     lib.orc_tree_vjp.argtypes = [P, P, P, P, D, D, D, P, P, P]
     lib.orc_tree_vjp.restype = C.c_int
+    lib.orc_tree_vjp_abs.argtypes = [P, P, P, P, D, D, D, P, P, P]
+    lib.orc_tree_vjp_abs.restype = C.c_int
     lib.orc_rollout_grad.argtypes = [I64, P, P, P, P, D, D, D, I32, D, I32, P, P, P, P, P]
     lib.orc_rollout_grad.restype = C.c_int
     lib.orc_gravity_dt_bound.argtypes = [I64, P, P, D, P]
@@ -249,6 +251,19 @@ def tree_vjp(pos, mass, lam, theta, softening=0.0, eps=None, leaf=16, G=1.0):
     gm = np.zeros(T.n)
     _check(_load().orc_tree_vjp(T._h, _ptr(T.pos), _ptr(T.mass), _ptr(T.eps), float(softening),
                                 float(G), float(theta), _ptr(lam), _ptr(gx), _ptr(gm)))
+    return gx, gm
+
+
+def tree_vjp_abs(pos, mass, lam, theta, softening=0.0, eps=None, leaf=16, G=1.0):
+    """(g_pos, g_mass) error scales of tree_vjp: the same walk with the
+    magnitudes of every contribution's parts added (each bounds |tree_vjp|)."""
+    T = Tree(pos, mass, eps, leaf)
+    lam = _f64(lam, (T.n, 3))
+    gx = np.zeros((T.n, 3))
+    gm = np.zeros(T.n)
+    _check(_load().orc_tree_vjp_abs(T._h, _ptr(T.pos), _ptr(T.mass), _ptr(T.eps),
+                                    float(softening), float(G), float(theta), _ptr(lam), _ptr(gx),
+                                    _ptr(gm)))
     return gx, gm
 
 

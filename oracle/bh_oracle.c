@@ -709,6 +709,28 @@ static void term_vjp(const double d[3], double e2, double G, double ms, const do
     *ge2 = -1.5 * G * ms * ld * inv5;
 }
 
+/* Magnitudes of the parts of one term of term_vjp, for error bounds: with
+ * |l|.|d| = sum_a |l_a| |d_a|, gd_a = G m_s (|l_a| / r^3 + 3 |d_a| |l|.|d| / r^5),
+ * gm = G |l|.|d| / r^3 and ge2 = 3/2 G m_s |l|.|d| / r^5: each bounds the
+ * absolute value of the corresponding part of term_vjp (triangle inequality)
+ * and is what a rounding of every operation in it is relative to. */
+static void term_vjp_abs(const double d[3], double e2, double G, double ms, const double l[3],
+                         double gd[3], double *gm, double *ge2)
+{
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2] + e2;
+    gd[0] = gd[1] = gd[2] = 0.0;
+    *gm = 0.0;
+    *ge2 = 0.0;
+    if (!term_counts(r2)) return;
+    double r = sqrt(r2);
+    double inv3 = 1.0 / (r2 * r);
+    double inv5 = inv3 / r2;
+    double ld = fabs(l[0]) * fabs(d[0]) + fabs(l[1]) * fabs(d[1]) + fabs(l[2]) * fabs(d[2]);
+    for (int a = 0; a < 3; a++) gd[a] = G * ms * (fabs(l[a]) * inv3 + 3.0 * fabs(d[a]) * ld * inv5);
+    *gm = G * ld * inv3;
+    *ge2 = 1.5 * G * ms * ld * inv5;
+}
+
 int orc_direct_vjp(int64_t n, const double *pos, const double *mass, const double *eps,
                    double eps0, double G, const double *lambda, double *g_pos, double *g_mass)
 {
@@ -741,6 +763,7 @@ typedef struct {
     double e02, G, theta2;
     double *g_pos, *g_mass;     /* body adjoints */
     double *nX, *nm, *ne2;      /* node adjoints: centre of mass, mass, <eps^2> */
+    int absmode;                /* accumulate the magnitudes of every contribution */
 } vjp_ctx;
 
 static void vjp_node(vjp_ctx *w, int64_t b, const double xb[3], double eb2, const double l[3],
@@ -755,9 +778,10 @@ static void vjp_node(vjp_ctx *w, int64_t b, const double xb[3], double eb2, cons
             double d[3] = {w->pos[3 * j] - xb[0], w->pos[3 * j + 1] - xb[1],
                            w->pos[3 * j + 2] - xb[2]};
             double e2 = w->eps ? 0.5 * (eb2 + w->eps[j] * w->eps[j]) : w->e02;
-            term_vjp(d, e2, w->G, w->mass[j], l, gd, &gm, &ge2);
+            if (w->absmode) term_vjp_abs(d, e2, w->G, w->mass[j], l, gd, &gm, &ge2);
+            else term_vjp(d, e2, w->G, w->mass[j], l, gd, &gm, &ge2);
             for (int a = 0; a < 3; a++) {
-                w->g_pos[3 * b + a] -= gd[a];
+                w->g_pos[3 * b + a] += w->absmode ? gd[a] : -gd[a];
                 w->g_pos[3 * j + a] += gd[a];
             }
             w->g_mass[j] += gm;
@@ -769,9 +793,10 @@ static void vjp_node(vjp_ctx *w, int64_t b, const double xb[3], double eb2, cons
     double sd = ldexp(t->L, -t->level[k]);
     if (sd * sd < w->theta2 * D2) {
         double e2 = w->eps ? 0.5 * (eb2 + t->eps2[k]) : w->e02;
-        term_vjp(d, e2, w->G, t->m[k], l, gd, &gm, &ge2);
+        if (w->absmode) term_vjp_abs(d, e2, w->G, t->m[k], l, gd, &gm, &ge2);
+        else term_vjp(d, e2, w->G, t->m[k], l, gd, &gm, &ge2);
         for (int a = 0; a < 3; a++) {
-            w->g_pos[3 * b + a] -= gd[a];
+            w->g_pos[3 * b + a] += w->absmode ? gd[a] : -gd[a];
             w->nX[3 * k + a] += gd[a];
         }
         w->nm[k] += gm;
@@ -781,9 +806,9 @@ static void vjp_node(vjp_ctx *w, int64_t b, const double xb[3], double eb2, cons
     for (int64_t c = t->child0[k]; c < t->child0[k] + t->nchild[k]; c++) vjp_node(w, b, xb, eb2, l, c);
 }
 
-int orc_tree_vjp(const orc_tree *t, const double *pos, const double *mass, const double *eps,
-                 double eps0, double G, double theta, const double *lambda, double *g_pos,
-                 double *g_mass)
+static int tree_vjp(const orc_tree *t, const double *pos, const double *mass, const double *eps,
+                    double eps0, double G, double theta, const double *lambda, double *g_pos,
+                    double *g_mass, int absmode)
 {
     if (!t) return 1;
     int64_t n = t->n;
@@ -803,7 +828,7 @@ int orc_tree_vjp(const orc_tree *t, const double *pos, const double *mass, const
         return 4;
     }
     vjp_ctx w = {t, pos, mass, eps, lambda, eps0 * eps0, G, theta * theta, g_pos, g_mass,
-                 nX, nm, ne2};
+                 nX, nm, ne2, absmode};
     for (int64_t b = 0; b < n; b++) {
         double eb2 = eps ? eps[b] * eps[b] : 0.0;
         vjp_node(&w, b, pos + 3 * b, eb2, lambda + 3 * b, 0);
@@ -821,16 +846,34 @@ int orc_tree_vjp(const orc_tree *t, const double *pos, const double *mass, const
             double dot = 0.0;
             for (int a = 0; a < 3; a++) {
                 g_pos[3 * j + a] += mass[j] / mN * nX[3 * k + a];
-                dot += (pos[3 * j + a] - t->com[3 * k + a]) * nX[3 * k + a];
+                double dx = pos[3 * j + a] - t->com[3 * k + a];
+                dot += (absmode ? fabs(dx) : dx) * nX[3 * k + a];
             }
             g_mass[j] += dot / mN;
-            if (eps) g_mass[j] += ne2[k] * (eps[j] * eps[j] - t->eps2[k]) / mN;
+            if (eps) {
+                double de = eps[j] * eps[j] - t->eps2[k];
+                g_mass[j] += ne2[k] * (absmode ? fabs(de) : de) / mN;
+            }
         }
     }
     free(nX);
     free(nm);
     free(ne2);
     return 0;
+}
+
+int orc_tree_vjp(const orc_tree *t, const double *pos, const double *mass, const double *eps,
+                 double eps0, double G, double theta, const double *lambda, double *g_pos,
+                 double *g_mass)
+{
+    return tree_vjp(t, pos, mass, eps, eps0, G, theta, lambda, g_pos, g_mass, 0);
+}
+
+int orc_tree_vjp_abs(const orc_tree *t, const double *pos, const double *mass, const double *eps,
+                     double eps0, double G, double theta, const double *lambda, double *g_pos,
+                     double *g_mass)
+{
+    return tree_vjp(t, pos, mass, eps, eps0, G, theta, lambda, g_pos, g_mass, 1);
 }
 
 /* VJP of A at pos for upstream lam: adds into gx and gm. */

@@ -127,6 +127,18 @@ int orc_tree_vjp(const orc_tree *t, const double *pos, const double *mass, const
                  double eps0, double G, double theta, const double *lambda, double *g_pos,
                  double *g_mass);
 
+/* Error scale of orc_tree_vjp: the same walk and node hand-down, with every
+ * contribution replaced by the magnitudes of its parts (G m_s (|l_a| / r^3 +
+ * 3 |d_a| sum_b |l_b||d_b| / r^5) for positions, G sum_b |l_b||d_b| / r^3 and
+ * 3/2 G m_s sum_b |l_b||d_b| / r^5 for mass and softening, and the absolute
+ * values of the hand-down factors) and all of them added. Each output bounds
+ * the absolute value of orc_tree_vjp's and is what the rounding of a
+ * different evaluation order or precision is relative to. ADDS like
+ * orc_tree_vjp. */
+int orc_tree_vjp_abs(const orc_tree *t, const double *pos, const double *mass, const double *eps,
+                     double eps0, double G, double theta, const double *lambda, double *g_pos,
+                     double *g_mass);
+
 /* Gradient of a scalar loss through nsteps kick-drift-kick steps that start
  * from (pos0, vel0) with a0 = A(pos0): given xbar, vbar = dL/dx_T, dL/dv_T,
  * writes gx0 = dL/dx0, gv0 = dL/dv0 and gm = dL/dm (all decisions of every

@@ -689,6 +689,136 @@ def pin_vjp_invariants():
         assert abs(float((m * gm).sum()) - la) <= 1e-12 * float(np.abs(lam * a).sum()), theta
 
 
+def pin_vjp_abs_two_body_closed_form():
+    """The error scale of the VJP for two bodies in one leaf, written out:
+    body 0 is the target of body 1's term and the source of body 0's term in
+    body 1's row; with d = x_1 - x_0, r^2 = |d|^2 + eps^2 and
+    L_i = sum_a |lam_i,a| |d_a|: g_x0,a = G m_1 (|lam_0,a| / r^3 + 3 |d_a| L_0 / r^5)
+    + G m_0 (|lam_1,a| / r^3 + 3 |d_a| L_1 / r^5), g_m0 = G L_1 / r^3."""
+    x = np.array([[0.1, -0.2, 0.3], [0.7, 0.4, -0.5]])
+    m = np.array([0.3, 1.7])
+    lam = np.array([[1.0, -2.0, 0.5], [-0.25, 0.75, 3.0]])
+    G, soft = 1.3, 0.2
+    gx, gm = oracle.tree_vjp_abs(x, m, lam, 0.5, softening=soft, leaf=16, G=G)
+    d = np.abs(x[1] - x[0])
+    r2 = float((d * d).sum()) + soft * soft
+    inv3, inv5 = r2 ** -1.5, r2 ** -2.5
+    L0, L1 = float((np.abs(lam[0]) * d).sum()), float((np.abs(lam[1]) * d).sum())
+    for b, (mo, Lb, Lo) in enumerate(((m[1], L0, L1), (m[0], L1, L0))):
+        o = 1 - b
+        want = (G * mo * (np.abs(lam[b]) * inv3 + 3 * d * Lb * inv5)
+                + G * m[b] * (np.abs(lam[o]) * inv3 + 3 * d * Lo * inv5))
+        np.testing.assert_allclose(gx[b], want, rtol=1e-14)
+        np.testing.assert_allclose(gm[b], G * Lo * inv3, rtol=1e-14)
+
+
+def set_based_vjp_abs(x, m, lam, theta, leaf, softening=0.0, eps=None, G=1.0):
+    """The VJP's error scale from the set definition of the walk (as in
+    set_based_bh): each term's part magnitudes G m_s (|l_a| / r^3 +
+    3 |d_a| L / r^5), G L / r^3 and 3/2 G m_s L / r^5 with L = sum |l_a||d_a|
+    go to the target (position part) and the source (all parts); an accepted
+    cell hands its sums to its members with |x_j - X| and |eps_j^2 - <eps^2>|."""
+    n = len(x)
+    q, x0, L = _quantise(x)
+    cells = {}
+    for lvl in range(22):
+        key = q >> (21 - lvl)
+        groups = {}
+        for i in range(n):
+            groups.setdefault((lvl, *key[i]), []).append(i)
+        for k, mem in groups.items():
+            if lvl == 0:
+                cells[k] = np.array(mem)
+            else:
+                parent = (lvl - 1, *(np.array(k[1:]) >> 1))
+                if parent in cells and len(cells[parent]) > leaf:
+                    cells[k] = np.array(mem)
+    eb2 = eps ** 2 if eps is not None else np.zeros(n)
+    gx = np.zeros((n, 3))
+    gm = np.zeros(n)
+
+    def parts(d, e2, ms, l):
+        r2 = (d * d).sum(1) + e2
+        inv3, inv5 = r2 ** -1.5, r2 ** -2.5
+        Ld = (np.abs(l) * np.abs(d)).sum(1)
+        gd = G * ms[:, None] * (np.abs(l) * inv3[:, None] + 3 * np.abs(d) * (Ld * inv5)[:, None])
+        return gd, G * Ld * inv3, 1.5 * G * ms * Ld * inv5
+
+    info = {}
+    for k, mem in cells.items():
+        mm = m[mem].sum()
+        com = (m[mem, None] * x[mem]).sum(0) / mm
+        e2 = (m[mem] * eb2[mem]).sum() / mm
+        is_leaf = len(mem) <= leaf or k[0] == 21
+        D2 = ((com[None, :] - x) ** 2).sum(1)
+        s2 = (L / 2 ** k[0]) ** 2
+        info[k] = (mem, mm, com, e2, is_leaf, s2 < theta * theta * D2)
+    for k, (mem, mm, com, e2, is_leaf, passes) in info.items():
+        lvl = k[0]
+        reach = np.ones(n, bool)
+        for a in range(lvl):
+            reach &= ~info[(a, *(np.array(k[1:]) >> (lvl - a)))][5]
+        if is_leaf:
+            for j in mem:
+                sel = reach.copy()
+                sel[j] = False
+                if not sel.any():
+                    continue
+                d = x[j][None, :] - x[sel]
+                e = 0.5 * (eb2[sel] + eb2[j]) if eps is not None else np.full(sel.sum(), softening ** 2)
+                gd, gmm, _ = parts(d, e, np.full(sel.sum(), m[j]), lam[sel])
+                gx[sel] += gd
+                gx[j] += gd.sum(0)
+                gm[j] += gmm.sum()
+        else:
+            sel = reach & passes
+            if not sel.any():
+                continue
+            d = com[None, :] - x[sel]
+            e = 0.5 * (eb2[sel] + e2) if eps is not None else np.full(sel.sum(), softening ** 2)
+            gd, gmm, ge2 = parts(d, e, np.full(sel.sum(), mm), lam[sel])
+            gx[sel] += gd
+            nX, nm, ne2 = gd.sum(0), gmm.sum(), 0.5 * ge2.sum()
+            for j in mem:
+                gx[j] += m[j] / mm * nX
+                gm[j] += nm + (np.abs(x[j] - com) * nX).sum() / mm
+                if eps is not None:
+                    gm[j] += ne2 * abs(eb2[j] - e2) / mm
+    return gx, gm
+
+
+def pin_vjp_abs_set_based():
+    """The oracle's VJP error scale equals the one built from the set
+    definition (nodes accepted, leaf pairs, hand-down to members)."""
+    rng = np.random.default_rng(26)
+    for x, theta, leaf, per_body in ((ics.uniform_ball(150, seed=5).pos, 0.7, 2, True),
+                                     (ics.plummer(120, seed=6).pos, 0.5, 1, False)):
+        n = len(x)
+        m = rng.random(n) + 0.2
+        eps = 0.02 + 0.02 * rng.random(n) if per_body else None
+        lam = rng.standard_normal((n, 3))
+        ax, am = oracle.tree_vjp_abs(x, m, lam, theta, softening=0.01, eps=eps, leaf=leaf, G=1.1)
+        sx, sm = set_based_vjp_abs(x, m, lam, theta, leaf, softening=0.01, eps=eps, G=1.1)
+        np.testing.assert_allclose(ax, sx, rtol=1e-12)
+        np.testing.assert_allclose(am, sm, rtol=1e-12)
+
+
+def pin_vjp_abs_bounds_vjp():
+    """Every output of the VJP's error scale bounds the VJP's absolute value
+    (tree with nodes, per-body softening), the scale does not depend on the
+    sign of lambda and is linear in its size."""
+    s = ics.rubble_pile(600, seed=25)
+    rng = np.random.default_rng(25)
+    lam = rng.standard_normal((600, 3))
+    gx, gm = oracle.tree_vjp(s.pos, s.mass, lam, 0.6, eps=s.eps, leaf=4)
+    ax, am = oracle.tree_vjp_abs(s.pos, s.mass, lam, 0.6, eps=s.eps, leaf=4)
+    assert np.all(np.abs(gx) <= ax) and np.all(np.abs(gm) <= am)
+    assert np.median(np.abs(gx) / ax) < 0.5  # terms of both signs: a real bound, not |g| itself
+    bx, bm = oracle.tree_vjp_abs(s.pos, s.mass, -2.0 * lam, 0.6, eps=s.eps, leaf=4)
+    np.testing.assert_allclose(bx, 2.0 * ax, rtol=1e-14)
+    np.testing.assert_allclose(bm, 2.0 * am, rtol=1e-14)
+
+
 def pin_vjp_theta_zero_is_direct():
     x, m, eps, lam, _ = _fd_case(seed=24, n=300)
     for e in (None, eps):

@@ -66,17 +66,24 @@ MUTANTS = {
                       "for (int64_t i = 0; i < 3 * n; i++) pos[i] += dt * (vel[i] - 0.5 * dt * acc[i]);"),
     "ekin_no_half": ("out[0] += 0.5 * m * (v[0] * v[0]", "out[0] += m * (v[0] * v[0]"),
     "angmom_sign": ("out[7] += m * (x[0] * v[1] - x[1] * v[0]);", "out[7] += m * (x[1] * v[0] - x[0] * v[1]);"),
+    "vjp_abs_outer_factor": ("gd[a] = G * ms * (fabs(l[a]) * inv3 + 3.0 * fabs(d[a]) * ld * inv5);",
+                             "gd[a] = G * ms * (fabs(l[a]) * inv3 + fabs(d[a]) * ld * inv5);"),
+    "vjp_abs_target_sign": ("w->g_pos[3 * b + a] += w->absmode ? gd[a] : -gd[a];\n                w->g_pos[3 * j + a]",
+                            "w->g_pos[3 * b + a] += -gd[a];\n                w->g_pos[3 * j + a]"),
+    "vjp_abs_signed_handdown": ("dot += (absmode ? fabs(dx) : dx) * nX[3 * k + a];",
+                                "dot += dx * nX[3 * k + a];"),
     "vjp_drop_outer": ("gd[a] = G * ms * (l[a] * inv3 - 3.0 * d[a] * ld * inv5);",
                        "gd[a] = G * ms * (l[a] * inv3);"),
     "vjp_outer_factor": ("gd[a] = G * ms * (l[a] * inv3 - 3.0 * d[a] * ld * inv5);",
                          "gd[a] = G * ms * (l[a] * inv3 - 2.0 * d[a] * ld * inv5);"),
     "vjp_source_sign": ("                g_pos[3 * j + a] += gd[a];\n            }\n            g_mass[j] += gm;\n        }\n    }\n    return 0;",
                         "                g_pos[3 * j + a] -= gd[a];\n            }\n            g_mass[j] += gm;\n        }\n    }\n    return 0;"),
-    "vjp_mass_term": ("*gm = G * ld * inv3;", "*gm = G * ld * inv5;"),
+    "vjp_mass_term": ("3.0 * d[a] * ld * inv5);\n    *gm = G * ld * inv3;",
+                      "3.0 * d[a] * ld * inv5);\n    *gm = G * ld * inv5;"),
     "vjp_node_com_mass": ("g_mass[j] += dot / mN;", "g_mass[j] += dot;"),
     "vjp_node_pos_weight": ("g_pos[3 * j + a] += mass[j] / mN * nX[3 * k + a];",
                             "g_pos[3 * j + a] += nX[3 * k + a];"),
-    "vjp_node_eps": ("if (eps) g_mass[j] += ne2[k] * (eps[j] * eps[j] - t->eps2[k]) / mN;", ""),
+    "vjp_node_eps": ("g_mass[j] += ne2[k] * (absmode ? fabs(de) : de) / mN;", "(void)de;"),
     "rollout_no_a0": ("    rc = accel_vjp(n, X, mass, eps, eps0, G, theta, leaf, ab, xb, gm);\n    if (rc) goto done;\n    memcpy(gx0",
                       "    memcpy(gx0"),
     "rollout_kick": ("for (size_t i = 0; i < n3; i++) ab[i] += h * vb[i];", "for (size_t i = 0; i < n3; i++) ab[i] += dt * vb[i];"),
