@@ -177,9 +177,10 @@ def bench_batched(args, n_scenes=256, steps=10, theta=0.5, dt=1e-3, soft=1e-3):
 
 def bench_adjoint(n=65536, nsteps=200, every=20, theta=0.5, dt=1e-3, soft=1e-3):
     """Differentiable rollout: forward KDK steps with checkpoints, then the
-    hand-written adjoint back to (x0, v0, m), against the forward alone; the
-    tree gradient against the FP64 direct-sum gradient, and FP32C against
-    FP64."""
+    hand-written adjoint back to (x0, v0, m), against the forward alone (each
+    the median of 3 runs after a warm-up); the tree gradient against the FP64
+    direct-sum gradient, and FP32C (FP32C forward and FP32C tree VJPs)
+    against FP64."""
     import torch
 
     from paper_1912_04197_amd import ics
@@ -210,9 +211,10 @@ def bench_adjoint(n=65536, nsteps=200, every=20, theta=0.5, dt=1e-3, soft=1e-3):
                            checkpoint_every=every)
             ((x - xt) ** 2).sum().backward()
 
+        fwd_bwd()  # warm-up: first-touch of the workspaces and kernels
         torch.cuda.reset_peak_memory_stats()
-        t_fb = _sync_time(fwd_bwd)
-        t_f = _sync_time(fwd)
+        t_fb = sorted(_sync_time(fwd_bwd) for _ in range(3))[1]  # median of 3
+        t_f = sorted(_sync_time(fwd) for _ in range(3))[1]
         peak = torch.cuda.max_memory_allocated()
         grads[label] = [t.grad.detach().clone() for t in (x0, v0, m)]
         ctx.close()
@@ -283,62 +285,96 @@ def bench_plummer(n=131072, nsteps=500, every=100, dt=1e-3, soft=1e-3, thetas=(0
     return out
 
 
-def bench_cold_collapse(n=1000, thetas=(0.1, 0.25, 0.5, 0.75), soft=0.1, dt=1e-3, every=25):
-    """The paper's accuracy experiment: N bodies at rest, uniform in a cube,
-    collapse and re-expand (two free-fall times); the position of every body
-    under the tree is compared with the direct sum's through e_i(t) =
-    |r_BH - r_N2| / |r_N2| in percent: its maximum over bodies (the paper's
-    figure), and for context its 99th percentile and median, over the run and
-    at the end of the contraction (one free-fall time). Semi-implicit Euler,
-    FP64, one-body leaves."""
-    import math
-
+def bench_cold_collapse(n=1000, thetas=(0.1, 0.25, 0.5, 0.75), soft=2.0, dt=5e-3, every=10,
+                        t_max=16.0):
+    """The paper's accuracy experiment: N bodies at rest, uniform in a cube of
+    side 2, pulse through one contraction and re-expansion; every body's
+    position under the tree is compared with the direct sum's through
+    e_i(t) = |r_BH - r_N2| / |r_N2| in percent. The softening (2, the cube's
+    side) makes the collapse a nearly reversible pulsation, as the paper
+    describes it: the end of the contraction is the direct run's minimum of the
+    half-mass radius (about its COM), and the pulsation ends at the next
+    maximum, where the bodies are nearly at rest again. Reported per theta:
+    the largest e_i over bodies at the end of the contraction, its maximum over
+    the pulsation and when, measured from the barycentre (frame-free) and in a
+    frame whose origin is a corner of the cube (domain [0, 2]^3, positions as a
+    simulation of a cubic domain would hold them). Semi-implicit Euler with
+    gravity every substep, FP64, one-body leaves."""
     import torch
 
     from paper_1912_04197_amd import ics
     from paper_1912_04197_amd.api import Context
 
     sc = ics.uniform_cube(n, seed=12)
-    rho = 1.0 / 8.0  # unit mass in a cube of side 2
-    t_ff = math.sqrt(3.0 * math.pi / (32.0 * rho))
-    nsteps = int(round(2.0 * t_ff / dt / every)) * every
+    nsamp = int(round(t_max / dt / every))
     m = torch.from_numpy(sc.mass).cuda()
 
-    def run(theta):
+    def run(theta, diag=False):
         ctx = Context(n, leaf_size=1, precision="fp64")
         p = torch.from_numpy(sc.pos).cuda()
         v = torch.zeros_like(p)
         a = (ctx.compute_accel(p, m, theta, softening=soft) if theta >= 0
              else ctx.compute_accel_direct(p, m, softening=soft))
-        snaps = []
-        for _ in range(nsteps // every):
+        e0 = ctx.diagnostics(p, v, m, softening=soft) if diag else None
+        snaps, ekin, energy = [], [], []
+        for _ in range(nsamp):
             ctx.step_euler(p, v, m, a, dt, every, theta=theta, softening=soft, sync=False)
             snaps.append(p.clone())
+            if diag:
+                d = ctx.diagnostics(p, v, m, softening=soft)
+                ekin.append(d[0])
+                energy.append(d[0] + d[1])
         ctx.sync()
         ctx.close()
-        return snaps
+        return snaps, e0, ekin, energy
 
     t0 = time.perf_counter()
-    ref = run(-1.0)
-    half = len(ref) // 2 - 1
+    ref, e0, ekin, energy = run(-1.0, diag=True)
+    com = torch.from_numpy((sc.mass[:, None] * sc.pos).sum(0) / sc.mass.sum()).cuda()
+    rhalf = [float(torch.linalg.norm(x - com, dim=1).median()) for x in ref]
+    r0 = float(torch.linalg.norm(torch.from_numpy(sc.pos).cuda() - com, dim=1).median())
+    kmin = min(range(len(rhalf)), key=rhalf.__getitem__)
+    kend = max(range(kmin, len(rhalf)), key=rhalf.__getitem__)
+    E0 = e0[0] + e0[1]
     out = {"workload": f"uniform cube N={n} side 2 at rest, eps={soft}, semi-implicit Euler "
-                       f"dt={dt} for two free-fall times ({nsteps} steps), leaf 1, FP64",
-           "samples_every_steps": every}
+                       f"dt={dt} (gravity every substep), leaf 1, FP64; positions sampled every "
+                       f"{every} substeps",
+           "direct_run": {
+               "t_end_of_contraction": round((kmin + 1) * every * dt, 3),
+               "t_end_of_pulsation": round((kend + 1) * every * dt, 3),
+               "half_mass_radius_initial": round(r0, 4),
+               "half_mass_radius_min": round(rhalf[kmin], 4),
+               "half_mass_radius_end": round(rhalf[kend], 4),
+               "ekin_end_over_max": round(ekin[kend] / max(ekin[: kend + 1]), 5),
+               "energy_rel_error_max": float(max(abs(e - E0) for e in energy[: kend + 1]) / abs(E0)),
+               "half_mass_radius_curve": [round(rhalf[k], 4) for k in
+                                          range(0, kend + 1, max(1, (kend + 1) // 12))],
+           }}
+    corner = torch.ones(3, dtype=torch.float64, device="cuda")  # cube [-1, 1]^3 -> [0, 2]^3
     for th in thetas:
-        snaps = run(th)
-        e = torch.stack([torch.linalg.norm(a - b, dim=1) / torch.linalg.norm(b, dim=1)
-                         for a, b in zip(snaps, ref)]) * 100
-        mx = e.max(dim=1).values
-        k = int(mx.argmax())
-        out[f"theta_{th}"] = {
-            "max_pct": round(float(mx[k]), 5), "at_fraction_of_run": round((k + 1) / len(mx), 3),
-            "p99_pct_peak": round(float(e.quantile(0.99, dim=1).max()), 5),
-            "median_pct_peak": round(float(e.median(dim=1).values.max()), 6),
-            "max_pct_end_of_contraction": round(float(mx[half]), 5),
-        }
-    peaks = [out[f"theta_{th}"]["max_pct"] for th in thetas]
-    out["error_increases_with_theta"] = all(x < y for x, y in zip(peaks, peaks[1:]))
-    log(f"cold collapse: peaks {peaks} ({time.perf_counter() - t0:.1f} s)")
+        snaps = run(th)[0][: kend + 1]
+        e_com = torch.stack([torch.linalg.norm(a - b, dim=1) / torch.linalg.norm(b - com, dim=1)
+                             for a, b in zip(snaps, ref)]) * 100
+        e_box = torch.stack([torch.linalg.norm(a - b, dim=1) / torch.linalg.norm(b + corner, dim=1)
+                             for a, b in zip(snaps, ref)]) * 100
+        rec = {}
+        for name, e in (("barycentric", e_com), ("corner_frame", e_box)):
+            mx = e.max(dim=1).values
+            k = int(mx.argmax())
+            rec[name] = {"max_pct_end_of_contraction": round(float(mx[kmin]), 6),
+                         "max_pct_over_pulsation": round(float(mx[k]), 6),
+                         "at_fraction_of_pulsation": round((k + 1) / len(mx), 3)}
+        out[f"theta_{th}"] = rec
+    for name in ("barycentric", "corner_frame"):
+        ends = [out[f"theta_{th}"][name]["max_pct_end_of_contraction"] for th in thetas]
+        out[f"ratio_theta_{thetas[-1]}_over_{thetas[0]}_{name}"] = round(ends[-1] / ends[0], 1)
+        out[f"error_increases_with_theta_{name}"] = all(x < y for x, y in zip(ends, ends[1:]))
+    out["paper_context"] = ("paper (N=1000, GeForce 940M): max error about 0.3 % at theta 0.75 at the "
+                            "end of contraction, about two orders of magnitude between theta 0.1 "
+                            "and 0.75; ICs, units and softening not stated")
+    log(f"cold collapse: end of contraction t={out['direct_run']['t_end_of_contraction']}, "
+        f"max error {[out[f'theta_{th}']['corner_frame']['max_pct_end_of_contraction'] for th in thetas]} % "
+        f"(corner frame) ({time.perf_counter() - t0:.1f} s)")
     return out
 
 

@@ -262,9 +262,13 @@ bh_status bh_autotune(const bh_config *base, void *hip_stream, int32_t n_scenes,
  * held fixed (both are piecewise constant in the inputs): a node term passes
  * its adjoint to the node's members through the centre of mass, the node
  * mass and the mass-weighted softening (eq. COMinternal). theta < 0
- * differentiates the direct sum. Computed in FP64 whatever the precision; the
- * tree form adds source-side terms with atomics, so its last bits depend on
- * scheduling. Needs BH_FLAG_ADJOINT (else BH_E_STATE). Errors: as
+ * differentiates the direct sum. The tree form is computed in the context's
+ * precision: in BH_FP32C each term's offset is the FP64 difference rounded
+ * once and the rest of the term is FP32, with FP32 partial sums over at most
+ * 8 items added into FP64 sums and adjoints (the error is bounded by a small
+ * multiple of 2^-24 times the sum of the terms' absolute values); the direct
+ * form is FP64 in either precision. The tree form adds source-side terms with
+ * atomics, so its last bits depend on scheduling. Needs BH_FLAG_ADJOINT (else BH_E_STATE). Errors: as
  * bh_compute_accel, plus BH_E_INVALID for NULL lambda, g_pos or g_mass. */
 bh_status bh_accel_vjp(bh_ctx *ctx, const double *pos, const double *mass, double softening,
                        const double *eps, double theta, const double *lambda, double *g_pos,

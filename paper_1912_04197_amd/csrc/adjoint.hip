@@ -78,6 +78,11 @@ __device__ inline double dpp(double v)
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
     return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
 }
+template <int CTRL>
+__device__ inline float dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
 
 // The group's bounding box decides a node for every body when the opening
 // test comes out the same anywhere in the box by this relative margin (the
@@ -98,7 +103,7 @@ constexpr int kPairCap = 448;  // pairs per batch
 // FP64 atomics. A sparse item becomes (item, body) pairs, one per lane, whose
 // target-side terms go to per-body and whose source-side terms go to per-item
 // FP64 sums in LDS, flushed to the adjoints once per batch.
-template <bool PEPS, int GB>
+template <bool PEPS, int GB, bool F32>
 __global__ __launch_bounds__(64) void k_vjp_walk(
     const Body *__restrict__ body, const double *__restrict__ beps2,
     const NodeInfo *__restrict__ ninfo, const NodeMom *__restrict__ nmom,
@@ -112,6 +117,9 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
     constexpr int LPB = 64 / GB;      // lanes per body
     constexpr uint64_t kBodyMask = GB == 64 ? ~0ull : ((1ull << GB) - 1ull);
     constexpr int kSparse = GB / 4;   // items reaching at most this many bodies go to pair mode
+    // FP32C: every term in FP32 from the FP64 offset rounded once, the terms
+    // of a step summed in FP32 and added into FP64 sums and adjoints
+    using VT = typename std::conditional<F32, float, double>::type;
     __shared__ int32_t st_c0[kStack];
     __shared__ uint8_t st_n[kStack];
     __shared__ uint64_t st_mask[kStack];
@@ -174,6 +182,7 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
     const int perm = ((lane & 1) << 2) | (lane & 2) | (GB == 64 ? lane >> 5 : (lane >> 3) & 1);
 
     double gx = 0.0, gy = 0.0, gz = 0.0;  // target-side gradient of this lane's body
+    const VT lxv = (VT)lx, lyv = (VT)ly, lzv = (VT)lz;
     int sp = 1, dq_head = 0, dq_tail = 0;
     uint32_t queued = 0, consumed = 0;
     if (lane == 0) {
@@ -186,24 +195,45 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
 
     // One softened term of source (x, y, z, m, e2) on a target at (bx, by, bz)
     // with softening eb and upstream (ux, uy, uz): the target-side gradient is
-    // minus the first three source-side components.
-    auto term = [&](const ItemV &it, double bx, double by, double bz, double eb, double ux,
-                    double uy, double uz, bool on, double out[5]) {
-        const double dx = it.x - bx, dy = it.y - by, dz = it.z - bz;
-        const double e2 = PEPS ? 0.5 * (eb + it.e2) : eps0sq;
-        const double r2 = dx * dx + dy * dy + dz * dz + e2;
-        out[0] = out[1] = out[2] = out[3] = out[4] = 0.0;
-        if (on && positive_normal(r2)) {
-            const double rinv = rsqrt_f64(r2), inv2 = rinv * rinv;
-            const double inv3 = inv2 * rinv;
-            const double inv5 = inv3 * inv2;
-            const double ld = ux * dx + uy * dy + uz * dz;
-            const double gms = G * it.m;
-            out[0] = gms * (ux * inv3 - 3.0 * dx * ld * inv5);
-            out[1] = gms * (uy * inv3 - 3.0 * dy * ld * inv5);
-            out[2] = gms * (uz * inv3 - 3.0 * dz * ld * inv5);
-            out[3] = G * ld * inv3;
-            out[4] = -1.5 * gms * ld * inv5;
+    // minus the first three source-side components. In FP32C the offset is the
+    // FP64 difference rounded once and the rest of the term is FP32; the term
+    // counts when its r^2 is a positive normal number of the precision used.
+    auto term = [&](const ItemV &it, double bx, double by, double bz, double eb, VT ux, VT uy,
+                    VT uz, bool on, VT out[5]) {
+        out[0] = out[1] = out[2] = out[3] = out[4] = VT(0);
+        if constexpr (F32) {
+            const float dx = (float)(it.x - bx), dy = (float)(it.y - by), dz = (float)(it.z - bz);
+            const float e2 = PEPS ? (float)(0.5 * (eb + it.e2)) : (float)eps0sq;
+            const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, e2)));
+            if (on && positive_normal_f(r2)) {
+                const float rinv = __builtin_amdgcn_rsqf(r2), inv2 = rinv * rinv;
+                const float inv3 = inv2 * rinv;
+                const float inv5 = inv3 * inv2;
+                const float ld = ux * dx + uy * dy + uz * dz;
+                const float gms = (float)(G * it.m);
+                const float c = 3.0f * ld * inv5;
+                out[0] = gms * (ux * inv3 - dx * c);
+                out[1] = gms * (uy * inv3 - dy * c);
+                out[2] = gms * (uz * inv3 - dz * c);
+                out[3] = (float)G * ld * inv3;
+                out[4] = -1.5f * gms * ld * inv5;
+            }
+        } else {
+            const double dx = it.x - bx, dy = it.y - by, dz = it.z - bz;
+            const double e2 = PEPS ? 0.5 * (eb + it.e2) : eps0sq;
+            const double r2 = dx * dx + dy * dy + dz * dz + e2;
+            if (on && positive_normal(r2)) {
+                const double rinv = rsqrt_f64(r2), inv2 = rinv * rinv;
+                const double inv3 = inv2 * rinv;
+                const double inv5 = inv3 * inv2;
+                const double ld = ux * dx + uy * dy + uz * dz;
+                const double gms = G * it.m;
+                out[0] = gms * (ux * inv3 - 3.0 * dx * ld * inv5);
+                out[1] = gms * (uy * inv3 - 3.0 * dy * ld * inv5);
+                out[2] = gms * (uz * inv3 - 3.0 * dz * ld * inv5);
+                out[3] = G * ld * inv3;
+                out[4] = -1.5 * gms * ld * inv5;
+            }
         }
     };
     // adds a source-side sum to the item's adjoints (e2 = (eps_B^2 + <eps^2>_N) / 2)
@@ -290,19 +320,31 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
         // dense items, eight per share of lanes per step
 #pragma unroll 1
         for (int j0 = 0; j0 < nd; j0 += 8 * LPB) {
-            double v[8][NC];
+            VT v[8][NC];
+            VT sx = VT(0), sy = VT(0), sz = VT(0);  // FP32C: this step's target-side terms
 #pragma unroll
             for (int t = 0; t < 8; t++) {
                 const int j = j0 + 8 * sub + (t ^ perm);
                 const ItemV it = items[j < nd ? j : j0];
                 const bool on = j < nd && ((it.mask >> bq) & 1ull);
-                double o[5];
-                term(it, me.x, me.y, me.z, eb2, lx, ly, lz, on, o);
-                gx -= o[0];
-                gy -= o[1];
-                gz -= o[2];
+                VT o[5];
+                term(it, me.x, me.y, me.z, eb2, lxv, lyv, lzv, on, o);
+                if constexpr (F32) {
+                    sx -= o[0];
+                    sy -= o[1];
+                    sz -= o[2];
+                } else {
+                    gx -= o[0];
+                    gy -= o[1];
+                    gz -= o[2];
+                }
 #pragma unroll
                 for (int q = 0; q < NC; q++) v[t][q] = o[q];
+            }
+            if constexpr (F32) {
+                gx += (double)sx;
+                gy += (double)sy;
+                gz += (double)sz;
             }
 #pragma unroll
             for (int t = 0; t < 4; t++)
@@ -314,7 +356,7 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
                 for (int q = 0; q < NC; q++) v[t][q] += dpp<kDppXor2>(v[t + 2][q]);
 #pragma unroll
             for (int q = 0; q < NC; q++) {
-                double w;
+                VT w;
                 if constexpr (GB == 64) {
                     w = v[0][q] + __shfl_xor(v[1][q], 32);
                     w += dpp<kDppRor4>(w);
@@ -334,7 +376,7 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
             if (lead && j < nd) {
                 double o[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-                for (int q = 0; q < NC; q++) o[q] = v[0][q];
+                for (int q = 0; q < NC; q++) o[q] = (double)v[0][q];
                 flush(items[j].src, o);
             }
         }
@@ -348,18 +390,18 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
             const int k = (int)(r >> 6), b = (int)(r & 63u);
             const double bx = __shfl(me.x, b), by = __shfl(me.y, b), bz = __shfl(me.z, b);
             const double eb = PEPS ? __shfl(eb2, b) : 0.0;
-            const double ux = __shfl(lx, b), uy = __shfl(ly, b), uz = __shfl(lz, b);
+            const VT ux = __shfl(lxv, b), uy = __shfl(lyv, b), uz = __shfl(lzv, b);
             const ItemV it = items[k];
-            double o[5];
+            VT o[5];
             term(it, bx, by, bz, eb, ux, uy, uz, on, o);
             if (on) {
 #pragma unroll
                 for (int q = 0; q < 3; q++)
-                    __hip_atomic_fetch_add(&tacc[3 * b + q], -o[q], __ATOMIC_RELAXED,
+                    __hip_atomic_fetch_add(&tacc[3 * b + q], -(double)o[q], __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
                 for (int q = 0; q < NC; q++)
-                    __hip_atomic_fetch_add(&sacc[5 * k + q], o[q], __ATOMIC_RELAXED,
+                    __hip_atomic_fetch_add(&sacc[5 * k + q], (double)o[q], __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
@@ -799,9 +841,16 @@ hipError_t launch_tree_vjp(const Workspace &w, const AdjointWork &aw, hipStream_
     const int ngroups = (int)((p.n + gb - 1) / gb);
     const int per_xcd = (ngroups + 7) / 8;
     auto walk = [&](auto peps, auto gbc) {
-        k_vjp_walk<decltype(peps)::value, decltype(gbc)::value><<<8 * per_xcd, 64, 0, s>>>(
-            w.body, w.beps2, w.ninfo, w.nmom, w.neps2, w.idx[0], w.box, p.n, ngroups, per_xcd,
-            p.th2, p.eps0sq, p.G, lambda, aw.gt, aw.badj, aw.nadj);
+        if (p.precision == BH_FP32C)
+            k_vjp_walk<decltype(peps)::value, decltype(gbc)::value, true>
+                <<<8 * per_xcd, 64, 0, s>>>(w.body, w.beps2, w.ninfo, w.nmom, w.neps2, w.idx[0],
+                                            w.box, p.n, ngroups, per_xcd, p.th2, p.eps0sq, p.G,
+                                            lambda, aw.gt, aw.badj, aw.nadj);
+        else
+            k_vjp_walk<decltype(peps)::value, decltype(gbc)::value, false>
+                <<<8 * per_xcd, 64, 0, s>>>(w.body, w.beps2, w.ninfo, w.nmom, w.neps2, w.idx[0],
+                                            w.box, p.n, ngroups, per_xcd, p.th2, p.eps0sq, p.G,
+                                            lambda, aw.gt, aw.badj, aw.nadj);
     };
     using T = std::true_type;
     using F = std::false_type;

@@ -235,7 +235,7 @@ bh_status vjp(bh_ctx *c, const double *pos, const double *mass, double softening
         p.phi = nullptr;
         p.counts = nullptr;
         p.per_body_eps = eps != nullptr;
-        p.precision = BH_FP64;
+        p.precision = c->cfg.precision;  // FP32C terms in an FP32C context
         p.group = vjp_group(c, n);
         BHX_HIP(c, bhx::launch_tree_vjp(c->w, c->aw, c->stream, p, lambda, g_pos, g_mass));
     } else {

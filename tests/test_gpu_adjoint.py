@@ -1,9 +1,11 @@
 """GPU force VJPs and rollout gradients against the FP64 oracle.
 
-Bars: the GPU VJPs are FP64 and differ from the oracle's only in summation
-order (the tree form also adds source terms with atomics in scheduling order),
-so each gradient matches to 1e-10 of its largest component; counts and tree
-decisions are shared with the forward path, which its own tests pin exactly.
+Bars: the FP64 VJPs differ from the oracle's only in summation order (the
+tree form also adds source terms with atomics in scheduling order), so each
+gradient matches to 1e-10 of its largest component; the FP32C tree VJP is held
+to 64u of the oracle's error scale of each output (derived below); counts and
+tree decisions are shared with the forward path, which its own tests pin
+exactly.
 """
 import numpy as np
 import pytest
@@ -73,6 +75,37 @@ def test_vjp_parity(api, name, n, seed, per_body, theta, leaf, group):
                            eps=None if eps is None else _dev(eps))
     _close(gx.cpu().numpy(), gx_ref, 1e-10, f"{name} g_pos")
     _close(gm.cpu().numpy(), gm_ref, 1e-10, f"{name} g_mass")
+
+
+# FP32C VJP bar: each term's offset is the FP64 difference rounded once
+# (u = 2^-24 of each component) and the rest of the term is FP32, about ten
+# roundings: at most ~12u of the magnitudes of its parts (the oracle's error
+# scale, tree_vjp_abs); lambda is rounded to FP32 (u); the target side sums 8
+# terms in FP32 (7u) and the source side sums a step's terms over the group's
+# lanes in a pairwise tree (6 levels, 6u) before FP64 atomics; the hand-down
+# to members is FP64. Together under ~26u of the scale; the bar is 64u.
+FP32C_VJP_TOL = 64 * 2.0 ** -24
+
+VJP32_CASES = [c for c in VJP_CASES if c[4] >= 0]
+
+
+@pytest.mark.parametrize("name,n,seed,per_body,theta,leaf,group",
+                         [pytest.param(*c, g, id=f"{c[0]}-g{g}") for c in VJP32_CASES
+                          for g in (0, 32, 64)])
+def test_vjp_parity_fp32c(api, name, n, seed, per_body, theta, leaf, group):
+    """The tree VJP in an FP32C context against the FP64 oracle, element by
+    element, within 64u of the oracle's error scale of each output."""
+    x, m, eps, lam = _case(n, seed, per_body)
+    soft = 0.0 if per_body else 1e-3
+    gx_ref, gm_ref = oracle.tree_vjp(x, m, lam, theta, softening=soft, eps=eps, leaf=leaf, G=0.9)
+    ax, am = oracle.tree_vjp_abs(x, m, lam, theta, softening=soft, eps=eps, leaf=leaf, G=0.9)
+    ctx = api.Context(n, leaf_size=leaf, precision="fp32c", G=0.9, adjoint=True, walk_group=group)
+    gx, gm = ctx.accel_vjp(_dev(x), _dev(m), _dev(lam), theta=theta, softening=soft,
+                           eps=None if eps is None else _dev(eps))
+    ex = np.abs(gx.cpu().numpy() - gx_ref)
+    em = np.abs(gm.cpu().numpy() - gm_ref)
+    assert np.all(ex <= FP32C_VJP_TOL * ax + 1e-300), f"{name} g_pos: worst {(ex / ax).max() / 2**-24:.1f}u"
+    assert np.all(em <= FP32C_VJP_TOL * am + 1e-300), f"{name} g_mass: worst {(em / am).max() / 2**-24:.1f}u"
 
 
 def test_vjp_accumulates_and_invariants(api):
