@@ -205,12 +205,13 @@ inline int64_t node_capacity(int64_t n, int leaf, int scenes = 1)
     return (int64_t)(scenes > 1 ? scenes : 1) + (int64_t)kMaxLevel * per_level;
 }
 
-// Launchers (tree.hip). All enqueue on `s` and never synchronise.
-// all_levels: launch every tree level instead of stopping one level below the
-// previous build's depth (the depth hint is a host read, frozen in a captured
-// graph; with all levels, a replay builds any tree depth at full width).
+// Launchers (tree.hip). All enqueue on `s` and never synchronise. The build
+// launches one kernel per tree level down to one below the depth the
+// previous build reported (a host read of pinned memory, frozen in a
+// captured graph) and handles deeper levels in one block: any depth is
+// built correctly, a deeper one more slowly.
 hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, const double *pos,
-                        const double *mass, const double *eps, int leaf, bool all_levels = false);
+                        const double *mass, const double *eps, int leaf);
 // scene_of[i] = scene of body i, from device offsets of n_scenes scenes
 hipError_t launch_scene_of(hipStream_t s, const int64_t *offsets, int n_scenes,
                            uint16_t *scene_of);

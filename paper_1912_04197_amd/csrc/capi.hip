@@ -48,6 +48,7 @@ struct bh_ctx {
     hipGraphExec_t gexec = nullptr;
     std::vector<double> gkey;
     bool capturing = false;
+    int gdepth = -1;  // depth hint the captured step's build was launched with
 };
 
 namespace {
@@ -182,8 +183,7 @@ bh_status force_tree(bh_ctx *c, const bhx::Layout &lay, const double *pos, const
     const int64_t n = lay.n;
     bh_status st = record(c, 0);
     if (st) return st;
-    BHX_HIP(c, bhx::launch_build(w, c->stream, lay, pos, mass, eps, c->cfg.leaf_size,
-                                 c->capturing));
+    BHX_HIP(c, bhx::launch_build(w, c->stream, lay, pos, mass, eps, c->cfg.leaf_size));
     st = record(c, 1);
     if (st) return st;
     c->tree_n = n;
@@ -282,6 +282,17 @@ bh_status set_layout(bh_ctx *c, int32_t n_scenes, const int64_t *offsets)
             const int64_t e = std::min(offsets[k + 1], f + bhx::kBoxChunk);
             c->h_chunks.insert(c->h_chunks.end(), {k, (int32_t)f, (int32_t)e});
         }
+    }
+    // Walk groups in the order the blocks are dealt, costliest first (the
+    // scenes by decreasing size: a body of a larger scene walks a deeper tree
+    // and interacts more), each scene's groups in Morton order, so that the
+    // cheap groups of small scenes fill the end of the launch.
+    std::vector<int32_t> by_size((size_t)n_scenes);
+    for (int32_t k = 0; k < n_scenes; k++) by_size[(size_t)k] = k;
+    std::stable_sort(by_size.begin(), by_size.end(), [&](int32_t a, int32_t b) {
+        return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
+    });
+    for (int32_t k : by_size) {
         for (int64_t f = offsets[k]; f < offsets[k + 1]; f += gb) {
             const int64_t e = std::min(offsets[k + 1], f + gb);
             c->h_groups.insert(c->h_groups.end(), {(int32_t)f, (int32_t)(e - f), k});
@@ -350,7 +361,13 @@ bh_status run_steps(bh_ctx *c, const bhx::Layout &lay, double *pos, double *vel,
                                (double)lay.n_scenes, (double)lay.n_groups, (double)lay.n_chunks,
                                (double)(lay.groups ? c->layout_gen : 0), softening, theta, dt};
     hipStream_t caller = c->stream;
-    if (!c->gexec || key != c->gkey) {
+    // The build launches one kernel per tree level down to one below the
+    // depth its previous run reported (pinned memory the device writes), and
+    // handles any deeper level in one block: a captured step keeps the hint
+    // it was captured with, so it is captured again once a replayed build
+    // reports a deeper tree (or the first capture had no hint yet).
+    const int depth_now = c->w.depth_host ? *(const volatile int32_t *)c->w.depth_host : -1;
+    if (!c->gexec || key != c->gkey || depth_now > c->gdepth) {
         if (c->gexec) {
             (void)hipGraphExecDestroy(c->gexec);
             c->gexec = nullptr;
@@ -362,6 +379,7 @@ bh_status run_steps(bh_ctx *c, const bhx::Layout &lay, double *pos, double *vel,
         BHX_HIP(c, hipStreamBeginCapture(c->cstream, hipStreamCaptureModeThreadLocal));
         c->stream = c->cstream;
         c->capturing = true;
+        c->gdepth = depth_now;
         bh_status s = kdk_step(c, lay, pos, vel, mass, softening, eps, theta, dt, acc);
         c->capturing = false;
         c->stream = caller;

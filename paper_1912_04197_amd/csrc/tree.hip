@@ -929,7 +929,7 @@ hipError_t launch_scene_of(hipStream_t s, const int64_t *offsets, int n_scenes,
 }
 
 hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, const double *pos,
-                        const double *mass, const double *eps, int leaf, bool all_levels)
+                        const double *mass, const double *eps, int leaf)
 {
     const int64_t n = lay.n;
     const int ns = lay.n_scenes;
@@ -975,7 +975,7 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
     // levels in one block was measured slower: its binary searches over all
     // bodies run four passes deep there.) The split only affects speed.
     int deep = kMaxLevel;
-    if (w.depth_host && !all_levels) {
+    if (w.depth_host) {
         const int prev = *(const volatile int32_t *)w.depth_host;
         if (prev >= 0 && prev + 1 < deep) deep = prev + 1;
     }

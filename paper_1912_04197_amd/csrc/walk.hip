@@ -170,9 +170,12 @@ __global__ __launch_bounds__(64) void k_walk(
     uint16_t *const rec = sh.ev.rec;
     QT *const qbuf = sh.ev.quad;
 
-    // Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous
-    // (so spatially compact) range of groups to share its L2.
-    const int grp = (int)(blockIdx.x & 7u) * per_xcd + (int)(blockIdx.x >> 3);
+    // Blocks are dealt to the 8 XCDs round-robin. One scene: give each XCD a
+    // contiguous (so spatially compact) range of groups to share its L2. A
+    // group table (several scenes) is already in dealing order, costliest
+    // first (per_xcd = 0): block b takes group b.
+    const int grp = per_xcd ? (int)(blockIdx.x & 7u) * per_xcd + (int)(blockIdx.x >> 3)
+                            : (int)blockIdx.x;
     if (grp >= ngroups) return;
 
     const int lane = threadIdx.x;
@@ -636,9 +639,9 @@ template <int PREC, bool PEPS, bool PHI, bool CNT, int GB, bool QUAD>
 hipError_t launch_t(const Workspace &w, hipStream_t s, const WalkParams &p)
 {
     const int ngroups = p.groups ? p.n_groups : (int)((p.n + GB - 1) / GB);
-    const int per_xcd = (ngroups + 7) / 8;
+    const int per_xcd = p.groups ? 0 : (ngroups + 7) / 8;
     if (ngroups == 0) return hipSuccess;
-    k_walk<PREC, PEPS, PHI, CNT, GB, QUAD><<<8 * per_xcd, 64, 0, s>>>(
+    k_walk<PREC, PEPS, PHI, CNT, GB, QUAD><<<p.groups ? ngroups : 8 * per_xcd, 64, 0, s>>>(
         w.body, w.beps2, w.ninfo, w.nmom, w.neps2, p.nquad, w.idx[0], w.box, p.groups, p.n, ngroups,
         per_xcd, p.th2, p.eps0sq, p.G, p.acc, p.phi, p.counts);
     return hipGetLastError();

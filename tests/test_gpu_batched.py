@@ -132,6 +132,33 @@ def test_step_leapfrog_graph_replays(api):
         assert torch.equal(st[0][1], st[1][1]) and torch.equal(st[0][2], st[1][2]), rep
 
 
+def test_step_graph_follows_tree_depth(api):
+    """A step graph is captured with the tree depth of its first build; the
+    bodies are then moved in place (same pointers) into a much deeper tree:
+    the replayed steps build it through the deep-level block, the next call
+    captures again, and every step equals the eager one bit for bit."""
+    n = 20000
+    s = ics.uniform_ball(n, seed=31)
+    deep = s.pos.copy()
+    deep[: n // 2] = 1e-6 * deep[: n // 2] + 0.3  # half the bodies in a tiny cluster
+    eager = api.Context(n, leaf_size=4, precision="fp32c")
+    graph = api.Context(n, leaf_size=4, precision="fp32c", graph=True)
+    st = []
+    for ctx in (eager, graph):
+        p, v, m = _dev(s.pos), _dev(s.vel), _dev(s.mass)
+        st.append((ctx, p, v, m, ctx.compute_accel(p, m, 0.5, softening=1e-3)))
+    for rep in range(4):
+        if rep == 2:
+            for ctx, p, v, m, a in st:
+                p.copy_(_dev(deep))
+                a.copy_(ctx.compute_accel(p, m, 0.5, softening=1e-3))
+        for ctx, p, v, m, a in st:
+            ctx.step_leapfrog(p, v, m, a, 1e-4, 3, theta=0.5, softening=1e-3)
+        torch.cuda.synchronize()
+        assert torch.equal(st[0][1], st[1][1]) and torch.equal(st[0][4], st[1][4]), rep
+    assert eager.tree().depth >= 15
+
+
 @pytest.mark.parametrize("leaf,group", [(16, 0), (4, 64)])
 def test_batched_256_scene_workload(api, leaf, group):
     """The batched workload at full size: 256 uniform balls, N log-uniform in
