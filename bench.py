@@ -585,6 +585,83 @@ def bench_leaf(args, leaf, pos0, vel0, mass, eps):
             "walk_roofline_frac": round(ach / PEAK_FP32_TFLOPS, 4)}
 
 
+def cpu_oracle_beside(args, scene, result):
+    """The FP64 CPU oracle timed beside the GPU on the other workloads, each on a
+    bounded sample (what was timed is stated per entry): a one-thread figure
+    for the headline walk, the Plummer sphere per theta, sampled batched
+    scenes and the rollout gradient at 256 and 4096 bodies."""
+    import numpy as np
+
+    import oracle
+    from paper_1912_04197_amd import ics
+
+    out = {"threads": oracle.num_threads()}
+    n, theta, leaf = args.n, args.theta, args.leaf
+    rng = np.random.default_rng(7)
+
+    def timed(fn):
+        t = time.perf_counter()
+        fn()
+        return time.perf_counter() - t
+
+    # headline walk on 65536 sampled targets, all threads and one thread
+    targets = np.sort(rng.choice(n, min(n, 65536), replace=False))
+    tree = oracle.Tree(scene.pos, scene.mass, scene.eps, leaf=leaf)
+    t_all = timed(lambda: tree.accel(theta, targets=targets))
+    nthr = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        t_one = timed(lambda: tree.accel(theta, targets=targets))
+    finally:
+        oracle.set_num_threads(nthr)
+    scale = n / len(targets)
+    out["headline_walk"] = {
+        "sample": f"tree walk of {len(targets)} sampled bodies of the 2^20 rubble pile (leaf {leaf}), "
+                  "built tree excluded; full-walk seconds extrapolated x N / sample",
+        "seconds_all_threads": round(t_all, 3), "seconds_one_thread": round(t_one, 3),
+        "full_walk_s_extrapolated_all_threads": round(t_all * scale, 2),
+        "full_walk_s_extrapolated_one_thread": round(t_one * scale, 2),
+        "gpu_walk_ms": result.get("walk_ms"),
+    }
+    # Plummer sphere (131072, leaf 16): the step-0 tree force per theta, full N;
+    # the direct sum on 1024 sampled targets
+    pl = ics.plummer(131072, seed=22)
+    pl_out = {"sample": "oracle tree force at step 0 on all 131072 bodies per theta (leaf 16, "
+                        "eps 1e-3); direct sum on 1024 sampled targets, extrapolated x N / 1024"}
+    gpu_pl = result.get("plummer", {})
+    for th in (0.3, 0.5, 0.7):
+        t = timed(lambda: oracle.bh(pl.pos, pl.mass, th, softening=1e-3, leaf=16))
+        g = gpu_pl.get(f"theta_{th}", {}).get("ms_per_step")
+        pl_out[f"theta_{th}"] = {"oracle_s": round(t, 3), "gpu_step_ms": g,
+                                 "gpu_speedup": round(t * 1e3 / g, 1) if g else None}
+    tg = np.sort(rng.choice(131072, 1024, replace=False))
+    t = timed(lambda: oracle.direct(pl.pos, pl.mass, softening=1e-3, targets=tg))
+    pl_out["direct_s_extrapolated"] = round(t * 131072 / 1024, 2)
+    out["plummer_131072"] = pl_out
+    # batched: 8 of the 256 scenes, the tree force at the tuned leaf
+    scenes = ics.batched_scenes(256, seed=44)
+    pick = rng.choice(256, 8, replace=False)
+    tuned = result.get("batched", {}).get("autotune", {}).get("leaf", 4)
+    t = sum(timed(lambda sc=scenes[k]: oracle.bh(sc.pos, sc.mass, 0.5, softening=1e-3, leaf=tuned))
+            for k in pick)
+    nb = sum(scenes[k].n for k in pick)
+    out["batched_8_scenes"] = {"sample": f"oracle tree force of 8 sampled scenes ({nb} bodies, "
+                                         f"leaf {tuned})", "oracle_s": round(t, 3),
+                               "oracle_us_per_body": round(t * 1e6 / nb, 3)}
+    # rollout gradient (tree theta 0.5, leaf 16) at 256 and 4096 bodies, 20 steps
+    ro = {"sample": "oracle rollout gradient (forward KDK steps, then one tree VJP per step), "
+                    "20 steps of dt 1e-3, eps 1e-3, theta 0.5, leaf 16"}
+    for nn in (256, 4096):
+        b = ics.uniform_ball(nn, seed=55)
+        xb = ics.perturbed_target(b.pos, seed=56) - b.pos
+        t = timed(lambda: oracle.rollout_grad(b.pos, b.vel, b.mass, 1e-3, 20, xb, np.zeros_like(xb),
+                                              softening=1e-3, theta=0.5, leaf=16))
+        ro[f"n_{nn}_ms_per_step"] = round(t * 1e3 / 20, 3)
+    out["rollout_gradient"] = ro
+    log(f"cpu oracle beside: one-thread walk {t_one:.2f} s on {len(targets)} bodies")
+    return out
+
+
 def direct_only(args):
     """One FP32C and one FP64 direct N^2 evaluation on the headline bodies, for
     profiler runs of the direct kernel."""
@@ -871,6 +948,7 @@ def main():
             "gpu_speedup": round(step_s * 1e3 / ms_step, 1),
         }
         log(f"cpu oracle {step_s:.2f} s per step on {oracle.num_threads()} threads")
+        result["cpu_oracle_beside"] = cpu_oracle_beside(args, scene, result)
 
     print(json.dumps(result), flush=True)
 

@@ -130,6 +130,14 @@ def num_threads() -> int:
     return int(_load().orc_num_threads())
 
 
+def set_num_threads(k: int) -> None:
+    """Threads for the oracle's later calls (timing a one-thread baseline)."""
+    lib = _load()
+    lib.orc_set_num_threads.argtypes = [C.c_int]
+    lib.orc_set_num_threads.restype = None
+    lib.orc_set_num_threads(int(k))
+
+
 def _targets(n, targets):
     if targets is None:
         return None, n

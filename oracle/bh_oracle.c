@@ -71,6 +71,15 @@ int orc_num_threads(void)
 #endif
 }
 
+void orc_set_num_threads(int k)
+{
+#ifdef _OPENMP
+    if (k >= 1) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
+
 static int check_bodies(int64_t n, const double *pos, const double *mass, const double *eps,
                         double eps0)
 {

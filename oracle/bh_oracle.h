@@ -150,6 +150,8 @@ int orc_rollout_grad(int64_t n, const double *pos0, const double *vel0, const do
 
 /* Number of OpenMP threads the oracle uses. */
 int orc_num_threads(void);
+/* Sets the number of OpenMP threads for the oracle's later calls (k >= 1). */
+void orc_set_num_threads(int k);
 
 #ifdef __cplusplus
 }
