@@ -28,16 +28,16 @@
 #include <type_traits>
 
 #include "bhx_impl.h"
+#include "walk_traverse.h"
 
 namespace bhx {
 namespace {
 
+using walkx::kPop;
+using walkx::PopCom;
+using walkx::PopData;
 constexpr int kStack = 320;
-constexpr int kReserve = 150;
-constexpr int kRanges = 8;
-constexpr int kPop = 8 * kRanges;
 constexpr int kRing = 128;
-static_assert((kRing & (kRing - 1)) == 0, "ring indices wrap by masking");
 constexpr int kBatch = 64;
 
 struct alignas(16) ItemV {  // staged source
@@ -48,24 +48,6 @@ struct alignas(16) ItemV {  // staged source
     int32_t pad0;
     int64_t pad1;
 };
-struct alignas(16) PopCom {
-    double x, y, z, s2;
-};
-struct alignas(16) PopData {
-    uint64_t mask;
-    int32_t node, first, count, child0;
-    int32_t nch, pad;
-};
-
-__device__ inline bool accept_node(double cx, double cy, double cz, double bx, double by,
-                                   double bz, double s2, double th2)
-{
-#pragma clang fp contract(off)
-    double dx = cx - bx, dy = cy - by, dz = cz - bz;
-    double D2 = dx * dx + dy * dy + dz * dz;
-    return s2 < th2 * D2;
-}
-
 // Lane exchanges inside a row of 16 lanes (DPP): quad_perm [1,0,3,2] is
 // lane ^ 1, quad_perm [2,3,0,1] is lane ^ 2, row_ror:4 and row_ror:8 rotate
 // the row by 4 and 8 lanes.
@@ -84,10 +66,6 @@ __device__ inline float dpp(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
-// The group's bounding box decides a node for every body when the opening
-// test comes out the same anywhere in the box by this relative margin (the
-// per-body test's own rounding is below 1e-15).
-constexpr double kMacMargin = 1e-12;
 constexpr int kPairCap = 448;  // pairs per batch
 
 // badj: per sorted body {gX x, y, z, gm}; nadj: per node {gX x, y, z, gm, ge2}.
@@ -120,14 +98,11 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
     // FP32C: every term in FP32 from the FP64 offset rounded once, the terms
     // of a step summed in FP32 and added into FP64 sums and adjoints
     using VT = typename std::conditional<F32, float, double>::type;
-    __shared__ int32_t st_c0[kStack];
-    __shared__ uint8_t st_n[kStack];
-    __shared__ uint64_t st_mask[kStack];
-    __shared__ int32_t dq_a[kRing];
-    __shared__ int32_t dq_n[kRing];
-    __shared__ uint32_t dq_at[kRing];
-    __shared__ uint64_t dq_mask[kRing];
-    __shared__ double s2tab[kLevels];
+    __shared__ walkx::Lds<kStack, kRing> L;
+    int32_t *const dq_a = L.dq_a;
+    int32_t *const dq_n = L.dq_n;
+    uint32_t *const dq_at = L.dq_at;
+    uint64_t *const dq_mask = L.dq_mask;
     union Shared {
         struct {
             PopCom pc[kPop];
@@ -164,19 +139,9 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
         lz = lambda[3 * o + 2];
     }
     const uint64_t active = __ballot(valid) & kBodyMask;
-    if (lane < kLevels) s2tab[lane] = box[0].s2[lane];
-    double glo_x = valid ? me.x : __builtin_huge_val(), ghi_x = valid ? me.x : -__builtin_huge_val();
-    double glo_y = valid ? me.y : __builtin_huge_val(), ghi_y = valid ? me.y : -__builtin_huge_val();
-    double glo_z = valid ? me.z : __builtin_huge_val(), ghi_z = valid ? me.z : -__builtin_huge_val();
-#pragma unroll
-    for (int o = 1; o < GB; o <<= 1) {
-        glo_x = fmin(glo_x, __shfl_xor(glo_x, o));
-        ghi_x = fmax(ghi_x, __shfl_xor(ghi_x, o));
-        glo_y = fmin(glo_y, __shfl_xor(glo_y, o));
-        ghi_y = fmax(ghi_y, __shfl_xor(ghi_y, o));
-        glo_z = fmin(glo_z, __shfl_xor(glo_z, o));
-        ghi_z = fmax(ghi_z, __shfl_xor(ghi_z, o));
-    }
+    if (lane < kLevels) L.s2tab[lane] = box[0].s2[lane];
+    double glo[3], ghi[3];  // the group's bounding box
+    walkx::group_box<GB>(valid, me.x, me.y, me.z, glo, ghi);
     // This lane's order of its share's eight items of a dense step: slot bits
     // 2 and 1 follow lane bits 0 and 1, slot bit 0 lane bit 5 (GB = 64) or 3.
     const int perm = ((lane & 1) << 2) | (lane & 2) | (GB == 64 ? lane >> 5 : (lane >> 3) & 1);
@@ -186,9 +151,9 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
     int sp = 1, dq_head = 0, dq_tail = 0;
     uint32_t queued = 0, consumed = 0;
     if (lane == 0) {
-        st_c0[0] = 0;
-        st_n[0] = 1;
-        st_mask[0] = active;
+        L.st_c0[0] = 0;
+        L.st_n[0] = 1;
+        L.st_mask[0] = active;
     }
     for (int i = lane; i < 3 * GB; i += 64) tacc[i] = 0.0;
     __syncthreads();
@@ -430,107 +395,8 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
     };
 
     while (sp > 0) {
-        int cr = min(kRanges, sp);
-        const int room = (kStack - kReserve - sp) / 7;
-        if (cr > room) cr = room > 1 ? room : 1;
-        const int base = sp - cr;
-        int32_t k = -1;
-        uint64_t mk = 0;
-        {
-            const int r = lane >> 3, o = lane & 7;
-            if (r < cr) {
-                const int e = base + r;
-                if (o < st_n[e]) {
-                    k = st_c0[e] + o;
-                    mk = st_mask[e];
-                }
-            }
-        }
-        const uint64_t vb = __ballot(k >= 0);
-        const int nv = __popcll(vb);
-        if (k >= 0) {
-            const int slot = (int)lanes_below(vb);
-            const NodeInfo info = ninfo[k];
-            const NodeMom nm = nmom[k];
-            const bool leaf = info.child0 < 0;
-            pc[slot] = PopCom{nm.x, nm.y, nm.z,
-                              leaf ? __builtin_huge_val() : s2tab[node_level(info)]};
-            pd[slot] = PopData{mk, k, info.first, info.count, info.child0, node_nchild(info), 0};
-        }
-        sp = base;
-        __syncthreads();
-        // opening tests: the group-box bound first, then every body for the
-        // nodes it leaves open (as in the forward walk)
-        uint64_t accepted = 0;
-        bool mixed = false;
-        if (lane < nv) {
-            const PopCom q = pc[lane];
-            if (q.s2 < __builtin_huge_val()) {
-                const double ex = fmax(0.0, fmax(glo_x - q.x, q.x - ghi_x));
-                const double ey = fmax(0.0, fmax(glo_y - q.y, q.y - ghi_y));
-                const double ez = fmax(0.0, fmax(glo_z - q.z, q.z - ghi_z));
-                const double fx = fmax(fabs(q.x - glo_x), fabs(q.x - ghi_x));
-                const double fy = fmax(fabs(q.y - glo_y), fabs(q.y - ghi_y));
-                const double fz = fmax(fabs(q.z - glo_z), fabs(q.z - ghi_z));
-                const double dmin2 = ex * ex + ey * ey + ez * ez;
-                const double dmax2 = fx * fx + fy * fy + fz * fz;
-                if (q.s2 < th2 * dmin2 * (1.0 - kMacMargin))
-                    accepted = kBodyMask;
-                else if (!(q.s2 > th2 * dmax2 * (1.0 + kMacMargin)))
-                    mixed = true;
-            }
-        }
-        uint64_t mb = __ballot(mixed);
-#pragma unroll 1
-        while (mb) {
-            int ps[LPB];
-#pragma unroll
-            for (int t = 0; t < LPB; t++) {
-                ps[t] = mb ? __builtin_ctzll(mb) : -1;
-                mb &= mb - 1;
-            }
-            int p = ps[0];
-#pragma unroll
-            for (int t = 1; t < LPB; t++)
-                if (sub == t) p = ps[t];
-            const PopCom q = pc[p < 0 ? 0 : p];
-            const bool ok = p >= 0 && accept_node(q.x, q.y, q.z, me.x, me.y, me.z, q.s2, th2);
-            const uint64_t bal = __ballot(ok);
-#pragma unroll
-            for (int t = 0; t < LPB; t++) {
-                const uint64_t field = (bal >> (t * GB)) & kBodyMask;
-                if (lane == ps[t]) accepted = field;
-            }
-        }
-        const bool mine = lane < nv;
-        PopData my = PopData{0ull, 0, 0, 0, 0, 0, 0};
-        if (mine) my = pd[lane];
-        const bool leaf = mine && my.child0 < 0;
-        const uint64_t M = my.mask;
-        const uint64_t A = (mine && !leaf) ? (accepted & M) : 0ull;
-        const uint64_t O = (mine && !leaf) ? (M & ~accepted) : 0ull;
-        const uint64_t pushb = __ballot(O != 0);
-        if (O != 0) {
-            const int e = sp + (int)lanes_below(pushb);
-            st_c0[e] = my.child0;
-            st_n[e] = (uint8_t)my.nch;
-            st_mask[e] = O;
-        }
-        sp += __popcll(pushb);
-        const bool hasq = leaf || A != 0;
-        const uint64_t qb = __ballot(hasq);
-        const uint32_t nitems = leaf ? (uint32_t)my.count : (A != 0 ? 1u : 0u);
-        const uint32_t incl = wave_incl_scan(nitems);
-        if (hasq) {
-            const int d = (dq_tail + (int)lanes_below(qb)) & (kRing - 1);
-            dq_a[d] = leaf ? my.first : ~my.node;
-            dq_n[d] = (int32_t)nitems;
-            dq_at[d] = queued + incl - nitems;
-            dq_mask[d] = leaf ? M : A;
-        }
-        dq_tail += __popcll(qb);
-        queued += (uint32_t)__shfl(incl, 63);
-        __syncthreads();
+        walkx::traverse_round<GB>(L, pc, pd, sp, dq_tail, queued, ninfo, nmom, glo, ghi, me.x, me.y,
+                                  me.z, th2);
         while (queued - consumed >= (uint32_t)kBatch) evaluate(kBatch);
     }
     while (queued != consumed) evaluate((int)min(queued - consumed, (uint32_t)kBatch));

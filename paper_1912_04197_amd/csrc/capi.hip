@@ -364,10 +364,13 @@ bh_status run_steps(bh_ctx *c, const bhx::Layout &lay, double *pos, double *vel,
     // The build launches one kernel per tree level down to one below the
     // depth its previous run reported (pinned memory the device writes), and
     // handles any deeper level in one block: a captured step keeps the hint
-    // it was captured with, so it is captured again once a replayed build
-    // reports a deeper tree (or the first capture had no hint yet).
+    // it was captured with (levels 0..gdepth split by their own launches, so
+    // trees of depth up to gdepth + 1 at full width), so it is captured again
+    // once a replayed build reports a deeper tree than that, or when the first
+    // capture had no hint yet (it launched every level).
     const int depth_now = c->w.depth_host ? *(const volatile int32_t *)c->w.depth_host : -1;
-    if (!c->gexec || key != c->gkey || depth_now > c->gdepth) {
+    const bool deeper = depth_now >= 0 && (c->gdepth < 0 || depth_now > c->gdepth + 1);
+    if (!c->gexec || key != c->gkey || deeper) {
         if (c->gexec) {
             (void)hipGraphExecDestroy(c->gexec);
             c->gexec = nullptr;

@@ -45,23 +45,19 @@
 #include <type_traits>
 
 #include "bhx_impl.h"
+#include "walk_traverse.h"
 
 namespace bhx {
 namespace {
 
+using walkx::kPop;
+using walkx::PopCom;
+using walkx::PopData;
 constexpr int kStack = 256;    // LDS traversal stack of child ranges
-constexpr int kReserve = 150;  // a depth-first descent adds <= 7 ranges per level
-constexpr int kRanges = 8;     // ranges popped per round (<= 8 nodes each)
-constexpr int kPop = 8 * kRanges;
 constexpr int kRing = 128;     // interaction descriptors: <= 64 left over + 64 new
-static_assert((kRing & (kRing - 1)) == 0, "ring indices wrap by masking");
 constexpr int kBatch = 64;     // items staged per evaluation batch
 constexpr int kFlush = 16;     // FP32 partial sums span at most this many items per lane
 constexpr int kPairCap = 448;  // body pairs evaluated one per lane in one batch
-// Relative margin of the group-box opening test. The per-body test's D^2
-// and theta^2 D^2 carry a relative rounding error below 1e-15, so a box
-// bound that clears the threshold by this margin decides every body alike.
-constexpr double kMacMargin = 1e-12;
 // Items per unrolled step of the dense sweep, by group size.
 template <int GB>
 constexpr int kSweepUnroll = GB == 64 ? 4 : 1;
@@ -81,25 +77,6 @@ struct alignas(16) ItemD {  // FP64 staged source
     int32_t src, pad0;
     int64_t pad1;
 };
-struct alignas(16) PopCom {  // popped node as the opening test needs it
-    double x, y, z, s2;      // s2 = +inf for a leaf (never accepted)
-};
-struct alignas(16) PopData {  // popped node as the bookkeeping needs it
-    uint64_t mask;
-    int32_t node, first, count, child0;  // child0 < 0: leaf
-    int32_t nch, pad;
-};
-
-// The opening test, rounded exactly as written: accept iff s^2 < theta^2 D^2.
-__device__ inline bool accept_node(double cx, double cy, double cz, double bx, double by,
-                                   double bz, double s2, double th2)
-{
-#pragma clang fp contract(off)
-    double dx = cx - bx, dy = cy - by, dz = cz - bz;
-    double D2 = dx * dx + dy * dy + dz * dz;
-    return s2 < th2 * D2;
-}
-
 // Quadrupole term of an accepted node with traceless Q (xx, yy, zz, xy, xz,
 // yz), d = COM - x_B, inv5 = 1/r^5 and ri2 = 1/r^2 of the softened distance:
 // a += -Q d / r^5 + 5/2 (d.Q d) d / r^7 and phi += -(d.Q d) / (2 r^5), before
@@ -139,14 +116,11 @@ __global__ __launch_bounds__(64) void k_walk(
     // (item, body) pairs, one pair per lane, into per-body FP64 sums in LDS.
     constexpr int kSparse = GB / 6;
 
-    __shared__ int32_t st_c0[kStack];
-    __shared__ uint8_t st_n[kStack];
-    __shared__ uint64_t st_mask[kStack];
-    __shared__ int32_t dq_a[kRing];      // leaf: first body; node: ~node
-    __shared__ int32_t dq_n[kRing];      // items in the descriptor
-    __shared__ uint32_t dq_at[kRing];    // running item number of its first item
-    __shared__ uint64_t dq_mask[kRing];
-    __shared__ double s2tab[kLevels];
+    __shared__ walkx::Lds<kStack, kRing> L;
+    int32_t *const dq_a = L.dq_a;
+    int32_t *const dq_n = L.dq_n;
+    uint32_t *const dq_at = L.dq_at;
+    uint64_t *const dq_mask = L.dq_mask;
     // The popped nodes are read only before a round's evaluations and the
     // staged items only during them, so the two share one LDS region.
     union Shared {
@@ -197,19 +171,9 @@ __global__ __launch_bounds__(64) void k_walk(
     const double ebh = 0.5 * eb2;  // (eps_B^2 + e_j^2) / 2 = ebh + e_j^2 / 2 exactly
     const uint64_t active = __ballot(valid) & kBodyMask;
     // the group's bounding box (exact: min and max of its bodies' coordinates)
-    double glo_x = valid ? me.x : __builtin_huge_val(), ghi_x = valid ? me.x : -__builtin_huge_val();
-    double glo_y = valid ? me.y : __builtin_huge_val(), ghi_y = valid ? me.y : -__builtin_huge_val();
-    double glo_z = valid ? me.z : __builtin_huge_val(), ghi_z = valid ? me.z : -__builtin_huge_val();
-#pragma unroll
-    for (int o = 1; o < GB; o <<= 1) {
-        glo_x = fmin(glo_x, __shfl_xor(glo_x, o));
-        ghi_x = fmax(ghi_x, __shfl_xor(ghi_x, o));
-        glo_y = fmin(glo_y, __shfl_xor(glo_y, o));
-        ghi_y = fmax(ghi_y, __shfl_xor(ghi_y, o));
-        glo_z = fmin(glo_z, __shfl_xor(glo_z, o));
-        ghi_z = fmax(ghi_z, __shfl_xor(ghi_z, o));
-    }
-    if (lane < kLevels) s2tab[lane] = box[scene].s2[lane];
+    double glo[3], ghi[3];  // the group's bounding box
+    walkx::group_box<GB>(valid, me.x, me.y, me.z, glo, ghi);
+    if (lane < kLevels) L.s2tab[lane] = box[scene].s2[lane];
 
     const float e2hB = (float)(0.5 * eb2);
     const float eps0f = (float)eps0sq;
@@ -226,9 +190,9 @@ __global__ __launch_bounds__(64) void k_walk(
     uint32_t queued = 0;     // items ever queued
     uint32_t consumed = 0;   // items ever evaluated
     if (lane == 0) {
-        st_c0[0] = scene;  // the scene's root (node `scene`), as a range of one
-        st_n[0] = 1;
-        st_mask[0] = active;
+        L.st_c0[0] = scene;  // the scene's root (node `scene`), as a range of one
+        L.st_n[0] = 1;
+        L.st_mask[0] = active;
     }
     for (int i = lane; i < 3 * GB; i += 64) pacc[i] = 0.0;
     if (PHI && lane < GB) pphi[lane] = 0.0;
@@ -480,121 +444,8 @@ __global__ __launch_bounds__(64) void k_walk(
     };
 
     while (sp > 0) {
-        // Pop cr ranges: after expanding them (each popped range may push up
-        // to 8 ranges) at least kReserve entries stay free for a depth-first
-        // descent, which adds at most 7 ranges per level below.
-        int cr = min(kRanges, sp);
-        const int room = (kStack - kReserve - sp) / 7;
-        if (cr > room) cr = room > 1 ? room : 1;
-        const int base = sp - cr;
-        int32_t k = -1;
-        uint64_t mk = 0;
-        {
-            const int r = lane >> 3, o = lane & 7;
-            if (r < cr) {
-                const int e = base + r;
-                if (o < st_n[e]) {
-                    k = st_c0[e] + o;
-                    mk = st_mask[e];
-                }
-            }
-        }
-        // compact the popped nodes into slots 0..nv-1
-        const uint64_t vb = __ballot(k >= 0);
-        const int nv = __popcll(vb);
-        if (k >= 0) {
-            const int slot = (int)lanes_below(vb);
-            const NodeInfo info = ninfo[k];
-            const NodeMom nm = nmom[k];
-            const bool leaf = info.child0 < 0;
-            pc[slot] = PopCom{nm.x, nm.y, nm.z,
-                              leaf ? __builtin_huge_val() : s2tab[node_level(info)]};
-            pd[slot] = PopData{mk, k, info.first, info.count, info.child0, node_nchild(info), 0};
-        }
-        sp = base;
-        __syncthreads();
-
-        // Opening tests. Lane p first bounds popped node p's distance to the
-        // group's bounding box: when the test comes out the same for every
-        // point of the box, with a margin far above the rounding of the
-        // per-body test, that is the decision of every body. The other
-        // ("mixed") internal nodes are tested by every body, 64 / GB nodes per
-        // step, one per share of lanes; the group's GB-bit result for popped
-        // node p goes to lane p.
-        uint64_t accepted = 0;
-        bool mixed = false;
-        if (lane < nv) {
-            const PopCom q = pc[lane];
-            if (q.s2 < __builtin_huge_val()) {
-                const double ex = fmax(0.0, fmax(glo_x - q.x, q.x - ghi_x));
-                const double ey = fmax(0.0, fmax(glo_y - q.y, q.y - ghi_y));
-                const double ez = fmax(0.0, fmax(glo_z - q.z, q.z - ghi_z));
-                const double fx = fmax(fabs(q.x - glo_x), fabs(q.x - ghi_x));
-                const double fy = fmax(fabs(q.y - glo_y), fabs(q.y - ghi_y));
-                const double fz = fmax(fabs(q.z - glo_z), fabs(q.z - ghi_z));
-                const double dmin2 = ex * ex + ey * ey + ez * ez;
-                const double dmax2 = fx * fx + fy * fy + fz * fz;
-                if (q.s2 < th2 * dmin2 * (1.0 - kMacMargin))
-                    accepted = kBodyMask;
-                else if (!(q.s2 > th2 * dmax2 * (1.0 + kMacMargin)))
-                    mixed = true;
-            }
-        }
-        uint64_t mb = __ballot(mixed);
-#pragma unroll 1
-        while (mb) {
-            int ps[LPB];
-#pragma unroll
-            for (int t = 0; t < LPB; t++) {
-                ps[t] = mb ? __builtin_ctzll(mb) : -1;
-                mb &= mb - 1;
-            }
-            int p = ps[0];
-#pragma unroll
-            for (int t = 1; t < LPB; t++)
-                if (sub == t) p = ps[t];
-            const PopCom q = pc[p < 0 ? 0 : p];
-            const bool ok = p >= 0 && accept_node(q.x, q.y, q.z, me.x, me.y, me.z, q.s2, th2);
-            const uint64_t bal = __ballot(ok);
-#pragma unroll
-            for (int t = 0; t < LPB; t++) {
-                const uint64_t field = (bal >> (t * GB)) & kBodyMask;
-                if (lane == ps[t]) accepted = field;
-            }
-        }
-
-        // Bookkeeping for popped node `lane`, all lanes at once.
-        const bool mine = lane < nv;
-        PopData my = PopData{0ull, 0, 0, 0, 0, 0, 0};
-        if (mine) my = pd[lane];
-        const bool leaf = mine && my.child0 < 0;
-        const uint64_t M = my.mask;
-        const uint64_t A = (mine && !leaf) ? (accepted & M) : 0ull;
-        const uint64_t O = (mine && !leaf) ? (M & ~accepted) : 0ull;
-        // opened by the bodies in O: push the child range
-        const uint64_t pushb = __ballot(O != 0);
-        if (O != 0) {
-            const int e = sp + (int)lanes_below(pushb);
-            st_c0[e] = my.child0;
-            st_n[e] = my.nch;
-            st_mask[e] = O;
-        }
-        sp += __popcll(pushb);
-        // a leaf, or accepted by the bodies in A: queue a descriptor
-        const bool hasq = leaf || A != 0;
-        const uint64_t qb = __ballot(hasq);
-        const uint32_t nitems = leaf ? (uint32_t)my.count : (A != 0 ? 1u : 0u);
-        const uint32_t incl = wave_incl_scan(nitems);
-        if (hasq) {
-            const int d = (dq_tail + (int)lanes_below(qb)) & (kRing - 1);
-            dq_a[d] = leaf ? my.first : ~my.node;
-            dq_n[d] = (int32_t)nitems;
-            dq_at[d] = queued + incl - nitems;
-            dq_mask[d] = leaf ? M : A;
-        }
-        dq_tail += __popcll(qb);
-        queued += (uint32_t)__shfl(incl, 63);
-        __syncthreads();
+        walkx::traverse_round<GB>(L, pc, pd, sp, dq_tail, queued, ninfo, nmom, glo, ghi, me.x, me.y,
+                                  me.z, th2);
         while (queued - consumed >= (uint32_t)kBatch) evaluate(kBatch);
     }
     while (queued != consumed) evaluate((int)min(queued - consumed, (uint32_t)kBatch));
