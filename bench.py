@@ -703,6 +703,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
                     help="only the timed steps (for profiler runs)")
+    ap.add_argument("--markers", action="store_true",
+                    help="roctx ranges around the headline context's phases (for marker traces)")
     ap.add_argument("--direct-only", action="store_true",
                     help="only one FP32C and one FP64 direct evaluation (for profiler runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -747,7 +749,8 @@ def main():
             ctx.step_leapfrog(pos, vel, mass, acc, dt, 1, theta=theta, eps=eps, sync=False)
 
     # ---- headline: FP32C tree leapfrog
-    ctx = Context(n, leaf_size=leaf, precision="fp32c", timing=True, walk_group=args.walk_group)
+    ctx = Context(n, leaf_size=leaf, precision="fp32c", timing=True, walk_group=args.walk_group,
+                  markers=args.markers)
     pos, vel = pos0.clone(), vel0.clone()
     acc = ctx.compute_accel(pos, mass, theta, eps=eps)
     log(f"warmup {args.warmup} steps")

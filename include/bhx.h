@@ -75,7 +75,7 @@ enum {
                              and replay it nsteps times on a stream of the
                              context, ordered after and before the caller's
                              stream by events */
-    BH_FLAG_QUAD = 16u    /* beyond the paper's monopole nodes: keep each node's
+    BH_FLAG_QUAD = 16u,   /* beyond the paper's monopole nodes: keep each node's
                              traceless quadrupole Q = sum m (3 d d^T - |d|^2 I)
                              about its centre of mass, and add to every accepted
                              node's term G (-Q d / r^5 + 5/2 (d.Q d) d / r^7),
@@ -83,6 +83,13 @@ enum {
                              -G (d.Q d) / (2 r^5)). Leaf pairs and opening
                              decisions are unchanged. The force VJPs do not
                              support it (BH_E_STATE). */
+    BH_FLAG_MARKERS = 32u /* push roctx ranges ("bhx build", "bhx walk", "bhx
+                             direct", "bhx vjp", "bhx step", "bhx step
+                             (graph)") around the host-side enqueueing of each
+                             phase, for profiler timelines (rocprofv3
+                             --marker-trace); the roctx library is loaded at
+                             bh_create and the flag does nothing when it is
+                             absent */
 };
 
 typedef struct {

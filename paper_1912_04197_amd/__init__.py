@@ -9,7 +9,8 @@ N^2 sum, and a kick-drift-kick leapfrog. The kernels live in libbhx.so
 from __future__ import annotations
 
 __all__ = ["Context", "BHError", "load_library", "compute_accel", "compute_accel_direct",
-           "step_leapfrog", "autotune", "gravity_dt_bound", "probe_fma", "rollout"]
+           "step_leapfrog", "autotune", "gravity_dt_bound", "probe_fma", "rollout", "save_state",
+           "load_state"]
 
 
 def load_library():
@@ -21,7 +22,7 @@ def load_library():
 
 def __getattr__(name):
     if name in ("Context", "BHError", "compute_accel", "compute_accel_direct", "step_leapfrog",
-                "autotune", "gravity_dt_bound", "probe_fma"):
+                "autotune", "gravity_dt_bound", "probe_fma", "save_state", "load_state"):
         from . import api
 
         return getattr(api, name)

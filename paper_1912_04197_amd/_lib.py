@@ -18,6 +18,7 @@ BH_FLAG_TIMING = 2
 BH_FLAG_ADJOINT = 4
 BH_FLAG_GRAPH = 8
 BH_FLAG_QUAD = 16
+BH_FLAG_MARKERS = 32
 
 
 class bh_config(C.Structure):

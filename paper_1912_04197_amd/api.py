@@ -7,8 +7,11 @@ missing library or a non-GPU tensor raises.
 from __future__ import annotations
 
 import ctypes as C
+import json
+import os
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 from . import _lib as L
@@ -79,14 +82,14 @@ class Context:
     def __init__(self, n_max: int, leaf_size: int = 16, precision: str = "fp32c", G: float = 1.0,
                  counts: bool = False, timing: bool = False, walk_group: int = 0,
                  adjoint: bool = False, max_scenes: int = 1, graph: bool = False,
-                 quad: bool = False):
+                 quad: bool = False, markers: bool = False):
         self._lib = L.load()
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: libbhx runs on the GPU only")
         prec = {"fp64": L.BH_FP64, "fp32c": L.BH_FP32C}[precision]
         flags = ((L.BH_FLAG_COUNTS if counts else 0) | (L.BH_FLAG_TIMING if timing else 0)
                  | (L.BH_FLAG_ADJOINT if adjoint else 0) | (L.BH_FLAG_GRAPH if graph else 0)
-                 | (L.BH_FLAG_QUAD if quad else 0))
+                 | (L.BH_FLAG_QUAD if quad else 0) | (L.BH_FLAG_MARKERS if markers else 0))
         cfg = L.bh_config(int(n_max), int(leaf_size), prec, float(G), flags, int(walk_group),
                           int(max_scenes))
         self.device = torch.device("cuda", torch.cuda.current_device())
@@ -209,8 +212,6 @@ class Context:
 
     @staticmethod
     def _offsets(offsets):
-        import numpy as np
-
         o = np.ascontiguousarray(offsets, dtype=np.int64)
         return o, int(o.shape[0]) - 1
 
@@ -356,8 +357,6 @@ def autotune(offsets, pos, vel, mass, theta=0.5, dt=1e-3, softening=0.0, eps=Non
              precision="fp32c", G=1.0, steps=3, quad=False):
     """Fastest (leaf_size, walk_group, ms_per_step) for bh_batched_step on these
     scenes (see bh_autotune); the state tensors are not modified."""
-    import numpy as np
-
     lib = L.load()
     o = np.ascontiguousarray(offsets, dtype=np.int64)
     ns = int(o.shape[0]) - 1
@@ -471,3 +470,63 @@ def step_leapfrog(pos, vel, mass, acc, dt, nsteps, theta=0.5, softening=0.0, *, 
     the accelerations at pos on entry; theta < 0: direct sum)."""
     ctx = _context_for(pos.shape[0], leaf, precision, G)
     ctx.step_leapfrog(pos, vel, mass, acc, dt, nsteps, theta=theta, softening=softening, eps=eps)
+
+
+_STATE_FORMAT = "bhx-state-1"
+_STATE_ARRAYS = ("pos", "vel", "acc", "mass", "eps")
+
+
+def save_state(path, pos, vel, mass, acc=None, eps=None, **meta):
+    """Writes a checkpoint of a simulation to ``path`` (a .npz file).
+
+    pos, vel (n, 3) and mass (n,) FP64, and optionally acc (n, 3), the
+    accelerations at pos that a kick-drift-kick step takes on entry, and eps
+    (n,) per-body softening lengths, are stored bit for bit; ``meta`` holds any
+    JSON-serialisable scalars (time, step count, theta, dt ...). With acc
+    stored, steps resumed from the checkpoint equal the uninterrupted steps bit
+    for bit. The file is written to a temporary name and renamed, so an
+    interrupted save leaves the previous checkpoint intact.
+    """
+    arrays = {"pos": pos, "vel": vel, "mass": mass, "acc": acc, "eps": eps}
+    n = int(mass.shape[0])
+    shapes = {"pos": (n, 3), "vel": (n, 3), "acc": (n, 3), "mass": (n,), "eps": (n,)}
+    out = {}
+    for k, t in arrays.items():
+        if t is None:
+            continue
+        if t.dtype != torch.float64 or tuple(t.shape) != shapes[k]:
+            raise ValueError(f"{k} must be float64 of shape {shapes[k]}")
+        out[k] = t.detach().cpu().numpy()
+    out["format"] = np.array(_STATE_FORMAT)
+    out["meta"] = np.array(json.dumps(meta, sort_keys=True))
+    path = os.fspath(path)
+    if not path.endswith(".npz"):
+        path += ".npz"
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, **out)
+    os.replace(tmp, path)
+    return path
+
+
+def load_state(path, device=None):
+    """Reads a checkpoint written by save_state.
+
+    Returns (arrays, meta): arrays maps "pos", "vel", "mass" and, when stored,
+    "acc" and "eps" to FP64 tensors on ``device`` (default: the current GPU),
+    and meta is the dict of scalars given at save time. Nothing in the file is
+    unpickled.
+    """
+    if device is None:
+        device = torch.device("cuda", torch.cuda.current_device())
+    with np.load(path, allow_pickle=False) as z:
+        if "format" not in z.files or str(z["format"]) != _STATE_FORMAT:
+            raise ValueError(f"{path}: not a {_STATE_FORMAT} checkpoint")
+        meta = json.loads(str(z["meta"]))
+        arrays = {k: torch.from_numpy(np.ascontiguousarray(z[k])).to(device)
+                  for k in _STATE_ARRAYS if k in z.files}
+    n = arrays["mass"].shape[0]
+    for k, t in arrays.items():
+        want = (n, 3) if k in ("pos", "vel", "acc") else (n,)
+        if t.dtype != torch.float64 or tuple(t.shape) != want:
+            raise ValueError(f"{path}: {k} has dtype {t.dtype} and shape {tuple(t.shape)}")
+    return arrays, meta

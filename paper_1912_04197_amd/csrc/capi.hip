@@ -3,6 +3,7 @@
 // stream, the device status latch, multi-scene layouts and graph capture of
 // integration steps.
 #include <algorithm>
+#include <dlfcn.h>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -50,6 +51,33 @@ struct bh_ctx {
     bool capturing = false;
     int gdepth = -1;  // depth hint the captured step's build was launched with
 };
+
+namespace {
+
+// roctx ranges for BH_FLAG_MARKERS, resolved from the ROCm tracing library at
+// run time so that the library does not depend on it.
+struct Roctx {
+    int (*push)(const char *) = nullptr;
+    int (*pop)() = nullptr;
+};
+const Roctx &roctx()
+{
+    static const Roctx r = [] {
+        Roctx x;
+        for (const char *lib : {"librocprofiler-sdk-roctx.so.1", "libroctx64.so.4"}) {
+            void *h = dlopen(lib, RTLD_NOW | RTLD_LOCAL);
+            if (!h) continue;
+            x.push = reinterpret_cast<int (*)(const char *)>(dlsym(h, "roctxRangePushA"));
+            x.pop = reinterpret_cast<int (*)()>(dlsym(h, "roctxRangePop"));
+            if (x.push && x.pop) break;
+            x = Roctx{};
+        }
+        return x;
+    }();
+    return r;
+}
+
+}  // namespace
 
 namespace {
 
@@ -140,6 +168,23 @@ bh_status fold_timing(bh_ctx *c)
     return BH_OK;
 }
 
+// A roctx range over one phase's enqueueing (BH_FLAG_MARKERS), popped when
+// the scope ends.
+struct Marker {
+    bool on;
+    Marker(const bh_ctx *c, const char *name)
+        : on((c->cfg.flags & BH_FLAG_MARKERS) && roctx().push != nullptr)
+    {
+        if (on) roctx().push(name);
+    }
+    Marker(const Marker &) = delete;
+    Marker &operator=(const Marker &) = delete;
+    ~Marker()
+    {
+        if (on) roctx().pop();
+    }
+};
+
 bh_status record(bh_ctx *c, int which)
 {
     if (!(c->cfg.flags & BH_FLAG_TIMING) || c->capturing) return BH_OK;
@@ -183,7 +228,10 @@ bh_status force_tree(bh_ctx *c, const bhx::Layout &lay, const double *pos, const
     const int64_t n = lay.n;
     bh_status st = record(c, 0);
     if (st) return st;
-    BHX_HIP(c, bhx::launch_build(w, c->stream, lay, pos, mass, eps, c->cfg.leaf_size));
+    {
+        Marker m(c, "bhx build");
+        BHX_HIP(c, bhx::launch_build(w, c->stream, lay, pos, mass, eps, c->cfg.leaf_size));
+    }
     st = record(c, 1);
     if (st) return st;
     c->tree_n = n;
@@ -202,7 +250,10 @@ bh_status force_tree(bh_ctx *c, const bhx::Layout &lay, const double *pos, const
     p.nquad = w.nquad;
     p.groups = lay.groups;
     p.n_groups = lay.n_groups;
-    BHX_HIP(c, bhx::launch_walk(w, c->stream, p));
+    {
+        Marker m(c, "bhx walk");
+        BHX_HIP(c, bhx::launch_walk(w, c->stream, p));
+    }
     if (p.counts) c->walk_n = n;
     return record(c, 2);
 }
@@ -210,6 +261,7 @@ bh_status force_tree(bh_ctx *c, const bhx::Layout &lay, const double *pos, const
 bh_status force_direct(bh_ctx *c, const double *pos, const double *mass, double softening,
                        const double *eps, double *acc, double *phi, int64_t n, int precision)
 {
+    Marker m(c, "bhx direct");
     BHX_HIP(c, bhx::launch_direct(c->stream, pos, mass, eps, n, softening * softening, c->cfg.G,
                                   precision, acc, phi, c->w.dpart));
     return BH_OK;
@@ -222,6 +274,7 @@ bh_status vjp(bh_ctx *c, const double *pos, const double *mass, double softening
               double *g_mass, int64_t n)
 {
     if (n == 0) return BH_OK;
+    Marker m(c, "bhx vjp");
     if (theta >= 0.0) {
         BHX_HIP(c, bhx::launch_build(c->w, c->stream, single(n), pos, mass, eps, c->cfg.leaf_size));
         c->tree_n = n;
@@ -327,6 +380,7 @@ bh_status kdk_step(bh_ctx *c, const bhx::Layout &lay, double *pos, double *vel,
                    const double *mass, double softening, const double *eps, double theta,
                    double dt, double *acc)
 {
+    Marker m(c, "bhx step");
     BHX_HIP(c, bhx::launch_kick_drift(c->stream, pos, vel, acc, lay.n, dt));
     bh_status s = theta >= 0.0
                       ? force_tree(c, lay, pos, mass, softening, eps, theta, acc, nullptr)
@@ -399,7 +453,10 @@ bh_status run_steps(bh_ctx *c, const bhx::Layout &lay, double *pos, double *vel,
     }
     BHX_HIP(c, hipEventRecord(c->gev[0], caller));
     BHX_HIP(c, hipStreamWaitEvent(c->cstream, c->gev[0], 0));
-    for (int32_t k = 0; k < nsteps; k++) BHX_HIP(c, hipGraphLaunch(c->gexec, c->cstream));
+    for (int32_t k = 0; k < nsteps; k++) {
+        Marker m(c, "bhx step (graph)");
+        BHX_HIP(c, hipGraphLaunch(c->gexec, c->cstream));
+    }
     BHX_HIP(c, hipEventRecord(c->gev[1], c->cstream));
     BHX_HIP(c, hipStreamWaitEvent(caller, c->gev[1], 0));
     return BH_OK;
@@ -419,13 +476,14 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
     if (!std::isfinite(cfg->G)) return BH_E_INVALID;
     if (cfg->flags &
         ~(uint32_t)(BH_FLAG_COUNTS | BH_FLAG_TIMING | BH_FLAG_ADJOINT | BH_FLAG_GRAPH |
-                    BH_FLAG_QUAD))
+                    BH_FLAG_QUAD | BH_FLAG_MARKERS))
         return BH_E_INVALID;
     if (cfg->max_scenes < 0 || cfg->max_scenes > bhx::kMaxScenes) return BH_E_INVALID;
     if (cfg->walk_group != 0 && cfg->walk_group != 16 && cfg->walk_group != 32 &&
         cfg->walk_group != 64)
         return BH_E_INVALID;
 
+    if (cfg->flags & BH_FLAG_MARKERS) (void)roctx();  // resolve the library once, here
     bh_ctx *c = new (std::nothrow) bh_ctx();
     if (!c) return BH_E_OOM;
     c->cfg = *cfg;

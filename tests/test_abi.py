@@ -40,6 +40,10 @@ def test_struct_layouts_match_header(tmp_path):
         lines.append(f'printf("%zu\\n", sizeof({sname}));')
         for fname, _ in cls._fields_:
             lines.append(f'printf("%zu\\n", offsetof({sname}, {fname}));')
+    consts = ["BH_FP64", "BH_FP32C", "BH_FLAG_COUNTS", "BH_FLAG_TIMING", "BH_FLAG_ADJOINT",
+              "BH_FLAG_GRAPH", "BH_FLAG_QUAD", "BH_FLAG_MARKERS"]
+    for k in consts:
+        lines.append(f'printf("%zu\\n", (size_t){k});')
     lines.append("return 0;}")
     src = tmp_path / "probe.c"
     src.write_text("\n".join(lines))
@@ -51,6 +55,7 @@ def test_struct_layouts_match_header(tmp_path):
     for cls in fields.values():
         want.append(C.sizeof(cls))
         want += [getattr(cls, f).offset for f, _ in cls._fields_]
+    want += [getattr(L, k) for k in consts]
     assert got == want
 
 
@@ -63,7 +68,7 @@ def _cfg(**kw):
 
 
 @pytest.mark.parametrize("bad", [dict(n_max=-1), dict(leaf_size=0), dict(leaf_size=65),
-                                 dict(precision=7), dict(G=float("nan")), dict(flags=32),
+                                 dict(precision=7), dict(G=float("nan")), dict(flags=64),
                                  dict(max_scenes=-1), dict(max_scenes=70000),
                                  dict(walk_group=8), dict(walk_group=48)])
 def test_create_rejects_bad_config(lib, bad):

@@ -1,0 +1,63 @@
+"""Resume from a checkpoint, and phase markers.
+
+Bars: steps resumed from a checkpoint (a fresh context, state reloaded from
+the file) equal the uninterrupted steps bit for bit; a context with roctx
+markers computes bit for bit what one without them computes.
+"""
+import numpy as np
+import pytest
+
+from paper_1912_04197_amd import ics
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    from paper_1912_04197_amd import api as A
+
+    return A
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("precision,graph", [("fp64", False), ("fp32c", True)])
+def test_resume_equals_uninterrupted(api, tmp_path, precision, graph):
+    s = ics.plummer(20000, seed=41)
+    kw = dict(theta=0.5, softening=1e-3)
+    whole = api.Context(s.n, leaf_size=4, precision=precision, graph=graph)
+    p, v, m = _dev(s.pos), _dev(s.vel), _dev(s.mass)
+    a = whole.compute_accel(p, m, 0.5, softening=1e-3)
+    whole.step_leapfrog(p, v, m, a, 1e-3, 10, **kw)
+    torch.cuda.synchronize()
+    path = api.save_state(tmp_path / "mid.npz", p, v, m, acc=a, step=10, dt=1e-3)
+    whole.step_leapfrog(p, v, m, a, 1e-3, 10, **kw)
+
+    st, meta = api.load_state(path)
+    assert meta == {"step": 10, "dt": 1e-3}
+    resumed = api.Context(s.n, leaf_size=4, precision=precision, graph=graph)
+    resumed.step_leapfrog(st["pos"], st["vel"], st["mass"], st["acc"], meta["dt"], 10, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(st["pos"], p) and torch.equal(st["vel"], v) and torch.equal(st["acc"], a)
+
+
+def test_markers_change_nothing(api):
+    s = ics.uniform_ball(30000, seed=42)
+    out = []
+    for markers in (False, True):
+        ctx = api.Context(s.n, leaf_size=4, precision="fp32c", markers=markers, adjoint=True)
+        p, v, m = _dev(s.pos), _dev(s.vel), _dev(s.mass)
+        a = ctx.compute_accel(p, m, 0.5, softening=1e-3)
+        d = ctx.compute_accel_direct(p, m, softening=1e-3)
+        ctx.step_leapfrog(p, v, m, a, 1e-3, 3, theta=0.5, softening=1e-3)
+        lam = _dev(np.ones((s.n, 3)))
+        gp, gm = ctx.accel_vjp(p, m, lam, theta=0.5, softening=1e-3)
+        torch.cuda.synchronize()
+        out.append((a, d, p, v, gp, gm))
+    for x, y in zip(*out):
+        assert torch.equal(x, y)
