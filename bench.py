@@ -36,19 +36,21 @@ PEAK_FP32_TFLOPS = 157.3    # MI355X published FP32 vector peak
 PEAK_FP64_TFLOPS = 78.6     # MI355X published FP64 vector peak
 NODE_BYTES = 56             # NodeInfo 16 + NodeMom 32 + node eps^2 8
 PEAK_HBM_TBS = 8.0           # MI355X published HBM3E bandwidth
-# Algorithmic HBM bytes per body of each phase of a step (reads and writes the
-# phase cannot avoid, once each), plus the node tables (NODE_BYTES per node)
-# written once by the build and read once by the walk.
+# Algorithmic HBM bytes per body of each phase of a step of a multi-step call
+# (reads and writes the phase cannot avoid, once each), plus the node tables
+# (NODE_BYTES per node) written once by the build and read once by the walk.
 BYTES_PER_BODY = {
-    # box (pos, mass, eps read) 40 + keys (pos read, key and index written) 36
-    # + sort (one read and one write of key and index) 24 + gather (pos, mass,
-    # eps, index read; body and eps^2 written) 84 + octree (keys searched) 8
-    # + moments (bodies and eps^2 read) 40
-    "build": 232,
+    # first kick, drift and box over the sorted state (body 32, v 24, a 24,
+    # eps^2 8, caller index 4 read; body, v, eps^2, index written: 160) + keys
+    # (positions read, key and index written) 36 + sort (one read and one
+    # write of key and index) 24 + gather (index, body, v, eps^2, caller index
+    # read; body, v, eps^2, caller index written) 140 + octree (keys searched)
+    # 8 + moments (bodies and eps^2 read) 40
+    "build": 408,
     # target body and eps^2 40, index 4, acceleration written 24
     "walk": 68,
-    # kick (v, a read; v written) 72 + kick-drift (x, v, a read; x, v written) 120
-    "integrate": 192,
+    # second kick (v, a read; v written)
+    "integrate": 72,
 }
 
 
@@ -526,8 +528,11 @@ def step_phases(n, nnodes, interactions, ms_step, build_ms, walk_ms):
     """Per-phase roofline of one step: each phase's floor is its algorithmic
     HBM bytes at the HBM peak or, for the walk, its flops at the FP32 vector
     peak if that is longer; the step fraction is the sum of the floors over
-    the measured step time. Build and walk are HIP-event times; `integrate` is
-    the rest of the step (two kicks, the drift and the gaps between launches)."""
+    the measured step time. Build and walk are HIP-event times (the build
+    includes the first kick and the drift, fused into its bounding-box pass);
+    `integrate` is the rest of the step (the second kick, the gaps between
+    launches, and the call's packing and unpacking of the state spread over
+    its steps)."""
     out = {}
     floor_total = 0.0
     measured = {"build": build_ms, "walk": walk_ms,
@@ -562,12 +567,11 @@ def bench_leaf(args, leaf, pos0, vel0, mass, eps):
     pos, vel = pos0.clone(), vel0.clone()
     acc = ctx.compute_accel(pos, mass, theta, eps=eps)
     steps = max(5, min(20, args.steps))
-    for _ in range(2):
-        ctx.step_leapfrog(pos, vel, mass, acc, dt, 1, theta=theta, eps=eps, sync=False)
+    ctx.step_leapfrog(pos, vel, mass, acc, dt, 2, theta=theta, eps=eps, sync=False)
     ctx.sync()
     ctx.timing_reset()
-    ms = _sync_time(lambda: [ctx.step_leapfrog(pos, vel, mass, acc, dt, 1, theta=theta, eps=eps,
-                                               sync=False) for _ in range(steps)]) / steps
+    ms = _sync_time(lambda: ctx.step_leapfrog(pos, vel, mass, acc, dt, steps, theta=theta, eps=eps,
+                                              sync=False)) / steps
     ctx.sync()
     st = ctx.stats()
     walk_ms = st["walk_ms"] / max(st["timed_evals"], 1)
@@ -745,8 +749,10 @@ def main():
     eps = torch.from_numpy(scene.eps).cuda()
 
     def run_steps(ctx, k, pos, vel, acc):
-        for _ in range(k):
-            ctx.step_leapfrog(pos, vel, mass, acc, dt, 1, theta=theta, eps=eps, sync=False)
+        # one call of k steps: the library keeps the state in Morton order
+        # between them (tree rebuilt every step)
+        if k > 0:
+            ctx.step_leapfrog(pos, vel, mass, acc, dt, k, theta=theta, eps=eps, sync=False)
 
     # ---- headline: FP32C tree leapfrog
     ctx = Context(n, leaf_size=leaf, precision="fp32c", timing=True, walk_group=args.walk_group,
@@ -770,6 +776,17 @@ def main():
     build_ms = st["build_ms"] / max(st["timed_evals"], 1)
     log(f"{ms_step:.3f} ms/step (walk {walk_ms:.3f} ms, build {build_ms:.3f} ms, "
         f"{st['timed_evals']} timed evaluations)")
+    # the same steps as one-step calls: the state is read from and written to
+    # the caller's arrays (caller order) around every step
+    p1, v1, a1 = pos.clone(), vel.clone(), acc.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.step_leapfrog(p1, v1, mass, a1, dt, 1, theta=theta, eps=eps, sync=False)
+    torch.cuda.synchronize()
+    ms_one = (time.perf_counter() - t0) * 1e3 / args.steps
+    del p1, v1, a1
+    log(f"one-step calls: {ms_one:.3f} ms/step")
 
     # interactions per step: counted at the first and the last timed state
     cctx = Context(n, leaf_size=leaf, precision="fp32c", counts=True)
@@ -811,6 +828,7 @@ def main():
         "nodes": nnodes,
         "walk_ms": round(walk_ms, 4),
         "build_ms": round(build_ms, 4),
+        "ms_per_step_one_step_calls": round(ms_one, 4),
         "roofline": {
             "bound": "alu",
             "achieved": round(achieved, 3),

@@ -182,8 +182,14 @@ bh_status bh_compute_accel_direct_noalloc(void *hip_stream, int32_t precision, d
  * v += dt/2 a; x += dt v; a = A(x); v += dt/2 a. `acc` must hold the
  * acceleration at the input positions (e.g. from bh_compute_accel) and is
  * updated, so consecutive calls do one force evaluation per step. theta >= 0
- * selects the tree, theta < 0 the direct sum. Errors: as bh_compute_accel,
- * plus BH_E_INVALID for nsteps < 0, dt not finite, vel == NULL. */
+ * selects the tree, theta < 0 the direct sum. With the tree, more than 4096
+ * bodies (or several scenes) and nsteps > 1 (or BH_FLAG_GRAPH), the state is
+ * kept inside the context between the steps of the call, in the Morton
+ * order of each step's sort: pos, vel and acc are read at the start of the
+ * call and written at its end. The results equal those of nsteps one-step calls bit
+ * for bit unless two bodies share a cell of the finest (2^21) grid, whose
+ * order within their leaf may then differ. Errors: as bh_compute_accel, plus
+ * BH_E_INVALID for nsteps < 0, dt not finite, vel == NULL. */
 bh_status bh_step_leapfrog(bh_ctx *ctx, double *pos, double *vel, const double *mass,
                            double softening, const double *eps, double theta, double dt,
                            int32_t nsteps, double *acc, int64_t n);

@@ -164,6 +164,16 @@ struct Workspace {
     uint32_t *sort_totals = nullptr;  // [256]
     Body *body = nullptr;             // sorted bodies
     double *beps2 = nullptr;          // sorted eps^2
+    // The state of a multi-step call, kept in the Morton order of the last
+    // build (body, beps2 and idx[0], the caller index of each sorted body,
+    // belong to it): velocities and accelerations in sorted order, and the
+    // drifted state before the next sort (same order as the sorted state).
+    double *tvel = nullptr;           // [n_cap][3]
+    double *tacc = nullptr;           // [n_cap][3]
+    Body *sbody = nullptr;            // [n_cap]
+    double *svel = nullptr;           // [n_cap][3]
+    double *seps2 = nullptr;          // [n_cap]
+    uint32_t *scidx = nullptr;        // [n_cap]
     NodeInfo *ninfo = nullptr;
     NodeMom *nmom = nullptr;
     double *neps2 = nullptr;
@@ -212,6 +222,13 @@ inline int64_t node_capacity(int64_t n, int leaf, int scenes = 1)
 // built correctly, a deeper one more slowly.
 hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, const double *pos,
                         const double *mass, const double *eps, int leaf);
+// The same build for one step on the sorted state (multi-step calls, more
+// than kSmallBuild bodies or several scenes): the step's first kick and its
+// drift (v = v + dt/2 a, x = x + dt v) run in the bounding-box pass over the
+// sorted state of the previous build, and the gather carries velocities,
+// softening and caller indices into the new order.
+hipError_t launch_build_state(const Workspace &w, hipStream_t s, const Layout &lay, bool use_eps,
+                              int leaf, double dt);
 // scene_of[i] = scene of body i, from device offsets of n_scenes scenes
 hipError_t launch_scene_of(hipStream_t s, const int64_t *offsets, int n_scenes,
                            uint16_t *scene_of);
@@ -223,8 +240,9 @@ struct WalkParams {
     double th2;     // theta^2
     double eps0sq;  // uniform softening squared (per-body eps not given)
     double G;
-    double *acc;    // caller order, n x 3
-    double *phi;    // caller order or nullptr
+    double *acc;    // caller order, n x 3 (sorted order with acc_sorted)
+    double *phi;    // caller order or nullptr (sorted order with acc_sorted)
+    bool acc_sorted = false;
     int32_t *counts;  // caller order n x 2 or nullptr
     bool per_body_eps;
     int precision;
@@ -274,6 +292,14 @@ hipError_t launch_contacts(const Workspace &w, hipStream_t s, const double *radi
 hipError_t launch_euler_substeps(hipStream_t s, double *pos, double *vel, const double *acc,
                                  int64_t n, double dt, int k);
 hipError_t launch_kick(hipStream_t s, double *vel, const double *acc, int64_t n, double dt);
+// The sorted state of a multi-step call from the caller's arrays (identity
+// order; checks masses and softening lengths, flagging ST_NONFINITE), and
+// back to them at its end.
+hipError_t launch_state_pack(const Workspace &w, hipStream_t s, const double *pos,
+                             const double *vel, const double *acc, const double *mass,
+                             const double *eps, int64_t n, uint32_t *status);
+hipError_t launch_state_unpack(const Workspace &w, hipStream_t s, double *pos, double *vel,
+                               double *acc, int64_t n);
 // Largest body density m / ((4/3) pi r^3) over the massive bodies and the
 // gravity time-step bound 1 / (2 sqrt(G rho)) of eq. (dt_g) into out[0]
 // (+inf with no massive body); work[0] is scratch; bad input sets ST_NONFINITE.

@@ -117,7 +117,8 @@ void free_ws(Workspace &w)
 {
     void *ptrs[] = {w.keys[0], w.keys[1], w.idx[0],  w.idx[1],      w.sort_counts,
                     w.sort_totals, w.body, w.beps2, w.ninfo, w.nmom, w.neps2, w.box,
-                    w.hdr, w.counts, w.scratch, w.red_part, w.nquad, w.dpart};
+                    w.hdr, w.counts, w.scratch, w.red_part, w.nquad, w.dpart,
+                    w.tvel, w.tacc, w.sbody, w.svel, w.seps2, w.scidx};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (w.depth_host) (void)hipHostFree(w.depth_host);
@@ -221,21 +222,14 @@ bhx::Layout single(int64_t n)
     return L;
 }
 
-bh_status force_tree(bh_ctx *c, const bhx::Layout &lay, const double *pos, const double *mass,
-                     double softening, const double *eps, double theta, double *acc, double *phi)
+// The walk of the tree just built, for the bodies of `lay`.
+bh_status walk(bh_ctx *c, const bhx::Layout &lay, double softening, bool use_eps, double theta,
+               double *acc, double *phi, bool acc_sorted)
 {
     Workspace &w = c->w;
     const int64_t n = lay.n;
-    bh_status st = record(c, 0);
-    if (st) return st;
-    {
-        Marker m(c, "bhx build");
-        BHX_HIP(c, bhx::launch_build(w, c->stream, lay, pos, mass, eps, c->cfg.leaf_size));
-    }
-    st = record(c, 1);
-    if (st) return st;
     c->tree_n = n;
-    c->tree_eps = eps != nullptr;
+    c->tree_eps = use_eps;
     bhx::WalkParams p;
     p.n = n;
     p.th2 = theta * theta;
@@ -243,8 +237,9 @@ bh_status force_tree(bh_ctx *c, const bhx::Layout &lay, const double *pos, const
     p.G = c->cfg.G;
     p.acc = acc;
     p.phi = phi;
+    p.acc_sorted = acc_sorted;
     p.counts = (c->cfg.flags & BH_FLAG_COUNTS) ? w.counts : nullptr;
-    p.per_body_eps = eps != nullptr;
+    p.per_body_eps = use_eps;
     p.precision = c->cfg.precision;
     p.group = walk_group(c, n);
     p.nquad = w.nquad;
@@ -255,6 +250,22 @@ bh_status force_tree(bh_ctx *c, const bhx::Layout &lay, const double *pos, const
         BHX_HIP(c, bhx::launch_walk(w, c->stream, p));
     }
     if (p.counts) c->walk_n = n;
+    return BH_OK;
+}
+
+bh_status force_tree(bh_ctx *c, const bhx::Layout &lay, const double *pos, const double *mass,
+                     double softening, const double *eps, double theta, double *acc, double *phi)
+{
+    bh_status st = record(c, 0);
+    if (st) return st;
+    {
+        Marker m(c, "bhx build");
+        BHX_HIP(c, bhx::launch_build(c->w, c->stream, lay, pos, mass, eps, c->cfg.leaf_size));
+    }
+    st = record(c, 1);
+    if (st) return st;
+    st = walk(c, lay, softening, eps != nullptr, theta, acc, phi, false);
+    if (st) return st;
     return record(c, 2);
 }
 
@@ -391,6 +402,49 @@ bh_status kdk_step(bh_ctx *c, const bhx::Layout &lay, double *pos, double *vel,
     return BH_OK;
 }
 
+// Multi-step calls on a tree (more than kSmallBuild bodies, or several
+// scenes) keep the state in the Morton order of the last build between
+// steps: packed from the caller's arrays at the start of the call and
+// written back at its end.
+bool sorted_state(const bhx::Layout &lay, double theta, int32_t nsteps, bool graph)
+{
+    return theta >= 0.0 && (nsteps > 1 || graph) &&
+           (lay.n_scenes > 1 || lay.n > bhx::kSmallBuild);
+}
+
+// One kick-drift-kick step on the sorted state: the first kick and the drift
+// run in the build's bounding-box pass, the walk writes the accelerations in
+// sorted order and the second kick uses them there.
+bh_status kdk_step_state(bh_ctx *c, const bhx::Layout &lay, double softening, bool use_eps,
+                         double theta, double dt)
+{
+    Marker m(c, "bhx step");
+    Workspace &w = c->w;
+    bh_status st = record(c, 0);
+    if (st) return st;
+    {
+        Marker mb(c, "bhx build");
+        BHX_HIP(c, bhx::launch_build_state(w, c->stream, lay, use_eps, c->cfg.leaf_size, dt));
+    }
+    st = record(c, 1);
+    if (st) return st;
+    st = walk(c, lay, softening, use_eps, theta, w.tacc, nullptr, true);
+    if (st) return st;
+    st = record(c, 2);
+    if (st) return st;
+    BHX_HIP(c, bhx::launch_kick(c->stream, w.tvel, w.tacc, lay.n, dt));
+    return BH_OK;
+}
+
+// One step of either kind.
+bh_status any_step(bh_ctx *c, bool state, const bhx::Layout &lay, double *pos, double *vel,
+                   const double *mass, double softening, const double *eps, double theta,
+                   double dt, double *acc)
+{
+    return state ? kdk_step_state(c, lay, softening, eps != nullptr, theta, dt)
+                 : kdk_step(c, lay, pos, vel, mass, softening, eps, theta, dt, acc);
+}
+
 // nsteps steps. With BH_FLAG_GRAPH one step is captured once per argument set
 // on the context's own stream and replayed; that stream is ordered after the
 // caller's stream and the caller's stream after it, with events.
@@ -399,11 +453,17 @@ bh_status run_steps(bh_ctx *c, const bhx::Layout &lay, double *pos, double *vel,
                     double dt, int32_t nsteps, double *acc)
 {
     if (nsteps <= 0 || lay.n == 0) return BH_OK;
-    if (!(c->cfg.flags & BH_FLAG_GRAPH)) {
+    const bool graph = (c->cfg.flags & BH_FLAG_GRAPH) != 0;
+    const bool state = sorted_state(lay, theta, nsteps, graph);
+    if (state)
+        BHX_HIP(c, bhx::launch_state_pack(c->w, c->stream, pos, vel, acc, mass, eps, lay.n,
+                                          &c->w.hdr->status));
+    if (!graph) {
         for (int32_t k = 0; k < nsteps; k++) {
-            bh_status s = kdk_step(c, lay, pos, vel, mass, softening, eps, theta, dt, acc);
+            bh_status s = any_step(c, state, lay, pos, vel, mass, softening, eps, theta, dt, acc);
             if (s) return s;
         }
+        if (state) BHX_HIP(c, bhx::launch_state_unpack(c->w, c->stream, pos, vel, acc, lay.n));
         return BH_OK;
     }
     // everything a captured step bakes in: pointers, sizes, the layout tables'
@@ -437,7 +497,7 @@ bh_status run_steps(bh_ctx *c, const bhx::Layout &lay, double *pos, double *vel,
         c->stream = c->cstream;
         c->capturing = true;
         c->gdepth = depth_now;
-        bh_status s = kdk_step(c, lay, pos, vel, mass, softening, eps, theta, dt, acc);
+        bh_status s = any_step(c, state, lay, pos, vel, mass, softening, eps, theta, dt, acc);
         c->capturing = false;
         c->stream = caller;
         hipGraph_t g = nullptr;
@@ -459,6 +519,7 @@ bh_status run_steps(bh_ctx *c, const bhx::Layout &lay, double *pos, double *vel,
     }
     BHX_HIP(c, hipEventRecord(c->gev[1], c->cstream));
     BHX_HIP(c, hipStreamWaitEvent(caller, c->gev[1], 0));
+    if (state) BHX_HIP(c, bhx::launch_state_unpack(c->w, caller, pos, vel, acc, lay.n));
     return BH_OK;
 }
 
@@ -514,6 +575,12 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
     A(dalloc(&w.sort_totals, 256));
     A(dalloc(&w.body, n));
     A(dalloc(&w.beps2, n));
+    A(dalloc(&w.tvel, 3 * n));
+    A(dalloc(&w.tacc, 3 * n));
+    A(dalloc(&w.sbody, n));
+    A(dalloc(&w.svel, 3 * n));
+    A(dalloc(&w.seps2, n));
+    A(dalloc(&w.scidx, n));
     A(dalloc(&w.ninfo, node_cap));
     A(dalloc(&w.nmom, node_cap));
     A(dalloc(&w.neps2, node_cap));

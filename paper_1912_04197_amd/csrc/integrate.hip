@@ -28,7 +28,8 @@ __global__ __launch_bounds__(256) void k_euler_substeps(double *__restrict__ pos
     pos[i] = x;
 }
 
-// v += dt/2 a ; x += dt v
+// v += dt/2 a ; x += dt v, each one fused multiply-add (the multi-step
+// path's kick and drift round them the same way)
 __global__ __launch_bounds__(256) void k_kick_drift(double *__restrict__ pos,
                                                     double *__restrict__ vel,
                                                     const double *__restrict__ acc, int64_t n3,
@@ -36,9 +37,9 @@ __global__ __launch_bounds__(256) void k_kick_drift(double *__restrict__ pos,
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n3) return;
-    const double v = vel[i] + h * acc[i];
+    const double v = fma(h, acc[i], vel[i]);
     vel[i] = v;
-    pos[i] = pos[i] + dt * v;
+    pos[i] = fma(dt, v, pos[i]);
 }
 
 // v += dt/2 a
@@ -47,7 +48,59 @@ __global__ __launch_bounds__(256) void k_kick(double *__restrict__ vel,
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n3) return;
-    vel[i] = vel[i] + h * acc[i];
+    vel[i] = fma(h, acc[i], vel[i]);
+}
+
+// The sorted state of a multi-step call from the caller's arrays, in caller
+// order (the first build sorts it); masses and softening lengths are checked
+// here once, as each build checks them on the caller-order path.
+__global__ __launch_bounds__(256) void k_state_pack(
+    const double *__restrict__ pos, const double *__restrict__ vel,
+    const double *__restrict__ acc, const double *__restrict__ mass,
+    const double *__restrict__ eps, int64_t n, Body *__restrict__ body,
+    double *__restrict__ tvel, double *__restrict__ tacc, double *__restrict__ beps2,
+    uint32_t *__restrict__ idx, uint32_t *__restrict__ status)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool bad = false;
+    if (i < n) {
+        const double m = mass[i];
+        bad = !(isfinite(m) && m >= 0.0);
+        body[i] = Body{pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], m};
+        for (int a = 0; a < 3; a++) {
+            tvel[3 * i + a] = vel[3 * i + a];
+            tacc[3 * i + a] = acc[3 * i + a];
+        }
+        if (eps) {
+            const double e = eps[i];
+            bad |= !(isfinite(e) && e >= 0.0);
+            beps2[i] = e * e;
+        }
+        idx[i] = (uint32_t)i;
+    }
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(status, ST_NONFINITE);
+}
+
+// The end of a multi-step call: the state back to the caller's arrays.
+__global__ __launch_bounds__(256) void k_state_unpack(const Body *__restrict__ body,
+                                                      const double *__restrict__ tvel,
+                                                      const double *__restrict__ tacc,
+                                                      const uint32_t *__restrict__ idx, int64_t n,
+                                                      double *__restrict__ pos,
+                                                      double *__restrict__ vel,
+                                                      double *__restrict__ acc)
+{
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const int64_t o = idx[s];
+    const Body b = body[s];
+    pos[3 * o] = b.x;
+    pos[3 * o + 1] = b.y;
+    pos[3 * o + 2] = b.z;
+    for (int a = 0; a < 3; a++) {
+        vel[3 * o + a] = tvel[3 * s + a];
+        acc[3 * o + a] = tacc[3 * s + a];
+    }
 }
 
 // Compensated FP64 sums: a value is carried as s + c with c the rounding
@@ -199,6 +252,24 @@ hipError_t launch_euler_substeps(hipStream_t s, double *pos, double *vel, const 
 {
     if (n <= 0 || k <= 0) return hipSuccess;
     k_euler_substeps<<<blocks(3 * n), 256, 0, s>>>(pos, vel, acc, 3 * n, dt, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_pack(const Workspace &w, hipStream_t s, const double *pos,
+                             const double *vel, const double *acc, const double *mass,
+                             const double *eps, int64_t n, uint32_t *status)
+{
+    if (n <= 0) return hipSuccess;
+    k_state_pack<<<blocks(n), 256, 0, s>>>(pos, vel, acc, mass, eps, n, w.body, w.tvel, w.tacc,
+                                           w.beps2, w.idx[0], status);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_unpack(const Workspace &w, hipStream_t s, double *pos, double *vel,
+                               double *acc, int64_t n)
+{
+    if (n <= 0) return hipSuccess;
+    k_state_unpack<<<blocks(n), 256, 0, s>>>(w.body, w.tvel, w.tacc, w.idx[0], n, pos, vel, acc);
     return hipGetLastError();
 }
 

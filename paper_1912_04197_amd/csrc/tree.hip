@@ -140,6 +140,70 @@ __global__ __launch_bounds__(kBoxThreads) void k_box_chunk(const double *__restr
     }
 }
 
+// The same work items for one step of a multi-step call, on the sorted state
+// of the previous build: kick and drift each body (v = v + (dt/2) a, then
+// x = x + dt v, each one fused multiply-add as the caller-order step rounds
+// it), write the new state in the same order to the S buffers with its mass,
+// softening and caller index, and reduce the box of the new positions.
+__global__ __launch_bounds__(kBoxThreads) void k_state_kick_drift(
+    const Body *__restrict__ body, const double *__restrict__ tvel,
+    const double *__restrict__ tacc, const double *__restrict__ beps2,
+    const uint32_t *__restrict__ cidx, int64_t n, double h, double dt,
+    const int32_t *__restrict__ chunks, Body *__restrict__ sbody, double *__restrict__ svel,
+    double *__restrict__ seps2, uint32_t *__restrict__ scidx, SceneBox *__restrict__ box,
+    TreeHeader *__restrict__ hdr)
+{
+    int sc = 0;
+    int64_t first = (int64_t)blockIdx.x * kBoxChunk, end = first + kBoxChunk;
+    if (chunks) {
+        sc = chunks[3 * blockIdx.x];
+        first = chunks[3 * blockIdx.x + 1];
+        end = chunks[3 * blockIdx.x + 2];
+    }
+    if (end > n) end = n;
+    double lo[3] = {kInf, kInf, kInf}, hi[3] = {-kInf, -kInf, -kInf};
+    bool bad = false;
+    for (int64_t i = first + threadIdx.x; i < end; i += kBoxThreads) {
+        const Body b = body[i];
+        const double x0[3] = {b.x, b.y, b.z};
+        double x[3], v[3];
+        for (int a = 0; a < 3; a++) {
+            v[a] = fma(h, tacc[3 * i + a], tvel[3 * i + a]);
+            x[a] = fma(dt, v[a], x0[a]);
+        }
+        sbody[i] = Body{x[0], x[1], x[2], b.m};
+        for (int a = 0; a < 3; a++) svel[3 * i + a] = v[a];
+        if (seps2) seps2[i] = beps2[i];
+        scidx[i] = cidx[i];
+        bad |= !(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]));
+        for (int a = 0; a < 3; a++) {
+            lo[a] = fmin(lo[a], x[a]);
+            hi[a] = fmax(hi[a], x[a]);
+        }
+    }
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&hdr->status, ST_NONFINITE);
+    __shared__ double red[kBoxThreads / 64][6];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int a = 0; a < 3; a++) {
+        double l = wave_min(lo[a]), hv = wave_max(hi[a]);
+        if (lane == 0) {
+            red[wave][a] = l;
+            red[wave][3 + a] = hv;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int a = threadIdx.x;
+        double v = red[0][a];
+        for (int w = 1; w < kBoxThreads / 64; w++)
+            v = a < 3 ? fmin(v, red[w][a]) : fmax(v, red[w][a]);
+        if (a < 3)
+            atomicMin(&box[sc].lo_enc[a], order_enc(v));
+        else
+            atomicMax(&box[sc].hi_enc[a - 3], order_enc(v));
+    }
+}
+
 // Root cube: side = largest extent (1 if all bodies coincide), centred on the
 // bounding box; the quantisation scale and the squared cell side per level.
 __device__ inline void root_cube(SceneBox &b, const double lo[3], const double hi[3])
@@ -212,7 +276,8 @@ __device__ inline uint64_t morton_key(const double *x, const SceneBox &b)
     return (spread3(qx) << 2) | (spread3(qy) << 1) | spread3(qz);
 }
 
-__global__ __launch_bounds__(256) void k_keys(const double *__restrict__ pos, int64_t n,
+// pos: body i's coordinates at pos + stride * i (3: caller arrays, 4: Body)
+__global__ __launch_bounds__(256) void k_keys(const double *__restrict__ pos, int stride, int64_t n,
                                               const SceneBox *__restrict__ box,
                                               const uint16_t *__restrict__ scene_of,
                                               uint64_t *__restrict__ keys,
@@ -220,7 +285,7 @@ __global__ __launch_bounds__(256) void k_keys(const double *__restrict__ pos, in
 {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    keys[i] = morton_key(pos + 3 * i, box[scene_of ? scene_of[i] : 0]);
+    keys[i] = morton_key(pos + stride * i, box[scene_of ? scene_of[i] : 0]);
     idx[i] = (uint32_t)i;
 }
 
@@ -420,6 +485,26 @@ __global__ __launch_bounds__(256) void k_gather(const double *__restrict__ pos,
         double e = eps[i];
         beps2[s] = e * e;
     }
+}
+
+// The state of a multi-step call into the new order: idx holds the S index
+// of each sorted body on entry and its caller index on return.
+__global__ __launch_bounds__(256) void k_gather_state(const Body *__restrict__ sbody,
+                                                      const double *__restrict__ svel,
+                                                      const double *__restrict__ seps2,
+                                                      const uint32_t *__restrict__ scidx,
+                                                      int64_t n, uint32_t *__restrict__ idx,
+                                                      Body *__restrict__ body,
+                                                      double *__restrict__ tvel,
+                                                      double *__restrict__ beps2)
+{
+    int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s >= n) return;
+    const int64_t p = idx[s];
+    body[s] = sbody[p];
+    for (int a = 0; a < 3; a++) tvel[3 * s + a] = svel[3 * p + a];
+    if (seps2) beps2[s] = seps2[p];
+    idx[s] = scidx[p];
 }
 
 // -------------------------------------------------------------- 5. build
@@ -928,25 +1013,15 @@ hipError_t launch_scene_of(hipStream_t s, const int64_t *offsets, int n_scenes,
     return hipGetLastError();
 }
 
-hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, const double *pos,
-                        const double *mass, const double *eps, int leaf)
+namespace {
+
+// Stages 2-3: keys of the bodies (coordinates at pos + stride * i) and the
+// sort, leaving the sorted order in idx[0].
+void enqueue_keys_sort(const Workspace &w, hipStream_t s, const Layout &lay, const double *pos,
+                       int stride)
 {
     const int64_t n = lay.n;
     const int ns = lay.n_scenes;
-    if (ns == 1 && n >= 1 && n <= kSmallBuild) {
-        k_build_small<<<1, kSmallThreads, 0, s>>>(pos, mass, eps, n, leaf, w.box, w.hdr, w.keys[0],
-                                                  w.idx[0], w.body, w.beps2, w.ninfo, w.nmom,
-                                                  w.neps2, w.nquad, w.node_cap, w.depth_dev);
-        return hipGetLastError();
-    }
-    const unsigned sb = (unsigned)((ns + 255) / 256);
-    k_box_init<<<sb, 256, 0, s>>>(w.box, ns);
-    const int nchunks = lay.chunks ? lay.n_chunks : (int)((n + kBoxChunk - 1) / kBoxChunk);
-    if (nchunks > 0)
-        k_box_chunk<<<nchunks, kBoxThreads, 0, s>>>(pos, mass, eps, n, lay.chunks, w.box, w.hdr);
-    k_box_final<<<sb, 256, 0, s>>>(w.box, ns, lay.offsets, n, w.hdr, w.ninfo);
-    if (n == 0) return hipGetLastError();
-
     // 8 passes on the Morton key, then (several scenes) one on each byte of
     // the scene index that is not always zero; the keys start in the buffer
     // that makes the last pass write buffer 0.
@@ -954,7 +1029,7 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
     const int passes = ns > 256 ? 10 : ns > 1 ? 9 : 8;
     const int first = passes & 1;
     const unsigned nb = blocks_for(n, 256, 1u << 30);
-    k_keys<<<nb, 256, 0, s>>>(pos, n, w.box, lay.scene_of, w.keys[first], w.idx[first]);
+    k_keys<<<nb, 256, 0, s>>>(pos, stride, n, w.box, lay.scene_of, w.keys[first], w.idx[first]);
     for (int pass = 0; pass < passes; pass++) {
         const int shift = pass < 8 ? 8 * pass : 64 + 8 * (pass - 8);
         const int src = (pass + first) & 1, dst = src ^ 1;
@@ -965,8 +1040,13 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
                                                      lay.offsets, ns, w.keys[dst], w.idx[dst], n,
                                                      shift, w.sort_counts, w.sort_totals, nblk);
     }
-    k_gather<<<nb, 256, 0, s>>>(pos, mass, eps, w.idx[0], n, w.body, w.beps2);
+}
 
+// Stages 5-6 on the sorted bodies.
+void enqueue_levels(const Workspace &w, hipStream_t s, const Layout &lay, int leaf, bool use_eps)
+{
+    const int64_t n = lay.n;
+    const int ns = lay.n_scenes;
     // Splitting: levels 0..deep-1 get a launch each, sized by the largest
     // scene; the levels from `deep` down, which the previous build on this
     // workspace left empty but for one level of growth, are handled in one
@@ -990,19 +1070,64 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
     }
     if (deep < kMaxLevel)
         k_build_tail<<<1, 1024, 0, s>>>(deep, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
-    const int use_eps = eps != nullptr;
+    const int ue = use_eps ? 1 : 0;
     k_moments_tail<<<1, 1024, 0, s>>>(deep, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0], w.box,
-                                      w.nmom, w.neps2, w.nquad, w.node_cap, use_eps);
+                                      w.nmom, w.neps2, w.nquad, w.node_cap, ue);
     for (int level = deep - 1; level >= head; level--) {
         const unsigned g = blocks_for(level_bound(level, n, ns), 256, 4096);
         k_moments_level<<<g, 256, 0, s>>>(level, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0], w.box,
-                                          w.nmom, w.neps2, w.nquad, w.node_cap, use_eps,
-                                          w.depth_dev);
+                                          w.nmom, w.neps2, w.nquad, w.node_cap, ue, w.depth_dev);
     }
     if (head > 0)
         k_moments_head<<<1, 1024, 0, s>>>(head, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0], w.box,
-                                          w.nmom, w.neps2, w.nquad, w.node_cap, use_eps,
-                                          w.depth_dev);
+                                          w.nmom, w.neps2, w.nquad, w.node_cap, ue, w.depth_dev);
+}
+
+}  // namespace
+
+hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, const double *pos,
+                        const double *mass, const double *eps, int leaf)
+{
+    const int64_t n = lay.n;
+    const int ns = lay.n_scenes;
+    if (ns == 1 && n >= 1 && n <= kSmallBuild) {
+        k_build_small<<<1, kSmallThreads, 0, s>>>(pos, mass, eps, n, leaf, w.box, w.hdr, w.keys[0],
+                                                  w.idx[0], w.body, w.beps2, w.ninfo, w.nmom,
+                                                  w.neps2, w.nquad, w.node_cap, w.depth_dev);
+        return hipGetLastError();
+    }
+    const unsigned sb = (unsigned)((ns + 255) / 256);
+    k_box_init<<<sb, 256, 0, s>>>(w.box, ns);
+    const int nchunks = lay.chunks ? lay.n_chunks : (int)((n + kBoxChunk - 1) / kBoxChunk);
+    if (nchunks > 0)
+        k_box_chunk<<<nchunks, kBoxThreads, 0, s>>>(pos, mass, eps, n, lay.chunks, w.box, w.hdr);
+    k_box_final<<<sb, 256, 0, s>>>(w.box, ns, lay.offsets, n, w.hdr, w.ninfo);
+    if (n == 0) return hipGetLastError();
+    enqueue_keys_sort(w, s, lay, pos, 3);
+    k_gather<<<blocks_for(n, 256, 1u << 30), 256, 0, s>>>(pos, mass, eps, w.idx[0], n, w.body,
+                                                          w.beps2);
+    enqueue_levels(w, s, lay, leaf, eps != nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_state(const Workspace &w, hipStream_t s, const Layout &lay, bool use_eps,
+                              int leaf, double dt)
+{
+    const int64_t n = lay.n;
+    const int ns = lay.n_scenes;
+    if (n <= 0) return hipSuccess;
+    const unsigned sb = (unsigned)((ns + 255) / 256);
+    k_box_init<<<sb, 256, 0, s>>>(w.box, ns);
+    const int nchunks = lay.chunks ? lay.n_chunks : (int)((n + kBoxChunk - 1) / kBoxChunk);
+    k_state_kick_drift<<<nchunks, kBoxThreads, 0, s>>>(
+        w.body, w.tvel, w.tacc, w.beps2, w.idx[0], n, 0.5 * dt, dt, lay.chunks, w.sbody, w.svel,
+        use_eps ? w.seps2 : nullptr, w.scidx, w.box, w.hdr);
+    k_box_final<<<sb, 256, 0, s>>>(w.box, ns, lay.offsets, n, w.hdr, w.ninfo);
+    enqueue_keys_sort(w, s, lay, reinterpret_cast<const double *>(w.sbody), 4);
+    k_gather_state<<<blocks_for(n, 256, 1u << 30), 256, 0, s>>>(
+        w.sbody, w.svel, use_eps ? w.seps2 : nullptr, w.scidx, n, w.idx[0], w.body, w.tvel,
+        w.beps2);
+    enqueue_levels(w, s, lay, leaf, use_eps);
     return hipGetLastError();
 }
 

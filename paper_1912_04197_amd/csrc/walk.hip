@@ -104,7 +104,7 @@ __global__ __launch_bounds__(64) void k_walk(
     const uint32_t *__restrict__ idx,
     const SceneBox *__restrict__ box, const int32_t *__restrict__ groups, int64_t n,
     int ngroups, int per_xcd, double th2, double eps0sq, double G, double *__restrict__ acc,
-    double *__restrict__ phi, int32_t *__restrict__ counts)
+    double *__restrict__ phi, int32_t *__restrict__ counts, bool acc_sorted)
 {
     static_assert(GB == 64 || GB == 32 || GB == 16, "group size");
     constexpr int LPB = 64 / GB;  // lanes per body
@@ -475,10 +475,11 @@ __global__ __launch_bounds__(64) void k_walk(
     }
     if (valid && sub == 0) {
         const int64_t o = idx[s];
-        acc[3 * o] = G * ax;
-        acc[3 * o + 1] = G * ay;
-        acc[3 * o + 2] = G * az;
-        if (PHI) phi[o] = G * ph;
+        const int64_t oa = acc_sorted ? s : o;  // where acc and phi go
+        acc[3 * oa] = G * ax;
+        acc[3 * oa + 1] = G * ay;
+        acc[3 * oa + 2] = G * az;
+        if (PHI) phi[oa] = G * ph;
         if (CNT) {
             counts[2 * o] = cnode;
             counts[2 * o + 1] = cpair;
@@ -494,7 +495,7 @@ hipError_t launch_t(const Workspace &w, hipStream_t s, const WalkParams &p)
     if (ngroups == 0) return hipSuccess;
     k_walk<PREC, PEPS, PHI, CNT, GB, QUAD><<<p.groups ? ngroups : 8 * per_xcd, 64, 0, s>>>(
         w.body, w.beps2, w.ninfo, w.nmom, w.neps2, p.nquad, w.idx[0], w.box, p.groups, p.n, ngroups,
-        per_xcd, p.th2, p.eps0sq, p.G, p.acc, p.phi, p.counts);
+        per_xcd, p.th2, p.eps0sq, p.G, p.acc, p.phi, p.counts, p.acc_sorted);
     return hipGetLastError();
 }
 

@@ -290,10 +290,11 @@ def test_plummer_131072_sampled(api):
 
 # ------------------------------------------------------------- leapfrog
 
-@pytest.mark.parametrize("theta", [0.5, -1.0])
-def test_leapfrog_parity(api, theta):
-    """2048-body uniform ball, 10 KDK steps of dt = 1e-3 (tree theta 0.5 leaf 8, or direct)."""
-    s = ics.uniform_ball(2048, seed=11)
+@pytest.mark.parametrize("theta,n", [(0.5, 2048), (-1.0, 2048), (0.5, 6000)])
+def test_leapfrog_parity(api, theta, n):
+    """Uniform ball, 10 KDK steps of dt = 1e-3 (tree theta 0.5 leaf 8, or direct);
+    at 6000 bodies the tree steps run on the Morton-ordered state."""
+    s = ics.uniform_ball(n, seed=11)
     xr, vr, ar = oracle.leapfrog(s.pos, s.vel, s.mass, 1e-3, 10, softening=1e-3, theta=theta,
                                  leaf=8)
     ctx = _ctx(api, s.n, leaf=8, precision="fp64", counts=False)

@@ -2,7 +2,8 @@
 
 Bars: steps resumed from a checkpoint (a fresh context, state reloaded from
 the file) equal the uninterrupted steps bit for bit; a context with roctx
-markers computes bit for bit what one without them computes.
+markers computes bit for bit what one without them computes (the force VJP,
+whose atomics add in any order, to 1e-10 of its largest entry).
 """
 import numpy as np
 import pytest
@@ -59,5 +60,8 @@ def test_markers_change_nothing(api):
         gp, gm = ctx.accel_vjp(p, m, lam, theta=0.5, softening=1e-3)
         torch.cuda.synchronize()
         out.append((a, d, p, v, gp, gm))
-    for x, y in zip(*out):
+    for x, y in zip(out[0][:4], out[1][:4]):
         assert torch.equal(x, y)
+    # the VJP adds its source-side terms with FP64 atomics: equal up to their order
+    for x, y in zip(out[0][4:], out[1][4:]):
+        assert (x - y).abs().max() <= 1e-10 * x.abs().max()
