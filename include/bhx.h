@@ -335,15 +335,20 @@ typedef struct {
 } bh_tree_view;
 bh_status bh_tree_export(bh_ctx *ctx, bh_tree_view *out);
 
-/* Summary (synchronises): node count and depth of the last build; totals of
- * accepted nodes and leaf pairs over all bodies of the last walk (0 unless
+/* Summary (synchronises): node count and depth of the last build, and which
+ * sort it used (bucket_sort = 1: two passes on the top 16 key bits and one
+ * block per range of whole buckets, chosen for one scene of more than 4096
+ * bodies when the previous build's level-5 nodes held at most 1024 bodies
+ * each; 0: eight 8-bit passes, or the one-block build); totals of accepted
+ * nodes and leaf pairs over all bodies of the last walk (0 unless
  * BH_FLAG_COUNTS); with BH_FLAG_TIMING, the number of tree force evaluations
  * and the summed device time (ms, HIP events on the context's stream) of their
- * build and walk phases since creation or the last bh_timing_reset(). */
+ * build and walk phases since creation or the last bh_timing_reset(). Both
+ * sorts give the same order. */
 typedef struct {
     int64_t nnodes;
     int32_t depth;
-    int32_t pad;
+    int32_t bucket_sort;
     int64_t total_nodes_accepted, total_leaf_pairs;
     int64_t timed_evals;
     double build_ms, walk_ms;

@@ -35,7 +35,7 @@ class bh_tree_view(C.Structure):
 
 
 class bh_stats_t(C.Structure):
-    _fields_ = [("nnodes", C.c_int64), ("depth", C.c_int32), ("pad", C.c_int32),
+    _fields_ = [("nnodes", C.c_int64), ("depth", C.c_int32), ("bucket_sort", C.c_int32),
                 ("total_nodes_accepted", C.c_int64), ("total_leaf_pairs", C.c_int64),
                 ("timed_evals", C.c_int64), ("build_ms", C.c_double), ("walk_ms", C.c_double)]
 

@@ -321,6 +321,7 @@ class Context:
         self._bind()
         self._rc(self._lib.bh_stats(self._h, C.byref(s)))
         return {"nnodes": int(s.nnodes), "depth": int(s.depth),
+                "bucket_sort": bool(s.bucket_sort),
                 "nodes_accepted": int(s.total_nodes_accepted), "leaf_pairs": int(s.total_leaf_pairs),
                 "timed_evals": int(s.timed_evals), "build_ms": float(s.build_ms),
                 "walk_ms": float(s.walk_ms)}

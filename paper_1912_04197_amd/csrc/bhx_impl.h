@@ -58,8 +58,10 @@ struct SceneBox {
 struct TreeHeader {
     int32_t level_count[kLevels + 1];  // nodes created per level (all scenes)
     uint32_t status;                   // ST_* bits
-    int32_t pad;
+    int32_t cell_max;                  // most bodies in one node of level kHintLevel
 };
+// The level whose largest node the build reports for the choice of sort.
+constexpr int kHintLevel = 5;
 
 // Body layout of one call: n bodies in n_scenes contiguous scenes. For one
 // scene every table is implicit (nullptr); otherwise scene_of gives each
@@ -184,9 +186,11 @@ struct Workspace {
     double *scratch = nullptr;    // [n_cap] potential for diagnostics
     double *red_part = nullptr;   // [reduction blocks][8][2] compensated partial sums
     double *dpart = nullptr;      // [kDirectPart] partial direct sums of split source ranges
-    // Deepest non-empty level of the last build, written by the device into
-    // pinned host memory (-1 before the first build): the next build launches
-    // the levels down to one below it one by one and the rest in one block.
+    // Launch hints of the last build, written by the device into pinned host
+    // memory (-1 before the first build): [0] its deepest non-empty level (the
+    // next build launches the levels down to one below it one by one and the
+    // rest in one block), [1] the most bodies in one node of level kHintLevel
+    // (which picks the next build's sort).
     int32_t *depth_host = nullptr;
     int32_t *depth_dev = nullptr;  // the same memory as the device sees it
 };
@@ -215,20 +219,27 @@ inline int64_t node_capacity(int64_t n, int leaf, int scenes = 1)
     return (int64_t)(scenes > 1 ? scenes : 1) + (int64_t)kMaxLevel * per_level;
 }
 
-// Launchers (tree.hip). All enqueue on `s` and never synchronise. The build
+// Launchers (tree.hip). All enqueue on `s` and never synchronise; `bucket`
+// (if given) receives the sort the build enqueued (bucket_sort_hint). The build
 // launches one kernel per tree level down to one below the depth the
 // previous build reported (a host read of pinned memory, frozen in a
 // captured graph) and handles deeper levels in one block: any depth is
 // built correctly, a deeper one more slowly.
 hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, const double *pos,
-                        const double *mass, const double *eps, int leaf);
+                        const double *mass, const double *eps, int leaf, bool *bucket = nullptr);
 // The same build for one step on the sorted state (multi-step calls, more
 // than kSmallBuild bodies or several scenes): the step's first kick and its
 // drift (v = v + dt/2 a, x = x + dt v) run in the bounding-box pass over the
 // sorted state of the previous build, and the gather carries velocities,
 // softening and caller indices into the new order.
 hipError_t launch_build_state(const Workspace &w, hipStream_t s, const Layout &lay, bool use_eps,
-                              int leaf, double dt);
+                              int leaf, double dt, bool *bucket = nullptr);
+// Whether the next build of `lay` sorts by buckets of the top key bits (one
+// scene above kSmallBuild bodies whose last build's level-kHintLevel nodes
+// all fit a block's range) rather than by eight key passes; a host read of
+// the pinned hints, frozen in a captured graph. Either sort gives the same
+// order; the choice only affects speed.
+bool bucket_sort_hint(const Workspace &w, const Layout &lay);
 // scene_of[i] = scene of body i, from device offsets of n_scenes scenes
 hipError_t launch_scene_of(hipStream_t s, const int64_t *offsets, int n_scenes,
                            uint16_t *scene_of);

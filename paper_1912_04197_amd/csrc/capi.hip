@@ -22,6 +22,7 @@ struct bh_ctx {
     Workspace w;
     std::string err;
     int64_t tree_n = -1;   // n of the last build, -1 before any
+    bool bucket = false;   // the last build sorted by buckets of the top key bits
     bool tree_eps = false; // the last build had per-body eps
     int64_t walk_n = -1;   // n of the last walk that wrote counts
     double *diag_out = nullptr;
@@ -50,6 +51,7 @@ struct bh_ctx {
     std::vector<double> gkey;
     bool capturing = false;
     int gdepth = -1;  // depth hint the captured step's build was launched with
+    int gbucket = -1; // sort the captured step's build was launched with (bucket_sort_hint)
 };
 
 namespace {
@@ -260,7 +262,8 @@ bh_status force_tree(bh_ctx *c, const bhx::Layout &lay, const double *pos, const
     if (st) return st;
     {
         Marker m(c, "bhx build");
-        BHX_HIP(c, bhx::launch_build(c->w, c->stream, lay, pos, mass, eps, c->cfg.leaf_size));
+        BHX_HIP(c, bhx::launch_build(c->w, c->stream, lay, pos, mass, eps, c->cfg.leaf_size,
+                                     &c->bucket));
     }
     st = record(c, 1);
     if (st) return st;
@@ -287,7 +290,8 @@ bh_status vjp(bh_ctx *c, const double *pos, const double *mass, double softening
     if (n == 0) return BH_OK;
     Marker m(c, "bhx vjp");
     if (theta >= 0.0) {
-        BHX_HIP(c, bhx::launch_build(c->w, c->stream, single(n), pos, mass, eps, c->cfg.leaf_size));
+        BHX_HIP(c, bhx::launch_build(c->w, c->stream, single(n), pos, mass, eps, c->cfg.leaf_size,
+                                 &c->bucket));
         c->tree_n = n;
         c->tree_eps = eps != nullptr;
         bhx::WalkParams p;
@@ -424,7 +428,8 @@ bh_status kdk_step_state(bh_ctx *c, const bhx::Layout &lay, double softening, bo
     if (st) return st;
     {
         Marker mb(c, "bhx build");
-        BHX_HIP(c, bhx::launch_build_state(w, c->stream, lay, use_eps, c->cfg.leaf_size, dt));
+        BHX_HIP(c, bhx::launch_build_state(w, c->stream, lay, use_eps, c->cfg.leaf_size, dt,
+                                           &c->bucket));
     }
     st = record(c, 1);
     if (st) return st;
@@ -484,7 +489,9 @@ bh_status run_steps(bh_ctx *c, const bhx::Layout &lay, double *pos, double *vel,
     // capture had no hint yet (it launched every level).
     const int depth_now = c->w.depth_host ? *(const volatile int32_t *)c->w.depth_host : -1;
     const bool deeper = depth_now >= 0 && (c->gdepth < 0 || depth_now > c->gdepth + 1);
-    if (!c->gexec || key != c->gkey || deeper) {
+    // likewise when the hints now pick the other sort (same order, other speed)
+    const int bucket_now = bhx::bucket_sort_hint(c->w, lay) ? 1 : 0;
+    if (!c->gexec || key != c->gkey || deeper || bucket_now != c->gbucket) {
         if (c->gexec) {
             (void)hipGraphExecDestroy(c->gexec);
             c->gexec = nullptr;
@@ -497,6 +504,7 @@ bh_status run_steps(bh_ctx *c, const bhx::Layout &lay, double *pos, double *vel,
         c->stream = c->cstream;
         c->capturing = true;
         c->gdepth = depth_now;
+        c->gbucket = bucket_now;
         bh_status s = any_step(c, state, lay, pos, vel, mass, softening, eps, theta, dt, acc);
         c->capturing = false;
         c->stream = caller;
@@ -605,9 +613,10 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
     A(dalloc(&w.red_part, (int64_t)bhx::kRedBlocks * 16));
     A(dalloc(&w.dpart, bhx::kDirectPart));
     A(dalloc(&c->diag_out, 8));
-    A(hipHostMalloc((void **)&w.depth_host, sizeof(int32_t), hipHostMallocMapped));
+    A(hipHostMalloc((void **)&w.depth_host, 2 * sizeof(int32_t), hipHostMallocMapped));
     if (r == hipSuccess) {
-        *w.depth_host = -1;
+        w.depth_host[0] = -1;
+        w.depth_host[1] = -1;
         r = hipHostGetDevicePointer((void **)&w.depth_dev, w.depth_host, 0);
     }
     if (cfg->flags & BH_FLAG_ADJOINT) {
@@ -680,7 +689,8 @@ bh_status bh_build_tree(bh_ctx *c, const double *pos, const double *mass, const 
 {
     bh_status s = check_bodies(c, pos, mass, n);
     if (s) return s;
-    BHX_HIP(c, bhx::launch_build(c->w, c->stream, single(n), pos, mass, eps, c->cfg.leaf_size));
+    BHX_HIP(c, bhx::launch_build(c->w, c->stream, single(n), pos, mass, eps, c->cfg.leaf_size,
+                                 &c->bucket));
     c->tree_n = n;
     c->tree_eps = eps != nullptr;
     return BH_OK;
@@ -764,7 +774,8 @@ bh_status bh_contact_components(bh_ctx *c, const double *pos, const double *mass
     *n_contacts = 0;
     *n_aggregates = 0;
     if (n == 0) return BH_OK;
-    BHX_HIP(c, bhx::launch_build(c->w, c->stream, single(n), pos, mass, radius, c->cfg.leaf_size));
+    BHX_HIP(c, bhx::launch_build(c->w, c->stream, single(n), pos, mass, radius, c->cfg.leaf_size,
+                                 &c->bucket));
     c->tree_n = n;
     c->tree_eps = true;
     auto *counters = (unsigned long long *)c->diag_out;
@@ -931,6 +942,7 @@ bh_status bh_stats(bh_ctx *c, bh_stats_t *out)
     std::memset(out, 0, sizeof(*out));
     out->nnodes = v.nnodes;
     out->depth = v.depth;
+    out->bucket_sort = c->bucket ? 1 : 0;
     if (c->walk_n > 0) {
         std::vector<int32_t> h((size_t)c->walk_n * 2);
         BHX_HIP(c, hipMemcpyAsync(h.data(), c->w.counts, h.size() * sizeof(int32_t),

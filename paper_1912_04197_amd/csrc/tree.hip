@@ -241,6 +241,7 @@ __global__ __launch_bounds__(256) void k_box_final(SceneBox *__restrict__ box, i
     if (sc == 0) {
         for (int l = 0; l <= kLevels; l++) hdr->level_count[l] = 0;
         hdr->level_count[0] = n > 0 ? n_scenes : 0;
+        hdr->cell_max = 0;
     }
     if (sc >= n_scenes) return;
     const int64_t first = offsets ? offsets[sc] : 0, end = offsets ? offsets[sc + 1] : n;
@@ -468,6 +469,212 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     }
 }
 
+// ------------------------------------------------------- 3b. bucket sort
+
+// One scene: two stable passes on the top 16 key bits (bits 47..62) group the
+// keys by bucket (equal top bits), in input order within each bucket; then
+// one block per tile of kLocalTile sorted positions takes the buckets that
+// start in its tile (through the end of the last one) and sorts them by the
+// whole key, stably: in LDS when they hold at most kLocalCap keys, else in
+// place in global memory with the other key buffer as scratch. A pass whose
+// digit is the same for every key of the range leaves it as it is and is
+// skipped. A stable sort has one result, so this is the order of the
+// eight-pass sort.
+constexpr int kTopShift = 47;
+constexpr int kLocalThreads = 1024;
+constexpr int kLocalWaves = kLocalThreads / 64;
+constexpr int kLocalCap = 5120;
+constexpr int kWaveKeys = kLocalCap / kLocalWaves;  // 5 rounds of 64 per wave
+constexpr int kLocalTile = 4096;
+static_assert(kWaveKeys % 64 == 0, "whole rounds per wave");
+
+struct LocalScratch {
+    uint32_t whist[kLocalWaves][256];  // per-wave digit counts, then offsets
+    uint32_t base[256];                // where each digit's keys of a chunk start
+    uint32_t part[4];                  // wave totals of a 256-entry scan
+};
+
+// Exclusive scan of v over threads 0..255 (the first four waves); every
+// thread of the block calls it.
+__device__ inline uint32_t scan256_excl(uint32_t v, uint32_t *part)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t x = tid < 256 ? v : 0u;
+    const uint32_t incl = wave_incl_scan(x);
+    if (lane == 63 && wave < 4) part[wave] = incl;
+    __syncthreads();
+    uint32_t add = 0;
+    for (int w = 0; w < 4 && w < wave; w++) add += part[w];
+    __syncthreads();  // part is reused by the next call
+    return add + incl - x;
+}
+
+// One stable counting pass of the block over keys ksrc[0..m) with values
+// vsrc into kdst / vdst, on the digit (key >> shift) & 255, in chunks of
+// kLocalCap keys taken in order. In a chunk, wave w holds keys w*kWaveKeys ..
+// in rounds of 64 and ranks them among equal digits with ballots and a
+// per-wave digit count; a key of digit d then goes to base[d] + (keys of d
+// in earlier waves) + rank, and base[d] advances by the chunk's count of d.
+// For m > kLocalCap, base starts from a count of every digit over all keys.
+template <typename KS, typename VS, typename KD, typename VD>
+__device__ __forceinline__ void block_radix_pass(KS ksrc, VS vsrc, KD kdst, VD vdst, int64_t m,
+                                                 int shift, LocalScratch &S)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool multi = m > kLocalCap;
+    if (multi) {
+        if (tid < 256) S.base[tid] = 0u;
+        __syncthreads();
+        for (int64_t i = tid; i < m; i += kLocalThreads)
+            atomicAdd(&S.base[(uint32_t)(ksrc[i] >> shift) & 255u], 1u);
+        __syncthreads();
+        const uint32_t ex = scan256_excl(tid < 256 ? S.base[tid] : 0u, S.part);
+        if (tid < 256) S.base[tid] = ex;
+        __syncthreads();
+    }
+    for (int64_t c0 = 0; c0 < m; c0 += kLocalCap) {
+        const int cm = (int)(m - c0 < kLocalCap ? m - c0 : kLocalCap);
+        for (int i = tid; i < kLocalWaves * 256; i += kLocalThreads) (&S.whist[0][0])[i] = 0u;
+        __syncthreads();
+        uint32_t rank[kWaveKeys / 64], dig[kWaveKeys / 64];
+#pragma unroll
+        for (int r = 0; r < kWaveKeys / 64; r++) {
+            const int i = wave * kWaveKeys + r * 64 + lane;
+            const bool valid = i < cm;
+            const uint32_t d = valid ? (uint32_t)(ksrc[c0 + i] >> shift) & 255u : 0u;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int bt = 0; bt < 8; bt++) {
+                const bool bit = (d >> bt) & 1u;
+                const uint64_t bal = __ballot(bit);
+                peers &= bit ? bal : ~bal;
+            }
+            const uint64_t lower = peers & lanemask_lt(lane);
+            const uint32_t before = valid ? S.whist[wave][d] : 0u;
+            if (valid && lower == 0) S.whist[wave][d] = before + (uint32_t)__popcll(peers);
+            rank[r] = before + (uint32_t)__popcll(lower);
+            dig[r] = d;
+        }
+        __syncthreads();
+        // digit tid: the offsets of the waves and the chunk's total
+        uint32_t run = 0;
+        if (tid < 256)
+            for (int w = 0; w < kLocalWaves; w++) {
+                const uint32_t c = S.whist[w][tid];
+                S.whist[w][tid] = run;
+                run += c;
+            }
+        if (!multi) {
+            const uint32_t ex = scan256_excl(run, S.part);
+            if (tid < 256) S.base[tid] = ex;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kWaveKeys / 64; r++) {
+            const int i = wave * kWaveKeys + r * 64 + lane;
+            if (i < cm) {
+                const uint32_t o = S.base[dig[r]] + S.whist[wave][dig[r]] + rank[r];
+                kdst[o] = ksrc[c0 + i];
+                vdst[o] = vsrc[c0 + i];
+            }
+        }
+        __syncthreads();
+        if (multi && tid < 256) S.base[tid] += run;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kLocalThreads) void k_sort_local(uint64_t *__restrict__ keys,
+                                                              uint32_t *__restrict__ idx,
+                                                              uint64_t *__restrict__ ktmp,
+                                                              uint32_t *__restrict__ itmp,
+                                                              int64_t n)
+{
+    __shared__ LocalScratch S;
+    __shared__ uint64_t skey[2][kLocalCap];
+    __shared__ uint32_t sval[2][kLocalCap];
+    __shared__ int64_t srange[2];
+    __shared__ uint32_t sdiff[2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t t0 = (int64_t)blockIdx.x * kLocalTile;
+    const int64_t t1 = t0 + kLocalTile < n ? t0 + kLocalTile : n;
+    // wave 0: the first bucket that starts in [t0, t1) (past the one holding
+    // key t0 - 1); wave 1: the end of the bucket holding key t1 - 1. Buckets
+    // are in ascending order of their top bits, so each is the first key at
+    // or after the search start whose top bits differ from that key's.
+    if (wave < 2) {
+        const int64_t from = wave == 0 ? t0 : t1;
+        int64_t pos = from;
+        if (wave == 1 || t0 > 0) {
+            const uint64_t top = keys[wave == 0 ? t0 - 1 : t1 - 1] >> kTopShift;
+            for (int64_t c = from;; c += 64) {
+                const int64_t i = c + lane;
+                const bool differs = i >= n || (keys[i] >> kTopShift) != top;
+                const uint64_t bal = __ballot(differs);
+                if (bal) {
+                    pos = c + __builtin_ctzll(bal);
+                    break;
+                }
+            }
+        }
+        if (lane == 0) srange[wave] = pos;
+    }
+    __syncthreads();
+    const int64_t a = srange[0], b = srange[1];
+    if (a >= t1) return;  // no bucket starts here: the block of its start sorts it
+    const int64_t m = b - a;
+    // the key bits that differ somewhere in the range (OR of key ^ first key)
+    if (tid < 2) sdiff[tid] = 0u;
+    __syncthreads();
+    {
+        const uint64_t k0 = keys[a];
+        uint64_t d = 0;
+        for (int64_t i = tid; i < m; i += kLocalThreads) d |= keys[a + i] ^ k0;
+        for (int o = 32; o > 0; o >>= 1) d |= __shfl_xor(d, o);
+        if (lane == 0) {
+            atomicOr(&sdiff[0], (uint32_t)d);
+            atomicOr(&sdiff[1], (uint32_t)(d >> 32));
+        }
+    }
+    __syncthreads();
+    const uint64_t diff = (uint64_t)sdiff[1] << 32 | sdiff[0];
+    if (m <= kLocalCap) {
+        for (int i = tid; i < m; i += kLocalThreads) {
+            skey[0][i] = keys[a + i];
+            sval[0][i] = idx[a + i];
+        }
+        __syncthreads();
+        int src = 0;
+        for (int pass = 0; pass < 8; pass++) {
+            if (((diff >> (8 * pass)) & 255u) == 0) continue;  // the same on every thread
+            block_radix_pass(skey[src], sval[src], skey[src ^ 1], sval[src ^ 1], m, 8 * pass, S);
+            src ^= 1;
+        }
+        for (int i = tid; i < m; i += kLocalThreads) {
+            keys[a + i] = skey[src][i];
+            idx[a + i] = sval[src][i];
+        }
+    } else {
+        // buffers alternate between the keys and the scratch; an odd number
+        // of passes ends with a copy back
+        bool in_keys = true;
+        for (int pass = 0; pass < 8; pass++) {
+            if (((diff >> (8 * pass)) & 255u) == 0) continue;
+            if (in_keys)
+                block_radix_pass(keys + a, idx + a, ktmp + a, itmp + a, m, 8 * pass, S);
+            else
+                block_radix_pass(ktmp + a, itmp + a, keys + a, idx + a, m, 8 * pass, S);
+            in_keys = !in_keys;
+        }
+        if (!in_keys) {
+            for (int64_t i = tid; i < m; i += kLocalThreads) {
+                keys[a + i] = ktmp[a + i];
+                idx[a + i] = itmp[a + i];
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------- 4. gather
 
 __global__ __launch_bounds__(256) void k_gather(const double *__restrict__ pos,
@@ -536,8 +743,9 @@ __device__ inline void level_range(const int32_t *counts, int level, int64_t nod
 // or a copy in LDS that a single-block kernel keeps and writes back. g_first
 // is the node of this thread's group of eight, stride the nodes per step.
 __device__ inline void build_nodes(int level, const uint64_t *__restrict__ keys, int32_t *counts,
-                                   uint32_t *status, NodeInfo *__restrict__ ninfo,
-                                   int64_t node_cap, int leaf, int64_t g_first, int64_t stride)
+                                   uint32_t *status, int32_t *cell_max,
+                                   NodeInfo *__restrict__ ninfo, int64_t node_cap, int leaf,
+                                   int64_t g_first, int64_t stride)
 {
     __shared__ uint32_t s_wtot[16];
     __shared__ int32_t s_base;
@@ -554,6 +762,7 @@ __device__ inline void build_nodes(int level, const uint64_t *__restrict__ keys,
         const int32_t k = beg + (int32_t)(live ? g : gb);
         const NodeInfo info = ninfo[k];
         const bool split = live && info.count > leaf && level < kMaxLevel;
+        if (level == kHintLevel && live && o == 0) atomicMax(cell_max, info.count);
         int32_t a = info.first, b = split ? info.first + info.count : info.first;
         while (a < b) {
             int32_t m = (a + b) >> 1;
@@ -606,7 +815,7 @@ __global__ __launch_bounds__(1024) void k_build_level(int level, const uint64_t 
                                                       int64_t node_cap, int leaf)
 {
     const int64_t per_block = blockDim.x >> 3;  // nodes per block and step
-    build_nodes(level, keys, hdr->level_count, &hdr->status, ninfo, node_cap, leaf,
+    build_nodes(level, keys, hdr->level_count, &hdr->status, &hdr->cell_max, ninfo, node_cap, leaf,
                 (int64_t)blockIdx.x * per_block + (threadIdx.x >> 3),
                 (int64_t)gridDim.x * per_block);
 }
@@ -620,8 +829,8 @@ __device__ inline void build_levels_block(int from, int upto, const uint64_t *__
 {
     for (int level = from; level < upto; level++) {
         if (scnt[level] == 0) break;
-        build_nodes(level, keys, scnt, &hdr->status, ninfo, node_cap, leaf, threadIdx.x >> 3,
-                    blockDim.x >> 3);
+        build_nodes(level, keys, scnt, &hdr->status, &hdr->cell_max, ninfo, node_cap, leaf,
+                    threadIdx.x >> 3, blockDim.x >> 3);
         __syncthreads();
     }
 }
@@ -731,6 +940,17 @@ __device__ inline void moments_nodes(int level, const int32_t *counts,
     }
 }
 
+// The launch hints of the build just finished, into pinned host memory:
+// its deepest non-empty level and its largest level-kHintLevel node.
+__device__ inline void report_hints(const TreeHeader *__restrict__ hdr, int32_t *out)
+{
+    int d = 0;
+    for (int l = 1; l <= kMaxLevel; l++)
+        if (hdr->level_count[l] > 0) d = l;
+    out[0] = d;
+    out[1] = hdr->cell_max;
+}
+
 __global__ __launch_bounds__(256) void k_moments_level(
     int level, const TreeHeader *__restrict__ hdr, const NodeInfo *__restrict__ ninfo,
     const Body *__restrict__ body, const double *__restrict__ beps2,
@@ -741,14 +961,9 @@ __global__ __launch_bounds__(256) void k_moments_level(
     moments_nodes(level, hdr->level_count, ninfo, body, beps2, keys, box, nmom, neps2, nquad,
                   node_cap, use_eps, (int64_t)blockIdx.x * 256 + threadIdx.x,
                   (int64_t)gridDim.x * 256);
-    // the root level reports the deepest non-empty level, as a launch hint
-    // for the next build (pinned host memory)
-    if (level == 0 && depth_out && blockIdx.x == 0 && threadIdx.x == 0) {
-        int d = 0;
-        for (int l = 1; l <= kMaxLevel; l++)
-            if (hdr->level_count[l] > 0) d = l;
-        *depth_out = d;
-    }
+    // the root level reports the launch hints for the next build
+    if (level == 0 && depth_out && blockIdx.x == 0 && threadIdx.x == 0)
+        report_hints(hdr, depth_out);
 }
 
 // Levels from-1 down to 0 of a single scene in one block, then the depth
@@ -769,12 +984,7 @@ __global__ __launch_bounds__(1024) void k_moments_head(
                       threadIdx.x, 1024);
         __syncthreads();
     }
-    if (depth_out && threadIdx.x == 0) {
-        int d = 0;
-        for (int l = 1; l <= kMaxLevel; l++)
-            if (hdr->level_count[l] > 0) d = l;
-        *depth_out = d;
-    }
+    if (depth_out && threadIdx.x == 0) report_hints(hdr, depth_out);
 }
 
 // Levels kMaxLevel down to `to` in one block (deep levels hold few nodes).
@@ -975,7 +1185,8 @@ __global__ __launch_bounds__(kSmallThreads) void k_build_small(
         int d = 0;
         for (int l = 1; l <= kMaxLevel; l++)
             if (scnt[l] > 0) d = l;
-        *depth_out = d;
+        depth_out[0] = d;
+        depth_out[1] = -1;  // no sort hint from a one-block build
     }
 }
 
@@ -1016,20 +1227,38 @@ hipError_t launch_scene_of(hipStream_t s, const int64_t *offsets, int n_scenes,
 namespace {
 
 // Stages 2-3: keys of the bodies (coordinates at pos + stride * i) and the
-// sort, leaving the sorted order in idx[0].
-void enqueue_keys_sort(const Workspace &w, hipStream_t s, const Layout &lay, const double *pos,
+// sort, leaving the sorted order in idx[0]; returns whether it sorted by
+// buckets.
+bool enqueue_keys_sort(const Workspace &w, hipStream_t s, const Layout &lay, const double *pos,
                        int stride)
 {
     const int64_t n = lay.n;
     const int ns = lay.n_scenes;
+    const int nblk = (int)((n + kSortTile - 1) / kSortTile);
+    const unsigned nb0 = blocks_for(n, 256, 1u << 30);
+    if (bucket_sort_hint(w, lay)) {
+        // two passes on the top 16 key bits (buffer 0 -> 1 -> 0), then the
+        // buckets in place
+        k_keys<<<nb0, 256, 0, s>>>(pos, stride, n, w.box, nullptr, w.keys[0], w.idx[0]);
+        for (int pass = 0; pass < 2; pass++) {
+            const int shift = kTopShift + 8 * pass, src = pass, dst = pass ^ 1;
+            k_sort_hist<<<nblk, kSortThreads, 0, s>>>(w.keys[src], w.idx[src], nullptr, nullptr, 1,
+                                                      n, shift, w.sort_counts, nblk);
+            k_sort_scan<<<256, 256, 0, s>>>(w.sort_counts, w.sort_totals, nblk);
+            k_sort_scatter<<<nblk, kSortThreads, 0, s>>>(w.keys[src], w.idx[src], nullptr, nullptr,
+                                                         1, w.keys[dst], w.idx[dst], n, shift,
+                                                         w.sort_counts, w.sort_totals, nblk);
+        }
+        k_sort_local<<<(unsigned)((n + kLocalTile - 1) / kLocalTile), kLocalThreads, 0, s>>>(
+            w.keys[0], w.idx[0], w.keys[1], w.idx[1], n);
+        return true;
+    }
     // 8 passes on the Morton key, then (several scenes) one on each byte of
     // the scene index that is not always zero; the keys start in the buffer
     // that makes the last pass write buffer 0.
-    const int nblk = (int)((n + kSortTile - 1) / kSortTile);
     const int passes = ns > 256 ? 10 : ns > 1 ? 9 : 8;
     const int first = passes & 1;
-    const unsigned nb = blocks_for(n, 256, 1u << 30);
-    k_keys<<<nb, 256, 0, s>>>(pos, stride, n, w.box, lay.scene_of, w.keys[first], w.idx[first]);
+    k_keys<<<nb0, 256, 0, s>>>(pos, stride, n, w.box, lay.scene_of, w.keys[first], w.idx[first]);
     for (int pass = 0; pass < passes; pass++) {
         const int shift = pass < 8 ? 8 * pass : 64 + 8 * (pass - 8);
         const int src = (pass + first) & 1, dst = src ^ 1;
@@ -1040,6 +1269,7 @@ void enqueue_keys_sort(const Workspace &w, hipStream_t s, const Layout &lay, con
                                                      lay.offsets, ns, w.keys[dst], w.idx[dst], n,
                                                      shift, w.sort_counts, w.sort_totals, nblk);
     }
+    return false;
 }
 
 // Stages 5-6 on the sorted bodies.
@@ -1085,9 +1315,19 @@ void enqueue_levels(const Workspace &w, hipStream_t s, const Layout &lay, int le
 
 }  // namespace
 
-hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, const double *pos,
-                        const double *mass, const double *eps, int leaf)
+bool bucket_sort_hint(const Workspace &w, const Layout &lay)
 {
+    if (lay.n_scenes != 1 || lay.n <= kSmallBuild || !w.depth_host) return false;
+    // a range is a tile plus at most one bucket, and a bucket lies inside one
+    // node of level kHintLevel (its top 16 bits fix the first 5 levels)
+    const int cell = ((const volatile int32_t *)w.depth_host)[1];
+    return cell >= 0 && cell <= kLocalCap - kLocalTile;
+}
+
+hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, const double *pos,
+                        const double *mass, const double *eps, int leaf, bool *bucket)
+{
+    if (bucket) *bucket = false;
     const int64_t n = lay.n;
     const int ns = lay.n_scenes;
     if (ns == 1 && n >= 1 && n <= kSmallBuild) {
@@ -1103,7 +1343,8 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
         k_box_chunk<<<nchunks, kBoxThreads, 0, s>>>(pos, mass, eps, n, lay.chunks, w.box, w.hdr);
     k_box_final<<<sb, 256, 0, s>>>(w.box, ns, lay.offsets, n, w.hdr, w.ninfo);
     if (n == 0) return hipGetLastError();
-    enqueue_keys_sort(w, s, lay, pos, 3);
+    const bool bk = enqueue_keys_sort(w, s, lay, pos, 3);
+    if (bucket) *bucket = bk;
     k_gather<<<blocks_for(n, 256, 1u << 30), 256, 0, s>>>(pos, mass, eps, w.idx[0], n, w.body,
                                                           w.beps2);
     enqueue_levels(w, s, lay, leaf, eps != nullptr);
@@ -1111,8 +1352,9 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
 }
 
 hipError_t launch_build_state(const Workspace &w, hipStream_t s, const Layout &lay, bool use_eps,
-                              int leaf, double dt)
+                              int leaf, double dt, bool *bucket)
 {
+    if (bucket) *bucket = false;
     const int64_t n = lay.n;
     const int ns = lay.n_scenes;
     if (n <= 0) return hipSuccess;
@@ -1123,7 +1365,8 @@ hipError_t launch_build_state(const Workspace &w, hipStream_t s, const Layout &l
         w.body, w.tvel, w.tacc, w.beps2, w.idx[0], n, 0.5 * dt, dt, lay.chunks, w.sbody, w.svel,
         use_eps ? w.seps2 : nullptr, w.scidx, w.box, w.hdr);
     k_box_final<<<sb, 256, 0, s>>>(w.box, ns, lay.offsets, n, w.hdr, w.ninfo);
-    enqueue_keys_sort(w, s, lay, reinterpret_cast<const double *>(w.sbody), 4);
+    const bool bk = enqueue_keys_sort(w, s, lay, reinterpret_cast<const double *>(w.sbody), 4);
+    if (bucket) *bucket = bk;
     k_gather_state<<<blocks_for(n, 256, 1u << 30), 256, 0, s>>>(
         w.sbody, w.svel, use_eps ? w.seps2 : nullptr, w.scidx, n, w.idx[0], w.body, w.tvel,
         w.beps2);
