@@ -742,6 +742,10 @@ __device__ inline void level_range(const int32_t *counts, int level, int64_t nod
 // iterations. `counts` is the per-level node count array: the tree header's,
 // or a copy in LDS that a single-block kernel keeps and writes back. g_first
 // is the node of this thread's group of eight, stride the nodes per step.
+// Nodes of at most this many bodies find their octant ranges by counting
+// (each octant's count fits a byte), larger ones by binary search.
+constexpr int32_t kLinearSplit = 64;
+
 __device__ inline void build_nodes(int level, const uint64_t *__restrict__ keys, int32_t *counts,
                                    uint32_t *status, int32_t *cell_max,
                                    NodeInfo *__restrict__ ninfo, int64_t node_cap, int leaf,
@@ -749,6 +753,7 @@ __device__ inline void build_nodes(int level, const uint64_t *__restrict__ keys,
 {
     __shared__ uint32_t s_wtot[16];
     __shared__ int32_t s_base;
+    __shared__ int32_t s_cmax;
     int32_t beg, cnt;
     level_range(counts, level, node_cap, &beg, &cnt);
     const int32_t next_beg = beg + cnt;
@@ -756,22 +761,41 @@ __device__ inline void build_nodes(int level, const uint64_t *__restrict__ keys,
     const int o = threadIdx.x & 7, gl = lane & ~7;
     const int shift = 60 - 3 * level;  // bits of the child octant at level + 1
     const int64_t b_first = g_first - (threadIdx.x >> 3);  // first node of this block's step
+    // level kHintLevel: the block's largest node, merged into cell_max once
+    int32_t cmax = 0;
+    if (level == kHintLevel && threadIdx.x == 0) s_cmax = 0;
     for (int64_t gb = b_first; gb < cnt; gb += stride) {
         const int64_t g = gb + (threadIdx.x >> 3);
         const bool live = g < cnt;
         const int32_t k = beg + (int32_t)(live ? g : gb);
         const NodeInfo info = ninfo[k];
         const bool split = live && info.count > leaf && level < kMaxLevel;
-        if (level == kHintLevel && live && o == 0) atomicMax(cell_max, info.count);
-        int32_t a = info.first, b = split ? info.first + info.count : info.first;
-        while (a < b) {
-            int32_t m = (a + b) >> 1;
-            if ((int)((keys[m] >> shift) & 7ull) < o)
-                a = m + 1;
-            else
-                b = m;
+        if (level == kHintLevel && live) cmax = max(cmax, info.count);
+        int32_t start;
+        if (info.count <= kLinearSplit) {
+            // few bodies: the 8 lanes read them all (independent loads) and
+            // count them per octant, one byte per octant, summed over the
+            // group; octant o starts after the bodies of octants below it
+            uint64_t hist = 0;
+            if (split)
+                for (int32_t j = o; j < info.count; j += 8)
+                    hist += 1ull << (8 * (int)((keys[info.first + j] >> shift) & 7ull));
+            hist += __shfl_xor(hist, 1, 8);
+            hist += __shfl_xor(hist, 2, 8);
+            hist += __shfl_xor(hist, 4, 8);
+            const uint64_t below = o == 0 ? 0ull : hist & (~0ull >> (64 - 8 * o));
+            start = info.first + (split ? (int32_t)((below * 0x0101010101010101ull) >> 56) : 0);
+        } else {
+            int32_t a = info.first, b = split ? info.first + info.count : info.first;
+            while (a < b) {
+                int32_t m = (a + b) >> 1;
+                if ((int)((keys[m] >> shift) & 7ull) < o)
+                    a = m + 1;
+                else
+                    b = m;
+            }
+            start = a;
         }
-        const int32_t start = a;
         int32_t end = __shfl_down(start, 1, 8);
         if (o == 7) end = info.first + info.count;
         const bool nonempty = split && end > start;
@@ -806,6 +830,13 @@ __device__ inline void build_nodes(int level, const uint64_t *__restrict__ keys,
             ninfo[k].child0 = (int32_t)c0;
             ninfo[k].lvl_nch = level | (nch << 8) | scene_bits;
         }
+    }
+    if (level == kHintLevel) {  // the same on every thread
+        for (int off = 32; off > 0; off >>= 1) cmax = max(cmax, __shfl_xor(cmax, off));
+        __syncthreads();
+        if (lane == 0 && cmax > 0) atomicMax(&s_cmax, cmax);
+        __syncthreads();
+        if (threadIdx.x == 0 && s_cmax > 0) atomicMax(cell_max, s_cmax);
     }
 }
 
