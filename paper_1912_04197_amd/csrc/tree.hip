@@ -473,25 +473,38 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
 
 // One scene: two stable passes on the top 16 key bits (bits 47..62) group the
 // keys by bucket (equal top bits), in input order within each bucket; then
-// one block per tile of kLocalTile sorted positions takes the buckets that
-// start in its tile (through the end of the last one) and sorts them by the
-// whole key, stably: in LDS when they hold at most kLocalCap keys, else in
+// one block per tile of sorted positions takes the buckets that start in its
+// tile (through the end of the last one) and sorts them by the whole key,
+// stably: in LDS when they hold at most its capacity of keys, else in
 // place in global memory with the other key buffer as scratch. A pass whose
 // digit is the same for every key of the range leaves it as it is and is
 // skipped. A stable sort has one result, so this is the order of the
 // eight-pass sort.
 constexpr int kTopShift = 47;
-constexpr int kLocalThreads = 1024;
-constexpr int kLocalWaves = kLocalThreads / 64;
-constexpr int kLocalCap = 5120;
-constexpr int kWaveKeys = kLocalCap / kLocalWaves;  // 5 rounds of 64 per wave
-constexpr int kLocalTile = 4096;
-static_assert(kWaveKeys % 64 == 0, "whole rounds per wave");
+// Block shapes of the bucket sort: a block of T threads holds up to 5 rounds
+// of 64 keys per wave (kCap = 5 T) and starts from tiles of kCap - 1024
+// keys, so a range never exceeds kCap when no bucket holds more than 1024
+// keys. Large sorts use 1024-thread blocks (4096-key tiles), smaller ones
+// 256-thread blocks (256-key tiles), so that both give enough blocks.
+template <int T>
+struct LocalShape {
+    static constexpr int kThreads = T;
+    static constexpr int kWaves = T / 64;
+    static constexpr int kCap = 5 * T;
+    static constexpr int kWaveKeys = kCap / kWaves;  // 5 rounds of 64
+    static constexpr int kTile = kCap - 1024;
+};
+using LocalBig = LocalShape<1024>;
+using LocalSmall = LocalShape<256>;
+constexpr int kBucketMax = 1024;  // bucket bound both shapes are sized for
+static_assert(LocalBig::kTile > 0 && LocalSmall::kTile > 0, "tiles");
+constexpr int64_t kBigSortFrom = (int64_t)256 * LocalBig::kTile;  // 256 blocks of the big shape
 
+template <typename Sh>
 struct LocalScratch {
-    uint32_t whist[kLocalWaves][256];  // per-wave digit counts, then offsets
-    uint32_t base[256];                // where each digit's keys of a chunk start
-    uint32_t part[4];                  // wave totals of a 256-entry scan
+    uint32_t whist[Sh::kWaves][256];  // per-wave digit counts, then offsets
+    uint32_t base[256];               // where each digit's keys of a chunk start
+    uint32_t part[4];                 // wave totals of a 256-entry scan
 };
 
 // Exclusive scan of v over threads 0..255 (the first four waves); every
@@ -511,35 +524,35 @@ __device__ inline uint32_t scan256_excl(uint32_t v, uint32_t *part)
 
 // One stable counting pass of the block over keys ksrc[0..m) with values
 // vsrc into kdst / vdst, on the digit (key >> shift) & 255, in chunks of
-// kLocalCap keys taken in order. In a chunk, wave w holds keys w*kWaveKeys ..
-// in rounds of 64 and ranks them among equal digits with ballots and a
-// per-wave digit count; a key of digit d then goes to base[d] + (keys of d
-// in earlier waves) + rank, and base[d] advances by the chunk's count of d.
-// For m > kLocalCap, base starts from a count of every digit over all keys.
-template <typename KS, typename VS, typename KD, typename VD>
+// kCap keys taken in order. In a chunk, wave w holds keys w*kWaveKeys .. in
+// rounds of 64 and ranks them among equal digits with ballots and a per-wave
+// digit count; a key of digit d then goes to base[d] + (keys of d in earlier
+// waves) + rank, and base[d] advances by the chunk's count of d. For
+// m > kCap, base starts from a count of every digit over all keys.
+template <typename Sh, typename KS, typename VS, typename KD, typename VD>
 __device__ __forceinline__ void block_radix_pass(KS ksrc, VS vsrc, KD kdst, VD vdst, int64_t m,
-                                                 int shift, LocalScratch &S)
+                                                 int shift, LocalScratch<Sh> &S)
 {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const bool multi = m > kLocalCap;
+    const bool multi = m > Sh::kCap;
     if (multi) {
         if (tid < 256) S.base[tid] = 0u;
         __syncthreads();
-        for (int64_t i = tid; i < m; i += kLocalThreads)
+        for (int64_t i = tid; i < m; i += Sh::kThreads)
             atomicAdd(&S.base[(uint32_t)(ksrc[i] >> shift) & 255u], 1u);
         __syncthreads();
         const uint32_t ex = scan256_excl(tid < 256 ? S.base[tid] : 0u, S.part);
         if (tid < 256) S.base[tid] = ex;
         __syncthreads();
     }
-    for (int64_t c0 = 0; c0 < m; c0 += kLocalCap) {
-        const int cm = (int)(m - c0 < kLocalCap ? m - c0 : kLocalCap);
-        for (int i = tid; i < kLocalWaves * 256; i += kLocalThreads) (&S.whist[0][0])[i] = 0u;
+    for (int64_t c0 = 0; c0 < m; c0 += Sh::kCap) {
+        const int cm = (int)(m - c0 < Sh::kCap ? m - c0 : Sh::kCap);
+        for (int i = tid; i < Sh::kWaves * 256; i += Sh::kThreads) (&S.whist[0][0])[i] = 0u;
         __syncthreads();
-        uint32_t rank[kWaveKeys / 64], dig[kWaveKeys / 64];
+        uint32_t rank[Sh::kWaveKeys / 64], dig[Sh::kWaveKeys / 64];
 #pragma unroll
-        for (int r = 0; r < kWaveKeys / 64; r++) {
-            const int i = wave * kWaveKeys + r * 64 + lane;
+        for (int r = 0; r < Sh::kWaveKeys / 64; r++) {
+            const int i = wave * Sh::kWaveKeys + r * 64 + lane;
             const bool valid = i < cm;
             const uint32_t d = valid ? (uint32_t)(ksrc[c0 + i] >> shift) & 255u : 0u;
             uint64_t peers = __ballot(valid);
@@ -559,7 +572,7 @@ __device__ __forceinline__ void block_radix_pass(KS ksrc, VS vsrc, KD kdst, VD v
         // digit tid: the offsets of the waves and the chunk's total
         uint32_t run = 0;
         if (tid < 256)
-            for (int w = 0; w < kLocalWaves; w++) {
+            for (int w = 0; w < Sh::kWaves; w++) {
                 const uint32_t c = S.whist[w][tid];
                 S.whist[w][tid] = run;
                 run += c;
@@ -570,8 +583,8 @@ __device__ __forceinline__ void block_radix_pass(KS ksrc, VS vsrc, KD kdst, VD v
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < kWaveKeys / 64; r++) {
-            const int i = wave * kWaveKeys + r * 64 + lane;
+        for (int r = 0; r < Sh::kWaveKeys / 64; r++) {
+            const int i = wave * Sh::kWaveKeys + r * 64 + lane;
             if (i < cm) {
                 const uint32_t o = S.base[dig[r]] + S.whist[wave][dig[r]] + rank[r];
                 kdst[o] = ksrc[c0 + i];
@@ -584,20 +597,21 @@ __device__ __forceinline__ void block_radix_pass(KS ksrc, VS vsrc, KD kdst, VD v
     }
 }
 
-__global__ __launch_bounds__(kLocalThreads) void k_sort_local(uint64_t *__restrict__ keys,
-                                                              uint32_t *__restrict__ idx,
-                                                              uint64_t *__restrict__ ktmp,
-                                                              uint32_t *__restrict__ itmp,
-                                                              int64_t n)
+template <typename Sh>
+__global__ __launch_bounds__(Sh::kThreads) void k_sort_local(uint64_t *__restrict__ keys,
+                                                             uint32_t *__restrict__ idx,
+                                                             uint64_t *__restrict__ ktmp,
+                                                             uint32_t *__restrict__ itmp,
+                                                             int64_t n)
 {
-    __shared__ LocalScratch S;
-    __shared__ uint64_t skey[2][kLocalCap];
-    __shared__ uint32_t sval[2][kLocalCap];
+    __shared__ LocalScratch<Sh> S;
+    __shared__ uint64_t skey[2][Sh::kCap];
+    __shared__ uint32_t sval[2][Sh::kCap];
     __shared__ int64_t srange[2];
     __shared__ uint32_t sdiff[2];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t t0 = (int64_t)blockIdx.x * kLocalTile;
-    const int64_t t1 = t0 + kLocalTile < n ? t0 + kLocalTile : n;
+    const int64_t t0 = (int64_t)blockIdx.x * Sh::kTile;
+    const int64_t t1 = t0 + Sh::kTile < n ? t0 + Sh::kTile : n;
     // wave 0: the first bucket that starts in [t0, t1) (past the one holding
     // key t0 - 1); wave 1: the end of the bucket holding key t1 - 1. Buckets
     // are in ascending order of their top bits, so each is the first key at
@@ -619,17 +633,16 @@ __global__ __launch_bounds__(kLocalThreads) void k_sort_local(uint64_t *__restri
         }
         if (lane == 0) srange[wave] = pos;
     }
+    if (tid < 2) sdiff[tid] = 0u;
     __syncthreads();
     const int64_t a = srange[0], b = srange[1];
     if (a >= t1) return;  // no bucket starts here: the block of its start sorts it
     const int64_t m = b - a;
     // the key bits that differ somewhere in the range (OR of key ^ first key)
-    if (tid < 2) sdiff[tid] = 0u;
-    __syncthreads();
     {
         const uint64_t k0 = keys[a];
         uint64_t d = 0;
-        for (int64_t i = tid; i < m; i += kLocalThreads) d |= keys[a + i] ^ k0;
+        for (int64_t i = tid; i < m; i += Sh::kThreads) d |= keys[a + i] ^ k0;
         for (int o = 32; o > 0; o >>= 1) d |= __shfl_xor(d, o);
         if (lane == 0) {
             atomicOr(&sdiff[0], (uint32_t)d);
@@ -638,8 +651,8 @@ __global__ __launch_bounds__(kLocalThreads) void k_sort_local(uint64_t *__restri
     }
     __syncthreads();
     const uint64_t diff = (uint64_t)sdiff[1] << 32 | sdiff[0];
-    if (m <= kLocalCap) {
-        for (int i = tid; i < m; i += kLocalThreads) {
+    if (m <= Sh::kCap) {
+        for (int i = tid; i < m; i += Sh::kThreads) {
             skey[0][i] = keys[a + i];
             sval[0][i] = idx[a + i];
         }
@@ -647,10 +660,11 @@ __global__ __launch_bounds__(kLocalThreads) void k_sort_local(uint64_t *__restri
         int src = 0;
         for (int pass = 0; pass < 8; pass++) {
             if (((diff >> (8 * pass)) & 255u) == 0) continue;  // the same on every thread
-            block_radix_pass(skey[src], sval[src], skey[src ^ 1], sval[src ^ 1], m, 8 * pass, S);
+            block_radix_pass<Sh>(skey[src], sval[src], skey[src ^ 1], sval[src ^ 1], m, 8 * pass,
+                                 S);
             src ^= 1;
         }
-        for (int i = tid; i < m; i += kLocalThreads) {
+        for (int i = tid; i < m; i += Sh::kThreads) {
             keys[a + i] = skey[src][i];
             idx[a + i] = sval[src][i];
         }
@@ -661,13 +675,13 @@ __global__ __launch_bounds__(kLocalThreads) void k_sort_local(uint64_t *__restri
         for (int pass = 0; pass < 8; pass++) {
             if (((diff >> (8 * pass)) & 255u) == 0) continue;
             if (in_keys)
-                block_radix_pass(keys + a, idx + a, ktmp + a, itmp + a, m, 8 * pass, S);
+                block_radix_pass<Sh>(keys + a, idx + a, ktmp + a, itmp + a, m, 8 * pass, S);
             else
-                block_radix_pass(ktmp + a, itmp + a, keys + a, idx + a, m, 8 * pass, S);
+                block_radix_pass<Sh>(ktmp + a, itmp + a, keys + a, idx + a, m, 8 * pass, S);
             in_keys = !in_keys;
         }
         if (!in_keys) {
-            for (int64_t i = tid; i < m; i += kLocalThreads) {
+            for (int64_t i = tid; i < m; i += Sh::kThreads) {
                 keys[a + i] = ktmp[a + i];
                 idx[a + i] = itmp[a + i];
             }
@@ -1280,8 +1294,14 @@ bool enqueue_keys_sort(const Workspace &w, hipStream_t s, const Layout &lay, con
                                                          1, w.keys[dst], w.idx[dst], n, shift,
                                                          w.sort_counts, w.sort_totals, nblk);
         }
-        k_sort_local<<<(unsigned)((n + kLocalTile - 1) / kLocalTile), kLocalThreads, 0, s>>>(
-            w.keys[0], w.idx[0], w.keys[1], w.idx[1], n);
+        if (n >= kBigSortFrom)
+            k_sort_local<LocalBig>
+                <<<(unsigned)((n + LocalBig::kTile - 1) / LocalBig::kTile), LocalBig::kThreads, 0,
+                   s>>>(w.keys[0], w.idx[0], w.keys[1], w.idx[1], n);
+        else
+            k_sort_local<LocalSmall>
+                <<<(unsigned)((n + LocalSmall::kTile - 1) / LocalSmall::kTile),
+                   LocalSmall::kThreads, 0, s>>>(w.keys[0], w.idx[0], w.keys[1], w.idx[1], n);
         return true;
     }
     // 8 passes on the Morton key, then (several scenes) one on each byte of
@@ -1352,7 +1372,7 @@ bool bucket_sort_hint(const Workspace &w, const Layout &lay)
     // a range is a tile plus at most one bucket, and a bucket lies inside one
     // node of level kHintLevel (its top 16 bits fix the first 5 levels)
     const int cell = ((const volatile int32_t *)w.depth_host)[1];
-    return cell >= 0 && cell <= kLocalCap - kLocalTile;
+    return cell >= 0 && cell <= kBucketMax;
 }
 
 hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, const double *pos,

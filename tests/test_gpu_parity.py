@@ -312,6 +312,29 @@ def test_bucket_sort_tree_parity(api, second):
         assert not ctx.stats()["bucket_sort"]
 
 
+@pytest.mark.parametrize("n", [1 << 20, 300000])
+def test_bucket_sort_equals_pass_sort(api, n):
+    """At 2^20 bodies the bucket sort runs 1024-thread blocks (below, 256): a
+    second build of the same bodies (bucket sort, chosen from the first
+    build's hint) gives the first build's order (eight passes, checked
+    against the oracle by the tree tests) and node set bit for bit."""
+    s = ics.rubble_pile(n, seed=63)
+    ctx = _ctx(api, n, leaf=4, precision="fp32c", counts=False)
+    out = []
+    for _ in range(2):
+        ctx.build_tree(_dev(s.pos), _dev(s.mass), _dev(s.eps))
+        st = ctx.stats()
+        t = ctx.tree()
+        info = t.info.cpu().numpy()
+        key = info[:, [0, 1, 3]]
+        o = np.lexsort(key.T[::-1])
+        out.append((st["bucket_sort"], t.order.cpu().numpy(), t.keys.cpu().numpy(), key[o],
+                    t.mom.cpu().numpy()[o]))
+    assert not out[0][0] and out[1][0]
+    for a, b in zip(out[0][1:], out[1][1:]):
+        assert np.array_equal(a, b)
+
+
 # ------------------------------------------------------------- leapfrog
 
 @pytest.mark.parametrize("theta,n", [(0.5, 2048), (-1.0, 2048), (0.5, 6000)])
