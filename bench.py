@@ -182,7 +182,8 @@ def bench_adjoint(n=65536, nsteps=200, every=20, theta=0.5, dt=1e-3, soft=1e-3):
     hand-written adjoint back to (x0, v0, m), against the forward alone (each
     the median of 3 runs after a warm-up); the tree gradient against the FP64
     direct-sum gradient, and FP32C (FP32C forward and FP32C tree VJPs)
-    against FP64."""
+    against FP64. The `_keep` entries keep every step's positions (24 B per
+    body and step) so that the backward pass recomputes nothing."""
     import torch
 
     from paper_1912_04197_amd import ics
@@ -194,8 +195,10 @@ def bench_adjoint(n=65536, nsteps=200, every=20, theta=0.5, dt=1e-3, soft=1e-3):
     out = {"workload": f"uniform ball N={n} theta={theta} eps={soft} dt={dt}, {nsteps} KDK "
                        f"steps, checkpoint every {every}, loss sum |x_T - x*|^2"}
     grads = {}
-    for label, prec, th in (("fp32c", "fp32c", theta), ("fp64", "fp64", theta),
-                            ("direct_fp64", "fp64", -1.0)):
+    for label, prec, th, keep in (("fp32c", "fp32c", theta, False), ("fp64", "fp64", theta, False),
+                                  ("direct_fp64", "fp64", -1.0, False),
+                                  ("fp32c_keep", "fp32c", theta, True),
+                                  ("fp64_keep", "fp64", theta, True)):
         ctx = Context(n, leaf_size=16, precision=prec, adjoint=True)
         x0 = torch.from_numpy(s.pos).cuda().requires_grad_(True)
         v0 = torch.from_numpy(s.vel).cuda().requires_grad_(True)
@@ -204,13 +207,13 @@ def bench_adjoint(n=65536, nsteps=200, every=20, theta=0.5, dt=1e-3, soft=1e-3):
         def fwd():
             with torch.no_grad():
                 rollout(x0, v0, m, ctx, dt, nsteps, theta=th, softening=soft,
-                        checkpoint_every=every)
+                        checkpoint_every=every, keep_positions=keep)
 
         def fwd_bwd():
             for t in (x0, v0, m):
                 t.grad = None
             x, _ = rollout(x0, v0, m, ctx, dt, nsteps, theta=th, softening=soft,
-                           checkpoint_every=every)
+                           checkpoint_every=every, keep_positions=keep)
             ((x - xt) ** 2).sum().backward()
 
         fwd_bwd()  # warm-up: first-touch of the workspaces and kernels
@@ -232,6 +235,8 @@ def bench_adjoint(n=65536, nsteps=200, every=20, theta=0.5, dt=1e-3, soft=1e-3):
     out["rel_l2_gap_x0_v0_m"] = {
         "tree_fp64_vs_direct_fp64": gap(grads["fp64"], grads["direct_fp64"]),
         "tree_fp32c_vs_tree_fp64": gap(grads["fp32c"], grads["fp64"]),
+        "fp32c_keep_vs_fp32c": gap(grads["fp32c_keep"], grads["fp32c"]),
+        "fp64_keep_vs_fp64": gap(grads["fp64_keep"], grads["fp64"]),
     }
     return out
 

@@ -306,6 +306,19 @@ bh_status bh_leapfrog_vjp(bh_ctx *ctx, const double *pos, const double *vel, con
                           double dt, int32_t nsteps, double *traj, double *xbar, double *vbar,
                           double *abar, double *g_mass, int64_t n);
 
+/* The same backward pass over steps whose positions the caller kept, with no
+ * recomputation: traj (nsteps x n x 3 float64, caller-owned, unchanged) holds
+ * the positions after each of the nsteps steps, in order, as
+ * bh_step_leapfrog computed them; xbar, vbar, abar and g_mass as for
+ * bh_leapfrog_vjp. A rollout whose positions all fit in device memory (24 B
+ * per body and step) then costs one force VJP per step and no force
+ * evaluation in its backward pass. Needs BH_FLAG_ADJOINT. Errors: as
+ * bh_leapfrog_vjp. */
+bh_status bh_leapfrog_vjp_stored(bh_ctx *ctx, const double *traj, const double *mass,
+                                 double softening, const double *eps, double theta, double dt,
+                                 int32_t nsteps, double *xbar, double *vbar, double *abar,
+                                 double *g_mass, int64_t n);
+
 /* Borrowed device view of the tree of the last build, valid until the next
  * build or bh_destroy. Bodies are held in Morton order: order[s] is the caller
  * index of the s-th sorted body and keys[s] its 63-bit Morton key (the three

@@ -69,6 +69,7 @@ SIGNATURES = {
                      C.POINTER(bh_tune_result)], C.c_int),
     "bh_batched_step": ([P, I32, P, P, P, P, D, P, D, D, I32, P], C.c_int),
     "bh_leapfrog_vjp": ([P, P, P, P, P, D, P, D, D, I32, P, P, P, P, P, I64], C.c_int),
+    "bh_leapfrog_vjp_stored": ([P, P, P, D, P, D, D, I32, P, P, P, P, I64], C.c_int),
     "bh_probe_fma": ([P, I32, I64, C.POINTER(D)], C.c_int),
     "bh_compute_accel_direct_noalloc": ([P, I32, D, P, P, D, P, P, P, I64], C.c_int),
 }

@@ -286,6 +286,28 @@ class Context:
         if sync:
             self.sync()
 
+    def leapfrog_vjp_stored(self, traj, mass, dt, nsteps, xbar, vbar, abar, g_mass, theta=0.5,
+                            softening=0.0, eps=None, sync=True):
+        """Backward over nsteps steps whose end positions traj[0..nsteps) the
+        caller kept (see bh_leapfrog_vjp_stored); no recomputation."""
+        n = int(mass.shape[0])
+        _check_f64("mass", mass, (n,), self.device)
+        if eps is not None:
+            _check_f64("eps", eps, (n,), self.device)
+        for name, t in (("xbar", xbar), ("vbar", vbar), ("abar", abar)):
+            _check_f64(name, t, (n, 3), self.device)
+        _check_f64("g_mass", g_mass, (n,), self.device)
+        if (traj.dtype != torch.float64 or not traj.is_contiguous() or traj.device != self.device
+                or traj.numel() < max(nsteps, 1) * n * 3):
+            raise ValueError("traj must be a contiguous float64 GPU tensor of nsteps x n x 3")
+        self._bind()
+        self._rc(self._lib.bh_leapfrog_vjp_stored(self._h, _ptr(traj), _ptr(mass),
+                                                  float(softening), _ptr(eps), float(theta),
+                                                  float(dt), int(nsteps), _ptr(xbar), _ptr(vbar),
+                                                  _ptr(abar), _ptr(g_mass), n))
+        if sync:
+            self.sync()
+
     def walk_counts(self, n):
         """(n, 2) int32 per-body counts of the last tree walk: accepted nodes, leaf pairs."""
         out = torch.empty((n, 2), dtype=torch.int32, device=self.device)

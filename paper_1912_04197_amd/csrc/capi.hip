@@ -531,6 +531,38 @@ bh_status run_steps(bh_ctx *c, const bhx::Layout &lay, double *pos, double *vel,
     return BH_OK;
 }
 
+// The argument checks the two leapfrog VJPs share.
+bh_status check_vjp_args(bh_ctx *c, double softening, double theta, double dt, int32_t nsteps)
+{
+    if (!(c->cfg.flags & BH_FLAG_ADJOINT))
+        return fail(c, BH_E_STATE, "the context was created without BH_FLAG_ADJOINT");
+    if ((c->cfg.flags & BH_FLAG_QUAD) && theta >= 0.0)
+        return fail(c, BH_E_STATE, "no VJP of the quadrupole walk (BH_FLAG_QUAD)");
+    if (std::isnan(theta) || std::isinf(theta)) return fail(c, BH_E_INVALID, "theta not finite");
+    if (!finite_nonneg(softening)) return fail(c, BH_E_INVALID, "softening must be finite and >= 0");
+    if (!std::isfinite(dt)) return fail(c, BH_E_INVALID, "dt not finite");
+    if (nsteps < 0) return fail(c, BH_E_INVALID, "nsteps < 0");
+    return BH_OK;
+}
+
+// The reverse sweep over nsteps steps whose end positions are traj[0..):
+// per step, last first, the second kick's adjoint, the force VJP at the
+// step's end positions, then the drift's and the first kick's.
+bh_status reverse_sweep(bh_ctx *c, const double *traj, const double *mass, double softening,
+                        const double *eps, double theta, double dt, int32_t nsteps, double *xbar,
+                        double *vbar, double *abar, double *g_mass, int64_t n)
+{
+    const int64_t n3 = 3 * n;
+    for (int32_t k = nsteps - 1; k >= 0; k--) {
+        BHX_HIP(c, bhx::launch_adj_kick(c->stream, abar, vbar, n, dt));
+        bh_status s =
+            vjp(c, traj + (int64_t)k * n3, mass, softening, eps, theta, abar, xbar, g_mass, n);
+        if (s) return s;
+        BHX_HIP(c, bhx::launch_adj_drift_kick(c->stream, vbar, abar, xbar, n, dt));
+    }
+    return BH_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -847,14 +879,8 @@ bh_status bh_leapfrog_vjp(bh_ctx *c, const double *pos, const double *vel, const
 {
     bh_status s = check_bodies(c, pos, mass, n);
     if (s) return s;
-    if (!(c->cfg.flags & BH_FLAG_ADJOINT))
-        return fail(c, BH_E_STATE, "the context was created without BH_FLAG_ADJOINT");
-    if ((c->cfg.flags & BH_FLAG_QUAD) && theta >= 0.0)
-        return fail(c, BH_E_STATE, "no VJP of the quadrupole walk (BH_FLAG_QUAD)");
-    if (std::isnan(theta) || std::isinf(theta)) return fail(c, BH_E_INVALID, "theta not finite");
-    if (!finite_nonneg(softening)) return fail(c, BH_E_INVALID, "softening must be finite and >= 0");
-    if (!std::isfinite(dt)) return fail(c, BH_E_INVALID, "dt not finite");
-    if (nsteps < 0) return fail(c, BH_E_INVALID, "nsteps < 0");
+    s = check_vjp_args(c, softening, theta, dt, nsteps);
+    if (s) return s;
     if (n > 0 && (!vel || !acc || !xbar || !vbar || !abar || !g_mass || (nsteps > 0 && !traj)))
         return fail(c, BH_E_INVALID, "NULL vel, acc, traj, xbar, vbar, abar or g_mass");
     if (n == 0 || nsteps == 0) return BH_OK;
@@ -874,14 +900,24 @@ bh_status bh_leapfrog_vjp(bh_ctx *c, const double *pos, const double *vel, const
         if (s) return s;
         BHX_HIP(c, bhx::launch_kick(c->stream, aw.vwork, aw.awork, n, dt));
     }
-    // reverse: second kick, force VJP at the step's end positions, drift, first kick
-    for (int32_t k = nsteps - 1; k >= 0; k--) {
-        BHX_HIP(c, bhx::launch_adj_kick(c->stream, abar, vbar, n, dt));
-        s = vjp(c, traj + (int64_t)k * n3, mass, softening, eps, theta, abar, xbar, g_mass, n);
-        if (s) return s;
-        BHX_HIP(c, bhx::launch_adj_drift_kick(c->stream, vbar, abar, xbar, n, dt));
-    }
-    return BH_OK;
+    return reverse_sweep(c, traj, mass, softening, eps, theta, dt, nsteps, xbar, vbar, abar,
+                         g_mass, n);
+}
+
+bh_status bh_leapfrog_vjp_stored(bh_ctx *c, const double *traj, const double *mass,
+                                 double softening, const double *eps, double theta, double dt,
+                                 int32_t nsteps, double *xbar, double *vbar, double *abar,
+                                 double *g_mass, int64_t n)
+{
+    bh_status s = check_bodies(c, traj, mass, n);
+    if (s) return s;
+    s = check_vjp_args(c, softening, theta, dt, nsteps);
+    if (s) return s;
+    if (n > 0 && (!xbar || !vbar || !abar || !g_mass))
+        return fail(c, BH_E_INVALID, "NULL xbar, vbar, abar or g_mass");
+    if (n == 0 || nsteps == 0) return BH_OK;
+    return reverse_sweep(c, traj, mass, softening, eps, theta, dt, nsteps, xbar, vbar, abar,
+                         g_mass, n);
 }
 
 bh_status bh_walk_counts(bh_ctx *c, int32_t *counts, int64_t n)

@@ -128,14 +128,20 @@ def test_vjp_accumulates_and_invariants(api):
 def test_vjp_requires_flag(api):
     ctx = api.Context(10, adjoint=False)
     z = torch.zeros((10, 3), dtype=torch.float64, device="cuda")
+    one = torch.ones(10, dtype=torch.float64, device="cuda")
     with pytest.raises(api.BHError, match="BH_E_STATE"):
-        ctx.accel_vjp(z, torch.ones(10, dtype=torch.float64, device="cuda"), z)
+        ctx.accel_vjp(z, one, z)
+    with pytest.raises(api.BHError, match="BH_E_STATE"):
+        ctx.leapfrog_vjp_stored(z.view(1, 10, 3), one, 1e-3, 1, z, z.clone(), z.clone(),
+                                one.clone())
 
 
+@pytest.mark.parametrize("keep", [False, True])
 @pytest.mark.parametrize("theta", [0.5, -1.0])
-def test_rollout_gradient_parity(api, theta):
+def test_rollout_gradient_parity(api, theta, keep):
     """N = 256 uniform ball, eps 1e-3, 20 KDK steps of dt = 1e-3, checkpoints
-    every 7 steps, loss sum |x_T - x*|^2 + 0.5 sum |v_T|^2, FP64."""
+    every 7 steps (or every position kept), loss sum |x_T - x*|^2 +
+    0.5 sum |v_T|^2, FP64."""
     from paper_1912_04197_amd.autograd import rollout
 
     n, T, dt, soft = 256, 20, 1e-3, 1e-3
@@ -148,7 +154,8 @@ def test_rollout_gradient_parity(api, theta):
     X0 = _dev(s.pos).requires_grad_(True)
     V0 = _dev(v0).requires_grad_(True)
     Mt = _dev(m).requires_grad_(True)
-    x, v = rollout(X0, V0, Mt, ctx, dt, T, theta=theta, softening=soft, checkpoint_every=7)
+    x, v = rollout(X0, V0, Mt, ctx, dt, T, theta=theta, softening=soft, checkpoint_every=7,
+                   keep_positions=keep)
     loss = ((x - _dev(xt)) ** 2).sum() + 0.5 * (v ** 2).sum()
     loss.backward()
     xf, vf, _ = oracle.leapfrog(s.pos, v0, m, dt, T, softening=soft, theta=theta, leaf=16)
@@ -160,8 +167,9 @@ def test_rollout_gradient_parity(api, theta):
     _close(Mt.grad.cpu().numpy(), gm, 1e-9, "gm")
 
 
+@pytest.mark.parametrize("keep", [False, True])
 @pytest.mark.parametrize("theta", [0.5, -1.0])
-def test_rollout_gradient_parity_4096(api, theta):
+def test_rollout_gradient_parity_4096(api, theta, keep):
     """The differentiable-rollout case at the size the CPU oracle can still
     follow: N = 4096 uniform ball (equal masses), eps 1e-3, 50 KDK steps of
     dt = 1e-3, checkpoints every 20 steps, loss sum |x_T - x*|^2, FP64; every
@@ -176,7 +184,8 @@ def test_rollout_gradient_parity_4096(api, theta):
     X0 = _dev(s.pos).requires_grad_(True)
     V0 = _dev(s.vel).requires_grad_(True)
     Mt = _dev(s.mass).requires_grad_(True)
-    x, _ = rollout(X0, V0, Mt, ctx, dt, T, theta=theta, softening=soft, checkpoint_every=20)
+    x, _ = rollout(X0, V0, Mt, ctx, dt, T, theta=theta, softening=soft, checkpoint_every=20,
+                   keep_positions=keep)
     ((x - _dev(xt)) ** 2).sum().backward()
     xf, vf, _ = oracle.leapfrog(s.pos, s.vel, s.mass, dt, T, softening=soft, theta=theta, leaf=16)
     assert np.abs(x.detach().cpu().numpy() - xf).max() < 1e-12
@@ -214,3 +223,13 @@ def test_rollout_65536_properties(api, precision):
     assert np.abs(gx.sum(0) - sx).max() <= 1e-8 * scale
     assert np.abs(gv.sum(0) - T * dt * sx).max() <= 1e-8 * scale
     assert np.all(np.isfinite(Mt.grad.cpu().numpy()))
+    # every position kept instead of recomputed: the same trajectory and, up
+    # to the order of the VJPs' atomic additions, the same gradients
+    g_ckpt = [t.grad.clone() for t in (X0, V0, Mt)]
+    for t in (X0, V0, Mt):
+        t.grad = None
+    x2, _ = rollout(X0, V0, Mt, ctx, dt, T, theta=0.5, softening=1e-3, keep_positions=True)
+    assert torch.equal(x2, x)
+    ((x2 - _dev(xt)) ** 2).sum().backward()
+    for g1, g2 in zip(g_ckpt, (X0.grad, V0.grad, Mt.grad)):
+        assert float((g1 - g2).abs().max()) <= 1e-10 * float(g1.abs().max())
