@@ -271,7 +271,30 @@ hipError_t launch_direct(hipStream_t s, const double *pos, const double *mass, c
                          double *phi, double *part);
 
 // adjoint.hip: workspace of the VJPs (BH_FLAG_ADJOINT)
+// The trees a checkpointed segment's recomputation builds, one per step, kept
+// for the VJPs at the same positions: slot k holds sorted bodies, eps^2,
+// caller indices and keys (n each), the node tables (node_cap each), the
+// scene box and the tree header of step k.
+struct TreeSlots {
+    int count = 0;
+    int64_t n = 0, node_cap = 0;
+    Body *body = nullptr;
+    double *beps2 = nullptr;
+    uint32_t *idx = nullptr;
+    uint64_t *keys = nullptr;
+    NodeInfo *ninfo = nullptr;
+    NodeMom *nmom = nullptr;
+    double *neps2 = nullptr;
+    SceneBox *box = nullptr;
+    TreeHeader *hdr = nullptr;
+};
+// A workspace whose tree arrays are slot k's (scratch arrays shared with w).
+Workspace slot_view(const Workspace &w, const TreeSlots &t, int k);
+// ORs the slots' status words into *status and clears them.
+hipError_t launch_merge_status(hipStream_t s, TreeHeader *slot_hdr, int count, uint32_t *status);
+
 struct AdjointWork {
+    TreeSlots trees;         // allocated by the first segment VJP that fits in memory
     double *gt = nullptr;    // [n_cap][3] target-side gradients, sorted order
     double *badj = nullptr;  // [n_cap][4] source-side body adjoints, sorted order
     double *nadj = nullptr;  // [node_cap][5] node adjoints: gX, gm, g<eps^2>

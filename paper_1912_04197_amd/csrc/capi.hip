@@ -107,8 +107,17 @@ hipError_t dalloc(T **p, int64_t count)
     return hipMalloc((void **)p, (size_t)count * sizeof(T));
 }
 
+void free_slots(bhx::TreeSlots &t)
+{
+    void *ptrs[] = {t.body, t.beps2, t.idx, t.keys, t.ninfo, t.nmom, t.neps2, t.box, t.hdr};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    t = bhx::TreeSlots{};
+}
+
 void free_aw(bhx::AdjointWork &a)
 {
+    free_slots(a.trees);
     void *ptrs[] = {a.gt, a.badj, a.nadj, a.npre, a.vwork, a.awork};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -225,10 +234,9 @@ bhx::Layout single(int64_t n)
 }
 
 // The walk of the tree just built, for the bodies of `lay`.
-bh_status walk(bh_ctx *c, const bhx::Layout &lay, double softening, bool use_eps, double theta,
-               double *acc, double *phi, bool acc_sorted)
+bh_status walk(bh_ctx *c, const Workspace &w, const bhx::Layout &lay, double softening,
+               bool use_eps, double theta, double *acc, double *phi, bool acc_sorted)
 {
-    Workspace &w = c->w;
     const int64_t n = lay.n;
     c->tree_n = n;
     c->tree_eps = use_eps;
@@ -255,19 +263,23 @@ bh_status walk(bh_ctx *c, const bhx::Layout &lay, double softening, bool use_eps
     return BH_OK;
 }
 
+// Build and walk on the context's tree arrays, or on those of `w` (a tree
+// slot of the adjoint).
 bh_status force_tree(bh_ctx *c, const bhx::Layout &lay, const double *pos, const double *mass,
-                     double softening, const double *eps, double theta, double *acc, double *phi)
+                     double softening, const double *eps, double theta, double *acc, double *phi,
+                     const Workspace *w = nullptr)
 {
+    const Workspace &ws = w ? *w : c->w;
     bh_status st = record(c, 0);
     if (st) return st;
     {
         Marker m(c, "bhx build");
-        BHX_HIP(c, bhx::launch_build(c->w, c->stream, lay, pos, mass, eps, c->cfg.leaf_size,
+        BHX_HIP(c, bhx::launch_build(ws, c->stream, lay, pos, mass, eps, c->cfg.leaf_size,
                                      &c->bucket));
     }
     st = record(c, 1);
     if (st) return st;
-    st = walk(c, lay, softening, eps != nullptr, theta, acc, phi, false);
+    st = walk(c, ws, lay, softening, eps != nullptr, theta, acc, phi, false);
     if (st) return st;
     return record(c, 2);
 }
@@ -285,15 +297,19 @@ bh_status force_direct(bh_ctx *c, const double *pos, const double *mass, double 
 // into g_pos and g_mass.
 bh_status vjp(bh_ctx *c, const double *pos, const double *mass, double softening,
               const double *eps, double theta, const double *lambda, double *g_pos,
-              double *g_mass, int64_t n)
+              double *g_mass, int64_t n, const Workspace *tree = nullptr)
 {
     if (n == 0) return BH_OK;
     Marker m(c, "bhx vjp");
     if (theta >= 0.0) {
-        BHX_HIP(c, bhx::launch_build(c->w, c->stream, single(n), pos, mass, eps, c->cfg.leaf_size,
-                                 &c->bucket));
-        c->tree_n = n;
-        c->tree_eps = eps != nullptr;
+        // `tree`: the tree of these positions, built by the segment's
+        // recomputation and kept in a slot; else build it here
+        if (!tree) {
+            BHX_HIP(c, bhx::launch_build(c->w, c->stream, single(n), pos, mass, eps,
+                                         c->cfg.leaf_size, &c->bucket));
+            c->tree_n = n;
+            c->tree_eps = eps != nullptr;
+        }
         bhx::WalkParams p;
         p.n = n;
         p.th2 = theta * theta;
@@ -305,7 +321,8 @@ bh_status vjp(bh_ctx *c, const double *pos, const double *mass, double softening
         p.per_body_eps = eps != nullptr;
         p.precision = c->cfg.precision;  // FP32C terms in an FP32C context
         p.group = vjp_group(c, n);
-        BHX_HIP(c, bhx::launch_tree_vjp(c->w, c->aw, c->stream, p, lambda, g_pos, g_mass));
+        BHX_HIP(c, bhx::launch_tree_vjp(tree ? *tree : c->w, c->aw, c->stream, p, lambda, g_pos,
+                                        g_mass));
     } else {
         BHX_HIP(c, bhx::launch_direct_vjp(c->stream, pos, mass, eps, n, softening * softening,
                                           c->cfg.G, lambda, g_pos, g_mass, c->w.dpart));
@@ -433,7 +450,7 @@ bh_status kdk_step_state(bh_ctx *c, const bhx::Layout &lay, double softening, bo
     }
     st = record(c, 1);
     if (st) return st;
-    st = walk(c, lay, softening, use_eps, theta, w.tacc, nullptr, true);
+    st = walk(c, w, lay, softening, use_eps, theta, w.tacc, nullptr, true);
     if (st) return st;
     st = record(c, 2);
     if (st) return st;
@@ -550,17 +567,62 @@ bh_status check_vjp_args(bh_ctx *c, double softening, double theta, double dt, i
 // step's end positions, then the drift's and the first kick's.
 bh_status reverse_sweep(bh_ctx *c, const double *traj, const double *mass, double softening,
                         const double *eps, double theta, double dt, int32_t nsteps, double *xbar,
-                        double *vbar, double *abar, double *g_mass, int64_t n)
+                        double *vbar, double *abar, double *g_mass, int64_t n,
+                        bool kept_trees = false)
 {
     const int64_t n3 = 3 * n;
     for (int32_t k = nsteps - 1; k >= 0; k--) {
         BHX_HIP(c, bhx::launch_adj_kick(c->stream, abar, vbar, n, dt));
-        bh_status s =
-            vjp(c, traj + (int64_t)k * n3, mass, softening, eps, theta, abar, xbar, g_mass, n);
+        const Workspace slot = kept_trees ? bhx::slot_view(c->w, c->aw.trees, k) : c->w;
+        bh_status s = vjp(c, traj + (int64_t)k * n3, mass, softening, eps, theta, abar, xbar,
+                          g_mass, n, kept_trees ? &slot : nullptr);
         if (s) return s;
         BHX_HIP(c, bhx::launch_adj_drift_kick(c->stream, vbar, abar, xbar, n, dt));
     }
     return BH_OK;
+}
+
+// Tree slots for the nsteps steps of a segment of n bodies: kept from an
+// earlier call when large enough, else allocated once the device has twice
+// their size free; false (the VJPs then rebuild their trees) otherwise.
+bool ensure_tree_slots(bh_ctx *c, int32_t nsteps, int64_t n)
+{
+    bhx::TreeSlots &t = c->aw.trees;
+    if (t.count >= nsteps && t.n >= n) return true;
+    free_slots(t);
+    const int64_t node_cap = bhx::node_capacity(n, c->cfg.leaf_size, 1);
+    const size_t per = (size_t)n * (sizeof(bhx::Body) + sizeof(double) + sizeof(uint32_t) +
+                                    sizeof(uint64_t)) +
+                       (size_t)node_cap * (sizeof(bhx::NodeInfo) + sizeof(bhx::NodeMom) +
+                                           sizeof(double)) +
+                       sizeof(bhx::SceneBox) + sizeof(bhx::TreeHeader);
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess || per * (size_t)nsteps * 2 > free_b)
+        return false;
+    t.n = n;
+    t.node_cap = node_cap;
+    const int64_t k = nsteps;
+    hipError_t r = hipSuccess;
+    auto A = [&](hipError_t x) {
+        if (r == hipSuccess) r = x;
+    };
+    A(dalloc(&t.body, k * n));
+    A(dalloc(&t.beps2, k * n));
+    A(dalloc(&t.idx, k * n));
+    A(dalloc(&t.keys, k * n));
+    A(dalloc(&t.ninfo, k * node_cap));
+    A(dalloc(&t.nmom, k * node_cap));
+    A(dalloc(&t.neps2, k * node_cap));
+    A(dalloc(&t.box, k));
+    A(dalloc(&t.hdr, k));
+    if (r == hipSuccess) r = hipMemset(t.hdr, 0, (size_t)k * sizeof(bhx::TreeHeader));
+    if (r != hipSuccess) {
+        (void)hipGetLastError();
+        free_slots(t);
+        return false;
+    }
+    t.count = nsteps;
+    return true;
 }
 
 }  // namespace
@@ -886,6 +948,9 @@ bh_status bh_leapfrog_vjp(bh_ctx *c, const double *pos, const double *vel, const
     if (n == 0 || nsteps == 0) return BH_OK;
     const int64_t n3 = 3 * n;
     bhx::AdjointWork &aw = c->aw;
+    // the tree of each recomputed step is kept for the VJP at the same
+    // positions when there is room (same build, so the same tree)
+    const bool keep = theta >= 0.0 && ensure_tree_slots(c, nsteps, n);
     // recompute the segment's positions exactly as bh_step_leapfrog does
     BHX_HIP(c, bhx::launch_copy(c->stream, aw.vwork, vel, n3));
     BHX_HIP(c, bhx::launch_copy(c->stream, aw.awork, acc, n3));
@@ -893,15 +958,21 @@ bh_status bh_leapfrog_vjp(bh_ctx *c, const double *pos, const double *vel, const
         const double *x_in = k == 0 ? pos : traj + (int64_t)(k - 1) * n3;
         double *x_out = traj + (int64_t)k * n3;
         BHX_HIP(c, bhx::launch_kick_drift_to(c->stream, x_in, aw.vwork, aw.awork, x_out, n, dt));
-        s = theta >= 0.0
-                ? force_tree(c, single(n), x_out, mass, softening, eps, theta, aw.awork, nullptr)
-                : force_direct(c, x_out, mass, softening, eps, aw.awork, nullptr, n,
-                               c->cfg.precision);
+        const Workspace slot = keep ? bhx::slot_view(c->w, aw.trees, k) : c->w;
+        s = theta >= 0.0 ? force_tree(c, single(n), x_out, mass, softening, eps, theta, aw.awork,
+                                      nullptr, keep ? &slot : nullptr)
+                         : force_direct(c, x_out, mass, softening, eps, aw.awork, nullptr, n,
+                                        c->cfg.precision);
         if (s) return s;
         BHX_HIP(c, bhx::launch_kick(c->stream, aw.vwork, aw.awork, n, dt));
     }
-    return reverse_sweep(c, traj, mass, softening, eps, theta, dt, nsteps, xbar, vbar, abar,
-                         g_mass, n);
+    s = reverse_sweep(c, traj, mass, softening, eps, theta, dt, nsteps, xbar, vbar, abar, g_mass,
+                      n, keep);
+    if (s) return s;
+    // bad input found by the slot builds is reported like the context's own
+    if (keep)
+        BHX_HIP(c, bhx::launch_merge_status(c->stream, aw.trees.hdr, nsteps, &c->w.hdr->status));
+    return BH_OK;
 }
 
 bh_status bh_leapfrog_vjp_stored(bh_ctx *c, const double *traj, const double *mass,

@@ -1364,7 +1364,43 @@ void enqueue_levels(const Workspace &w, hipStream_t s, const Layout &lay, int le
                                           w.nmom, w.neps2, w.nquad, w.node_cap, ue, w.depth_dev);
 }
 
+__global__ __launch_bounds__(64) void k_merge_status(TreeHeader *__restrict__ slot_hdr, int count,
+                                                     uint32_t *__restrict__ status)
+{
+    for (int k = threadIdx.x; k < count; k += 64) {
+        const uint32_t st = slot_hdr[k].status;
+        if (st) {
+            atomicOr(status, st);
+            slot_hdr[k].status = 0u;
+        }
+    }
+}
+
 }  // namespace
+
+Workspace slot_view(const Workspace &w, const TreeSlots &t, int k)
+{
+    Workspace v = w;
+    v.body = t.body + (int64_t)k * t.n;
+    v.beps2 = t.beps2 + (int64_t)k * t.n;
+    v.idx[0] = t.idx + (int64_t)k * t.n;
+    v.keys[0] = t.keys + (int64_t)k * t.n;
+    v.ninfo = t.ninfo + (int64_t)k * t.node_cap;
+    v.nmom = t.nmom + (int64_t)k * t.node_cap;
+    v.neps2 = t.neps2 + (int64_t)k * t.node_cap;
+    v.node_cap = t.node_cap;
+    v.box = t.box + k;
+    v.hdr = t.hdr + k;
+    v.max_scenes = 1;
+    return v;
+}
+
+hipError_t launch_merge_status(hipStream_t s, TreeHeader *slot_hdr, int count, uint32_t *status)
+{
+    if (count <= 0) return hipSuccess;
+    k_merge_status<<<1, 64, 0, s>>>(slot_hdr, count, status);
+    return hipGetLastError();
+}
 
 bool bucket_sort_hint(const Workspace &w, const Layout &lay)
 {

@@ -233,3 +233,24 @@ def test_rollout_65536_properties(api, precision):
     ((x2 - _dev(xt)) ** 2).sum().backward()
     for g1, g2 in zip(g_ckpt, (X0.grad, V0.grad, Mt.grad)):
         assert float((g1 - g2).abs().max()) <= 1e-10 * float(g1.abs().max())
+
+
+def test_segment_vjp_reports_bad_input(api):
+    """The trees a segment VJP keeps have their own status words: bad input
+    they meet is still reported at the next synchronisation."""
+    n = 6000
+    s = ics.uniform_ball(n, seed=71)
+    ctx = api.Context(n, leaf_size=16, precision="fp64", adjoint=True)
+    x, v, m = _dev(s.pos), _dev(s.vel), _dev(s.mass)
+    a = ctx.compute_accel(x, m, 0.5, softening=1e-3)
+    z = torch.zeros_like(x)
+    traj = torch.empty((3, n, 3), dtype=torch.float64, device="cuda")
+    bad = m.clone()
+    bad[123] = float("nan")
+    with pytest.raises(api.BHError, match="BH_E_NONFINITE"):
+        ctx.leapfrog_vjp(x, v, a, bad, 1e-3, 3, traj, z.clone(), z.clone(), z.clone(),
+                         torch.zeros_like(m), theta=0.5, softening=1e-3)
+    gm = torch.zeros_like(m)
+    ctx.leapfrog_vjp(x, v, a, m, 1e-3, 3, traj, z.clone(), z.clone(), torch.ones_like(x), gm,
+                     theta=0.5, softening=1e-3)  # the latch was cleared
+    assert torch.isfinite(gm).all()
