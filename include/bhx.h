@@ -299,8 +299,13 @@ bh_status bh_accel_vjp(bh_ctx *ctx, const double *pos, const double *mass, doubl
  * bh_accel_vjp-equivalent product is taken per step (at the positions after
  * it) and its mass gradient ADDED to g_mass. The dependence of acc on pos is
  * left to the caller (a bh_accel_vjp at the rollout's first positions with
- * the final abar). Needs BH_FLAG_ADJOINT. Errors: as bh_step_leapfrog, plus
- * BH_E_INVALID for NULL traj, xbar, vbar, abar or g_mass. */
+ * the final abar). With the tree, the context keeps the tree of each
+ * recomputed step for the product at the same positions instead of building
+ * it again: the first call allocates nsteps slots of about 52 B per body and
+ * 56 B per node of the node-table bound when the device has twice that free
+ * (else the products rebuild), held until bh_destroy. Needs BH_FLAG_ADJOINT.
+ * Errors: as bh_step_leapfrog, plus BH_E_INVALID for NULL traj, xbar, vbar,
+ * abar or g_mass. */
 bh_status bh_leapfrog_vjp(bh_ctx *ctx, const double *pos, const double *vel, const double *acc,
                           const double *mass, double softening, const double *eps, double theta,
                           double dt, int32_t nsteps, double *traj, double *xbar, double *vbar,
