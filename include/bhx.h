@@ -57,7 +57,9 @@ typedef enum {
     BH_E_HIP = 5,       /* a HIP runtime call failed; see bh_last_error() */
     BH_E_STACK = 6,     /* reserved: an unknown device status; the walk's traversal stack is
                            sized so that trees of at most 21 levels cannot overflow it */
-    BH_E_STATE = 7      /* call out of order, e.g. bh_tree_export() before any build */
+    BH_E_STATE = 7,     /* call out of order, e.g. bh_tree_export() before any build */
+    BH_E_CHECK = 8      /* only from libbhx_checked.so (the same library with device-side
+                           invariant checks): a check failed (bh_last_error names it) */
 } bh_status;
 
 /* precision of the pairwise terms */

@@ -6,12 +6,16 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libbhx.so")
+# BHX_LIBRARY=checked loads libbhx_checked.so, the build with device-side
+# invariant checks (failures reported as BH_E_CHECK)
+LIB_PATH = os.path.join(HERE, "libbhx_checked.so" if os.environ.get("BHX_LIBRARY") == "checked"
+                        else "libbhx.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "bhx.h")
 
-BH_OK, BH_E_INVALID, BH_E_NONFINITE, BH_E_CAPACITY, BH_E_OOM, BH_E_HIP, BH_E_STACK, BH_E_STATE = range(8)
+(BH_OK, BH_E_INVALID, BH_E_NONFINITE, BH_E_CAPACITY, BH_E_OOM, BH_E_HIP, BH_E_STACK, BH_E_STATE,
+ BH_E_CHECK) = range(9)
 STATUS_NAMES = ["BH_OK", "BH_E_INVALID", "BH_E_NONFINITE", "BH_E_CAPACITY", "BH_E_OOM",
-                "BH_E_HIP", "BH_E_STACK", "BH_E_STATE"]
+                "BH_E_HIP", "BH_E_STACK", "BH_E_STATE", "BH_E_CHECK"]
 BH_FP64, BH_FP32C = 0, 1
 BH_FLAG_COUNTS = 1
 BH_FLAG_TIMING = 2

@@ -245,7 +245,8 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
             const int32_t a = dq_a[d];
             mk = dq_mask[d];
             if (a >= 0) {
-                const int32_t src = a + (int32_t)(q - dq_at[d]);
+                int32_t src = a + (int32_t)(q - dq_at[d]);
+                if (!check_ok(src < n, CK_INDEX)) src = 0;
                 const int64_t rel = (int64_t)src - g0;
                 if (rel >= 0 && rel < GB) mk &= ~(1ull << rel);
                 const Body b = body[src];
@@ -266,6 +267,7 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
         const int nd = __popcll(db);
         const int ns = __popcll(fb);
         const int np = fb ? __builtin_amdgcn_readlane((int)pend, 63 - __builtin_clzll(fb)) : 0;
+        BHX_CHECK(np <= kPairCap, CK_PAIRS);
         if (dense || (fits && pk > 0)) {
             const int slot = dense ? (int)lanes_below(db) : nd + (int)lanes_below(fb);
             items[slot] = ld_it;
@@ -397,6 +399,7 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
     while (sp > 0) {
         walkx::traverse_round<GB>(L, pc, pd, sp, dq_tail, queued, ninfo, nmom, glo, ghi, me.x, me.y,
                                   me.z, th2);
+        BHX_CHECK(dq_tail - dq_head <= kRing, CK_RING);
         while (queued - consumed >= (uint32_t)kBatch) evaluate(kBatch);
     }
     while (queued != consumed) evaluate((int)min(queued - consumed, (uint32_t)kBatch));
@@ -696,6 +699,8 @@ inline unsigned blocks(int64_t items, unsigned cap = 1u << 30)
 }
 
 }  // namespace
+
+BHX_DEFINE_TAKE_CHECKS(adjoint_take_checks)
 
 hipError_t launch_tree_vjp(const Workspace &w, const AdjointWork &aw, hipStream_t s,
                            const WalkParams &p, const double *lambda, double *g_pos,

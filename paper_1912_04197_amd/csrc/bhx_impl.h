@@ -8,6 +8,7 @@
 #include <cstdint>
 
 #include "bhx.h"
+#include "checks.h"
 
 namespace bhx {
 

@@ -767,6 +767,19 @@ bh_status bh_sync(bh_ctx *c)
     BHX_HIP(c, hipMemcpyAsync(&st, &c->w.hdr->status, sizeof(st), hipMemcpyDeviceToHost,
                               c->stream));
     BHX_HIP(c, hipStreamSynchronize(c->stream));
+    uint32_t ck = 0;  // device checks (checked build only)
+    BHX_HIP(c, bhx::walk_take_checks(&ck));
+    BHX_HIP(c, bhx::adjoint_take_checks(&ck));
+    BHX_HIP(c, bhx::tree_take_checks(&ck));
+    if (ck) {
+        static const char *names[] = {"traversal stack", "interaction ring", "pair list",
+                                      "index bounds", "key order", "child partition",
+                                      "bucket range"};
+        std::string msg = "device check failed:";
+        for (int b = 0; b < 7; b++)
+            if (ck & (1u << b)) msg += std::string(" ") + names[b];
+        return fail(c, BH_E_CHECK, msg);
+    }
     if (st == 0) return BH_OK;
     const uint32_t zero = 0;
     BHX_HIP(c, hipMemcpyAsync(&c->w.hdr->status, &zero, sizeof(zero), hipMemcpyHostToDevice,

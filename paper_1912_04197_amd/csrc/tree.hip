@@ -689,6 +689,19 @@ __global__ __launch_bounds__(Sh::kThreads) void k_sort_local(uint64_t *__restric
     }
 }
 
+#ifdef BHX_CHECKS
+// The checked build's verification of a one-scene sort: keys in order and
+// every index inside the array.
+__global__ __launch_bounds__(256) void k_check_order(const uint64_t *__restrict__ keys,
+                                                     const uint32_t *__restrict__ idx, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    BHX_CHECK(idx[i] < n, CK_INDEX);
+    BHX_CHECK(i == 0 || keys[i - 1] <= keys[i], CK_ORDER);
+}
+#endif
+
 // ------------------------------------------------------------- 4. gather
 
 __global__ __launch_bounds__(256) void k_gather(const double *__restrict__ pos,
@@ -701,6 +714,7 @@ __global__ __launch_bounds__(256) void k_gather(const double *__restrict__ pos,
     int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= n) return;
     uint32_t i = idx[s];
+    if (!check_ok(i < n, CK_INDEX)) i = 0;
     body[s] = Body{pos[3 * (int64_t)i], pos[3 * (int64_t)i + 1], pos[3 * (int64_t)i + 2], mass[i]};
     if (eps) {
         double e = eps[i];
@@ -721,7 +735,8 @@ __global__ __launch_bounds__(256) void k_gather_state(const Body *__restrict__ s
 {
     int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= n) return;
-    const int64_t p = idx[s];
+    int64_t p = idx[s];
+    if (!check_ok(p < n, CK_INDEX)) p = 0;
     body[s] = sbody[p];
     for (int a = 0; a < 3; a++) tvel[3 * s + a] = svel[3 * p + a];
     if (seps2) beps2[s] = seps2[p];
@@ -812,6 +827,9 @@ __device__ inline void build_nodes(int level, const uint64_t *__restrict__ keys,
         }
         int32_t end = __shfl_down(start, 1, 8);
         if (o == 7) end = info.first + info.count;
+        BHX_CHECK(!split || (start >= info.first && start <= end &&
+                             end <= info.first + info.count),
+                  CK_PARTITION);
         const bool nonempty = split && end > start;
         const uint32_t gm = (uint32_t)(__ballot(nonempty) >> gl) & 0xffu;
         const int nch = __popc(gm);
@@ -1302,6 +1320,9 @@ bool enqueue_keys_sort(const Workspace &w, hipStream_t s, const Layout &lay, con
             k_sort_local<LocalSmall>
                 <<<(unsigned)((n + LocalSmall::kTile - 1) / LocalSmall::kTile),
                    LocalSmall::kThreads, 0, s>>>(w.keys[0], w.idx[0], w.keys[1], w.idx[1], n);
+#ifdef BHX_CHECKS
+        k_check_order<<<nb0, 256, 0, s>>>(w.keys[0], w.idx[0], n);
+#endif
         return true;
     }
     // 8 passes on the Morton key, then (several scenes) one on each byte of
@@ -1320,6 +1341,9 @@ bool enqueue_keys_sort(const Workspace &w, hipStream_t s, const Layout &lay, con
                                                      lay.offsets, ns, w.keys[dst], w.idx[dst], n,
                                                      shift, w.sort_counts, w.sort_totals, nblk);
     }
+#ifdef BHX_CHECKS
+    if (ns == 1) k_check_order<<<nb0, 256, 0, s>>>(w.keys[0], w.idx[0], n);
+#endif
     return false;
 }
 
@@ -1377,6 +1401,8 @@ __global__ __launch_bounds__(64) void k_merge_status(TreeHeader *__restrict__ sl
 }
 
 }  // namespace
+
+BHX_DEFINE_TAKE_CHECKS(tree_take_checks)
 
 Workspace slot_view(const Workspace &w, const TreeSlots &t, int k)
 {

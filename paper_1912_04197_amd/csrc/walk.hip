@@ -233,6 +233,7 @@ __global__ __launch_bounds__(64) void k_walk(
             mk = dq_mask[d];
             if (a >= 0) {
                 src = a + (int32_t)(q - dq_at[d]);
+                if (!check_ok(src < n, CK_INDEX)) src = 0;
                 const int64_t rel = (int64_t)src - g0;
                 if (rel >= 0 && rel < GB) mk &= ~(1ull << rel);  // not itself
                 const Body b = body[src];
@@ -260,6 +261,7 @@ __global__ __launch_bounds__(64) void k_walk(
         const uint64_t fb = __ballot(fits && pk > 0);
         const int nd = __popcll(db);
         const int np = fb ? __builtin_amdgcn_readlane((int)pend, 63 - __builtin_clzll(fb)) : 0;
+        BHX_CHECK(np <= kPairCap, CK_PAIRS);
         if (dense || (fits && pk > 0)) {
             const int slot = dense ? (int)lanes_below(db) : nd + (int)lanes_below(fb);
             if constexpr (PREC == BH_FP64) {
@@ -446,6 +448,7 @@ __global__ __launch_bounds__(64) void k_walk(
     while (sp > 0) {
         walkx::traverse_round<GB>(L, pc, pd, sp, dq_tail, queued, ninfo, nmom, glo, ghi, me.x, me.y,
                                   me.z, th2);
+        BHX_CHECK(dq_tail - dq_head <= kRing, CK_RING);
         while (queued - consumed >= (uint32_t)kBatch) evaluate(kBatch);
     }
     while (queued != consumed) evaluate((int)min(queued - consumed, (uint32_t)kBatch));
@@ -526,6 +529,8 @@ hipError_t launch_p(const Workspace &w, hipStream_t s, const WalkParams &p)
 }
 
 }  // namespace
+
+BHX_DEFINE_TAKE_CHECKS(walk_take_checks)
 
 hipError_t launch_walk(const Workspace &w, hipStream_t s, const WalkParams &p)
 {

@@ -180,9 +180,11 @@ __device__ inline void traverse_round(Lds<kStack, kRing> &L, PopCom *pc, PopData
     const uint64_t pushb = __ballot(O != 0);
     if (O != 0) {
         const int e = sp + (int)lanes_below(pushb);
-        L.st_c0[e] = my.child0;
-        L.st_n[e] = (uint8_t)my.nch;
-        L.st_mask[e] = O;
+        if (check_ok(e < kStack, CK_STACK)) {
+            L.st_c0[e] = my.child0;
+            L.st_n[e] = (uint8_t)my.nch;
+            L.st_mask[e] = O;
+        }
     }
     sp += __popcll(pushb);
     const bool hasq = leaf || A != 0;

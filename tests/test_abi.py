@@ -31,6 +31,17 @@ def test_header_symbols_exported(lib):
     assert set(declared) == set(L.SIGNATURES), "binding and header disagree"
 
 
+def test_checked_library_exports_the_same_symbols():
+    """libbhx_checked.so (device-side invariant checks) is the same C ABI."""
+    checked = os.path.join(os.path.dirname(L.LIB_PATH), "libbhx_checked.so")
+    if not os.path.exists(checked):
+        pytest.fail("libbhx_checked.so is not built (run __graft_entry__.build())")
+    out = subprocess.run(["nm", "-D", "--defined-only", checked], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    assert set(L.header_symbols()) <= exported
+
+
 def test_struct_layouts_match_header(tmp_path):
     """The ctypes mirrors agree with the C compiler's layout of include/bhx.h."""
     fields = {"bh_config": L.bh_config, "bh_tree_view": L.bh_tree_view, "bh_stats_t": L.bh_stats_t,
@@ -41,7 +52,9 @@ def test_struct_layouts_match_header(tmp_path):
         for fname, _ in cls._fields_:
             lines.append(f'printf("%zu\\n", offsetof({sname}, {fname}));')
     consts = ["BH_FP64", "BH_FP32C", "BH_FLAG_COUNTS", "BH_FLAG_TIMING", "BH_FLAG_ADJOINT",
-              "BH_FLAG_GRAPH", "BH_FLAG_QUAD", "BH_FLAG_MARKERS"]
+              "BH_FLAG_GRAPH", "BH_FLAG_QUAD", "BH_FLAG_MARKERS", "BH_OK", "BH_E_INVALID",
+              "BH_E_NONFINITE", "BH_E_CAPACITY", "BH_E_OOM", "BH_E_HIP", "BH_E_STACK",
+              "BH_E_STATE", "BH_E_CHECK"]
     for k in consts:
         lines.append(f'printf("%zu\\n", (size_t){k});')
     lines.append("return 0;}")
