@@ -760,108 +760,149 @@ __device__ inline void level_range(const int32_t *counts, int level, int64_t nod
     *cnt = (int32_t)(c < node_cap - b ? c : node_cap - b);
 }
 
-// Splits every node of `level` holding more than `leaf` bodies. Eight lanes
-// per node: lane o binary-searches the first body of octant o; the non-empty
-// children are written contiguously in octant order. All nodes a block holds
-// in one loop step reserve their children with a single atomic on the next
-// level's count (scans over the wave and over the block's waves give each
-// node its offset): on a level of many nodes, one atomic per node or per wave
-// serialises on that counter. Must be called by every thread of the block
-// (a multiple of 64 threads, at most 1024); every thread runs the same loop
-// iterations. `counts` is the per-level node count array: the tree header's,
-// or a copy in LDS that a single-block kernel keeps and writes back. g_first
-// is the node of this thread's group of eight, stride the nodes per step.
+// Splits every node of `level` holding more than `leaf` bodies, eight lanes
+// per node (one chunk: blockDim / 8 nodes): lane o finds the first body of
+// octant o, and the non-empty children are written contiguously in octant
+// order. A step of the block takes one chunk of nodes; or, `compact` (levels
+// where most nodes are leaves), one node per thread, of which the ones that
+// split are listed in LDS and split chunk by chunk, so that a leaf costs one
+// load. All nodes of a chunk reserve their children with a single atomic on
+// the next level's count (scans over the wave and over the block's waves give
+// each node its offset): one atomic per node or per wave serialises on that
+// counter. Must be called by every thread of the block (a multiple of 64
+// threads, at most 1024); every thread runs the same loop iterations.
+// `counts` is the per-level node count array: the tree header's, or a copy
+// in LDS that a single-block kernel keeps and writes back. The block's steps
+// start at nodes b_first + j stride, j = 0, 1, ... (b_first = block index x
+// nodes per step; stride = that times the number of blocks).
 // Nodes of at most this many bodies find their octant ranges by counting
 // (each octant's count fits a byte), larger ones by binary search.
 constexpr int32_t kLinearSplit = 64;
 
+template <bool compact>
 __device__ inline void build_nodes(int level, const uint64_t *__restrict__ keys, int32_t *counts,
                                    uint32_t *status, int32_t *cell_max,
                                    NodeInfo *__restrict__ ninfo, int64_t node_cap, int leaf,
-                                   int64_t g_first, int64_t stride)
+                                   int64_t b_first, int64_t stride)
 {
     __shared__ uint32_t s_wtot[16];
     __shared__ int32_t s_base;
     __shared__ int32_t s_cmax;
+    __shared__ int32_t s_list[compact ? 1024 : 1];  // the step's nodes that split
     int32_t beg, cnt;
     level_range(counts, level, node_cap, &beg, &cnt);
     const int32_t next_beg = beg + cnt;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
     const int o = threadIdx.x & 7, gl = lane & ~7;
     const int shift = 60 - 3 * level;  // bits of the child octant at level + 1
-    const int64_t b_first = g_first - (threadIdx.x >> 3);  // first node of this block's step
     // level kHintLevel: the block's largest node, merged into cell_max once
     int32_t cmax = 0;
     if (level == kHintLevel && threadIdx.x == 0) s_cmax = 0;
-    for (int64_t gb = b_first; gb < cnt; gb += stride) {
-        const int64_t g = gb + (threadIdx.x >> 3);
-        const bool live = g < cnt;
-        const int32_t k = beg + (int32_t)(live ? g : gb);
-        const NodeInfo info = ninfo[k];
-        const bool split = live && info.count > leaf && level < kMaxLevel;
-        if (level == kHintLevel && live) cmax = max(cmax, info.count);
-        int32_t start;
-        if (info.count <= kLinearSplit) {
-            // few bodies: the 8 lanes read them all (independent loads) and
-            // count them per octant, one byte per octant, summed over the
-            // group; octant o starts after the bodies of octants below it
-            uint64_t hist = 0;
-            if (split)
-                for (int32_t j = o; j < info.count; j += 8)
-                    hist += 1ull << (8 * (int)((keys[info.first + j] >> shift) & 7ull));
-            hist += __shfl_xor(hist, 1, 8);
-            hist += __shfl_xor(hist, 2, 8);
-            hist += __shfl_xor(hist, 4, 8);
-            const uint64_t below = o == 0 ? 0ull : hist & (~0ull >> (64 - 8 * o));
-            start = info.first + (split ? (int32_t)((below * 0x0101010101010101ull) >> 56) : 0);
-        } else {
-            int32_t a = info.first, b = split ? info.first + info.count : info.first;
-            while (a < b) {
-                int32_t m = (a + b) >> 1;
-                if ((int)((keys[m] >> shift) & 7ull) < o)
-                    a = m + 1;
-                else
-                    b = m;
+    const uint32_t chunk = blockDim.x >> 3;
+    for (int64_t b0 = b_first; b0 < cnt; b0 += stride) {
+        uint32_t nlist;  // nodes of the step to give eight lanes each
+        if constexpr (compact) {
+            // one node per thread: list the ones that split
+            const int64_t g = b0 + threadIdx.x;
+            bool splits = false;
+            if (g < cnt) {
+                const int32_t c = ninfo[beg + (int32_t)g].count;
+                splits = c > leaf && level < kMaxLevel;
+                if (level == kHintLevel) cmax = max(cmax, c);
             }
-            start = a;
+            const uint64_t sb = __ballot(splits);
+            if (lane == 0) s_wtot[wave] = (uint32_t)__popcll(sb);
+            __syncthreads();
+            uint32_t lbefore = 0;
+            nlist = 0;
+            for (int w = 0; w < nwaves; w++) {
+                const uint32_t t = s_wtot[w];
+                if (w < wave) lbefore += t;
+                nlist += t;
+            }
+            if (splits) s_list[lbefore + lanes_below(sb)] = beg + (int32_t)g;
+            __syncthreads();  // the list is complete and s_wtot free again
+        } else {
+            nlist = (uint32_t)min((int64_t)chunk, cnt - b0);
         }
-        int32_t end = __shfl_down(start, 1, 8);
-        if (o == 7) end = info.first + info.count;
-        BHX_CHECK(!split || (start >= info.first && start <= end &&
-                             end <= info.first + info.count),
-                  CK_PARTITION);
-        const bool nonempty = split && end > start;
-        const uint32_t gm = (uint32_t)(__ballot(nonempty) >> gl) & 0xffu;
-        const int nch = __popc(gm);
-        const int rank = __popc(gm & ((1u << o) - 1u));
-        const uint32_t mine = o == 0 ? (uint32_t)nch : 0u;
-        const uint32_t incl = wave_incl_scan(mine);
-        if (lane == 63) s_wtot[wave] = incl;
-        __syncthreads();
-        uint32_t before = 0, btot = 0;
-        for (int w = 0; w < nwaves; w++) {
-            const uint32_t t = s_wtot[w];
-            if (w < wave) before += t;
-            btot += t;
+        for (uint32_t c0 = 0; c0 < nlist; c0 += chunk) {
+            const uint32_t gi = c0 + (threadIdx.x >> 3);
+            const bool live = gi < nlist;
+            const uint32_t gl_node = live ? gi : c0;
+            int32_t k;
+            if constexpr (compact)
+                k = s_list[gl_node];
+            else
+                k = beg + (int32_t)(b0 + gl_node);
+            const NodeInfo info = ninfo[k];
+            if (!compact && level == kHintLevel && live) cmax = max(cmax, info.count);
+            const bool split = live && info.count > leaf && level < kMaxLevel;
+            int32_t start;
+            if (info.count <= kLinearSplit) {
+                // few bodies: the 8 lanes read them all (independent loads) and
+                // count them per octant, one byte per octant, summed over the
+                // group; octant o starts after the bodies of octants below it
+                uint64_t hist = 0;
+                if (split)
+                    for (int32_t j = o; j < info.count; j += 8)
+                        hist += 1ull << (8 * (int)((keys[info.first + j] >> shift) & 7ull));
+                hist += __shfl_xor(hist, 1, 8);
+                hist += __shfl_xor(hist, 2, 8);
+                hist += __shfl_xor(hist, 4, 8);
+                const uint64_t below = o == 0 ? 0ull : hist & (~0ull >> (64 - 8 * o));
+                start = info.first + (split ? (int32_t)((below * 0x0101010101010101ull) >> 56) : 0);
+            } else {
+                int32_t a = info.first, b = split ? info.first + info.count : info.first;
+                while (a < b) {
+                    int32_t m = (a + b) >> 1;
+                    if ((int)((keys[m] >> shift) & 7ull) < o)
+                        a = m + 1;
+                    else
+                        b = m;
+                }
+                start = a;
+            }
+            int32_t end = __shfl_down(start, 1, 8);
+            if (o == 7) end = info.first + info.count;
+            BHX_CHECK(!split || (start >= info.first && start <= end &&
+                                 end <= info.first + info.count),
+                      CK_PARTITION);
+            const bool nonempty = split && end > start;
+            const uint32_t gm = (uint32_t)(__ballot(nonempty) >> gl) & 0xffu;
+            const int nch = __popc(gm);
+            const int rank = __popc(gm & ((1u << o) - 1u));
+            const uint32_t mine = o == 0 ? (uint32_t)nch : 0u;
+            const uint32_t incl = wave_incl_scan(mine);
+            if (lane == 63) s_wtot[wave] = incl;
+            __syncthreads();
+            uint32_t before = 0, btot = 0;
+            for (int w = 0; w < nwaves; w++) {
+                const uint32_t t = s_wtot[w];
+                if (w < wave) before += t;
+                btot += t;
+            }
+            if (threadIdx.x == 0 && btot > 0)
+                s_base = atomicAdd(&counts[level + 1], (int32_t)btot);
+            __syncthreads();
+            const int32_t base = btot > 0 ? s_base : 0;
+            const int32_t slot =
+                base + (int32_t)(before + __shfl(incl, gl) - __shfl(mine, gl));
+            __syncthreads();  // s_wtot and s_base are rewritten by the next chunk
+            if (!split) continue;
+            const int64_t cfirst = (int64_t)next_beg + slot;
+            if (cfirst + nch > node_cap) {
+                if (o == 0) atomicOr(status, ST_CAPACITY);
+                continue;
+            }
+            const int32_t scene_bits = info.lvl_nch & (int32_t)0xffff0000;
+            if (nonempty)
+                ninfo[cfirst + rank] = NodeInfo{start, end - start, -1, (level + 1) | scene_bits};
+            if (o == 0) {
+                ninfo[k].child0 = (int32_t)cfirst;
+                ninfo[k].lvl_nch = level | (nch << 8) | scene_bits;
+            }
         }
-        if (threadIdx.x == 0 && btot > 0) s_base = atomicAdd(&counts[level + 1], (int32_t)btot);
-        __syncthreads();
-        const int32_t base = btot > 0 ? s_base : 0;
-        const int32_t slot =
-            base + (int32_t)(before + __shfl(incl, gl) - __shfl(mine, gl));
-        __syncthreads();  // s_wtot and s_base are rewritten by the next step
-        if (!split) continue;
-        const int64_t c0 = (int64_t)next_beg + slot;
-        if (c0 + nch > node_cap) {
-            if (o == 0) atomicOr(status, ST_CAPACITY);
-            continue;
-        }
-        const int32_t scene_bits = info.lvl_nch & (int32_t)0xffff0000;
-        if (nonempty) ninfo[c0 + rank] = NodeInfo{start, end - start, -1, (level + 1) | scene_bits};
-        if (o == 0) {
-            ninfo[k].child0 = (int32_t)c0;
-            ninfo[k].lvl_nch = level | (nch << 8) | scene_bits;
-        }
+        if constexpr (compact) __syncthreads();  // s_list is rewritten by the next step
     }
     if (level == kHintLevel) {  // the same on every thread
         for (int off = 32; off > 0; off >>= 1) cmax = max(cmax, __shfl_xor(cmax, off));
@@ -872,19 +913,21 @@ __device__ inline void build_nodes(int level, const uint64_t *__restrict__ keys,
     }
 }
 
+template <bool compact>
 __global__ __launch_bounds__(1024) void k_build_level(int level, const uint64_t *__restrict__ keys,
                                                       TreeHeader *__restrict__ hdr,
                                                       NodeInfo *__restrict__ ninfo,
                                                       int64_t node_cap, int leaf)
 {
-    const int64_t per_block = blockDim.x >> 3;  // nodes per block and step
-    build_nodes(level, keys, hdr->level_count, &hdr->status, &hdr->cell_max, ninfo, node_cap, leaf,
-                (int64_t)blockIdx.x * per_block + (threadIdx.x >> 3),
-                (int64_t)gridDim.x * per_block);
+    const int64_t per_step = compact ? blockDim.x : blockDim.x >> 3;  // nodes per block step
+    build_nodes<compact>(level, keys, hdr->level_count, &hdr->status, &hdr->cell_max, ninfo,
+                         node_cap, leaf, (int64_t)blockIdx.x * per_step,
+                         (int64_t)gridDim.x * per_step);
 }
 
 // Levels from..upto-1 in one block, on a copy of the node counts in LDS
 // (no other kernel runs meanwhile); stops at the first empty level.
+template <bool compact>
 __device__ inline void build_levels_block(int from, int upto, const uint64_t *__restrict__ keys,
                                           TreeHeader *__restrict__ hdr,
                                           NodeInfo *__restrict__ ninfo, int64_t node_cap,
@@ -892,8 +935,8 @@ __device__ inline void build_levels_block(int from, int upto, const uint64_t *__
 {
     for (int level = from; level < upto; level++) {
         if (scnt[level] == 0) break;
-        build_nodes(level, keys, scnt, &hdr->status, &hdr->cell_max, ninfo, node_cap, leaf,
-                    threadIdx.x >> 3, blockDim.x >> 3);
+        build_nodes<compact>(level, keys, scnt, &hdr->status, &hdr->cell_max, ninfo, node_cap, leaf,
+                             0, compact ? blockDim.x : blockDim.x >> 3);
         __syncthreads();
     }
 }
@@ -907,7 +950,7 @@ __global__ __launch_bounds__(1024) void k_build_tail(int from, const uint64_t *_
     __shared__ int32_t scnt[kLevels + 1];
     if (threadIdx.x <= kLevels) scnt[threadIdx.x] = hdr->level_count[threadIdx.x];
     __syncthreads();
-    build_levels_block(from, kMaxLevel, keys, hdr, ninfo, node_cap, leaf, scnt);
+    build_levels_block<true>(from, kMaxLevel, keys, hdr, ninfo, node_cap, leaf, scnt);
     __syncthreads();
     if (threadIdx.x <= kLevels) hdr->level_count[threadIdx.x] = scnt[threadIdx.x];
 }
@@ -1234,7 +1277,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_build_small(
     __syncthreads();
 
     // 5. tree, top-down, with the node counts and the sorted keys in LDS
-    build_levels_block(0, kMaxLevel, skey[0], hdr, ninfo, node_cap, leaf, scnt);
+    build_levels_block<false>(0, kMaxLevel, skey[0], hdr, ninfo, node_cap, leaf, scnt);
     __syncthreads();
     // 6. moments, bottom-up
     for (int level = kMaxLevel; level >= 0; level--) {
@@ -1359,19 +1402,26 @@ void enqueue_levels(const Workspace &w, hipStream_t s, const Layout &lay, int le
     // 0..head-1, at most 585 nodes) in one block too. (Splitting the top
     // levels in one block was measured slower: its binary searches over all
     // bodies run four passes deep there.) The split only affects speed.
-    int deep = kMaxLevel;
+    int deep = kMaxLevel, prev = -1;
     if (w.depth_host) {
-        const int prev = *(const volatile int32_t *)w.depth_host;
+        prev = *(const volatile int32_t *)w.depth_host;
         if (prev >= 0 && prev + 1 < deep) deep = prev + 1;
     }
     const int head = ns == 1 ? (deep < 4 ? deep : 4) : 0;
     for (int level = 0; level < deep; level++) {
-        // levels of many nodes take 1024-thread blocks (fewer reservations on
-        // the level counter), small ones 256 (more CUs for their searches)
-        const int64_t threads = level_bound(level, n, ns) * 8;
+        // the three deepest levels the previous build reported hold mostly
+        // leaves: one thread per node, the splitting ones listed; above, eight
+        // lanes per node. Levels of many nodes take 1024-thread blocks (fewer
+        // reservations on the level counter), small ones 256 (more CUs for
+        // their searches). The choice only affects speed.
+        const bool compact = prev >= 0 && level >= prev - 2;
+        const int64_t threads = level_bound(level, n, ns) * (compact ? 1 : 8);
         const int bs = threads >= 65536 ? 1024 : 256;
         const unsigned g = blocks_for(threads, bs, bs == 1024 ? 1024 : 4096);
-        k_build_level<<<g, bs, 0, s>>>(level, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
+        if (compact)
+            k_build_level<true><<<g, bs, 0, s>>>(level, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
+        else
+            k_build_level<false><<<g, bs, 0, s>>>(level, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
     }
     if (deep < kMaxLevel)
         k_build_tail<<<1, 1024, 0, s>>>(deep, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
