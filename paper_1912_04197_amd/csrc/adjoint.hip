@@ -45,8 +45,9 @@ struct alignas(16) ItemV {  // staged source
     double e2;      // source's squared softening (eps_j^2 or <eps^2>_N)
     uint64_t mask;
     int32_t src;    // sorted body index, or ~node
-    int32_t pad0;
-    int64_t pad1;
+    float gm;       // G m rounded to FP32 (FP32C terms)
+    float e2h;      // half the squared softening rounded to FP32 (FP32C terms)
+    int32_t pad;
 };
 // Lane exchanges inside a row of 16 lanes (DPP): quad_perm [1,0,3,2] is
 // lane ^ 1, quad_perm [2,3,0,1] is lane ^ 2, row_ror:4 and row_ror:8 rotate
@@ -131,6 +132,7 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
     const bool valid = s < n;
     const Body me = body[valid ? s : g0];
     const double eb2 = PEPS ? beps2[valid ? s : g0] : 0.0;
+    const float ebhf = (float)(0.5 * eb2);  // FP32C: half the target's squared softening
     double lx = 0.0, ly = 0.0, lz = 0.0;
     if (valid) {
         const int64_t o = idx[s];
@@ -163,19 +165,21 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
     // minus the first three source-side components. In FP32C the offset is the
     // FP64 difference rounded once and the rest of the term is FP32; the term
     // counts when its r^2 is a positive normal number of the precision used.
-    auto term = [&](const ItemV &it, double bx, double by, double bz, double eb, VT ux, VT uy,
-                    VT uz, bool on, VT out[5]) {
+    // In FP32C the pair softening is the sum of the two halves rounded to
+    // FP32 (ebh: the target's), as in the forward FP32C walk.
+    auto term = [&](const ItemV &it, double bx, double by, double bz, double eb, float ebh, VT ux,
+                    VT uy, VT uz, bool on, VT out[5]) {
         out[0] = out[1] = out[2] = out[3] = out[4] = VT(0);
         if constexpr (F32) {
             const float dx = (float)(it.x - bx), dy = (float)(it.y - by), dz = (float)(it.z - bz);
-            const float e2 = PEPS ? (float)(0.5 * (eb + it.e2)) : (float)eps0sq;
+            const float e2 = PEPS ? it.e2h + ebh : (float)eps0sq;
             const float r2 = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, e2)));
             if (on && positive_normal_f(r2)) {
                 const float rinv = __builtin_amdgcn_rsqf(r2), inv2 = rinv * rinv;
                 const float inv3 = inv2 * rinv;
                 const float inv5 = inv3 * inv2;
                 const float ld = ux * dx + uy * dy + uz * dz;
-                const float gms = (float)(G * it.m);
+                const float gms = it.gm;
                 const float c = 3.0f * ld * inv5;
                 out[0] = gms * (ux * inv3 - dx * c);
                 out[1] = gms * (uy * inv3 - dy * c);
@@ -221,7 +225,7 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
 
     auto evaluate = [&](int c) {
         uint64_t mk = 0;
-        ItemV ld_it{0.0, 0.0, 0.0, 0.0, 0.0, 0ull, 0, 0, 0};
+        ItemV ld_it{0.0, 0.0, 0.0, 0.0, 0.0, 0ull, 0, 0.f, 0.f, 0};
         // The descriptor of item consumed + lane: each descriptor that starts
         // inside the batch flags its first item (only the head descriptor can
         // start at item 0, and it may also start before the batch), so item
@@ -250,10 +254,14 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
                 const int64_t rel = (int64_t)src - g0;
                 if (rel >= 0 && rel < GB) mk &= ~(1ull << rel);
                 const Body b = body[src];
-                ld_it = ItemV{b.x, b.y, b.z, b.m, PEPS ? beps2[src] : 0.0, mk, src, 0, 0};
+                const double e2 = PEPS ? beps2[src] : 0.0;
+                ld_it = ItemV{b.x,  b.y, b.z, b.m, e2, mk, src, (float)(G * b.m),
+                              (float)(0.5 * e2), 0};
             } else {
                 const NodeMom nm = nmom[~a];
-                ld_it = ItemV{nm.x, nm.y, nm.z, nm.m, PEPS ? neps2[~a] : 0.0, mk, a, 0, 0};
+                const double e2 = PEPS ? neps2[~a] : 0.0;
+                ld_it = ItemV{nm.x, nm.y, nm.z, nm.m, e2, mk, a, (float)(G * nm.m),
+                              (float)(0.5 * e2), 0};
             }
         }
         const int pk = __popcll(mk);
@@ -295,7 +303,7 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
                 const ItemV it = items[j < nd ? j : j0];
                 const bool on = j < nd && ((it.mask >> bq) & 1ull);
                 VT o[5];
-                term(it, me.x, me.y, me.z, eb2, lxv, lyv, lzv, on, o);
+                term(it, me.x, me.y, me.z, eb2, ebhf, lxv, lyv, lzv, on, o);
                 if constexpr (F32) {
                     sx -= o[0];
                     sy -= o[1];
@@ -356,11 +364,12 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
             const uint32_t r = rec[on ? i : i0];
             const int k = (int)(r >> 6), b = (int)(r & 63u);
             const double bx = __shfl(me.x, b), by = __shfl(me.y, b), bz = __shfl(me.z, b);
-            const double eb = PEPS ? __shfl(eb2, b) : 0.0;
+            const double eb = PEPS && !F32 ? __shfl(eb2, b) : 0.0;
+            const float ebh = PEPS && F32 ? __shfl(ebhf, b) : 0.f;
             const VT ux = __shfl(lxv, b), uy = __shfl(lyv, b), uz = __shfl(lzv, b);
             const ItemV it = items[k];
             VT o[5];
-            term(it, bx, by, bz, eb, ux, uy, uz, on, o);
+            term(it, bx, by, bz, eb, ebh, ux, uy, uz, on, o);
             if (on) {
 #pragma unroll
                 for (int q = 0; q < 3; q++)
