@@ -63,6 +63,7 @@ struct TreeHeader {
 };
 // The level whose largest node the build reports for the choice of sort.
 constexpr int kHintLevel = 5;
+constexpr int kHintWords = 2 + kLevels;  // pinned launch-hint words of a workspace
 
 // Body layout of one call: n bodies in n_scenes contiguous scenes. For one
 // scene every table is implicit (nullptr); otherwise scene_of gives each
@@ -191,7 +192,8 @@ struct Workspace {
     // memory (-1 before the first build): [0] its deepest non-empty level (the
     // next build launches the levels down to one below it one by one and the
     // rest in one block), [1] the most bodies in one node of level kHintLevel
-    // (which picks the next build's sort).
+    // (which picks the next build's sort), [2 + l] its node count on level l
+    // (which picks how level l is split), kHintWords words in all.
     int32_t *depth_host = nullptr;
     int32_t *depth_dev = nullptr;  // the same memory as the device sees it
 };

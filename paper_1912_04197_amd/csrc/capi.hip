@@ -707,10 +707,10 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
     A(dalloc(&w.red_part, (int64_t)bhx::kRedBlocks * 16));
     A(dalloc(&w.dpart, bhx::kDirectPart));
     A(dalloc(&c->diag_out, 8));
-    A(hipHostMalloc((void **)&w.depth_host, 2 * sizeof(int32_t), hipHostMallocMapped));
+    A(hipHostMalloc((void **)&w.depth_host, bhx::kHintWords * sizeof(int32_t),
+                    hipHostMallocMapped));
     if (r == hipSuccess) {
-        w.depth_host[0] = -1;
-        w.depth_host[1] = -1;
+        for (int i = 0; i < bhx::kHintWords; i++) w.depth_host[i] = -1;
         r = hipHostGetDevicePointer((void **)&w.depth_dev, w.depth_host, 0);
     }
     if (cfg->flags & BH_FLAG_ADJOINT) {

@@ -1047,7 +1047,8 @@ __device__ inline void moments_nodes(int level, const int32_t *counts,
 }
 
 // The launch hints of the build just finished, into pinned host memory:
-// its deepest non-empty level and its largest level-kHintLevel node.
+// its deepest non-empty level, its largest level-kHintLevel node and its
+// node count per level.
 __device__ inline void report_hints(const TreeHeader *__restrict__ hdr, int32_t *out)
 {
     int d = 0;
@@ -1055,6 +1056,7 @@ __device__ inline void report_hints(const TreeHeader *__restrict__ hdr, int32_t 
         if (hdr->level_count[l] > 0) d = l;
     out[0] = d;
     out[1] = hdr->cell_max;
+    for (int l = 0; l < kLevels; l++) out[2 + l] = hdr->level_count[l];
 }
 
 __global__ __launch_bounds__(256) void k_moments_level(
@@ -1293,6 +1295,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_build_small(
             if (scnt[l] > 0) d = l;
         depth_out[0] = d;
         depth_out[1] = -1;  // no sort hint from a one-block build
+        for (int l = 0; l < kLevels; l++) depth_out[2 + l] = scnt[l];
     }
 }
 
@@ -1403,25 +1406,30 @@ void enqueue_levels(const Workspace &w, hipStream_t s, const Layout &lay, int le
     // levels in one block was measured slower: its binary searches over all
     // bodies run four passes deep there.) The split only affects speed.
     int deep = kMaxLevel, prev = -1;
-    if (w.depth_host) {
-        prev = *(const volatile int32_t *)w.depth_host;
+    const volatile int32_t *hint = w.depth_host;
+    if (hint) {
+        prev = hint[0];
         if (prev >= 0 && prev + 1 < deep) deep = prev + 1;
     }
     const int head = ns == 1 ? (deep < 4 ? deep : 4) : 0;
     for (int level = 0; level < deep; level++) {
-        // the three deepest levels the previous build reported hold mostly
-        // leaves: one thread per node, the splitting ones listed; above, eight
-        // lanes per node. Levels of many nodes take 1024-thread blocks (fewer
-        // reservations on the level counter), small ones 256 (more CUs for
-        // their searches). The choice only affects speed.
-        const bool compact = prev >= 0 && level >= prev - 2;
+        // a level whose next level held no more nodes in the previous build
+        // holds mostly leaves: one thread per node, the splitting ones listed;
+        // otherwise eight lanes per node. Levels of many nodes take 1024-thread
+        // blocks (fewer reservations on the level counter), small ones 256
+        // (more CUs for their searches). The choice only affects speed.
+        const bool compact =
+            prev >= 0 && level < kMaxLevel && hint[2 + level] > 0 &&
+            hint[3 + level] <= hint[2 + level];
         const int64_t threads = level_bound(level, n, ns) * (compact ? 1 : 8);
         const int bs = threads >= 65536 ? 1024 : 256;
         const unsigned g = blocks_for(threads, bs, bs == 1024 ? 1024 : 4096);
         if (compact)
-            k_build_level<true><<<g, bs, 0, s>>>(level, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
+            k_build_level<true>
+                <<<g, bs, 0, s>>>(level, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
         else
-            k_build_level<false><<<g, bs, 0, s>>>(level, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
+            k_build_level<false>
+                <<<g, bs, 0, s>>>(level, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
     }
     if (deep < kMaxLevel)
         k_build_tail<<<1, 1024, 0, s>>>(deep, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
