@@ -177,13 +177,15 @@ def bench_batched(args, n_scenes=256, steps=10, theta=0.5, dt=1e-3, soft=1e-3):
     }
 
 
-def bench_adjoint(n=65536, nsteps=200, every=20, theta=0.5, dt=1e-3, soft=1e-3):
+def bench_adjoint(n=65536, nsteps=200, every=20, theta=0.5, dt=1e-3, soft=1e-3, leaf=2):
     """Differentiable rollout: forward KDK steps with checkpoints, then the
     hand-written adjoint back to (x0, v0, m), against the forward alone (each
     the median of 3 runs after a warm-up); the tree gradient against the FP64
     direct-sum gradient, and FP32C (FP32C forward and FP32C tree VJPs)
     against FP64. The `_keep` entries keep every step's positions (24 B per
-    body and step) so that the backward pass recomputes nothing."""
+    body and step) so that the backward pass recomputes nothing. Leaf 2: the
+    fastest forward+backward of leaves 1-16 on this workload (the VJP's terms
+    are dearer than the forward's, so fewer interactions pay more)."""
     import torch
 
     from paper_1912_04197_amd import ics
@@ -192,14 +194,14 @@ def bench_adjoint(n=65536, nsteps=200, every=20, theta=0.5, dt=1e-3, soft=1e-3):
 
     s = ics.uniform_ball(n, seed=55)
     xt = torch.from_numpy(ics.perturbed_target(s.pos, seed=56)).cuda()
-    out = {"workload": f"uniform ball N={n} theta={theta} eps={soft} dt={dt}, {nsteps} KDK "
-                       f"steps, checkpoint every {every}, loss sum |x_T - x*|^2"}
+    out = {"workload": f"uniform ball N={n} theta={theta} eps={soft} dt={dt}, leaf {leaf}, "
+                       f"{nsteps} KDK steps, checkpoint every {every}, loss sum |x_T - x*|^2"}
     grads = {}
     for label, prec, th, keep in (("fp32c", "fp32c", theta, False), ("fp64", "fp64", theta, False),
                                   ("direct_fp64", "fp64", -1.0, False),
                                   ("fp32c_keep", "fp32c", theta, True),
                                   ("fp64_keep", "fp64", theta, True)):
-        ctx = Context(n, leaf_size=16, precision=prec, adjoint=True)
+        ctx = Context(n, leaf_size=leaf, precision=prec, adjoint=True)
         x0 = torch.from_numpy(s.pos).cuda().requires_grad_(True)
         v0 = torch.from_numpy(s.vel).cuda().requires_grad_(True)
         m = torch.from_numpy(s.mass).cuda().requires_grad_(True)

@@ -167,30 +167,31 @@ def test_rollout_gradient_parity(api, theta, keep):
     _close(Mt.grad.cpu().numpy(), gm, 1e-9, "gm")
 
 
-@pytest.mark.parametrize("keep", [False, True])
-@pytest.mark.parametrize("theta", [0.5, -1.0])
-def test_rollout_gradient_parity_4096(api, theta, keep):
+@pytest.mark.parametrize("theta,keep,leaf", [(0.5, False, 16), (0.5, True, 16), (-1.0, False, 16),
+                                             (-1.0, True, 16), (0.5, False, 2), (0.5, True, 2)])
+def test_rollout_gradient_parity_4096(api, theta, keep, leaf):
     """The differentiable-rollout case at the size the CPU oracle can still
     follow: N = 4096 uniform ball (equal masses), eps 1e-3, 50 KDK steps of
     dt = 1e-3, checkpoints every 20 steps, loss sum |x_T - x*|^2, FP64; every
     component of the gradients with respect to x0, v0 and m against the
-    oracle's reverse sweep (tree: theta 0.5, leaf 16, decisions held fixed)."""
+    oracle's reverse sweep (tree: theta 0.5, leaf 16 or the full-size
+    workload's leaf 2, decisions held fixed)."""
     from paper_1912_04197_amd.autograd import rollout
 
     n, T, dt, soft = 4096, 50, 1e-3, 1e-3
     s = ics.uniform_ball(n, seed=55)
     xt = ics.perturbed_target(s.pos, seed=56)
-    ctx = api.Context(n, leaf_size=16, precision="fp64", adjoint=True)
+    ctx = api.Context(n, leaf_size=leaf, precision="fp64", adjoint=True)
     X0 = _dev(s.pos).requires_grad_(True)
     V0 = _dev(s.vel).requires_grad_(True)
     Mt = _dev(s.mass).requires_grad_(True)
     x, _ = rollout(X0, V0, Mt, ctx, dt, T, theta=theta, softening=soft, checkpoint_every=20,
                    keep_positions=keep)
     ((x - _dev(xt)) ** 2).sum().backward()
-    xf, vf, _ = oracle.leapfrog(s.pos, s.vel, s.mass, dt, T, softening=soft, theta=theta, leaf=16)
+    xf, vf, _ = oracle.leapfrog(s.pos, s.vel, s.mass, dt, T, softening=soft, theta=theta, leaf=leaf)
     assert np.abs(x.detach().cpu().numpy() - xf).max() < 1e-12
     gx, gv, gm = oracle.rollout_grad(s.pos, s.vel, s.mass, dt, T, 2 * (xf - xt), np.zeros_like(vf),
-                                     softening=soft, theta=theta, leaf=16)
+                                     softening=soft, theta=theta, leaf=leaf)
     _close(X0.grad.cpu().numpy(), gx, 1e-9, "gx0")
     _close(V0.grad.cpu().numpy(), gv, 1e-9, "gv0")
     _close(Mt.grad.cpu().numpy(), gm, 1e-9, "gm")
@@ -199,7 +200,7 @@ def test_rollout_gradient_parity_4096(api, theta, keep):
 @pytest.mark.parametrize("precision", ["fp64", "fp32c"])
 def test_rollout_65536_properties(api, precision):
     """The differentiable-rollout workload at full size: N = 65536 uniform
-    ball, eps 1e-3, theta 0.5, leaf 16, 200 KDK steps of dt = 1e-3,
+    ball, eps 1e-3, theta 0.5, leaf 2, 200 KDK steps of dt = 1e-3,
     checkpoints every 20 steps, loss sum |x_T - x*|^2. A translation of x0
     translates the whole trajectory and a uniform boost of v0 shifts x_T by
     T dt times it, so sum_i gx0_i = sum_i dL/dx_T and
@@ -209,7 +210,7 @@ def test_rollout_65536_properties(api, precision):
     n, T, dt = 65536, 200, 1e-3
     s = ics.uniform_ball(n, seed=55)
     xt = ics.perturbed_target(s.pos, seed=56)
-    ctx = api.Context(n, leaf_size=16, precision=precision, adjoint=True)
+    ctx = api.Context(n, leaf_size=2, precision=precision, adjoint=True)
     X0 = _dev(s.pos).requires_grad_(True)
     V0 = _dev(s.vel).requires_grad_(True)
     Mt = _dev(s.mass).requires_grad_(True)
