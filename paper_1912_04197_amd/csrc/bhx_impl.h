@@ -64,6 +64,12 @@ struct TreeHeader {
 // The level whose largest node the build reports for the choice of sort.
 constexpr int kHintLevel = 5;
 constexpr int kHintWords = 2 + kLevels;  // pinned launch-hint words of a workspace
+// The levels 1..kPrefixLevels of a single scene's tree are read off the
+// sorted keys: a level-kPrefixLevels cell is the key's top 3 kPrefixLevels
+// bits, and the first body of each such cell gives every cell range above it.
+constexpr int kPrefixLevels = 5;
+constexpr int kPrefixCells = 1 << (3 * kPrefixLevels);  // 32768
+constexpr int kPrefixShift = 63 - 3 * kPrefixLevels;
 
 // Body layout of one call: n bodies in n_scenes contiguous scenes. For one
 // scene every table is implicit (nullptr); otherwise scene_of gives each
@@ -196,6 +202,10 @@ struct Workspace {
     // (which picks how level l is split), kHintWords words in all.
     int32_t *depth_host = nullptr;
     int32_t *depth_dev = nullptr;  // the same memory as the device sees it
+    // [kPrefixCells] first sorted body of each level-kPrefixLevels cell, or
+    // INT32_MAX ("none"): set at creation, written by one build and restored
+    // to "none" by the same build once read.
+    int32_t *prefix_mark = nullptr;
 };
 
 // The direct sum splits its sources over up to kDirectSplits block rows when

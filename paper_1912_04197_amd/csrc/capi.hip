@@ -129,7 +129,7 @@ void free_ws(Workspace &w)
     void *ptrs[] = {w.keys[0], w.keys[1], w.idx[0],  w.idx[1],      w.sort_counts,
                     w.sort_totals, w.body, w.beps2, w.ninfo, w.nmom, w.neps2, w.box,
                     w.hdr, w.counts, w.scratch, w.red_part, w.nquad, w.dpart,
-                    w.tvel, w.tacc, w.sbody, w.svel, w.seps2, w.scidx};
+                    w.tvel, w.tacc, w.sbody, w.svel, w.seps2, w.scidx, w.prefix_mark};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     if (w.depth_host) (void)hipHostFree(w.depth_host);
@@ -684,6 +684,9 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
     A(dalloc(&w.seps2, n));
     A(dalloc(&w.scidx, n));
     A(dalloc(&w.ninfo, node_cap));
+    A(dalloc(&w.prefix_mark, bhx::kPrefixCells));
+    if (r == hipSuccess)
+        r = hipMemsetD32((hipDeviceptr_t)w.prefix_mark, INT32_MAX, bhx::kPrefixCells);
     A(dalloc(&w.nmom, node_cap));
     A(dalloc(&w.neps2, node_cap));
     A(dalloc(&w.box, max_scenes));

@@ -955,6 +955,219 @@ __global__ __launch_bounds__(1024) void k_build_tail(int from, const uint64_t *_
     if (threadIdx.x <= kLevels) hdr->level_count[threadIdx.x] = scnt[threadIdx.x];
 }
 
+// The top levels of a single scene, from the sorted keys. A level-l cell
+// holds the bodies whose keys start with its 3 l bits, a contiguous run of
+// the sorted keys, so the first body of every level-kPrefixLevels cell
+// gives the body range of every cell on levels 1..kPrefixLevels. A cell is a
+// node iff it holds a body and its parent holds more than `leaf` (then every
+// ancestor does too and splits), and a node's children are its non-empty
+// octants: the nodes the level-by-level split creates, numbered here in
+// Morton order within each level, with no searches and no atomics.
+
+// First body of each non-empty level-kPrefixLevels cell: where the cell part
+// of the key changes along the sorted keys (one writer per cell).
+__global__ __launch_bounds__(256) void k_prefix_marks(const uint64_t *__restrict__ keys, int64_t n,
+                                                      int32_t *__restrict__ mark)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t c = (uint32_t)(keys[i] >> kPrefixShift);
+    if (i == 0 || (uint32_t)(keys[i - 1] >> kPrefixShift) != c) mark[c] = (int32_t)i;
+}
+
+// Exclusive prefix sums of K values at once over the 1024 threads of a block,
+// with their totals; every thread calls it. s_w: LDS [16][K].
+template <int K>
+__device__ inline void block_excl_scan_1024(uint32_t (&v)[K], uint32_t (&tot)[K],
+                                            uint32_t (*s_w)[K])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t incl[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) incl[k] = wave_incl_scan(v[k]);
+    if (lane == 63)
+        for (int k = 0; k < K; k++) s_w[wave][k] = incl[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        uint32_t before = 0, t = 0;
+#pragma unroll
+        for (int w = 0; w < 16; w++) {  // independent LDS reads, all in flight
+            const uint32_t x = s_w[w][k];
+            if (w < wave) before += x;
+            t += x;
+        }
+        v[k] = before + incl[k] - v[k];
+        tot[k] = t;
+    }
+    __syncthreads();  // s_w may be reused
+}
+
+// Levels 1..kPrefixLevels of one scene of n > 0 sorted bodies (the root,
+// node 0, written by k_box_final): one block of 1024 threads. Reads the marks
+// of k_prefix_marks (restoring them to "none"), turns them into the first
+// body of every level-5 cell (held in LDS, one pad word after every 32 so
+// that a thread's 32 consecutive cells fall in distinct banks), and writes
+// the nodes of levels 1..5 (those of level 5 unsplit, for the level-5 split),
+// the children of the root and of levels 1..4, and the node counts of levels
+// 1..5. Thread t decides level-5 cells 32 t..32 t + 31, level-4 cells
+// 4 t..4 t + 3 and cell t of levels 1..3; the level-4 and level-5 nodes are
+// then written with consecutive lanes on consecutive cells, so that the
+// stores of a wave fall on consecutive nodes.
+static_assert(kPrefixLevels == 5 && kPrefixCells == 32 * 1024, "one block, 32 cells a thread");
+__device__ inline int prefix_pad(int c) { return c + (c >> 5); }
+__global__ __launch_bounds__(1024) void k_prefix_levels(int32_t *__restrict__ mark, int64_t n,
+                                                        TreeHeader *__restrict__ hdr,
+                                                        NodeInfo *__restrict__ ninfo,
+                                                        int64_t node_cap, int leaf)
+{
+    __shared__ int32_t s_st[kPrefixCells + kPrefixCells / 32 + 1];  // first body per cell, padded
+    __shared__ int32_t s_wmin[16];
+    __shared__ uint32_t s_w[16][5];
+    __shared__ uint32_t s_r2[64], s_r3[512];  // ranks of the level-2 and level-3 cells
+    __shared__ uint32_t s_r4[1024], s_m4[1024], s_r5[1024], s_m5[1024];  // per thread
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int32_t nn = (int32_t)n;
+    // 1. the marks (all loads in flight at once), restored to "none"
+    {
+        int32_t mv[kPrefixCells / 1024];
+#pragma unroll
+        for (int k = 0; k < kPrefixCells / 1024; k++) mv[k] = mark[t + 1024 * k];
+#pragma unroll
+        for (int k = 0; k < kPrefixCells / 1024; k++) {
+            s_st[prefix_pad(t + 1024 * k)] = mv[k];
+            mark[t + 1024 * k] = INT32_MAX;
+        }
+    }
+    if (t == 0) s_st[prefix_pad(kPrefixCells)] = nn;
+    __syncthreads();
+    // 2. first body of every cell = the smallest mark at or after it (n past
+    // the last): a suffix minimum over the thread's cells and the threads
+    // after. With it, this thread's level-4 cells that hold bodies (nz4) and
+    // its level-5 cells that hold bodies under a level-4 cell that splits (m5).
+    const int c0 = 32 * t;
+    uint32_t nz4 = 0, m5 = 0;
+    {
+        int32_t st[33];
+#pragma unroll
+        for (int j = 0; j < 32; j++) st[j] = s_st[prefix_pad(c0 + j)];
+        int32_t lm = st[0];
+#pragma unroll
+        for (int j = 1; j < 32; j++) lm = min(lm, st[j]);
+        int32_t x = lm;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t y = __shfl_down(x, o);
+            if (lane + o < 64) x = min(x, y);
+        }
+        int32_t carry = __shfl_down(x, 1);
+        if (lane == 63) carry = INT32_MAX;
+        if (lane == 0) s_wmin[wave] = x;
+        __syncthreads();
+        carry = min(carry, nn);
+#pragma unroll
+        for (int w = 0; w < 16; w++)
+            if (w > wave) carry = min(carry, s_wmin[w]);
+        st[32] = carry;
+#pragma unroll
+        for (int j = 31; j >= 0; j--) st[j] = min(st[j], st[j + 1]);
+        BHX_CHECK(st[0] >= 0, CK_PARTITION);
+#pragma unroll
+        for (int j = 0; j < 32; j++) s_st[prefix_pad(c0 + j)] = st[j];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int32_t c4 = st[8 * q + 8] - st[8 * q];
+            if (c4 > 0) nz4 |= 1u << q;
+            if (c4 > leaf)
+#pragma unroll
+                for (int j = 8 * q; j < 8 * q + 8; j++)
+                    if (st[j + 1] > st[j]) m5 |= 1u << j;
+        }
+    }
+    __syncthreads();
+    auto S = [&](int c) { return s_st[prefix_pad(c)]; };  // first body of level-5 cell c
+    auto cnt = [&](int l, int c) {  // bodies of level-l cell c
+        const int sh = 3 * (5 - l);
+        return S((c + 1) << sh) - S(c << sh);
+    };
+    // 3. which cells are nodes, level by level
+    const bool e1 = t < 8 && cnt(1, t) > 0 && nn > leaf;
+    const bool e2 = t < 64 && cnt(2, t) > 0 && cnt(1, t >> 3) > leaf;
+    const bool e3 = t < 512 && cnt(3, t) > 0 && cnt(2, t >> 3) > leaf;
+    const uint32_t m4 = cnt(3, t >> 1) > leaf ? nz4 : 0u;  // under a level-3 cell that splits
+    uint32_t r[5] = {e1 ? 1u : 0u, e2 ? 1u : 0u, e3 ? 1u : 0u, (uint32_t)__popc(m4),
+                     (uint32_t)__popc(m5)};
+    uint32_t tot[5];
+    block_excl_scan_1024<5>(r, tot, s_w);
+    if (t < 64) s_r2[t] = r[1];
+    if (t < 512) s_r3[t] = r[2];
+    s_r4[t] = r[3];
+    s_m4[t] = m4;
+    s_r5[t] = r[4];
+    s_m5[t] = m5;
+    __syncthreads();
+    // 4. the nodes: level l starts after the nodes of the levels above
+    const int64_t beg1 = 1, beg2 = beg1 + tot[0], beg3 = beg2 + tot[1], beg4 = beg3 + tot[2],
+                  beg5 = beg4 + tot[3];
+    if (beg5 + tot[4] > node_cap) {
+        if (t == 0) atomicOr(&hdr->status, ST_CAPACITY);
+        return;  // the same on every thread
+    }
+    auto nonempty8 = [&](int l, int c) {  // non-empty children of level-l cell c, l <= 4
+        int k = 0;
+        for (int o = 0; o < 8; o++) k += cnt(l + 1, 8 * c + o) > 0;
+        return k;
+    };
+    if (t == 0) {
+        for (int l = 1; l <= 5; l++) hdr->level_count[l] = (int32_t)tot[l - 1];
+        if (nn > leaf) {
+            ninfo[0].child0 = (int32_t)beg1;
+            ninfo[0].lvl_nch = nonempty8(0, 0) << 8;
+        }
+    }
+    // levels 1..3: cell t; its first child's rank is that of the first cell
+    // of its eight on the next level
+    auto upper = [&](int l, bool exists, uint32_t rank, int64_t beg, int64_t beg_next,
+                     const uint32_t *rnext, int rsel) {
+        if (!exists) return;
+        const int32_t c = cnt(l, t);
+        NodeInfo ni{S(t << (3 * (5 - l))), c, -1, l};
+        if (c > leaf) {
+            ni.child0 = (int32_t)(beg_next + rnext[rsel]);
+            ni.lvl_nch = l | (nonempty8(l, t) << 8);
+        }
+        ninfo[beg + rank] = ni;
+    };
+    upper(1, e1, r[0], beg1, beg2, s_r2, 8 * t);
+    upper(2, e2, r[1], beg2, beg3, s_r3, 8 * t);
+    upper(3, e3, r[2], beg3, beg4, s_r4, 2 * t);  // level-4 cell 8 t is thread 2 t's first
+    // level 4, cell c4 = 1024 k + t (owner thread c4 / 4)
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int c4 = 1024 * k + t, o = c4 >> 2, q = c4 & 3;
+        const uint32_t mo = s_m4[o];
+        if (!((mo >> q) & 1u)) continue;
+        const int32_t first = S(c4 << 3), c = S((c4 + 1) << 3) - first;
+        NodeInfo ni{first, c, -1, 4};
+        if (c > leaf) {
+            const uint32_t m5o = s_m5[o];  // the owner of its children too
+            ni.child0 = (int32_t)(beg5 + s_r5[o] + __popc(m5o & ((1u << (8 * q)) - 1u)));
+            ni.lvl_nch = 4 | (__popc((m5o >> (8 * q)) & 0xffu) << 8);
+        }
+        ninfo[beg4 + s_r4[o] + __popc(mo & ((1u << q) - 1u))] = ni;
+    }
+    // level 5, cell c = 1024 k + t (owner thread c / 32)
+#pragma unroll 4
+    for (int k = 0; k < 32; k++) {
+        const int c = 1024 * k + t, o = c >> 5, j = c & 31;
+        const uint32_t m5o = s_m5[o];
+        if (!((m5o >> j) & 1u)) continue;
+        const int32_t first = S(c);
+        ninfo[beg5 + s_r5[o] + __popc(m5o & ((1u << j) - 1u))] =
+            NodeInfo{first, S(c + 1) - first, -1, 5};
+    }
+}
+
 // ------------------------------------------------------------ 6. moments
 
 // Mass, centre of mass and mass-weighted softening of every node of `level`,
@@ -1412,7 +1625,14 @@ void enqueue_levels(const Workspace &w, hipStream_t s, const Layout &lay, int le
         if (prev >= 0 && prev + 1 < deep) deep = prev + 1;
     }
     const int head = ns == 1 ? (deep < 4 ? deep : 4) : 0;
-    for (int level = 0; level < deep; level++) {
+    // one scene: levels 1..kPrefixLevels from the sorted keys in two launches
+    // instead of one per level (when the previous build went deeper)
+    const bool prefix = ns == 1 && deep > kPrefixLevels && w.prefix_mark != nullptr;
+    if (prefix) {
+        k_prefix_marks<<<blocks_for(n, 256, 1u << 30), 256, 0, s>>>(w.keys[0], n, w.prefix_mark);
+        k_prefix_levels<<<1, 1024, 0, s>>>(w.prefix_mark, n, w.hdr, w.ninfo, w.node_cap, leaf);
+    }
+    for (int level = prefix ? kPrefixLevels : 0; level < deep; level++) {
         // a level whose next level held no more nodes in the previous build
         // holds mostly leaves: one thread per node, the splitting ones listed;
         // otherwise eight lanes per node. Levels of many nodes take 1024-thread
