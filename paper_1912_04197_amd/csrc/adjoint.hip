@@ -68,6 +68,7 @@ __device__ inline float dpp(float v)
 }
 
 constexpr int kPairCap = 448;  // pairs per batch
+constexpr int kPushHead = 4;   // levels whose coefficients are pushed down in one block
 
 // badj: per sorted body {gX x, y, z, gm}; nadj: per node {gX x, y, z, gm, ge2}.
 //
@@ -464,17 +465,9 @@ __device__ inline void node_coeffs(const double *__restrict__ nadj, const NodeMo
     }
 }
 
-__global__ void k_vjp_root(const double *__restrict__ nadj, const NodeMom *__restrict__ nmom,
-                           const double *__restrict__ neps2, int use_eps,
-                           double *__restrict__ npre)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double c[5];
-    node_coeffs(nadj, nmom[0], use_eps ? neps2[0] : 0.0, 0, c);
-    for (int q = 0; q < 5; q++) npre[q] = c[q];
-}
-
-// npre[child] = npre[node] + coefficients(child), for every node of `level`.
+// npre[child] = npre[node] + coefficients(child), for every child of the
+// nodes of `level`: work item g takes child slot g % 8 of the level's node
+// g / 8, so that a node's children are done side by side.
 __device__ inline void push_level(int level, const TreeHeader *__restrict__ hdr,
                                   const NodeInfo *__restrict__ ninfo,
                                   const NodeMom *__restrict__ nmom,
@@ -486,16 +479,16 @@ __device__ inline void push_level(int level, const TreeHeader *__restrict__ hdr,
     for (int l = 0; l < level; l++) beg += hdr->level_count[l];
     int64_t cnt = hdr->level_count[level];
     if (beg + cnt > node_cap) cnt = node_cap - beg;
-    for (int64_t g = g_first; g < cnt; g += stride) {
-        const int64_t k = beg + g;
+    for (int64_t g = g_first; g < 8 * cnt; g += stride) {
+        const int64_t k = beg + (g >> 3);
+        const int o = (int)(g & 7);
         const NodeInfo info = ninfo[k];
-        if (info.child0 < 0) continue;
+        if (info.child0 < 0 || o >= node_nchild(info)) continue;
+        const int32_t c = info.child0 + o;
+        double cf[5];
+        node_coeffs(nadj, nmom[c], use_eps ? neps2[c] : 0.0, c, cf);
         const double *p = npre + 5 * k;
-        for (int32_t c = info.child0; c < info.child0 + node_nchild(info); c++) {
-            double cf[5];
-            node_coeffs(nadj, nmom[c], use_eps ? neps2[c] : 0.0, c, cf);
-            for (int q = 0; q < 5; q++) npre[5 * (int64_t)c + q] = p[q] + cf[q];
-        }
+        for (int q = 0; q < 5; q++) npre[5 * (int64_t)c + q] = p[q] + cf[q];
     }
 }
 
@@ -508,6 +501,29 @@ __global__ __launch_bounds__(256) void k_vjp_push(int level, const TreeHeader *_
 {
     push_level(level, hdr, ninfo, nmom, neps2, use_eps, nadj, npre, node_cap,
                (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
+}
+
+// The root's coefficients, then levels 0..upto-1 in one block (the top
+// levels hold few nodes).
+__global__ __launch_bounds__(1024) void k_vjp_push_head(int upto, const TreeHeader *__restrict__ hdr,
+                                                        const NodeInfo *__restrict__ ninfo,
+                                                        const NodeMom *__restrict__ nmom,
+                                                        const double *__restrict__ neps2,
+                                                        int use_eps, const double *__restrict__ nadj,
+                                                        double *__restrict__ npre, int64_t node_cap)
+{
+    if (threadIdx.x == 0) {
+        double c[5];
+        node_coeffs(nadj, nmom[0], use_eps ? neps2[0] : 0.0, 0, c);
+        for (int q = 0; q < 5; q++) npre[q] = c[q];
+    }
+    __syncthreads();
+    for (int level = 0; level < upto; level++) {
+        if (hdr->level_count[level] == 0) break;  // the same on every thread
+        push_level(level, hdr, ninfo, nmom, neps2, use_eps, nadj, npre, node_cap, threadIdx.x,
+                   1024);
+        __syncthreads();
+    }
 }
 
 // Levels from..kMaxLevel-1 in one block, stopping at the first level with no
@@ -747,17 +763,21 @@ hipError_t launch_tree_vjp(const Workspace &w, const AdjointWork &aw, hipStream_
         else walk(F{}, I64{});
     }
     const int use_eps = p.per_body_eps ? 1 : 0;
-    k_vjp_root<<<1, 64, 0, s>>>(aw.nadj, w.nmom, w.neps2, use_eps, aw.npre);
-    // one launch per level down to one below the previous build's depth (a
-    // hint kept by the build), the rest in one block
+    // the root and the top levels (at most 585 nodes) in one block, then one
+    // launch per level down to one below the previous build's depth (a hint
+    // kept by the build), the rest in one block
     int deep = kMaxLevel;
     if (w.depth_host) {
         const int prev = *(const volatile int32_t *)w.depth_host;
         if (prev >= 0 && prev + 1 < deep) deep = prev + 1;
     }
-    int64_t bound = 1;
-    for (int level = 0; level < deep; level++) {
-        const unsigned g = blocks(bound < p.n ? bound : p.n, 4096);
+    const int head = deep < kPushHead ? deep : kPushHead;
+    k_vjp_push_head<<<1, 1024, 0, s>>>(head, w.hdr, w.ninfo, w.nmom, w.neps2, use_eps, aw.nadj,
+                                       aw.npre, w.node_cap);
+    int64_t bound = (int64_t)1 << (3 * head);  // nodes a level can hold
+    for (int level = head; level < deep; level++) {
+        const int64_t nodes = bound < p.n ? bound : p.n;
+        const unsigned g = blocks(8 * nodes, 4096);
         k_vjp_push<<<g, 256, 0, s>>>(level, w.hdr, w.ninfo, w.nmom, w.neps2, use_eps, aw.nadj,
                                      aw.npre, w.node_cap);
         if (bound < p.n) bound *= 8;
