@@ -1189,25 +1189,48 @@ __device__ inline void moments_nodes(int level, const int32_t *counts,
     for (int64_t g = g_first; g < cnt; g += stride) {
         const int32_t k = beg + (int32_t)g;
         const NodeInfo info = ninfo[k];
+        // sums in member order; each group's loads are all issued before
+        // its first addition
         double ms = 0.0, mx = 0.0, my = 0.0, mz = 0.0, me = 0.0;
         if (info.child0 < 0) {
-            for (int32_t s = info.first; s < info.first + info.count; s++) {
-                const Body b = body[s];
-                ms += b.m;
-                mx += b.x * b.m;
-                my += b.y * b.m;
-                mz += b.z * b.m;
-                if (use_eps) me += beps2[s] * b.m;
+            const int32_t end = info.first + info.count;
+            for (int32_t s0 = info.first; s0 < end; s0 += 4) {
+                Body b[4];
+                double e[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int32_t s = s0 + u < end ? s0 + u : s0;
+                    b[u] = body[s];
+                    e[u] = use_eps ? beps2[s] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    if (s0 + u >= end) break;
+                    ms += b[u].m;
+                    mx += b[u].x * b[u].m;
+                    my += b[u].y * b[u].m;
+                    mz += b[u].z * b[u].m;
+                    if (use_eps) me += e[u] * b[u].m;
+                }
             }
         } else {
             const int nch = node_nchild(info);
-            for (int32_t c = info.child0; c < info.child0 + nch; c++) {
-                const NodeMom cm = nmom[c];
-                ms += cm.m;
-                mx += cm.x * cm.m;
-                my += cm.y * cm.m;
-                mz += cm.z * cm.m;
-                if (use_eps) me += neps2[c] * cm.m;
+            NodeMom cm[8];
+            double e[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                const int32_t c = info.child0 + (u < nch ? u : 0);
+                cm[u] = nmom[c];
+                e[u] = use_eps ? neps2[c] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                if (u >= nch) break;
+                ms += cm[u].m;
+                mx += cm[u].x * cm[u].m;
+                my += cm[u].y * cm[u].m;
+                mz += cm[u].z * cm[u].m;
+                if (use_eps) me += e[u] * cm[u].m;
             }
         }
         NodeMom out;
