@@ -108,7 +108,31 @@ TREE_CASES = [
     # the largest scene built by one block, and the smallest that is not
     ("ball4096_leaf2", lambda: ics.uniform_ball(4096, seed=14), 2, False),
     ("ball4097_leaf2", lambda: ics.uniform_ball(4097, seed=14), 2, False),
+    # shapes for the top levels read off the sorted keys (above 4096 bodies):
+    # one dominant point (a single chain of cells down to level 21), a bucket
+    # that holds every body (the root stays a leaf), and bodies on a line
+    # (most cells of every level empty)
+    ("clump5000_leaf16", lambda: _clump(5000, 4000, seed=17), 16, False),
+    ("ball5000_leaf5000", lambda: ics.uniform_ball(5000, seed=18), 5000, False),
+    ("line9000_leaf3", lambda: _line(9000, seed=19), 3, False),
 ]
+
+
+def _clump(n, on_point, seed):
+    """n bodies, the first on_point of them on one point, the rest in a ball."""
+    s = ics.uniform_ball(n, seed=seed)
+    s.pos[:on_point] = [0.1, -0.2, 0.3]
+    return s
+
+
+def _line(n, seed):
+    """n bodies spread along a segment, with a small transverse scatter."""
+    s = ics.uniform_ball(n, seed=seed)
+    rng = np.random.default_rng(seed)
+    t = rng.random(n)
+    s.pos[:] = np.stack([2.0 * t - 1.0, 0.25 * t + 1e-4 * rng.standard_normal(n),
+                         1e-4 * rng.standard_normal(n)], axis=1)
+    return s
 
 
 @pytest.mark.parametrize("name,make,leaf,per_body", TREE_CASES, ids=[c[0] for c in TREE_CASES])

@@ -114,3 +114,20 @@ def test_multi_step_bad_input_latched(api):
         ctx.step_leapfrog(p.clone(), bad_v, m, a.clone(), 1e-3, 3, theta=0.5, softening=1e-3)
     ctx.step_leapfrog(p, v, m, a, 1e-3, 3, theta=0.5, softening=1e-3)  # the latch was cleared
     assert torch.isfinite(p).all()
+
+
+@pytest.mark.parametrize("n,leaf,clump", [(50, 2, 0), (5000, 16, 4000)])
+def test_level_launches_small_and_clumped_multi_step(api, n, leaf, clump):
+    """Multi-step calls build through the per-level launches at any size (the
+    top levels read off the sorted keys): a 50-body scene, and 5000 bodies of
+    which 4000 sit on one point, against the oracle's FP64 leapfrog."""
+    s = ics.uniform_ball(n, seed=54)
+    pos, vel, mass = s.pos.copy(), s.vel.copy(), s.mass.copy()
+    pos[:clump] = [0.1, -0.2, 0.3]
+    xr, vr, _ = oracle.leapfrog(pos, vel, mass, 1e-3, 6, softening=1e-3, theta=0.5, leaf=leaf)
+    ctx = api.Context(n, leaf_size=leaf, precision="fp64")
+    p, v, m = _dev(pos), _dev(vel), _dev(mass)
+    a = ctx.compute_accel(p, m, 0.5, softening=1e-3)
+    ctx.step_leapfrog(p, v, m, a, 1e-3, 6, theta=0.5, softening=1e-3)
+    assert np.abs(p.cpu().numpy() - xr).max() < 1e-13
+    assert np.abs(v.cpu().numpy() - vr).max() < 1e-11
