@@ -109,11 +109,11 @@ TREE_CASES = [
     ("ball4096_leaf2", lambda: ics.uniform_ball(4096, seed=14), 2, False),
     ("ball4097_leaf2", lambda: ics.uniform_ball(4097, seed=14), 2, False),
     # shapes for the top levels read off the sorted keys (above 4096 bodies):
-    # one dominant point (a single chain of cells down to level 21), a bucket
-    # that holds every body (the root stays a leaf), and bodies on a line
-    # (most cells of every level empty)
+    # one dominant point (a single chain of cells down to level 21), a ball
+    # with far outliers (leaves on levels 1-3 beside a deep subtree), and
+    # bodies on a line (most cells of every level empty)
     ("clump5000_leaf16", lambda: _clump(5000, 4000, seed=17), 16, False),
-    ("ball5000_leaf5000", lambda: ics.uniform_ball(5000, seed=18), 5000, False),
+    ("outliers5000_leaf64", lambda: _outliers(5000, 24, seed=18), 64, False),
     ("line9000_leaf3", lambda: _line(9000, seed=19), 3, False),
 ]
 
@@ -122,6 +122,14 @@ def _clump(n, on_point, seed):
     """n bodies, the first on_point of them on one point, the rest in a ball."""
     s = ics.uniform_ball(n, seed=seed)
     s.pos[:on_point] = [0.1, -0.2, 0.3]
+    return s
+
+
+def _outliers(n, k, seed):
+    """A ball of n - k bodies and k bodies scattered over a cube 200 times wider."""
+    s = ics.uniform_ball(n, seed=seed)
+    rng = np.random.default_rng(seed)
+    s.pos[:k] = 200.0 * rng.random((k, 3)) - 100.0
     return s
 
 
