@@ -704,15 +704,28 @@ __global__ __launch_bounds__(256) void k_check_order(const uint64_t *__restrict_
 
 // ------------------------------------------------------------- 4. gather
 
+// With mark: the first sorted body of each non-empty level-kPrefixLevels
+// cell, where the cell part of the key changes (one writer per cell), for
+// k_prefix_levels.
+__device__ inline void prefix_mark(const uint64_t *__restrict__ keys, int64_t s,
+                                   int32_t *__restrict__ mark)
+{
+    const uint32_t c = (uint32_t)(keys[s] >> kPrefixShift);
+    if (s == 0 || (uint32_t)(keys[s - 1] >> kPrefixShift) != c) mark[c] = (int32_t)s;
+}
+
 __global__ __launch_bounds__(256) void k_gather(const double *__restrict__ pos,
                                                 const double *__restrict__ mass,
                                                 const double *__restrict__ eps,
                                                 const uint32_t *__restrict__ idx, int64_t n,
                                                 Body *__restrict__ body,
-                                                double *__restrict__ beps2)
+                                                double *__restrict__ beps2,
+                                                const uint64_t *__restrict__ keys,
+                                                int32_t *__restrict__ mark)
 {
     int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= n) return;
+    if (mark) prefix_mark(keys, s, mark);
     uint32_t i = idx[s];
     if (!check_ok(i < n, CK_INDEX)) i = 0;
     body[s] = Body{pos[3 * (int64_t)i], pos[3 * (int64_t)i + 1], pos[3 * (int64_t)i + 2], mass[i]};
@@ -731,10 +744,13 @@ __global__ __launch_bounds__(256) void k_gather_state(const Body *__restrict__ s
                                                       int64_t n, uint32_t *__restrict__ idx,
                                                       Body *__restrict__ body,
                                                       double *__restrict__ tvel,
-                                                      double *__restrict__ beps2)
+                                                      double *__restrict__ beps2,
+                                                      const uint64_t *__restrict__ keys,
+                                                      int32_t *__restrict__ mark)
 {
     int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (s >= n) return;
+    if (mark) prefix_mark(keys, s, mark);
     int64_t p = idx[s];
     if (!check_ok(p < n, CK_INDEX)) p = 0;
     body[s] = sbody[p];
@@ -964,17 +980,6 @@ __global__ __launch_bounds__(1024) void k_build_tail(int from, const uint64_t *_
 // octants: the nodes the level-by-level split creates, numbered here in
 // Morton order within each level, with no searches and no atomics.
 
-// First body of each non-empty level-kPrefixLevels cell: where the cell part
-// of the key changes along the sorted keys (one writer per cell).
-__global__ __launch_bounds__(256) void k_prefix_marks(const uint64_t *__restrict__ keys, int64_t n,
-                                                      int32_t *__restrict__ mark)
-{
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t c = (uint32_t)(keys[i] >> kPrefixShift);
-    if (i == 0 || (uint32_t)(keys[i - 1] >> kPrefixShift) != c) mark[c] = (int32_t)i;
-}
-
 // Exclusive prefix sums of K values at once over the 1024 threads of a block,
 // with their totals; every thread calls it. s_w: LDS [16][K].
 template <int K>
@@ -1005,7 +1010,7 @@ __device__ inline void block_excl_scan_1024(uint32_t (&v)[K], uint32_t (&tot)[K]
 
 // Levels 1..kPrefixLevels of one scene of n > 0 sorted bodies (the root,
 // node 0, written by k_box_final): one block of 1024 threads. Reads the marks
-// of k_prefix_marks (restoring them to "none"), turns them into the first
+// the gather wrote (restoring them to "none"), turns them into the first
 // body of every level-5 cell (held in LDS, one pad word after every 32 so
 // that a thread's 32 consecutive cells fall in distinct banks), and writes
 // the nodes of levels 1..5 (those of level 5 unsplit, for the level-5 split),
@@ -1629,8 +1634,29 @@ bool enqueue_keys_sort(const Workspace &w, hipStream_t s, const Layout &lay, con
     return false;
 }
 
-// Stages 5-6 on the sorted bodies.
-void enqueue_levels(const Workspace &w, hipStream_t s, const Layout &lay, int leaf, bool use_eps)
+// How a build launches its levels, read once from the previous build's hints:
+// levels 0..deep-1 get a launch each (the deeper ones share one block), and
+// with `prefix` a single scene's levels 1..kPrefixLevels are read off the
+// sorted keys instead (the gather writes the marks k_prefix_levels reads).
+struct LevelPlan {
+    int deep = kMaxLevel, prev = -1;
+    bool prefix = false;
+};
+
+LevelPlan plan_levels(const Workspace &w, const Layout &lay)
+{
+    LevelPlan p;
+    if (w.depth_host) {
+        p.prev = *(const volatile int32_t *)w.depth_host;
+        if (p.prev >= 0 && p.prev + 1 < p.deep) p.deep = p.prev + 1;
+    }
+    p.prefix = lay.n_scenes == 1 && p.deep > kPrefixLevels && w.prefix_mark != nullptr;
+    return p;
+}
+
+// Stages 5-6 on the sorted bodies (with the plan the gather was launched with).
+void enqueue_levels(const Workspace &w, hipStream_t s, const Layout &lay, int leaf, bool use_eps,
+                    const LevelPlan &plan)
 {
     const int64_t n = lay.n;
     const int ns = lay.n_scenes;
@@ -1641,21 +1667,14 @@ void enqueue_levels(const Workspace &w, hipStream_t s, const Layout &lay, int le
     // 0..head-1, at most 585 nodes) in one block too. (Splitting the top
     // levels in one block was measured slower: its binary searches over all
     // bodies run four passes deep there.) The split only affects speed.
-    int deep = kMaxLevel, prev = -1;
+    const int deep = plan.deep, prev = plan.prev;
     const volatile int32_t *hint = w.depth_host;
-    if (hint) {
-        prev = hint[0];
-        if (prev >= 0 && prev + 1 < deep) deep = prev + 1;
-    }
     const int head = ns == 1 ? (deep < 4 ? deep : 4) : 0;
-    // one scene: levels 1..kPrefixLevels from the sorted keys in two launches
-    // instead of one per level (when the previous build went deeper)
-    const bool prefix = ns == 1 && deep > kPrefixLevels && w.prefix_mark != nullptr;
-    if (prefix) {
-        k_prefix_marks<<<blocks_for(n, 256, 1u << 30), 256, 0, s>>>(w.keys[0], n, w.prefix_mark);
+    // one scene: levels 1..kPrefixLevels from the marks of the gather in one
+    // block instead of one launch per level (when the previous build went deeper)
+    if (plan.prefix)
         k_prefix_levels<<<1, 1024, 0, s>>>(w.prefix_mark, n, w.hdr, w.ninfo, w.node_cap, leaf);
-    }
-    for (int level = prefix ? kPrefixLevels : 0; level < deep; level++) {
+    for (int level = plan.prefix ? kPrefixLevels : 0; level < deep; level++) {
         // a level whose next level held no more nodes in the previous build
         // holds mostly leaves: one thread per node, the splitting ones listed;
         // otherwise eight lanes per node. Levels of many nodes take 1024-thread
@@ -1759,9 +1778,11 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
     if (n == 0) return hipGetLastError();
     const bool bk = enqueue_keys_sort(w, s, lay, pos, 3);
     if (bucket) *bucket = bk;
+    const LevelPlan plan = plan_levels(w, lay);
     k_gather<<<blocks_for(n, 256, 1u << 30), 256, 0, s>>>(pos, mass, eps, w.idx[0], n, w.body,
-                                                          w.beps2);
-    enqueue_levels(w, s, lay, leaf, eps != nullptr);
+                                                          w.beps2, w.keys[0],
+                                                          plan.prefix ? w.prefix_mark : nullptr);
+    enqueue_levels(w, s, lay, leaf, eps != nullptr, plan);
     return hipGetLastError();
 }
 
@@ -1781,10 +1802,11 @@ hipError_t launch_build_state(const Workspace &w, hipStream_t s, const Layout &l
     k_box_final<<<sb, 256, 0, s>>>(w.box, ns, lay.offsets, n, w.hdr, w.ninfo);
     const bool bk = enqueue_keys_sort(w, s, lay, reinterpret_cast<const double *>(w.sbody), 4);
     if (bucket) *bucket = bk;
+    const LevelPlan plan = plan_levels(w, lay);
     k_gather_state<<<blocks_for(n, 256, 1u << 30), 256, 0, s>>>(
         w.sbody, w.svel, use_eps ? w.seps2 : nullptr, w.scidx, n, w.idx[0], w.body, w.tvel,
-        w.beps2);
-    enqueue_levels(w, s, lay, leaf, use_eps);
+        w.beps2, w.keys[0], plan.prefix ? w.prefix_mark : nullptr);
+    enqueue_levels(w, s, lay, leaf, use_eps, plan);
     return hipGetLastError();
 }
 
