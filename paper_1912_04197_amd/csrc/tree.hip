@@ -351,6 +351,34 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint64_t *__re
 }
 
 // Exclusive scan of one digit's row of tile counts; one block per digit.
+// k_keys for one scene with the tile layout of k_sort_hist, and that kernel's
+// digit counts of the first pass (bits shift..shift+7) of the same tile.
+__global__ __launch_bounds__(kSortThreads) void k_keys_hist(const double *__restrict__ pos,
+                                                            int stride, int64_t n,
+                                                            const SceneBox *__restrict__ box,
+                                                            uint64_t *__restrict__ keys,
+                                                            uint32_t *__restrict__ idx, int shift,
+                                                            uint32_t *__restrict__ counts,
+                                                            int nblk)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const SceneBox &b = box[0];
+    const int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; r++) {
+        const int64_t i = base + r * kSortThreads + threadIdx.x;
+        if (i < n) {
+            const uint64_t key = morton_key(pos + stride * i, b);
+            keys[i] = key;
+            idx[i] = (uint32_t)i;
+            atomicAdd(&h[(uint32_t)(key >> shift) & 255u], 1u);
+        }
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+}
+
 __global__ __launch_bounds__(256) void k_sort_scan(uint32_t *__restrict__ counts,
                                                    uint32_t *__restrict__ totals, int nblk)
 {
@@ -1589,11 +1617,14 @@ bool enqueue_keys_sort(const Workspace &w, hipStream_t s, const Layout &lay, con
     if (bucket_sort_hint(w, lay)) {
         // two passes on the top 16 key bits (buffer 0 -> 1 -> 0), then the
         // buckets in place
-        k_keys<<<nb0, 256, 0, s>>>(pos, stride, n, w.box, nullptr, w.keys[0], w.idx[0]);
+        // the keys come with the first pass's digit counts
+        k_keys_hist<<<nblk, kSortThreads, 0, s>>>(pos, stride, n, w.box, w.keys[0], w.idx[0],
+                                                  kTopShift, w.sort_counts, nblk);
         for (int pass = 0; pass < 2; pass++) {
             const int shift = kTopShift + 8 * pass, src = pass, dst = pass ^ 1;
-            k_sort_hist<<<nblk, kSortThreads, 0, s>>>(w.keys[src], w.idx[src], nullptr, nullptr, 1,
-                                                      n, shift, w.sort_counts, nblk);
+            if (pass > 0)
+                k_sort_hist<<<nblk, kSortThreads, 0, s>>>(w.keys[src], w.idx[src], nullptr, nullptr,
+                                                          1, n, shift, w.sort_counts, nblk);
             k_sort_scan<<<256, 256, 0, s>>>(w.sort_counts, w.sort_totals, nblk);
             k_sort_scatter<<<nblk, kSortThreads, 0, s>>>(w.keys[src], w.idx[src], nullptr, nullptr,
                                                          1, w.keys[dst], w.idx[dst], n, shift,
