@@ -525,6 +525,13 @@ struct LocalShape {
 using LocalBig = LocalShape<1024>;
 using LocalSmall = LocalShape<256>;
 constexpr int kBucketMax = 1024;  // bucket bound both shapes are sized for
+// Buckets sorted by comparison instead of radix passes: when the previous
+// build held at most kRankPerNode bodies per level-5 node on average (a
+// bucket is half such a node), in ranges whose buckets all hold at most
+// kRankMax keys. Each key's comparisons walk its bucket in LDS, so the cost
+// grows with the bucket; with tens of keys per bucket the passes are faster.
+constexpr int kRankMax = 32;
+constexpr int64_t kRankPerNode = 8;
 static_assert(LocalBig::kTile > 0 && LocalSmall::kTile > 0, "tiles");
 constexpr int64_t kBigSortFrom = (int64_t)256 * LocalBig::kTile;  // 256 blocks of the big shape
 
@@ -630,13 +637,14 @@ __global__ __launch_bounds__(Sh::kThreads) void k_sort_local(uint64_t *__restric
                                                              uint32_t *__restrict__ idx,
                                                              uint64_t *__restrict__ ktmp,
                                                              uint32_t *__restrict__ itmp,
-                                                             int64_t n)
+                                                             int64_t n, int rank_small)
 {
     __shared__ LocalScratch<Sh> S;
     __shared__ uint64_t skey[2][Sh::kCap];
     __shared__ uint32_t sval[2][Sh::kCap];
     __shared__ int64_t srange[2];
     __shared__ uint32_t sdiff[2];
+    __shared__ uint32_t sbig;  // a bucket of more than kRankMax keys in the range
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t t0 = (int64_t)blockIdx.x * Sh::kTile;
     const int64_t t1 = t0 + Sh::kTile < n ? t0 + Sh::kTile : n;
@@ -684,7 +692,50 @@ __global__ __launch_bounds__(Sh::kThreads) void k_sort_local(uint64_t *__restric
             skey[0][i] = keys[a + i];
             sval[0][i] = idx[a + i];
         }
+        if (tid == 0) sbig = rank_small ? 0u : 1u;
         __syncthreads();
+        // With rank_small, and buckets of at most kRankMax keys: each key's
+        // place is its bucket's start plus the number of keys of the bucket
+        // before it in (key, position) order, a stable sort by comparison,
+        // with no radix passes. A larger bucket sends the whole range to the
+        // radix passes below.
+        constexpr int kR = Sh::kCap / Sh::kThreads;
+        int32_t dest[kR];
+#pragma unroll
+        for (int r = 0; r < kR; r++) {
+            const int i = tid + r * Sh::kThreads;
+            dest[r] = -1;
+            if (!rank_small || i >= m) continue;
+            const uint64_t k = skey[0][i];
+            const uint64_t top = k >> kTopShift;
+            int bs = i, be = i + 1;
+            while (bs > 0 && i - bs < kRankMax && (skey[0][bs - 1] >> kTopShift) == top) bs--;
+            while (be < m && be - bs <= kRankMax && (skey[0][be] >> kTopShift) == top) be++;
+            const bool big = be - bs > kRankMax ||
+                             (bs > 0 && i - bs == kRankMax && (skey[0][bs - 1] >> kTopShift) == top);
+            if (big) {
+                sbig = 1u;
+                continue;
+            }
+            int32_t rank = bs;
+            for (int j = bs; j < be; j++) {
+                const uint64_t kj = skey[0][j];
+                rank += kj < k || (kj == k && j < i);
+            }
+            dest[r] = rank;
+        }
+        __syncthreads();
+        if (sbig == 0u) {  // the same on every thread
+#pragma unroll
+            for (int r = 0; r < kR; r++) {
+                const int i = tid + r * Sh::kThreads;
+                if (i < m) {
+                    keys[a + dest[r]] = skey[0][i];
+                    idx[a + dest[r]] = sval[0][i];
+                }
+            }
+            return;
+        }
         int src = 0;
         for (int pass = 0; pass < 8; pass++) {
             if (((diff >> (8 * pass)) & 255u) == 0) continue;  // the same on every thread
@@ -1630,14 +1681,19 @@ bool enqueue_keys_sort(const Workspace &w, hipStream_t s, const Layout &lay, con
                                                          1, w.keys[dst], w.idx[dst], n, shift,
                                                          w.sort_counts, w.sort_totals, nblk);
         }
+        // small buckets are placed by comparison (the previous build's mean
+        // bodies per level-5 node picks it; only speed depends on it)
+        const int32_t n5 = ((const volatile int32_t *)w.depth_host)[2 + kHintLevel];
+        const int rank_small = n5 > 0 && n <= kRankPerNode * (int64_t)n5 ? 1 : 0;
         if (n >= kBigSortFrom)
             k_sort_local<LocalBig>
                 <<<(unsigned)((n + LocalBig::kTile - 1) / LocalBig::kTile), LocalBig::kThreads, 0,
-                   s>>>(w.keys[0], w.idx[0], w.keys[1], w.idx[1], n);
+                   s>>>(w.keys[0], w.idx[0], w.keys[1], w.idx[1], n, rank_small);
         else
             k_sort_local<LocalSmall>
                 <<<(unsigned)((n + LocalSmall::kTile - 1) / LocalSmall::kTile),
-                   LocalSmall::kThreads, 0, s>>>(w.keys[0], w.idx[0], w.keys[1], w.idx[1], n);
+                   LocalSmall::kThreads, 0, s>>>(w.keys[0], w.idx[0], w.keys[1], w.idx[1], n,
+                                                 rank_small);
 #ifdef BHX_CHECKS
         k_check_order<<<nb0, 256, 0, s>>>(w.keys[0], w.idx[0], n);
 #endif

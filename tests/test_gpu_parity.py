@@ -320,14 +320,16 @@ def test_plummer_131072_sampled(api):
         _check_acc(acc[sample], ref_acc, aabs, FP32C_TOL, f"plummer theta={theta}")
 
 
-@pytest.mark.parametrize("second", ["uniform", "cluster"])
+@pytest.mark.parametrize("second", ["uniform", "cluster", "clump400"])
 def test_bucket_sort_tree_parity(api, second):
     """A build of one scene above 4096 bodies sorts by buckets of the top 16
     key bits when the context's previous build had at most 1024 bodies in
     every level-5 node. Such a build's tree equals the oracle's bit for bit,
-    with its ranges of whole buckets sorted in LDS (a uniform ball) or, where
-    half the bodies crowd into a cluster far smaller than a level-5 cell
-    (50,000 bodies in one bucket), in global memory."""
+    with its ranges of whole buckets sorted in LDS (a uniform ball: buckets
+    of a few keys, each key placed by comparison within its bucket; 400
+    bodies crowded into one bucket: that range by radix passes in LDS) or,
+    where half the bodies crowd into a cluster far smaller than a level-5
+    cell (50,000 bodies in one bucket), in global memory."""
     n = 100000
     first = ics.uniform_ball(n, seed=61)
     ctx = _ctx(api, n, leaf=8, precision="fp64", counts=False)
@@ -336,6 +338,8 @@ def test_bucket_sort_tree_parity(api, second):
     s = ics.uniform_ball(n, seed=62)
     if second == "cluster":
         s.pos[: n // 2] = 1e-3 * s.pos[: n // 2] + 0.2
+    if second == "clump400":
+        s.pos[:400] = 1e-5 * s.pos[:400] + 0.2
     _check_tree(ctx, s, 8, per_body=False)
     assert ctx.stats()["bucket_sort"]
     if second == "cluster":
