@@ -637,7 +637,9 @@ __global__ __launch_bounds__(Sh::kThreads) void k_sort_local(uint64_t *__restric
                                                              uint32_t *__restrict__ idx,
                                                              uint64_t *__restrict__ ktmp,
                                                              uint32_t *__restrict__ itmp,
-                                                             int64_t n, int rank_small)
+                                                             int64_t n, int rank_small,
+                                                             const int64_t *__restrict__ offsets,
+                                                             int ns)
 {
     __shared__ LocalScratch<Sh> S;
     __shared__ uint64_t skey[2][Sh::kCap];
@@ -645,13 +647,32 @@ __global__ __launch_bounds__(Sh::kThreads) void k_sort_local(uint64_t *__restric
     __shared__ int64_t srange[2];
     __shared__ uint32_t sdiff[2];
     __shared__ uint32_t sbig;  // a bucket of more than kRankMax keys in the range
+    __shared__ int64_t soff[kLdsScenes + 1];  // scene starts in sorted order (several scenes)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t t0 = (int64_t)blockIdx.x * Sh::kTile;
     const int64_t t1 = t0 + Sh::kTile < n ? t0 + Sh::kTile : n;
+    // Several scenes (at most kLdsScenes): each keeps its caller range of
+    // positions, so a bucket also ends where a scene starts.
+    if (ns > 1)
+        for (int i = tid; i <= ns; i += Sh::kThreads) soff[i] = offsets[i];
+    __syncthreads();
+    auto next_start = [&](int64_t x) {  // the first scene start at or after x (n past the last)
+        if (ns <= 1) return n;
+        int lo = 0, hi = ns;  // soff[hi] = n >= x
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (soff[mid] >= x)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        return soff[lo];
+    };
     // wave 0: the first bucket that starts in [t0, t1) (past the one holding
-    // key t0 - 1); wave 1: the end of the bucket holding key t1 - 1. Buckets
-    // are in ascending order of their top bits, so each is the first key at
-    // or after the search start whose top bits differ from that key's.
+    // key t0 - 1); wave 1: the end of the bucket holding key t1 - 1. Within a
+    // scene buckets are in ascending order of their top bits, so each ends at
+    // the first key whose top bits differ from the search start's, or at the
+    // next scene's start.
     if (wave < 2) {
         const int64_t from = wave == 0 ? t0 : t1;
         int64_t pos = from;
@@ -666,105 +687,115 @@ __global__ __launch_bounds__(Sh::kThreads) void k_sort_local(uint64_t *__restric
                     break;
                 }
             }
+            pos = min(pos, next_start(from));
         }
         if (lane == 0) srange[wave] = pos;
     }
-    if (tid < 2) sdiff[tid] = 0u;
     __syncthreads();
-    const int64_t a = srange[0], b = srange[1];
-    if (a >= t1) return;  // no bucket starts here: the block of its start sorts it
-    const int64_t m = b - a;
-    // the key bits that differ somewhere in the range (OR of key ^ first key)
-    {
-        const uint64_t k0 = keys[a];
-        uint64_t d = 0;
-        for (int64_t i = tid; i < m; i += Sh::kThreads) d |= keys[a + i] ^ k0;
-        for (int o = 32; o > 0; o >>= 1) d |= __shfl_xor(d, o);
-        if (lane == 0) {
-            atomicOr(&sdiff[0], (uint32_t)d);
-            atomicOr(&sdiff[1], (uint32_t)(d >> 32));
-        }
-    }
-    __syncthreads();
-    const uint64_t diff = (uint64_t)sdiff[1] << 32 | sdiff[0];
-    if (m <= Sh::kCap) {
-        for (int i = tid; i < m; i += Sh::kThreads) {
-            skey[0][i] = keys[a + i];
-            sval[0][i] = idx[a + i];
-        }
-        if (tid == 0) sbig = rank_small ? 0u : 1u;
+    const int64_t ra = srange[0], rb = srange[1];
+    if (ra >= t1) return;  // no bucket starts here: the block of its start sorts it
+    // the range [ra, rb) one scene at a time
+    auto sort_range = [&](const int64_t a, const int64_t m) {
+        __syncthreads();  // the previous range is done with the LDS
+        if (tid < 2) sdiff[tid] = 0u;
         __syncthreads();
-        // With rank_small, and buckets of at most kRankMax keys: each key's
-        // place is its bucket's start plus the number of keys of the bucket
-        // before it in (key, position) order, a stable sort by comparison,
-        // with no radix passes. A larger bucket sends the whole range to the
-        // radix passes below.
-        constexpr int kR = Sh::kCap / Sh::kThreads;
-        int32_t dest[kR];
-#pragma unroll
-        for (int r = 0; r < kR; r++) {
-            const int i = tid + r * Sh::kThreads;
-            dest[r] = -1;
-            if (!rank_small || i >= m) continue;
-            const uint64_t k = skey[0][i];
-            const uint64_t top = k >> kTopShift;
-            int bs = i, be = i + 1;
-            while (bs > 0 && i - bs < kRankMax && (skey[0][bs - 1] >> kTopShift) == top) bs--;
-            while (be < m && be - bs <= kRankMax && (skey[0][be] >> kTopShift) == top) be++;
-            const bool big = be - bs > kRankMax ||
-                             (bs > 0 && i - bs == kRankMax && (skey[0][bs - 1] >> kTopShift) == top);
-            if (big) {
-                sbig = 1u;
-                continue;
+        // the key bits that differ somewhere in the range (OR of key ^ first key)
+        {
+            const uint64_t k0 = keys[a];
+            uint64_t d = 0;
+            for (int64_t i = tid; i < m; i += Sh::kThreads) d |= keys[a + i] ^ k0;
+            for (int o = 32; o > 0; o >>= 1) d |= __shfl_xor(d, o);
+            if (lane == 0) {
+                atomicOr(&sdiff[0], (uint32_t)d);
+                atomicOr(&sdiff[1], (uint32_t)(d >> 32));
             }
-            int32_t rank = bs;
-            for (int j = bs; j < be; j++) {
-                const uint64_t kj = skey[0][j];
-                rank += kj < k || (kj == k && j < i);
-            }
-            dest[r] = rank;
         }
         __syncthreads();
-        if (sbig == 0u) {  // the same on every thread
+        const uint64_t diff = (uint64_t)sdiff[1] << 32 | sdiff[0];
+        if (m <= Sh::kCap) {
+            for (int i = tid; i < m; i += Sh::kThreads) {
+                skey[0][i] = keys[a + i];
+                sval[0][i] = idx[a + i];
+            }
+            if (tid == 0) sbig = rank_small ? 0u : 1u;
+            __syncthreads();
+            // With rank_small, and buckets of at most kRankMax keys: each key's
+            // place is its bucket's start plus the number of keys of the bucket
+            // before it in (key, position) order, a stable sort by comparison,
+            // with no radix passes. A larger bucket sends the whole range to the
+            // radix passes below.
+            constexpr int kR = Sh::kCap / Sh::kThreads;
+            int32_t dest[kR];
 #pragma unroll
             for (int r = 0; r < kR; r++) {
                 const int i = tid + r * Sh::kThreads;
-                if (i < m) {
-                    keys[a + dest[r]] = skey[0][i];
-                    idx[a + dest[r]] = sval[0][i];
+                dest[r] = -1;
+                if (!rank_small || i >= m) continue;
+                const uint64_t k = skey[0][i];
+                const uint64_t top = k >> kTopShift;
+                int bs = i, be = i + 1;
+                while (bs > 0 && i - bs < kRankMax && (skey[0][bs - 1] >> kTopShift) == top) bs--;
+                while (be < m && be - bs <= kRankMax && (skey[0][be] >> kTopShift) == top) be++;
+                const bool big = be - bs > kRankMax ||
+                                 (bs > 0 && i - bs == kRankMax && (skey[0][bs - 1] >> kTopShift) == top);
+                if (big) {
+                    sbig = 1u;
+                    continue;
+                }
+                int32_t rank = bs;
+                for (int j = bs; j < be; j++) {
+                    const uint64_t kj = skey[0][j];
+                    rank += kj < k || (kj == k && j < i);
+                }
+                dest[r] = rank;
+            }
+            __syncthreads();
+            if (sbig == 0u) {  // the same on every thread
+#pragma unroll
+                for (int r = 0; r < kR; r++) {
+                    const int i = tid + r * Sh::kThreads;
+                    if (i < m) {
+                        keys[a + dest[r]] = skey[0][i];
+                        idx[a + dest[r]] = sval[0][i];
+                    }
+                }
+                return;
+            }
+            int src = 0;
+            for (int pass = 0; pass < 8; pass++) {
+                if (((diff >> (8 * pass)) & 255u) == 0) continue;  // the same on every thread
+                block_radix_pass<Sh>(skey[src], sval[src], skey[src ^ 1], sval[src ^ 1], m, 8 * pass,
+                                     S);
+                src ^= 1;
+            }
+            for (int i = tid; i < m; i += Sh::kThreads) {
+                keys[a + i] = skey[src][i];
+                idx[a + i] = sval[src][i];
+            }
+        } else {
+            // buffers alternate between the keys and the scratch; an odd number
+            // of passes ends with a copy back
+            bool in_keys = true;
+            for (int pass = 0; pass < 8; pass++) {
+                if (((diff >> (8 * pass)) & 255u) == 0) continue;
+                if (in_keys)
+                    block_radix_pass<Sh>(keys + a, idx + a, ktmp + a, itmp + a, m, 8 * pass, S);
+                else
+                    block_radix_pass<Sh>(ktmp + a, itmp + a, keys + a, idx + a, m, 8 * pass, S);
+                in_keys = !in_keys;
+            }
+            if (!in_keys) {
+                for (int64_t i = tid; i < m; i += Sh::kThreads) {
+                    keys[a + i] = ktmp[a + i];
+                    idx[a + i] = itmp[a + i];
                 }
             }
-            return;
         }
-        int src = 0;
-        for (int pass = 0; pass < 8; pass++) {
-            if (((diff >> (8 * pass)) & 255u) == 0) continue;  // the same on every thread
-            block_radix_pass<Sh>(skey[src], sval[src], skey[src ^ 1], sval[src ^ 1], m, 8 * pass,
-                                 S);
-            src ^= 1;
-        }
-        for (int i = tid; i < m; i += Sh::kThreads) {
-            keys[a + i] = skey[src][i];
-            idx[a + i] = sval[src][i];
-        }
-    } else {
-        // buffers alternate between the keys and the scratch; an odd number
-        // of passes ends with a copy back
-        bool in_keys = true;
-        for (int pass = 0; pass < 8; pass++) {
-            if (((diff >> (8 * pass)) & 255u) == 0) continue;
-            if (in_keys)
-                block_radix_pass<Sh>(keys + a, idx + a, ktmp + a, itmp + a, m, 8 * pass, S);
-            else
-                block_radix_pass<Sh>(ktmp + a, itmp + a, keys + a, idx + a, m, 8 * pass, S);
-            in_keys = !in_keys;
-        }
-        if (!in_keys) {
-            for (int64_t i = tid; i < m; i += Sh::kThreads) {
-                keys[a + i] = ktmp[a + i];
-                idx[a + i] = itmp[a + i];
-            }
-        }
+    };
+    for (int64_t sa = ra; sa < rb;) {
+        const int64_t sb = min(rb, next_start(sa + 1));
+        sort_range(sa, sb - sa);
+        sa = sb;
     }
 }
 
@@ -772,12 +803,27 @@ __global__ __launch_bounds__(Sh::kThreads) void k_sort_local(uint64_t *__restric
 // The checked build's verification of a one-scene sort: keys in order and
 // every index inside the array.
 __global__ __launch_bounds__(256) void k_check_order(const uint64_t *__restrict__ keys,
-                                                     const uint32_t *__restrict__ idx, int64_t n)
+                                                     const uint32_t *__restrict__ idx, int64_t n,
+                                                     const int64_t *__restrict__ offsets, int ns)
 {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     BHX_CHECK(idx[i] < n, CK_INDEX);
-    BHX_CHECK(i == 0 || keys[i - 1] <= keys[i], CK_ORDER);
+    if (i == 0 || keys[i - 1] <= keys[i]) return;
+    // a descent is in order only where a scene starts
+    bool start = false;
+    if (ns > 1) {
+        int lo = 0, hi = ns;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (offsets[mid] >= i)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        start = offsets[lo] == i;
+    }
+    BHX_CHECK(start, CK_ORDER);
 }
 #endif
 
@@ -1666,20 +1712,28 @@ bool enqueue_keys_sort(const Workspace &w, hipStream_t s, const Layout &lay, con
     const int nblk = (int)((n + kSortTile - 1) / kSortTile);
     const unsigned nb0 = blocks_for(n, 256, 1u << 30);
     if (bucket_sort_hint(w, lay)) {
-        // two passes on the top 16 key bits (buffer 0 -> 1 -> 0), then the
-        // buckets in place
-        // the keys come with the first pass's digit counts
-        k_keys_hist<<<nblk, kSortThreads, 0, s>>>(pos, stride, n, w.box, w.keys[0], w.idx[0],
-                                                  kTopShift, w.sort_counts, nblk);
-        for (int pass = 0; pass < 2; pass++) {
-            const int shift = kTopShift + 8 * pass, src = pass, dst = pass ^ 1;
-            if (pass > 0)
-                k_sort_hist<<<nblk, kSortThreads, 0, s>>>(w.keys[src], w.idx[src], nullptr, nullptr,
-                                                          1, n, shift, w.sort_counts, nblk);
+        // two passes on the top 16 key bits and, for several scenes, one on
+        // the scene index (ending in buffer 0), then the buckets in place
+        const int passes = ns > 1 ? 3 : 2;
+        const int first = passes & 1;
+        if (ns == 1)  // the keys come with the first pass's digit counts
+            k_keys_hist<<<nblk, kSortThreads, 0, s>>>(pos, stride, n, w.box, w.keys[0], w.idx[0],
+                                                      kTopShift, w.sort_counts, nblk);
+        else
+            k_keys<<<nb0, 256, 0, s>>>(pos, stride, n, w.box, lay.scene_of, w.keys[first],
+                                       w.idx[first]);
+        for (int pass = 0; pass < passes; pass++) {
+            const int shift = pass < 2 ? kTopShift + 8 * pass : 64;
+            const int src = (pass + first) & 1, dst = src ^ 1;
+            if (ns > 1 || pass > 0)
+                k_sort_hist<<<nblk, kSortThreads, 0, s>>>(w.keys[src], w.idx[src], lay.scene_of,
+                                                          lay.offsets, ns, n, shift, w.sort_counts,
+                                                          nblk);
             k_sort_scan<<<256, 256, 0, s>>>(w.sort_counts, w.sort_totals, nblk);
-            k_sort_scatter<<<nblk, kSortThreads, 0, s>>>(w.keys[src], w.idx[src], nullptr, nullptr,
-                                                         1, w.keys[dst], w.idx[dst], n, shift,
-                                                         w.sort_counts, w.sort_totals, nblk);
+            k_sort_scatter<<<nblk, kSortThreads, 0, s>>>(w.keys[src], w.idx[src], lay.scene_of,
+                                                         lay.offsets, ns, w.keys[dst], w.idx[dst],
+                                                         n, shift, w.sort_counts, w.sort_totals,
+                                                         nblk);
         }
         // small buckets are placed by comparison (the previous build's mean
         // bodies per level-5 node picks it; only speed depends on it)
@@ -1688,14 +1742,14 @@ bool enqueue_keys_sort(const Workspace &w, hipStream_t s, const Layout &lay, con
         if (n >= kBigSortFrom)
             k_sort_local<LocalBig>
                 <<<(unsigned)((n + LocalBig::kTile - 1) / LocalBig::kTile), LocalBig::kThreads, 0,
-                   s>>>(w.keys[0], w.idx[0], w.keys[1], w.idx[1], n, rank_small);
+                   s>>>(w.keys[0], w.idx[0], w.keys[1], w.idx[1], n, rank_small, lay.offsets, ns);
         else
             k_sort_local<LocalSmall>
                 <<<(unsigned)((n + LocalSmall::kTile - 1) / LocalSmall::kTile),
                    LocalSmall::kThreads, 0, s>>>(w.keys[0], w.idx[0], w.keys[1], w.idx[1], n,
-                                                 rank_small);
+                                                 rank_small, lay.offsets, ns);
 #ifdef BHX_CHECKS
-        k_check_order<<<nb0, 256, 0, s>>>(w.keys[0], w.idx[0], n);
+        k_check_order<<<nb0, 256, 0, s>>>(w.keys[0], w.idx[0], n, lay.offsets, ns);
 #endif
         return true;
     }
@@ -1716,7 +1770,7 @@ bool enqueue_keys_sort(const Workspace &w, hipStream_t s, const Layout &lay, con
                                                      shift, w.sort_counts, w.sort_totals, nblk);
     }
 #ifdef BHX_CHECKS
-    if (ns == 1) k_check_order<<<nb0, 256, 0, s>>>(w.keys[0], w.idx[0], n);
+    k_check_order<<<nb0, 256, 0, s>>>(w.keys[0], w.idx[0], n, lay.offsets, ns);
 #endif
     return false;
 }
@@ -1837,7 +1891,7 @@ hipError_t launch_merge_status(hipStream_t s, TreeHeader *slot_hdr, int count, u
 
 bool bucket_sort_hint(const Workspace &w, const Layout &lay)
 {
-    if (lay.n_scenes != 1 || lay.n <= kSmallBuild || !w.depth_host) return false;
+    if (lay.n_scenes > kLdsScenes || lay.n <= kSmallBuild || !w.depth_host) return false;
     // a range is a tile plus at most one bucket, and a bucket lies inside one
     // node of level kHintLevel (its top 16 bits fix the first 5 levels)
     const int cell = ((const volatile int32_t *)w.depth_host)[1];

@@ -59,13 +59,20 @@ def test_batched_accel_parity(api, precision):
 
 @pytest.mark.parametrize("group", [64, 16])
 def test_batched_equals_single_scene_calls(api, group):
+    """Each scene of a batch equals its own single-scene call bit for bit, on
+    the first batched build (sorted by passes) and on the second (sorted by
+    buckets of the top key bits per scene, chosen from the first build's
+    hint)."""
     sc, off, pos, mass = _scenes(9, 30, 3000, 8)
+    assert off[-1] > 4096  # the bucket sort needs more than one block's bodies
     ctx = api.Context(len(mass), leaf_size=16, precision="fp32c", max_scenes=9, walk_group=group)
-    acc = ctx.batched_accel(off, _dev(pos), _dev(mass), 0.6, softening=1e-3).cpu().numpy()
     single = api.Context(len(mass), leaf_size=16, precision="fp32c", walk_group=group)
-    for k, s in enumerate(sc):
-        a1 = single.compute_accel(_dev(s.pos), _dev(s.mass), 0.6, softening=1e-3).cpu().numpy()
-        assert np.array_equal(acc[off[k]:off[k + 1]], a1), k
+    for call in range(2):
+        acc = ctx.batched_accel(off, _dev(pos), _dev(mass), 0.6, softening=1e-3).cpu().numpy()
+        assert ctx.stats()["bucket_sort"] == (call == 1)
+        for k, s in enumerate(sc):
+            a1 = single.compute_accel(_dev(s.pos), _dev(s.mass), 0.6, softening=1e-3).cpu().numpy()
+            assert np.array_equal(acc[off[k]:off[k + 1]], a1), (call, k)
 
 
 def test_batched_step_graph_replays(api):
@@ -176,6 +183,11 @@ def test_batched_256_scene_workload(api, leaf, group):
     mass = _dev(np.concatenate([s.mass for s in scenes]))
     acc = ctx.batched_accel(off, pos, mass, 0.5, softening=1e-3).cpu().numpy()
     cnt = ctx.walk_counts(n).cpu().numpy()
+    # a second build sorts each scene by buckets (the first build's hint): the
+    # same order, so the same accelerations bit for bit
+    acc2 = ctx.batched_accel(off, pos, mass, 0.5, softening=1e-3).cpu().numpy()
+    assert ctx.stats()["bucket_sort"]
+    assert np.array_equal(acc2, acc)
     rng = np.random.default_rng(4)
     for k in rng.choice(256, 8, replace=False):
         s = scenes[k]
