@@ -20,8 +20,8 @@
 //      summed in registers and LDS, each source's terms are summed over the
 //      group and added with FP64 atomics into the body or node adjoints;
 //   3. node adjoints become per-node coefficients (A = gX / m_N,
-//      E = ge2 / m_N, C = gm - X.A - <eps^2> E), summed top-down over each
-//      body's ancestors, one launch per level;
+//      E = ge2 / m_N, C = gm - X.A - <eps^2> E), summed from the root down
+//      over each leaf's ancestors (found through a parent table);
 //   4. per body: g_x += m_j sum A, g_m += sum C + x_j . sum A + eps_j^2 sum E,
 //      plus its own target and source terms, added into the caller's arrays.
 // Source-side atomics make the last bits of the gradients order-dependent.
@@ -68,7 +68,6 @@ __device__ inline float dpp(float v)
 }
 
 constexpr int kPairCap = 448;  // pairs per batch
-constexpr int kPushHead = 4;   // levels whose coefficients are pushed down in one block
 
 // badj: per sorted body {gX x, y, z, gm}; nadj: per node {gX x, y, z, gm, ge2}.
 //
@@ -428,11 +427,12 @@ __global__ __launch_bounds__(64) void k_vjp_walk(
     }
 }
 
-// Zeroes body adjoints (4 per body) and the adjoints and prefix sums of the
-// nodes that exist (5 + 5 per node).
+// Zeroes body adjoints (4 per body) and node adjoints (5 per node that
+// exists), and writes each node's parent (-1 for the root).
 __global__ __launch_bounds__(256) void k_vjp_clear(double *__restrict__ badj, int64_t n,
                                                    double *__restrict__ nadj,
-                                                   double *__restrict__ npre,
+                                                   int32_t *__restrict__ nparent,
+                                                   const NodeInfo *__restrict__ ninfo,
                                                    const TreeHeader *__restrict__ hdr,
                                                    int64_t node_cap)
 {
@@ -440,10 +440,16 @@ __global__ __launch_bounds__(256) void k_vjp_clear(double *__restrict__ badj, in
     for (int l = 0; l < kLevels; l++) nn += hdr->level_count[l];
     if (nn > node_cap) nn = node_cap;
     const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < 4 * n; i += stride) badj[i] = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < 5 * nn; i += stride) {
-        nadj[i] = 0.0;
-        npre[i] = 0.0;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    for (int64_t i = t; i < 4 * n; i += stride) badj[i] = 0.0;
+    for (int64_t i = t; i < 5 * nn; i += stride) nadj[i] = 0.0;
+    if (t == 0 && nn > 0) nparent[0] = -1;
+    for (int64_t k = t; k < nn; k += stride) {
+        const NodeInfo info = ninfo[k];
+        if (info.child0 < 0) continue;
+        const int nch = node_nchild(info);
+        for (int o = 0; o < nch; o++)
+            if (check_ok((int64_t)info.child0 + o < nn, CK_INDEX)) nparent[info.child0 + o] = (int32_t)k;
     }
 }
 
@@ -465,92 +471,19 @@ __device__ inline void node_coeffs(const double *__restrict__ nadj, const NodeMo
     }
 }
 
-// npre[child] = npre[node] + coefficients(child), for every child of the
-// nodes of `level`: work item g takes child slot g % 8 of the level's node
-// g / 8, so that a node's children are done side by side.
-__device__ inline void push_level(int level, const TreeHeader *__restrict__ hdr,
-                                  const NodeInfo *__restrict__ ninfo,
-                                  const NodeMom *__restrict__ nmom,
-                                  const double *__restrict__ neps2, int use_eps,
-                                  const double *__restrict__ nadj, double *__restrict__ npre,
-                                  int64_t node_cap, int64_t g_first, int64_t stride)
-{
-    int64_t beg = 0;
-    for (int l = 0; l < level; l++) beg += hdr->level_count[l];
-    int64_t cnt = hdr->level_count[level];
-    if (beg + cnt > node_cap) cnt = node_cap - beg;
-    for (int64_t g = g_first; g < 8 * cnt; g += stride) {
-        const int64_t k = beg + (g >> 3);
-        const int o = (int)(g & 7);
-        const NodeInfo info = ninfo[k];
-        if (info.child0 < 0 || o >= node_nchild(info)) continue;
-        const int32_t c = info.child0 + o;
-        double cf[5];
-        node_coeffs(nadj, nmom[c], use_eps ? neps2[c] : 0.0, c, cf);
-        const double *p = npre + 5 * k;
-        for (int q = 0; q < 5; q++) npre[5 * (int64_t)c + q] = p[q] + cf[q];
-    }
-}
-
-__global__ __launch_bounds__(256) void k_vjp_push(int level, const TreeHeader *__restrict__ hdr,
-                                                  const NodeInfo *__restrict__ ninfo,
-                                                  const NodeMom *__restrict__ nmom,
-                                                  const double *__restrict__ neps2, int use_eps,
-                                                  const double *__restrict__ nadj,
-                                                  double *__restrict__ npre, int64_t node_cap)
-{
-    push_level(level, hdr, ninfo, nmom, neps2, use_eps, nadj, npre, node_cap,
-               (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256);
-}
-
-// The root's coefficients, then levels 0..upto-1 in one block (the top
-// levels hold few nodes).
-__global__ __launch_bounds__(1024) void k_vjp_push_head(int upto, const TreeHeader *__restrict__ hdr,
-                                                        const NodeInfo *__restrict__ ninfo,
-                                                        const NodeMom *__restrict__ nmom,
-                                                        const double *__restrict__ neps2,
-                                                        int use_eps, const double *__restrict__ nadj,
-                                                        double *__restrict__ npre, int64_t node_cap)
-{
-    if (threadIdx.x == 0) {
-        double c[5];
-        node_coeffs(nadj, nmom[0], use_eps ? neps2[0] : 0.0, 0, c);
-        for (int q = 0; q < 5; q++) npre[q] = c[q];
-    }
-    __syncthreads();
-    for (int level = 0; level < upto; level++) {
-        if (hdr->level_count[level] == 0) break;  // the same on every thread
-        push_level(level, hdr, ninfo, nmom, neps2, use_eps, nadj, npre, node_cap, threadIdx.x,
-                   1024);
-        __syncthreads();
-    }
-}
-
-// Levels from..kMaxLevel-1 in one block, stopping at the first level with no
-// nodes (deep levels hold few nodes).
-__global__ __launch_bounds__(1024) void k_vjp_push_tail(int from, const TreeHeader *__restrict__ hdr,
-                                                        const NodeInfo *__restrict__ ninfo,
-                                                        const NodeMom *__restrict__ nmom,
-                                                        const double *__restrict__ neps2,
-                                                        int use_eps, const double *__restrict__ nadj,
-                                                        double *__restrict__ npre, int64_t node_cap)
-{
-    for (int level = from; level < kMaxLevel; level++) {
-        if (hdr->level_count[level] == 0) break;  // the same on every thread
-        push_level(level, hdr, ninfo, nmom, neps2, use_eps, nadj, npre, node_cap, threadIdx.x,
-                   1024);
-        __syncthreads();
-    }
-}
-
-// Every leaf hands the ancestor sums to its members and adds the members'
-// own terms into the caller's gradient arrays (caller order, +=).
+// Every leaf hands the ancestor sums of the node coefficients to its
+// members and adds the members' own terms into the caller's gradient arrays
+// (caller order, +=). A leaf collects its chain of ancestors through the
+// parent table (at most kLevels nodes) and sums their coefficients from the
+// root down.
 __global__ __launch_bounds__(256) void k_vjp_finish(
     const TreeHeader *__restrict__ hdr, const NodeInfo *__restrict__ ninfo,
+    const NodeMom *__restrict__ nmom, const double *__restrict__ neps2,
+    const int32_t *__restrict__ nparent, const double *__restrict__ nadj,
     const Body *__restrict__ body, const double *__restrict__ beps2, int use_eps,
-    const uint32_t *__restrict__ idx, const double *__restrict__ npre,
-    const double *__restrict__ gt, const double *__restrict__ badj, double *__restrict__ g_pos,
-    double *__restrict__ g_mass, int64_t node_cap)
+    const uint32_t *__restrict__ idx, const double *__restrict__ gt,
+    const double *__restrict__ badj, double *__restrict__ g_pos, double *__restrict__ g_mass,
+    int64_t node_cap)
 {
     int64_t nn = 0;
     for (int l = 0; l < kLevels; l++) nn += hdr->level_count[l];
@@ -559,7 +492,22 @@ __global__ __launch_bounds__(256) void k_vjp_finish(
          k += (int64_t)gridDim.x * 256) {
         const NodeInfo info = ninfo[k];
         if (info.child0 >= 0) continue;
-        const double *p = npre + 5 * k;
+        int32_t chain[kLevels];  // chain[d]: the leaf's ancestor d levels up, or -1
+        int32_t cur = (int32_t)k;
+#pragma unroll
+        for (int d = 0; d < kLevels; d++) {
+            chain[d] = cur;
+            cur = cur >= 0 ? nparent[cur] : -1;
+        }
+        double p[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int d = kLevels - 1; d >= 0; d--) {
+            const int32_t c = chain[d];
+            if (c < 0) continue;
+            double cf[5];
+            node_coeffs(nadj, nmom[c], use_eps ? neps2[c] : 0.0, c, cf);
+            for (int q = 0; q < 5; q++) p[q] = p[q] + cf[q];
+        }
         for (int32_t s = info.first; s < info.first + info.count; s++) {
             const Body b = body[s];
             const double e2 = use_eps ? beps2[s] : 0.0;
@@ -732,7 +680,8 @@ hipError_t launch_tree_vjp(const Workspace &w, const AdjointWork &aw, hipStream_
                            double *g_mass)
 {
     if (p.n <= 0) return hipSuccess;
-    k_vjp_clear<<<1024, 256, 0, s>>>(aw.badj, p.n, aw.nadj, aw.npre, w.hdr, w.node_cap);
+    k_vjp_clear<<<1024, 256, 0, s>>>(aw.badj, p.n, aw.nadj, aw.nparent, w.ninfo, w.hdr,
+                                     w.node_cap);
     const int gb = p.group == 16 || p.group == 32 ? p.group : 64;
     const int ngroups = (int)((p.n + gb - 1) / gb);
     const int per_xcd = (ngroups + 7) / 8;
@@ -763,31 +712,9 @@ hipError_t launch_tree_vjp(const Workspace &w, const AdjointWork &aw, hipStream_
         else walk(F{}, I64{});
     }
     const int use_eps = p.per_body_eps ? 1 : 0;
-    // the root and the top levels (at most 585 nodes) in one block, then one
-    // launch per level down to one below the previous build's depth (a hint
-    // kept by the build), the rest in one block
-    int deep = kMaxLevel;
-    if (w.depth_host) {
-        const int prev = *(const volatile int32_t *)w.depth_host;
-        if (prev >= 0 && prev + 1 < deep) deep = prev + 1;
-    }
-    const int head = deep < kPushHead ? deep : kPushHead;
-    k_vjp_push_head<<<1, 1024, 0, s>>>(head, w.hdr, w.ninfo, w.nmom, w.neps2, use_eps, aw.nadj,
-                                       aw.npre, w.node_cap);
-    int64_t bound = (int64_t)1 << (3 * head);  // nodes a level can hold
-    for (int level = head; level < deep; level++) {
-        const int64_t nodes = bound < p.n ? bound : p.n;
-        const unsigned g = blocks(8 * nodes, 4096);
-        k_vjp_push<<<g, 256, 0, s>>>(level, w.hdr, w.ninfo, w.nmom, w.neps2, use_eps, aw.nadj,
-                                     aw.npre, w.node_cap);
-        if (bound < p.n) bound *= 8;
-    }
-    if (deep < kMaxLevel)
-        k_vjp_push_tail<<<1, 1024, 0, s>>>(deep, w.hdr, w.ninfo, w.nmom, w.neps2, use_eps, aw.nadj,
-                                           aw.npre, w.node_cap);
-    k_vjp_finish<<<blocks(p.n, 4096), 256, 0, s>>>(w.hdr, w.ninfo, w.body, w.beps2, use_eps,
-                                                   w.idx[0], aw.npre, aw.gt, aw.badj, g_pos,
-                                                   g_mass, w.node_cap);
+    k_vjp_finish<<<blocks(p.n, 4096), 256, 0, s>>>(w.hdr, w.ninfo, w.nmom, w.neps2, aw.nparent,
+                                                   aw.nadj, w.body, w.beps2, use_eps, w.idx[0],
+                                                   aw.gt, aw.badj, g_pos, g_mass, w.node_cap);
     return hipGetLastError();
 }
 

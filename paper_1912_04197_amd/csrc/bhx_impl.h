@@ -311,7 +311,7 @@ struct AdjointWork {
     double *gt = nullptr;    // [n_cap][3] target-side gradients, sorted order
     double *badj = nullptr;  // [n_cap][4] source-side body adjoints, sorted order
     double *nadj = nullptr;  // [node_cap][5] node adjoints: gX, gm, g<eps^2>
-    double *npre = nullptr;  // [node_cap][5] ancestor sums of the node coefficients
+    int32_t *nparent = nullptr;  // [node_cap] parent of each node (-1: the root)
     double *vwork = nullptr; // [n_cap][3] velocity while a segment is recomputed
     double *awork = nullptr; // [n_cap][3] acceleration while a segment is recomputed
 };

@@ -118,7 +118,7 @@ void free_slots(bhx::TreeSlots &t)
 void free_aw(bhx::AdjointWork &a)
 {
     free_slots(a.trees);
-    void *ptrs[] = {a.gt, a.badj, a.nadj, a.npre, a.vwork, a.awork};
+    void *ptrs[] = {a.gt, a.badj, a.nadj, a.nparent, a.vwork, a.awork};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     a = bhx::AdjointWork{};
@@ -720,7 +720,7 @@ bh_status bh_create(const bh_config *cfg, void *hip_stream, bh_ctx **out)
         A(dalloc(&c->aw.gt, 3 * n));
         A(dalloc(&c->aw.badj, 4 * n));
         A(dalloc(&c->aw.nadj, 5 * node_cap));
-        A(dalloc(&c->aw.npre, 5 * node_cap));
+        A(dalloc(&c->aw.nparent, node_cap));
         A(dalloc(&c->aw.vwork, 3 * n));
         A(dalloc(&c->aw.awork, 3 * n));
     }
