@@ -1082,20 +1082,6 @@ __device__ inline void build_levels_block(int from, int upto, const uint64_t *__
     }
 }
 
-// Levels from..kMaxLevel-1 in one block (deep levels hold few nodes).
-__global__ __launch_bounds__(1024) void k_build_tail(int from, const uint64_t *__restrict__ keys,
-                                                     TreeHeader *__restrict__ hdr,
-                                                     NodeInfo *__restrict__ ninfo,
-                                                     int64_t node_cap, int leaf)
-{
-    __shared__ int32_t scnt[kLevels + 1];
-    if (threadIdx.x <= kLevels) scnt[threadIdx.x] = hdr->level_count[threadIdx.x];
-    __syncthreads();
-    build_levels_block<true>(from, kMaxLevel, keys, hdr, ninfo, node_cap, leaf, scnt);
-    __syncthreads();
-    if (threadIdx.x <= kLevels) hdr->level_count[threadIdx.x] = scnt[threadIdx.x];
-}
-
 // The top levels of a single scene, from the sorted keys. A level-l cell
 // holds the bodies whose keys start with its 3 l bits, a contiguous run of
 // the sorted keys, so the first body of every level-kPrefixLevels cell
@@ -1461,22 +1447,29 @@ __global__ __launch_bounds__(1024) void k_moments_head(
     if (depth_out && threadIdx.x == 0) report_hints(hdr, depth_out);
 }
 
-// Levels kMaxLevel down to `to` in one block (deep levels hold few nodes).
+// The deep levels in one block (they hold few nodes): with `split`, first
+// the split of levels to..kMaxLevel-1 (stopping at the first empty level,
+// the node counts kept in LDS), then the moments of levels kMaxLevel down
+// to `to`.
 __global__ __launch_bounds__(1024) void k_moments_tail(
-    int to, const TreeHeader *__restrict__ hdr, const NodeInfo *__restrict__ ninfo,
-    const Body *__restrict__ body, const double *__restrict__ beps2,
-    const uint64_t *__restrict__ keys, const SceneBox *__restrict__ box,
+    int to, int split, const uint64_t *__restrict__ keys, TreeHeader *__restrict__ hdr,
+    NodeInfo *__restrict__ ninfo, const Body *__restrict__ body,
+    const double *__restrict__ beps2, const SceneBox *__restrict__ box,
     NodeMom *__restrict__ nmom, double *__restrict__ neps2, double *__restrict__ nquad,
-    int64_t node_cap, int use_eps)
+    int64_t node_cap, int leaf, int use_eps)
 {
     __shared__ int32_t scnt[kLevels + 1];
     if (threadIdx.x <= kLevels) scnt[threadIdx.x] = hdr->level_count[threadIdx.x];
     __syncthreads();
+    if (split) {  // the same on every thread
+        build_levels_block<true>(to, kMaxLevel, keys, hdr, ninfo, node_cap, leaf, scnt);
+        __syncthreads();
+        if (threadIdx.x <= kLevels) hdr->level_count[threadIdx.x] = scnt[threadIdx.x];
+    }
     for (int level = kMaxLevel; level >= to; level--) {
         if (scnt[level] == 0) continue;  // the same on every thread
         moments_nodes(level, scnt, ninfo, body, beps2, keys, box, nmom, neps2, nquad, node_cap,
-                      use_eps,
-                      threadIdx.x, 1024);
+                      use_eps, threadIdx.x, 1024);
         __syncthreads();
     }
 }
@@ -1834,11 +1827,11 @@ void enqueue_levels(const Workspace &w, hipStream_t s, const Layout &lay, int le
             k_build_level<false>
                 <<<g, bs, 0, s>>>(level, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
     }
-    if (deep < kMaxLevel)
-        k_build_tail<<<1, 1024, 0, s>>>(deep, w.keys[0], w.hdr, w.ninfo, w.node_cap, leaf);
+    // the levels from `deep` down: their split and their moments in one block
     const int ue = use_eps ? 1 : 0;
-    k_moments_tail<<<1, 1024, 0, s>>>(deep, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0], w.box,
-                                      w.nmom, w.neps2, w.nquad, w.node_cap, ue);
+    k_moments_tail<<<1, 1024, 0, s>>>(deep, deep < kMaxLevel ? 1 : 0, w.keys[0], w.hdr, w.ninfo,
+                                      w.body, w.beps2, w.box, w.nmom, w.neps2, w.nquad,
+                                      w.node_cap, leaf, ue);
     for (int level = deep - 1; level >= head; level--) {
         const unsigned g = blocks_for(level_bound(level, n, ns), 256, 4096);
         k_moments_level<<<g, 256, 0, s>>>(level, w.hdr, w.ninfo, w.body, w.beps2, w.keys[0], w.box,
