@@ -228,6 +228,18 @@ __device__ inline void root_cube(SceneBox &b, const double lo[3], const double h
     }
 }
 
+// Root cube of a scene into `out` from the reduced box encodings of `in`
+// (the same SceneBox or a copy); a scene without bodies gets the cube at 0.
+__device__ inline void scene_root_cube(SceneBox &out, const SceneBox &in, bool any)
+{
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; a++) {
+        lo[a] = any ? order_dec(in.lo_enc[a]) : 0.0;
+        hi[a] = any ? order_dec(in.hi_enc[a]) : 0.0;
+    }
+    root_cube(out, lo, hi);
+}
+
 // One thread per scene: root cube from the box, and the scene's root node
 // (level 0, its bodies' whole range in sorted order). Thread 0 also resets
 // the per-level node counts.
@@ -246,12 +258,7 @@ __global__ __launch_bounds__(256) void k_box_final(SceneBox *__restrict__ box, i
     if (sc >= n_scenes) return;
     const int64_t first = offsets ? offsets[sc] : 0, end = offsets ? offsets[sc + 1] : n;
     SceneBox &b = box[sc];
-    double lo[3], hi[3];
-    for (int a = 0; a < 3; a++) {
-        lo[a] = end > first ? order_dec(b.lo_enc[a]) : 0.0;
-        hi[a] = end > first ? order_dec(b.hi_enc[a]) : 0.0;
-    }
-    root_cube(b, lo, hi);
+    scene_root_cube(b, b, end > first);
     if (end > first)
         ninfo[sc] = NodeInfo{(int32_t)first, (int32_t)(end - first), -1, (int32_t)(sc << 16)};
 }
@@ -351,20 +358,37 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint64_t *__re
 }
 
 // Exclusive scan of one digit's row of tile counts; one block per digit.
-// k_keys for one scene with the tile layout of k_sort_hist, and that kernel's
-// digit counts of the first pass (bits shift..shift+7) of the same tile.
+// k_box_final and k_keys for one scene, with the tile layout of k_sort_hist,
+// and that kernel's digit counts of the first pass (bits shift..shift+7) of
+// the same tile.
 __global__ __launch_bounds__(kSortThreads) void k_keys_hist(const double *__restrict__ pos,
                                                             int stride, int64_t n,
-                                                            const SceneBox *__restrict__ box,
+                                                            SceneBox *__restrict__ box,
+                                                            TreeHeader *__restrict__ hdr,
+                                                            NodeInfo *__restrict__ ninfo,
                                                             uint64_t *__restrict__ keys,
                                                             uint32_t *__restrict__ idx, int shift,
                                                             uint32_t *__restrict__ counts,
                                                             int nblk)
 {
+#pragma clang fp contract(off)
     __shared__ uint32_t h[256];
+    __shared__ SceneBox b;  // this block's copy of the root cube
     h[threadIdx.x] = 0;
+    // k_box_final's work for the one scene (n > 0): every block computes the
+    // root cube from the reduced box for itself, block 0 also stores it, the
+    // level counts and the root node (no block reads those fields here)
+    if (threadIdx.x == 0) {
+        scene_root_cube(b, box[0], true);
+        if (blockIdx.x == 0) {
+            scene_root_cube(box[0], box[0], true);
+            for (int l = 0; l <= kLevels; l++) hdr->level_count[l] = 0;
+            hdr->level_count[0] = 1;
+            hdr->cell_max = 0;
+            ninfo[0] = NodeInfo{0, (int32_t)n, -1, 0};
+        }
+    }
     __syncthreads();
-    const SceneBox &b = box[0];
     const int64_t base = (int64_t)blockIdx.x * kSortTile;
     for (int r = 0; r < kSortItems; r++) {
         const int64_t i = base + r * kSortThreads + threadIdx.x;
@@ -1698,20 +1722,21 @@ namespace {
 // sort, leaving the sorted order in idx[0]; returns whether it sorted by
 // buckets.
 bool enqueue_keys_sort(const Workspace &w, hipStream_t s, const Layout &lay, const double *pos,
-                       int stride)
+                       int stride, bool bucket)
 {
     const int64_t n = lay.n;
     const int ns = lay.n_scenes;
     const int nblk = (int)((n + kSortTile - 1) / kSortTile);
     const unsigned nb0 = blocks_for(n, 256, 1u << 30);
-    if (bucket_sort_hint(w, lay)) {
+    if (bucket) {
         // two passes on the top 16 key bits and, for several scenes, one on
         // the scene index (ending in buffer 0), then the buckets in place
         const int passes = ns > 1 ? 3 : 2;
         const int first = passes & 1;
-        if (ns == 1)  // the keys come with the first pass's digit counts
-            k_keys_hist<<<nblk, kSortThreads, 0, s>>>(pos, stride, n, w.box, w.keys[0], w.idx[0],
-                                                      kTopShift, w.sort_counts, nblk);
+        if (ns == 1)  // the root cube, the keys and the first pass's digit counts
+            k_keys_hist<<<nblk, kSortThreads, 0, s>>>(pos, stride, n, w.box, w.hdr, w.ninfo,
+                                                      w.keys[0], w.idx[0], kTopShift,
+                                                      w.sort_counts, nblk);
         else
             k_keys<<<nb0, 256, 0, s>>>(pos, stride, n, w.box, lay.scene_of, w.keys[first],
                                        w.idx[first]);
@@ -1908,9 +1933,12 @@ hipError_t launch_build(const Workspace &w, hipStream_t s, const Layout &lay, co
     const int nchunks = lay.chunks ? lay.n_chunks : (int)((n + kBoxChunk - 1) / kBoxChunk);
     if (nchunks > 0)
         k_box_chunk<<<nchunks, kBoxThreads, 0, s>>>(pos, mass, eps, n, lay.chunks, w.box, w.hdr);
-    k_box_final<<<sb, 256, 0, s>>>(w.box, ns, lay.offsets, n, w.hdr, w.ninfo);
+    // the sort is chosen once (a host read of the previous build's hint); a
+    // single scene's bucket sort finishes the box in its key kernel
+    const bool bk = n > 0 && bucket_sort_hint(w, lay);
+    if (!(bk && ns == 1)) k_box_final<<<sb, 256, 0, s>>>(w.box, ns, lay.offsets, n, w.hdr, w.ninfo);
     if (n == 0) return hipGetLastError();
-    const bool bk = enqueue_keys_sort(w, s, lay, pos, 3);
+    enqueue_keys_sort(w, s, lay, pos, 3, bk);
     if (bucket) *bucket = bk;
     const LevelPlan plan = plan_levels(w, lay);
     k_gather<<<blocks_for(n, 256, 1u << 30), 256, 0, s>>>(pos, mass, eps, w.idx[0], n, w.body,
@@ -1933,8 +1961,9 @@ hipError_t launch_build_state(const Workspace &w, hipStream_t s, const Layout &l
     k_state_kick_drift<<<nchunks, kBoxThreads, 0, s>>>(
         w.body, w.tvel, w.tacc, w.beps2, w.idx[0], n, 0.5 * dt, dt, lay.chunks, w.sbody, w.svel,
         use_eps ? w.seps2 : nullptr, w.scidx, w.box, w.hdr);
-    k_box_final<<<sb, 256, 0, s>>>(w.box, ns, lay.offsets, n, w.hdr, w.ninfo);
-    const bool bk = enqueue_keys_sort(w, s, lay, reinterpret_cast<const double *>(w.sbody), 4);
+    const bool bk = bucket_sort_hint(w, lay);  // read once, as in launch_build
+    if (!(bk && ns == 1)) k_box_final<<<sb, 256, 0, s>>>(w.box, ns, lay.offsets, n, w.hdr, w.ninfo);
+    enqueue_keys_sort(w, s, lay, reinterpret_cast<const double *>(w.sbody), 4, bk);
     if (bucket) *bucket = bk;
     const LevelPlan plan = plan_levels(w, lay);
     k_gather_state<<<blocks_for(n, 256, 1u << 30), 256, 0, s>>>(
