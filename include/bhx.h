@@ -356,8 +356,9 @@ typedef struct {
 bh_status bh_tree_export(bh_ctx *ctx, bh_tree_view *out);
 
 /* Summary (synchronises): node count and depth of the last build, and which
- * sort it used (bucket_sort = 1: two passes on the top 16 key bits and one
- * block per range of whole buckets, chosen for one scene of more than 4096
+ * sort it used (bucket_sort = 1: two passes on the top 16 key bits, one more
+ * on the scene index for a batch, and one block per range of whole buckets,
+ * chosen for one scene, or a batch of at most 256 scenes, of more than 4096
  * bodies when the previous build's level-5 nodes held at most 1024 bodies
  * each; 0: eight 8-bit passes, or the one-block build); totals of accepted
  * nodes and leaf pairs over all bodies of the last walk (0 unless
